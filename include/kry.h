@@ -1,0 +1,194 @@
+/*
+ * kry.h -- C ABI of the MI355X (gfx950) projected Krylov simulation library.
+ *
+ * Method: Bak, Tran, Johnson, "Numerical Verification of Affine Systems with
+ * up to a Billion Dimensions" (arXiv 1804.01583).  For a system x' = A x + b,
+ * an initial box set x0 = sum_j z_j g_j (+ center), z_j in [zc_j - r_j,
+ * zc_j + r_j], output rows y = C x and time points t = s*dt, s = 0..S, the
+ * library computes the basis matrix C e^{A s dt} E of Sections 3.1-3.2
+ * (output and initial-space projection) one column of E at a time
+ * (Section 4.1), each column by the Krylov approximation
+ *     e^{A t} v ~ |v| V_k e^{H_k t} e_1            (Section 4.2, Eq. approx-formula)
+ * with Lanczos (Algorithm 3) for symmetric A, projecting P = C V_k on the
+ * fly so the basis V_k is never stored (Algorithm 4).  The affine term b is
+ * removed by augmenting the state with a constant variable (Section 2.1).
+ * It then checks every time step for an intersection of the reachable output
+ * range with the unsafe set (the per-step LP of Section 2.1, specialised to a
+ * box initial set) and returns the first violation with a counter-example.
+ *
+ * Conventions for every entry point:
+ *  - Device pointers are caller-owned and borrowed until kry_plan_destroy.
+ *    Host pointers are read during the call only.
+ *  - All GPU work is enqueued on the caller's hipStream_t given to kry_plan.
+ *  - Every call returns a kry_status; no C++ exception crosses this ABI.  On
+ *    a non-OK status, kry_last_error() returns a thread-local message.
+ *  - Dimensions are 64-bit; vectors of n > 2^31 entries are supported.
+ */
+#ifndef KRY_H
+#define KRY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KRY_OK = 0,
+    KRY_EINVAL = 1,    /* invalid argument: shapes, ranges, NULL pointers, non-finite scalars */
+    KRY_ENOMEM = 2,    /* device allocation failed or workspace too small */
+    KRY_EDEVICE = 3,   /* a HIP runtime call failed */
+    KRY_ENUMERIC = 4,  /* non-finite value met in the Krylov recurrence */
+    KRY_ENOTSUP = 5    /* combination not supported by this build */
+} kry_status;
+
+typedef enum { KRY_FP64 = 0, KRY_FP32_BASIS = 1 } kry_precision;
+
+/* KRY_AUTO picks Lanczos when the system is declared symmetric. */
+typedef enum { KRY_AUTO = 0, KRY_LANCZOS = 1, KRY_ARNOLDI = 2, KRY_BLOCK_ARNOLDI = 3 } kry_method;
+
+typedef enum { KRY_CSR = 0, KRY_STENCIL7 = 1 } kry_kind;
+
+/* The system matrix A and the forcing b (Section 2, x' = A x + b).
+ * KRY_CSR: rowptr[n+1] (int64), colidx[nnz] (int32, < n), vals[nnz] (FP64),
+ *   all device memory, rows in order; duplicate columns are summed.
+ * KRY_STENCIL7: matrix-free 7-point stencil on an nx*ny*nz grid ordered
+ *   index = (ix*ny + iy)*nz + iz; (A v)_i = c0 v_i + cx (v_{i-+x}) + cy (...) +
+ *   cz (...), neighbours outside the grid are zero (Dirichlet).
+ * b: device n-vector or NULL.  When non-NULL the state is augmented with a
+ *   constant variable a = 1 (Section 2.1) and one extra simulation runs.
+ * symmetric: the caller promises A == A^T (needed by Lanczos, Section 4.3).
+ * anorm: max absolute row sum of A, or 0 to let kry_plan compute it; it only
+ *   scales the breakdown test (a Krylov step whose new norm is at most
+ *   1024 * eps * anorm ends the run: the space is invariant, Section 4.2). */
+typedef struct kry_system {
+    int64_t n;
+    int32_t kind;
+    int32_t symmetric;
+    const int64_t* rowptr;
+    const int32_t* colidx;
+    const double* vals;
+    int64_t nnz;
+    int64_t nx, ny, nz;
+    double c0, cx, cy, cz;
+    const double* b;
+    double anorm;
+} kry_system;
+
+/* A sparse vector as nseg disjoint half-open index ranges [lo, hi), sorted
+ * ascending, each with one value w.  Host arrays. */
+typedef struct kry_segs {
+    int64_t nseg;
+    const int64_t* lo;
+    const int64_t* hi;
+    const double* w;
+} kry_segs;
+
+/* One column g_j of E with its box coefficient z_j in [zc - radius, zc + radius]
+ * (Section 3.2, initial space I_z given as a box). */
+typedef struct kry_gen {
+    kry_segs seg;
+    double zc;
+    double radius;
+} kry_gen;
+
+/* Output row r is unsafe at a step when y_r can take a value in [lo, hi]
+ * (closed; +-INFINITY allowed).  The unsafe set is the union over rows. */
+typedef struct kry_interval {
+    double lo, hi;
+} kry_interval;
+
+typedef struct kry_verdict {
+    int64_t first_step;  /* first violated step s (time s*dt), or -1 when safe */
+    int32_t row;         /* violated output row at that step, -1 when safe */
+    int32_t status;      /* KRY_OK, or KRY_ENUMERIC if a non-finite basis entry was met */
+    double y;            /* output value of the counter-example */
+    double lo, hi;       /* reachable output range of that row at that step */
+} kry_verdict;
+
+typedef struct kry_plan kry_plan;
+
+/* kry_plan -- validate the problem, split E into simulation runs and prepare
+ * the device state for them (Sections 2.1, 3.2, 4.1).
+ * Runs, in this order: one per generator [g_j; 0], one for the fixed center
+ * [x_c; 0] when center != NULL (device n-vector), one for the augmented
+ * variable [0; 1] when sys->b != NULL.
+ *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
+ *  k: Krylov dimension per run, 1 <= k <= 64.  The augmented run uses k-1
+ *     Lanczos steps on A from b bordered by one row and column, which spans
+ *     the same k-dimensional Krylov space of the augmented matrix.
+ *  dt, steps: time points s*dt for s = 0..steps (steps + 1 rows of output).
+ *  precision: KRY_FP64 (KRY_FP32_BASIS returns KRY_ENOTSUP in this build).
+ *  method: KRY_AUTO or KRY_LANCZOS (needs symmetric); others KRY_ENOTSUP.
+ *  block_p: runs advanced together per sparse mat-vec launch (1, 2, 4 or 8;
+ *     0 = automatic).  Results do not depend on it.
+ *  workspace: device buffer of workspace_bytes >= kry_footprint(...), or NULL
+ *     to let the plan allocate (and free) its own.
+ *  hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * The plan borrows sys->rowptr/colidx/vals/b and center until destroyed. */
+kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
+                           const double* center, const kry_segs* C, int32_t o, int32_t k,
+                           double dt, int64_t steps, int32_t precision, int32_t method,
+                           int32_t block_p, void* workspace, size_t workspace_bytes,
+                           void* hip_stream, kry_plan** out);
+
+/* kry_project_expm -- run the Krylov process of every run (Algorithms 3-4),
+ * then form the basis matrix for all steps:
+ *   basis[s][r][run] = beta0_run * (P_run e^{H_run s dt} e_1)[r]
+ * (Eq. approx-formula projected by C).  basis_out: host or device pointer to
+ * (steps+1) * o * nruns doubles, or NULL to keep the basis on the device for
+ * kry_check_box_safety only.  With a host pointer the call waits for the
+ * stream; otherwise it returns once the work is enqueued. */
+kry_status kry_project_expm(kry_plan* plan, double* basis_out);
+
+/* kry_check_box_safety -- per step s and output row r, the reachable output
+ * range over the box is [mid - rad, mid + rad] with
+ *   mid = sum_gen basis*zc + sum_fixed basis,  rad = sum_gen |basis|*radius,
+ * exact for a box initial set (the LP of Section 2.1 reduces to it).  Row r is
+ * violated when the range meets unsafe[r].  Reports the first (step, row) in
+ * step-major order and a counter-example z (z_out: host array of ngen doubles,
+ * may be NULL): the box point z_j = zc_j + d*lam*sign(basis_j)*r_j whose output
+ * is the nearest end of unsafe[r] (lam = 0 when mid is already inside).
+ * Needs kry_project_expm first.  Waits for the stream. */
+kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out,
+                                double* z_out);
+
+/* kry_footprint -- device workspace bytes a plan with these sizes needs
+ * (the Krylov vectors, per-block partial sums, H, P and the basis; Section 3.5
+ * gives the method's own memory model, this adds the GPU's staging). */
+kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
+                         int32_t precision, int32_t method, int32_t block_p, size_t* bytes);
+
+/* kry_plan_runs -- number of runs of a plan and their roles
+ * (roles_out: nruns ints, 0 = generator, 1 = center, 2 = augmented; may be NULL). */
+kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out);
+
+/* kry_plan_krylov -- after kry_project_expm, copy one run's Krylov data to the
+ * host: k_eff (Krylov dimension used; smaller than k after a breakdown),
+ * beta0 = |start|, the run's Hessenberg matrix H (k_eff x k_eff row-major,
+ * bordered for the augmented run), h_next = h_{k+1,k}, and P = C V
+ * (o x k_eff row-major).  Any output pointer may be NULL.  Waits for the stream. */
+kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
+                           double* h_next, double* P);
+
+void kry_plan_destroy(kry_plan* plan);
+
+/* Thread-local text of the last error on this thread. */
+const char* kry_last_error(void);
+
+/* Kernel timing with HIP events on the plan's stream: when enabled, each
+ * launch of the library's kernels is bracketed by events and its duration
+ * added to a per-kernel total.  kry_profile_read returns, for kernel name
+ * `name` (see kry_profile_names), the number of launches and the summed
+ * milliseconds since the last reset; it waits for outstanding events. */
+kry_status kry_profile_enable(int32_t on);
+kry_status kry_profile_reset(void);
+kry_status kry_profile_read(const char* name, int64_t* launches, double* total_ms);
+const char* kry_profile_names(void);   /* comma-separated kernel names */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KRY_H */

@@ -1,0 +1,325 @@
+"""Seeded synthetic inputs for projected Krylov verification problems.
+
+This module only *builds inputs*: system matrices (CSR or a 7-point stencil
+descriptor), forcing vectors, initial-set generators, output rows and unsafe
+intervals.  It holds none of the verification method's arithmetic, so both the
+CPU oracle (``oracle/``) and the GPU library's tests and benchmark can draw
+their inputs from here without sharing any of the method.
+
+Problem statement followed (paper, Section 2 "Affine Verification Review"):
+dynamics x' = A x + b, an initial set, an unsafe set, a step dt and a number
+of steps S.  Initial sets are boxes in an initial space x0 = E z (Section 3.2):
+each generator is a sparse column of E (a set of index ranges with values)
+with z_j in [zc_j - r_j, zc_j + r_j].  Outputs y = C x use sparse rows of C
+(Section 3.1).  An optional dense ``center`` vector is a fixed (coefficient 1)
+part of x0 that is not in the generators' span.
+
+Grid ordering for 3D problems: index = (ix * ny + iy) * nz + iz (x slowest).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "Segments", "Generator", "Problem",
+    "segments_from_ranges", "box_segments", "csr_stencil7",
+    "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil",
+    "random_symmetric", "small_heat3d",
+]
+
+
+@dataclass
+class Segments:
+    """A sparse vector given as disjoint, sorted half-open index ranges
+    [lo[i], hi[i]) that each carry one value w[i]."""
+    lo: np.ndarray
+    hi: np.ndarray
+    w: np.ndarray
+
+    def __post_init__(self):
+        self.lo = np.ascontiguousarray(self.lo, dtype=np.int64)
+        self.hi = np.ascontiguousarray(self.hi, dtype=np.int64)
+        self.w = np.ascontiguousarray(self.w, dtype=np.float64)
+        if not (self.lo.shape == self.hi.shape == self.w.shape):
+            raise ValueError("segment arrays differ in length")
+        if np.any(self.hi <= self.lo):
+            raise ValueError("empty or inverted segment")
+        if self.lo.size > 1 and np.any(self.lo[1:] < self.hi[:-1]):
+            raise ValueError("segments must be sorted and disjoint")
+
+    @property
+    def nseg(self) -> int:
+        return int(self.lo.size)
+
+    @property
+    def count(self) -> int:
+        return int((self.hi - self.lo).sum())
+
+    def dense(self, n: int) -> np.ndarray:
+        v = np.zeros(n)
+        for a, b, w in zip(self.lo, self.hi, self.w):
+            v[a:b] = w
+        return v
+
+
+@dataclass
+class Generator:
+    """One column of E as index ranges, with its box z in [zc-radius, zc+radius]."""
+    seg: Segments
+    zc: float
+    radius: float
+
+
+@dataclass
+class Problem:
+    name: str
+    n: int
+    kind: str                      # "csr" or "stencil7"
+    symmetric: bool
+    gens: List[Generator]
+    C: List[Segments]              # o output rows
+    unsafe: np.ndarray             # (o, 2): row r is unsafe when y_r in [lo, hi]
+    k: int
+    dt: float
+    steps: int                     # S; time points s = 0..S
+    b: Optional[np.ndarray] = None
+    center: Optional[np.ndarray] = None
+    # CSR
+    rowptr: Optional[np.ndarray] = None
+    colidx: Optional[np.ndarray] = None
+    vals: Optional[np.ndarray] = None
+    # 7-point stencil with zero (Dirichlet) values outside the grid
+    grid: Optional[Tuple[int, int, int]] = None
+    coef: Optional[Tuple[float, float, float, float]] = None   # (c0, cx, cy, cz)
+    seed: int = 0
+    note: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def o(self) -> int:
+        return len(self.C)
+
+    @property
+    def nnz(self) -> int:
+        return 0 if self.colidx is None else int(self.colidx.size)
+
+    def csr(self):
+        """(rowptr, colidx, vals); a stencil problem is expanded to CSR."""
+        if self.kind == "csr":
+            return self.rowptr, self.colidx, self.vals
+        nx, ny, nz = self.grid
+        return csr_stencil7(nx, ny, nz, *self.coef)
+
+
+def segments_from_ranges(ranges, values=1.0) -> Segments:
+    ranges = sorted(ranges)
+    vals = np.broadcast_to(np.asarray(values, dtype=np.float64), (len(ranges),))
+    return Segments(np.array([r[0] for r in ranges]), np.array([r[1] for r in ranges]), np.array(vals))
+
+
+def box_segments(grid, box, value=1.0) -> Segments:
+    """Index ranges of the cells of a 3D box ((x0,x1),(y0,y1),(z0,z1)), half
+    open, in a grid (nx, ny, nz) ordered x slowest.  Runs along z are merged
+    when the box spans the whole z (and y) extent."""
+    nx, ny, nz = grid
+    (x0, x1), (y0, y1), (z0, z1) = box
+    assert 0 <= x0 < x1 <= nx and 0 <= y0 < y1 <= ny and 0 <= z0 < z1 <= nz
+    if z0 == 0 and z1 == nz and y0 == 0 and y1 == ny:
+        lo = np.array([x0 * ny * nz]); hi = np.array([x1 * ny * nz])
+    elif z0 == 0 and z1 == nz:
+        xs = np.arange(x0, x1)
+        lo = (xs * ny + y0) * nz
+        hi = (xs * ny + y1) * nz
+    else:
+        xs, ys = np.meshgrid(np.arange(x0, x1), np.arange(y0, y1), indexing="ij")
+        base = ((xs * ny + ys) * nz).ravel()
+        lo = base + z0
+        hi = base + z1
+    return Segments(lo, hi, np.full(lo.size, float(value)))
+
+
+def csr_stencil7(nx, ny, nz, c0, cx, cy, cz):
+    """CSR (int64 rowptr, int32 colidx, float64 values) of the 7-point
+    stencil with zero values outside the grid; columns ascending per row."""
+    n = nx * ny * nz
+    if n >= 2**31:
+        raise ValueError("CSR expansion limited to n < 2^31 (int32 columns)")
+    idx = np.arange(n, dtype=np.int64)
+    iz = idx % nz
+    iy = (idx // nz) % ny
+    ix = idx // (ny * nz)
+    offs = [(-ny * nz, ix > 0, cx), (-nz, iy > 0, cy), (-1, iz > 0, cz), (0, None, c0),
+            (1, iz < nz - 1, cz), (nz, iy < ny - 1, cy), (ny * nz, ix < nx - 1, cx)]
+    cols = np.empty((n, 7), dtype=np.int64)
+    vals = np.empty((n, 7), dtype=np.float64)
+    mask = np.empty((n, 7), dtype=bool)
+    for j, (d, ok, c) in enumerate(offs):
+        cols[:, j] = idx + d
+        vals[:, j] = c
+        mask[:, j] = True if ok is None else ok
+    counts = mask.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    colidx = cols[mask].astype(np.int32)
+    v = vals[mask]
+    return rowptr, colidx, v
+
+
+# ---------------------------------------------------------------------------
+# The paper's worked example (Section 2.2 "Timed Harmonic Oscillator Example")
+# ---------------------------------------------------------------------------
+
+def harmonic_oscillator() -> Problem:
+    """x' = y, y' = -x, t' = 1 (the t equation carries the affine term);
+    x0 = -5, y0 in [0, 1], t0 = 0; unsafe when x = 4; step pi/4 up to pi."""
+    rowptr = np.array([0, 1, 2, 2], dtype=np.int64)
+    colidx = np.array([1, 0], dtype=np.int32)
+    vals = np.array([1.0, -1.0])
+    b = np.array([0.0, 0.0, 1.0])
+    gen = Generator(segments_from_ranges([(1, 2)]), zc=0.5, radius=0.5)
+    center = np.array([-5.0, 0.0, 0.0])
+    C = [segments_from_ranges([(0, 1)])]
+    unsafe = np.array([[4.0, 4.0]])
+    return Problem("harmonic", 3, "csr", False, [gen], C, unsafe, k=3, dt=math.pi / 4, steps=4,
+                   b=b, center=center, rowptr=rowptr, colidx=colidx, vals=vals,
+                   note="paper Section 2.2 worked example")
+
+
+# ---------------------------------------------------------------------------
+# 1D heat equation, n = 200 (tridiagonal (1,-2,1)/h^2, Dirichlet ends)
+# ---------------------------------------------------------------------------
+
+def heat1d(n=200, k=30, dt=1e-4, steps=1000, seed=1) -> Problem:
+    h = 1.0 / (n + 1)
+    rowptr, colidx, vals = csr_stencil7(1, 1, n, -2.0 / h**2, 0.0, 0.0, 1.0 / h**2)
+    rng = np.random.default_rng(seed)
+    xc = rng.uniform(0.0, 1.0, size=10)
+    gens = [Generator(segments_from_ranges([(j, j + 1)]), zc=float(xc[j]), radius=0.05)
+            for j in range(10)]
+    # output: mean of x_90..x_110 (1-based), i.e. indices 89..109
+    C = [segments_from_ranges([(89, 110)], 1.0 / 21.0)]
+    unsafe = np.array([[0.9, math.inf]])
+    return Problem("heat1d", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
+                   note="1D heat, box radius 0.05 on x_1..x_10, mean(x_90..x_110) >= 0.9 unsafe")
+
+
+# ---------------------------------------------------------------------------
+# 3D heat equation (Dirichlet faces), diffusivity D, h = 1/(m+1)
+# ---------------------------------------------------------------------------
+
+def _heat3d_parts(m, D, seed, forcing_cube=10, forcing=0.1):
+    h = 1.0 / (m + 1)
+    c = D / h**2
+    coef = (-6.0 * c, c, c, c)
+    forcing_cube = min(forcing_cube, m)
+    rng = np.random.default_rng(seed)
+    off = rng.integers(0, m - forcing_cube + 1, size=3)
+    fbox = tuple((int(o), int(o) + forcing_cube) for o in off)
+    b = box_segments((m, m, m), fbox, forcing).dense(m**3)
+    return coef, b, fbox
+
+
+def heat3d_csr(m=100, D=0.01, k=40, dt=0.02, steps=2000, seed=2, unsafe_scale=None) -> Problem:
+    """3D heat on an m^3 grid stored as CSR, forcing b = 0.1 on a seeded
+    10^3 sub-cube (state augmentation), one box generator over the [0,10)^3
+    corner at 1.0 +- 0.1, outputs = means over the generator cube, the
+    forcing cube and the central cube."""
+    n = m**3
+    coef, b, fbox = _heat3d_parts(m, D, seed)
+    rowptr, colidx, vals = csr_stencil7(m, m, m, *coef)
+    g = min(10, m)
+    gbox = ((0, g), (0, g), (0, g))
+    gens = [Generator(box_segments((m, m, m), gbox, 1.0), zc=1.0, radius=0.1)]
+    cc = max(m // 2 - g // 2, 0)
+    cbox = ((cc, cc + g), (cc, cc + g), (cc, cc + g))
+    C = []
+    for bx in (gbox, fbox, cbox):
+        cells = int(np.prod([hi - lo for lo, hi in bx]))
+        C.append(box_segments((m, m, m), bx, 1.0 / cells))
+    # unsafe thresholds: region means reaching these values are unsafe.
+    thr = np.array([1.2, 0.5, 0.5]) if unsafe_scale is None else np.asarray(unsafe_scale, float)
+    unsafe = np.stack([thr, np.full(3, math.inf)], axis=1)
+    return Problem("heat3d_csr", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   b=b, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
+                   meta={"m": m, "forcing_box": fbox, "gen_box": gbox, "center_box": cbox},
+                   note="3D heat CSR with affine forcing")
+
+
+def small_heat3d(m=12, D=0.01, k=20, dt=0.02, steps=200, seed=7) -> Problem:
+    """A small version of heat3d_csr for fast parity runs."""
+    p = heat3d_csr(m=m, D=D, k=k, dt=dt, steps=steps, seed=seed)
+    p.name = "small_heat3d"
+    return p
+
+
+def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
+    """Matrix-free 3D heat (7-point stencil descriptor), forcing 0.1 on a
+    seeded 100^3 sub-cube, generator = heated region x in [0,0.4],
+    y in [0,0.2], z in [0,0.1] (paper Section 5.3) at 1.0 +- 0.1, outputs =
+    the grid center point and the mean over the heated region."""
+    n = m**3
+    h = 1.0 / (m + 1)
+    c = D / h**2
+    coef = (-6.0 * c, c, c, c)
+    rng = np.random.default_rng(seed)
+    fc = max(m // 10, 1)
+    off = rng.integers(0, m - fc + 1, size=3)
+    fbox = tuple((int(o), int(o) + fc) for o in off)
+    b = box_segments((m, m, m), fbox, 0.1).dense(n)
+    gbox = ((0, max(int(round(0.4 * m)), 1)), (0, max(int(round(0.2 * m)), 1)),
+            (0, max(int(round(0.1 * m)), 1)))
+    gseg = box_segments((m, m, m), gbox, 1.0)
+    gens = [Generator(gseg, zc=1.0, radius=0.1)]
+    mid = m // 2
+    cpt = ((mid * m + mid) * m + mid)
+    C = [segments_from_ranges([(cpt, cpt + 1)]), box_segments((m, m, m), gbox, 1.0 / gseg.count)]
+    unsafe = np.array([[0.5, math.inf], [1.2, math.inf]])
+    return Problem("heat3d_stencil", n, "stencil7", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   b=b, grid=(m, m, m), coef=coef, seed=seed,
+                   meta={"m": m, "forcing_box": fbox, "gen_box": gbox},
+                   note="matrix-free 3D heat with affine forcing")
+
+
+# ---------------------------------------------------------------------------
+# Small random problems for parity edge cases
+# ---------------------------------------------------------------------------
+
+def random_symmetric(n=300, nnz_per_row=5, k=12, steps=50, dt=0.05, ngen=3, o=2, seed=11,
+                     affine=True, center=False) -> Problem:
+    """A random sparse symmetric negative-definite-ish matrix (symmetrised
+    random pattern minus a diagonal shift), random index-range generators
+    and output rows."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), nnz_per_row)
+    cols = rng.integers(0, n, size=rows.size)
+    v = rng.normal(0.0, 1.0, size=rows.size)
+    M = np.zeros((n, n))
+    np.add.at(M, (rows, cols), v)
+    M = 0.5 * (M + M.T)
+    M -= np.diag(np.abs(M).sum(axis=1) + 0.5)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    nzr, nzc = np.nonzero(M)
+    np.add.at(rowptr, nzr + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    colidx = nzc.astype(np.int32)
+    vals = M[nzr, nzc]
+    gens = []
+    starts = np.sort(rng.choice(np.arange(0, n - 8, 8), size=ngen, replace=False))
+    for s in starts:
+        L = int(rng.integers(1, 8))
+        gens.append(Generator(segments_from_ranges([(int(s), int(s) + L)], float(rng.uniform(0.5, 2))),
+                              zc=float(rng.uniform(-1, 1)), radius=float(rng.uniform(0.05, 0.3))))
+    C = []
+    for _ in range(o):
+        a = int(rng.integers(0, n - 20))
+        C.append(segments_from_ranges([(a, a + int(rng.integers(1, 20)))], float(rng.uniform(0.1, 1))))
+    unsafe = np.stack([np.full(o, 0.5), np.full(o, math.inf)], axis=1)
+    b = rng.normal(0, 1, size=n) * (rng.uniform(size=n) < 0.1) if affine else None
+    ctr = rng.normal(0, 1, size=n) * (rng.uniform(size=n) < 0.05) if center else None
+    return Problem("random_symmetric", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   b=b, center=ctr, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed)
