@@ -156,9 +156,12 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
 
 /* kry_footprint -- device workspace bytes a plan with these sizes needs
  * (the Krylov vectors, per-block partial sums, H, P and the basis; Section 3.5
- * gives the method's own memory model, this adds the GPU's staging). */
+ * gives the method's own memory model, this adds the GPU's staging).
+ * nruns = generators + (center given) + (b given); nseg_total = segments of
+ * all generators and output rows together. */
 kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
-                         int32_t precision, int32_t method, int32_t block_p, size_t* bytes);
+                         int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
+                         size_t* bytes);
 
 /* kry_plan_runs -- number of runs of a plan and their roles
  * (roles_out: nruns ints, 0 = generator, 1 = center, 2 = augmented; may be NULL). */

@@ -252,16 +252,20 @@ def build_runs(problem) -> List[Run]:
 
 
 def krylov_run(problem, run: Run, A=None, Aaug=None, C=None, method="auto", k=None) -> RunResult:
+    """One simulation.  Every run's breakdown test uses the scale ||A||_inf of
+    the system matrix (the augmented run included), so all runs of a problem
+    share one threshold."""
     A = system_matrix(problem) if A is None else A
     C = output_matrix(problem) if C is None else C
     k = problem.k if k is None else k
+    opnorm = inf_norm(A)
     if run.role == "affine":
         Aaug = augment(A, problem.b) if Aaug is None else Aaug
         Caug = sp.hstack([C, sp.csr_matrix((C.shape[0], 1))]).tocsr()
-        return arnoldi(Aaug, run.start, k, Caug)
+        return arnoldi(Aaug, run.start, k, Caug, opnorm=opnorm)
     if method == "arnoldi" or (method == "auto" and not problem.symmetric):
-        return arnoldi(A, run.start, k, C)
-    return lanczos(A, run.start, k, C)
+        return arnoldi(A, run.start, k, C, opnorm=opnorm)
+    return lanczos(A, run.start, k, C, opnorm=opnorm)
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,653 @@
+// Host side of the C ABI declared in include/kry.h: validation, the split of
+// the initial space into simulation runs (paper Sections 2.1, 3.2, 4.1),
+// workspace layout, batching of runs per mat-vec launch, and the launch
+// sequence of the Lanczos process (Algorithms 3-4) and of the small stage.
+#include "kry.h"
+#include "kry_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace kry;
+
+namespace {
+
+thread_local std::string g_err;
+
+kry_status fail(kry_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define KRY_HIP(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(KRY_EDEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing with events (opt-in)
+// ---------------------------------------------------------------------------
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void drain() {
+        for (auto& p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                auto& t = totals[p.name];
+                t.first += 1;
+                t.second += ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+};
+Profiler& prof() {
+    static Profiler* p = new Profiler();
+    return *p;
+}
+
+const char* kKernelNames =
+    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,eig_coeffs,assemble,check";
+
+// Runs `launch` bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch) {
+    Profiler& P = prof();
+    if (!P.on) return launch();
+    hipEvent_t a, b;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        a = P.get();
+        b = P.get();
+    }
+    if (!a || !b) return launch();
+    hipEventRecord(a, s);
+    hipError_t e = launch();
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(P.mu);
+    P.pending.push_back({name, a, b});
+    return e;
+}
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Row partition: depends on n only (never on the batch), so results of a run
+// do not depend on how runs are batched.
+int64_t rows_per_block_for(int64_t n) {
+    const int64_t env = env_int("KRY_ROWS_PER_BLOCK", 0);
+    if (env > 0) return align_up((size_t)env, kBlock);
+    const int64_t target_blocks = 2048;
+    int64_t rpb = (n + target_blocks - 1) / target_blocks;
+    rpb = (int64_t)align_up((size_t)std::max<int64_t>(rpb, kBlock), kBlock);
+    return rpb;
+}
+
+int max_batch_for(int o, int block_p) {
+    int p = 8;
+    while (p > 1 && p * (1 + o) > kMaxNV) p >>= 1;
+    if (block_p > 0) {
+        int b = 1;
+        while (b * 2 <= block_p && b * 2 <= p) b *= 2;
+        p = b;
+    }
+    return p;
+}
+
+struct Layout {
+    size_t vec, partials, counter, scal, theta, coef, msize, basis, verdict, anorm, meta, total;
+    ScalLayout L;
+    int64_t rpb;
+    int32_t nblocks;
+    int pmax;
+};
+
+Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
+                   size_t meta_bytes) {
+    Layout Y{};
+    Y.rpb = rows_per_block_for(n);
+    Y.nblocks = (int32_t)((n + Y.rpb - 1) / Y.rpb);
+    Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
+    {
+        int p = 1;
+        while (p * 2 <= Y.pmax) p *= 2;
+        Y.pmax = p;
+    }
+    ScalLayout& L = Y.L;
+    L.k = k;
+    L.o = o;
+    L.alpha = 0;
+    L.beta = L.alpha + (k + 2);
+    L.sigma = L.beta + (k + 2);
+    L.proj = L.sigma + (k + 3);
+    L.misc = L.proj + o * (k + 1);
+    L.stride = (int64_t)align_up((size_t)(L.misc + MISC_COUNT), 8);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
+    Y.vec = take(3 * (size_t)n * Y.pmax * sizeof(double));
+    Y.partials = take((size_t)Y.nblocks * kMaxNV * sizeof(double));
+    Y.counter = take(64 * sizeof(unsigned int));
+    Y.scal = take((size_t)nruns * L.stride * sizeof(double));
+    Y.theta = take((size_t)nruns * k * sizeof(double));
+    Y.coef = take((size_t)nruns * o * k * sizeof(double));
+    Y.msize = take((size_t)nruns * sizeof(int32_t));
+    Y.basis = take((size_t)(steps + 1) * o * nruns * sizeof(double));
+    Y.verdict = take((size_t)(6 + nruns) * sizeof(double));
+    Y.anorm = take(sizeof(double));
+    Y.meta = take(meta_bytes);
+    Y.total = off;
+    return Y;
+}
+
+kry_status check_segs(const kry_segs& s, int64_t n, const char* what) {
+    if (s.nseg < 0) return fail(KRY_EINVAL, std::string(what) + ": negative segment count");
+    if (s.nseg > 0 && (!s.lo || !s.hi || !s.w)) return fail(KRY_EINVAL, std::string(what) + ": NULL segment array");
+    for (int64_t i = 0; i < s.nseg; ++i) {
+        if (s.lo[i] < 0 || s.hi[i] > n || s.hi[i] <= s.lo[i])
+            return fail(KRY_EINVAL, std::string(what) + ": segment out of range or empty");
+        if (i > 0 && s.lo[i] < s.hi[i - 1])
+            return fail(KRY_EINVAL, std::string(what) + ": segments not sorted and disjoint");
+        if (!std::isfinite(s.w[i])) return fail(KRY_EINVAL, std::string(what) + ": non-finite segment value");
+    }
+    return KRY_OK;
+}
+
+// Max absolute row sum of a stencil operator: rows differ only by which
+// neighbours exist, so enumerate the (up to 27) boundary classes.  Terms
+// are added in ascending column order like a CSR row.
+double stencil_inf_norm(const kry_system& s) {
+    double best = 0.0;
+    const int64_t dims[3] = {s.nx, s.ny, s.nz};
+    for (int cx = 0; cx < 3; ++cx)
+        for (int cy = 0; cy < 3; ++cy)
+            for (int cz = 0; cz < 3; ++cz) {
+                // class c: 0 = first index, 1 = interior, 2 = last index
+                const int cls[3] = {cx, cy, cz};
+                bool exists = true;
+                bool lo[3], hi[3];
+                for (int d = 0; d < 3; ++d) {
+                    const int64_t m = dims[d];
+                    if (cls[d] == 1 && m < 3) exists = false;
+                    if (cls[d] == 2 && m < 2) exists = false;
+                    const int64_t idx = cls[d] == 0 ? 0 : (cls[d] == 1 ? 1 : m - 1);
+                    lo[d] = idx > 0;
+                    hi[d] = idx < m - 1;
+                }
+                if (!exists) continue;
+                double t = 0.0;
+                if (lo[0]) t += std::fabs(s.cx);
+                if (lo[1]) t += std::fabs(s.cy);
+                if (lo[2]) t += std::fabs(s.cz);
+                t += std::fabs(s.c0);
+                if (hi[2]) t += std::fabs(s.cz);
+                if (hi[1]) t += std::fabs(s.cy);
+                if (hi[0]) t += std::fabs(s.cx);
+                best = std::max(best, t);
+            }
+    return best;
+}
+
+}  // namespace
+
+struct kry_plan {
+    kry_system sys{};
+    int32_t ngen = 0, nruns = 0, o = 0, k = 0;
+    double dt = 0.0;
+    int64_t steps = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int32_t> role;
+    std::vector<double> zc, radius;
+    std::vector<int32_t> gen_set;
+    int32_t oset0 = 0;
+    const double* center = nullptr;
+    Layout Y{};
+    char* ws = nullptr;
+    bool owns_ws = false;
+    std::vector<char> meta_host;
+    SegTable T{};
+    int32_t* role_dev = nullptr;
+    double* zc_dev = nullptr;
+    double* rad_dev = nullptr;
+    int lpr = 1;
+    bool projected = false;
+    std::vector<double> verdict_host;
+
+    double* vec(int i) { return reinterpret_cast<double*>(ws + Y.vec) + (size_t)i * sys.n * Y.pmax; }
+    double* partials() { return reinterpret_cast<double*>(ws + Y.partials); }
+    unsigned int* counter() { return reinterpret_cast<unsigned int*>(ws + Y.counter); }
+    double* scal() { return reinterpret_cast<double*>(ws + Y.scal); }
+    double* theta() { return reinterpret_cast<double*>(ws + Y.theta); }
+    double* coef() { return reinterpret_cast<double*>(ws + Y.coef); }
+    int32_t* msize() { return reinterpret_cast<int32_t*>(ws + Y.msize); }
+    double* basis() { return reinterpret_cast<double*>(ws + Y.basis); }
+    double* verdict() { return reinterpret_cast<double*>(ws + Y.verdict); }
+    double* anorm() { return reinterpret_cast<double*>(ws + Y.anorm); }
+};
+
+namespace {
+
+// Metadata block uploaded once per plan: segment table, per-run roles and
+// box coefficients.
+size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns) {
+    size_t b = 0;
+    b = align_up(b + (size_t)total_segs * 8, 16);   // lo
+    b = align_up(b + (size_t)total_segs * 8, 16);   // hi
+    b = align_up(b + (size_t)total_segs * 8, 16);   // w
+    b = align_up(b + (size_t)(nsets + 1) * 4, 16);  // set_begin
+    b = align_up(b + (size_t)nruns * 4, 16);        // role
+    b = align_up(b + (size_t)nruns * 8, 16);        // zc
+    b = align_up(b + (size_t)nruns * 8, 16);        // radius
+    return b;
+}
+
+kry_status validate_system(const kry_system* sys) {
+    if (!sys) return fail(KRY_EINVAL, "system is NULL");
+    if (sys->n <= 0) return fail(KRY_EINVAL, "n must be positive");
+    if (sys->kind == KRY_CSR) {
+        if (!sys->rowptr || !sys->colidx || !sys->vals) return fail(KRY_EINVAL, "CSR arrays must be non-NULL");
+        if (sys->nnz < 0) return fail(KRY_EINVAL, "nnz must be >= 0");
+        if (sys->n >= (int64_t)1 << 31) return fail(KRY_EINVAL, "CSR needs n < 2^31 (int32 column indices)");
+    } else if (sys->kind == KRY_STENCIL7) {
+        if (sys->nx <= 0 || sys->ny <= 0 || sys->nz <= 0 || sys->nx * sys->ny * sys->nz != sys->n)
+            return fail(KRY_EINVAL, "stencil grid must satisfy nx*ny*nz == n");
+        if (!std::isfinite(sys->c0) || !std::isfinite(sys->cx) || !std::isfinite(sys->cy) || !std::isfinite(sys->cz))
+            return fail(KRY_EINVAL, "stencil coefficients must be finite");
+    } else {
+        return fail(KRY_EINVAL, "unknown system kind");
+    }
+    if (!(sys->anorm >= 0.0) || !std::isfinite(sys->anorm)) return fail(KRY_EINVAL, "anorm must be finite and >= 0");
+    return KRY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kry_last_error(void) { return g_err.c_str(); }
+
+kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
+                         int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
+                         size_t* bytes) {
+    kry_status st = validate_system(sys);
+    if (st != KRY_OK) return st;
+    if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
+    if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kMaxK || steps < 0 || nseg_total < 0)
+        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 64, steps >= 0, nseg_total >= 0 required");
+    if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
+    (void)method;
+    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns));
+    *bytes = Y.total;
+    return KRY_OK;
+}
+
+kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
+                           const double* center, const kry_segs* C, int32_t o, int32_t k,
+                           double dt, int64_t steps, int32_t precision, int32_t method,
+                           int32_t block_p, void* workspace, size_t workspace_bytes,
+                           void* hip_stream, kry_plan** out) {
+    if (!out) return fail(KRY_EINVAL, "out is NULL");
+    *out = nullptr;
+    kry_status st = validate_system(sys);
+    if (st != KRY_OK) return st;
+    if (ngen < 0 || (ngen > 0 && !gens)) return fail(KRY_EINVAL, "bad generator list");
+    if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
+    if (k < 1 || k > kMaxK) return fail(KRY_EINVAL, "k must be in [1, 64]");
+    if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
+    if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
+    if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
+    if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+    if (method != KRY_LANCZOS) return fail(KRY_ENOTSUP, "only Lanczos (symmetric A) is supported in this build");
+    if (!sys->symmetric) return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
+    if (block_p < 0) return fail(KRY_EINVAL, "block_p must be >= 0");
+    const int64_t n = sys->n;
+    for (int32_t g = 0; g < ngen; ++g) {
+        st = check_segs(gens[g].seg, n, "generator");
+        if (st != KRY_OK) return st;
+        if (!std::isfinite(gens[g].zc) || !(gens[g].radius >= 0.0) || !std::isfinite(gens[g].radius))
+            return fail(KRY_EINVAL, "generator box must have finite center and radius >= 0");
+    }
+    for (int32_t q = 0; q < o; ++q) {
+        st = check_segs(C[q], n, "output row");
+        if (st != KRY_OK) return st;
+    }
+
+    auto* plan = new kry_plan();
+    plan->sys = *sys;
+    plan->ngen = ngen;
+    plan->o = o;
+    plan->k = k;
+    plan->dt = dt;
+    plan->steps = steps;
+    plan->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    plan->center = center;
+    for (int32_t g = 0; g < ngen; ++g) {
+        plan->role.push_back(0);
+        plan->zc.push_back(gens[g].zc);
+        plan->radius.push_back(gens[g].radius);
+    }
+    if (center) { plan->role.push_back(1); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
+    if (sys->b) { plan->role.push_back(2); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
+    plan->nruns = (int32_t)plan->role.size();
+    if (plan->nruns == 0) {
+        delete plan;
+        return fail(KRY_EINVAL, "nothing to simulate: no generator, center or forcing");
+    }
+
+    // segment table: generator sets 0..ngen-1, output sets ngen..ngen+o-1
+    int64_t total_segs = 0;
+    for (int32_t g = 0; g < ngen; ++g) total_segs += gens[g].seg.nseg;
+    for (int32_t q = 0; q < o; ++q) total_segs += C[q].nseg;
+    if (total_segs >= ((int64_t)1 << 31)) { delete plan; return fail(KRY_EINVAL, "too many segments"); }
+    const int32_t nsets = ngen + o;
+    const size_t mbytes = meta_size(total_segs, nsets, plan->nruns);
+    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes);
+    const Layout& Y = plan->Y;
+
+    if (workspace) {
+        if (workspace_bytes < Y.total) {
+            delete plan;
+            return fail(KRY_ENOMEM, "workspace too small: need " + std::to_string(Y.total) + " bytes");
+        }
+        if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
+            delete plan;
+            return fail(KRY_EINVAL, "workspace must be 256-byte aligned");
+        }
+        plan->ws = static_cast<char*>(workspace);
+    } else {
+        void* p = nullptr;
+        if (hipMalloc(&p, Y.total) != hipSuccess) {
+            delete plan;
+            return fail(KRY_ENOMEM, "hipMalloc of " + std::to_string(Y.total) + " bytes failed");
+        }
+        plan->ws = static_cast<char*>(p);
+        plan->owns_ws = true;
+    }
+
+    // pack and upload metadata
+    plan->meta_host.assign(mbytes, 0);
+    char* base = plan->meta_host.data();
+    size_t off = 0;
+    auto* lo = reinterpret_cast<int64_t*>(base + off); off = align_up(off + total_segs * 8, 16);
+    auto* hi = reinterpret_cast<int64_t*>(base + off); off = align_up(off + total_segs * 8, 16);
+    auto* w = reinterpret_cast<double*>(base + off); off = align_up(off + total_segs * 8, 16);
+    auto* sb = reinterpret_cast<int32_t*>(base + off); off = align_up(off + (nsets + 1) * 4, 16);
+    auto* rl = reinterpret_cast<int32_t*>(base + off); off = align_up(off + plan->nruns * 4, 16);
+    auto* zc = reinterpret_cast<double*>(base + off); off = align_up(off + plan->nruns * 8, 16);
+    auto* rd = reinterpret_cast<double*>(base + off); off = align_up(off + plan->nruns * 8, 16);
+    int64_t at = 0;
+    int32_t set = 0;
+    auto add_set = [&](const kry_segs& s) {
+        sb[set++] = (int32_t)at;
+        for (int64_t i = 0; i < s.nseg; ++i, ++at) { lo[at] = s.lo[i]; hi[at] = s.hi[i]; w[at] = s.w[i]; }
+    };
+    for (int32_t g = 0; g < ngen; ++g) { plan->gen_set.push_back(set); add_set(gens[g].seg); }
+    plan->oset0 = set;
+    for (int32_t q = 0; q < o; ++q) add_set(C[q]);
+    sb[set] = (int32_t)at;
+    for (int32_t r = 0; r < plan->nruns; ++r) { rl[r] = plan->role[r]; zc[r] = plan->zc[r]; rd[r] = plan->radius[r]; }
+    char* dmeta = plan->ws + Y.meta;
+    plan->T.lo = reinterpret_cast<const int64_t*>(dmeta + ((char*)lo - base));
+    plan->T.hi = reinterpret_cast<const int64_t*>(dmeta + ((char*)hi - base));
+    plan->T.w = reinterpret_cast<const double*>(dmeta + ((char*)w - base));
+    plan->T.set_begin = reinterpret_cast<const int32_t*>(dmeta + ((char*)sb - base));
+    plan->role_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)rl - base));
+    plan->zc_dev = reinterpret_cast<double*>(dmeta + ((char*)zc - base));
+    plan->rad_dev = reinterpret_cast<double*>(dmeta + ((char*)rd - base));
+
+    auto cleanup = [&](kry_status s) { kry_plan_destroy(plan); return s; };
+    if (hipMemcpyAsync(dmeta, base, mbytes, hipMemcpyHostToDevice, plan->stream) != hipSuccess)
+        return cleanup(fail(KRY_EDEVICE, "metadata upload failed"));
+    if (launch_fill_zero_u32(plan->counter(), 64, plan->stream) != hipSuccess)
+        return cleanup(fail(KRY_EDEVICE, "counter reset launch failed"));
+
+    // ||A||_inf scales the breakdown test
+    if (sys->anorm > 0.0 || sys->kind == KRY_STENCIL7) {
+        const double a = sys->anorm > 0.0 ? sys->anorm : stencil_inf_norm(*sys);
+        plan->verdict_host.assign(1, a);
+        if (hipMemcpyAsync(plan->anorm(), plan->verdict_host.data(), sizeof(double), hipMemcpyHostToDevice,
+                           plan->stream) != hipSuccess)
+            return cleanup(fail(KRY_EDEVICE, "anorm upload failed"));
+        if (hipStreamSynchronize(plan->stream) != hipSuccess)
+            return cleanup(fail(KRY_EDEVICE, "stream sync failed"));
+    } else {
+        CsrArgs A{sys->rowptr, sys->colidx, sys->vals};
+        hipError_t e = timed("row_abs_max", plan->stream, [&] {
+            return launch_row_abs_max(A, n, plan->partials(), Y.nblocks, Y.rpb, plan->counter(),
+                                      plan->anorm(), plan->stream);
+        });
+        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e)));
+    }
+    const double avg = sys->kind == KRY_CSR ? (double)sys->nnz / (double)n : 7.0;
+    int lpr = env_int("KRY_LPR", 0);
+    if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8) lpr = avg > 24 ? 8 : (avg > 12 ? 4 : 1);
+    plan->lpr = lpr;
+    *out = plan;
+    return KRY_OK;
+}
+
+kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    const Layout& Y = plan->Y;
+    const int64_t n = plan->sys.n;
+    hipStream_t s = plan->stream;
+    const double tau_scale = 1024.0 * 2.220446049250313e-16;
+    int32_t r0 = 0;
+    while (r0 < plan->nruns) {
+        int P = Y.pmax;
+        while (P > 1 && r0 + P > plan->nruns) P >>= 1;
+        BatchArgs B{};
+        B.n = n;
+        B.rows_per_block = Y.rpb;
+        B.nblocks = Y.nblocks;
+        B.run0 = r0;
+        B.scal = plan->scal();
+        B.L = Y.L;
+        B.partials = plan->partials();
+        B.counter = plan->counter();
+        B.anorm = plan->anorm();
+        B.tau_scale = tau_scale;
+        StartSrc src{};
+        for (int p = 0; p < kMaxP; ++p) { src.dense[p] = nullptr; src.set[p] = -1; }
+        for (int p = 0; p < P; ++p) {
+            const int r = r0 + p;
+            if (plan->role[r] == 0) src.set[p] = plan->gen_set[r];
+            else if (plan->role[r] == 1) src.dense[p] = plan->center;
+            else src.dense[p] = plan->sys.b;
+        }
+        hipError_t e = timed("start", s, [&] {
+            return launch_start(P, plan->o, src, plan->T, plan->oset0, plan->vec(0), B, s);
+        });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
+        for (int j = 1; j <= plan->k; ++j) {
+            double* ucur = plan->vec((j - 1) % 3);
+            double* uprev = plan->vec((j + 1) % 3);   // (j - 2) mod 3
+            double* w = plan->vec(j % 3);
+            if (plan->sys.kind == KRY_CSR) {
+                CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals};
+                e = timed("spmv_csr", s, [&] { return launch_spmv_csr(P, plan->lpr, A, ucur, uprev, w, B, j, s); });
+            } else {
+                StencilArgs A{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx,
+                              plan->sys.cy, plan->sys.cz};
+                e = timed("spmv_stencil", s, [&] { return launch_spmv_stencil(P, A, ucur, uprev, w, B, j, s); });
+            }
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("spmv: ") + hipGetErrorString(e));
+            e = timed("sweep", s, [&] { return launch_sweep(P, plan->o, plan->T, plan->oset0, ucur, w, B, j, s); });
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
+        }
+        r0 += P;
+    }
+    ExpmArgs E{plan->scal(), Y.L, plan->role_dev, plan->theta(), plan->coef(), plan->msize()};
+    hipError_t e = timed("eig_coeffs", s, [&] { return launch_eig_coeffs(E, plan->nruns, s); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("eig_coeffs: ") + hipGetErrorString(e));
+    AssembleArgs A{plan->theta(), plan->coef(), plan->msize(), plan->role_dev, plan->nruns, plan->o,
+                   plan->k, plan->steps, plan->dt, plan->basis()};
+    e = timed("assemble", s, [&] { return launch_assemble(A, s); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("assemble: ") + hipGetErrorString(e));
+    plan->projected = true;
+    if (basis_out) {
+        const size_t bytes = (size_t)(plan->steps + 1) * plan->o * plan->nruns * sizeof(double);
+        hipPointerAttribute_t attr{};
+        bool device_ptr = false;
+        if (hipPointerGetAttributes(&attr, basis_out) == hipSuccess)
+            device_ptr = attr.type == hipMemoryTypeDevice;
+        else
+            (void)hipGetLastError();
+        KRY_HIP(hipMemcpyAsync(basis_out, plan->basis(), bytes, hipMemcpyDefault, s));
+        if (!device_ptr) KRY_HIP(hipStreamSynchronize(s));
+    }
+    return KRY_OK;
+}
+
+kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out, double* z_out) {
+    if (!plan || !unsafe || !out) return fail(KRY_EINVAL, "plan, unsafe and out must be non-NULL");
+    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    CheckArgs C{};
+    C.basis = plan->basis();
+    C.zc = plan->zc_dev;
+    C.radius = plan->rad_dev;
+    C.nruns = plan->nruns;
+    C.o = plan->o;
+    C.steps = plan->steps;
+    for (int q = 0; q < plan->o; ++q) {
+        if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
+        C.ulo[q] = unsafe[q].lo;
+        C.uhi[q] = unsafe[q].hi;
+    }
+    C.verdict = plan->verdict();
+    hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
+    plan->verdict_host.assign(6 + plan->nruns, 0.0);
+    KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, plan->stream));
+    KRY_HIP(hipStreamSynchronize(plan->stream));
+    const double* v = plan->verdict_host.data();
+    out->first_step = (int64_t)v[0];
+    out->row = (int32_t)v[1];
+    out->y = v[2];
+    out->lo = v[3];
+    out->hi = v[4];
+    out->status = (int32_t)v[5];
+    if (z_out) {
+        int32_t g = 0;
+        for (int32_t r = 0; r < plan->nruns; ++r)
+            if (plan->role[r] == 0) z_out[g++] = v[6 + r];
+    }
+    return KRY_OK;
+}
+
+kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (nruns) *nruns = plan->nruns;
+    if (roles_out)
+        for (int32_t r = 0; r < plan->nruns; ++r) roles_out[r] = plan->role[r];
+    return KRY_OK;
+}
+
+kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
+                           double* h_next, double* P) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
+    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    const ScalLayout& L = plan->Y.L;
+    std::vector<double> sc(L.stride);
+    KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal() + (size_t)run * L.stride, L.stride * sizeof(double),
+                           hipMemcpyDeviceToHost, plan->stream));
+    KRY_HIP(hipStreamSynchronize(plan->stream));
+    const int k = plan->k;
+    int m = (int)sc[L.misc + MISC_KEFF];
+    const bool bordered = plan->role[run] == 2;
+    // dimension of the (augmented) Krylov space
+    int dim = m;
+    if (bordered) dim = (m > k - 1 ? k - 1 : m) + 1;
+    if (k_eff) *k_eff = dim;
+    if (beta0) *beta0 = bordered ? 1.0 : sc[L.beta + 0];
+    const int tri = bordered ? dim - 1 : dim;
+    if (H) {
+        std::fill(H, H + (size_t)dim * dim, 0.0);
+        const int sh = bordered ? 1 : 0;
+        if (bordered && dim > 1) H[1 * dim + 0] = sc[L.beta + 0];
+        for (int i = 0; i < tri; ++i) {
+            H[(i + sh) * dim + (i + sh)] = sc[L.alpha + i + 1];
+            if (i + 1 < tri) {
+                H[(i + sh) * dim + (i + 1 + sh)] = sc[L.beta + i + 1];
+                H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
+            }
+        }
+    }
+    if (h_next) *h_next = tri > 0 ? sc[L.beta + tri] : (bordered ? sc[L.beta + 0] : 0.0);
+    if (P) {
+        for (int q = 0; q < plan->o; ++q) {
+            double* row = P + (size_t)q * dim;
+            int c0 = 0;
+            if (bordered) { if (dim > 0) row[0] = 0.0; c0 = 1; }
+            for (int c = 0; c < tri; ++c) row[c0 + c] = sc[L.proj + q * (k + 1) + c];
+        }
+    }
+    return KRY_OK;
+}
+
+void kry_plan_destroy(kry_plan* plan) {
+    if (!plan) return;
+    if (plan->owns_ws && plan->ws) {
+        (void)hipStreamSynchronize(plan->stream);
+        (void)hipFree(plan->ws);
+    }
+    delete plan;
+}
+
+kry_status kry_profile_enable(int32_t on) {
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.on = on != 0;
+    return KRY_OK;
+}
+
+kry_status kry_profile_reset(void) {
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.drain();
+    P.totals.clear();
+    return KRY_OK;
+}
+
+kry_status kry_profile_read(const char* name, int64_t* launches, double* total_ms) {
+    if (!name) return fail(KRY_EINVAL, "name is NULL");
+    Profiler& P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.drain();
+    auto it = P.totals.find(name);
+    if (launches) *launches = it == P.totals.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == P.totals.end() ? 0.0 : it->second.second;
+    return KRY_OK;
+}
+
+const char* kry_profile_names(void) { return kKernelNames; }
+
+}  // extern "C"

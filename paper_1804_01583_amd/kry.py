@@ -1,0 +1,307 @@
+"""ctypes binding of libkry.so (include/kry.h).  Argument marshalling only:
+every step of the verification path runs in the library's HIP kernels.
+
+The functions keep the C names (kry_plan_create, kry_project_expm,
+kry_check_box_safety, kry_footprint, kry_plan_runs, kry_plan_krylov,
+kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
+tensors a plan borrows alive and destroys the plan when it is dropped.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkry.so")
+
+KRY_OK, KRY_EINVAL, KRY_ENOMEM, KRY_EDEVICE, KRY_ENUMERIC, KRY_ENOTSUP = range(6)
+KRY_FP64, KRY_FP32_BASIS = 0, 1
+KRY_AUTO, KRY_LANCZOS, KRY_ARNOLDI, KRY_BLOCK_ARNOLDI = range(4)
+KRY_CSR, KRY_STENCIL7 = 0, 1
+ROLE_NAMES = {0: "gen", 1: "center", 2: "affine"}
+
+
+class KryError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"kry status {status}: {msg}")
+        self.status = status
+
+
+class KrySystem(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("kind", ct.c_int32), ("symmetric", ct.c_int32),
+                ("rowptr", ct.c_void_p), ("colidx", ct.c_void_p), ("vals", ct.c_void_p),
+                ("nnz", ct.c_int64), ("nx", ct.c_int64), ("ny", ct.c_int64), ("nz", ct.c_int64),
+                ("c0", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double), ("cz", ct.c_double),
+                ("b", ct.c_void_p), ("anorm", ct.c_double)]
+
+
+class KrySegs(ct.Structure):
+    _fields_ = [("nseg", ct.c_int64), ("lo", ct.c_void_p), ("hi", ct.c_void_p), ("w", ct.c_void_p)]
+
+
+class KryGen(ct.Structure):
+    _fields_ = [("seg", KrySegs), ("zc", ct.c_double), ("radius", ct.c_double)]
+
+
+class KryInterval(ct.Structure):
+    _fields_ = [("lo", ct.c_double), ("hi", ct.c_double)]
+
+
+class KryVerdict(ct.Structure):
+    _fields_ = [("first_step", ct.c_int64), ("row", ct.c_int32), ("status", ct.c_int32),
+                ("y", ct.c_double), ("lo", ct.c_double), ("hi", ct.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1804_01583_amd.build`")
+    lib = ct.CDLL(LIB_PATH)
+    P = ct.c_void_p
+    lib.kry_plan_create.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
+                                    ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
+                                    ct.c_int32, ct.c_int32, ct.c_int32, P, ct.c_size_t, P, ct.POINTER(P)]
+    lib.kry_project_expm.argtypes = [P, P]
+    lib.kry_check_box_safety.argtypes = [P, ct.POINTER(KryInterval), ct.POINTER(KryVerdict), P]
+    lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
+                                  ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
+    lib.kry_plan_runs.argtypes = [P, ct.POINTER(ct.c_int32), P]
+    lib.kry_plan_krylov.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double), P,
+                                    ct.POINTER(ct.c_double), P]
+    lib.kry_plan_destroy.argtypes = [P]
+    lib.kry_plan_destroy.restype = None
+    lib.kry_last_error.restype = ct.c_char_p
+    lib.kry_profile_enable.argtypes = [ct.c_int32]
+    lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
+    lib.kry_profile_names.restype = ct.c_char_p
+    for f in ("kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+              "kry_plan_runs", "kry_plan_krylov", "kry_profile_enable", "kry_profile_reset",
+              "kry_profile_read"):
+        getattr(lib, f).restype = ct.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ["kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+            "kry_plan_runs", "kry_plan_krylov", "kry_plan_destroy", "kry_last_error",
+            "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
+
+
+def _check(status: int):
+    if status != KRY_OK:
+        raise KryError(status, lib.kry_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return int(t)
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def kry_plan_create(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Sequence[KrySegs], k: int,
+                    dt: float, steps: int, precision=KRY_FP64, method=KRY_AUTO, block_p=0,
+                    workspace_ptr=None, workspace_bytes=0, stream_ptr=None) -> int:
+    garr = (KryGen * max(len(gens), 1))(*gens)
+    carr = (KrySegs * len(C))(*C)
+    out = ct.c_void_p()
+    _check(lib.kry_plan_create(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps,
+                               precision, method, block_p, workspace_ptr, workspace_bytes, stream_ptr,
+                               ct.byref(out)))
+    return out.value
+
+
+def kry_project_expm(plan: int, basis_out_ptr=None):
+    _check(lib.kry_project_expm(plan, basis_out_ptr))
+
+
+def kry_check_box_safety(plan: int, unsafe: np.ndarray, ngen: int):
+    o = unsafe.shape[0]
+    U = (KryInterval * o)(*[KryInterval(float(a), float(b)) for a, b in unsafe])
+    v = KryVerdict()
+    z = np.zeros(max(ngen, 1))
+    _check(lib.kry_check_box_safety(plan, U, ct.byref(v), z.ctypes.data))
+    return v, z[:ngen]
+
+
+def kry_footprint(system: KrySystem, nruns: int, o: int, k: int, steps: int, nseg_total: int,
+                  precision=KRY_FP64, method=KRY_AUTO, block_p=0) -> int:
+    b = ct.c_size_t()
+    _check(lib.kry_footprint(ct.byref(system), nruns, o, k, steps, nseg_total, precision, method, block_p,
+                             ct.byref(b)))
+    return b.value
+
+
+def kry_plan_runs(plan: int):
+    n = ct.c_int32()
+    _check(lib.kry_plan_runs(plan, ct.byref(n), None))
+    roles = np.zeros(n.value, dtype=np.int32)
+    _check(lib.kry_plan_runs(plan, ct.byref(n), roles.ctypes.data))
+    return [ROLE_NAMES[int(r)] for r in roles]
+
+
+def kry_plan_krylov(plan: int, run: int, k: int, o: int):
+    keff = ct.c_int32()
+    beta0 = ct.c_double()
+    hn = ct.c_double()
+    H = np.zeros((k + 1) * (k + 1))
+    P = np.zeros(o * (k + 1))
+    _check(lib.kry_plan_krylov(plan, run, ct.byref(keff), ct.byref(beta0), H.ctypes.data, ct.byref(hn),
+                               P.ctypes.data))
+    m = keff.value
+    return {"k_eff": m, "beta0": beta0.value, "H": H[:m * m].reshape(m, m).copy(),
+            "h_next": hn.value, "P": P[:o * m].reshape(o, m).copy()}
+
+
+def kry_plan_destroy(plan: int):
+    lib.kry_plan_destroy(plan)
+
+
+def profile_enable(on: bool = True):
+    _check(lib.kry_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib.kry_profile_reset())
+
+
+def profile_read(name: str):
+    n = ct.c_int64()
+    ms = ct.c_double()
+    _check(lib.kry_profile_read(name.encode(), ct.byref(n), ct.byref(ms)))
+    return n.value, ms.value
+
+
+def profile_names():
+    return lib.kry_profile_names().decode().split(",")
+
+
+# ---------------------------------------------------------------------------
+# owner object
+# ---------------------------------------------------------------------------
+
+def _segs(seg, keep) -> KrySegs:
+    lo = np.ascontiguousarray(seg.lo, dtype=np.int64)
+    hi = np.ascontiguousarray(seg.hi, dtype=np.int64)
+    w = np.ascontiguousarray(seg.w, dtype=np.float64)
+    keep += [lo, hi, w]
+    return KrySegs(lo.size, lo.ctypes.data, hi.ctypes.data, w.ctypes.data)
+
+
+class DeviceSystem:
+    """The system matrix, forcing and optional center of a problem in device
+    memory (torch tensors), uploaded once and reusable by many plans.
+    ``problem`` is any object with the attributes of workloads.Problem."""
+
+    def __init__(self, problem, device="cuda"):
+        import torch
+        self.problem = problem
+        self.device = device
+        self.tensors = []
+        s = KrySystem()
+        s.n = problem.n
+        s.symmetric = 1 if problem.symmetric else 0
+        if problem.kind == "csr":
+            s.kind = KRY_CSR
+            self.rowptr = torch.as_tensor(np.asarray(problem.rowptr, np.int64), device=device)
+            self.colidx = torch.as_tensor(np.asarray(problem.colidx, np.int32), device=device)
+            self.vals = torch.as_tensor(np.asarray(problem.vals, np.float64), device=device)
+            s.rowptr, s.colidx, s.vals = _ptr(self.rowptr), _ptr(self.colidx), _ptr(self.vals)
+            s.nnz = int(self.colidx.numel())
+        else:
+            s.kind = KRY_STENCIL7
+            s.nx, s.ny, s.nz = problem.grid
+            s.c0, s.cx, s.cy, s.cz = problem.coef
+        self.b = None
+        if problem.b is not None:
+            self.b = torch.as_tensor(np.asarray(problem.b, np.float64), device=device)
+            s.b = _ptr(self.b)
+        self.center = None
+        if problem.center is not None:
+            self.center = torch.as_tensor(np.asarray(problem.center, np.float64), device=device)
+        s.anorm = 0.0
+        self.sys = s
+
+
+class Plan:
+    """kry_plan_create + owned references.  ``workspace``: 'torch' takes the
+    workspace from torch's caching allocator, 'library' lets the plan
+    allocate its own."""
+
+    def __init__(self, dsys: DeviceSystem, k=None, dt=None, steps=None, precision=KRY_FP64,
+                 method=KRY_AUTO, block_p=0, stream=None, workspace="torch", gens=None, C=None):
+        import torch
+        p = dsys.problem
+        self.dsys = dsys
+        self.k = p.k if k is None else k
+        self.dt = p.dt if dt is None else dt
+        self.steps = p.steps if steps is None else steps
+        gens = p.gens if gens is None else gens
+        C = p.C if C is None else C
+        self.ngen = len(gens)
+        self.o = len(C)
+        keep = []
+        self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
+        self._C = [_segs(c, keep) for c in C]
+        self._keep = keep
+        nruns = self.ngen + (dsys.center is not None) + (dsys.b is not None)
+        self.stream = torch.cuda.current_stream(dsys.device) if stream is None else stream
+        ws_ptr, ws_bytes = None, 0
+        self.workspace = None
+        if workspace == "torch":
+            nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
+            ws_bytes = kry_footprint(dsys.sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
+                                     method, block_p)
+            self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dsys.device)
+            ws_ptr = self.workspace.data_ptr()
+        self.handle = None
+        self.handle = kry_plan_create(dsys.sys, self._gens, _ptr(dsys.center), self._C, self.k, self.dt,
+                                      self.steps, precision, method, block_p, ws_ptr, ws_bytes,
+                                      self.stream.cuda_stream)
+        self.roles = kry_plan_runs(self.handle)
+
+    @property
+    def nruns(self):
+        return len(self.roles)
+
+    def project_expm(self, out=None):
+        """Runs the Krylov processes and fills the basis; ``out`` may be a
+        torch tensor (device or host) of shape (steps+1, o, nruns)."""
+        kry_project_expm(self.handle, _ptr(out))
+        return out
+
+    def basis(self):
+        import torch
+        out = torch.empty((self.steps + 1, self.o, self.nruns), dtype=torch.float64)
+        kry_project_expm(self.handle, out.data_ptr())
+        return out.numpy()
+
+    def check(self, unsafe):
+        v, z = kry_check_box_safety(self.handle, np.asarray(unsafe, np.float64), self.ngen)
+        return {"first_step": int(v.first_step), "row": int(v.row), "status": int(v.status), "y": v.y,
+                "lo": v.lo, "hi": v.hi, "z": z}
+
+    def krylov(self, run: int):
+        return kry_plan_krylov(self.handle, run, self.k, self.o)
+
+    def close(self):
+        if self.handle:
+            kry_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

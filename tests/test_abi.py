@@ -1,0 +1,107 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/kry.h declares, the ctypes structs have the C layout (checked
+against a C program compiled here with gcc), and argument validation
+rejects bad input before any device work."""
+import math
+import os
+import re
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kry.h")
+
+
+def _declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kry_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1804_01583_amd import kry
+    names = _declared_functions()
+    assert "kry_plan_create" in names and "kry_check_box_safety" in names
+    for name in names:
+        assert hasattr(kry.lib, name), name
+    assert set(kry.EXPORTED) == set(names)
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_struct_layout_matches_header(tmp_path):
+    from paper_1804_01583_amd import kry
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "kry.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(kry_system), sizeof(kry_segs),"
+        " sizeof(kry_gen), sizeof(kry_interval), sizeof(kry_verdict), offsetof(kry_system, b),"
+        " offsetof(kry_system, anorm), offsetof(kry_verdict, y)); return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    import ctypes as ct
+    want = [ct.sizeof(kry.KrySystem), ct.sizeof(kry.KrySegs), ct.sizeof(kry.KryGen), ct.sizeof(kry.KryInterval),
+            ct.sizeof(kry.KryVerdict), kry.KrySystem.b.offset, kry.KrySystem.anorm.offset, kry.KryVerdict.y.offset]
+    assert got == want
+
+
+def _csr_system(n=10):
+    from paper_1804_01583_amd import kry
+    s = kry.KrySystem()
+    s.n = n
+    s.kind = kry.KRY_CSR
+    s.symmetric = 1
+    s.rowptr = s.colidx = s.vals = 0x1000   # never dereferenced by validation
+    s.nnz = n
+    return s
+
+
+def test_footprint_is_host_only_and_scales_with_n():
+    from paper_1804_01583_amd import kry
+    small = kry.kry_footprint(_csr_system(10_000), 2, 3, 40, 2000, 300)
+    big = kry.kry_footprint(_csr_system(1_000_000), 2, 3, 40, 2000, 300)
+    # three interleaved vectors of the batch dominate (Lanczos keeps 3 vectors, paper Sec. 3.5)
+    assert big - small >= 3 * 2 * 8 * (1_000_000 - 10_000)
+    assert big - small <= 4 * 2 * 8 * (1_000_000 - 10_000) + (1 << 20)
+
+
+@pytest.mark.parametrize("bad", ["n", "k", "o", "steps", "dt", "seg_order", "seg_range", "nonsym", "fp32"])
+def test_plan_rejects_bad_arguments(bad):
+    from paper_1804_01583_amd import kry
+    import workloads as W
+    s = _csr_system(50)
+    k, steps, dt, o = 5, 10, 0.1, 1
+    gens = [W.Generator(W.segments_from_ranges([(0, 3)]), 0.0, 1.0)]
+    C = [W.segments_from_ranges([(5, 9)])]
+    precision, method = kry.KRY_FP64, kry.KRY_AUTO
+    if bad == "n":
+        s.n = 0
+    elif bad == "k":
+        k = 0
+    elif bad == "o":
+        C = [W.segments_from_ranges([(5, 9)])] * 9
+    elif bad == "steps":
+        steps = -1
+    elif bad == "dt":
+        dt = math.nan
+    elif bad == "seg_order":
+        gens = [W.Generator(W.Segments.__new__(W.Segments), 0.0, 1.0)]
+        gens[0].seg.lo = np.array([5, 0]); gens[0].seg.hi = np.array([7, 2]); gens[0].seg.w = np.ones(2)
+    elif bad == "seg_range":
+        C = [W.segments_from_ranges([(45, 60)])]
+    elif bad == "nonsym":
+        s.symmetric = 0
+        method = kry.KRY_LANCZOS
+    elif bad == "fp32":
+        precision = kry.KRY_FP32_BASIS
+    keep = []
+    kg = [kry.KryGen(kry._segs(g.seg, keep), g.zc, g.radius) for g in gens]
+    kc = [kry._segs(c, keep) for c in C]
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_plan_create(s, kg, None, kc, k, dt, steps, precision, method, 0, 0x100, 1 << 40, None)
+    expected = kry.KRY_ENOTSUP if bad == "fp32" else kry.KRY_EINVAL
+    assert ei.value.status == expected
+    assert len(kry.lib.kry_last_error()) > 0

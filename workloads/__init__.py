@@ -246,7 +246,7 @@ def heat3d_csr(m=100, D=0.01, k=40, dt=0.02, steps=2000, seed=2, unsafe_scale=No
     unsafe = np.stack([thr, np.full(3, math.inf)], axis=1)
     return Problem("heat3d_csr", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
                    b=b, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
-                   meta={"m": m, "forcing_box": fbox, "gen_box": gbox, "center_box": cbox},
+                   meta={"m": m, "forcing_box": fbox, "gen_box": gbox, "center_box": cbox, "coef": coef},
                    note="3D heat CSR with affine forcing")
 
 
