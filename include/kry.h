@@ -115,7 +115,7 @@ typedef struct kry_plan kry_plan;
  * [x_c; 0] when center != NULL (device n-vector), one for the augmented
  * variable [0; 1] when sys->b != NULL.
  *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
- *  k: Krylov dimension per run, 1 <= k <= 64.  The augmented run uses k-1
+ *  k: Krylov dimension per run, 1 <= k <= 56.  The augmented run uses k-1
  *     Lanczos steps on A from b bordered by one row and column, which spans
  *     the same k-dimensional Krylov space of the augmented matrix.
  *  dt, steps: time points s*dt for s = 0..steps (steps + 1 rows of output).

@@ -69,7 +69,7 @@ Profiler& prof() {
 }
 
 const char* kKernelNames =
-    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,eig_coeffs,assemble,check";
+    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,finish,expm_chain,assemble,check";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -104,10 +104,19 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 int64_t rows_per_block_for(int64_t n) {
     const int64_t env = env_int("KRY_ROWS_PER_BLOCK", 0);
     if (env > 0) return align_up((size_t)env, kBlock);
-    const int64_t target_blocks = 2048;
+    // blocks per kernel: enough waves to hide gather latency, few enough that
+    // every block can re-read all block partials of the previous kernel
+    const int64_t target_blocks = env_int("KRY_TARGET_BLOCKS", 1024);
     int64_t rpb = (n + target_blocks - 1) / target_blocks;
     rpb = (int64_t)align_up((size_t)std::max<int64_t>(rpb, kBlock), kBlock);
     return rpb;
+}
+
+// Blocks of the row partition, rounded up to a multiple of the 8 XCDs
+// (trailing blocks may own no rows).
+int32_t nblocks_for(int64_t n, int64_t rpb) {
+    const int64_t nb = (n + rpb - 1) / rpb;
+    return (int32_t)align_up((size_t)nb, 8);
 }
 
 int max_batch_for(int o, int block_p) {
@@ -122,18 +131,20 @@ int max_batch_for(int o, int block_p) {
 }
 
 struct Layout {
-    size_t vec, partials, counter, scal, theta, coef, msize, basis, verdict, anorm, meta, total;
+    size_t vec, np_part, ap_part, scal, zmat, anch, msize, scale, basis, cpart, verdict, anorm, meta, total;
     ScalLayout L;
     int64_t rpb;
     int32_t nblocks;
     int pmax;
+    int32_t B, nanch;
+    int32_t nvp;
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
                    size_t meta_bytes) {
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
-    Y.nblocks = (int32_t)((n + Y.rpb - 1) / Y.rpb);
+    Y.nblocks = nblocks_for(n, Y.rpb);
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
     {
         int p = 1;
@@ -152,13 +163,20 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
     Y.vec = take(3 * (size_t)n * Y.pmax * sizeof(double));
-    Y.partials = take((size_t)Y.nblocks * kMaxNV * sizeof(double));
-    Y.counter = take(64 * sizeof(unsigned int));
+    Y.nvp = Y.pmax * (1 + o);
+    Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
+    Y.ap_part = take((size_t)Y.nblocks * kMaxP * sizeof(double));
     Y.scal = take((size_t)nruns * L.stride * sizeof(double));
-    Y.theta = take((size_t)nruns * k * sizeof(double));
-    Y.coef = take((size_t)nruns * o * k * sizeof(double));
+    // time steps s = b * B + r: B anchors of the Z chain, nanch of the anchor chain
+    Y.B = 1;
+    while ((int64_t)Y.B * Y.B < steps + 1 && Y.B < 256) Y.B <<= 1;
+    Y.nanch = (int32_t)((steps + 1 + Y.B - 1) / Y.B);
+    Y.zmat = take((size_t)nruns * Y.B * kMaxO * kMaxK * sizeof(double));
+    Y.anch = take((size_t)nruns * Y.nanch * kMaxK * sizeof(double));
     Y.msize = take((size_t)nruns * sizeof(int32_t));
+    Y.scale = take((size_t)nruns * sizeof(double));
     Y.basis = take((size_t)(steps + 1) * o * nruns * sizeof(double));
+    Y.cpart = take((size_t)2 * check_blocks(steps, o) * sizeof(double));
     Y.verdict = take((size_t)(6 + nruns) * sizeof(double));
     Y.anorm = take(sizeof(double));
     Y.meta = take(meta_bytes);
@@ -214,6 +232,27 @@ double stencil_inf_norm(const kry_system& s) {
     return best;
 }
 
+// Numerator coefficients of the [13/13] Pade approximant of e^x, scaled so
+// the x^13 coefficient is 1: b_j = (26 - j)! / (j! (13 - j)!), exact in 64-bit
+// integers (the largest, 26!/13!, is below 2^56) and rounded once to double.
+void pade13(double* b) {
+    for (int j = 0; j <= 13; ++j) {
+        uint64_t num = 1;
+        for (int t = 14 - j; t <= 26 - j; ++t) num *= (uint64_t)t;   // (26-j)! / (13-j)!
+        uint64_t den = 1;
+        for (int t = 2; t <= j; ++t) den *= (uint64_t)t;            // j!
+        b[j] = (double)(num / den);
+    }
+}
+
+kry_status prepare_device() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] { err = expm_prepare(); });
+    if (err != hipSuccess) return fail(KRY_EDEVICE, std::string("expm LDS setup: ") + hipGetErrorString(err));
+    return KRY_OK;
+}
+
 }  // namespace
 
 struct kry_plan {
@@ -240,12 +279,14 @@ struct kry_plan {
     std::vector<double> verdict_host;
 
     double* vec(int i) { return reinterpret_cast<double*>(ws + Y.vec) + (size_t)i * sys.n * Y.pmax; }
-    double* partials() { return reinterpret_cast<double*>(ws + Y.partials); }
-    unsigned int* counter() { return reinterpret_cast<unsigned int*>(ws + Y.counter); }
+    double* np_part() { return reinterpret_cast<double*>(ws + Y.np_part); }
+    double* ap_part() { return reinterpret_cast<double*>(ws + Y.ap_part); }
     double* scal() { return reinterpret_cast<double*>(ws + Y.scal); }
-    double* theta() { return reinterpret_cast<double*>(ws + Y.theta); }
-    double* coef() { return reinterpret_cast<double*>(ws + Y.coef); }
+    double* zmat() { return reinterpret_cast<double*>(ws + Y.zmat); }
+    double* anch() { return reinterpret_cast<double*>(ws + Y.anch); }
     int32_t* msize() { return reinterpret_cast<int32_t*>(ws + Y.msize); }
+    double* scale() { return reinterpret_cast<double*>(ws + Y.scale); }
+    double* cpart() { return reinterpret_cast<double*>(ws + Y.cpart); }
     double* basis() { return reinterpret_cast<double*>(ws + Y.basis); }
     double* verdict() { return reinterpret_cast<double*>(ws + Y.verdict); }
     double* anorm() { return reinterpret_cast<double*>(ws + Y.anorm); }
@@ -255,8 +296,9 @@ namespace {
 
 // Metadata block uploaded once per plan: segment table, per-run roles and
 // box coefficients.
-size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns) {
+size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns, int32_t nblocks) {
     size_t b = 0;
+    b = align_up(b + (size_t)nsets * nblocks * 2 * 4, 16);   // per-block segment ranges
     b = align_up(b + (size_t)total_segs * 8, 16);   // lo
     b = align_up(b + (size_t)total_segs * 8, 16);   // hi
     b = align_up(b + (size_t)total_segs * 8, 16);   // w
@@ -299,10 +341,11 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (st != KRY_OK) return st;
     if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
     if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kMaxK || steps < 0 || nseg_total < 0)
-        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 64, steps >= 0, nseg_total >= 0 required");
+        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56, steps >= 0, nseg_total >= 0 required");
     if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
     (void)method;
-    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns));
+    const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
+    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns, nb));
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -318,7 +361,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (st != KRY_OK) return st;
     if (ngen < 0 || (ngen > 0 && !gens)) return fail(KRY_EINVAL, "bad generator list");
     if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
-    if (k < 1 || k > kMaxK) return fail(KRY_EINVAL, "k must be in [1, 64]");
+    if (k < 1 || k > kMaxK) return fail(KRY_EINVAL, "k must be in [1, 56]");
     if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
     if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
@@ -338,6 +381,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
         if (st != KRY_OK) return st;
     }
 
+    st = prepare_device();
+    if (st != KRY_OK) return st;
     auto* plan = new kry_plan();
     plan->sys = *sys;
     plan->ngen = ngen;
@@ -366,7 +411,9 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     for (int32_t q = 0; q < o; ++q) total_segs += C[q].nseg;
     if (total_segs >= ((int64_t)1 << 31)) { delete plan; return fail(KRY_EINVAL, "too many segments"); }
     const int32_t nsets = ngen + o;
-    const size_t mbytes = meta_size(total_segs, nsets, plan->nruns);
+    const int64_t rpb = rows_per_block_for(n);
+    const int32_t nblk = nblocks_for(n, rpb);
+    const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
     plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes);
     const Layout& Y = plan->Y;
 
@@ -394,6 +441,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     plan->meta_host.assign(mbytes, 0);
     char* base = plan->meta_host.data();
     size_t off = 0;
+    auto* blk = reinterpret_cast<int32_t*>(base + off); off = align_up(off + (size_t)nsets * Y.nblocks * 2 * 4, 16);
     auto* lo = reinterpret_cast<int64_t*>(base + off); off = align_up(off + total_segs * 8, 16);
     auto* hi = reinterpret_cast<int64_t*>(base + off); off = align_up(off + total_segs * 8, 16);
     auto* w = reinterpret_cast<double*>(base + off); off = align_up(off + total_segs * 8, 16);
@@ -411,12 +459,27 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     plan->oset0 = set;
     for (int32_t q = 0; q < o; ++q) add_set(C[q]);
     sb[set] = (int32_t)at;
+    // per logical block b (rows [b*rpb, (b+1)*rpb)), the segments of each set
+    // that overlap it: [first with hi > row0, first with lo >= row1)
+    for (int32_t s = 0; s < nsets; ++s) {
+        int32_t first = sb[s], last = sb[s];
+        for (int32_t b = 0; b < Y.nblocks; ++b) {
+            const int64_t r0 = (int64_t)b * Y.rpb;
+            const int64_t r1 = std::min(n, r0 + Y.rpb);
+            while (first < sb[s + 1] && hi[first] <= r0) ++first;
+            if (last < first) last = first;
+            while (last < sb[s + 1] && lo[last] < r1) ++last;
+            blk[((int64_t)s * Y.nblocks + b) * 2] = first;
+            blk[((int64_t)s * Y.nblocks + b) * 2 + 1] = r1 > r0 ? last : first;
+        }
+    }
     for (int32_t r = 0; r < plan->nruns; ++r) { rl[r] = plan->role[r]; zc[r] = plan->zc[r]; rd[r] = plan->radius[r]; }
     char* dmeta = plan->ws + Y.meta;
     plan->T.lo = reinterpret_cast<const int64_t*>(dmeta + ((char*)lo - base));
     plan->T.hi = reinterpret_cast<const int64_t*>(dmeta + ((char*)hi - base));
     plan->T.w = reinterpret_cast<const double*>(dmeta + ((char*)w - base));
     plan->T.set_begin = reinterpret_cast<const int32_t*>(dmeta + ((char*)sb - base));
+    plan->T.blk = reinterpret_cast<const int32_t*>(dmeta + ((char*)blk - base));
     plan->role_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)rl - base));
     plan->zc_dev = reinterpret_cast<double*>(dmeta + ((char*)zc - base));
     plan->rad_dev = reinterpret_cast<double*>(dmeta + ((char*)rd - base));
@@ -424,8 +487,6 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     auto cleanup = [&](kry_status s) { kry_plan_destroy(plan); return s; };
     if (hipMemcpyAsync(dmeta, base, mbytes, hipMemcpyHostToDevice, plan->stream) != hipSuccess)
         return cleanup(fail(KRY_EDEVICE, "metadata upload failed"));
-    if (launch_fill_zero_u32(plan->counter(), 64, plan->stream) != hipSuccess)
-        return cleanup(fail(KRY_EDEVICE, "counter reset launch failed"));
 
     // ||A||_inf scales the breakdown test
     if (sys->anorm > 0.0 || sys->kind == KRY_STENCIL7) {
@@ -439,8 +500,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     } else {
         CsrArgs A{sys->rowptr, sys->colidx, sys->vals};
         hipError_t e = timed("row_abs_max", plan->stream, [&] {
-            return launch_row_abs_max(A, n, plan->partials(), Y.nblocks, Y.rpb, plan->counter(),
-                                      plan->anorm(), plan->stream);
+            return launch_row_abs_max(A, n, plan->np_part(), Y.nblocks, Y.rpb, plan->anorm(), plan->stream);
         });
         if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e)));
     }
@@ -466,11 +526,13 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         B.n = n;
         B.rows_per_block = Y.rpb;
         B.nblocks = Y.nblocks;
+        B.xcd_map = env_int("KRY_XCD_MAP", 1) != 0 ? 1 : 0;
         B.run0 = r0;
         B.scal = plan->scal();
         B.L = Y.L;
-        B.partials = plan->partials();
-        B.counter = plan->counter();
+        B.np_part = plan->np_part();
+        B.nvp = Y.nvp;
+        B.ap_part = plan->ap_part();
         B.anorm = plan->anorm();
         B.tau_scale = tau_scale;
         StartSrc src{};
@@ -501,13 +563,26 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             e = timed("sweep", s, [&] { return launch_sweep(P, plan->o, plan->T, plan->oset0, ucur, w, B, j, s); });
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
         }
+        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, s); });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
         r0 += P;
     }
-    ExpmArgs E{plan->scal(), Y.L, plan->role_dev, plan->theta(), plan->coef(), plan->msize()};
-    hipError_t e = timed("eig_coeffs", s, [&] { return launch_eig_coeffs(E, plan->nruns, s); });
-    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("eig_coeffs: ") + hipGetErrorString(e));
-    AssembleArgs A{plan->theta(), plan->coef(), plan->msize(), plan->role_dev, plan->nruns, plan->o,
-                   plan->k, plan->steps, plan->dt, plan->basis()};
+    ExpmArgs E{};
+    E.scal = plan->scal();
+    E.L = Y.L;
+    E.role = plan->role_dev;
+    E.dt = plan->dt;
+    E.B = Y.B;
+    E.nanch = Y.nanch;
+    pade13(E.pade);
+    E.Z = plan->zmat();
+    E.anch = plan->anch();
+    E.msize = plan->msize();
+    E.scale = plan->scale();
+    hipError_t e = timed("expm_chain", s, [&] { return launch_expm_chain(E, plan->nruns, s); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("expm_chain: ") + hipGetErrorString(e));
+    AssembleArgs A{plan->zmat(), plan->anch(), plan->msize(), plan->scale(), plan->nruns, plan->o,
+                   Y.B, Y.nanch, plan->steps, plan->basis()};
     e = timed("assemble", s, [&] { return launch_assemble(A, s); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("assemble: ") + hipGetErrorString(e));
     plan->projected = true;
@@ -540,6 +615,7 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
         C.ulo[q] = unsafe[q].lo;
         C.uhi[q] = unsafe[q].hi;
     }
+    C.part = plan->cpart();
     C.verdict = plan->verdict();
     hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));

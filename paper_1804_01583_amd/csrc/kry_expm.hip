@@ -2,15 +2,16 @@
 // Section 4.2, Eq. approx-formula), the basis matrix of Section 3.2 and the
 // per-step box check that stands in for the LP of Section 2.1.
 //
-// For the symmetric tridiagonal H of Lanczos, H = Q diag(theta) Q^T is
-// computed once per run by a parallel cyclic Jacobi method (Golub & Van Loan,
-// Matrix Computations, Sec. 8.5: symmetric 2x2 Schur rotations applied to
-// disjoint pairs chosen by a round-robin ordering), held in LDS by one
-// workgroup.  Then every step is independent:
-//   generator / center run:  y_s = beta0 * P Q diag(e^{theta s dt}) Q^T e_1
-//   augmented run [0;1]:     H~ = [[0, 0], [|b| e_1, T]] gives
-//                            y_s = |b| * P Q diag((e^{theta t} - 1)/theta) Q^T e_1
-// so no step depends on the previous one and no error accumulates over steps.
+// Per run, one workgroup keeps H in LDS and computes
+//   Phi = e^{H dt}   by Pade [13/13] with scaling and squaring
+//                    (N. J. Higham, SIAM J. Matrix Anal. Appl. 26(4), 2005),
+//   Psi = Phi^B      by squaring (B a power of two near sqrt(steps + 1)),
+// then two short chains, Z_r = P Phi^r (r < B) and a_b = Psi^b e_1, so that
+//   y_s = beta0 * Z_{s mod B} a_{s div B},   s = 0..steps,
+// is assembled for all steps in parallel by k_assemble.  The chains are
+// at most B and (steps+1)/B long, instead of one recurrence over all steps.
+// The augmented run uses the bordered matrix H~ = [[0, 0], [|b| e_1, T]] and
+// P~ = [0, C Q] with scale 1; generator and center runs use T itself.
 #include "kry_internal.h"
 
 #include <cmath>
@@ -19,136 +20,268 @@ namespace kry {
 
 namespace {
 
-constexpr int kLd = kMaxK + 1;   // padded LDS row length
+constexpr int kLd = kMaxK + 1;          // padded LDS row length
+constexpr int kSlot = kMaxK * kLd;      // one matrix in LDS
+constexpr double kTheta13 = 5.371920351148152;   // Higham 2005: degree-13 limit of |X|_1
 
-__device__ __forceinline__ double* run_scal(const ExpmArgs& E, int r) {
+__device__ __forceinline__ const double* run_scal(const ExpmArgs& E, int r) {
     return E.scal + (int64_t)r * E.L.stride;
 }
 
-// One workgroup per run.
-__global__ __launch_bounds__(kBlock) void k_eig_coeffs(ExpmArgs E) {
-    __shared__ double A[kMaxK * kLd];
-    __shared__ double Q[kMaxK * kLd];
-    __shared__ double s_c[kMaxK / 2], s_s[kMaxK / 2];
-    __shared__ int s_p[kMaxK / 2], s_q[kMaxK / 2];
-    __shared__ double s_red[2 * (kBlock / 64)];
-    __shared__ int s_stop;
+// C = A * B(l, j) for mm x mm matrices in LDS (mm even); `extra(i, j)` is
+// added to each entry.  Each thread owns 2x2 output blocks.  C must not
+// alias A or the storage B reads.
+template <class FB, class FE>
+__device__ __forceinline__ void mm_lds(const double* A, FB Bf, double* C, int mm, FE extra) {
+    const int nb = mm >> 1;
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+        const int i = 2 * (t / nb), j = 2 * (t % nb);
+        double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+        for (int l = 0; l < mm; ++l) {
+            const double a0 = A[i * kLd + l], a1 = A[(i + 1) * kLd + l];
+            const double b0 = Bf(l, j), b1 = Bf(l, j + 1);
+            c00 = fma(a0, b0, c00);
+            c01 = fma(a0, b1, c01);
+            c10 = fma(a1, b0, c10);
+            c11 = fma(a1, b1, c11);
+        }
+        C[i * kLd + j] = c00 + extra(i, j);
+        C[i * kLd + j + 1] = c01 + extra(i, j + 1);
+        C[(i + 1) * kLd + j] = c10 + extra(i + 1, j);
+        C[(i + 1) * kLd + j + 1] = c11 + extra(i + 1, j + 1);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void square_lds(const double* A, double* C, int mm) {
+    mm_lds(A, [A](int l, int j) { return A[l * kLd + j]; }, C, mm, [](int, int) { return 0.0; });
+}
+
+// Solve M F = R in place (F overwrites R) by Gauss-Jordan elimination with
+// partial pivoting; M is destroyed.  mm <= 64 so one wave finds the pivot.
+__device__ void solve_lds(double* M, double* R, int mm, int* s_piv, double* s_f) {
+    for (int c = 0; c < mm; ++c) {
+        if (threadIdx.x < 64) {
+            const int r = c + threadIdx.x;
+            double v = (r < mm) ? fabs(M[r * kLd + c]) : -1.0;
+            int at = r;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(v, off, 64);
+                const int oa = __shfl_xor(at, off, 64);
+                if (ov > v || (ov == v && oa < at)) { v = ov; at = oa; }
+            }
+            if (threadIdx.x == 0) *s_piv = at;
+        }
+        __syncthreads();
+        const int piv = *s_piv;
+        if (piv != c) {
+            for (int j = threadIdx.x; j < 2 * mm; j += blockDim.x) {
+                double* X = (j < mm) ? M : R;
+                const int jj = (j < mm) ? j : j - mm;
+                const double t = X[c * kLd + jj];
+                X[c * kLd + jj] = X[piv * kLd + jj];
+                X[piv * kLd + jj] = t;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < mm) s_f[threadIdx.x] = M[threadIdx.x * kLd + c];
+        __syncthreads();
+        const double inv = 1.0 / s_f[c];
+        for (int j = threadIdx.x; j < 2 * mm; j += blockDim.x) {
+            double* X = (j < mm) ? M : R;
+            const int jj = (j < mm) ? j : j - mm;
+            X[c * kLd + jj] *= inv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < mm * 2 * mm; e += blockDim.x) {
+            const int r = e / (2 * mm), j = e % (2 * mm);
+            if (r == c) continue;
+            double* X = (j < mm) ? M : R;
+            const int jj = (j < mm) ? j : j - mm;
+            X[r * kLd + jj] = fma(-s_f[r], X[c * kLd + jj], X[r * kLd + jj]);
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per run: Phi, Psi and the two chains.
+__global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
+    extern __shared__ double lds[];
+    double* S0 = lds;
+    double* S1 = lds + 1 * kSlot;
+    double* S2 = lds + 2 * kSlot;
+    double* S3 = lds + 3 * kSlot;
+    double* S4 = lds + 4 * kSlot;
+    double* S5 = lds + 5 * kSlot;
+    __shared__ double s_f[kMaxK];
+    __shared__ double s_red[kExpmThreads / 64];
+    __shared__ int s_piv;
 
     const int run = blockIdx.x;
     const double* sc = run_scal(E, run);
     const int k = E.L.k, o = E.L.o;
     const int keff = (int)sc[E.L.misc + MISC_KEFF];
-    int m = keff;
-    if (E.role[run] == 2 && m > k - 1) m = k - 1;   // augmented run: k-1 Lanczos steps + border
-    if (threadIdx.x == 0) E.msize[run] = m;
-    if (m <= 0) return;
-    const int mm = m + (m & 1);        // even size for the round-robin pairing
-    const int half = mm / 2;
+    const bool bordered = E.role[run] == 2;
+    int m = keff;                            // size of H
+    if (bordered) m = (keff > k - 1 ? k - 1 : keff) + 1;
+    if (keff <= 0) m = 0;                    // zero start vector: the run contributes nothing
+    if (threadIdx.x == 0) {
+        E.msize[run] = m;
+        E.scale[run] = bordered ? 1.0 : sc[E.L.beta + 0];
+    }
+    if (m == 0) return;
+    const int mm = m + (m & 1);
     const int tid = threadIdx.x;
 
-    for (int idx = tid; idx < mm * mm; idx += kBlock) {
+    // X = H dt (zero padded to mm)
+    for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
         const int i = idx / mm, c = idx % mm;
-        double a = 0.0;
+        double h = 0.0;
         if (i < m && c < m) {
-            if (i == c) a = sc[E.L.alpha + i + 1];
-            else if (c == i + 1) a = sc[E.L.beta + i + 1];
-            else if (i == c + 1) a = sc[E.L.beta + c + 1];
+            if (!bordered) {
+                if (i == c) h = sc[E.L.alpha + i + 1];
+                else if (c == i + 1) h = sc[E.L.beta + i + 1];
+                else if (i == c + 1) h = sc[E.L.beta + c + 1];
+            } else {
+                // row/column 0 is the augmented variable; T occupies 1..m-1
+                if (i == 1 && c == 0) h = sc[E.L.beta + 0];
+                else if (i >= 1 && c >= 1) {
+                    const int a = i - 1, b = c - 1;
+                    if (a == b) h = sc[E.L.alpha + a + 1];
+                    else if (b == a + 1) h = sc[E.L.beta + a + 1];
+                    else if (a == b + 1) h = sc[E.L.beta + b + 1];
+                }
+            }
         }
-        A[i * kLd + c] = a;
-        Q[i * kLd + c] = (i == c) ? 1.0 : 0.0;
+        S0[i * kLd + c] = h * E.dt;
     }
     __syncthreads();
 
-    const double eps = 2.220446049250313e-16;
-    const int N = mm - 1;              // rotating players 0..N-1, fixed player N
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        // convergence: off(A) <= eps * |A|_F
-        double v[2] = {0.0, 0.0};
-        for (int idx = tid; idx < mm * mm; idx += kBlock) {
-            const int i = idx / mm, c = idx % mm;
-            const double a = A[i * kLd + c];
-            v[1] = fma(a, a, v[1]);
-            if (i != c) v[0] = fma(a, a, v[0]);
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            v[0] += __shfl_xor(v[0], off, 64);
-            v[1] += __shfl_xor(v[1], off, 64);
-        }
-        if ((tid & 63) == 0) { s_red[2 * (tid >> 6)] = v[0]; s_red[2 * (tid >> 6) + 1] = v[1]; }
-        __syncthreads();
-        if (tid == 0) {
-            double off2 = 0.0, fro2 = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w) { off2 += s_red[2 * w]; fro2 += s_red[2 * w + 1]; }
-            s_stop = (off2 <= eps * eps * fro2) ? 1 : 0;
-        }
-        __syncthreads();
-        if (s_stop) break;
-
-        for (int round = 0; round < N; ++round) {
-            if (tid < half) {
-                int p, q;
-                if (tid == 0) { p = round; q = N; }
-                else { p = (round + tid) % N; q = (round - tid + N) % N; }
-                if (p > q) { const int t = p; p = q; q = t; }
-                const double apq = A[p * kLd + q];
-                double c = 1.0, s = 0.0;
-                if (apq != 0.0) {
-                    const double tau = (A[q * kLd + q] - A[p * kLd + p]) / (2.0 * apq);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                s_p[tid] = p; s_q[tid] = q; s_c[tid] = c; s_s[tid] = s;
-            }
-            __syncthreads();
-            // rows: A <- J^T A
-            for (int idx = tid; idx < half * mm; idx += kBlock) {
-                const int pr = idx / mm, x = idx % mm;
-                const int p = s_p[pr], q = s_q[pr];
-                const double c = s_c[pr], s = s_s[pr];
-                const double ap = A[p * kLd + x], aq = A[q * kLd + x];
-                A[p * kLd + x] = c * ap - s * aq;
-                A[q * kLd + x] = s * ap + c * aq;
-            }
-            __syncthreads();
-            // columns: A <- A J, Q <- Q J
-            for (int idx = tid; idx < half * mm; idx += kBlock) {
-                const int pr = idx / mm, x = idx % mm;
-                const int p = s_p[pr], q = s_q[pr];
-                const double c = s_c[pr], s = s_s[pr];
-                const double ap = A[x * kLd + p], aq = A[x * kLd + q];
-                A[x * kLd + p] = c * ap - s * aq;
-                A[x * kLd + q] = s * ap + c * aq;
-                const double qp = Q[x * kLd + p], qq = Q[x * kLd + q];
-                Q[x * kLd + p] = c * qp - s * qq;
-                Q[x * kLd + q] = s * qp + c * qq;
-            }
-            __syncthreads();
-            if (tid < half) {
-                const int p = s_p[tid], q = s_q[tid];
-                A[p * kLd + q] = 0.0;
-                A[q * kLd + p] = 0.0;
-            }
-            __syncthreads();
-        }
+    // scaling: |X|_1 <= theta_13 after dividing by 2^sq
+    double colsum = 0.0;
+    if (tid < mm) {
+        for (int i = 0; i < mm; ++i) colsum += fabs(S0[i * kLd + tid]);
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) colsum = fmax(colsum, __shfl_xor(colsum, off, 64));
+    if ((tid & 63) == 0) s_red[tid >> 6] = colsum;
+    __syncthreads();
+    double nrm = 0.0;
+    for (int w = 0; w < (int)blockDim.x / 64; ++w) nrm = fmax(nrm, s_red[w]);
+    int sq = 0;
+    if (nrm > kTheta13) sq = (int)ceil(log2(nrm / kTheta13));
+    const double shrink = ldexp(1.0, -sq);
+    __syncthreads();
+    for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
+        const int i = idx / mm, c = idx % mm;
+        S0[i * kLd + c] *= shrink;
+    }
+    __syncthreads();
 
-    // theta_i and coef[q][i] = beta0 * (P Q)[q,i] * Q[0,i]
-    const double beta0 = sc[E.L.beta + 0];
-    double* theta = E.theta + (int64_t)run * k;
-    double* coef = E.coef + (int64_t)run * o * k;
-    for (int i = tid; i < m; i += kBlock) theta[i] = A[i * kLd + i];
-    for (int idx = tid; idx < o * m; idx += kBlock) {
-        const int q = idx / m, i = idx % m;
-        const double* Prow = sc + E.L.proj + q * (k + 1);
-        double s = 0.0;
-        for (int l = 0; l < m; ++l) s = fma(Prow[l], Q[l * kLd + i], s);
-        coef[q * k + i] = beta0 * s * Q[0 * kLd + i];
+    // Pade [13/13]: U = X (X6 (b13 X6 + b11 X4 + b9 X2) + b7 X6 + b5 X4 + b3 X2 + b1 I)
+    //               V =    X6 (b12 X6 + b10 X4 + b8 X2) + b6 X6 + b4 X4 + b2 X2 + b0 I
+    const double* b = E.pade;
+    square_lds(S0, S1, mm);                                                    // X2
+    square_lds(S1, S2, mm);                                                    // X4
+    mm_lds(S2, [S1](int l, int j) { return S1[l * kLd + j]; }, S3, mm,
+           [](int, int) { return 0.0; });                                      // X6
+    mm_lds(S3, [=](int l, int j) {
+               const int e = l * kLd + j;
+               return b[13] * S3[e] + b[11] * S2[e] + b[9] * S1[e];
+           }, S4, mm, [=](int i, int j) {
+               const int e = i * kLd + j;
+               return b[7] * S3[e] + b[5] * S2[e] + b[3] * S1[e] + (i == j ? b[1] : 0.0);
+           });                                                                 // U' in S4
+    mm_lds(S3, [=](int l, int j) {
+               const int e = l * kLd + j;
+               return b[12] * S3[e] + b[10] * S2[e] + b[8] * S1[e];
+           }, S5, mm, [=](int i, int j) {
+               const int e = i * kLd + j;
+               return b[6] * S3[e] + b[4] * S2[e] + b[2] * S1[e] + (i == j ? b[0] : 0.0);
+           });                                                                 // V in S5
+    mm_lds(S0, [S4](int l, int j) { return S4[l * kLd + j]; }, S1, mm,
+           [](int, int) { return 0.0; });                                      // U in S1
+    for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
+        const int e = (idx / mm) * kLd + idx % mm;
+        const double u = S1[e], v = S5[e];
+        S5[e] = v - u;
+        S1[e] = v + u;
+    }
+    __syncthreads();
+    solve_lds(S5, S1, mm, &s_piv, s_f);                                        // r13(X) in S1
+
+    // LDS matrices below are addressed as lds + slot * kSlot with an integer
+    // slot, never through stored pointers, so the accesses stay ds_* (LDS)
+    // instructions instead of generic flat ones.
+    // undo the scaling: Phi = r13(X)^(2^sq), ping-pong between slots 1 and 2
+    int phi = 1;
+    for (int i = 0; i < sq; ++i) {
+        square_lds(lds + phi * kSlot, lds + (3 - phi) * kSlot, mm);
+        phi = 3 - phi;
+    }
+    // Psi = Phi^B, ping-pong between slots 3 and 4
+    int psi = phi;
+    for (int e = 1, nxt = 3; e < E.B; e <<= 1) {
+        square_lds(lds + psi * kSlot, lds + nxt * kSlot, mm);
+        psi = nxt;
+        nxt = 7 - nxt;
+    }
+    const double* Phi = lds + phi * kSlot;
+    const double* Psi = lds + psi * kSlot;
+
+    // chains: Z_{r+1} = Z_r Phi (r + 1 < B), a_{b+1} = Psi a_b (b + 1 < nanch);
+    // slot 0 holds the ping-pong buffers: Z at [cur * kMaxO * kLd], a at [2 * kMaxO * kLd + cur * kLd]
+    constexpr int kZ = kMaxO * kLd;
+    for (int idx = tid; idx < o * mm; idx += blockDim.x) {
+        const int q = idx / mm, c = idx % mm;
+        double pv = 0.0;
+        if (c < m) {
+            const int col = bordered ? c - 1 : c;
+            pv = (col >= 0) ? sc[E.L.proj + q * (k + 1) + col] : 0.0;
+        }
+        lds[q * kLd + c] = pv;
+    }
+    if (tid < mm) lds[2 * kZ + tid] = (tid == 0) ? 1.0 : 0.0;
+    __syncthreads();
+    double* Zg = E.Z + (int64_t)run * E.B * kMaxO * kMaxK;
+    double* Ag = E.anch + (int64_t)run * E.nanch * kMaxK;
+    const int iters = max(E.B, E.nanch);
+    for (int r = 0; r < iters; ++r) {
+        const int cur = r & 1, nxt = cur ^ 1;
+        const double* zc = lds + cur * kZ;
+        const double* ac = lds + 2 * kZ + cur * kLd;
+        // publish step r
+        if (r < E.B) {
+            for (int idx = tid; idx < o * mm; idx += blockDim.x) {
+                const int q = idx / mm, c = idx % mm;
+                Zg[((int64_t)r * kMaxO + q) * kMaxK + c] = zc[q * kLd + c];
+            }
+        }
+        if (r < E.nanch) {
+            for (int c = tid; c < mm; c += blockDim.x) Ag[(int64_t)r * kMaxK + c] = ac[c];
+        }
+        // advance
+        if (tid < o * mm) {
+            if (r + 1 < E.B) {
+                const int q = tid / mm, c = tid % mm;
+                double acc = 0.0;
+                for (int l = 0; l < mm; ++l) acc = fma(zc[q * kLd + l], Phi[l * kLd + c], acc);
+                lds[nxt * kZ + q * kLd + c] = acc;
+            }
+        } else if (tid < o * mm + mm) {
+            if (r + 1 < E.nanch) {
+                const int i = tid - o * mm;
+                double acc = 0.0;
+                for (int l = 0; l < mm; ++l) acc = fma(Psi[i * kLd + l], ac[l], acc);
+                lds[2 * kZ + nxt * kLd + i] = acc;
+            }
+        }
+        __syncthreads();
     }
 }
 
-// basis[s][q][run] = sum_i coef[q][i] f(theta_i, s dt), one thread per (s, run)
+// basis[s][q][run] = scale * Z_{s mod B}[q] . a_{s div B}; one thread per (s, run)
 __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (A.steps + 1) * A.nruns;
@@ -156,35 +289,37 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     const int64_t s = idx / A.nruns;
     const int run = (int)(idx % A.nruns);
     const int m = A.msize[run];
-    const double t = (double)s * A.dt;
-    const bool bordered = A.role[run] == 2;
-    const double* theta = A.theta + (int64_t)run * A.k;
-    const double* coef = A.coef + (int64_t)run * A.o * A.k;
     double y[kMaxO];
 #pragma unroll
     for (int q = 0; q < kMaxO; ++q) y[q] = 0.0;
-    for (int i = 0; i < m; ++i) {
-        const double th = theta[i];
-        double f;
-        if (bordered) f = (th != 0.0) ? expm1(th * t) / th : t;
-        else f = exp(th * t);
+    if (m > 0) {
+        const double* z = A.Z + (((int64_t)run * A.B + (s % A.B)) * kMaxO) * kMaxK;
+        const double* a = A.anch + ((int64_t)run * A.nanch + (s / A.B)) * kMaxK;
+        for (int i = 0; i < m; ++i) {
+            const double ai = a[i];
 #pragma unroll
-        for (int q = 0; q < kMaxO; ++q)
-            if (q < A.o) y[q] = fma(coef[q * A.k + i], f, y[q]);
+            for (int q = 0; q < kMaxO; ++q)
+                if (q < A.o) y[q] = fma(z[q * kMaxK + i], ai, y[q]);
+        }
+        const double sc = A.scale[run];
+#pragma unroll
+        for (int q = 0; q < kMaxO; ++q) y[q] *= sc;
     }
 #pragma unroll
     for (int q = 0; q < kMaxO; ++q)
         if (q < A.o) A.basis[(s * A.o + q) * A.nruns + run] = y[q];
 }
 
-// a9: first violated (step, row) and its counter-example.  One workgroup.
-__global__ __launch_bounds__(kBlock) void k_check(CheckArgs C) {
+// a9, part 1: each block finds the first violated (step, row) among its
+// entries (step-major order) and whether a non-finite range was met.
+__global__ __launch_bounds__(kBlock) void k_check_blocks(CheckArgs C) {
     __shared__ long long s_min[kBlock / 64];
     __shared__ int s_bad[kBlock / 64];
     const int64_t total = (C.steps + 1) * C.o;
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     long long best = total;
     int bad = 0;
-    for (int64_t e = threadIdx.x; e < total; e += kBlock) {
+    if (e < total) {
         const int64_t s = e / C.o;
         const int q = (int)(e % C.o);
         const double* M = C.basis + (s * C.o + q) * C.nruns;
@@ -193,9 +328,8 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs C) {
             mid = fma(M[r], C.zc[r], mid);
             rad = fma(fabs(M[r]), C.radius[r], rad);
         }
-        if (!isfinite(mid) || !isfinite(rad)) { bad = 1; continue; }
-        const bool hit = (mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q]);
-        if (hit && e < best) best = e;
+        if (!isfinite(mid) || !isfinite(rad)) bad = 1;
+        else if ((mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q])) best = e;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -205,22 +339,48 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs C) {
     }
     if ((threadIdx.x & 63) == 0) { s_min[threadIdx.x >> 6] = best; s_bad[threadIdx.x >> 6] = bad; }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            best = s_min[w] < best ? s_min[w] : best;
+            bad |= s_bad[w];
+        }
+        C.part[2 * blockIdx.x] = (double)best;
+        C.part[2 * blockIdx.x + 1] = (double)bad;
+    }
+}
+
+// a9, part 2: the first violation over all blocks and its counter-example.
+__global__ __launch_bounds__(kBlock) void k_check_final(CheckArgs C, int nb) {
+    __shared__ double s_min[kBlock / 64];
+    __shared__ double s_bad[kBlock / 64];
+    const double total = (double)((C.steps + 1) * C.o);
+    double best = total, bad = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        best = fmin(best, C.part[2 * b]);
+        bad = fmax(bad, C.part[2 * b + 1]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        best = fmin(best, __shfl_xor(best, off, 64));
+        bad = fmax(bad, __shfl_xor(bad, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) { s_min[threadIdx.x >> 6] = best; s_bad[threadIdx.x >> 6] = bad; }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     for (int w = 1; w < kBlock / 64; ++w) {
-        best = s_min[w] < best ? s_min[w] : best;
-        bad |= s_bad[w];
+        best = fmin(best, s_min[w]);
+        bad = fmax(bad, s_bad[w]);
     }
-    best = s_min[0] < best ? s_min[0] : best;
-    bad |= s_bad[0];
     double* out = C.verdict;
-    out[5] = bad ? 4.0 : 0.0;    // KRY_ENUMERIC
+    out[5] = bad > 0.0 ? 4.0 : 0.0;    // KRY_ENUMERIC
     if (best >= total) {
         out[0] = -1.0; out[1] = -1.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
         for (int r = 0; r < C.nruns; ++r) out[6 + r] = C.zc[r];
         return;
     }
-    const int64_t s = best / C.o;
-    const int q = (int)(best % C.o);
+    const int64_t e = (int64_t)best;
+    const int64_t s = e / C.o;
+    const int q = (int)(e % C.o);
     const double* M = C.basis + (s * C.o + q) * C.nruns;
     double mid = 0.0, rad = 0.0;
     for (int r = 0; r < C.nruns; ++r) {
@@ -243,9 +403,16 @@ __global__ __launch_bounds__(kBlock) void k_check(CheckArgs C) {
 
 }  // namespace
 
-hipError_t launch_eig_coeffs(const ExpmArgs& E, int32_t nruns, hipStream_t s) {
+size_t expm_lds_bytes() { return (size_t)6 * kSlot * sizeof(double); }
+
+hipError_t expm_prepare() {
+    return hipFuncSetAttribute((const void*)k_expm_chain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)expm_lds_bytes());
+}
+
+hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s) {
     if (nruns <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eig_coeffs, dim3(nruns), dim3(kBlock), 0, s, E);
+    hipLaunchKernelGGL(k_expm_chain, dim3(nruns), dim3(kExpmThreads), expm_lds_bytes(), s, E);
     return hipGetLastError();
 }
 
@@ -256,8 +423,14 @@ hipError_t launch_assemble(const AssembleArgs& A, hipStream_t s) {
     return hipGetLastError();
 }
 
+int check_blocks(int64_t steps, int32_t o) { return (int)(((steps + 1) * o + kBlock - 1) / kBlock); }
+
 hipError_t launch_check(const CheckArgs& C, hipStream_t s) {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, C);
+    const int nb = check_blocks(C.steps, C.o);
+    hipLaunchKernelGGL(k_check_blocks, dim3(nb), dim3(kBlock), 0, s, C);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_check_final, dim3(1), dim3(kBlock), 0, s, C, nb);
     return hipGetLastError();
 }
 

@@ -10,9 +10,10 @@ namespace kry {
 
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kMaxO = 8;         // output rows
-constexpr int kMaxK = 64;        // Krylov dimension (eigen-solve held in LDS)
+constexpr int kMaxK = 56;        // Krylov dimension (six k x k matrices held in LDS)
+constexpr int kExpmThreads = 512;
 constexpr int kMaxP = 8;         // runs advanced per mat-vec launch
-constexpr int kMaxNV = 40;       // values reduced per block: P * (1 + O)
+constexpr int kMaxNV = 24;       // values reduced per block: P * (1 + O)
 
 // All segment sets of a plan (generators and output rows) concatenated:
 // set s owns segments [set_begin[s], set_begin[s+1]), sorted and disjoint.
@@ -21,6 +22,7 @@ struct SegTable {
     const int64_t* hi;
     const double* w;
     const int32_t* set_begin;
+    const int32_t* blk;      // [nsets][nblocks][2]: segments of set s overlapping logical block b
 };
 
 // Per-run scalars live in one FP64 array; run r starts at r * stride.
@@ -41,15 +43,23 @@ struct ScalLayout {
 enum { MISC_KEFF = 0, MISC_DONE = 1, MISC_NONFINITE = 2, MISC_COUNT = 4 };
 
 // One batch of runs that a mat-vec launch advances together.
+//
+// Grid-wide sums never cross blocks inside a kernel: each block writes one
+// partial per value, and every block of the next kernel sums those partials
+// itself, in the same fixed order, so all blocks hold bit-identical totals.
+// Only kernel boundaries order memory between blocks (no device-scope
+// fences, which on a multi-XCD part write back and invalidate L2).
 struct BatchArgs {
     int64_t n;
     int64_t rows_per_block;
     int32_t nblocks;
+    int32_t xcd_map;         // 1: contiguous row ranges per XCD (see logical_block)
     int32_t run0;            // first run of the batch
     double* scal;            // per-run scalar base
     ScalLayout L;
-    double* partials;        // [nblocks][NV] block partial sums
-    unsigned int* counter;   // arrival counter of the grid reduction (left at 0)
+    double* np_part;         // [k+1 stages][nvp][nblocks]: |u_j|^2 per run, then (C u_j)_q per run
+    int32_t nvp;             // values per stage in np_part (>= P * (1 + o))
+    double* ap_part;         // [kMaxP][nblocks]:  v_j . w per run
     const double* anorm;     // ||A||_inf on the device
     double tau_scale;        // breakdown when beta_j <= tau_scale * ||A||_inf
 };
@@ -71,24 +81,28 @@ struct StartSrc {
     int32_t set[kMaxP];          // segment set of a generator, or -1
 };
 
-// Inputs of the small eigen-solve / exponential stage, one entry per run.
+// Inputs of the small exponential stage, one workgroup per run.
 struct ExpmArgs {
-    double* scal;
+    const double* scal;
     ScalLayout L;
     const int32_t* role;     // 0 generator, 1 center, 2 augmented
-    double* theta;           // [nruns][k] eigenvalues of H
-    double* coef;            // [nruns][o][k] beta0 * (P Q)[q,i] * Q[0,i]
-    int32_t* msize;          // [nruns] size of the tridiagonal used
+    double dt;
+    int32_t B;               // anchor spacing (power of two)
+    int32_t nanch;           // anchors per run: ceil((steps + 1) / B)
+    double pade[14];         // [13/13] Pade numerator coefficients, b_13 = 1
+    double* Z;               // [nruns][B][kMaxO][kMaxK]  P Phi^r
+    double* anch;            // [nruns][nanch][kMaxK]     Psi^b e_1
+    int32_t* msize;          // [nruns] size of H used (0: the run contributes 0)
+    double* scale;           // [nruns] beta0, or 1 for the augmented run
 };
 
 struct AssembleArgs {
-    const double* theta;
-    const double* coef;
+    const double* Z;
+    const double* anch;
     const int32_t* msize;
-    const int32_t* role;
-    int32_t nruns, o, k;
+    const double* scale;
+    int32_t nruns, o, B, nanch;
     int64_t steps;
-    double dt;
     double* basis;           // [(steps+1)][o][nruns]
 };
 
@@ -99,14 +113,14 @@ struct CheckArgs {
     int32_t nruns, o;
     int64_t steps;
     double ulo[kMaxO], uhi[kMaxO];
+    double* part;            // [2 * check_blocks] first hit and non-finite flag per block
     double* verdict;         // [first_step, row, y, lo, hi, status, z[nruns]]
 };
 
 // ---- launchers (kry_lanczos.hip, kry_expm.hip) ----------------------------
-hipError_t launch_fill_zero_u32(unsigned int* p, int64_t count, hipStream_t s);
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
-                              int64_t rows_per_block, unsigned int* counter, double* out,
-                              hipStream_t s);
+                              int64_t rows_per_block, double* out, hipStream_t s);
+hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s);
 hipError_t launch_start(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0,
                         double* u, const BatchArgs& B, hipStream_t s);
 hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
@@ -117,7 +131,9 @@ hipError_t launch_spmv_stencil(int P, const StencilArgs& A, const double* ucur,
                                hipStream_t s);
 hipError_t launch_sweep(int P, int O, const SegTable& T, int32_t oset0, const double* ucur,
                         double* w, const BatchArgs& B, int j, hipStream_t s);
-hipError_t launch_eig_coeffs(const ExpmArgs& E, int32_t nruns, hipStream_t s);
+hipError_t expm_prepare();
+hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);
+int check_blocks(int64_t steps, int32_t o);
 hipError_t launch_assemble(const AssembleArgs& A, hipStream_t s);
 hipError_t launch_check(const CheckArgs& C, hipStream_t s);
 

@@ -1,19 +1,21 @@
 // Streaming kernels of the Lanczos process (paper Algorithms 3 and 4) on gfx950.
 //
 // One Lanczos iteration j of a batch of P independent runs is two launches:
-//   spmv  : w = A v_j - beta_{j-1} v_{j-1}        and the dot alpha_j = v_j . w
-//   sweep : w -= alpha_j v_j,  beta_j = |w|,  P[:, j] = C w / beta_j
+//   spmv  : w = A v_j - beta_{j-1} v_{j-1}        and block partials of v_j . w
+//   sweep : w -= alpha_j v_j                       and block partials of |w|^2, C w
 // Vectors are stored unnormalised (u_j, with v_j = sigma_j u_j and
-// sigma_j = 1 / beta_{j-1} kept on the device), so no pass is spent on the
-// normalisation of Algorithm 3; the scale is applied where the vector is read.
-// Batches store their P vectors interleaved ([n][P]) so a gathered column of
-// A reads P contiguous values.
+// sigma_j = 1 / beta_{j-1}), so no pass is spent on the normalisation of
+// Algorithm 3; the scale is applied where the vector is read.  Batches store
+// their P vectors interleaved ([n][P]) so a gathered column of A reads P
+// contiguous values.
 //
-// Grid-wide sums are deterministic: each block reduces its rows in a fixed
-// order (per-thread row loop, wave butterfly, LDS across waves), writes one
-// partial per value, and the last block to arrive sums all partials in block
-// order.  The row -> block partition depends on n only, so a run's arithmetic
-// does not depend on which batch (or P) it is advanced in.
+// Reductions: a kernel writes one partial per block and value; every block of
+// the next kernel sums them in the same fixed order (strided per thread, wave
+// butterfly, waves in order), so all blocks hold bit-identical scalars and
+// block 0 records them (alpha_j, beta_{j-1}, sigma_j, k_eff).  The partials of
+// |u_j|^2 and C u_j are kept per iteration, and k_finish turns them into the
+// columns of P = C V once per batch.  The row -> block partition depends on n
+// only, so a run's arithmetic does not depend on which batch (or P) advances it.
 #include "kry_internal.h"
 
 #include <cmath>
@@ -22,169 +24,266 @@ namespace kry {
 
 namespace {
 
-struct OpSum {
-    static __device__ __forceinline__ double apply(double a, double b) { return a + b; }
-    static constexpr double identity = 0.0;
-};
-struct OpMax {
-    static __device__ __forceinline__ double apply(double a, double b) { return a > b ? a : b; }
-    static constexpr double identity = 0.0;   // used on absolute values only
-};
-
-template <int NV, class Op>
-__device__ __forceinline__ void wave_allreduce(double (&v)[NV]) {
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] = Op::apply(v[i], __shfl_xor(v[i], off, 64));
+        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
     }
 }
 
-// Reduces v over the block; thread i < NV returns total i.  `lds` holds
-// (kBlock / 64) * NV doubles.  Must be reached by every thread.
-template <int NV, class Op>
-__device__ __forceinline__ double block_reduce(double (&v)[NV], double* lds) {
-    wave_allreduce<NV, Op>(v);
+// Sum of v over the block; thread i < NV returns total i.  `lds` holds
+// (kBlock / 64) * NV doubles.  Every thread must call it.
+template <int NV>
+__device__ __forceinline__ double block_sum(double (&v)[NV], double* lds) {
+    wave_sum<NV>(v);
     const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    if (lane == 0) {
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
     }
     __syncthreads();
-    double t = Op::identity;
+    double t = 0.0;
     if (threadIdx.x < NV) {
         t = lds[threadIdx.x];
 #pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) t = Op::apply(t, lds[w * NV + threadIdx.x]);
+        for (int w = 1; w < kBlock / 64; ++w) t += lds[w * NV + threadIdx.x];
     }
     __syncthreads();
     return t;
 }
 
-// Block partials -> grid totals.  Returns true in the last block to arrive;
-// there s_tot[i] holds total i (visible to all threads of that block).  The
-// arrival counter is returned to 0 for the next launch.
-template <int NV, class Op>
-__device__ bool grid_reduce(double (&v)[NV], double* partials, unsigned int* counter,
-                            double* s_lds, double* s_tot) {
-    __shared__ int s_last;
-    const double t = block_reduce<NV, Op>(v, s_lds);
-    if (threadIdx.x < NV) {
-        __hip_atomic_store(&partials[(int64_t)blockIdx.x * NV + threadIdx.x], t, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev =
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
+// Workgroups are dispatched to the 8 XCDs round-robin by blockIdx; the
+// logical block (row range) of a workgroup is chosen so each XCD works on a
+// contiguous eighth of the rows, which keeps the +-m^2 neighbours of a 3D
+// stencil row in the same XCD's L2.  nblocks is a multiple of 8.
+__device__ __forceinline__ int logical_block(int nblocks, int xcd_map = 1) {
+    if (!xcd_map) return (int)blockIdx.x;
+    return (int)(blockIdx.x & 7) * (nblocks >> 3) + (int)(blockIdx.x >> 3);
+}
+
+// Writes the block totals of v as partials part[i * nblocks + block].
+template <int NV>
+__device__ __forceinline__ void store_partials(double (&v)[NV], double* part, int nblocks, double* lds,
+                                               int xcd_map) {
+    const double t = block_sum<NV>(v, lds);
+    if (threadIdx.x < NV) part[(int64_t)threadIdx.x * nblocks + logical_block(nblocks, xcd_map)] = t;
+}
+
+// Totals of values vbeg..vbeg+NV-1 of a partial array over nb blocks, in a
+// fixed order; result in s_out[0..NV) for every thread.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* part, int nb, int vbeg, double* lds, double* s_out) {
     double acc[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = Op::identity;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-            acc[i] = Op::apply(acc[i], __hip_atomic_load(&partials[(int64_t)b * NV + i],
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (int i = 0; i < NV; ++i) acc[i] += part[(int64_t)(vbeg + i) * nb + b];
     }
-    const double tot = block_reduce<NV, Op>(acc, s_lds);
-    if (threadIdx.x < NV) s_tot[threadIdx.x] = tot;
-    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double t = block_sum<NV>(acc, lds);
+    if (threadIdx.x < NV) s_out[threadIdx.x] = t;
     __syncthreads();
-    return true;
 }
-
-// First segment of set `s` with hi > r0, and first with lo >= r1.
-__device__ void seg_range(const SegTable& T, int s, int64_t r0, int64_t r1, int32_t* b, int32_t* e) {
-    int lo = T.set_begin[s], hi = T.set_begin[s + 1];
-    int a = lo, z = hi;
-    while (a < z) {
-        const int m = (a + z) >> 1;
-        if (T.hi[m] > r0) z = m; else a = m + 1;
-    }
-    int c = a, d = hi;
-    while (c < d) {
-        const int m = (c + d) >> 1;
-        if (T.lo[m] >= r1) d = m; else c = m + 1;
-    }
-    *b = a;
-    *e = c;
-}
-
-// Membership of increasing rows in one segment set, amortised O(1) per row.
-struct SegCursor {
-    int32_t cur, end;
-    __device__ __forceinline__ double weight(const SegTable& T, int64_t r) {
-        while (cur < end && T.hi[cur] <= r) ++cur;
-        return (cur < end && T.lo[cur] <= r) ? T.w[cur] : 0.0;
-    }
-};
 
 __device__ __forceinline__ double* run_scal(const BatchArgs& B, int p) {
     return B.scal + (int64_t)(B.run0 + p) * B.L.stride;
 }
 
-__device__ __forceinline__ int64_t block_row0(const BatchArgs& B) {
-    return (int64_t)blockIdx.x * B.rows_per_block;
+// Stage j-1 -> sigma_j.  nrm2 = |u_j|^2 (u_j is the start vector for j = 1,
+// the swept vector of iteration j-1 otherwise).  A step whose norm is at most
+// 1024 eps ||A||_inf ends the run (invariant Krylov space); sigma stays 0 from
+// then on, which keeps every later vector exactly zero.
+struct Stage {
+    double beta, sigma, cprev;
+    int keff;          // new k_eff to record, or -1 to leave it
+    bool nonfinite;
+};
+
+__device__ __forceinline__ Stage stage_update_v(int k, double sig_prev, double tau, int j, double nrm2) {
+    Stage st;
+    st.beta = sqrt(nrm2);
+    st.keff = -1;
+    st.nonfinite = false;
+    st.cprev = 0.0;
+    if (j == 1) {
+        const bool ok = st.beta > 0.0 && isfinite(st.beta);
+        st.sigma = ok ? 1.0 / st.beta : 0.0;
+        st.keff = ok ? k : 0;
+        st.nonfinite = !isfinite(st.beta);
+        return st;
+    }
+    st.cprev = st.beta * sig_prev;
+    if (sig_prev == 0.0) {
+        st.sigma = 0.0;
+        st.cprev = 0.0;
+    } else if (!isfinite(st.beta)) {
+        st.sigma = 0.0;
+        st.cprev = 0.0;
+        st.keff = j - 1;
+        st.nonfinite = true;
+    } else if (st.beta <= tau) {
+        st.sigma = 0.0;
+        st.keff = j - 1;
+    } else {
+        st.sigma = 1.0 / st.beta;
+    }
+    return st;
+}
+
+__device__ __forceinline__ Stage stage_update(const BatchArgs& B, const double* sc, int j, double nrm2) {
+    return stage_update_v(B.L.k, j > 1 ? sc[B.L.sigma + j - 1] : 0.0, B.tau_scale * *B.anorm, j, nrm2);
+}
+
+// Block 0 of the kernel that consumes stage j-1 records its scalars (the
+// projections are summed later, once per batch, by k_finish).
+__device__ __forceinline__ void record_stage(const BatchArgs& B, int P, int j, const double* nrm2) {
+    if (threadIdx.x < P) {
+        const int p = threadIdx.x;
+        double* sc = run_scal(B, p);
+        const Stage st = stage_update(B, sc, j, nrm2[p]);
+        sc[B.L.beta + j - 1] = st.beta;
+        sc[B.L.sigma + j] = st.sigma;
+        if (st.keff >= 0) sc[B.L.misc + MISC_KEFF] = (double)st.keff;
+        if (j == 1) sc[B.L.misc + MISC_NONFINITE] = st.nonfinite ? 1.0 : 0.0;
+        else if (st.nonfinite) sc[B.L.misc + MISC_NONFINITE] = 1.0;
+    }
+}
+
+__device__ __forceinline__ double* stage_part(const BatchArgs& B, int stage) {
+    return B.np_part + (int64_t)stage * B.nvp * B.nblocks;
 }
 
 // ---------------------------------------------------------------------------
 
-__global__ void k_fill_zero_u32(unsigned int* p, int64_t count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0u;
-}
-
-// max_r sum_e |vals[e]| (row sums in CSR order, one thread per row)
+// max_r sum_e |vals[e]| (row sums in CSR order, one thread per row): block
+// maxima, then one block reduces them.
 __global__ __launch_bounds__(kBlock) void k_row_abs_max(CsrArgs A, int64_t n, int64_t rows_per_block,
-                                                        double* partials, unsigned int* counter,
-                                                        double* out) {
-    __shared__ double s_lds[(kBlock / 64) * 1];
-    __shared__ double s_tot[1];
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+                                                        double* part) {
+    __shared__ double s_m[kBlock / 64];
+    const int lb = logical_block((int)gridDim.x);
+    const int64_t r0 = (int64_t)lb * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
-    double v[1] = {0.0};
+    double v = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
         double s = 0.0;
         for (int64_t e = A.rowptr[r]; e < A.rowptr[r + 1]; ++e) s += fabs(A.vals[e]);
-        v[0] = s > v[0] ? s : v[0];
+        v = s > v ? s : v;
     }
-    if (grid_reduce<1, OpMax>(v, partials, counter, s_lds, s_tot)) {
-        if (threadIdx.x == 0) *out = s_tot[0];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) v = s_m[w] > v ? s_m[w] : v;
+        part[lb] = v;
     }
 }
 
-// a2: start vectors u_1 of the runs, beta0 = |u_1|, sigma_1 = 1/beta0 and
-// P[:, 0] = C v_1 (Algorithm 4, first two statements).
+__global__ __launch_bounds__(kBlock) void k_reduce_max(const double* part, int nb, double* out) {
+    __shared__ double s_m[kBlock / 64];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) v = part[b] > v ? part[b] : v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) v = s_m[w] > v ? s_m[w] : v;
+        *out = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Segment sets (generators and output rows) a block needs are staged in LDS.
+// The plan precomputes, for every set and logical block, the range of that
+// set's segments overlapping the block's rows (SegTable::blk), so a block
+// finds them with one load; up to kSegCap of them are copied to LDS, a set
+// with more keeps reading global memory.
+constexpr int kSegCap = 64;
+
+template <int NS>
+struct SegStage {
+    int64_t lo[NS][kSegCap];
+    int64_t hi[NS][kSegCap];
+    double w[NS][kSegCap];
+    int32_t beg[NS], end[NS];
+};
+
+// Every thread must call it.  sets[i] < 0 stages an empty set.
+template <int NS>
+__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, const int (&sets)[NS],
+                                               int lb, int nblocks) {
+    if (threadIdx.x < NS) {
+        const int s = sets[threadIdx.x];
+        int32_t b = 0, e = 0;
+        if (s >= 0) {
+            b = T.blk[((int64_t)s * nblocks + lb) * 2];
+            e = T.blk[((int64_t)s * nblocks + lb) * 2 + 1];
+        }
+        st.beg[threadIdx.x] = b;
+        st.end[threadIdx.x] = e;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < NS * kSegCap; idx += kBlock) {
+        const int i = idx / kSegCap, c = idx % kSegCap;
+        const int g = st.beg[i] + c;
+        if (g < st.end[i]) {
+            st.lo[i][c] = T.lo[g];
+            st.hi[i][c] = T.hi[g];
+            st.w[i][c] = T.w[g];
+        }
+    }
+    __syncthreads();
+}
+
+// Weight of increasing rows in one staged set, amortised O(1) per row.
+struct SegCursor {
+    int32_t cur, cnt, gcur, gend;
+    template <int NS>
+    __device__ __forceinline__ void init(const SegStage<NS>& st, int i) {
+        const int n = st.end[i] - st.beg[i];
+        cur = 0;
+        cnt = n <= kSegCap ? n : 0;
+        gcur = n <= kSegCap ? 0 : st.beg[i];
+        gend = n <= kSegCap ? 0 : st.end[i];
+    }
+    template <int NS>
+    __device__ __forceinline__ double weight(const SegStage<NS>& st, int i, const SegTable& T, int64_t r) {
+        while (cur < cnt && st.hi[i][cur] <= r) ++cur;
+        if (cur < cnt) return st.lo[i][cur] <= r ? st.w[i][cur] : 0.0;
+        while (gcur < gend && T.hi[gcur] <= r) ++gcur;
+        return (gcur < gend && T.lo[gcur] <= r) ? T.w[gcur] : 0.0;
+    }
+};
+
+// a2: start vectors u_1 of the runs and the partials of |u_1|^2 and C u_1
+// (Algorithm 4, first two statements; the scaling happens in the next kernel).
 template <int P, int O>
 __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int32_t oset0,
                                                   double* __restrict__ u, BatchArgs B) {
     constexpr int NV = P * (1 + O);
     __shared__ double s_lds[(kBlock / 64) * NV];
-    __shared__ double s_tot[NV];
-    __shared__ int32_t s_b[P + O], s_e[P + O];
-    const int64_t r0 = block_row0(B);
+    __shared__ SegStage<P + O> st;
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
-    if (threadIdx.x < P + O) {
-        const int i = threadIdx.x;
-        const int set = (i < P) ? src.set[i] : oset0 + (i - P);
-        if (set >= 0) seg_range(T, set, r0, r1, &s_b[i], &s_e[i]);
-        else { s_b[i] = 0; s_e[i] = 0; }
-    }
-    __syncthreads();
+    int sets[P + O];
+#pragma unroll
+    for (int i = 0; i < P; ++i) sets[i] = src.set[i];
+#pragma unroll
+    for (int q = 0; q < O; ++q) sets[P + q] = oset0 + q;
+    stage_segments<P + O>(st, T, sets, lb, B.nblocks);
     SegCursor cur[P + O];
 #pragma unroll
-    for (int i = 0; i < P + O; ++i) { cur[i].cur = s_b[i]; cur[i].end = s_e[i]; }
-    const double* dense[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) dense[p] = src.dense[p];
-
+    for (int i = 0; i < P + O; ++i) cur[i].init(st, i);
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
@@ -192,95 +291,163 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
         double val[P];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if (dense[p] != nullptr) val[p] = dense[p][r];
-            else if (src.set[p] >= 0) val[p] = cur[p].weight(T, r);
+            if (src.dense[p] != nullptr) val[p] = src.dense[p][r];
+            else if (src.set[p] >= 0) val[p] = cur[p].weight(st, p, T, r);
             else val[p] = 0.0;
             u[r * P + p] = val[p];
             acc[p] = fma(val[p], val[p], acc[p]);
         }
 #pragma unroll
         for (int q = 0; q < O; ++q) {
-            const double cw = cur[P + q].weight(T, r);
+            const double cw = cur[P + q].weight(st, P + q, T, r);
             if (cw != 0.0) {
 #pragma unroll
                 for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
             }
         }
     }
-    if (grid_reduce<NV, OpSum>(acc, B.partials, B.counter, s_lds, s_tot)) {
-        if (threadIdx.x < P) {
-            const int p = threadIdx.x;
-            double* sc = run_scal(B, p);
-            const double beta0 = sqrt(s_tot[p]);
-            const double sig = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
-            sc[B.L.beta + 0] = beta0;
-            sc[B.L.sigma + 1] = sig;
-            for (int q = 0; q < O; ++q) sc[B.L.proj + q * (B.L.k + 1) + 0] = sig * s_tot[P + q * P + p];
-            sc[B.L.misc + MISC_KEFF] = beta0 > 0.0 ? (double)B.L.k : 0.0;
-            sc[B.L.misc + MISC_DONE] = beta0 > 0.0 ? 0.0 : 1.0;
-            sc[B.L.misc + MISC_NONFINITE] = isfinite(beta0) ? 0.0 : 1.0;
-        }
+    store_partials<NV>(acc, stage_part(B, 0), B.nblocks, s_lds, B.xcd_map);
+}
+
+// Loads for the reduction of stage j-1's norms, issued before any row work
+// so their latency overlaps it; thread t sums blocks t, t + kBlock, ...
+template <int P>
+__device__ __forceinline__ void load_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
+                                                 double (&sig_prev)[P], double& anorm) {
+    const double* part = stage_part(B, j - 1);
+#pragma unroll
+    for (int p = 0; p < P; ++p) pacc[p] = 0.0;
+    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) pacc[p] += part[(int64_t)p * B.nblocks + b];
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) sig_prev[p] = (j > 1) ? run_scal(B, p)[B.L.sigma + j - 1] : 0.0;
+    anorm = *B.anorm;
+}
+
+// Finishes the stage j-1 reduction: sigma_j and cprev = beta_{j-1} sigma_{j-1}
+// for every run; block 0 records the stage.  Every thread must call it.
+template <int P>
+__device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
+                                                   const double (&sig_prev)[P], double anorm, double* s_lds,
+                                                   double* s_nrm, double (&sig)[P], double (&cprev)[P]) {
+    const double t = block_sum<P>(pacc, s_lds);
+    if (threadIdx.x < P) s_nrm[threadIdx.x] = t;
+    __syncthreads();
+    if (blockIdx.x == 0) record_stage(B, P, j, s_nrm);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const Stage st = stage_update_v(B.L.k, sig_prev[p], B.tau_scale * anorm, j, s_nrm[p]);
+        sig[p] = st.sigma;
+        cprev[p] = st.cprev;
     }
 }
 
 // a3 + first half of a4: w = sigma_j A u_j - beta_{j-1} sigma_{j-1} u_{j-1};
-// alpha_j = (sigma_j u_j) . w.  LPR lanes cooperate on one row.
+// partials of (sigma_j u_j) . w.  LPR lanes cooperate on one row.  Rows are
+// taken in chunks of RC per lane group; the first chunk's gathers are issued
+// before the stage reduction they do not depend on.
 template <int P, int LPR>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __restrict__ ucur,
                                                      const double* __restrict__ uprev,
                                                      double* __restrict__ w, BatchArgs B, int j) {
-    __shared__ double s_lds[(kBlock / 64) * P];
-    __shared__ double s_tot[P];
-    double sig[P], cprev[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const double* sc = run_scal(B, p);
-        sig[p] = sc[B.L.sigma + j];
-        cprev[p] = (j > 1) ? sc[B.L.beta + j - 1] * sc[B.L.sigma + j - 1] : 0.0;
-    }
-    const int64_t r0 = block_row0(B);
-    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
     constexpr int G = kBlock / LPR;
+    constexpr int RC = 2;
+    constexpr int U = P >= 8 ? 2 : (P >= 4 ? 4 : 8);
+    __shared__ double s_lds[(kBlock / 64) * P];
+    __shared__ double s_nrm[P];
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
     const int sub = threadIdx.x % LPR;
-    double dot[P];
+    const int slot = threadIdx.x / LPR;
+    double pacc[P], sig_prev[P], anorm;
+    load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
+    double sig[P], cprev[P], dot[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) dot[p] = 0.0;
-    for (int64_t r = r0 + threadIdx.x / LPR; r < r1; r += G) {
-        const int64_t e0 = A.rowptr[r], e1 = A.rowptr[r + 1];
-        double acc[P];
+    for (int p = 0; p < P; ++p) { sig[p] = 0.0; cprev[p] = 0.0; dot[p] = 0.0; }
+    const int64_t span = (int64_t)G * RC;
+    const int nch = (int)((B.rows_per_block + span - 1) / span);
+    for (int ch = 0; ch < nch; ++ch) {
+        int64_t rr[RC], e0[RC], e1[RC];
+        double acc[RC][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) acc[p] = 0.0;
-        for (int64_t e = e0 + sub; e < e1; e += LPR) {
-            const int64_t c = A.colidx[e];
-            const double a = A.vals[e];
+        for (int i = 0; i < RC; ++i) {
+            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * G + slot;
+            const bool live = rr[i] < r1;
+            e0[i] = live ? A.rowptr[rr[i]] : 0;
+            e1[i] = live ? A.rowptr[rr[i] + 1] : 0;
 #pragma unroll
-            for (int p = 0; p < P; ++p) acc[p] = fma(a, ucur[c * P + p], acc[p]);
+            for (int p = 0; p < P; ++p) acc[i][p] = 0.0;
+        }
+        // first U entries per lane of every row of the chunk, predicated; a
+        // masked slot reads entry 0 of the vector and adds nothing
+        {
+            int32_t c[RC][U];
+            double a[RC][U];
+#pragma unroll
+            for (int i = 0; i < RC; ++i) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t ee = e0[i] + sub + (int64_t)u * LPR;
+                    const bool ok = ee < e1[i];
+                    c[i][u] = ok ? A.colidx[ee] : 0;
+                    a[i][u] = ok ? A.vals[ee] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < RC; ++i) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = e0[i] + sub + (int64_t)u * LPR < e1[i];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const double x = ucur[(int64_t)c[i][u] * P + p];
+                        acc[i][p] = ok ? fma(a[i][u], x, acc[i][p]) : acc[i][p];
+                    }
+                }
+            }
+        }
+        // longer rows
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            for (int64_t e = e0[i] + sub + (int64_t)U * LPR; e < e1[i]; e += LPR) {
+                const int64_t c = A.colidx[e];
+                const double a = A.vals[e];
+#pragma unroll
+                for (int p = 0; p < P; ++p) acc[i][p] = fma(a, ucur[c * P + p], acc[i][p]);
+            }
         }
         if (LPR > 1) {
 #pragma unroll
             for (int off = LPR / 2; off >= 1; off >>= 1) {
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[p] += __shfl_xor(acc[p], off, LPR);
+                for (int i = 0; i < RC; ++i) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[i][p] += __shfl_xor(acc[i][p], off, LPR);
+                }
             }
         }
+        if (ch == 0) finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
         if (sub == 0) {
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                double y = sig[p] * acc[p];
-                if (j > 1) y = fma(-cprev[p], uprev[r * P + p], y);
-                w[r * P + p] = y;
-                dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
+            for (int i = 0; i < RC; ++i) {
+                if (rr[i] < r1) {
+                    const int64_t r = rr[i];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        double y = sig[p] * acc[i][p];
+                        if (j > 1) y = fma(-cprev[p], uprev[r * P + p], y);
+                        w[r * P + p] = y;
+                        dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
+                    }
+                }
             }
         }
     }
-    if (grid_reduce<P, OpSum>(dot, B.partials, B.counter, s_lds, s_tot)) {
-        if (threadIdx.x < P) {
-            double* sc = run_scal(B, threadIdx.x);
-            const double a = s_tot[threadIdx.x];
-            sc[B.L.alpha + j] = a;
-            if (!isfinite(a)) sc[B.L.misc + MISC_NONFINITE] = 1.0;
-        }
-    }
+    if (nch == 0) finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
+    store_partials<P>(dot, B.ap_part, B.nblocks, s_lds, B.xcd_map);
 }
 
 // Matrix-free 7-point stencil version of k_spmv_csr (zero outside the grid),
@@ -290,16 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
                                                          const double* __restrict__ uprev,
                                                          double* __restrict__ w, BatchArgs B, int j) {
     __shared__ double s_lds[(kBlock / 64) * P];
-    __shared__ double s_tot[P];
-    double sig[P], cprev[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const double* sc = run_scal(B, p);
-        sig[p] = sc[B.L.sigma + j];
-        cprev[p] = (j > 1) ? sc[B.L.beta + j - 1] * sc[B.L.sigma + j - 1] : 0.0;
-    }
-    const int64_t r0 = block_row0(B);
+    __shared__ double s_nrm[P];
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
+    double pacc[P], sig_prev[P], anorm;
+    load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
+    double sig[P], cprev[P];
+    finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
     const int64_t sx = S.ny * S.nz, sy = S.nz;
     double dot[P];
 #pragma unroll
@@ -325,84 +490,132 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
             dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
         }
     }
-    if (grid_reduce<P, OpSum>(dot, B.partials, B.counter, s_lds, s_tot)) {
-        if (threadIdx.x < P) {
-            double* sc = run_scal(B, threadIdx.x);
-            const double a = s_tot[threadIdx.x];
-            sc[B.L.alpha + j] = a;
-            if (!isfinite(a)) sc[B.L.misc + MISC_NONFINITE] = 1.0;
-        }
-    }
+    store_partials<P>(dot, B.ap_part, B.nblocks, s_lds, B.xcd_map);
 }
 
-// Second half of a4 + a5 + a6: w -= alpha_j v_j; beta_j = |w|; breakdown test;
-// sigma_{j+1} = 1/beta_j; P[:, j] = sigma_{j+1} C w.
+// Second half of a4 + the partials of a5 and a6: alpha_j = sum of the dot
+// partials; w -= alpha_j sigma_j u_j; partials of |w|^2 and C w.  The first
+// chunk of rows is loaded before the alpha reduction completes.
 template <int P, int O>
 __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                                                   const double* __restrict__ ucur,
                                                   double* __restrict__ w, BatchArgs B, int j) {
     constexpr int NV = P * (1 + O);
+    constexpr int RC = 4;
     __shared__ double s_lds[(kBlock / 64) * NV];
-    __shared__ double s_tot[NV];
-    __shared__ int32_t s_b[O], s_e[O];
-    const int64_t r0 = block_row0(B);
+    __shared__ double s_alpha[P];
+    __shared__ SegStage<O> st;
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
-    if (threadIdx.x < O) seg_range(T, oset0 + threadIdx.x, r0, r1, &s_b[threadIdx.x], &s_e[threadIdx.x]);
-    double coef[P];
+    // alpha partials and sigma_j: loads issued first
+    double pacc[P], sigj[P];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const double* sc = run_scal(B, p);
-        coef[p] = sc[B.L.alpha + j] * sc[B.L.sigma + j];
+    for (int p = 0; p < P; ++p) pacc[p] = 0.0;
+    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) pacc[p] += B.ap_part[(int64_t)p * B.nblocks + b];
     }
-    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < P; ++p) sigj[p] = run_scal(B, p)[B.L.sigma + j];
+    int sets[O];
+#pragma unroll
+    for (int q = 0; q < O; ++q) sets[q] = oset0 + q;
+    stage_segments<O>(st, T, sets, lb, B.nblocks);
     SegCursor cur[O];
 #pragma unroll
-    for (int q = 0; q < O; ++q) { cur[q].cur = s_b[q]; cur[q].end = s_e[q]; }
-    double acc[NV];
+    for (int q = 0; q < O; ++q) cur[q].init(st, q);
+    double acc[NV], coef[P];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        double val[P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            val[p] = fma(-coef[p], ucur[r * P + p], w[r * P + p]);
-            w[r * P + p] = val[p];
-            acc[p] = fma(val[p], val[p], acc[p]);
+    for (int p = 0; p < P; ++p) coef[p] = 0.0;
+    const int64_t span = (int64_t)kBlock * RC;
+    const int nch = (int)((B.rows_per_block + span - 1) / span);
+    for (int ch = 0; ch < max(nch, 1); ++ch) {
+        double uv[RC][P], wv[RC][P];
+        int64_t rr[RC];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            const bool live = rr[i] < r1;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                uv[i][p] = live ? ucur[rr[i] * P + p] : 0.0;
+                wv[i][p] = live ? w[rr[i] * P + p] : 0.0;
+            }
+        }
+        if (ch == 0) {
+            const double t = block_sum<P>(pacc, s_lds);
+            if (threadIdx.x < P) s_alpha[threadIdx.x] = t;
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < P; ++p) coef[p] = s_alpha[p] * sigj[p];
+            if (blockIdx.x == 0 && threadIdx.x < P) {
+                double* sc = run_scal(B, threadIdx.x);
+                sc[B.L.alpha + j] = s_alpha[threadIdx.x];
+                if (!isfinite(s_alpha[threadIdx.x])) sc[B.L.misc + MISC_NONFINITE] = 1.0;
+            }
         }
 #pragma unroll
-        for (int q = 0; q < O; ++q) {
-            const double cw = cur[q].weight(T, r);
-            if (cw != 0.0) {
+        for (int i = 0; i < RC; ++i) {
+            if (rr[i] < r1) {
+                const int64_t r = rr[i];
+                double val[P];
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+                for (int p = 0; p < P; ++p) {
+                    val[p] = fma(-coef[p], uv[i][p], wv[i][p]);
+                    w[r * P + p] = val[p];
+                    acc[p] = fma(val[p], val[p], acc[p]);
+                }
+#pragma unroll
+                for (int q = 0; q < O; ++q) {
+                    const double cw = cur[q].weight(st, q, T, r);
+                    if (cw != 0.0) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+                    }
+                }
             }
         }
     }
-    if (grid_reduce<NV, OpSum>(acc, B.partials, B.counter, s_lds, s_tot)) {
-        if (threadIdx.x < P) {
-            const int p = threadIdx.x;
-            double* sc = run_scal(B, p);
-            const bool done = sc[B.L.misc + MISC_DONE] != 0.0;
-            const double beta = sqrt(s_tot[p]);
-            sc[B.L.beta + j] = beta;
-            double sig = 0.0;
-            if (!done) {
-                if (!isfinite(beta)) {
-                    sc[B.L.misc + MISC_NONFINITE] = 1.0;
-                    sc[B.L.misc + MISC_DONE] = 1.0;
-                    sc[B.L.misc + MISC_KEFF] = (double)j;
-                } else if (beta <= B.tau_scale * *B.anorm) {
-                    sc[B.L.misc + MISC_DONE] = 1.0;
-                    sc[B.L.misc + MISC_KEFF] = (double)j;
-                } else {
-                    sig = 1.0 / beta;
-                }
-            }
-            sc[B.L.sigma + j + 1] = sig;
-            if (j < B.L.k) {
-                for (int q = 0; q < O; ++q) sc[B.L.proj + q * (B.L.k + 1) + j] = sig * s_tot[P + q * P + p];
-            }
-        }
+    store_partials<NV>(acc, stage_part(B, j), B.nblocks, s_lds, B.xcd_map);
+}
+
+// After the last sweep, one block per stage c = 0..k: P[:, c] = sigma_{c+1} C u_{c+1}
+// from the stored partials of that stage; block k also records the final
+// stage (beta_k, sigma_{k+1}, and k_eff when the run breaks down there).
+// Values are summed by groups of threads, each group in a fixed order.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o) {
+    __shared__ double s_part[kBlock];
+    __shared__ double s_tot[P * (1 + kMaxO)];
+    const int c = blockIdx.x;
+    const int nv = P * (1 + o);
+    const int grp = kBlock / nv;
+    const int v = threadIdx.x / grp, g = threadIdx.x % grp;
+    const double* part = stage_part(B, c);
+    double acc = 0.0;
+    if (v < nv) {
+        for (int b = g; b < B.nblocks; b += grp) acc += part[(int64_t)v * B.nblocks + b];
+    }
+    s_part[threadIdx.x] = acc;
+    __syncthreads();
+    if (v < nv && g == 0) {
+        double t = 0.0;
+        for (int i = 0; i < grp; ++i) t += s_part[v * grp + i];
+        s_tot[v] = t;
+    }
+    __syncthreads();
+    if (c == B.L.k) record_stage(B, P, c + 1, s_tot);
+    __syncthreads();
+    if (threadIdx.x < P * o) {
+        const int q = threadIdx.x / P, p = threadIdx.x % P;
+        double* sc = run_scal(B, p);
+        double sig;
+        if (c == B.L.k) sig = stage_update(B, sc, c + 1, s_tot[p]).sigma;
+        else sig = sc[B.L.sigma + c + 1];
+        sc[B.L.proj + q * (B.L.k + 1) + c] = sig * s_tot[P + q * P + p];
     }
 }
 
@@ -427,13 +640,21 @@ hipError_t launch_spmv_t(const CsrArgs& A, const double* ucur, const double* upr
     return hipGetLastError();
 }
 
-// Dispatch over O for a fixed P; P * (1 + O) <= kMaxNV limits P = 8 to O <= 4.
-#define KRY_DISPATCH_O4(FN, P, O, ...)                \
+// Dispatch over O for a fixed P; P * (1 + O) <= kMaxNV limits P = 4 to
+// O <= 5 and P = 8 to O <= 2.
+#define KRY_DISPATCH_O2(FN, P, O, ...)                \
+    switch (O) {                                      \
+        case 1: return FN<P, 1>(__VA_ARGS__);         \
+        case 2: return FN<P, 2>(__VA_ARGS__);         \
+        default: return hipErrorInvalidValue;         \
+    }
+#define KRY_DISPATCH_O5(FN, P, O, ...)                \
     switch (O) {                                      \
         case 1: return FN<P, 1>(__VA_ARGS__);         \
         case 2: return FN<P, 2>(__VA_ARGS__);         \
         case 3: return FN<P, 3>(__VA_ARGS__);         \
         case 4: return FN<P, 4>(__VA_ARGS__);         \
+        case 5: return FN<P, 5>(__VA_ARGS__);         \
         default: return hipErrorInvalidValue;         \
     }
 #define KRY_DISPATCH_O8(FN, P, O, ...)                \
@@ -451,18 +672,12 @@ hipError_t launch_spmv_t(const CsrArgs& A, const double* ucur, const double* upr
 
 }  // namespace
 
-hipError_t launch_fill_zero_u32(unsigned int* p, int64_t count, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    const int64_t blocks = (count + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, count);
-    return hipGetLastError();
-}
-
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
-                              int64_t rows_per_block, unsigned int* counter, double* out,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_row_abs_max, dim3(nblocks), dim3(kBlock), 0, s, A, n, rows_per_block,
-                       partials, counter, out);
+                              int64_t rows_per_block, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_abs_max, dim3(nblocks), dim3(kBlock), 0, s, A, n, rows_per_block, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(kBlock), 0, s, partials, nblocks, out);
     return hipGetLastError();
 }
 
@@ -472,8 +687,8 @@ hipError_t launch_start(int P, int O, const StartSrc& src, const SegTable& T, in
     switch (P) {
         case 1: KRY_DISPATCH_O8(launch_start_t, 1, O, src, T, oset0, u, B, s)
         case 2: KRY_DISPATCH_O8(launch_start_t, 2, O, src, T, oset0, u, B, s)
-        case 4: KRY_DISPATCH_O8(launch_start_t, 4, O, src, T, oset0, u, B, s)
-        case 8: KRY_DISPATCH_O4(launch_start_t, 8, O, src, T, oset0, u, B, s)
+        case 4: KRY_DISPATCH_O5(launch_start_t, 4, O, src, T, oset0, u, B, s)
+        case 8: KRY_DISPATCH_O2(launch_start_t, 8, O, src, T, oset0, u, B, s)
         default: return hipErrorInvalidValue;
     }
 }
@@ -484,22 +699,34 @@ hipError_t launch_sweep(int P, int O, const SegTable& T, int32_t oset0, const do
     switch (P) {
         case 1: KRY_DISPATCH_O8(launch_sweep_t, 1, O, T, oset0, ucur, w, B, j, s)
         case 2: KRY_DISPATCH_O8(launch_sweep_t, 2, O, T, oset0, ucur, w, B, j, s)
-        case 4: KRY_DISPATCH_O8(launch_sweep_t, 4, O, T, oset0, ucur, w, B, j, s)
-        case 8: KRY_DISPATCH_O4(launch_sweep_t, 8, O, T, oset0, ucur, w, B, j, s)
+        case 4: KRY_DISPATCH_O5(launch_sweep_t, 4, O, T, oset0, ucur, w, B, j, s)
+        case 8: KRY_DISPATCH_O2(launch_sweep_t, 8, O, T, oset0, ucur, w, B, j, s)
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s) {
+    const dim3 grid(B.L.k + 1);
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_finish<1>), grid, dim3(kBlock), 0, s, B, O); break;
+        case 2: hipLaunchKernelGGL((k_finish<2>), grid, dim3(kBlock), 0, s, B, O); break;
+        case 4: hipLaunchKernelGGL((k_finish<4>), grid, dim3(kBlock), 0, s, B, O); break;
+        case 8: hipLaunchKernelGGL((k_finish<8>), grid, dim3(kBlock), 0, s, B, O); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
                            const double* uprev, double* w, const BatchArgs& B, int j,
                            hipStream_t s) {
-#define KRY_LPR(PP)                                                          \
-    switch (lpr) {                                                           \
-        case 1: return launch_spmv_t<PP, 1>(A, ucur, uprev, w, B, j, s);     \
-        case 2: return launch_spmv_t<PP, 2>(A, ucur, uprev, w, B, j, s);     \
-        case 4: return launch_spmv_t<PP, 4>(A, ucur, uprev, w, B, j, s);     \
-        case 8: return launch_spmv_t<PP, 8>(A, ucur, uprev, w, B, j, s);     \
-        default: return hipErrorInvalidValue;                                \
+#define KRY_LPR(PP)                                                             \
+    switch (lpr) {                                                              \
+        case 1: return launch_spmv_t<PP, 1>(A, ucur, uprev, w, B, j, s);        \
+        case 2: return launch_spmv_t<PP, 2>(A, ucur, uprev, w, B, j, s);        \
+        case 4: return launch_spmv_t<PP, 4>(A, ucur, uprev, w, B, j, s);        \
+        case 8: return launch_spmv_t<PP, 8>(A, ucur, uprev, w, B, j, s);        \
+        default: return hipErrorInvalidValue;                                   \
     }
     switch (P) {
         case 1: KRY_LPR(1)
