@@ -69,7 +69,8 @@ Profiler& prof() {
 }
 
 const char* kKernelNames =
-    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,finish,expm_chain,assemble,check";
+    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
+    "assemble,check";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -83,9 +84,9 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
         b = P.get();
     }
     if (!a || !b) return launch();
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     hipError_t e = launch();
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> g(P.mu);
     P.pending.push_back({name, a, b});
     return e;
@@ -138,14 +139,17 @@ struct Layout {
     int pmax;
     int32_t B, nanch;
     int32_t nvp;
+    int32_t nvec;
+    size_t hpart, hcoef;
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
-                   size_t meta_bytes) {
+                   size_t meta_bytes, int32_t method) {
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
     Y.nblocks = nblocks_for(n, Y.rpb);
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
+    if (method == KRY_ARNOLDI) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
     {
         int p = 1;
         while (p * 2 <= Y.pmax) p *= 2;
@@ -159,10 +163,15 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     L.sigma = L.beta + (k + 2);
     L.proj = L.sigma + (k + 3);
     L.misc = L.proj + o * (k + 1);
-    L.stride = (int64_t)align_up((size_t)(L.misc + MISC_COUNT), 8);
+    L.hess = L.misc + MISC_COUNT;
+    L.stride = (int64_t)align_up((size_t)(L.hess + (k + 1) * k), 8);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
-    Y.vec = take(3 * (size_t)n * Y.pmax * sizeof(double));
+    // Lanczos keeps three vectors per run (Algorithm 4); Arnoldi the whole basis
+    Y.nvec = method == KRY_ARNOLDI ? k + 1 : 3;
+    Y.vec = take((size_t)Y.nvec * n * Y.pmax * sizeof(double));
+    Y.hpart = method == KRY_ARNOLDI ? take((size_t)kMaxK * kMaxP * Y.nblocks * sizeof(double)) : 0;
+    Y.hcoef = method == KRY_ARNOLDI ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
     Y.ap_part = take((size_t)Y.nblocks * kMaxP * sizeof(double));
@@ -275,10 +284,13 @@ struct kry_plan {
     double* zc_dev = nullptr;
     double* rad_dev = nullptr;
     int lpr = 1;
+    int32_t method = KRY_LANCZOS;
     bool projected = false;
     std::vector<double> verdict_host;
 
     double* vec(int i) { return reinterpret_cast<double*>(ws + Y.vec) + (size_t)i * sys.n * Y.pmax; }
+    double* hpart() { return reinterpret_cast<double*>(ws + Y.hpart); }
+    double* hcoef() { return reinterpret_cast<double*>(ws + Y.hcoef); }
     double* np_part() { return reinterpret_cast<double*>(ws + Y.np_part); }
     double* ap_part() { return reinterpret_cast<double*>(ws + Y.ap_part); }
     double* scal() { return reinterpret_cast<double*>(ws + Y.scal); }
@@ -343,9 +355,10 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kMaxK || steps < 0 || nseg_total < 0)
         return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56, steps >= 0, nseg_total >= 0 required");
     if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
-    (void)method;
     const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
-    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns, nb));
+    if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns, nb),
+                                 method);
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -366,8 +379,9 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
     if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    if (method != KRY_LANCZOS) return fail(KRY_ENOTSUP, "only Lanczos (symmetric A) is supported in this build");
-    if (!sys->symmetric) return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
+    if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
+        return fail(KRY_ENOTSUP, "method must be KRY_AUTO, KRY_LANCZOS or KRY_ARNOLDI in this build");
+    if (method == KRY_LANCZOS && !sys->symmetric) return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
     if (block_p < 0) return fail(KRY_EINVAL, "block_p must be >= 0");
     const int64_t n = sys->n;
     for (int32_t g = 0; g < ngen; ++g) {
@@ -414,7 +428,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
     const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
-    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes);
+    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method);
+    plan->method = method;
     const Layout& Y = plan->Y;
 
     if (workspace) {
@@ -547,10 +562,12 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             return launch_start(P, plan->o, src, plan->T, plan->oset0, plan->vec(0), B, s);
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
+        const bool arnoldi = plan->method == KRY_ARNOLDI;
         for (int j = 1; j <= plan->k; ++j) {
-            double* ucur = plan->vec((j - 1) % 3);
-            double* uprev = plan->vec((j + 1) % 3);   // (j - 2) mod 3
-            double* w = plan->vec(j % 3);
+            // Lanczos rotates three vectors; Arnoldi keeps u_1..u_{k+1}
+            double* ucur = arnoldi ? plan->vec(j - 1) : plan->vec((j - 1) % 3);
+            double* uprev = arnoldi ? nullptr : plan->vec((j + 1) % 3);   // (j - 2) mod 3
+            double* w = arnoldi ? plan->vec(j) : plan->vec(j % 3);
             if (plan->sys.kind == KRY_CSR) {
                 CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals};
                 e = timed("spmv_csr", s, [&] { return launch_spmv_csr(P, plan->lpr, A, ucur, uprev, w, B, j, s); });
@@ -560,8 +577,22 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                 e = timed("spmv_stencil", s, [&] { return launch_spmv_stencil(P, A, ucur, uprev, w, B, j, s); });
             }
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("spmv: ") + hipGetErrorString(e));
-            e = timed("sweep", s, [&] { return launch_sweep(P, plan->o, plan->T, plan->oset0, ucur, w, B, j, s); });
-            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
+            if (!arnoldi) {
+                e = timed("sweep", s, [&] { return launch_sweep(P, plan->o, plan->T, plan->oset0, ucur, w, B, j, s); });
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
+                continue;
+            }
+            // CGS2 against u_1..u_j (Algorithm 1's projection loop, classical form, twice)
+            ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef()};
+            for (int pass = 1; pass <= 2; ++pass) {
+                e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ar, B, j, s); });
+                if (e == hipSuccess) e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ar, B, j, pass, s); });
+                if (e == hipSuccess)
+                    e = timed("arn_update", s, [&] {
+                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j, pass == 2 ? 1 : 0, s);
+                    });
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
+            }
         }
         e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
@@ -572,6 +603,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     E.L = Y.L;
     E.role = plan->role_dev;
     E.dt = plan->dt;
+    E.hess_mode = plan->method == KRY_ARNOLDI ? 1 : 0;
     E.B = Y.B;
     E.nanch = Y.nanch;
     pade13(E.pade);
@@ -670,6 +702,11 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
         const int sh = bordered ? 1 : 0;
         if (bordered && dim > 1) H[1 * dim + 0] = sc[L.beta + 0];
         for (int i = 0; i < tri; ++i) {
+            if (plan->method == KRY_ARNOLDI) {
+                for (int c = i; c < tri; ++c) H[(i + sh) * dim + (c + sh)] = sc[L.hess + i * k + c];
+                if (i + 1 < tri) H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
+                continue;
+            }
             H[(i + sh) * dim + (i + sh)] = sc[L.alpha + i + 1];
             if (i + 1 < tri) {
                 H[(i + sh) * dim + (i + 1 + sh)] = sc[L.beta + i + 1];

@@ -139,15 +139,16 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
         const int i = idx / mm, c = idx % mm;
         double h = 0.0;
         if (i < m && c < m) {
-            if (!bordered) {
-                if (i == c) h = sc[E.L.alpha + i + 1];
-                else if (c == i + 1) h = sc[E.L.beta + i + 1];
-                else if (i == c + 1) h = sc[E.L.beta + c + 1];
-            } else {
-                // row/column 0 is the augmented variable; T occupies 1..m-1
-                if (i == 1 && c == 0) h = sc[E.L.beta + 0];
-                else if (i >= 1 && c >= 1) {
-                    const int a = i - 1, b = c - 1;
+            // row/column 0 of the bordered matrix is the augmented variable;
+            // the Krylov matrix of A occupies 1..m-1 there
+            const int sh = bordered ? 1 : 0;
+            if (bordered && i == 1 && c == 0) h = sc[E.L.beta + 0];
+            else if (i >= sh && c >= sh) {
+                const int a = i - sh, b = c - sh;
+                if (E.hess_mode) {
+                    if (a <= b) h = sc[E.L.hess + a * k + b];
+                    else if (a == b + 1) h = sc[E.L.beta + b + 1];
+                } else {
                     if (a == b) h = sc[E.L.alpha + a + 1];
                     else if (b == a + 1) h = sc[E.L.beta + a + 1];
                     else if (a == b + 1) h = sc[E.L.beta + b + 1];

@@ -39,6 +39,7 @@ struct ScalLayout {
     int32_t sigma;
     int32_t proj;
     int32_t misc;
+    int32_t hess;    // Arnoldi: H[i][c] at hess + i * k + c, i <= k, c < k
 };
 enum { MISC_KEFF = 0, MISC_DONE = 1, MISC_NONFINITE = 2, MISC_COUNT = 4 };
 
@@ -87,6 +88,7 @@ struct ExpmArgs {
     ScalLayout L;
     const int32_t* role;     // 0 generator, 1 center, 2 augmented
     double dt;
+    int32_t hess_mode;       // 0: tridiagonal from alpha/beta (Lanczos); 1: Hessenberg (Arnoldi)
     int32_t B;               // anchor spacing (power of two)
     int32_t nanch;           // anchors per run: ceil((steps + 1) / B)
     double pade[14];         // [13/13] Pade numerator coefficients, b_13 = 1
@@ -117,6 +119,18 @@ struct CheckArgs {
     double* verdict;         // [first_step, row, y, lo, hi, status, z[nruns]]
 };
 
+// Classical Gram-Schmidt with reorthogonalisation (CGS2) for Arnoldi.  The
+// basis is stored unnormalised, column-major per run batch: u_i at
+// V + (i - 1) * n * P ([n][P] interleaved), v_i = sigma_i u_i.
+struct ArnArgs {
+    const double* V;         // u_1 .. u_j (j = iteration), each [n][P]
+    int64_t vstride;         // elements from u_i to u_{i+1} (n * the plan's largest batch)
+    double* w;               // vector being orthogonalised ([n][P]), u_{j+1} once swept
+    double* hpart;           // [kMaxK][kMaxP][nblocks] partials of u_i . w
+    double* hcoef;           // [kMaxK][kMaxP] coefficients of the current pass (h_i * sigma_i)
+};
+constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
+
 // ---- launchers (kry_lanczos.hip, kry_expm.hip) ----------------------------
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
                               int64_t rows_per_block, double* out, hipStream_t s);
@@ -136,5 +150,9 @@ hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);
 int check_blocks(int64_t steps, int32_t o);
 hipError_t launch_assemble(const AssembleArgs& A, hipStream_t s);
 hipError_t launch_check(const CheckArgs& C, hipStream_t s);
+hipError_t launch_arn_dots(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s);
+hipError_t launch_arn_reduce(int P, const ArnArgs& A, const BatchArgs& B, int j, int pass, hipStream_t s);
+hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
+                             const BatchArgs& B, int j, int last, hipStream_t s);
 
 }  // namespace kry

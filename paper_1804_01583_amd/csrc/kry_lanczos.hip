@@ -16,7 +16,7 @@
 // |u_j|^2 and C u_j are kept per iteration, and k_finish turns them into the
 // columns of P = C V once per batch.  The row -> block partition depends on n
 // only, so a run's arithmetic does not depend on which batch (or P) advances it.
-#include "kry_internal.h"
+#include "kry_device.h"
 
 #include <cmath>
 
@@ -24,137 +24,7 @@ namespace kry {
 
 namespace {
 
-template <int NV>
-__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] += __shfl_xor(v[i], off, 64);
-    }
-}
-
-// Sum of v over the block; thread i < NV returns total i.  `lds` holds
-// (kBlock / 64) * NV doubles.  Every thread must call it.
-template <int NV>
-__device__ __forceinline__ double block_sum(double (&v)[NV], double* lds) {
-    wave_sum<NV>(v);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
-    }
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x < NV) {
-        t = lds[threadIdx.x];
-#pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) t += lds[w * NV + threadIdx.x];
-    }
-    __syncthreads();
-    return t;
-}
-
-// Workgroups are dispatched to the 8 XCDs round-robin by blockIdx; the
-// logical block (row range) of a workgroup is chosen so each XCD works on a
-// contiguous eighth of the rows, which keeps the +-m^2 neighbours of a 3D
-// stencil row in the same XCD's L2.  nblocks is a multiple of 8.
-__device__ __forceinline__ int logical_block(int nblocks, int xcd_map = 1) {
-    if (!xcd_map) return (int)blockIdx.x;
-    return (int)(blockIdx.x & 7) * (nblocks >> 3) + (int)(blockIdx.x >> 3);
-}
-
-// Writes the block totals of v as partials part[i * nblocks + block].
-template <int NV>
-__device__ __forceinline__ void store_partials(double (&v)[NV], double* part, int nblocks, double* lds,
-                                               int xcd_map) {
-    const double t = block_sum<NV>(v, lds);
-    if (threadIdx.x < NV) part[(int64_t)threadIdx.x * nblocks + logical_block(nblocks, xcd_map)] = t;
-}
-
-// Totals of values vbeg..vbeg+NV-1 of a partial array over nb blocks, in a
-// fixed order; result in s_out[0..NV) for every thread.
-template <int NV>
-__device__ __forceinline__ void sum_partials(const double* part, int nb, int vbeg, double* lds, double* s_out) {
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += part[(int64_t)(vbeg + i) * nb + b];
-    }
-    const double t = block_sum<NV>(acc, lds);
-    if (threadIdx.x < NV) s_out[threadIdx.x] = t;
-    __syncthreads();
-}
-
-__device__ __forceinline__ double* run_scal(const BatchArgs& B, int p) {
-    return B.scal + (int64_t)(B.run0 + p) * B.L.stride;
-}
-
-// Stage j-1 -> sigma_j.  nrm2 = |u_j|^2 (u_j is the start vector for j = 1,
-// the swept vector of iteration j-1 otherwise).  A step whose norm is at most
-// 1024 eps ||A||_inf ends the run (invariant Krylov space); sigma stays 0 from
-// then on, which keeps every later vector exactly zero.
-struct Stage {
-    double beta, sigma, cprev;
-    int keff;          // new k_eff to record, or -1 to leave it
-    bool nonfinite;
-};
-
-__device__ __forceinline__ Stage stage_update_v(int k, double sig_prev, double tau, int j, double nrm2) {
-    Stage st;
-    st.beta = sqrt(nrm2);
-    st.keff = -1;
-    st.nonfinite = false;
-    st.cprev = 0.0;
-    if (j == 1) {
-        const bool ok = st.beta > 0.0 && isfinite(st.beta);
-        st.sigma = ok ? 1.0 / st.beta : 0.0;
-        st.keff = ok ? k : 0;
-        st.nonfinite = !isfinite(st.beta);
-        return st;
-    }
-    st.cprev = st.beta * sig_prev;
-    if (sig_prev == 0.0) {
-        st.sigma = 0.0;
-        st.cprev = 0.0;
-    } else if (!isfinite(st.beta)) {
-        st.sigma = 0.0;
-        st.cprev = 0.0;
-        st.keff = j - 1;
-        st.nonfinite = true;
-    } else if (st.beta <= tau) {
-        st.sigma = 0.0;
-        st.keff = j - 1;
-    } else {
-        st.sigma = 1.0 / st.beta;
-    }
-    return st;
-}
-
-__device__ __forceinline__ Stage stage_update(const BatchArgs& B, const double* sc, int j, double nrm2) {
-    return stage_update_v(B.L.k, j > 1 ? sc[B.L.sigma + j - 1] : 0.0, B.tau_scale * *B.anorm, j, nrm2);
-}
-
-// Block 0 of the kernel that consumes stage j-1 records its scalars (the
-// projections are summed later, once per batch, by k_finish).
-__device__ __forceinline__ void record_stage(const BatchArgs& B, int P, int j, const double* nrm2) {
-    if (threadIdx.x < P) {
-        const int p = threadIdx.x;
-        double* sc = run_scal(B, p);
-        const Stage st = stage_update(B, sc, j, nrm2[p]);
-        sc[B.L.beta + j - 1] = st.beta;
-        sc[B.L.sigma + j] = st.sigma;
-        if (st.keff >= 0) sc[B.L.misc + MISC_KEFF] = (double)st.keff;
-        if (j == 1) sc[B.L.misc + MISC_NONFINITE] = st.nonfinite ? 1.0 : 0.0;
-        else if (st.nonfinite) sc[B.L.misc + MISC_NONFINITE] = 1.0;
-    }
-}
-
-__device__ __forceinline__ double* stage_part(const BatchArgs& B, int stage) {
-    return B.np_part + (int64_t)stage * B.nvp * B.nblocks;
-}
-
+using namespace dev;
 // ---------------------------------------------------------------------------
 
 // max_r sum_e |vals[e]| (row sums in CSR order, one thread per row): block
@@ -200,69 +70,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_max(const double* part, int n
         *out = v;
     }
 }
-
-// ---------------------------------------------------------------------------
-// Segment sets (generators and output rows) a block needs are staged in LDS.
-// The plan precomputes, for every set and logical block, the range of that
-// set's segments overlapping the block's rows (SegTable::blk), so a block
-// finds them with one load; up to kSegCap of them are copied to LDS, a set
-// with more keeps reading global memory.
-constexpr int kSegCap = 64;
-
-template <int NS>
-struct SegStage {
-    int64_t lo[NS][kSegCap];
-    int64_t hi[NS][kSegCap];
-    double w[NS][kSegCap];
-    int32_t beg[NS], end[NS];
-};
-
-// Every thread must call it.  sets[i] < 0 stages an empty set.
-template <int NS>
-__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, const int (&sets)[NS],
-                                               int lb, int nblocks) {
-    if (threadIdx.x < NS) {
-        const int s = sets[threadIdx.x];
-        int32_t b = 0, e = 0;
-        if (s >= 0) {
-            b = T.blk[((int64_t)s * nblocks + lb) * 2];
-            e = T.blk[((int64_t)s * nblocks + lb) * 2 + 1];
-        }
-        st.beg[threadIdx.x] = b;
-        st.end[threadIdx.x] = e;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < NS * kSegCap; idx += kBlock) {
-        const int i = idx / kSegCap, c = idx % kSegCap;
-        const int g = st.beg[i] + c;
-        if (g < st.end[i]) {
-            st.lo[i][c] = T.lo[g];
-            st.hi[i][c] = T.hi[g];
-            st.w[i][c] = T.w[g];
-        }
-    }
-    __syncthreads();
-}
-
-// Weight of increasing rows in one staged set, amortised O(1) per row.
-struct SegCursor {
-    int32_t cur, cnt, gcur, gend;
-    template <int NS>
-    __device__ __forceinline__ void init(const SegStage<NS>& st, int i) {
-        const int n = st.end[i] - st.beg[i];
-        cur = 0;
-        cnt = n <= kSegCap ? n : 0;
-        gcur = n <= kSegCap ? 0 : st.beg[i];
-        gend = n <= kSegCap ? 0 : st.end[i];
-    }
-    template <int NS>
-    __device__ __forceinline__ double weight(const SegStage<NS>& st, int i, const SegTable& T, int64_t r) {
-        while (cur < cnt && st.hi[i][cur] <= r) ++cur;
-        if (cur < cnt) return st.lo[i][cur] <= r ? st.w[i][cur] : 0.0;
-        while (gcur < gend && T.hi[gcur] <= r) ++gcur;
-        return (gcur < gend && T.lo[gcur] <= r) ? T.w[gcur] : 0.0;
-    }
-};
 
 // a2: start vectors u_1 of the runs and the partials of |u_1|^2 and C u_1
 // (Algorithm 4, first two statements; the scaling happens in the next kernel).
@@ -344,8 +151,9 @@ __device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, do
     }
 }
 
-// a3 + first half of a4: w = sigma_j A u_j - beta_{j-1} sigma_{j-1} u_{j-1};
-// partials of (sigma_j u_j) . w.  LPR lanes cooperate on one row.  Rows are
+// a3 + first half of a4: w = sigma_j A u_j - beta_{j-1} sigma_{j-1} u_{j-1}
+// (Lanczos), or w = sigma_j A u_j when uprev is null (Arnoldi); partials of
+// (sigma_j u_j) . w.  LPR lanes cooperate on one row.  Rows are
 // taken in chunks of RC per lane group; the first chunk's gathers are issued
 // before the stage reduction they do not depend on.
 template <int P, int LPR>
@@ -438,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         double y = sig[p] * acc[i][p];
-                        if (j > 1) y = fma(-cprev[p], uprev[r * P + p], y);
+                        if (j > 1 && uprev != nullptr) y = fma(-cprev[p], uprev[r * P + p], y);
                         w[r * P + p] = y;
                         dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
                     }
@@ -485,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
             if (iy < S.ny - 1) acc = fma(S.cy, ucur[(r + sy) * P + p], acc);
             if (ix < S.nx - 1) acc = fma(S.cx, ucur[(r + sx) * P + p], acc);
             double y = sig[p] * acc;
-            if (j > 1) y = fma(-cprev[p], uprev[r * P + p], y);
+            if (j > 1 && uprev != nullptr) y = fma(-cprev[p], uprev[r * P + p], y);
             w[r * P + p] = y;
             dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
         }

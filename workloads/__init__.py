@@ -28,7 +28,7 @@ __all__ = [
     "Segments", "Generator", "Problem",
     "segments_from_ranges", "box_segments", "csr_stencil7",
     "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil",
-    "random_symmetric", "small_heat3d",
+    "random_symmetric", "small_heat3d", "conv_diff3d",
 ]
 
 
@@ -323,3 +323,68 @@ def random_symmetric(n=300, nnz_per_row=5, k=12, steps=50, dt=0.05, ngen=3, o=2,
     ctr = rng.normal(0, 1, size=n) * (rng.uniform(size=n) < 0.05) if center else None
     return Problem("random_symmetric", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
                    b=b, center=ctr, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed)
+
+
+# ---------------------------------------------------------------------------
+# Nonsymmetric 3D convection-diffusion (first-order upwind convection, central
+# diffusion, Dirichlet), plus random off-stencil entries
+# ---------------------------------------------------------------------------
+
+def conv_diff3d(nx=200, ny=200, nz=250, peclet=5.0, extra_per_row=2, extra_sigma=1e-3, ngen=16,
+                gen_len=1000, o=5, k=30, dt=1e-4, steps=1000, seed=3) -> Problem:
+    """u' = D lap(u) - v . grad(u) on an nx*ny*nz grid with h = 1/(max dim + 1),
+    per-node velocity v ~ U[-1,1]^3, D = h / peclet (cell Peclet number
+    max|v_i| h / D = peclet), upwind differences for the convection, and
+    `extra_per_row` random off-stencil entries ~ N(0, extra_sigma) per row.
+    Generators: indicators of `ngen` disjoint seeded index ranges of length
+    `gen_len`, 1.0 +- 0.1; outputs: means over `o` seeded ranges, the first
+    two overlapping generator ranges."""
+    n = nx * ny * nz
+    h = 1.0 / (max(nx, ny, nz) + 1)
+    D = h / peclet
+    rng = np.random.default_rng(seed)
+    vel = rng.uniform(-1.0, 1.0, size=(n, 3))
+    idx = np.arange(n, dtype=np.int64)
+    iz = idx % nz
+    iy = (idx // nz) % ny
+    ix = idx // (ny * nz)
+    d = D / h**2
+    diag = np.full(n, -6.0 * d) - np.abs(vel).sum(axis=1) / h
+    cols, vals = [idx], [diag]
+    for axis, (coord, m, stride) in enumerate(((ix, nx, ny * nz), (iy, ny, nz), (iz, nz, 1))):
+        v = vel[:, axis]
+        lo_ok, hi_ok = coord > 0, coord < m - 1
+        cols.append(np.where(lo_ok, idx - stride, -1)); vals.append(d + np.maximum(v, 0.0) / h)
+        cols.append(np.where(hi_ok, idx + stride, -1)); vals.append(d + np.maximum(-v, 0.0) / h)
+    for _ in range(extra_per_row):
+        cols.append(rng.integers(0, n, size=n)); vals.append(rng.normal(0.0, extra_sigma, size=n))
+    C_ = np.stack(cols, axis=1)
+    V_ = np.stack(vals, axis=1)
+    rows = np.repeat(idx, C_.shape[1])
+    C_ = C_.ravel(); V_ = V_.ravel()
+    keep = C_ >= 0
+    rows, C_, V_ = rows[keep], C_[keep], V_[keep]
+    order = np.lexsort((C_, rows))
+    rows, C_, V_ = rows[order], C_[order], V_[order]
+    # merge duplicate (row, column) pairs
+    first = np.ones(rows.size, dtype=bool)
+    first[1:] = (rows[1:] != rows[:-1]) | (C_[1:] != C_[:-1])
+    grp = np.cumsum(first) - 1
+    vals_m = np.zeros(int(first.sum()))
+    np.add.at(vals_m, grp, V_)
+    rows_m, cols_m = rows[first], C_[first]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rowptr, rows_m + 1, 1)
+    rowptr = np.cumsum(rowptr)
+    slots = rng.choice(n // gen_len, size=ngen + o, replace=False) * gen_len
+    gens = [Generator(segments_from_ranges([(int(s), int(s) + gen_len)], 1.0), zc=1.0, radius=0.1)
+            for s in slots[:ngen]]
+    out_starts = list(slots[ngen:ngen + o])
+    for q in range(min(2, o)):
+        out_starts[q] = int(slots[q]) + gen_len // 2          # overlaps generator q
+    C = [segments_from_ranges([(int(s), int(s) + gen_len)], 1.0 / gen_len) for s in out_starts]
+    unsafe = np.stack([np.full(o, 0.5), np.full(o, math.inf)], axis=1)
+    return Problem("conv_diff3d", n, "csr", False, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   rowptr=rowptr, colidx=cols_m.astype(np.int32), vals=vals_m, seed=seed,
+                   meta={"grid": (nx, ny, nz), "D": D, "h": h},
+                   note="nonsymmetric upwind convection-diffusion with random off-stencil entries")
