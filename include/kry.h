@@ -50,6 +50,15 @@ typedef enum { KRY_AUTO = 0, KRY_LANCZOS = 1, KRY_ARNOLDI = 2, KRY_BLOCK_ARNOLDI
 
 typedef enum { KRY_CSR = 0, KRY_STENCIL7 = 1 } kry_kind;
 
+/* A sparse vector as nseg disjoint half-open index ranges [lo, hi), sorted
+ * ascending, each with one value w.  Host arrays. */
+typedef struct kry_segs {
+    int64_t nseg;
+    const int64_t* lo;
+    const int64_t* hi;
+    const double* w;
+} kry_segs;
+
 /* The system matrix A and the forcing b (Section 2, x' = A x + b).
  * KRY_CSR: rowptr[n+1] (int64), colidx[nnz] (int32, < n), vals[nnz] (FP64),
  *   all device memory, rows in order; duplicate columns are summed.
@@ -58,6 +67,8 @@ typedef enum { KRY_CSR = 0, KRY_STENCIL7 = 1 } kry_kind;
  *   cz (...), neighbours outside the grid are zero (Dirichlet).
  * b: device n-vector or NULL.  When non-NULL the state is augmented with a
  *   constant variable a = 1 (Section 2.1) and one extra simulation runs.
+ * b_segs: the forcing as index ranges (host), used when b is NULL; for large
+ *   systems whose forcing is a few regions.
  * symmetric: the caller promises A == A^T (needed by Lanczos, Section 4.3).
  * anorm: max absolute row sum of A, or 0 to let kry_plan compute it; it only
  *   scales the breakdown test (a Krylov step whose new norm is at most
@@ -74,16 +85,8 @@ typedef struct kry_system {
     double c0, cx, cy, cz;
     const double* b;
     double anorm;
+    const kry_segs* b_segs;
 } kry_system;
-
-/* A sparse vector as nseg disjoint half-open index ranges [lo, hi), sorted
- * ascending, each with one value w.  Host arrays. */
-typedef struct kry_segs {
-    int64_t nseg;
-    const int64_t* lo;
-    const int64_t* hi;
-    const double* w;
-} kry_segs;
 
 /* One column g_j of E with its box coefficient z_j in [zc - radius, zc + radius]
  * (Section 3.2, initial space I_z given as a box). */
@@ -113,7 +116,7 @@ typedef struct kry_plan kry_plan;
  * the device state for them (Sections 2.1, 3.2, 4.1).
  * Runs, in this order: one per generator [g_j; 0], one for the fixed center
  * [x_c; 0] when center != NULL (device n-vector), one for the augmented
- * variable [0; 1] when sys->b != NULL.
+ * variable [0; 1] when sys->b or sys->b_segs is given.
  *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
  *  k: Krylov dimension per run, 1 <= k <= 56.  The augmented run uses k-1
  *     Lanczos steps on A from b bordered by one row and column, which spans

@@ -245,7 +245,7 @@ def build_runs(problem) -> List[Run]:
     runs = [Run("gen", g.seg.dense(n), j) for j, g in enumerate(problem.gens)]
     if problem.center is not None:
         runs.append(Run("center", np.asarray(problem.center, np.float64), -1))
-    if problem.b is not None:
+    if problem.has_forcing:
         e = np.zeros(n + 1); e[n] = 1.0
         runs.append(Run("affine", e, -1))
     return runs
@@ -260,7 +260,7 @@ def krylov_run(problem, run: Run, A=None, Aaug=None, C=None, method="auto", k=No
     k = problem.k if k is None else k
     opnorm = inf_norm(A)
     if run.role == "affine":
-        Aaug = augment(A, problem.b) if Aaug is None else Aaug
+        Aaug = augment(A, problem.forcing()) if Aaug is None else Aaug
         Caug = sp.hstack([C, sp.csr_matrix((C.shape[0], 1))]).tocsr()
         return arnoldi(Aaug, run.start, k, Caug, opnorm=opnorm)
     if method == "arnoldi" or (method == "auto" and not problem.symmetric):
@@ -317,7 +317,7 @@ def verify(problem, method="auto", k=None, steps=None, dt=None):
     dt = problem.dt if dt is None else dt
     A = system_matrix(problem)
     C = output_matrix(problem)
-    Aaug = augment(A, problem.b) if problem.b is not None else None
+    Aaug = augment(A, problem.forcing()) if problem.has_forcing else None
     runs = build_runs(problem)
     results = [krylov_run(problem, r, A=A, Aaug=Aaug, C=C, method=method, k=k) for r in runs]
     basis = np.stack([project_steps(res, dt, steps) for res in results], axis=2)

@@ -274,6 +274,7 @@ struct kry_plan {
     std::vector<double> zc, radius;
     std::vector<int32_t> gen_set;
     int32_t oset0 = 0;
+    int32_t bset = -1;
     const double* center = nullptr;
     Layout Y{};
     char* ws = nullptr;
@@ -337,6 +338,11 @@ kry_status validate_system(const kry_system* sys) {
         return fail(KRY_EINVAL, "unknown system kind");
     }
     if (!(sys->anorm >= 0.0) || !std::isfinite(sys->anorm)) return fail(KRY_EINVAL, "anorm must be finite and >= 0");
+    if (sys->b && sys->b_segs) return fail(KRY_EINVAL, "give the forcing as b or as b_segs, not both");
+    if (sys->b_segs) {
+        const kry_status st = check_segs(*sys->b_segs, sys->n, "forcing");
+        if (st != KRY_OK) return st;
+    }
     return KRY_OK;
 }
 
@@ -357,8 +363,8 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
     const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nruns + o, nruns, nb),
-                                 method);
+    const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
+    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method);
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -412,7 +418,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
         plan->radius.push_back(gens[g].radius);
     }
     if (center) { plan->role.push_back(1); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
-    if (sys->b) { plan->role.push_back(2); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
+    if (sys->b || sys->b_segs) { plan->role.push_back(2); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
     plan->nruns = (int32_t)plan->role.size();
     if (plan->nruns == 0) {
         delete plan;
@@ -423,8 +429,9 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     int64_t total_segs = 0;
     for (int32_t g = 0; g < ngen; ++g) total_segs += gens[g].seg.nseg;
     for (int32_t q = 0; q < o; ++q) total_segs += C[q].nseg;
+    if (sys->b_segs) total_segs += sys->b_segs->nseg;
     if (total_segs >= ((int64_t)1 << 31)) { delete plan; return fail(KRY_EINVAL, "too many segments"); }
-    const int32_t nsets = ngen + o;
+    const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0);
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
     const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
@@ -473,6 +480,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     for (int32_t g = 0; g < ngen; ++g) { plan->gen_set.push_back(set); add_set(gens[g].seg); }
     plan->oset0 = set;
     for (int32_t q = 0; q < o; ++q) add_set(C[q]);
+    plan->bset = -1;
+    if (sys->b_segs) { plan->bset = set; add_set(*sys->b_segs); }
     sb[set] = (int32_t)at;
     // per logical block b (rows [b*rpb, (b+1)*rpb)), the segments of each set
     // that overlap it: [first with hi > row0, first with lo >= row1)
@@ -523,6 +532,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     int lpr = env_int("KRY_LPR", 0);
     if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8) lpr = avg > 24 ? 8 : (avg > 12 ? 4 : 1);
     plan->lpr = lpr;
+    plan->sys.b_segs = nullptr;    // copied into the segment table; not kept
     *out = plan;
     return KRY_OK;
 }
@@ -556,7 +566,8 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             const int r = r0 + p;
             if (plan->role[r] == 0) src.set[p] = plan->gen_set[r];
             else if (plan->role[r] == 1) src.dense[p] = plan->center;
-            else src.dense[p] = plan->sys.b;
+            else if (plan->sys.b) src.dense[p] = plan->sys.b;
+            else src.set[p] = plan->bset;
         }
         hipError_t e = timed("start", s, [&] {
             return launch_start(P, plan->o, src, plan->T, plan->oset0, plan->vec(0), B, s);

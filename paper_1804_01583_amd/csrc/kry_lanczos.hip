@@ -259,7 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
 }
 
 // Matrix-free 7-point stencil version of k_spmv_csr (zero outside the grid),
-// neighbours summed in ascending index order like a CSR row.
+// neighbours summed in ascending index order like a CSR row.  Each thread
+// decodes its first row's grid coordinates once and advances them as it
+// strides by kBlock rows, so no division runs per row.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const double* __restrict__ ucur,
                                                          const double* __restrict__ uprev,
@@ -271,31 +273,41 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
     double pacc[P], sig_prev[P], anorm;
     load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
+    int64_t r = r0 + threadIdx.x;
+    int64_t iz = r % S.nz;
+    int64_t iy = (r / S.nz) % S.ny;
+    int64_t ix = r / (S.nz * S.ny);
     double sig[P], cprev[P];
     finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
     const int64_t sx = S.ny * S.nz, sy = S.nz;
+    const bool prev = j > 1 && uprev != nullptr;
     double dot[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) dot[p] = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        const int64_t iz = r % S.nz;
-        const int64_t t = r / S.nz;
-        const int64_t iy = t % S.ny;
-        const int64_t ix = t / S.ny;
+    for (; r < r1; r += kBlock) {
+        const bool xl = ix > 0, xh = ix < S.nx - 1;
+        const bool yl = iy > 0, yh = iy < S.ny - 1;
+        const bool zl = iz > 0, zh = iz < S.nz - 1;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             double acc = 0.0;
-            if (ix > 0) acc = fma(S.cx, ucur[(r - sx) * P + p], acc);
-            if (iy > 0) acc = fma(S.cy, ucur[(r - sy) * P + p], acc);
-            if (iz > 0) acc = fma(S.cz, ucur[(r - 1) * P + p], acc);
-            acc = fma(S.c0, ucur[r * P + p], acc);
-            if (iz < S.nz - 1) acc = fma(S.cz, ucur[(r + 1) * P + p], acc);
-            if (iy < S.ny - 1) acc = fma(S.cy, ucur[(r + sy) * P + p], acc);
-            if (ix < S.nx - 1) acc = fma(S.cx, ucur[(r + sx) * P + p], acc);
+            if (xl) acc = fma(S.cx, ucur[(r - sx) * P + p], acc);
+            if (yl) acc = fma(S.cy, ucur[(r - sy) * P + p], acc);
+            if (zl) acc = fma(S.cz, ucur[(r - 1) * P + p], acc);
+            const double own = ucur[r * P + p];
+            acc = fma(S.c0, own, acc);
+            if (zh) acc = fma(S.cz, ucur[(r + 1) * P + p], acc);
+            if (yh) acc = fma(S.cy, ucur[(r + sy) * P + p], acc);
+            if (xh) acc = fma(S.cx, ucur[(r + sx) * P + p], acc);
             double y = sig[p] * acc;
-            if (j > 1 && uprev != nullptr) y = fma(-cprev[p], uprev[r * P + p], y);
+            if (prev) y = fma(-cprev[p], uprev[r * P + p], y);
             w[r * P + p] = y;
-            dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
+            dot[p] = fma(sig[p] * own, y, dot[p]);
+        }
+        iz += kBlock;
+        while (iz >= S.nz) {
+            iz -= S.nz;
+            if (++iy == S.ny) { iy = 0; ++ix; }
         }
     }
     store_partials<P>(dot, B.ap_part, B.nblocks, s_lds, B.xcd_map);

@@ -31,16 +31,16 @@ class KryError(RuntimeError):
         self.status = status
 
 
+class KrySegs(ct.Structure):
+    _fields_ = [("nseg", ct.c_int64), ("lo", ct.c_void_p), ("hi", ct.c_void_p), ("w", ct.c_void_p)]
+
+
 class KrySystem(ct.Structure):
     _fields_ = [("n", ct.c_int64), ("kind", ct.c_int32), ("symmetric", ct.c_int32),
                 ("rowptr", ct.c_void_p), ("colidx", ct.c_void_p), ("vals", ct.c_void_p),
                 ("nnz", ct.c_int64), ("nx", ct.c_int64), ("ny", ct.c_int64), ("nz", ct.c_int64),
                 ("c0", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double), ("cz", ct.c_double),
-                ("b", ct.c_void_p), ("anorm", ct.c_double)]
-
-
-class KrySegs(ct.Structure):
-    _fields_ = [("nseg", ct.c_int64), ("lo", ct.c_void_p), ("hi", ct.c_void_p), ("w", ct.c_void_p)]
+                ("b", ct.c_void_p), ("anorm", ct.c_double), ("b_segs", ct.POINTER(KrySegs))]
 
 
 class KryGen(ct.Structure):
@@ -224,9 +224,13 @@ class DeviceSystem:
             s.nx, s.ny, s.nz = problem.grid
             s.c0, s.cx, s.cy, s.cz = problem.coef
         self.b = None
+        self._keep = []
         if problem.b is not None:
             self.b = torch.as_tensor(np.asarray(problem.b, np.float64), device=device)
             s.b = _ptr(self.b)
+        elif getattr(problem, "b_seg", None) is not None:
+            self._bseg = _segs(problem.b_seg, self._keep)
+            s.b_segs = ct.pointer(self._bseg)
         self.center = None
         if problem.center is not None:
             self.center = torch.as_tensor(np.asarray(problem.center, np.float64), device=device)
@@ -255,12 +259,15 @@ class Plan:
         self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
         self._C = [_segs(c, keep) for c in C]
         self._keep = keep
-        nruns = self.ngen + (dsys.center is not None) + (dsys.b is not None)
+        has_forcing = dsys.b is not None or getattr(p, "b_seg", None) is not None
+        nruns = self.ngen + (dsys.center is not None) + has_forcing
         self.stream = torch.cuda.current_stream(dsys.device) if stream is None else stream
         ws_ptr, ws_bytes = None, 0
         self.workspace = None
         if workspace == "torch":
             nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
+            if getattr(p, "b_seg", None) is not None and dsys.b is None:
+                nseg += p.b_seg.nseg
             ws_bytes = kry_footprint(dsys.sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
                                      method, block_p)
             self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dsys.device)

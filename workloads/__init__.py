@@ -98,6 +98,19 @@ class Problem:
     seed: int = 0
     note: str = ""
     meta: dict = field(default_factory=dict)
+    b_seg: Optional[Segments] = None    # forcing as index ranges (instead of a dense b)
+
+    @property
+    def has_forcing(self) -> bool:
+        return self.b is not None or self.b_seg is not None
+
+    def forcing(self) -> Optional[np.ndarray]:
+        """Dense forcing vector b (None when there is none)."""
+        if self.b is not None:
+            return np.asarray(self.b, np.float64)
+        if self.b_seg is not None:
+            return self.b_seg.dense(self.n)
+        return None
 
     @property
     def o(self) -> int:
@@ -270,7 +283,7 @@ def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
     fc = max(m // 10, 1)
     off = rng.integers(0, m - fc + 1, size=3)
     fbox = tuple((int(o), int(o) + fc) for o in off)
-    b = box_segments((m, m, m), fbox, 0.1).dense(n)
+    bseg = box_segments((m, m, m), fbox, 0.1)
     gbox = ((0, max(int(round(0.4 * m)), 1)), (0, max(int(round(0.2 * m)), 1)),
             (0, max(int(round(0.1 * m)), 1)))
     gseg = box_segments((m, m, m), gbox, 1.0)
@@ -280,7 +293,7 @@ def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
     C = [segments_from_ranges([(cpt, cpt + 1)]), box_segments((m, m, m), gbox, 1.0 / gseg.count)]
     unsafe = np.array([[0.5, math.inf], [1.2, math.inf]])
     return Problem("heat3d_stencil", n, "stencil7", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
-                   b=b, grid=(m, m, m), coef=coef, seed=seed,
+                   b_seg=bseg, grid=(m, m, m), coef=coef, seed=seed,
                    meta={"m": m, "forcing_box": fbox, "gen_box": gbox},
                    note="matrix-free 3D heat with affine forcing")
 
