@@ -49,7 +49,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--m", type=int, default=100)
+    ap.add_argument("--m", type=int, default=None, help="grid edge (default 100; 1000 for heat3d_stencil)")
+    ap.add_argument("--workload", default="heat3d_csr",
+                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d"],
+                    help="heat3d_csr is the benchmark line; the others are measured the same way")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
@@ -68,7 +71,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log("building inputs")
-    p = W.heat3d_csr(m=args.m)
+    if args.workload == "heat3d_csr":
+        p = W.heat3d_csr(m=args.m or 100)
+    elif args.workload == "heat3d_stencil":
+        p = W.heat3d_stencil(m=args.m or 1000)
+    elif args.workload == "heat1d":
+        p = W.heat1d()
+    else:
+        p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=2, o=5, k=30)
     dsys = kry.DeviceSystem(p, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -113,24 +123,30 @@ def main():
     verified = (p.steps + 1) * nruns
     value = verified / (elapsed / args.steps)
 
-    # algorithmic bytes per launch (runs of the batch advanced together)
+    # algorithmic bytes per launch (all runs of the plan advanced by one launch)
     n, nnz = p.n, p.nnz
-    P = nruns                      # 2 runs fit one batch for o = 3
-    spmv_bytes = 12 * nnz + 8 * (n + 1) + 3 * 8 * n * P     # A (val+col), rowptr, read v_j, v_{j-1}, write w
-    sweep_bytes = 3 * 8 * n * P                             # read v_j, w; write w
-    for name, b in (("spmv_csr", spmv_bytes), ("sweep", sweep_bytes)):
+    P = nruns
+    dom_name = "spmv_csr" if p.kind == "csr" else "spmv_stencil"
+    if p.kind == "csr":
+        spmv_bytes = 12 * nnz + 8 * (n + 1) + 3 * 8 * n * P     # A (val+col), rowptr, read v_j, v_{j-1}, write w
+    else:
+        spmv_bytes = 3 * 8 * n * P                              # read v_j, v_{j-1}, write w (matrix-free)
+    sweep_bytes = 3 * 8 * n * P                                 # read v_j, w; write w
+    for name, b in ((dom_name, spmv_bytes), ("sweep", sweep_bytes)):
         if name in kern:
             kern[name]["bytes"] = b
             kern[name]["GBps"] = b / (kern[name]["avg_us"] * 1e-6) / 1e9
-    dom = kern.get("spmv_csr", {})
+    dom = kern.get(dom_name, {})
     achieved = dom.get("GBps", 0.0)
-    traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_csr_heat3d_m100_pmc.md"))
+    traffic = None
+    if args.workload == "heat3d_csr" and (args.m or 100) == 100:
+        traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_csr_heat3d_m100_pmc.md"))
     # Lanczos iteration = spmv + sweep: bytes and time of both kernels
     step_bytes = spmv_bytes + sweep_bytes
     step_us = dom.get("avg_us", 0.0) + kern.get("sweep", {}).get("avg_us", 0.0)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and p.n <= 2_000_000:
         log("timing the CPU oracle on the same workload (one whole verification)")
         cpu = cpu_baseline(p)
 
@@ -147,12 +163,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"3D heat {args.m}^3 CSR (n={n}, nnz={nnz}) + affine forcing, Lanczos k={p.k}, "
-                               f"dt={p.dt}, {p.steps} steps, o={p.o}, runs={nruns}, FP64",
-                   "n": n, "nnz": nnz, "k": p.k, "time_steps": p.steps, "runs": nruns,
-                   "precision": "fp64", "method": "lanczos"},
+        "config": {"workload": describe(p, nruns), "n": n, "nnz": nnz, "k": p.k, "time_steps": p.steps,
+                   "runs": nruns, "precision": "fp64", "method": "lanczos" if p.symmetric else "arnoldi"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": "spmv_csr",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom_name,
                      "bytes_per_launch": spmv_bytes},
         "ms_per_step_with_kernel_events": 1000.0 * elapsed_ev / args.steps,
         "krylov_iteration": {"bytes": step_bytes, "us": step_us,
@@ -162,6 +176,18 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def describe(p, nruns):
+    if p.name == "heat3d_csr":
+        m = p.meta["m"]
+        return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
+                f"{p.steps} steps, o={p.o}, runs={nruns}, FP64")
+    if p.name == "heat3d_stencil":
+        m = p.meta["m"]
+        return (f"3D heat {m}^3 matrix-free 7-point (n={p.n}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
+                f"{p.steps} steps, o={p.o}, runs={nruns}, FP64")
+    return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} FP64"
 
 
 def counter_traffic(path):

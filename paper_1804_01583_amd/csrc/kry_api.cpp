@@ -120,6 +120,18 @@ int32_t nblocks_for(int64_t n, int64_t rpb) {
     return (int32_t)align_up((size_t)nb, 8);
 }
 
+// Column blocks of the marching stencil mat-vec (one thread per (y, z) column
+// walking along x), or 0 where the row-partitioned kernel is used: marching
+// needs enough columns to fill the chip.  KRY_STENCIL_MARCH=0/1 forces it.
+int32_t march_blocks_for(const kry_system& sys) {
+    if (sys.kind != KRY_STENCIL7) return 0;
+    const int64_t ncol = sys.ny * sys.nz;
+    const int mode = env_int("KRY_STENCIL_MARCH", -1);
+    const bool use = mode >= 0 ? mode != 0 : (ncol >= (int64_t)kBlock * 1024 && sys.nx >= 64);
+    if (!use) return 0;
+    return (int32_t)align_up((size_t)((ncol + kBlock - 1) / kBlock), 8);
+}
+
 int max_batch_for(int o, int block_p) {
     int p = 8;
     while (p > 1 && p * (1 + o) > kMaxNV) p >>= 1;
@@ -140,14 +152,16 @@ struct Layout {
     int32_t B, nanch;
     int32_t nvp;
     int32_t nvec;
+    int32_t march;        // column blocks of the marching stencil kernel (0: row kernel)
     size_t hpart, hcoef;
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
-                   size_t meta_bytes, int32_t method) {
+                   size_t meta_bytes, int32_t method, int32_t march) {
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
     Y.nblocks = nblocks_for(n, Y.rpb);
+    Y.march = march;
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
     if (method == KRY_ARNOLDI) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
     {
@@ -174,7 +188,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.hcoef = method == KRY_ARNOLDI ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
-    Y.ap_part = take((size_t)Y.nblocks * kMaxP * sizeof(double));
+    Y.ap_part = take((size_t)std::max(Y.nblocks, Y.march) * kMaxP * sizeof(double));
     Y.scal = take((size_t)nruns * L.stride * sizeof(double));
     // time steps s = b * B + r: B anchors of the Z chain, nanch of the anchor chain
     Y.B = 1;
@@ -364,7 +378,8 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
     const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
-    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method);
+    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
+                                 march_blocks_for(*sys));
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -435,7 +450,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
     const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
-    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method);
+    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys));
     plan->method = method;
     const Layout& Y = plan->Y;
 
@@ -558,6 +573,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         B.np_part = plan->np_part();
         B.nvp = Y.nvp;
         B.ap_part = plan->ap_part();
+        B.ap_nblocks = Y.march > 0 ? Y.march : Y.nblocks;
         B.anorm = plan->anorm();
         B.tau_scale = tau_scale;
         StartSrc src{};
@@ -585,7 +601,12 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             } else {
                 StencilArgs A{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx,
                               plan->sys.cy, plan->sys.cz};
-                e = timed("spmv_stencil", s, [&] { return launch_spmv_stencil(P, A, ucur, uprev, w, B, j, s); });
+                if (Y.march > 0)
+                    e = timed("spmv_stencil", s, [&] {
+                        return launch_spmv_stencil_march(P, A, ucur, uprev, w, B, j, s);
+                    });
+                else
+                    e = timed("spmv_stencil", s, [&] { return launch_spmv_stencil(P, A, ucur, uprev, w, B, j, s); });
             }
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("spmv: ") + hipGetErrorString(e));
             if (!arnoldi) {

@@ -60,7 +60,8 @@ struct BatchArgs {
     ScalLayout L;
     double* np_part;         // [k+1 stages][nvp][nblocks]: |u_j|^2 per run, then (C u_j)_q per run
     int32_t nvp;             // values per stage in np_part (>= P * (1 + o))
-    double* ap_part;         // [kMaxP][nblocks]:  v_j . w per run
+    double* ap_part;         // [kMaxP][ap_nblocks]:  v_j . w per run
+    int32_t ap_nblocks;      // blocks of the mat-vec launch (its own partition for the marching stencil)
     const double* anorm;     // ||A||_inf on the device
     double tau_scale;        // breakdown when beta_j <= tau_scale * ||A||_inf
 };
@@ -143,6 +144,9 @@ hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
 hipError_t launch_spmv_stencil(int P, const StencilArgs& A, const double* ucur,
                                const double* uprev, double* w, const BatchArgs& B, int j,
                                hipStream_t s);
+hipError_t launch_spmv_stencil_march(int P, const StencilArgs& A, const double* ucur,
+                                     const double* uprev, double* w, const BatchArgs& B, int j,
+                                     hipStream_t s);
 hipError_t launch_sweep(int P, int O, const SegTable& T, int32_t oset0, const double* ucur,
                         double* w, const BatchArgs& B, int j, hipStream_t s);
 hipError_t expm_prepare();

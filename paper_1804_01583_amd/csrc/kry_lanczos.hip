@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
         }
     }
     if (nch == 0) finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
-    store_partials<P>(dot, B.ap_part, B.nblocks, s_lds, B.xcd_map);
+    store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
 }
 
 // Matrix-free 7-point stencil version of k_spmv_csr (zero outside the grid),
@@ -310,7 +310,140 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
             if (++iy == S.ny) { iy = 0; ++ix; }
         }
     }
-    store_partials<P>(dot, B.ap_part, B.nblocks, s_lds, B.xcd_map);
+    store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
+}
+
+// The P interleaved entries of one row, as 16-byte loads where P is even.
+template <int P>
+__device__ __forceinline__ void load_row(const double* __restrict__ base, int64_t row, double (&v)[P]) {
+    if constexpr (P == 1) {
+        v[0] = base[row];
+    } else {
+        const double2* q = reinterpret_cast<const double2*>(base + row * P);
+#pragma unroll
+        for (int h = 0; h < P / 2; ++h) {
+            const double2 t = q[h];
+            v[2 * h] = t.x;
+            v[2 * h + 1] = t.y;
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_row(double* __restrict__ base, int64_t row, const double (&v)[P]) {
+    if constexpr (P == 1) {
+        base[row] = v[0];
+    } else {
+        double2* q = reinterpret_cast<double2*>(base + row * P);
+#pragma unroll
+        for (int h = 0; h < P / 2; ++h) q[h] = make_double2(v[2 * h], v[2 * h + 1]);
+    }
+}
+
+// One x step of the marching stencil: row r = ix * sx + col with u at x-1,
+// x, x+1 in xm, x0, xp; loads the x+2 plane into nx2 (a clamped in-bounds
+// address past the end: that value is never used, since the x + 1 term is
+// skipped at the last plane).
+struct MarchCol {
+    int64_t col, sx;
+    int64_t dyl, dyh, dzl, dzh;
+    bool yl, yh, zl, zh, live, prev;
+};
+
+template <int P>
+__device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol& M, int64_t ix,
+                                           const double* __restrict__ ucur, const double* __restrict__ up,
+                                           double* __restrict__ w, const double (&sig)[P],
+                                           const double (&cprev)[P], const double (&xm)[P],
+                                           const double (&x0)[P], const double (&xp)[P], double (&nx2)[P],
+                                           double (&dot)[P]) {
+    const int64_t r = ix * M.sx + M.col;
+    double vyl[P], vzl[P], vzh[P], vyh[P], vpr[P];
+    load_row<P>(ucur, r + M.dyl, vyl);
+    load_row<P>(ucur, r + M.dzl, vzl);
+    load_row<P>(ucur, r + M.dzh, vzh);
+    load_row<P>(ucur, r + M.dyh, vyh);
+    load_row<P>(up, r, vpr);
+    load_row<P>(ucur, ix + 2 < S.nx ? r + 2 * M.sx : r, nx2);
+    double y[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        double acc = 0.0;
+        if (ix > 0) acc = fma(S.cx, xm[p], acc);
+        if (M.yl) acc = fma(S.cy, vyl[p], acc);
+        if (M.zl) acc = fma(S.cz, vzl[p], acc);
+        acc = fma(S.c0, x0[p], acc);
+        if (M.zh) acc = fma(S.cz, vzh[p], acc);
+        if (M.yh) acc = fma(S.cy, vyh[p], acc);
+        if (ix < S.nx - 1) acc = fma(S.cx, xp[p], acc);
+        y[p] = sig[p] * acc;
+        if (M.prev) y[p] = fma(-cprev[p], vpr[p], y[p]);
+        dot[p] = fma(sig[p] * x0[p], y[p], dot[p]);
+    }
+    if (M.live) store_row<P>(w, r, y);
+}
+
+// Matrix-free 7-point stencil, marching form: one thread per (y, z) grid
+// column walks along x and keeps u at x-1, x, x+1 in registers (the x+2 plane
+// is loaded one step ahead), so each element of u is read from HBM once; the
+// y and z neighbours are the same plane's entries of neighbouring threads and
+// come from cache.  Column blocks are mapped XCD-contiguously so the y +- 1
+// columns share an L2.  Every load is unconditional (boundary neighbours read
+// a clamped in-bounds address and are then dropped) and the four plane
+// registers rotate by unrolling, so the x+2 load stays in flight across the
+// step.  Same summation order per row as k_spmv_stencil.  The dot partials
+// are indexed by column block (ap_nblocks of them).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, const double* __restrict__ ucur,
+                                                               const double* __restrict__ uprev,
+                                                               double* __restrict__ w, BatchArgs B, int j) {
+    __shared__ double s_lds[(kBlock / 64) * P];
+    __shared__ double s_nrm[P];
+    const int cb = logical_block(B.ap_nblocks, B.xcd_map);
+    const int64_t ncol = S.ny * S.nz;
+    const int64_t col0 = (int64_t)cb * kBlock + threadIdx.x;
+    MarchCol M;
+    M.live = col0 < ncol;
+    M.col = M.live ? col0 : ncol - 1;          // dead lanes shadow a live column and store nothing
+    M.sx = ncol;
+    double pacc[P], sig_prev[P], anorm;
+    load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
+    const int64_t iy = M.col / S.nz;
+    const int64_t iz = M.col % S.nz;
+    double a[P], b[P], c[P], d[P];
+    load_row<P>(ucur, M.col, b);
+    load_row<P>(ucur, S.nx > 1 ? M.col + M.sx : M.col, c);
+#pragma unroll
+    for (int p = 0; p < P; ++p) a[p] = 0.0;
+    double sig[P], cprev[P];
+    finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
+    M.prev = j > 1 && uprev != nullptr;
+    const double* __restrict__ up = M.prev ? uprev : ucur;
+    M.yl = iy > 0;
+    M.yh = iy < S.ny - 1;
+    M.zl = iz > 0;
+    M.zh = iz < S.nz - 1;
+    M.dyl = M.yl ? -S.nz : 0;
+    M.dyh = M.yh ? S.nz : 0;
+    M.dzl = M.zl ? -1 : 0;
+    M.dzh = M.zh ? 1 : 0;
+    double dot[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) dot[p] = 0.0;
+    for (int64_t ix = 0; ix < S.nx; ix += 4) {
+        march_step<P>(S, M, ix, ucur, up, w, sig, cprev, a, b, c, d, dot);
+        if (ix + 1 >= S.nx) break;
+        march_step<P>(S, M, ix + 1, ucur, up, w, sig, cprev, b, c, d, a, dot);
+        if (ix + 2 >= S.nx) break;
+        march_step<P>(S, M, ix + 2, ucur, up, w, sig, cprev, c, d, a, b, dot);
+        if (ix + 3 >= S.nx) break;
+        march_step<P>(S, M, ix + 3, ucur, up, w, sig, cprev, d, a, b, c, dot);
+    }
+    if (!M.live) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) dot[p] = 0.0;
+    }
+    store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
 }
 
 // Second half of a4 + the partials of a5 and a6: alpha_j = sum of the dot
@@ -332,9 +465,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
     double pacc[P], sigj[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) pacc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
+    for (int b = threadIdx.x; b < B.ap_nblocks; b += kBlock) {
 #pragma unroll
-        for (int p = 0; p < P; ++p) pacc[p] += B.ap_part[(int64_t)p * B.nblocks + b];
+        for (int p = 0; p < P; ++p) pacc[p] += B.ap_part[(int64_t)p * B.ap_nblocks + b];
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) sigj[p] = run_scal(B, p)[B.L.sigma + j];
@@ -556,6 +689,19 @@ hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
         default: return hipErrorInvalidValue;
     }
 #undef KRY_LPR
+}
+
+hipError_t launch_spmv_stencil_march(int P, const StencilArgs& A, const double* ucur,
+                                     const double* uprev, double* w, const BatchArgs& B, int j,
+                                     hipStream_t s) {
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_spmv_stencil_march<1>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
+        case 2: hipLaunchKernelGGL((k_spmv_stencil_march<2>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
+        case 4: hipLaunchKernelGGL((k_spmv_stencil_march<4>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
+        case 8: hipLaunchKernelGGL((k_spmv_stencil_march<8>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_spmv_stencil(int P, const StencilArgs& A, const double* ucur,

@@ -144,3 +144,37 @@ def test_workspace_from_library_allocation():
     a = gpu_verify(p, workspace="library")["basis"]
     b = gpu_verify(p, workspace="torch")["basis"]
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("block_p", [1, 2, 4, 0])
+def test_marching_stencil_ragged_grid(monkeypatch, block_p):
+    # the marching mat-vec (one thread per (y, z) column) on a grid whose
+    # column count is not a multiple of the block, forced on at a small size
+    monkeypatch.setenv("KRY_STENCIL_MARCH", "1")
+    grid = (13, 17, 19)
+    n = int(np.prod(grid))
+    rng = np.random.default_rng(31)
+    gens = [W.Generator(W.box_segments(grid, ((2 + g, 6 + g), (3, 9 + g), (1 + g, 12)), 1.0),
+                        zc=0.5 * g, radius=0.2) for g in range(5)]
+    C = [W.box_segments(grid, ((6, 7), (8, 9), (9, 10)), 1.0),
+         W.box_segments(grid, ((0, 13), (0, 17), (0, 19)), 1.0 / n),
+         W.box_segments(grid, ((10, 13), (0, 4), (15, 19)), 2.0)]
+    b = np.zeros(n)
+    b[rng.choice(n, 40, replace=False)] = rng.uniform(0.5, 1.5, 40)
+    p = W.Problem("march", n, "stencil7", True, gens, C, np.array([[math.inf, math.inf]] * 3),
+                  k=22, dt=0.05, steps=90, b=b, grid=grid, coef=(-0.9, 0.1, 0.12, 0.14))
+    got, ref = _compare(p, block_p=block_p)
+    monkeypatch.setenv("KRY_STENCIL_MARCH", "0")
+    rows = gpu_verify(p, block_p=block_p)
+    assert_basis_parity(got["basis"], rows["basis"])
+
+
+def test_marching_stencil_under_arnoldi(monkeypatch):
+    monkeypatch.setenv("KRY_STENCIL_MARCH", "1")
+    p = W.small_heat3d(m=10, k=15, steps=50)
+    ps = W.Problem("stencil", p.n, "stencil7", True, p.gens, p.C, p.unsafe, k=p.k, dt=p.dt, steps=p.steps,
+                   b=p.b, grid=(10, 10, 10), coef=p.meta["coef"])
+    require_gpu()
+    ref = oracle.verify(ps, method="arnoldi")
+    got = gpu_verify(ps, method=2)
+    assert_basis_parity(got["basis"], ref["basis"])
