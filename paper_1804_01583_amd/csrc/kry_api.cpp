@@ -153,17 +153,21 @@ struct Layout {
     int32_t nvp;
     int32_t nvec;
     int32_t march;        // column blocks of the marching stencil kernel (0: row kernel)
-    size_t hpart, hcoef;
+    int32_t esize;        // bytes per stored vector element: 8 (FP64) or 4 (FP32 basis)
+    bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
+    size_t hpart, hcoef, vals32;
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
-                   size_t meta_bytes, int32_t method, int32_t march) {
+                   size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32) {
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
     Y.nblocks = nblocks_for(n, Y.rpb);
     Y.march = march;
+    Y.esize = precision == KRY_FP32_BASIS ? 4 : 8;
+    Y.stored = method == KRY_ARNOLDI || precision == KRY_FP32_BASIS;
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
-    if (method == KRY_ARNOLDI) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
+    if (Y.stored) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
     {
         int p = 1;
         while (p * 2 <= Y.pmax) p *= 2;
@@ -181,11 +185,13 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     L.stride = (int64_t)align_up((size_t)(L.hess + (k + 1) * k), 8);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
-    // Lanczos keeps three vectors per run (Algorithm 4); Arnoldi the whole basis
-    Y.nvec = method == KRY_ARNOLDI ? k + 1 : 3;
-    Y.vec = take((size_t)Y.nvec * n * Y.pmax * sizeof(double));
-    Y.hpart = method == KRY_ARNOLDI ? take((size_t)kMaxK * kMaxP * Y.nblocks * sizeof(double)) : 0;
-    Y.hcoef = method == KRY_ARNOLDI ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
+    // Lanczos keeps three vectors per run (Algorithm 4); Arnoldi, and every
+    // method in FP32-basis mode (full reorthogonalisation), the whole basis
+    Y.nvec = Y.stored ? k + 1 : 3;
+    Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
+    Y.hpart = Y.stored ? take((size_t)kMaxK * kMaxP * Y.nblocks * sizeof(double)) : 0;
+    Y.hcoef = Y.stored ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
+    Y.vals32 = nnz32 > 0 ? take((size_t)nnz32 * sizeof(float)) : 0;
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
     Y.ap_part = take((size_t)std::max(Y.nblocks, Y.march) * kMaxP * sizeof(double));
@@ -303,7 +309,11 @@ struct kry_plan {
     bool projected = false;
     std::vector<double> verdict_host;
 
-    double* vec(int i) { return reinterpret_cast<double*>(ws + Y.vec) + (size_t)i * sys.n * Y.pmax; }
+    bool f32 = false;
+    bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
+
+    void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
+    float* vals32() { return reinterpret_cast<float*>(ws + Y.vals32); }
     double* hpart() { return reinterpret_cast<double*>(ws + Y.hpart); }
     double* hcoef() { return reinterpret_cast<double*>(ws + Y.hcoef); }
     double* np_part() { return reinterpret_cast<double*>(ws + Y.np_part); }
@@ -374,12 +384,13 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
     if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kMaxK || steps < 0 || nseg_total < 0)
         return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56, steps >= 0, nseg_total >= 0 required");
-    if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
+    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
     const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
     const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
+    const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
-                                 march_blocks_for(*sys));
+                                 march_blocks_for(*sys), precision, nnz32);
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -398,7 +409,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (k < 1 || k > kMaxK) return fail(KRY_EINVAL, "k must be in [1, 56]");
     if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
-    if (precision != KRY_FP64) return fail(KRY_ENOTSUP, "only KRY_FP64 is supported in this build");
+    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
     if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
         return fail(KRY_ENOTSUP, "method must be KRY_AUTO, KRY_LANCZOS or KRY_ARNOLDI in this build");
@@ -450,8 +461,12 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
     const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
-    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys));
+    const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
+    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys), precision,
+                          nnz32);
     plan->method = method;
+    plan->f32 = precision == KRY_FP32_BASIS;
+    plan->hess_mode = plan->Y.stored;
     const Layout& Y = plan->Y;
 
     if (workspace) {
@@ -543,6 +558,11 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
         });
         if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e)));
     }
+    // FP32-basis mode reads an FP32 copy of the CSR values
+    if (Y.vals32) {
+        hipError_t e = launch_to_f32(sys->vals, plan->vals32(), sys->nnz, plan->stream);
+        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("to_f32: ") + hipGetErrorString(e)));
+    }
     const double avg = sys->kind == KRY_CSR ? (double)sys->nnz / (double)n : 7.0;
     int lpr = env_int("KRY_LPR", 0);
     if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8) lpr = avg > 24 ? 8 : (avg > 12 ? 4 : 1);
@@ -557,7 +577,9 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
-    const double tau_scale = 1024.0 * 2.220446049250313e-16;
+    // breakdown when beta_j <= 1024 eps ||A||_inf, eps of the precision the
+    // vectors are stored in (FP32 rounding noise must not pass for a new direction)
+    const double tau_scale = 1024.0 * (plan->f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
     int32_t r0 = 0;
     while (r0 < plan->nruns) {
         int P = Y.pmax;
@@ -585,43 +607,50 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             else if (plan->sys.b) src.dense[p] = plan->sys.b;
             else src.set[p] = plan->bset;
         }
+        const bool f32 = plan->f32;
         hipError_t e = timed("start", s, [&] {
-            return launch_start(P, plan->o, src, plan->T, plan->oset0, plan->vec(0), B, s);
+            return launch_start(P, plan->o, f32, src, plan->T, plan->oset0, plan->vec(0), B, s);
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
-        const bool arnoldi = plan->method == KRY_ARNOLDI;
+        const bool lanczos = plan->method == KRY_LANCZOS;
         for (int j = 1; j <= plan->k; ++j) {
-            // Lanczos rotates three vectors; Arnoldi keeps u_1..u_{k+1}
-            double* ucur = arnoldi ? plan->vec(j - 1) : plan->vec((j - 1) % 3);
-            double* uprev = arnoldi ? nullptr : plan->vec((j + 1) % 3);   // (j - 2) mod 3
-            double* w = arnoldi ? plan->vec(j) : plan->vec(j % 3);
+            // FP64 Lanczos rotates three vectors (Algorithm 4); otherwise u_1..u_{k+1} are kept
+            void* ucur = Y.stored ? plan->vec(j - 1) : plan->vec((j - 1) % 3);
+            void* uprev = !lanczos ? nullptr : (Y.stored ? (j >= 2 ? plan->vec(j - 2) : nullptr)
+                                                         : plan->vec((j + 1) % 3));   // (j - 2) mod 3
+            void* w = Y.stored ? plan->vec(j) : plan->vec(j % 3);
             if (plan->sys.kind == KRY_CSR) {
-                CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals};
-                e = timed("spmv_csr", s, [&] { return launch_spmv_csr(P, plan->lpr, A, ucur, uprev, w, B, j, s); });
+                CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
+                e = timed("spmv_csr", s, [&] {
+                    return launch_spmv_csr(P, plan->lpr, f32, A, ucur, uprev, w, B, j, s);
+                });
             } else {
                 StencilArgs A{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx,
                               plan->sys.cy, plan->sys.cz};
-                if (Y.march > 0)
-                    e = timed("spmv_stencil", s, [&] {
-                        return launch_spmv_stencil_march(P, A, ucur, uprev, w, B, j, s);
-                    });
-                else
-                    e = timed("spmv_stencil", s, [&] { return launch_spmv_stencil(P, A, ucur, uprev, w, B, j, s); });
+                e = timed("spmv_stencil", s, [&] {
+                    return launch_spmv_stencil(P, Y.march > 0, f32, A, ucur, uprev, w, B, j, s);
+                });
             }
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("spmv: ") + hipGetErrorString(e));
-            if (!arnoldi) {
-                e = timed("sweep", s, [&] { return launch_sweep(P, plan->o, plan->T, plan->oset0, ucur, w, B, j, s); });
+            if (lanczos) {
+                e = timed("sweep", s, [&] {
+                    return launch_sweep(P, plan->o, f32, plan->T, plan->oset0, ucur, w, B, j, s);
+                });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
-                continue;
+                if (!Y.stored) continue;
             }
-            // CGS2 against u_1..u_j (Algorithm 1's projection loop, classical form, twice)
-            ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef()};
-            for (int pass = 1; pass <= 2; ++pass) {
+            // Arnoldi: CGS2 against u_1..u_j (Algorithm 1's projection loop, classical
+            // form, twice).  Lanczos with a stored basis: one classical pass over the
+            // three-term result removes what rounding left along u_1..u_j.
+            ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef(), f32 ? 1 : 0, lanczos ? 1 : 0};
+            const int passes = lanczos ? 1 : 2;
+            for (int pass = 1; pass <= passes; ++pass) {
                 e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ar, B, j, s); });
                 if (e == hipSuccess) e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ar, B, j, pass, s); });
                 if (e == hipSuccess)
                     e = timed("arn_update", s, [&] {
-                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j, pass == 2 ? 1 : 0, s);
+                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j, pass == passes ? 1 : 0,
+                                                 s);
                     });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
             }
@@ -635,7 +664,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     E.L = Y.L;
     E.role = plan->role_dev;
     E.dt = plan->dt;
-    E.hess_mode = plan->method == KRY_ARNOLDI ? 1 : 0;
+    E.hess_mode = plan->hess_mode ? 1 : 0;
     E.B = Y.B;
     E.nanch = Y.nanch;
     pade13(E.pade);
@@ -734,7 +763,7 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
         const int sh = bordered ? 1 : 0;
         if (bordered && dim > 1) H[1 * dim + 0] = sc[L.beta + 0];
         for (int i = 0; i < tri; ++i) {
-            if (plan->method == KRY_ARNOLDI) {
+            if (plan->hess_mode) {
                 for (int c = i; c < tri; ++c) H[(i + sh) * dim + (c + sh)] = sc[L.hess + i * k + c];
                 if (i + 1 < tri) H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
                 continue;

@@ -10,6 +10,15 @@
 //   k_arn_update : w -= sum_i h_i v_i; on the second pass also the partials of
 //                  |w|^2 and C w that the next mat-vec turns into beta_j, sigma_{j+1}
 // The mat-vec itself is k_spmv_csr / k_spmv_stencil without the three-term part.
+//
+// The same kernels give Lanczos in FP32-basis mode its one full
+// reorthogonalisation pass: after the three-term step (k_spmv + k_sweep) has
+// removed beta_{j-1} v_{j-1} and alpha_j v_j, a single classical pass removes
+// the rounding-level components left along u_1..u_j, and H keeps the
+// tridiagonal entries plus these corrections.  (A single pass over the vector
+// before alpha_j v_j is removed is not enough: its error along old vectors
+// grows by about |alpha / beta| per step.)  Vectors are E = double or
+// E = float; sums are FP64.
 #include "kry_device.h"
 
 #include <cmath>
@@ -20,7 +29,7 @@ namespace {
 
 using namespace dev;
 
-template <int P>
+template <typename E, int P>
 __global__ __launch_bounds__(kBlock) void k_arn_dots(ArnArgs A, BatchArgs B, int j) {
     constexpr int NV = kArnChunk * P;
     __shared__ double s_lds[(kBlock / 64) * NV];
@@ -32,16 +41,18 @@ __global__ __launch_bounds__(kBlock) void k_arn_dots(ArnArgs A, BatchArgs B, int
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const E* V = static_cast<const E*>(A.V);
+    const E* w = static_cast<const E*>(A.w);
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
         double wv[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) wv[p] = A.w[r * P + p];
+        load_row<E, P>(w, r, wv);
 #pragma unroll
         for (int ii = 0; ii < kArnChunk; ++ii) {
             if (ii < ni) {
-                const double* u = A.V + (int64_t)(i0 + ii) * A.vstride;
+                double uv[P];
+                load_row<E, P>(V + (int64_t)(i0 + ii) * A.vstride, r, uv);
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[ii * P + p] = fma(u[r * P + p], wv[p], acc[ii * P + p]);
+                for (int p = 0; p < P; ++p) acc[ii * P + p] = fma(uv[p], wv[p], acc[ii * P + p]);
             }
         }
     }
@@ -71,14 +82,19 @@ __global__ __launch_bounds__(kBlock) void k_arn_reduce(ArnArgs A, BatchArgs B, i
         const double sig = sc[B.L.sigma + i + 1];
         const double h = t * sig;
         double* hij = sc + B.L.hess + i * B.L.k + (j - 1);
-        if (pass == 1) *hij = h;
+        // Lanczos: the three-term step already removed beta_{j-1} v_{j-1} and
+        // alpha_j v_j; H keeps them beside this pass's corrections
+        double border = 0.0;
+        if (A.lanczos && i == j - 2) border = sc[B.L.beta + j - 1];
+        if (A.lanczos && i == j - 1) border = sc[B.L.alpha + j];
+        if (pass == 1) *hij = h + border;
         else *hij += h;
         if (!isfinite(h)) sc[B.L.misc + MISC_NONFINITE] = 1.0;
         A.hcoef[i * kMaxP + p] = h * sig;
     }
 }
 
-template <int P, int O>
+template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_arn_update(SegTable T, int32_t oset0, ArnArgs A, BatchArgs B, int j,
                                                        int last) {
     constexpr int NV = P * (1 + O);
@@ -100,20 +116,23 @@ __global__ __launch_bounds__(kBlock) void k_arn_update(SegTable T, int32_t oset0
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const E* V = static_cast<const E*>(A.V);
+    E* w = static_cast<E*>(A.w);
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
         double val[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) val[p] = A.w[r * P + p];
+        load_row<E, P>(w, r, val);
         for (int i = 0; i < j; ++i) {
-            const double* u = A.V + (int64_t)i * A.vstride;
+            double uv[P];
+            load_row<E, P>(V + (int64_t)i * A.vstride, r, uv);
 #pragma unroll
-            for (int p = 0; p < P; ++p) val[p] = fma(-s_c[i * P + p], u[r * P + p], val[p]);
+            for (int p = 0; p < P; ++p) val[p] = fma(-s_c[i * P + p], uv[p], val[p]);
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            A.w[r * P + p] = val[p];
+            val[p] = (double)(E)val[p];
             acc[p] = fma(val[p], val[p], acc[p]);
         }
+        store_row<E, P>(w, r, val);
         if (last) {
 #pragma unroll
             for (int q = 0; q < O; ++q) {
@@ -128,23 +147,51 @@ __global__ __launch_bounds__(kBlock) void k_arn_update(SegTable T, int32_t oset0
     if (last) store_partials<NV>(acc, stage_part(B, j), B.nblocks, s_lds, B.xcd_map);
 }
 
-template <int P, int O>
+template <typename E, int P, int O>
 hipError_t launch_update_t(const SegTable& T, int32_t oset0, const ArnArgs& A, const BatchArgs& B, int j,
                            int last, hipStream_t s) {
-    hipLaunchKernelGGL((k_arn_update<P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0, A, B, j, last);
+    hipLaunchKernelGGL((k_arn_update<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0, A, B, j, last);
     return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_dots_e(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s) {
+    const dim3 grid(B.nblocks, (j + kArnChunk - 1) / kArnChunk);
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_arn_dots<E, 1>), grid, dim3(kBlock), 0, s, A, B, j); break;
+        case 2: hipLaunchKernelGGL((k_arn_dots<E, 2>), grid, dim3(kBlock), 0, s, A, B, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_update_e(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
+                           const BatchArgs& B, int j, int last, hipStream_t s) {
+#define KRY_ARN_O(PP)                                                                \
+    switch (O) {                                                                     \
+        case 1: return launch_update_t<E, PP, 1>(T, oset0, A, B, j, last, s);        \
+        case 2: return launch_update_t<E, PP, 2>(T, oset0, A, B, j, last, s);        \
+        case 3: return launch_update_t<E, PP, 3>(T, oset0, A, B, j, last, s);        \
+        case 4: return launch_update_t<E, PP, 4>(T, oset0, A, B, j, last, s);        \
+        case 5: return launch_update_t<E, PP, 5>(T, oset0, A, B, j, last, s);        \
+        case 6: return launch_update_t<E, PP, 6>(T, oset0, A, B, j, last, s);        \
+        case 7: return launch_update_t<E, PP, 7>(T, oset0, A, B, j, last, s);        \
+        case 8: return launch_update_t<E, PP, 8>(T, oset0, A, B, j, last, s);        \
+        default: return hipErrorInvalidValue;                                        \
+    }
+    switch (P) {
+        case 1: KRY_ARN_O(1)
+        case 2: KRY_ARN_O(2)
+        default: return hipErrorInvalidValue;
+    }
+#undef KRY_ARN_O
 }
 
 }  // namespace
 
 hipError_t launch_arn_dots(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s) {
-    const dim3 grid(B.nblocks, (j + kArnChunk - 1) / kArnChunk);
-    switch (P) {
-        case 1: hipLaunchKernelGGL((k_arn_dots<1>), grid, dim3(kBlock), 0, s, A, B, j); break;
-        case 2: hipLaunchKernelGGL((k_arn_dots<2>), grid, dim3(kBlock), 0, s, A, B, j); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return A.f32 ? launch_dots_e<float>(P, A, B, j, s) : launch_dots_e<double>(P, A, B, j, s);
 }
 
 hipError_t launch_arn_reduce(int P, const ArnArgs& A, const BatchArgs& B, int j, int pass, hipStream_t s) {
@@ -158,24 +205,8 @@ hipError_t launch_arn_reduce(int P, const ArnArgs& A, const BatchArgs& B, int j,
 
 hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
                              const BatchArgs& B, int j, int last, hipStream_t s) {
-#define KRY_ARN_O(PP)                                                              \
-    switch (O) {                                                                   \
-        case 1: return launch_update_t<PP, 1>(T, oset0, A, B, j, last, s);         \
-        case 2: return launch_update_t<PP, 2>(T, oset0, A, B, j, last, s);         \
-        case 3: return launch_update_t<PP, 3>(T, oset0, A, B, j, last, s);         \
-        case 4: return launch_update_t<PP, 4>(T, oset0, A, B, j, last, s);         \
-        case 5: return launch_update_t<PP, 5>(T, oset0, A, B, j, last, s);         \
-        case 6: return launch_update_t<PP, 6>(T, oset0, A, B, j, last, s);         \
-        case 7: return launch_update_t<PP, 7>(T, oset0, A, B, j, last, s);         \
-        case 8: return launch_update_t<PP, 8>(T, oset0, A, B, j, last, s);         \
-        default: return hipErrorInvalidValue;                                      \
-    }
-    switch (P) {
-        case 1: KRY_ARN_O(1)
-        case 2: KRY_ARN_O(2)
-        default: return hipErrorInvalidValue;
-    }
-#undef KRY_ARN_O
+    return A.f32 ? launch_update_e<float>(P, O, T, oset0, A, B, j, last, s)
+                 : launch_update_e<double>(P, O, T, oset0, A, B, j, last, s);
 }
 
 }  // namespace kry

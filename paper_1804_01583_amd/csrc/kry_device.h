@@ -75,6 +75,62 @@ __device__ __forceinline__ void sum_partials(const double* part, int nb, int vbe
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Krylov vectors are stored as E = double (FP64 mode) or E = float (FP32
+// basis mode) with the P runs of a batch interleaved ([n][P]); all arithmetic
+// is FP64.  load_row / store_row move the P entries of one row with the
+// widest aligned vector access (rows are P * sizeof(E) bytes apart and every
+// vector starts 256-byte aligned).
+template <typename E, int N>
+struct VecOf;
+template <> struct VecOf<double, 1> { using type = double; };
+template <> struct VecOf<double, 2> { using type = double2; };
+template <> struct VecOf<float, 1> { using type = float; };
+template <> struct VecOf<float, 2> { using type = float2; };
+template <> struct VecOf<float, 4> { using type = float4; };
+
+template <typename E, int P>
+constexpr int row_chunk() {
+    return sizeof(E) == 8 ? (P >= 2 ? 2 : 1) : (P >= 4 ? 4 : P);
+}
+
+template <typename E, int P>
+__device__ __forceinline__ void load_row(const E* __restrict__ base, int64_t row, double (&v)[P]) {
+    constexpr int W = row_chunk<E, P>();
+    using Vec = typename VecOf<E, W>::type;
+    const Vec* q = reinterpret_cast<const Vec*>(base + row * P);
+#pragma unroll
+    for (int h = 0; h < P / W; ++h) {
+        const Vec t = q[h];
+        if constexpr (W == 1) {
+            v[h] = (double)t;
+        } else {
+            const E* e = reinterpret_cast<const E*>(&t);
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[h * W + i] = (double)e[i];
+        }
+    }
+}
+
+template <typename E, int P>
+__device__ __forceinline__ void store_row(E* __restrict__ base, int64_t row, const double (&v)[P]) {
+    constexpr int W = row_chunk<E, P>();
+    using Vec = typename VecOf<E, W>::type;
+    Vec* q = reinterpret_cast<Vec*>(base + row * P);
+#pragma unroll
+    for (int h = 0; h < P / W; ++h) {
+        if constexpr (W == 1) {
+            q[h] = (E)v[h];
+        } else {
+            Vec t;
+            E* e = reinterpret_cast<E*>(&t);
+#pragma unroll
+            for (int i = 0; i < W; ++i) e[i] = (E)v[h * W + i];
+            q[h] = t;
+        }
+    }
+}
+
 __device__ __forceinline__ double* run_scal(const BatchArgs& B, int p) {
     return B.scal + (int64_t)(B.run0 + p) * B.L.stride;
 }

@@ -70,6 +70,7 @@ struct CsrArgs {
     const int64_t* rowptr;
     const int32_t* colidx;
     const double* vals;
+    const float* vals32;     // FP32 copy of vals, read by the FP32-basis kernels
 };
 
 struct StencilArgs {
@@ -120,15 +121,18 @@ struct CheckArgs {
     double* verdict;         // [first_step, row, y, lo, hi, status, z[nruns]]
 };
 
-// Classical Gram-Schmidt with reorthogonalisation (CGS2) for Arnoldi.  The
+// Classical Gram-Schmidt against the stored basis: CGS2 for Arnoldi, and the
+// one full reorthogonalisation pass of Lanczos in FP32-basis mode.  The
 // basis is stored unnormalised, column-major per run batch: u_i at
-// V + (i - 1) * n * P ([n][P] interleaved), v_i = sigma_i u_i.
+// V + (i - 1) * vstride ([n][P] interleaved, elements of type E), v_i = sigma_i u_i.
 struct ArnArgs {
-    const double* V;         // u_1 .. u_j (j = iteration), each [n][P]
+    const void* V;           // u_1 .. u_j (j = iteration), each [n][P]
     int64_t vstride;         // elements from u_i to u_{i+1} (n * the plan's largest batch)
-    double* w;               // vector being orthogonalised ([n][P]), u_{j+1} once swept
+    void* w;                 // vector being orthogonalised ([n][P]), u_{j+1} once swept
     double* hpart;           // [kMaxK][kMaxP][nblocks] partials of u_i . w
     double* hcoef;           // [kMaxK][kMaxP] coefficients of the current pass (h_i * sigma_i)
+    int32_t f32;             // 1: E = float, else double
+    int32_t lanczos;         // 1: w is a Lanczos three-term result; H_{j-1,j} and H_{j,j} add beta_{j-1}, alpha_j
 };
 constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
 
@@ -136,19 +140,17 @@ constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
                               int64_t rows_per_block, double* out, hipStream_t s);
 hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s);
-hipError_t launch_start(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        double* u, const BatchArgs& B, hipStream_t s);
-hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
-                           const double* uprev, double* w, const BatchArgs& B, int j,
-                           hipStream_t s);
-hipError_t launch_spmv_stencil(int P, const StencilArgs& A, const double* ucur,
-                               const double* uprev, double* w, const BatchArgs& B, int j,
-                               hipStream_t s);
-hipError_t launch_spmv_stencil_march(int P, const StencilArgs& A, const double* ucur,
-                                     const double* uprev, double* w, const BatchArgs& B, int j,
-                                     hipStream_t s);
-hipError_t launch_sweep(int P, int O, const SegTable& T, int32_t oset0, const double* ucur,
-                        double* w, const BatchArgs& B, int j, hipStream_t s);
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+// f32 selects E = float storage of the Krylov vectors (and vals32 for CSR).
+hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
+                        void* u, const BatchArgs& B, hipStream_t s);
+hipError_t launch_spmv_csr(int P, int lpr, bool f32, const CsrArgs& A, const void* ucur,
+                           const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s);
+// march: the column-marching kernel (grid ap_nblocks), else the row kernel.
+hipError_t launch_spmv_stencil(int P, bool march, bool f32, const StencilArgs& A, const void* ucur,
+                               const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s);
+hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,
+                        void* w, const BatchArgs& B, int j, hipStream_t s);
 hipError_t expm_prepare();
 hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);
 int check_blocks(int64_t steps, int32_t o);

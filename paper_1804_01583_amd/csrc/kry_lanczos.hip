@@ -7,7 +7,9 @@
 // sigma_j = 1 / beta_{j-1}), so no pass is spent on the normalisation of
 // Algorithm 3; the scale is applied where the vector is read.  Batches store
 // their P vectors interleaved ([n][P]) so a gathered column of A reads P
-// contiguous values.
+// contiguous values.  Vectors (and, for CSR, the matrix values) are held as
+// E = double, or E = float in FP32-basis mode; arithmetic and every reduction
+// stay FP64.
 //
 // Reductions: a kernel writes one partial per block and value; every block of
 // the next kernel sums them in the same fixed order (strided per thread, wave
@@ -71,11 +73,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce_max(const double* part, int n
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ in, float* __restrict__ out,
+                                                   int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) out[i] = (float)in[i];
+}
+
 // a2: start vectors u_1 of the runs and the partials of |u_1|^2 and C u_1
 // (Algorithm 4, first two statements; the scaling happens in the next kernel).
-template <int P, int O>
+template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int32_t oset0,
-                                                  double* __restrict__ u, BatchArgs B) {
+                                                  E* __restrict__ u, BatchArgs B) {
     constexpr int NV = P * (1 + O);
     __shared__ double s_lds[(kBlock / 64) * NV];
     __shared__ SegStage<P + O> st;
@@ -101,9 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
             if (src.dense[p] != nullptr) val[p] = src.dense[p][r];
             else if (src.set[p] >= 0) val[p] = cur[p].weight(st, p, T, r);
             else val[p] = 0.0;
-            u[r * P + p] = val[p];
+            val[p] = (double)(E)val[p];          // the norm and projection of the stored vector
             acc[p] = fma(val[p], val[p], acc[p]);
         }
+        store_row<E, P>(u, r, val);
 #pragma unroll
         for (int q = 0; q < O; ++q) {
             const double cw = cur[P + q].weight(st, P + q, T, r);
@@ -156,10 +165,16 @@ __device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, do
 // (sigma_j u_j) . w.  LPR lanes cooperate on one row.  Rows are
 // taken in chunks of RC per lane group; the first chunk's gathers are issued
 // before the stage reduction they do not depend on.
-template <int P, int LPR>
-__global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __restrict__ ucur,
-                                                     const double* __restrict__ uprev,
-                                                     double* __restrict__ w, BatchArgs B, int j) {
+template <typename E, int P, int LPR>
+__device__ __forceinline__ double csr_val(const CsrArgs& A, int64_t e) {
+    if constexpr (sizeof(E) == 4) return (double)A.vals32[e];
+    else return A.vals[e];
+}
+
+template <typename E, int P, int LPR>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restrict__ ucur,
+                                                     const E* __restrict__ uprev,
+                                                     E* __restrict__ w, BatchArgs B, int j) {
     constexpr int G = kBlock / LPR;
     constexpr int RC = 2;
     constexpr int U = P >= 8 ? 2 : (P >= 4 ? 4 : 8);
@@ -201,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
                     const int64_t ee = e0[i] + sub + (int64_t)u * LPR;
                     const bool ok = ee < e1[i];
                     c[i][u] = ok ? A.colidx[ee] : 0;
-                    a[i][u] = ok ? A.vals[ee] : 0.0;
+                    a[i][u] = ok ? csr_val<E, P, LPR>(A, ee) : 0.0;
                 }
             }
 #pragma unroll
@@ -209,11 +224,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool ok = e0[i] + sub + (int64_t)u * LPR < e1[i];
+                    double x[P];
+                    load_row<E, P>(ucur, (int64_t)c[i][u], x);
 #pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const double x = ucur[(int64_t)c[i][u] * P + p];
-                        acc[i][p] = ok ? fma(a[i][u], x, acc[i][p]) : acc[i][p];
-                    }
+                    for (int p = 0; p < P; ++p) acc[i][p] = ok ? fma(a[i][u], x[p], acc[i][p]) : acc[i][p];
                 }
             }
         }
@@ -222,9 +236,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
         for (int i = 0; i < RC; ++i) {
             for (int64_t e = e0[i] + sub + (int64_t)U * LPR; e < e1[i]; e += LPR) {
                 const int64_t c = A.colidx[e];
-                const double a = A.vals[e];
+                const double a = csr_val<E, P, LPR>(A, e);
+                double x[P];
+                load_row<E, P>(ucur, c, x);
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[i][p] = fma(a, ucur[c * P + p], acc[i][p]);
+                for (int p = 0; p < P; ++p) acc[i][p] = fma(a, x[p], acc[i][p]);
             }
         }
         if (LPR > 1) {
@@ -243,13 +259,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
             for (int i = 0; i < RC; ++i) {
                 if (rr[i] < r1) {
                     const int64_t r = rr[i];
+                    double own[P], pv[P], y[P];
+                    load_row<E, P>(ucur, r, own);
+                    if (j > 1 && uprev != nullptr) load_row<E, P>(uprev, r, pv);
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        double y = sig[p] * acc[i][p];
-                        if (j > 1 && uprev != nullptr) y = fma(-cprev[p], uprev[r * P + p], y);
-                        w[r * P + p] = y;
-                        dot[p] = fma(sig[p] * ucur[r * P + p], y, dot[p]);
+                        y[p] = sig[p] * acc[i][p];
+                        if (j > 1 && uprev != nullptr) y[p] = fma(-cprev[p], pv[p], y[p]);
+                        y[p] = (double)(E)y[p];
+                        dot[p] = fma(sig[p] * own[p], y[p], dot[p]);
                     }
+                    store_row<E, P>(w, r, y);
                 }
             }
         }
@@ -262,10 +282,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const double* __
 // neighbours summed in ascending index order like a CSR row.  Each thread
 // decodes its first row's grid coordinates once and advances them as it
 // strides by kBlock rows, so no division runs per row.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const double* __restrict__ ucur,
-                                                         const double* __restrict__ uprev,
-                                                         double* __restrict__ w, BatchArgs B, int j) {
+template <typename E, int P>
+__global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const E* __restrict__ ucur,
+                                                         const E* __restrict__ uprev,
+                                                         E* __restrict__ w, BatchArgs B, int j) {
     __shared__ double s_lds[(kBlock / 64) * P];
     __shared__ double s_nrm[P];
     const int lb = logical_block(B.nblocks, B.xcd_map);
@@ -288,22 +308,31 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
         const bool xl = ix > 0, xh = ix < S.nx - 1;
         const bool yl = iy > 0, yh = iy < S.ny - 1;
         const bool zl = iz > 0, zh = iz < S.nz - 1;
+        double vxl[P], vyl[P], vzl[P], own[P], vzh[P], vyh[P], vxh[P], pv[P], y[P];
+        load_row<E, P>(ucur, xl ? r - sx : r, vxl);
+        load_row<E, P>(ucur, yl ? r - sy : r, vyl);
+        load_row<E, P>(ucur, zl ? r - 1 : r, vzl);
+        load_row<E, P>(ucur, r, own);
+        load_row<E, P>(ucur, zh ? r + 1 : r, vzh);
+        load_row<E, P>(ucur, yh ? r + sy : r, vyh);
+        load_row<E, P>(ucur, xh ? r + sx : r, vxh);
+        load_row<E, P>(prev ? uprev : ucur, r, pv);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             double acc = 0.0;
-            if (xl) acc = fma(S.cx, ucur[(r - sx) * P + p], acc);
-            if (yl) acc = fma(S.cy, ucur[(r - sy) * P + p], acc);
-            if (zl) acc = fma(S.cz, ucur[(r - 1) * P + p], acc);
-            const double own = ucur[r * P + p];
-            acc = fma(S.c0, own, acc);
-            if (zh) acc = fma(S.cz, ucur[(r + 1) * P + p], acc);
-            if (yh) acc = fma(S.cy, ucur[(r + sy) * P + p], acc);
-            if (xh) acc = fma(S.cx, ucur[(r + sx) * P + p], acc);
-            double y = sig[p] * acc;
-            if (prev) y = fma(-cprev[p], uprev[r * P + p], y);
-            w[r * P + p] = y;
-            dot[p] = fma(sig[p] * own, y, dot[p]);
+            if (xl) acc = fma(S.cx, vxl[p], acc);
+            if (yl) acc = fma(S.cy, vyl[p], acc);
+            if (zl) acc = fma(S.cz, vzl[p], acc);
+            acc = fma(S.c0, own[p], acc);
+            if (zh) acc = fma(S.cz, vzh[p], acc);
+            if (yh) acc = fma(S.cy, vyh[p], acc);
+            if (xh) acc = fma(S.cx, vxh[p], acc);
+            y[p] = sig[p] * acc;
+            if (prev) y[p] = fma(-cprev[p], pv[p], y[p]);
+            y[p] = (double)(E)y[p];
+            dot[p] = fma(sig[p] * own[p], y[p], dot[p]);
         }
+        store_row<E, P>(w, r, y);
         iz += kBlock;
         while (iz >= S.nz) {
             iz -= S.nz;
@@ -311,33 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const do
         }
     }
     store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
-}
-
-// The P interleaved entries of one row, as 16-byte loads where P is even.
-template <int P>
-__device__ __forceinline__ void load_row(const double* __restrict__ base, int64_t row, double (&v)[P]) {
-    if constexpr (P == 1) {
-        v[0] = base[row];
-    } else {
-        const double2* q = reinterpret_cast<const double2*>(base + row * P);
-#pragma unroll
-        for (int h = 0; h < P / 2; ++h) {
-            const double2 t = q[h];
-            v[2 * h] = t.x;
-            v[2 * h + 1] = t.y;
-        }
-    }
-}
-
-template <int P>
-__device__ __forceinline__ void store_row(double* __restrict__ base, int64_t row, const double (&v)[P]) {
-    if constexpr (P == 1) {
-        base[row] = v[0];
-    } else {
-        double2* q = reinterpret_cast<double2*>(base + row * P);
-#pragma unroll
-        for (int h = 0; h < P / 2; ++h) q[h] = make_double2(v[2 * h], v[2 * h + 1]);
-    }
 }
 
 // One x step of the marching stencil: row r = ix * sx + col with u at x-1,
@@ -350,21 +352,21 @@ struct MarchCol {
     bool yl, yh, zl, zh, live, prev;
 };
 
-template <int P>
+template <typename E, int P>
 __device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol& M, int64_t ix,
-                                           const double* __restrict__ ucur, const double* __restrict__ up,
-                                           double* __restrict__ w, const double (&sig)[P],
+                                           const E* __restrict__ ucur, const E* __restrict__ up,
+                                           E* __restrict__ w, const double (&sig)[P],
                                            const double (&cprev)[P], const double (&xm)[P],
                                            const double (&x0)[P], const double (&xp)[P], double (&nx2)[P],
                                            double (&dot)[P]) {
     const int64_t r = ix * M.sx + M.col;
     double vyl[P], vzl[P], vzh[P], vyh[P], vpr[P];
-    load_row<P>(ucur, r + M.dyl, vyl);
-    load_row<P>(ucur, r + M.dzl, vzl);
-    load_row<P>(ucur, r + M.dzh, vzh);
-    load_row<P>(ucur, r + M.dyh, vyh);
-    load_row<P>(up, r, vpr);
-    load_row<P>(ucur, ix + 2 < S.nx ? r + 2 * M.sx : r, nx2);
+    load_row<E, P>(ucur, r + M.dyl, vyl);
+    load_row<E, P>(ucur, r + M.dzl, vzl);
+    load_row<E, P>(ucur, r + M.dzh, vzh);
+    load_row<E, P>(ucur, r + M.dyh, vyh);
+    load_row<E, P>(up, r, vpr);
+    load_row<E, P>(ucur, ix + 2 < S.nx ? r + 2 * M.sx : r, nx2);
     double y[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -378,9 +380,10 @@ __device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol&
         if (ix < S.nx - 1) acc = fma(S.cx, xp[p], acc);
         y[p] = sig[p] * acc;
         if (M.prev) y[p] = fma(-cprev[p], vpr[p], y[p]);
+        y[p] = (double)(E)y[p];
         dot[p] = fma(sig[p] * x0[p], y[p], dot[p]);
     }
-    if (M.live) store_row<P>(w, r, y);
+    if (M.live) store_row<E, P>(w, r, y);
 }
 
 // Matrix-free 7-point stencil, marching form: one thread per (y, z) grid
@@ -393,10 +396,10 @@ __device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol&
 // registers rotate by unrolling, so the x+2 load stays in flight across the
 // step.  Same summation order per row as k_spmv_stencil.  The dot partials
 // are indexed by column block (ap_nblocks of them).
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, const double* __restrict__ ucur,
-                                                               const double* __restrict__ uprev,
-                                                               double* __restrict__ w, BatchArgs B, int j) {
+template <typename E, int P>
+__global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, const E* __restrict__ ucur,
+                                                               const E* __restrict__ uprev,
+                                                               E* __restrict__ w, BatchArgs B, int j) {
     __shared__ double s_lds[(kBlock / 64) * P];
     __shared__ double s_nrm[P];
     const int cb = logical_block(B.ap_nblocks, B.xcd_map);
@@ -411,14 +414,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, co
     const int64_t iy = M.col / S.nz;
     const int64_t iz = M.col % S.nz;
     double a[P], b[P], c[P], d[P];
-    load_row<P>(ucur, M.col, b);
-    load_row<P>(ucur, S.nx > 1 ? M.col + M.sx : M.col, c);
+    load_row<E, P>(ucur, M.col, b);
+    load_row<E, P>(ucur, S.nx > 1 ? M.col + M.sx : M.col, c);
 #pragma unroll
     for (int p = 0; p < P; ++p) a[p] = 0.0;
     double sig[P], cprev[P];
     finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
     M.prev = j > 1 && uprev != nullptr;
-    const double* __restrict__ up = M.prev ? uprev : ucur;
+    const E* __restrict__ up = M.prev ? uprev : ucur;
     M.yl = iy > 0;
     M.yh = iy < S.ny - 1;
     M.zl = iz > 0;
@@ -431,13 +434,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, co
 #pragma unroll
     for (int p = 0; p < P; ++p) dot[p] = 0.0;
     for (int64_t ix = 0; ix < S.nx; ix += 4) {
-        march_step<P>(S, M, ix, ucur, up, w, sig, cprev, a, b, c, d, dot);
+        march_step<E, P>(S, M, ix, ucur, up, w, sig, cprev, a, b, c, d, dot);
         if (ix + 1 >= S.nx) break;
-        march_step<P>(S, M, ix + 1, ucur, up, w, sig, cprev, b, c, d, a, dot);
+        march_step<E, P>(S, M, ix + 1, ucur, up, w, sig, cprev, b, c, d, a, dot);
         if (ix + 2 >= S.nx) break;
-        march_step<P>(S, M, ix + 2, ucur, up, w, sig, cprev, c, d, a, b, dot);
+        march_step<E, P>(S, M, ix + 2, ucur, up, w, sig, cprev, c, d, a, b, dot);
         if (ix + 3 >= S.nx) break;
-        march_step<P>(S, M, ix + 3, ucur, up, w, sig, cprev, d, a, b, c, dot);
+        march_step<E, P>(S, M, ix + 3, ucur, up, w, sig, cprev, d, a, b, c, dot);
     }
     if (!M.live) {
 #pragma unroll
@@ -449,10 +452,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, co
 // Second half of a4 + the partials of a5 and a6: alpha_j = sum of the dot
 // partials; w -= alpha_j sigma_j u_j; partials of |w|^2 and C w.  The first
 // chunk of rows is loaded before the alpha reduction completes.
-template <int P, int O>
+template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
-                                                  const double* __restrict__ ucur,
-                                                  double* __restrict__ w, BatchArgs B, int j) {
+                                                  const E* __restrict__ ucur,
+                                                  E* __restrict__ w, BatchArgs B, int j) {
     constexpr int NV = P * (1 + O);
     constexpr int RC = 4;
     __shared__ double s_lds[(kBlock / 64) * NV];
@@ -492,11 +495,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
         for (int i = 0; i < RC; ++i) {
             rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
             const bool live = rr[i] < r1;
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-                uv[i][p] = live ? ucur[rr[i] * P + p] : 0.0;
-                wv[i][p] = live ? w[rr[i] * P + p] : 0.0;
-            }
+            const int64_t rl = live ? rr[i] : 0;    // dead rows read row 0 and drop it
+            load_row<E, P>(ucur, rl, uv[i]);
+            load_row<E, P>(w, rl, wv[i]);
         }
         if (ch == 0) {
             const double t = block_sum<P>(pacc, s_lds);
@@ -517,10 +518,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                 double val[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    val[p] = fma(-coef[p], uv[i][p], wv[i][p]);
-                    w[r * P + p] = val[p];
+                    val[p] = (double)(E)fma(-coef[p], uv[i][p], wv[i][p]);
                     acc[p] = fma(val[p], val[p], acc[p]);
                 }
+                store_row<E, P>(w, r, val);
 #pragma unroll
                 for (int q = 0; q < O; ++q) {
                     const double cw = cur[q].weight(st, q, T, r);
@@ -572,56 +573,125 @@ __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o) {
     }
 }
 
-template <int P, int O>
-hipError_t launch_start_t(const StartSrc& src, const SegTable& T, int32_t oset0, double* u,
+template <typename E, int P, int O>
+hipError_t launch_start_t(const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
                           const BatchArgs& B, hipStream_t s) {
-    hipLaunchKernelGGL((k_start<P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0, u, B);
+    hipLaunchKernelGGL((k_start<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
+                       static_cast<E*>(u), B);
     return hipGetLastError();
 }
 
-template <int P, int O>
-hipError_t launch_sweep_t(const SegTable& T, int32_t oset0, const double* ucur, double* w,
+template <typename E, int P, int O>
+hipError_t launch_sweep_t(const SegTable& T, int32_t oset0, const void* ucur, void* w,
                           const BatchArgs& B, int j, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0, ucur, w, B, j);
+    hipLaunchKernelGGL((k_sweep<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0,
+                       static_cast<const E*>(ucur), static_cast<E*>(w), B, j);
     return hipGetLastError();
 }
 
-template <int P, int LPR>
-hipError_t launch_spmv_t(const CsrArgs& A, const double* ucur, const double* uprev, double* w,
+template <typename E, int P, int LPR>
+hipError_t launch_spmv_t(const CsrArgs& A, const void* ucur, const void* uprev, void* w,
                          const BatchArgs& B, int j, hipStream_t s) {
-    hipLaunchKernelGGL((k_spmv_csr<P, LPR>), dim3(B.nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j);
+    hipLaunchKernelGGL((k_spmv_csr<E, P, LPR>), dim3(B.nblocks), dim3(kBlock), 0, s, A,
+                       static_cast<const E*>(ucur), static_cast<const E*>(uprev), static_cast<E*>(w), B, j);
     return hipGetLastError();
 }
 
-// Dispatch over O for a fixed P; P * (1 + O) <= kMaxNV limits P = 4 to
+// Dispatch over O for fixed E and P; P * (1 + O) <= kMaxNV limits P = 4 to
 // O <= 5 and P = 8 to O <= 2.
-#define KRY_DISPATCH_O2(FN, P, O, ...)                \
+#define KRY_DISPATCH_O2(FN, E, P, O, ...)             \
     switch (O) {                                      \
-        case 1: return FN<P, 1>(__VA_ARGS__);         \
-        case 2: return FN<P, 2>(__VA_ARGS__);         \
+        case 1: return FN<E, P, 1>(__VA_ARGS__);      \
+        case 2: return FN<E, P, 2>(__VA_ARGS__);      \
         default: return hipErrorInvalidValue;         \
     }
-#define KRY_DISPATCH_O5(FN, P, O, ...)                \
+#define KRY_DISPATCH_O5(FN, E, P, O, ...)             \
     switch (O) {                                      \
-        case 1: return FN<P, 1>(__VA_ARGS__);         \
-        case 2: return FN<P, 2>(__VA_ARGS__);         \
-        case 3: return FN<P, 3>(__VA_ARGS__);         \
-        case 4: return FN<P, 4>(__VA_ARGS__);         \
-        case 5: return FN<P, 5>(__VA_ARGS__);         \
+        case 1: return FN<E, P, 1>(__VA_ARGS__);      \
+        case 2: return FN<E, P, 2>(__VA_ARGS__);      \
+        case 3: return FN<E, P, 3>(__VA_ARGS__);      \
+        case 4: return FN<E, P, 4>(__VA_ARGS__);      \
+        case 5: return FN<E, P, 5>(__VA_ARGS__);      \
         default: return hipErrorInvalidValue;         \
     }
-#define KRY_DISPATCH_O8(FN, P, O, ...)                \
+#define KRY_DISPATCH_O8(FN, E, P, O, ...)             \
     switch (O) {                                      \
-        case 1: return FN<P, 1>(__VA_ARGS__);         \
-        case 2: return FN<P, 2>(__VA_ARGS__);         \
-        case 3: return FN<P, 3>(__VA_ARGS__);         \
-        case 4: return FN<P, 4>(__VA_ARGS__);         \
-        case 5: return FN<P, 5>(__VA_ARGS__);         \
-        case 6: return FN<P, 6>(__VA_ARGS__);         \
-        case 7: return FN<P, 7>(__VA_ARGS__);         \
-        case 8: return FN<P, 8>(__VA_ARGS__);         \
+        case 1: return FN<E, P, 1>(__VA_ARGS__);      \
+        case 2: return FN<E, P, 2>(__VA_ARGS__);      \
+        case 3: return FN<E, P, 3>(__VA_ARGS__);      \
+        case 4: return FN<E, P, 4>(__VA_ARGS__);      \
+        case 5: return FN<E, P, 5>(__VA_ARGS__);      \
+        case 6: return FN<E, P, 6>(__VA_ARGS__);      \
+        case 7: return FN<E, P, 7>(__VA_ARGS__);      \
+        case 8: return FN<E, P, 8>(__VA_ARGS__);      \
         default: return hipErrorInvalidValue;         \
     }
+#define KRY_DISPATCH_PO(FN, E, P, O, ...)                                  \
+    switch (P) {                                                           \
+        case 1: KRY_DISPATCH_O8(FN, E, 1, O, __VA_ARGS__)                  \
+        case 2: KRY_DISPATCH_O8(FN, E, 2, O, __VA_ARGS__)                  \
+        case 4: KRY_DISPATCH_O5(FN, E, 4, O, __VA_ARGS__)                  \
+        case 8: KRY_DISPATCH_O2(FN, E, 8, O, __VA_ARGS__)                  \
+        default: return hipErrorInvalidValue;                              \
+    }
+
+template <typename E>
+hipError_t launch_start_e(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
+                          const BatchArgs& B, hipStream_t s) {
+    KRY_DISPATCH_PO(launch_start_t, E, P, O, src, T, oset0, u, B, s)
+}
+
+template <typename E>
+hipError_t launch_sweep_e(int P, int O, const SegTable& T, int32_t oset0, const void* ucur, void* w,
+                          const BatchArgs& B, int j, hipStream_t s) {
+    KRY_DISPATCH_PO(launch_sweep_t, E, P, O, T, oset0, ucur, w, B, j, s)
+}
+
+template <typename E>
+hipError_t launch_spmv_csr_e(int P, int lpr, const CsrArgs& A, const void* ucur, const void* uprev, void* w,
+                             const BatchArgs& B, int j, hipStream_t s) {
+#define KRY_LPR(PP)                                                                \
+    switch (lpr) {                                                                 \
+        case 1: return launch_spmv_t<E, PP, 1>(A, ucur, uprev, w, B, j, s);        \
+        case 2: return launch_spmv_t<E, PP, 2>(A, ucur, uprev, w, B, j, s);        \
+        case 4: return launch_spmv_t<E, PP, 4>(A, ucur, uprev, w, B, j, s);        \
+        case 8: return launch_spmv_t<E, PP, 8>(A, ucur, uprev, w, B, j, s);        \
+        default: return hipErrorInvalidValue;                                      \
+    }
+    switch (P) {
+        case 1: KRY_LPR(1)
+        case 2: KRY_LPR(2)
+        case 4: KRY_LPR(4)
+        case 8: KRY_LPR(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef KRY_LPR
+}
+
+template <typename E, int P>
+hipError_t launch_stencil_pe(bool march, const StencilArgs& A, const void* ucur, const void* uprev, void* w,
+                             const BatchArgs& B, int j, hipStream_t s) {
+    const E* uc = static_cast<const E*>(ucur);
+    const E* up = static_cast<const E*>(uprev);
+    E* ww = static_cast<E*>(w);
+    if (march)
+        hipLaunchKernelGGL((k_spmv_stencil_march<E, P>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j);
+    else
+        hipLaunchKernelGGL((k_spmv_stencil<E, P>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j);
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_stencil_e(int P, bool march, const StencilArgs& A, const void* ucur, const void* uprev,
+                            void* w, const BatchArgs& B, int j, hipStream_t s) {
+    switch (P) {
+        case 1: return launch_stencil_pe<E, 1>(march, A, ucur, uprev, w, B, j, s);
+        case 2: return launch_stencil_pe<E, 2>(march, A, ucur, uprev, w, B, j, s);
+        case 4: return launch_stencil_pe<E, 4>(march, A, ucur, uprev, w, B, j, s);
+        case 8: return launch_stencil_pe<E, 8>(march, A, ucur, uprev, w, B, j, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace
 
@@ -634,28 +704,26 @@ hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int
     return hipGetLastError();
 }
 
-hipError_t launch_start(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        double* u, const BatchArgs& B, hipStream_t s) {
-    if (P * (1 + O) > kMaxNV) return hipErrorInvalidValue;
-    switch (P) {
-        case 1: KRY_DISPATCH_O8(launch_start_t, 1, O, src, T, oset0, u, B, s)
-        case 2: KRY_DISPATCH_O8(launch_start_t, 2, O, src, T, oset0, u, B, s)
-        case 4: KRY_DISPATCH_O5(launch_start_t, 4, O, src, T, oset0, u, B, s)
-        case 8: KRY_DISPATCH_O2(launch_start_t, 8, O, src, T, oset0, u, B, s)
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + kBlock - 1) / kBlock;
+    const int grid = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(kBlock), 0, s, in, out, n);
+    return hipGetLastError();
 }
 
-hipError_t launch_sweep(int P, int O, const SegTable& T, int32_t oset0, const double* ucur,
-                        double* w, const BatchArgs& B, int j, hipStream_t s) {
+hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
+                        void* u, const BatchArgs& B, hipStream_t s) {
     if (P * (1 + O) > kMaxNV) return hipErrorInvalidValue;
-    switch (P) {
-        case 1: KRY_DISPATCH_O8(launch_sweep_t, 1, O, T, oset0, ucur, w, B, j, s)
-        case 2: KRY_DISPATCH_O8(launch_sweep_t, 2, O, T, oset0, ucur, w, B, j, s)
-        case 4: KRY_DISPATCH_O5(launch_sweep_t, 4, O, T, oset0, ucur, w, B, j, s)
-        case 8: KRY_DISPATCH_O2(launch_sweep_t, 8, O, T, oset0, ucur, w, B, j, s)
-        default: return hipErrorInvalidValue;
-    }
+    return f32 ? launch_start_e<float>(P, O, src, T, oset0, u, B, s)
+               : launch_start_e<double>(P, O, src, T, oset0, u, B, s);
+}
+
+hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,
+                        void* w, const BatchArgs& B, int j, hipStream_t s) {
+    if (P * (1 + O) > kMaxNV) return hipErrorInvalidValue;
+    return f32 ? launch_sweep_e<float>(P, O, T, oset0, ucur, w, B, j, s)
+               : launch_sweep_e<double>(P, O, T, oset0, ucur, w, B, j, s);
 }
 
 hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s) {
@@ -670,51 +738,16 @@ hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_csr(int P, int lpr, const CsrArgs& A, const double* ucur,
-                           const double* uprev, double* w, const BatchArgs& B, int j,
-                           hipStream_t s) {
-#define KRY_LPR(PP)                                                             \
-    switch (lpr) {                                                              \
-        case 1: return launch_spmv_t<PP, 1>(A, ucur, uprev, w, B, j, s);        \
-        case 2: return launch_spmv_t<PP, 2>(A, ucur, uprev, w, B, j, s);        \
-        case 4: return launch_spmv_t<PP, 4>(A, ucur, uprev, w, B, j, s);        \
-        case 8: return launch_spmv_t<PP, 8>(A, ucur, uprev, w, B, j, s);        \
-        default: return hipErrorInvalidValue;                                   \
-    }
-    switch (P) {
-        case 1: KRY_LPR(1)
-        case 2: KRY_LPR(2)
-        case 4: KRY_LPR(4)
-        case 8: KRY_LPR(8)
-        default: return hipErrorInvalidValue;
-    }
-#undef KRY_LPR
+hipError_t launch_spmv_csr(int P, int lpr, bool f32, const CsrArgs& A, const void* ucur,
+                           const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s) {
+    return f32 ? launch_spmv_csr_e<float>(P, lpr, A, ucur, uprev, w, B, j, s)
+               : launch_spmv_csr_e<double>(P, lpr, A, ucur, uprev, w, B, j, s);
 }
 
-hipError_t launch_spmv_stencil_march(int P, const StencilArgs& A, const double* ucur,
-                                     const double* uprev, double* w, const BatchArgs& B, int j,
-                                     hipStream_t s) {
-    switch (P) {
-        case 1: hipLaunchKernelGGL((k_spmv_stencil_march<1>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 2: hipLaunchKernelGGL((k_spmv_stencil_march<2>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 4: hipLaunchKernelGGL((k_spmv_stencil_march<4>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 8: hipLaunchKernelGGL((k_spmv_stencil_march<8>), dim3(B.ap_nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_spmv_stencil(int P, const StencilArgs& A, const double* ucur,
-                               const double* uprev, double* w, const BatchArgs& B, int j,
-                               hipStream_t s) {
-    switch (P) {
-        case 1: hipLaunchKernelGGL((k_spmv_stencil<1>), dim3(B.nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 2: hipLaunchKernelGGL((k_spmv_stencil<2>), dim3(B.nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 4: hipLaunchKernelGGL((k_spmv_stencil<4>), dim3(B.nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        case 8: hipLaunchKernelGGL((k_spmv_stencil<8>), dim3(B.nblocks), dim3(kBlock), 0, s, A, ucur, uprev, w, B, j); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+hipError_t launch_spmv_stencil(int P, bool march, bool f32, const StencilArgs& A, const void* ucur,
+                               const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s) {
+    return f32 ? launch_stencil_e<float>(P, march, A, ucur, uprev, w, B, j, s)
+               : launch_stencil_e<double>(P, march, A, ucur, uprev, w, B, j, s);
 }
 
 }  // namespace kry

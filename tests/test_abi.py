@@ -68,7 +68,7 @@ def test_footprint_is_host_only_and_scales_with_n():
     assert big - small <= 4 * 2 * 8 * (1_000_000 - 10_000) + (1 << 20)
 
 
-@pytest.mark.parametrize("bad", ["n", "k", "o", "steps", "dt", "seg_order", "seg_range", "nonsym", "fp32"])
+@pytest.mark.parametrize("bad", ["n", "k", "o", "steps", "dt", "seg_order", "seg_range", "nonsym", "precision"])
 def test_plan_rejects_bad_arguments(bad):
     from paper_1804_01583_amd import kry
     import workloads as W
@@ -95,13 +95,13 @@ def test_plan_rejects_bad_arguments(bad):
     elif bad == "nonsym":
         s.symmetric = 0
         method = kry.KRY_LANCZOS
-    elif bad == "fp32":
-        precision = kry.KRY_FP32_BASIS
+    elif bad == "precision":
+        precision = 7
     keep = []
     kg = [kry.KryGen(kry._segs(g.seg, keep), g.zc, g.radius) for g in gens]
     kc = [kry._segs(c, keep) for c in C]
     with pytest.raises(kry.KryError) as ei:
         kry.kry_plan_create(s, kg, None, kc, k, dt, steps, precision, method, 0, 0x100, 1 << 40, None)
-    expected = kry.KRY_ENOTSUP if bad == "fp32" else kry.KRY_EINVAL
+    expected = kry.KRY_EINVAL
     assert ei.value.status == expected
     assert len(kry.lib.kry_last_error()) > 0

@@ -1,0 +1,122 @@
+"""FP32-basis mode (vectors and CSR values stored in FP32, every sum and
+coefficient in FP64, full reorthogonalisation against the stored basis) on
+the GPU against the FP64 oracle.
+
+The paper fixes no precision for this mode, so the bound is stated here.
+Storing a vector in FP32 rounds each entry by a relative 2^-24, and with full
+reorthogonalisation the computed H is V^T A V + E with |E| ~ eps_32 ||A||
+(as for any backward-stable Krylov process): the result is that of a
+perturbed matrix.  For a dissipative A (|e^{At}| <= 1) a perturbation E
+changes e^{At} v by at most t |E| |v| over [0, t], so per (output row, run)
+
+    max_s |y_gpu - y_ref| <= tol * max_s |y_ref|,
+    tol = max(1e-5, 2 eps_32 ||A||_inf T),      T = steps * dt.
+
+(Measured errors sit 10x or more below it.)  Rows that are structurally zero
+in the oracle stay exactly zero: the stored zeros are exact."""
+import math
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection so the first test does not pay for it)
+
+import oracle
+import workloads as W
+from paper_1804_01583_amd import kry
+from tests.gpu_helpers import assert_basis_parity, gpu_verify, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = 2.0 ** -23
+
+
+def fp32_tol(problem):
+    anorm = oracle.krylov.inf_norm(oracle.krylov.system_matrix(problem))
+    return max(1e-5, 2.0 * EPS32 * anorm * problem.steps * problem.dt)
+
+
+def _compare32(problem, oracle_method="auto", **kw):
+    require_gpu()
+    ref = oracle.verify(problem, method=oracle_method)
+    got = gpu_verify(problem, precision=kry.KRY_FP32_BASIS, **kw)
+    assert got["roles"] == ref["roles"]
+    anorm = oracle.krylov.inf_norm(oracle.krylov.system_matrix(problem))
+    for g, r in zip(got["runs"], ref["runs"]):
+        kg = g["k_eff"]
+        if kg != r.k_eff:
+            # FP32 storage ends the run once beta_j <= 1024 eps_32 ||A||: allowed
+            # only where the oracle's own beta_j is that small
+            assert 0 < kg < r.k_eff, (kg, r.k_eff)
+            assert abs(r.H[kg, kg - 1]) <= 1024 * EPS32 * anorm, (kg, r.H[kg, kg - 1])
+        if kg == 0:
+            continue
+        assert abs(g["beta0"] - r.beta0) <= 1e-7 * abs(r.beta0)
+        hs = np.abs(r.H).max()
+        np.testing.assert_allclose(g["H"], r.H[:kg, :kg], rtol=0, atol=1e-5 * hs)
+    tol = fp32_tol(problem)
+    worst = assert_basis_parity(got["basis"], ref["basis"], rtol=tol)
+    gv, ov = got["verdict"], ref["verdict"]
+    assert gv["status"] == 0
+    assert (gv["first_step"], gv["row"]) == (ov["first_step"], ov["row"])
+    if ov["first_step"] >= 0:
+        np.testing.assert_allclose(gv["z"], ov["z"], rtol=1e-4, atol=1e-6)
+    print(f"  FP32-basis worst relative error {worst:.2e} (bound {tol:.1e})", flush=True)
+    return got, ref
+
+
+@pytest.mark.parametrize("m,k", [(12, 20), (9, 30)])
+def test_fp32_heat3d_csr_with_forcing(m, k):
+    p = W.small_heat3d(m=m, k=k, steps=150)
+    _compare32(p)
+
+
+@pytest.mark.parametrize("march", ["0", "1"])
+def test_fp32_stencil(monkeypatch, march):
+    monkeypatch.setenv("KRY_STENCIL_MARCH", march)
+    p = W.small_heat3d(m=11, k=18, steps=60)
+    ps = W.Problem("stencil", p.n, "stencil7", True, p.gens, p.C, p.unsafe, k=p.k, dt=p.dt, steps=p.steps,
+                   b=p.b, grid=(11, 11, 11), coef=p.meta["coef"])
+    _compare32(ps)
+
+
+@pytest.mark.parametrize("block_p", [1, 2])
+def test_fp32_random_symmetric_all_roles(block_p):
+    p = W.random_symmetric(n=700, ngen=4, o=3, k=16, steps=60, seed=21, affine=True, center=True)
+    _compare32(p, block_p=block_p)
+
+
+def test_fp32_nonsymmetric_arnoldi():
+    p = W.conv_diff3d(12, 12, 14, ngen=3, gen_len=40, o=3, k=20, steps=120, dt=1e-3, seed=3)
+    _compare32(p)
+
+
+def test_fp32_batching_is_bitwise_invariant():
+    require_gpu()
+    p = W.random_symmetric(n=1501, ngen=5, o=2, k=14, steps=30, seed=6, affine=True, center=False)
+    dsys = kry.DeviceSystem(p)
+    ref = gpu_verify(p, dsys=dsys, block_p=1, precision=kry.KRY_FP32_BASIS)["basis"]
+    got = gpu_verify(p, dsys=dsys, block_p=2, precision=kry.KRY_FP32_BASIS)["basis"]
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_fp32_breakdown_on_eigenvector():
+    # the FP32-rounded eigenvector leaves a residual far below 1024 eps_32 ||A||
+    p = W.heat1d(steps=50)
+    n = p.n
+    h = 1.0 / (n + 1)
+    p.gens = [W.Generator(W.segments_from_ranges([(0, 5)], 0.0), 0.0, 1.0)]
+    p.center = np.sin(3 * math.pi * np.arange(1, n + 1) * h)
+    p.C = [W.segments_from_ranges([(90, 111)], 1.0 / 21.0)]
+    got, _ = _compare32(p)
+    assert [r["k_eff"] for r in got["runs"]] == [0, 1]
+
+
+def test_fp32_close_to_fp64_gpu_at_larger_size():
+    # 40^3 heat, k = 40: the FP32-basis result against the FP64 GPU path
+    require_gpu()
+    p = W.heat3d_csr(m=40, k=40, steps=400)
+    a = gpu_verify(p)
+    b = gpu_verify(p, precision=kry.KRY_FP32_BASIS)
+    tol = fp32_tol(p)
+    worst = assert_basis_parity(b["basis"], a["basis"], rtol=tol)
+    print(f"  FP32 vs FP64 worst relative error {worst:.2e} (bound {tol:.1e})", flush=True)
