@@ -14,6 +14,10 @@ Prints one JSON line.  Options:
   --warmup W      untimed steps first (default 3)
   --no-cpu-baseline   skip timing the CPU oracle
   --m M           grid edge (default 100)
+  --workload W    heat3d_csr (the benchmark line), heat3d_stencil (1000^3 matrix-free),
+                  heat1d, conv_diff3d
+  --precision P   fp64 (default) or fp32 (FP32-basis mode; the FP64 path is then
+                  timed too, for the ratio to plain FP64)
   --calib-copy    run a plain device copy of known size (for counter calibration) and exit
 """
 from __future__ import annotations
@@ -53,6 +57,7 @@ def main():
     ap.add_argument("--workload", default="heat3d_csr",
                     choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d"],
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
@@ -80,70 +85,23 @@ def main():
     else:
         p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=2, o=5, k=30)
     dsys = kry.DeviceSystem(p, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    def step():
-        plan = kry.Plan(dsys, stream=stream)
-        plan.project_expm(None)
-        v = plan.check(p.unsafe)
-        nr = plan.nruns
-        plan.close()
-        return v, nr
-
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        verdict, nruns = step()
-    torch.cuda.synchronize()
-    # timed region 1: the whole job, no instrumentation -> value
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        verdict, nruns = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # timed region 2: the same steps with every kernel launch bracketed by HIP
-    # events on the plan's stream -> per-kernel durations for the roofline
-    log(f"timing {args.steps} steps with per-kernel events")
-    kry.profile_enable(True)
-    kry.profile_reset()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        verdict, nruns = step()
-    torch.cuda.synchronize()
-    elapsed_ev = time.perf_counter() - t1
-    kry.profile_enable(False)
-    kern = {}
-    for name in kry.profile_names():
-        cnt, ms = kry.profile_read(name)
-        if cnt:
-            kern[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt, "total_ms_per_step": ms / args.steps}
-    ms_per_step = 1000.0 * elapsed / args.steps
-    verified = (p.steps + 1) * nruns
-    value = verified / (elapsed / args.steps)
-
-    # algorithmic bytes per launch (all runs of the plan advanced by one launch)
+    f32 = args.precision == "fp32"
+    m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup)
+    fp64_ref = None
+    if f32:
+        torch.cuda.empty_cache()
+        log("plain FP64 on the same workload, for the ratio")
+        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup)
+        fp64_ref = {"value": m64["value"], "ms_per_step": m64["ms_per_step"],
+                    "ratio_fp32_over_fp64": m["value"] / m64["value"]}
+    kern, nruns, verdict = m["kern"], m["nruns"], m["verdict"]
     n, nnz = p.n, p.nnz
-    P = nruns
-    dom_name = "spmv_csr" if p.kind == "csr" else "spmv_stencil"
-    if p.kind == "csr":
-        spmv_bytes = 12 * nnz + 8 * (n + 1) + 3 * 8 * n * P     # A (val+col), rowptr, read v_j, v_{j-1}, write w
-    else:
-        spmv_bytes = 3 * 8 * n * P                              # read v_j, v_{j-1}, write w (matrix-free)
-    sweep_bytes = 3 * 8 * n * P                                 # read v_j, w; write w
-    for name, b in ((dom_name, spmv_bytes), ("sweep", sweep_bytes)):
-        if name in kern:
-            kern[name]["bytes"] = b
-            kern[name]["GBps"] = b / (kern[name]["avg_us"] * 1e-6) / 1e9
+    dom_name = m["dom_name"]
     dom = kern.get(dom_name, {})
     achieved = dom.get("GBps", 0.0)
     traffic = None
-    if args.workload == "heat3d_csr" and (args.m or 100) == 100:
+    if args.workload == "heat3d_csr" and (args.m or 100) == 100 and not f32:
         traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_csr_heat3d_m100_pmc.md"))
-    # Lanczos iteration = spmv + sweep: bytes and time of both kernels
-    step_bytes = spmv_bytes + sweep_bytes
-    step_us = dom.get("avg_us", 0.0) + kern.get("sweep", {}).get("avg_us", 0.0)
 
     cpu = None
     if not args.no_cpu_baseline and p.n <= 2_000_000:
@@ -152,42 +110,120 @@ def main():
 
     out = {
         "metric": "Krylov step HBM GB/s (% peak); verified time-steps/s vs plain FP64; p99 query latency",
-        "value": value,
+        "value": m["value"],
         "unit": "verified time-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not f32 else "f32-storage/f64-arith",
         "data": "synthetic",
-        "config": {"workload": describe(p, nruns), "n": n, "nnz": nnz, "k": p.k, "time_steps": p.steps,
-                   "runs": nruns, "precision": "fp64", "method": "lanczos" if p.symmetric else "arnoldi"},
+        "config": {"workload": describe(p, nruns, args.precision), "n": n, "nnz": nnz, "k": p.k,
+                   "time_steps": p.steps, "runs": nruns, "precision": args.precision,
+                   "method": "lanczos" if p.symmetric else "arnoldi"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom_name,
-                     "bytes_per_launch": spmv_bytes},
-        "ms_per_step_with_kernel_events": 1000.0 * elapsed_ev / args.steps,
-        "krylov_iteration": {"bytes": step_bytes, "us": step_us,
-                             "GBps": step_bytes / (step_us * 1e-6) / 1e9 if step_us else None},
+                     "bytes_per_launch": dom.get("bytes")},
+        "ms_per_step_with_kernel_events": m["ms_per_step_ev"],
         "kernels": kern,
+        "fp64_reference": fp64_ref,
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def describe(p, nruns):
+def measure(torch, kry, p, dsys, precision, steps, warmup):
+    """Times `steps` whole verifications (after `warmup`), then the same with
+    per-kernel HIP events; returns the throughput and per-kernel figures."""
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan = kry.Plan(dsys, stream=stream, precision=precision)
+        plan.project_expm(None)
+        v = plan.check(p.unsafe)
+        nr = plan.nruns
+        plan.close()
+        return v, nr
+
+    log(f"warmup {warmup} (precision {precision})")
+    for _ in range(warmup):
+        verdict, nruns = step()
+    torch.cuda.synchronize()
+    # timed region 1: the whole job, no instrumentation -> value
+    log(f"timing {steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        verdict, nruns = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # timed region 2: the same steps with every kernel launch bracketed by HIP
+    # events on the plan's stream -> per-kernel durations for the roofline
+    log(f"timing {steps} steps with per-kernel events")
+    kry.profile_enable(True)
+    kry.profile_reset()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        verdict, nruns = step()
+    torch.cuda.synchronize()
+    elapsed_ev = time.perf_counter() - t1
+    kry.profile_enable(False)
+    kern = {}
+    for name in kry.profile_names():
+        cnt, ms = kry.profile_read(name)
+        if cnt:
+            kern[name] = {"launches": cnt, "avg_us": 1000.0 * ms / cnt, "total_ms_per_step": ms / steps}
+    # algorithmic bytes per launch, all runs of the plan advanced by one launch
+    # (P = runs per batch; every workload here fits one batch)
+    es = 4 if precision == kry.KRY_FP32_BASIS else 8
+    n, nnz, P, k = p.n, p.nnz, nruns, p.k
+    vec = es * n * P
+    if p.kind == "csr":
+        mat = (4 if es == 4 else 8) * nnz + 4 * nnz + 8 * (n + 1)   # values, int32 columns, int64 row pointers
+    else:
+        mat = 0                                                   # matrix-free
+    lanczos = p.symmetric
+    per_launch = {
+        "spmv_csr": mat + (3 if lanczos else 2) * vec,        # read v_j (and v_{j-1}), write w
+        "spmv_stencil": (3 if lanczos else 2) * vec,
+        "sweep": 3 * vec,                                     # read v_j, w; write w
+        "start": vec,                                         # write u_1
+        # classical Gram-Schmidt passes over the stored basis, averaged over
+        # iterations j = 1..k (j stored vectors read per pass)
+        "arn_dots": vec * (1 + (k + 1) / 2.0),
+        "arn_update": vec * (2 + (k + 1) / 2.0),
+    }
+    for name, b in per_launch.items():
+        if name in kern:
+            kern[name]["bytes"] = b
+            kern[name]["GBps"] = b / (kern[name]["avg_us"] * 1e-6) / 1e9
+    mv = "spmv_csr" if p.kind == "csr" else "spmv_stencil"
+    # the roofline kernel: the mat-vec, or the one with the most time when a
+    # stored-basis pass outweighs it
+    dom_name = mv
+    for name in ("arn_update", "arn_dots"):
+        if name in kern and kern[name]["total_ms_per_step"] > kern.get(dom_name, {}).get("total_ms_per_step", 0):
+            dom_name = name
+    return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
+            "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
+            "dom_name": dom_name}
+
+
+def describe(p, nruns, precision):
+    prec = "FP64" if precision == "fp64" else "FP32 basis (FP64 sums), full reorthogonalisation"
     if p.name == "heat3d_csr":
         m = p.meta["m"]
         return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
-                f"{p.steps} steps, o={p.o}, runs={nruns}, FP64")
+                f"{p.steps} steps, o={p.o}, runs={nruns}, {prec}")
     if p.name == "heat3d_stencil":
         m = p.meta["m"]
         return (f"3D heat {m}^3 matrix-free 7-point (n={p.n}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
-                f"{p.steps} steps, o={p.o}, runs={nruns}, FP64")
-    return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} FP64"
+                f"{p.steps} steps, o={p.o}, runs={nruns}, {prec}")
+    return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} {prec}"
 
 
 def counter_traffic(path):

@@ -44,16 +44,17 @@ __global__ __launch_bounds__(kBlock) void k_arn_dots(ArnArgs A, BatchArgs B, int
     const E* V = static_cast<const E*>(A.V);
     const E* w = static_cast<const E*>(A.w);
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        double wv[P];
+        // all loads of a row are issued together: slots past the last stored
+        // vector re-read vector i0, and their sums are never stored
+        double wv[P], uv[kArnChunk][P];
         load_row<E, P>(w, r, wv);
 #pragma unroll
-        for (int ii = 0; ii < kArnChunk; ++ii) {
-            if (ii < ni) {
-                double uv[P];
-                load_row<E, P>(V + (int64_t)(i0 + ii) * A.vstride, r, uv);
+        for (int ii = 0; ii < kArnChunk; ++ii)
+            load_row<E, P>(V + (int64_t)(ii < ni ? i0 + ii : i0) * A.vstride, r, uv[ii]);
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[ii * P + p] = fma(uv[p], wv[p], acc[ii * P + p]);
-            }
+        for (int ii = 0; ii < kArnChunk; ++ii) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) acc[ii * P + p] = fma(uv[ii][p], wv[p], acc[ii * P + p]);
         }
     }
     const double t = block_sum<NV>(acc, s_lds);

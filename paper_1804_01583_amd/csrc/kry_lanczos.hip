@@ -224,10 +224,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restr
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const bool ok = e0[i] + sub + (int64_t)u * LPR < e1[i];
-                    double x[P];
-                    load_row<E, P>(ucur, (int64_t)c[i][u], x);
+                    // element-wise gathers keep the live registers (and so the
+                    // occupancy) lower than one wide load per row
 #pragma unroll
-                    for (int p = 0; p < P; ++p) acc[i][p] = ok ? fma(a[i][u], x[p], acc[i][p]) : acc[i][p];
+                    for (int p = 0; p < P; ++p) {
+                        const double x = (double)ucur[(int64_t)c[i][u] * P + p];
+                        acc[i][p] = ok ? fma(a[i][u], x, acc[i][p]) : acc[i][p];
+                    }
                 }
             }
         }
