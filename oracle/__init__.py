@@ -18,7 +18,9 @@ Billion Dimensions", arXiv 1804.01583):
 * the small matrix exponential by Pade [13/13] scaling and squaring
   (Higham 2005), one independent exponential per time step,
 * the per-step check, specialised from the LP of Section 2.1 to a box
-  initial set and per-row interval unsafe sets, with a counter-example.
+  initial set and per-row interval unsafe sets, with a counter-example,
+* block Arnoldi over p generator columns at once (``block``), the same
+  Galerkin approximant for a block start.
 
 All pins of these functions live in ``tests/test_oracle_*.py``.
 """
@@ -27,3 +29,4 @@ from .krylov import (  # noqa: F401
     project_steps, build_runs, verify, box_check, system_matrix, output_matrix,
     RunResult, krylov_run,
 )
+from .block import BlockResult, block_arnoldi, block_project_steps, block_verify, qr_posdiag  # noqa: F401

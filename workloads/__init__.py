@@ -394,7 +394,7 @@ def conv_diff3d(nx=200, ny=200, nz=250, peclet=5.0, extra_per_row=2, extra_sigma
             for s in slots[:ngen]]
     out_starts = list(slots[ngen:ngen + o])
     for q in range(min(2, o)):
-        out_starts[q] = int(slots[q]) + gen_len // 2          # overlaps generator q
+        out_starts[q] = min(int(slots[q]) + gen_len // 2, n - gen_len)   # overlaps generator q
     C = [segments_from_ranges([(int(s), int(s) + gen_len)], 1.0 / gen_len) for s in out_starts]
     unsafe = np.stack([np.full(o, 0.5), np.full(o, math.inf)], axis=1)
     return Problem("conv_diff3d", n, "csr", False, gens, C, unsafe, k=k, dt=dt, steps=steps,
