@@ -120,12 +120,24 @@ typedef struct kry_plan kry_plan;
  *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
  *  k: Krylov dimension per run, 1 <= k <= 56.  The augmented run uses k-1
  *     Lanczos steps on A from b bordered by one row and column, which spans
- *     the same k-dimensional Krylov space of the augmented matrix.
+ *     the same k-dimensional Krylov space of the augmented matrix.  For
+ *     KRY_BLOCK_ARNOLDI, k counts block steps (1 <= k <= 32; dimension p k).
  *  dt, steps: time points s*dt for s = 0..steps (steps + 1 rows of output).
- *  precision: KRY_FP64 (KRY_FP32_BASIS returns KRY_ENOTSUP in this build).
- *  method: KRY_AUTO or KRY_LANCZOS (needs symmetric); others KRY_ENOTSUP.
+ *  precision: KRY_FP64, or KRY_FP32_BASIS: Krylov vectors (and CSR values)
+ *     stored in FP32, every sum, coefficient and the small exponential in
+ *     FP64, the whole basis kept and each new vector reorthogonalised against
+ *     it (Lanczos: one classical pass after the three-term step; Arnoldi and
+ *     block Arnoldi: two passes).  Breakdown then uses eps of FP32.
+ *  method: KRY_AUTO (Lanczos when symmetric, else Arnoldi), KRY_LANCZOS
+ *     (Algorithm 3; needs symmetric), KRY_ARNOLDI (Algorithm 1, classical
+ *     Gram-Schmidt twice), or KRY_BLOCK_ARNOLDI: the generators in blocks of
+ *     p <= 16 columns, each block one block Krylov space
+ *     span{G, AG, ..., A^{k-1} G} with C e^{At} G ~ C V e^{Ht} E_1 R_0
+ *     (CSR systems, generator runs only: KRY_ENOTSUP with a center or a
+ *     forcing; KRY_ENUMERIC when a block's generators are dependent).
  *  block_p: runs advanced together per sparse mat-vec launch (1, 2, 4 or 8;
- *     0 = automatic).  Results do not depend on it.
+ *     0 = automatic); results do not depend on it.  For KRY_BLOCK_ARNOLDI
+ *     the block width p (1..16; 0 = min(ngen, 16)).
  *  workspace: device buffer of workspace_bytes >= kry_footprint(...), or NULL
  *     to let the plan allocate (and free) its own.
  *  hip_stream: hipStream_t to enqueue on (NULL = default stream).
@@ -170,6 +182,15 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
  * (roles_out: nruns ints, 0 = generator, 1 = center, 2 = augmented; may be NULL). */
 kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out);
 
+/* kry_plan_block -- after kry_project_expm of a KRY_BLOCK_ARNOLDI plan, the
+ * number of block runs (nblocks; generators b*p .. b*p + p - 1 form block b)
+ * and, for block >= 0, that run's data on the host: k_eff (block steps used,
+ * fewer than k after a breakdown), p (its columns), H ((p k_eff) x (p k_eff)
+ * row-major block Hessenberg, H = V^T A V), R0 (p x p upper triangular with a
+ * positive diagonal, G = V_1 R0 for the block's generators G) and
+ * P = C V (o x p k_eff).  Any output pointer may be NULL. */
+kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
+                          double* H, double* R0, double* P);
 /* kry_plan_krylov -- after kry_project_expm, copy one run's Krylov data to the
  * host: k_eff (Krylov dimension used; smaller than k after a breakdown),
  * beta0 = |start|, the run's Hessenberg matrix H (k_eff x k_eff row-major,

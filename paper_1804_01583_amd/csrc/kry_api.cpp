@@ -70,7 +70,7 @@ Profiler& prof() {
 
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
-    "assemble,check";
+    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -132,6 +132,8 @@ int32_t march_blocks_for(const kry_system& sys) {
     return (int32_t)align_up((size_t)((ncol + kBlock - 1) / kBlock), 8);
 }
 
+constexpr int kProjGroups = 32;   // workgroups per output row in the block projection
+
 int max_batch_for(int o, int block_p) {
     int p = 8;
     while (p > 1 && p * (1 + o) > kMaxNV) p >>= 1;
@@ -153,6 +155,12 @@ struct Layout {
     int32_t nvp;
     int32_t nvec;
     int32_t march;        // column blocks of the marching stencil kernel (0: row kernel)
+    // block Arnoldi
+    int32_t bw = 0;       // block width (generators per block run)
+    int32_t brb = 0;      // row blocks of the Gram kernel
+    int64_t brows = 0;    // rows per Gram row block
+    size_t bvec = 0, bgpart = 0, bcoef = 0, bH = 0, bP = 0, bR0 = 0, brfirst = 0, bstate = 0, bppart = 0, bS0 = 0,
+           bdense = 0;
     int32_t esize;        // bytes per stored vector element: 8 (FP64) or 4 (FP32 basis)
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     size_t hpart, hcoef, vals32;
@@ -183,11 +191,13 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     L.misc = L.proj + o * (k + 1);
     L.hess = L.misc + MISC_COUNT;
     L.stride = (int64_t)align_up((size_t)(L.hess + (k + 1) * k), 8);
-    size_t off = 0;
+    // offset 0 is reserved: an offset of 0 marks a region the plan does not have
+    size_t off = 256;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
     // Lanczos keeps three vectors per run (Algorithm 4); Arnoldi, and every
     // method in FP32-basis mode (full reorthogonalisation), the whole basis
-    Y.nvec = Y.stored ? k + 1 : 3;
+    if (method == KRY_BLOCK_ARNOLDI) { Y.pmax = 1; Y.stored = false; }
+    Y.nvec = method == KRY_BLOCK_ARNOLDI ? 0 : (Y.stored ? k + 1 : 3);
     Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
     Y.hpart = Y.stored ? take((size_t)kMaxK * kMaxP * Y.nblocks * sizeof(double)) : 0;
     Y.hcoef = Y.stored ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
@@ -208,6 +218,23 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.cpart = take((size_t)2 * check_blocks(steps, o) * sizeof(double));
     Y.verdict = take((size_t)(6 + nruns) * sizeof(double));
     Y.anorm = take(sizeof(double));
+    if (method == KRY_BLOCK_ARNOLDI) {
+        Y.bw = block_p;
+        Y.brb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(512, (n + 63) / 64));
+        Y.brows = (int64_t)align_up((size_t)((n + Y.brb - 1) / Y.brb), 4);
+        const int64_t m = (int64_t)kBW * k;
+        Y.bvec = take((size_t)(k + 1) * n * kBW * Y.esize);
+        Y.bgpart = take((size_t)(k + 1) * Y.brb * 256 * sizeof(double));
+        Y.bcoef = take((size_t)(k + 1) * 256 * sizeof(double));
+        Y.bH = take((size_t)(m + kBW) * m * sizeof(double));
+        Y.bP = take((size_t)o * (m + kBW) * sizeof(double));
+        Y.bR0 = take(256 * sizeof(double));
+        Y.brfirst = take(256 * sizeof(double));
+        Y.bstate = take(4 * sizeof(int32_t));
+        Y.bppart = take((size_t)o * kProjGroups * kBW * sizeof(double));
+        Y.bS0 = take((size_t)m * kBW * sizeof(double));
+        Y.bdense = take(dense_workspace_doubles((int)m, o, kBW, Y.B, Y.nanch) * sizeof(double));
+    }
     Y.meta = take(meta_bytes);
     Y.total = off;
     return Y;
@@ -308,12 +335,21 @@ struct kry_plan {
     int32_t method = KRY_LANCZOS;
     bool projected = false;
     std::vector<double> verdict_host;
+    // block Arnoldi: per block run, k_eff (blocks), width, H (m x m), R0 (p x p), P (o x m) on the host
+    struct BlockInfo {
+        int32_t k_eff = 0, p = 0;
+        std::vector<double> H, R0, P;
+    };
+    std::vector<BlockInfo> blocks;
+    bool nonfinite = false;
 
     bool f32 = false;
     bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
 
     void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
     float* vals32() { return reinterpret_cast<float*>(ws + Y.vals32); }
+    template <typename T>
+    T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
     double* hpart() { return reinterpret_cast<double*>(ws + Y.hpart); }
     double* hcoef() { return reinterpret_cast<double*>(ws + Y.hcoef); }
     double* np_part() { return reinterpret_cast<double*>(ws + Y.np_part); }
@@ -382,11 +418,17 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     kry_status st = validate_system(sys);
     if (st != KRY_OK) return st;
     if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
-    if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kMaxK || steps < 0 || nseg_total < 0)
-        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56, steps >= 0, nseg_total >= 0 required");
-    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
-    const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : kMaxK;
+    if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kmax || steps < 0 || nseg_total < 0)
+        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56 (32 block steps), steps >= 0, "
+                                "nseg_total >= 0 required");
+    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+    if (method == KRY_BLOCK_ARNOLDI) {
+        if (block_p < 0 || block_p > kBW) return fail(KRY_EINVAL, "block Arnoldi: block_p must be <= 16");
+        block_p = block_p > 0 ? block_p : std::min<int32_t>(nruns, kBW);
+    }
+    const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
     const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
@@ -406,15 +448,27 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (st != KRY_OK) return st;
     if (ngen < 0 || (ngen > 0 && !gens)) return fail(KRY_EINVAL, "bad generator list");
     if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
-    if (k < 1 || k > kMaxK) return fail(KRY_EINVAL, "k must be in [1, 56]");
+    if (method == KRY_BLOCK_ARNOLDI) {
+        if (k < 1 || k > kMaxKB) return fail(KRY_EINVAL, "block Arnoldi: k (block steps) must be in [1, 32]");
+    } else if (k < 1 || k > kMaxK) {
+        return fail(KRY_EINVAL, "k must be in [1, 56]");
+    }
     if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
     if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
-        return fail(KRY_ENOTSUP, "method must be KRY_AUTO, KRY_LANCZOS or KRY_ARNOLDI in this build");
+    if (method != KRY_LANCZOS && method != KRY_ARNOLDI && method != KRY_BLOCK_ARNOLDI)
+        return fail(KRY_EINVAL, "unknown method");
     if (method == KRY_LANCZOS && !sys->symmetric) return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
     if (block_p < 0) return fail(KRY_EINVAL, "block_p must be >= 0");
+    if (method == KRY_BLOCK_ARNOLDI) {
+        if (sys->kind != KRY_CSR) return fail(KRY_ENOTSUP, "block Arnoldi needs a CSR system");
+        if (center || sys->b || sys->b_segs)
+            return fail(KRY_ENOTSUP, "block Arnoldi simulates generator columns only (no center, no forcing)");
+        if (ngen < 1) return fail(KRY_EINVAL, "block Arnoldi needs at least one generator");
+        if (block_p > kBW) return fail(KRY_EINVAL, "block Arnoldi: block_p must be <= 16");
+        block_p = block_p > 0 ? block_p : std::min<int32_t>(ngen, kBW);
+    }
     const int64_t n = sys->n;
     for (int32_t g = 0; g < ngen; ++g) {
         st = check_segs(gens[g].seg, n, "generator");
@@ -572,8 +626,166 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     return KRY_OK;
 }
 
+namespace {
+
+// Marks the basis as formed and copies it out (waits when the target is host memory).
+kry_status finish_projection(kry_plan* plan, double* basis_out) {
+    plan->projected = true;
+    if (basis_out) {
+        hipStream_t s = plan->stream;
+        const size_t bytes = (size_t)(plan->steps + 1) * plan->o * plan->nruns * sizeof(double);
+        hipPointerAttribute_t attr{};
+        bool device_ptr = false;
+        if (hipPointerGetAttributes(&attr, basis_out) == hipSuccess)
+            device_ptr = attr.type == hipMemoryTypeDevice;
+        else
+            (void)hipGetLastError();
+        KRY_HIP(hipMemcpyAsync(basis_out, plan->basis(), bytes, hipMemcpyDefault, s));
+        if (!device_ptr) KRY_HIP(hipStreamSynchronize(s));
+    }
+    return KRY_OK;
+}
+
+// Block Arnoldi for the generator columns, bw at a time (the block form of
+// Algorithm 1 with CGS2 and CholQR2), then the dense stage for each block run.
+kry_status project_block(kry_plan* plan) {
+    const Layout& Y = plan->Y;
+    const int64_t n = plan->sys.n;
+    hipStream_t s = plan->stream;
+    const bool f32 = plan->f32;
+    const int k = plan->k, o = plan->o;
+    const int64_t m_max = (int64_t)kBW * k;
+    const int64_t vstride = n * kBW;     // elements from one stored block to the next
+    auto V = [&](int i) -> void* { return plan->ws + Y.bvec + (size_t)i * vstride * Y.esize; };
+    BlockArgs B{};
+    B.n = n;
+    B.rb = Y.brb;
+    B.rows_per_rb = Y.brows;
+    B.gpart = plan->at<double>(Y.bgpart);
+    B.coef = plan->at<double>(Y.bcoef);
+    B.H = plan->at<double>(Y.bH);
+    B.ldh = (int32_t)m_max;
+    B.P = plan->at<double>(Y.bP);
+    B.ldp = (int32_t)(m_max + kBW);
+    B.R0 = plan->at<double>(Y.bR0);
+    B.rfirst = plan->at<double>(Y.brfirst);
+    B.state = plan->at<int32_t>(Y.bstate);
+    B.anorm = plan->anorm();
+    B.tau_scale = 1024.0 * (f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
+    plan->blocks.clear();
+    hipError_t e = hipSuccess;
+#define KRY_STEP(name, call)                                                                       \
+    do {                                                                                           \
+        e = timed(name, s, [&] { return call; });                                                  \
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string(name) + ": " + hipGetErrorString(e)); \
+    } while (0)
+    for (int32_t b0 = 0; b0 < plan->ngen; b0 += Y.bw) {
+        const int p = std::min<int32_t>(Y.bw, plan->ngen - b0);
+        B.p = p;
+        BlockStart S{};
+        for (int c = 0; c < kBW; ++c) S.set[c] = c < p ? plan->gen_set[b0 + c] : -1;
+        S.p = p;
+        KRY_STEP("bfill", launch_fill_i32(B.state, 4, 0, s));
+        KRY_STEP("bfill", launch_fill(B.H, (m_max + kBW) * m_max, 0.0, s));
+        KRY_STEP("bfill", launch_fill(B.P, (int64_t)o * (m_max + kBW), 0.0, s));
+        KRY_STEP("bfill", launch_fill(plan->at<double>(Y.bS0), m_max * kBW, 0.0, s));
+        KRY_STEP("bstart", launch_bstart(f32, plan->T, S, V(0), n, s));
+        // CholQR2 of the start block: G = V_1 R0
+        for (int pass = 1; pass <= 2; ++pass) {
+            KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, 1, V(0), B, s));
+            KRY_STEP("bgram_red", launch_bgram_red(B, 1, 0, 2, s));
+            KRY_STEP("bchol", launch_bchol(B, 0, pass, s));
+            KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, 1, V(0), 0, B, s));
+        }
+        KRY_STEP("bproj", launch_bproj(f32, plan->T, plan->oset0, o, V(0), plan->at<double>(Y.bppart), kProjGroups, 0,
+                                       B, s));
+        for (int j = 1; j <= k; ++j) {
+            void* W = V(j);
+            KRY_STEP("bspmm", launch_bspmm(f32, A, V(j - 1), W, B, s));
+            // CGS2 against V_1..V_j; the last step only needs the coefficients
+            for (int pass = 1; pass <= 2; ++pass) {
+                KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, j, W, B, s));
+                KRY_STEP("bgram_red", launch_bgram_red(B, j, j, pass - 1, s));
+                if (j < k || pass == 1) KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, j, W, 1, B, s));
+            }
+            if (j == k) break;
+            // CholQR2: W = V_{j+1} H_{j+1,j}
+            for (int pass = 1; pass <= 2; ++pass) {
+                KRY_STEP("bgram", launch_bgram(f32, W, vstride, 1, W, B, s));
+                KRY_STEP("bgram_red", launch_bgram_red(B, 1, j, 2, s));
+                KRY_STEP("bchol", launch_bchol(B, j, pass, s));
+                KRY_STEP("bupdate", launch_bupdate(f32, W, vstride, 1, W, 0, B, s));
+            }
+            KRY_STEP("bproj", launch_bproj(f32, plan->T, plan->oset0, o, W, plan->at<double>(Y.bppart), kProjGroups,
+                                           j, B, s));
+        }
+        int32_t st[4];
+        KRY_HIP(hipMemcpyAsync(st, B.state, sizeof(st), hipMemcpyDeviceToHost, s));
+        KRY_HIP(hipStreamSynchronize(s));
+        if (st[2]) plan->nonfinite = true;
+        const int keff = std::min(st[1], k);
+        if (keff <= 0) return fail(KRY_ENUMERIC, "block Arnoldi: the generators of a block are linearly dependent");
+        const int m = kBW * keff;
+        // S0 = E_1 R0 (first 16 rows)
+        KRY_HIP(hipMemcpyAsync(plan->at<double>(Y.bS0), B.R0, 256 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        DenseJob J{};
+        J.H = B.H;
+        J.ldh = B.ldh;
+        J.m = m;
+        J.dt = plan->dt;
+        J.P = B.P;
+        J.ldp = B.ldp;
+        J.o = o;
+        J.S0 = plan->at<double>(Y.bS0);
+        J.lds0 = kBW;
+        J.w = p;
+        J.B = Y.B;
+        J.nanch = Y.nanch;
+        J.steps = plan->steps;
+        J.basis = plan->basis();
+        J.nruns = plan->nruns;
+        J.run0 = b0;
+        double hn = 0.0;
+        e = timed("dense_expm", s, [&] { return dense_expm_steps(J, plan->at<double>(Y.bdense), &hn, s); });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("dense stage: ") + hipGetErrorString(e));
+        // keep H, R0 and P of this block run for kry_plan_block
+        kry_plan::BlockInfo bi;
+        bi.k_eff = keff;
+        bi.p = p;
+        std::vector<double> Hfull((size_t)m * m_max), Pfull((size_t)o * B.ldp), R0(256);
+        KRY_HIP(hipMemcpyAsync(Hfull.data(), B.H, Hfull.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        KRY_HIP(hipMemcpyAsync(Pfull.data(), B.P, Pfull.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        KRY_HIP(hipMemcpyAsync(R0.data(), B.R0, 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+        KRY_HIP(hipStreamSynchronize(s));
+        // drop the zero columns of a block narrower than 16
+        const int mp = p * keff;
+        bi.H.assign((size_t)mp * mp, 0.0);
+        bi.P.assign((size_t)o * mp, 0.0);
+        bi.R0.assign((size_t)p * p, 0.0);
+        for (int a = 0; a < mp; ++a) {
+            const int ra = (a / p) * kBW + a % p;
+            for (int c = 0; c < mp; ++c) bi.H[(size_t)a * mp + c] = Hfull[(size_t)ra * m_max + (c / p) * kBW + c % p];
+        }
+        for (int q = 0; q < o; ++q)
+            for (int c = 0; c < mp; ++c) bi.P[(size_t)q * mp + c] = Pfull[(size_t)q * B.ldp + (c / p) * kBW + c % p];
+        for (int a = 0; a < p; ++a)
+            for (int c = 0; c < p; ++c) bi.R0[(size_t)a * p + c] = R0[(size_t)a * kBW + c];
+        plan->blocks.push_back(std::move(bi));
+    }
+#undef KRY_STEP
+    return KRY_OK;
+}
+
+}  // namespace
+
 kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (plan->method == KRY_BLOCK_ARNOLDI) {
+        kry_status st = project_block(plan);
+        if (st != KRY_OK) return st;
+        return finish_projection(plan, basis_out);
+    }
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
@@ -678,19 +890,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                    Y.B, Y.nanch, plan->steps, plan->basis()};
     e = timed("assemble", s, [&] { return launch_assemble(A, s); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("assemble: ") + hipGetErrorString(e));
-    plan->projected = true;
-    if (basis_out) {
-        const size_t bytes = (size_t)(plan->steps + 1) * plan->o * plan->nruns * sizeof(double);
-        hipPointerAttribute_t attr{};
-        bool device_ptr = false;
-        if (hipPointerGetAttributes(&attr, basis_out) == hipSuccess)
-            device_ptr = attr.type == hipMemoryTypeDevice;
-        else
-            (void)hipGetLastError();
-        KRY_HIP(hipMemcpyAsync(basis_out, plan->basis(), bytes, hipMemcpyDefault, s));
-        if (!device_ptr) KRY_HIP(hipStreamSynchronize(s));
-    }
-    return KRY_OK;
+    return finish_projection(plan, basis_out);
 }
 
 kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out, double* z_out) {
@@ -723,6 +923,7 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
     out->lo = v[3];
     out->hi = v[4];
     out->status = (int32_t)v[5];
+    if (plan->nonfinite) out->status = KRY_ENUMERIC;
     if (z_out) {
         int32_t g = 0;
         for (int32_t r = 0; r < plan->nruns; ++r)
@@ -744,6 +945,7 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
     if (!plan) return fail(KRY_EINVAL, "plan is NULL");
     if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
     if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs: use kry_plan_block");
     const ScalLayout& L = plan->Y.L;
     std::vector<double> sc(L.stride);
     KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal() + (size_t)run * L.stride, L.stride * sizeof(double),
@@ -784,6 +986,23 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
             for (int c = 0; c < tri; ++c) row[c0 + c] = sc[L.proj + q * (k + 1) + c];
         }
     }
+    return KRY_OK;
+}
+
+kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
+                          double* H, double* R0, double* P) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (plan->method != KRY_BLOCK_ARNOLDI) return fail(KRY_EINVAL, "not a block Arnoldi plan");
+    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    if (nblocks) *nblocks = (int32_t)plan->blocks.size();
+    if (block < 0) return KRY_OK;
+    if (block >= (int32_t)plan->blocks.size()) return fail(KRY_EINVAL, "block out of range");
+    const auto& b = plan->blocks[block];
+    if (k_eff) *k_eff = b.k_eff;
+    if (p) *p = b.p;
+    if (H) std::copy(b.H.begin(), b.H.end(), H);
+    if (R0) std::copy(b.R0.begin(), b.R0.end(), R0);
+    if (P) std::copy(b.P.begin(), b.P.end(), P);
     return KRY_OK;
 }
 

@@ -1,0 +1,396 @@
+// Block Arnoldi on gfx950: p <= 16 generator columns simulated as one block
+// Krylov space span{G, A G, ..., A^{k-1} G} (the block form of Algorithm 1,
+// Section 4.2 written for a block start).  Blocks are 16 columns wide; a
+// block of p < 16 real columns carries zero columns that stay zero.
+//
+// Storage: block i of the basis is an [n][16] row-major array (one 128-byte
+// row of FP64, or 64 bytes of FP32, per grid row), blocks kept for the whole
+// run.  One block step j:
+//   k_bspmm      W = A V_j                               (16 lanes per CSR row)
+//   k_bgram      partials of V_i^T W, i = 1..j           (MFMA f64 16x16x4)
+//   k_bgram_red  H_{i,j} += sum of partials; -H_{i,j} kept for the update
+//   k_bupdate    W += sum_i V_i (-H_{i,j})               (MFMA f64 16x16x4)
+//   (the Gram-Schmidt pair runs twice: CGS2)
+//   k_bgram / k_bchol / k_bupdate: CholQR2 of W = V_{j+1} H_{j+1,j} (Gram
+//   matrix, Cholesky in one thread, W R^{-1} in place), twice
+//   k_bproj      partials of C V_{j+1}                   (only rows inside C's segments)
+// All sums are FP64 and in a fixed order; no atomics.
+//
+// MFMA f64 16x16x4 lane layout (measured on gfx950): A[m][k] is held by lane
+// m + 16k, B[k][n] by lane n + 16k, and D[m][n] by lane n + 16 (m % 4) in
+// accumulator register m / 4.
+#include "kry_device.h"
+
+#include <cmath>
+
+namespace kry {
+
+namespace {
+
+using namespace dev;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bool block_done(const BlockArgs& B) { return B.state[0] != 0; }
+
+// ---------------------------------------------------------------------------
+// Start block: column c < p of V_1 (unnormalised) is generator c of the block.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_bstart(SegTable T, BlockStart S, E* __restrict__ V, int64_t n) {
+    const int c = threadIdx.x & 15;
+    const int grp = threadIdx.x >> 4;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 16);
+    // each lane walks its column's segment set with a cursor over rows
+    const int s = c < S.p ? S.set[c] : -1;
+    int32_t cur = s >= 0 ? T.set_begin[s] : 0;
+    const int32_t end = s >= 0 ? T.set_begin[s + 1] : 0;
+    for (int64_t r = (int64_t)blockIdx.x * (kBlock / 16) + grp; r < n; r += stride) {
+        double v = 0.0;
+        if (s >= 0) {
+            while (cur < end && T.hi[cur] <= r) ++cur;
+            if (cur < end && T.lo[cur] <= r) v = T.w[cur];
+        }
+        V[r * kBW + c] = (E)v;
+    }
+}
+
+// W = A V_j: a group of 16 lanes owns a row, lane c its column c; the CSR
+// entries of the row are read by all 16 lanes (one cache line), the gathered
+// row of V_j is one contiguous 16-value load.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict__ V, E* __restrict__ W, int64_t n,
+                                                  BlockArgs B) {
+    if (block_done(B)) return;
+    const int c = threadIdx.x & 15;
+    const int grp = threadIdx.x >> 4;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 16);
+    for (int64_t r = (int64_t)blockIdx.x * (kBlock / 16) + grp; r < n; r += stride) {
+        const int64_t e0 = A.rowptr[r], e1 = A.rowptr[r + 1];
+        double acc = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t col = A.colidx[e];
+            const double a = sizeof(E) == 4 ? (double)A.vals32[e] : A.vals[e];
+            acc = fma(a, (double)V[col * kBW + c], acc);
+        }
+        W[r * kBW + c] = (E)acc;
+    }
+}
+
+// Partials of X_i^T Y, i < nx, over the rows of row block blockIdx.x.  Wave
+// w of the workgroup owns i = w, w + 4, ... (NI of them at most), so a row of
+// Y is fetched from memory once per workgroup; each MFMA consumes 4 rows.
+// Rows past the block's end read row r0 and are multiplied by zero.
+template <typename E, int NI>
+__global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int64_t xstride, int nx,
+                                                  const E* __restrict__ Y, BlockArgs B) {
+    if (block_done(B)) return;
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * B.rows_per_rb;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_rb);
+    const int col = l & 15, sub = l >> 4;
+    v4d acc[NI];
+#pragma unroll
+    for (int u = 0; u < NI; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; r += 4) {
+        const int64_t row = r + sub;
+        const bool ok = row < r1;
+        const int64_t rr = ok ? row : r0;
+        const double yv = (double)Y[rr * kBW + col];
+        const double b = ok ? yv : 0.0;
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+            const int i = wave + 4 * u;
+            if (i < nx) {                              // uniform per wave
+                const double a = (double)X0[(int64_t)i * xstride + rr * kBW + col];
+                acc[u] = mfma16(ok ? a : 0.0, b, acc[u]);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NI; ++u) {
+        const int i = wave + 4 * u;
+        if (i >= nx) continue;
+        double* out = B.gpart + ((int64_t)i * B.rb + blockIdx.x) * 256;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[(4 * q + sub) * 16 + col] = acc[u][q];   // D[m][col], m = 4q + sub
+    }
+}
+
+// Sums the row-block partials of block i = blockIdx.x (thread t = entry t of
+// the 16 x 16 result) in a fixed order.  mode 0/1: Gram-Schmidt pass 1/2,
+// H_{i,j} = / += result and coef_i = -result; mode 2: Gram matrix into coef_0.
+__global__ __launch_bounds__(256) void k_bgram_red(BlockArgs B, int j, int mode) {
+    if (block_done(B)) return;
+    const int i = blockIdx.x, t = threadIdx.x;
+    const double* part = B.gpart + (int64_t)i * B.rb * 256;
+    double s = 0.0;
+    for (int b = 0; b < B.rb; ++b) s += part[(int64_t)b * 256 + t];
+    if (mode == 2) {
+        B.coef[t] = s;
+        return;
+    }
+    const int m = t >> 4, c = t & 15;
+    double* h = B.H + (int64_t)(16 * i + m) * B.ldh + 16 * (j - 1) + c;
+    if (mode == 0) *h = s;
+    else *h += s;
+    B.coef[(int64_t)i * 256 + t] = -s;
+}
+
+// CholQR step on the Gram matrix G = W^T W in coef_0 (one thread; 16 x 16):
+// G = R^T R with R upper triangular and a positive diagonal; padded columns
+// (c >= p) get R_cc = 1.  coef_0 <- R^{-1} for the in-place W R^{-1}.
+// pass 1 also decides breakdown: a diagonal R_cc <= tau ends the run before
+// block j + 1 (or, for the start block j = 0, marks it rank deficient).
+// pass 2 writes H_{j+1,j} = R2 R1 (start block: R0 = R2 R1).
+__global__ __launch_bounds__(64) void k_bchol(BlockArgs B, int j, int pass) {
+    if (block_done(B) || threadIdx.x != 0) return;
+    double G[16][16], R[16][16], Ri[16][16];
+    for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) { G[a][b] = B.coef[a * 16 + b]; R[a][b] = 0.0; Ri[a][b] = 0.0; }
+    // breakdown: R_cc <= 1024 eps ||A||_inf for a new block; for the start
+    // block, R_cc <= 1024 eps max_c |g_c| (dependent generator columns)
+    double gmax = 0.0;
+    for (int c = 0; c < B.p; ++c) gmax = fmax(gmax, sqrt(fmax(G[c][c], 0.0)));
+    const double tau = j == 0 ? B.tau_scale * gmax : B.tau_scale * *B.anorm;
+    bool bad = false, nonfinite = false;
+    for (int c = 0; c < 16; ++c) {
+        if (c >= B.p) { R[c][c] = 1.0; continue; }
+        double d = G[c][c];
+        for (int q = 0; q < c; ++q) d -= R[q][c] * R[q][c];
+        if (!isfinite(d)) nonfinite = true;
+        const double rc = d > 0.0 ? sqrt(d) : 0.0;
+        if (pass == 1 && !(rc > tau)) bad = true;
+        if (rc <= 0.0) { R[c][c] = 1.0; bad = true; continue; }
+        R[c][c] = rc;
+        for (int b = c + 1; b < B.p; ++b) {
+            double v = G[c][b];
+            for (int q = 0; q < c; ++q) v -= R[q][c] * R[q][b];
+            R[c][b] = v / rc;
+        }
+    }
+    if (nonfinite) { B.state[2] = 1; bad = true; }
+    if (bad) {
+        B.state[0] = 1;
+        B.state[1] = j;            // blocks of the run (0: the start block itself is unusable)
+        return;
+    }
+    // upper-triangular inverse by back substitution, column by column
+    for (int c = 0; c < 16; ++c) {
+        Ri[c][c] = 1.0 / R[c][c];
+        for (int a = c - 1; a >= 0; --a) {
+            double v = 0.0;
+            for (int q = a + 1; q <= c; ++q) v += R[a][q] * Ri[q][c];
+            Ri[a][c] = -v / R[a][a];
+        }
+    }
+    for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) B.coef[a * 16 + b] = Ri[a][b];
+    if (pass == 1) {
+        for (int a = 0; a < 16; ++a)
+            for (int b = 0; b < 16; ++b) B.rfirst[a * 16 + b] = R[a][b];
+        return;
+    }
+    // R_total = R2 R1 (both upper triangular)
+    double* dst = j == 0 ? B.R0 : B.H + (int64_t)(16 * j) * B.ldh + 16 * (j - 1);
+    const int64_t ld = j == 0 ? 16 : B.ldh;
+    for (int a = 0; a < 16; ++a)
+        for (int b = 0; b < 16; ++b) {
+            double v = 0.0;
+            for (int q = a; q <= b; ++q) v += R[a][q] * B.rfirst[q * 16 + b];
+            dst[a * ld + b] = (a < B.p && b < B.p) ? v : 0.0;
+        }
+    B.state[1] = j + 1;
+}
+
+// Y = (accumulate ? Y : 0) + sum_{i < nx} X_i M_i, M_i = coef_i (16 x 16).
+// One wave per 16-row tile.  Lane l loads its row r0 + l % 16, columns
+// 4 (l / 16) .. 4 (l / 16) + 3 (one 32-byte load); MFMA t (t = 0..3) pairs
+// slot k = l / 16 with column 4k + t, so the four MFMAs cover all 16
+// columns of X_i without moving data between lanes.  In place (X_0 = Y) is
+// safe: a wave reads its whole tile before it writes.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_bupdate(const E* __restrict__ X0, int64_t xstride, int nx,
+                                                    E* __restrict__ Y, int accumulate, BlockArgs B) {
+    if (block_done(B)) return;
+    __shared__ double s_m[8 * 256];
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t tiles = (B.n + 15) / 16;
+    const int64_t tile = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+    const bool live = tile < tiles;
+    const int64_t r0 = (live ? tile : 0) * 16;
+    const int col = l & 15, sub = l >> 4;
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    if (accumulate && live) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t row = r0 + 4 * q + sub;
+            acc[q] = row < B.n ? (double)Y[row * kBW + col] : 0.0;
+        }
+    }
+    const int64_t xrow = r0 + col;
+    const bool xok = live && xrow < B.n;
+    for (int i0 = 0; i0 < nx; i0 += 8) {
+        const int ni = min(8, nx - i0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < ni * 256; t += kBlock) s_m[t] = B.coef[(int64_t)i0 * 256 + t];
+        __syncthreads();
+        for (int ii = 0; ii < ni; ++ii) {
+            const E* X = X0 + (int64_t)(i0 + ii) * xstride;
+            double xv[4];
+            const int64_t rr = xok ? xrow : 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double v = (double)X[rr * kBW + 4 * sub + t];
+                xv[t] = xok ? v : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma16(xv[t], s_m[ii * 256 + (4 * sub + t) * 16 + col], acc);
+        }
+    }
+    if (!live) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t row = r0 + 4 * q + sub;
+        if (row < B.n) Y[row * kBW + col] = (E)acc[q];
+    }
+}
+
+// Partials of C V_j over the rows of each output set only: workgroup
+// (q, g) takes rows lo + g * 16 + group, stepping by 16 * gridDim.y, of every
+// segment of set q; group of 16 lanes per row, lane = column.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_bproj(SegTable T, int32_t oset0, const E* __restrict__ V,
+                                                  double* __restrict__ part, BlockArgs B) {
+    if (block_done(B)) return;
+    __shared__ double s_acc[kBlock];
+    const int q = blockIdx.x, g = blockIdx.y, G = gridDim.y;
+    const int c = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const int s = oset0 + q;
+    double acc = 0.0;
+    for (int32_t seg = T.set_begin[s]; seg < T.set_begin[s + 1]; ++seg) {
+        const int64_t lo = T.lo[seg], hi = T.hi[seg];
+        const double w = T.w[seg];
+        for (int64_t r = lo + (int64_t)g * 16 + grp; r < hi; r += (int64_t)16 * G)
+            acc = fma(w, (double)V[r * kBW + c], acc);
+    }
+    s_acc[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 16; ++k) t += s_acc[k * 16 + threadIdx.x];
+        part[((int64_t)q * G + g) * 16 + threadIdx.x] = t;
+    }
+}
+
+// P[:, 16 j + c] = sum of the projection partials (one thread per (q, c)).
+__global__ __launch_bounds__(128) void k_bproj_red(const double* __restrict__ part, int o, int G, int j,
+                                                   BlockArgs B) {
+    if (block_done(B)) return;
+    const int t = threadIdx.x;
+    if (t >= o * 16) return;
+    const int q = t / 16, c = t % 16;
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += part[((int64_t)q * G + g) * 16 + c];
+    B.P[(int64_t)q * B.ldp + 16 * j + c] = c < B.p ? s : 0.0;
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------
+
+hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void* V, int64_t n, hipStream_t s) {
+    const int64_t want = (n + kBlock / 16 - 1) / (kBlock / 16);
+    const int grid = (int)std::min<int64_t>(want, 8192);
+    if (f32) hipLaunchKernelGGL(k_bstart<float>, dim3(grid), dim3(kBlock), 0, s, T, S, static_cast<float*>(V), n);
+    else hipLaunchKernelGGL(k_bstart<double>, dim3(grid), dim3(kBlock), 0, s, T, S, static_cast<double*>(V), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, const BlockArgs& B, hipStream_t s) {
+    const int64_t want = (B.n + kBlock / 16 - 1) / (kBlock / 16);
+    const int grid = (int)std::min<int64_t>(want, 16384);
+    if (f32)
+        hipLaunchKernelGGL(k_bspmm<float>, dim3(grid), dim3(kBlock), 0, s, A, static_cast<const float*>(V),
+                           static_cast<float*>(W), B.n, B);
+    else
+        hipLaunchKernelGGL(k_bspmm<double>, dim3(grid), dim3(kBlock), 0, s, A, static_cast<const double*>(V),
+                           static_cast<double*>(W), B.n, B);
+    return hipGetLastError();
+}
+
+template <typename E, int NI>
+hipError_t launch_bgram_t(const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_bgram<E, NI>), dim3(B.rb), dim3(kBlock), 0, s, static_cast<const E*>(X0), xstride, nx,
+                       static_cast<const E*>(Y), B);
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_bgram_e(const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
+                          hipStream_t s) {
+    switch ((nx + 3) / 4) {
+        case 1: return launch_bgram_t<E, 1>(X0, xstride, nx, Y, B, s);
+        case 2: return launch_bgram_t<E, 2>(X0, xstride, nx, Y, B, s);
+        case 3: return launch_bgram_t<E, 3>(X0, xstride, nx, Y, B, s);
+        case 4: return launch_bgram_t<E, 4>(X0, xstride, nx, Y, B, s);
+        case 5: return launch_bgram_t<E, 5>(X0, xstride, nx, Y, B, s);
+        case 6: return launch_bgram_t<E, 6>(X0, xstride, nx, Y, B, s);
+        case 7: return launch_bgram_t<E, 7>(X0, xstride, nx, Y, B, s);
+        case 8: return launch_bgram_t<E, 8>(X0, xstride, nx, Y, B, s);
+        case 9: return launch_bgram_t<E, 9>(X0, xstride, nx, Y, B, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
+                        hipStream_t s) {
+    if (nx < 1 || nx > kMaxKB + 1) return hipErrorInvalidValue;
+    return f32 ? launch_bgram_e<float>(X0, xstride, nx, Y, B, s) : launch_bgram_e<double>(X0, xstride, nx, Y, B, s);
+}
+
+hipError_t launch_bgram_red(const BlockArgs& B, int nx, int j, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_bgram_red, dim3(nx), dim3(256), 0, s, B, j, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_bchol(const BlockArgs& B, int j, int pass, hipStream_t s) {
+    hipLaunchKernelGGL(k_bchol, dim3(1), dim3(64), 0, s, B, j, pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_bupdate(bool f32, const void* X0, int64_t xstride, int nx, void* Y, int accumulate,
+                          const BlockArgs& B, hipStream_t s) {
+    const int64_t tiles = (B.n + 15) / 16;
+    const int64_t grid = (tiles + kBlock / 64 - 1) / (kBlock / 64);
+    if (grid > INT32_MAX) return hipErrorInvalidValue;
+    if (f32)
+        hipLaunchKernelGGL(k_bupdate<float>, dim3((unsigned)grid), dim3(kBlock), 0, s, static_cast<const float*>(X0),
+                           xstride, nx, static_cast<float*>(Y), accumulate, B);
+    else
+        hipLaunchKernelGGL(k_bupdate<double>, dim3((unsigned)grid), dim3(kBlock), 0, s,
+                           static_cast<const double*>(X0), xstride, nx, static_cast<double*>(Y), accumulate, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_bproj(bool f32, const SegTable& T, int32_t oset0, int o, const void* V, double* part, int G,
+                        int j, const BlockArgs& B, hipStream_t s) {
+    const dim3 grid(o, G);
+    if (f32)
+        hipLaunchKernelGGL(k_bproj<float>, grid, dim3(kBlock), 0, s, T, oset0, static_cast<const float*>(V), part, B);
+    else
+        hipLaunchKernelGGL(k_bproj<double>, grid, dim3(kBlock), 0, s, T, oset0, static_cast<const double*>(V), part,
+                           B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bproj_red, dim3(1), dim3(128), 0, s, part, o, G, j, B);
+    return hipGetLastError();
+}
+
+}  // namespace kry

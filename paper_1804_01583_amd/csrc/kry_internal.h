@@ -136,6 +136,68 @@ struct ArnArgs {
 };
 constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
 
+// ---- block Arnoldi (kry_block.hip) ------------------------------------------
+constexpr int kBW = 16;          // block width: p <= 16 real columns, the rest zero
+constexpr int kMaxKB = 32;       // block steps (Krylov dimension 16 k <= 512)
+
+struct BlockStart {
+    int32_t set[kBW];            // segment set of generator column c (c < p)
+    int32_t p;
+};
+
+struct BlockArgs {
+    int64_t n;
+    int32_t p;                   // real columns of this block run
+    int32_t rb;                  // row blocks of the Gram kernel
+    int64_t rows_per_rb;         // rows per row block
+    double* gpart;               // [kMaxKB + 1][rb][256] partials of 16 x 16 products
+    double* coef;                // [kMaxKB + 1][256] reduced blocks / update coefficients
+    double* H;                   // block Hessenberg, row-major, ldh columns
+    int32_t ldh;
+    double* P;                   // C V, o rows of ldp
+    int32_t ldp;
+    double* R0;                  // 16 x 16: G = V_1 R0
+    double* rfirst;              // 16 x 16: R of the first CholQR pass
+    int32_t* state;              // [0] done, [1] blocks formed, [2] non-finite
+    const double* anorm;         // ||A||_inf on the device
+    double tau_scale;            // breakdown when R_cc <= tau_scale * ||A||_inf
+};
+
+hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void* V, int64_t n, hipStream_t s);
+hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, const BlockArgs& B, hipStream_t s);
+hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
+                        hipStream_t s);
+// mode 0 / 1: Gram-Schmidt pass 1 / 2 of block column j; mode 2: Gram matrix
+hipError_t launch_bgram_red(const BlockArgs& B, int nx, int j, int mode, hipStream_t s);
+hipError_t launch_bchol(const BlockArgs& B, int j, int pass, hipStream_t s);
+hipError_t launch_bupdate(bool f32, const void* X0, int64_t xstride, int nx, void* Y, int accumulate,
+                          const BlockArgs& B, hipStream_t s);
+hipError_t launch_bproj(bool f32, const SegTable& T, int32_t oset0, int o, const void* V, double* part, int G,
+                        int j, const BlockArgs& B, hipStream_t s);
+
+// ---- dense stage for large Krylov dimensions (kry_dense.hip) --------------
+struct DenseJob {
+    const double* H;             // m x m (row-major, ldh)
+    int32_t ldh;
+    int32_t m;
+    double dt;
+    const double* P;             // o x m (ldp)
+    int32_t ldp;
+    int32_t o;
+    const double* S0;            // m x w start coefficients (lds0)
+    int32_t lds0;
+    int32_t w;
+    int32_t B, nanch;            // steps s = b B + r
+    int64_t steps;
+    double* basis;               // [(steps+1)][o][nruns]
+    int32_t nruns, run0;
+};
+size_t dense_workspace_doubles(int m, int o, int w, int B, int nanch);
+// Enqueues the whole stage; waits once for |H|_1 (the number of squarings).
+hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+
 // ---- launchers (kry_lanczos.hip, kry_expm.hip) ----------------------------
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
                               int64_t rows_per_block, double* out, hipStream_t s);

@@ -3,7 +3,7 @@ every step of the verification path runs in the library's HIP kernels.
 
 The functions keep the C names (kry_plan_create, kry_project_expm,
 kry_check_box_safety, kry_footprint, kry_plan_runs, kry_plan_krylov,
-kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
+kry_plan_block, kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
 tensors a plan borrows alive and destroys the plan when it is dropped.
 """
 from __future__ import annotations
@@ -57,6 +57,10 @@ class KryVerdict(ct.Structure):
 
 
 def _load():
+    # torch ships its own HIP runtime; load it first so libkry.so binds to the
+    # same runtime instance (two instances in one process do not share devices)
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_1804_01583_amd.build`")
     lib = ct.CDLL(LIB_PATH)
@@ -71,6 +75,8 @@ def _load():
     lib.kry_plan_runs.argtypes = [P, ct.POINTER(ct.c_int32), P]
     lib.kry_plan_krylov.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double), P,
                                     ct.POINTER(ct.c_double), P]
+    lib.kry_plan_block.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                                   ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_plan_destroy.argtypes = [P]
     lib.kry_plan_destroy.restype = None
     lib.kry_last_error.restype = ct.c_char_p
@@ -78,7 +84,7 @@ def _load():
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
     for f in ("kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
-              "kry_plan_runs", "kry_plan_krylov", "kry_profile_enable", "kry_profile_reset",
+              "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_profile_enable", "kry_profile_reset",
               "kry_profile_read"):
         getattr(lib, f).restype = ct.c_int
     return lib
@@ -87,7 +93,7 @@ def _load():
 lib = _load()
 
 EXPORTED = ["kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
-            "kry_plan_runs", "kry_plan_krylov", "kry_plan_destroy", "kry_last_error",
+            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
 
 
@@ -162,6 +168,23 @@ def kry_plan_krylov(plan: int, run: int, k: int, o: int):
     m = keff.value
     return {"k_eff": m, "beta0": beta0.value, "H": H[:m * m].reshape(m, m).copy(),
             "h_next": hn.value, "P": P[:o * m].reshape(o, m).copy()}
+
+
+def kry_plan_block(plan: int, block: int, o: int):
+    """Block run `block` of a block Arnoldi plan: k_eff, p, H, R0, P (or the
+    number of block runs when block < 0)."""
+    nb, keff, pp = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(lib.kry_plan_block(plan, -1, ct.byref(nb), None, None, None, None, None))
+    if block < 0:
+        return nb.value
+    _check(lib.kry_plan_block(plan, block, None, ct.byref(keff), ct.byref(pp), None, None, None))
+    m = keff.value * pp.value
+    H = np.zeros(max(m * m, 1))
+    R0 = np.zeros(max(pp.value * pp.value, 1))
+    Pm = np.zeros(max(o * m, 1))
+    _check(lib.kry_plan_block(plan, block, None, None, None, H.ctypes.data, R0.ctypes.data, Pm.ctypes.data))
+    return {"k_eff": keff.value, "p": pp.value, "H": H[:m * m].reshape(m, m).copy(),
+            "R0": R0[:pp.value ** 2].reshape(pp.value, pp.value).copy(), "P": Pm[:o * m].reshape(o, m).copy()}
 
 
 def kry_plan_destroy(plan: int):
@@ -301,6 +324,10 @@ class Plan:
 
     def krylov(self, run: int):
         return kry_plan_krylov(self.handle, run, self.k, self.o)
+
+    def blocks(self):
+        """Block Arnoldi plans: one dict per block run (see kry_plan_block)."""
+        return [kry_plan_block(self.handle, b, self.o) for b in range(kry_plan_block(self.handle, -1, self.o))]
 
     def close(self):
         if self.handle:
