@@ -18,6 +18,8 @@ Prints one JSON line.  Options:
                   heat1d, conv_diff3d
   --precision P   fp64 (default) or fp32 (FP32-basis mode; the FP64 path is then
                   timed too, for the ratio to plain FP64)
+  --method M      auto (Lanczos / Arnoldi by symmetry) or block (block Arnoldi,
+                  the default for conv_diff3d: 16 generators as one p = 16 block)
   --calib-copy    run a plain device copy of known size (for counter calibration) and exit
 """
 from __future__ import annotations
@@ -58,6 +60,7 @@ def main():
                     choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d"],
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--method", default=None, choices=["auto", "block"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
@@ -83,15 +86,17 @@ def main():
     elif args.workload == "heat1d":
         p = W.heat1d()
     else:
-        p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=2, o=5, k=30)
+        p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=16, o=5, k=30)
+    method_name = args.method or ("block" if args.workload == "conv_diff3d" else "auto")
+    method = kry.KRY_BLOCK_ARNOLDI if method_name == "block" else kry.KRY_AUTO
     dsys = kry.DeviceSystem(p, device="cuda")
     f32 = args.precision == "fp32"
-    m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup)
+    m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
         log("plain FP64 on the same workload, for the ratio")
-        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup)
+        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup, method)
         fp64_ref = {"value": m64["value"], "ms_per_step": m64["ms_per_step"],
                     "ratio_fp32_over_fp64": m["value"] / m64["value"]}
     kern, nruns, verdict = m["kern"], m["nruns"], m["verdict"]
@@ -121,9 +126,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if not f32 else "f32-storage/f64-arith",
         "data": "synthetic",
-        "config": {"workload": describe(p, nruns, args.precision), "n": n, "nnz": nnz, "k": p.k,
+        "config": {"workload": describe(p, nruns, args.precision, method_name), "n": n, "nnz": nnz, "k": p.k,
                    "time_steps": p.steps, "runs": nruns, "precision": args.precision,
-                   "method": "lanczos" if p.symmetric else "arnoldi"},
+                   "method": "block_arnoldi" if method_name == "block" else
+                             ("lanczos" if p.symmetric else "arnoldi")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom_name,
                      "bytes_per_launch": dom.get("bytes")},
@@ -136,13 +142,13 @@ def main():
     print(json.dumps(out))
 
 
-def measure(torch, kry, p, dsys, precision, steps, warmup):
+def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
     """Times `steps` whole verifications (after `warmup`), then the same with
     per-kernel HIP events; returns the throughput and per-kernel figures."""
     stream = torch.cuda.current_stream()
 
     def step():
-        plan = kry.Plan(dsys, stream=stream, precision=precision)
+        plan = kry.Plan(dsys, stream=stream, precision=precision, method=method)
         plan.project_expm(None)
         v = plan.check(p.unsafe)
         nr = plan.nruns
@@ -201,6 +207,32 @@ def measure(torch, kry, p, dsys, precision, steps, warmup):
         if name in kern:
             kern[name]["bytes"] = b
             kern[name]["GBps"] = b / (kern[name]["avg_us"] * 1e-6) / 1e9
+    if method == kry.KRY_BLOCK_ARNOLDI:
+        # per whole block run: bytes each kernel must move, summed over its
+        # launches (16-wide blocks of es-byte entries, n rows)
+        blk = 16 * es * n
+        tot = {"bspmm": 0.0, "bgram": 0.0, "bupdate": 0.0, "bstart": blk}
+        tot["bgram"] += 2 * blk                      # start block CholQR2: Gram of V_1
+        tot["bupdate"] += 2 * 2 * blk                # and V_1 R^{-1} in place
+        for j in range(1, k + 1):
+            tot["bspmm"] += mat + 2 * blk            # A, V_j streamed once, W written
+            for ps in (1, 2):
+                tot["bgram"] += (j + 1) * blk        # V_1..V_j and W
+                if j < k or ps == 1:
+                    tot["bupdate"] += (j + 2) * blk  # V_1..V_j, W read, W written
+            if j < k:
+                tot["bgram"] += 2 * blk
+                tot["bupdate"] += 2 * 2 * blk
+        nblk = -(-len(p.gens) // 16)
+        for name, b in tot.items():
+            if name in kern:
+                kern[name]["bytes"] = b * nblk / max(kern[name]["launches"] / steps, 1)
+                kern[name]["GBps"] = kern[name]["bytes"] / (kern[name]["avg_us"] * 1e-6) / 1e9
+        dom_name = max((n_ for n_ in ("bgram", "bupdate", "bspmm") if n_ in kern),
+                       key=lambda n_: kern[n_]["total_ms_per_step"])
+        return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
+                "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
+                "dom_name": dom_name}
     mv = "spmv_csr" if p.kind == "csr" else "spmv_stencil"
     # the roofline kernel: the mat-vec, or the one with the most time when a
     # stored-basis pass outweighs it
@@ -213,8 +245,13 @@ def measure(torch, kry, p, dsys, precision, steps, warmup):
             "dom_name": dom_name}
 
 
-def describe(p, nruns, precision):
+def describe(p, nruns, precision, method_name="auto"):
     prec = "FP64" if precision == "fp64" else "FP32 basis (FP64 sums), full reorthogonalisation"
+    if p.name == "conv_diff3d":
+        g = p.meta["grid"]
+        meth = "block Arnoldi p=16" if method_name == "block" else "Arnoldi"
+        return (f"3D convection-diffusion {g[0]}x{g[1]}x{g[2]} CSR (n={p.n}, nnz={p.nnz}, nonsymmetric), "
+                f"{len(p.gens)} generators, {meth}, k={p.k}, dt={p.dt}, {p.steps} steps, o={p.o}, {prec}")
     if p.name == "heat3d_csr":
         m = p.meta["m"]
         return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "

@@ -220,7 +220,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.anorm = take(sizeof(double));
     if (method == KRY_BLOCK_ARNOLDI) {
         Y.bw = block_p;
-        Y.brb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(512, (n + 63) / 64));
+        Y.brb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 63) / 64));
         Y.brows = (int64_t)align_up((size_t)((n + Y.brb - 1) / Y.brb), 4);
         const int64_t m = (int64_t)kBW * k;
         Y.bvec = take((size_t)(k + 1) * n * kBW * Y.esize);

@@ -58,9 +58,11 @@ __global__ __launch_bounds__(kBlock) void k_bstart(SegTable T, BlockStart S, E* 
     }
 }
 
-// W = A V_j: a group of 16 lanes owns a row, lane c its column c; the CSR
-// entries of the row are read by all 16 lanes (one cache line), the gathered
-// row of V_j is one contiguous 16-value load.
+// W = A V_j: a group of 16 lanes owns a row, lane c its column c.  The
+// group reads up to 16 CSR entries of the row at once (one per lane) and
+// passes them round by shuffles, so all 16 gathers of V_j rows (each one
+// contiguous 16-value row) are in flight together; slots past the row's end
+// carry value 0 and column 0.
 template <typename E>
 __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict__ V, E* __restrict__ W, int64_t n,
                                                   BlockArgs B) {
@@ -71,10 +73,20 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict
     for (int64_t r = (int64_t)blockIdx.x * (kBlock / 16) + grp; r < n; r += stride) {
         const int64_t e0 = A.rowptr[r], e1 = A.rowptr[r + 1];
         double acc = 0.0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t col = A.colidx[e];
-            const double a = sizeof(E) == 4 ? (double)A.vals32[e] : A.vals[e];
-            acc = fma(a, (double)V[col * kBW + c], acc);
+        for (int64_t eb = e0; eb < e1; eb += 16) {
+            const int64_t e = eb + c;
+            const bool ok = e < e1;
+            const int32_t mycol = ok ? A.colidx[e] : 0;
+            const double myval = ok ? (sizeof(E) == 4 ? (double)A.vals32[e] : A.vals[e]) : 0.0;
+            double x[16], a[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int32_t col = __shfl(mycol, q, 16);
+                a[q] = __shfl(myval, q, 16);
+                x[q] = (double)V[(int64_t)col * kBW + c];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc = fma(a[q], x[q], acc);
         }
         W[r * kBW + c] = (E)acc;
     }
@@ -82,11 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict
 
 // Partials of X_i^T Y, i < nx, over the rows of row block blockIdx.x.  Wave
 // w of the workgroup owns i = w, w + 4, ... (NI of them at most), so a row of
-// Y is fetched from memory once per workgroup; each MFMA consumes 4 rows.
-// Rows past the block's end read row r0 and are multiplied by zero.
+// Y is fetched from memory once per workgroup; each MFMA consumes 4 rows and
+// an iteration issues the loads of RS MFMA steps before using them.  Slots
+// past nx re-read X_{nx-1} and are never stored; rows past the block's end
+// read row r0 and are multiplied by zero.
 template <typename E, int NI>
 __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int64_t xstride, int nx,
                                                   const E* __restrict__ Y, BlockArgs B) {
+    constexpr int RS = NI <= 4 ? 4 : 2;
     if (block_done(B)) return;
     const int l = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -96,19 +111,30 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
     v4d acc[NI];
 #pragma unroll
     for (int u = 0; u < NI; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int64_t r = r0; r < r1; r += 4) {
-        const int64_t row = r + sub;
-        const bool ok = row < r1;
-        const int64_t rr = ok ? row : r0;
-        const double yv = (double)Y[rr * kBW + col];
-        const double b = ok ? yv : 0.0;
+    const E* Xu[NI];
+#pragma unroll
+    for (int u = 0; u < NI; ++u) Xu[u] = X0 + (int64_t)min(wave + 4 * u, nx - 1) * xstride;
+    for (int64_t r = r0; r < r1; r += 4 * RS) {
+        int64_t rr[RS];
+        bool ok[RS];
+        double yb[RS], xa[NI][RS];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const int64_t row = r + 4 * q + sub;
+            ok[q] = row < r1;
+            rr[q] = ok[q] ? row : r0;
+            yb[q] = (double)Y[rr[q] * kBW + col];
+        }
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
-            const int i = wave + 4 * u;
-            if (i < nx) {                              // uniform per wave
-                const double a = (double)X0[(int64_t)i * xstride + rr * kBW + col];
-                acc[u] = mfma16(ok ? a : 0.0, b, acc[u]);
-            }
+#pragma unroll
+            for (int q = 0; q < RS; ++q) xa[u][q] = (double)Xu[u][rr[q] * kBW + col];
+        }
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const double b = ok[q] ? yb[q] : 0.0;
+#pragma unroll
+            for (int u = 0; u < NI; ++u) acc[u] = mfma16(xa[u][q], b, acc[u]);
         }
     }
 #pragma unroll
@@ -121,15 +147,25 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
     }
 }
 
-// Sums the row-block partials of block i = blockIdx.x (thread t = entry t of
-// the 16 x 16 result) in a fixed order.  mode 0/1: Gram-Schmidt pass 1/2,
-// H_{i,j} = / += result and coef_i = -result; mode 2: Gram matrix into coef_0.
+// Sums the row-block partials of block i = blockIdx.x, entries
+// 16 blockIdx.y .. 16 blockIdx.y + 15: 16 threads per entry take every 16th
+// row block, then their sums are added in order.  mode 0/1: Gram-Schmidt
+// pass 1/2, H_{i,j} = / += result and coef_i = -result; mode 2: Gram matrix
+// into coef_0.
 __global__ __launch_bounds__(256) void k_bgram_red(BlockArgs B, int j, int mode) {
     if (block_done(B)) return;
-    const int i = blockIdx.x, t = threadIdx.x;
+    __shared__ double s_sum[256];
+    const int i = blockIdx.x;
+    const int t = blockIdx.y * 16 + (threadIdx.x & 15);
+    const int chunk = threadIdx.x >> 4;
     const double* part = B.gpart + (int64_t)i * B.rb * 256;
     double s = 0.0;
-    for (int b = 0; b < B.rb; ++b) s += part[(int64_t)b * 256 + t];
+    for (int b = chunk; b < B.rb; b += 16) s += part[(int64_t)b * 256 + t];
+    s_sum[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x >= 16) return;
+    s = 0.0;
+    for (int c = 0; c < 16; ++c) s += s_sum[c * 16 + threadIdx.x];
     if (mode == 2) {
         B.coef[t] = s;
         return;
@@ -141,46 +177,59 @@ __global__ __launch_bounds__(256) void k_bgram_red(BlockArgs B, int j, int mode)
     B.coef[(int64_t)i * 256 + t] = -s;
 }
 
-// CholQR step on the Gram matrix G = W^T W in coef_0 (one thread; 16 x 16):
-// G = R^T R with R upper triangular and a positive diagonal; padded columns
-// (c >= p) get R_cc = 1.  coef_0 <- R^{-1} for the in-place W R^{-1}.
+// CholQR step on the Gram matrix G = W^T W in coef_0 (one wave, 16 x 16 in
+// LDS): G = R^T R with R upper triangular and a positive diagonal; padded
+// columns (c >= p) get R_cc = 1.  coef_0 <- R^{-1} for the in-place W R^{-1}.
 // pass 1 also decides breakdown: a diagonal R_cc <= tau ends the run before
 // block j + 1 (or, for the start block j = 0, marks it rank deficient).
 // pass 2 writes H_{j+1,j} = R2 R1 (start block: R0 = R2 R1).
 __global__ __launch_bounds__(64) void k_bchol(BlockArgs B, int j, int pass) {
-    if (block_done(B) || threadIdx.x != 0) return;
-    double G[16][16], R[16][16], Ri[16][16];
-    for (int a = 0; a < 16; ++a)
-        for (int b = 0; b < 16; ++b) { G[a][b] = B.coef[a * 16 + b]; R[a][b] = 0.0; Ri[a][b] = 0.0; }
+    if (block_done(B)) return;
+    __shared__ double G[16][17], R[16][17], Ri[16][17];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 256; e += 64) {
+        G[e / 16][e % 16] = B.coef[e];
+        R[e / 16][e % 16] = 0.0;
+        Ri[e / 16][e % 16] = 0.0;
+    }
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
     // breakdown: R_cc <= 1024 eps ||A||_inf for a new block; for the start
     // block, R_cc <= 1024 eps max_c |g_c| (dependent generator columns)
     double gmax = 0.0;
     for (int c = 0; c < B.p; ++c) gmax = fmax(gmax, sqrt(fmax(G[c][c], 0.0)));
     const double tau = j == 0 ? B.tau_scale * gmax : B.tau_scale * *B.anorm;
-    bool bad = false, nonfinite = false;
     for (int c = 0; c < 16; ++c) {
-        if (c >= B.p) { R[c][c] = 1.0; continue; }
+        // every thread forms the pivot (same operations, same value)
         double d = G[c][c];
         for (int q = 0; q < c; ++q) d -= R[q][c] * R[q][c];
-        if (!isfinite(d)) nonfinite = true;
-        const double rc = d > 0.0 ? sqrt(d) : 0.0;
-        if (pass == 1 && !(rc > tau)) bad = true;
-        if (rc <= 0.0) { R[c][c] = 1.0; bad = true; continue; }
-        R[c][c] = rc;
-        for (int b = c + 1; b < B.p; ++b) {
-            double v = G[c][b];
-            for (int q = 0; q < c; ++q) v -= R[q][c] * R[q][b];
-            R[c][b] = v / rc;
+        const bool real = c < B.p;
+        const double rc = real ? (d > 0.0 ? sqrt(d) : 0.0) : 1.0;
+        if (tid == 0 && real) {
+            if (!isfinite(d)) s_bad = 2;
+            else if (!(rc > 0.0) || (pass == 1 && !(rc > tau))) s_bad = s_bad ? s_bad : 1;
         }
+        const double piv = rc > 0.0 ? rc : 1.0;
+        if (tid == c) R[c][c] = piv;
+        if (real && tid > c && tid < B.p) {
+            double v = G[c][tid];
+            for (int q = 0; q < c; ++q) v -= R[q][c] * R[q][tid];
+            R[c][tid] = v / piv;
+        }
+        __syncthreads();
     }
-    if (nonfinite) { B.state[2] = 1; bad = true; }
-    if (bad) {
-        B.state[0] = 1;
-        B.state[1] = j;            // blocks of the run (0: the start block itself is unusable)
+    if (s_bad) {
+        if (tid == 0) {
+            if (s_bad == 2) B.state[2] = 1;
+            B.state[0] = 1;
+            B.state[1] = j;        // blocks of the run (0: the start block itself is unusable)
+        }
         return;
     }
-    // upper-triangular inverse by back substitution, column by column
-    for (int c = 0; c < 16; ++c) {
+    // R^{-1}: thread c < 16 solves column c by back substitution
+    if (tid < 16) {
+        const int c = tid;
         Ri[c][c] = 1.0 / R[c][c];
         for (int a = c - 1; a >= 0; --a) {
             double v = 0.0;
@@ -188,23 +237,22 @@ __global__ __launch_bounds__(64) void k_bchol(BlockArgs B, int j, int pass) {
             Ri[a][c] = -v / R[a][a];
         }
     }
-    for (int a = 0; a < 16; ++a)
-        for (int b = 0; b < 16; ++b) B.coef[a * 16 + b] = Ri[a][b];
+    __syncthreads();
+    for (int e = tid; e < 256; e += 64) B.coef[e] = Ri[e / 16][e % 16];
     if (pass == 1) {
-        for (int a = 0; a < 16; ++a)
-            for (int b = 0; b < 16; ++b) B.rfirst[a * 16 + b] = R[a][b];
+        for (int e = tid; e < 256; e += 64) B.rfirst[e] = R[e / 16][e % 16];
         return;
     }
     // R_total = R2 R1 (both upper triangular)
     double* dst = j == 0 ? B.R0 : B.H + (int64_t)(16 * j) * B.ldh + 16 * (j - 1);
     const int64_t ld = j == 0 ? 16 : B.ldh;
-    for (int a = 0; a < 16; ++a)
-        for (int b = 0; b < 16; ++b) {
-            double v = 0.0;
-            for (int q = a; q <= b; ++q) v += R[a][q] * B.rfirst[q * 16 + b];
-            dst[a * ld + b] = (a < B.p && b < B.p) ? v : 0.0;
-        }
-    B.state[1] = j + 1;
+    for (int e = tid; e < 256; e += 64) {
+        const int a = e / 16, b = e % 16;
+        double v = 0.0;
+        for (int q = a; q <= b; ++q) v += R[a][q] * B.rfirst[q * 16 + b];
+        dst[a * ld + b] = (a < B.p && b < B.p) ? v : 0.0;
+    }
+    if (tid == 0) B.state[1] = j + 1;
 }
 
 // Y = (accumulate ? Y : 0) + sum_{i < nx} X_i M_i, M_i = coef_i (16 x 16).
@@ -356,7 +404,7 @@ hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const
 }
 
 hipError_t launch_bgram_red(const BlockArgs& B, int nx, int j, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_bgram_red, dim3(nx), dim3(256), 0, s, B, j, mode);
+    hipLaunchKernelGGL(k_bgram_red, dim3(nx, 16), dim3(256), 0, s, B, j, mode);
     return hipGetLastError();
 }
 
