@@ -162,6 +162,8 @@ struct Layout {
     size_t bvec = 0, bgpart = 0, bcoef = 0, bH = 0, bP = 0, bR0 = 0, brfirst = 0, bstate = 0, bppart = 0, bS0 = 0,
            bdense = 0;
     int32_t esize;        // bytes per stored vector element: 8 (FP64) or 4 (FP32 basis)
+    bool dense_runs = false;   // k > 56: each run's exponential in the dense stage
+    size_t dH = 0, dP = 0, dS0 = 0, dws = 0;
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     size_t hpart, hcoef, vals32;
 };
@@ -173,7 +175,9 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.nblocks = nblocks_for(n, Y.rpb);
     Y.march = march;
     Y.esize = precision == KRY_FP32_BASIS ? 4 : 8;
-    Y.stored = method == KRY_ARNOLDI || precision == KRY_FP32_BASIS;
+    // Lanczos keeps its basis and reorthogonalises when it stores FP32 vectors
+    // or runs past k = 56 (plain three-term Lanczos loses orthogonality there)
+    Y.stored = method == KRY_ARNOLDI || precision == KRY_FP32_BASIS || k > kMaxK;
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
     if (Y.stored) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
     {
@@ -199,8 +203,8 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     if (method == KRY_BLOCK_ARNOLDI) { Y.pmax = 1; Y.stored = false; }
     Y.nvec = method == KRY_BLOCK_ARNOLDI ? 0 : (Y.stored ? k + 1 : 3);
     Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
-    Y.hpart = Y.stored ? take((size_t)kMaxK * kMaxP * Y.nblocks * sizeof(double)) : 0;
-    Y.hcoef = Y.stored ? take((size_t)kMaxK * kMaxP * sizeof(double)) : 0;
+    Y.hpart = Y.stored ? take((size_t)k * kMaxP * Y.nblocks * sizeof(double)) : 0;
+    Y.hcoef = Y.stored ? take((size_t)k * kMaxP * sizeof(double)) : 0;
     Y.vals32 = nnz32 > 0 ? take((size_t)nnz32 * sizeof(float)) : 0;
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
@@ -210,8 +214,16 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.B = 1;
     while ((int64_t)Y.B * Y.B < steps + 1 && Y.B < 256) Y.B <<= 1;
     Y.nanch = (int32_t)((steps + 1 + Y.B - 1) / Y.B);
-    Y.zmat = take((size_t)nruns * Y.B * kMaxO * kMaxK * sizeof(double));
-    Y.anch = take((size_t)nruns * Y.nanch * kMaxK * sizeof(double));
+    // small exponential in LDS (k <= 56) or the dense stage, one run at a time
+    Y.dense_runs = method != KRY_BLOCK_ARNOLDI && k > kMaxK;
+    Y.zmat = Y.dense_runs ? 0 : take((size_t)nruns * Y.B * kMaxO * kMaxK * sizeof(double));
+    Y.anch = Y.dense_runs ? 0 : take((size_t)nruns * Y.nanch * kMaxK * sizeof(double));
+    if (Y.dense_runs) {
+        Y.dH = take((size_t)k * k * sizeof(double));
+        Y.dP = take((size_t)o * k * sizeof(double));
+        Y.dS0 = take((size_t)k * sizeof(double));
+        Y.dws = take(dense_workspace_doubles(k, o, 1, Y.B, Y.nanch) * sizeof(double));
+    }
     Y.msize = take((size_t)nruns * sizeof(int32_t));
     Y.scale = take((size_t)nruns * sizeof(double));
     Y.basis = take((size_t)(steps + 1) * o * nruns * sizeof(double));
@@ -419,9 +431,9 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (st != KRY_OK) return st;
     if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : kMaxK;
+    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : kMaxKD;
     if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kmax || steps < 0 || nseg_total < 0)
-        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 56 (32 block steps), steps >= 0, "
+        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 512 (32 block steps), steps >= 0, "
                                 "nseg_total >= 0 required");
     if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
     if (method == KRY_BLOCK_ARNOLDI) {
@@ -450,8 +462,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
     if (method == KRY_BLOCK_ARNOLDI) {
         if (k < 1 || k > kMaxKB) return fail(KRY_EINVAL, "block Arnoldi: k (block steps) must be in [1, 32]");
-    } else if (k < 1 || k > kMaxK) {
-        return fail(KRY_EINVAL, "k must be in [1, 56]");
+    } else if (k < 1 || k > kMaxKD) {
+        return fail(KRY_EINVAL, "k must be in [1, 512]");
     }
     if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
@@ -879,6 +891,43 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     E.hess_mode = plan->hess_mode ? 1 : 0;
     E.B = Y.B;
     E.nanch = Y.nanch;
+    if (Y.dense_runs) {
+        // sizes of the runs' matrices decide the dense stage's shapes
+        std::vector<double> sc((size_t)plan->nruns * Y.L.stride);
+        KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal(), sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        KRY_HIP(hipStreamSynchronize(s));
+        for (int32_t run = 0; run < plan->nruns; ++run) {
+            const int keff = (int)sc[(size_t)run * Y.L.stride + Y.L.misc + MISC_KEFF];
+            const bool bordered = plan->role[run] == 2;
+            int m = bordered ? std::min(keff, plan->k - 1) + 1 : keff;
+            if (keff <= 0) m = 0;
+            hipError_t e = hipSuccess;
+            if (m > 0) e = launch_build_dense(E, run, m, plan->at<double>(Y.dH), plan->at<double>(Y.dP),
+                                              plan->at<double>(Y.dS0), s);
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("build_dense: ") + hipGetErrorString(e));
+            DenseJob J{};
+            J.H = plan->at<double>(Y.dH);
+            J.ldh = m;
+            J.m = m;
+            J.dt = plan->dt;
+            J.P = plan->at<double>(Y.dP);
+            J.ldp = m;
+            J.o = plan->o;
+            J.S0 = plan->at<double>(Y.dS0);
+            J.lds0 = 1;
+            J.w = 1;
+            J.B = Y.B;
+            J.nanch = Y.nanch;
+            J.steps = plan->steps;
+            J.basis = plan->basis();
+            J.nruns = plan->nruns;
+            J.run0 = run;
+            double hn = 0.0;
+            e = timed("dense_expm", s, [&] { return dense_expm_steps(J, plan->at<double>(Y.dws), &hn, s); });
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("dense stage: ") + hipGetErrorString(e));
+        }
+        return finish_projection(plan, basis_out);
+    }
     pade13(E.pade);
     E.Z = plan->zmat();
     E.anch = plan->anch();

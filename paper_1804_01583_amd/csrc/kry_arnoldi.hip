@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_arn_update(SegTable T, int32_t oset0
                                                        int last) {
     constexpr int NV = P * (1 + O);
     __shared__ double s_lds[(kBlock / 64) * NV];
-    __shared__ double s_c[kMaxK * P];
+    __shared__ double s_c[kMaxKD * P];
     __shared__ SegStage<O> st;
     const int lb = logical_block(B.nblocks, B.xcd_map);
     const int64_t r0 = (int64_t)lb * B.rows_per_block;

@@ -145,6 +145,49 @@ __global__ __launch_bounds__(256) void k_fill_i32(int32_t* p, int64_t count, int
 }
 }  // namespace
 
+namespace {
+// The same H, P and start scale as k_expm_chain forms in LDS (tridiagonal from
+// alpha/beta for Lanczos, Hessenberg store for a stored basis, bordered by
+// the augmented variable for the affine run).
+__global__ __launch_bounds__(256) void k_build_dense(ExpmArgs E, int run, int m, double* __restrict__ H,
+                                                     double* __restrict__ P, double* __restrict__ S0) {
+    const double* sc = E.scal + (int64_t)run * E.L.stride;
+    const int k = E.L.k, o = E.L.o;
+    const bool bordered = E.role[run] == 2;
+    const int sh = bordered ? 1 : 0;
+    for (int idx = threadIdx.x + blockIdx.x * 256; idx < m * m; idx += gridDim.x * 256) {
+        const int i = idx / m, c = idx % m;
+        double h = 0.0;
+        if (bordered && i == 1 && c == 0) h = sc[E.L.beta + 0];
+        else if (i >= sh && c >= sh) {
+            const int a = i - sh, b = c - sh;
+            if (E.hess_mode) {
+                if (a <= b) h = sc[E.L.hess + a * k + b];
+                else if (a == b + 1) h = sc[E.L.beta + b + 1];
+            } else {
+                if (a == b) h = sc[E.L.alpha + a + 1];
+                else if (b == a + 1) h = sc[E.L.beta + a + 1];
+                else if (a == b + 1) h = sc[E.L.beta + b + 1];
+            }
+        }
+        H[idx] = h;
+    }
+    for (int idx = threadIdx.x + blockIdx.x * 256; idx < o * m; idx += gridDim.x * 256) {
+        const int q = idx / m, c = idx % m;
+        const int col = c - sh;
+        P[idx] = col >= 0 ? sc[E.L.proj + q * (k + 1) + col] : 0.0;
+    }
+    for (int idx = threadIdx.x + blockIdx.x * 256; idx < m; idx += gridDim.x * 256)
+        S0[idx] = idx == 0 ? (bordered ? 1.0 : sc[E.L.beta + 0]) : 0.0;
+}
+}  // namespace
+
+hipError_t launch_build_dense(const ExpmArgs& E, int run, int m, double* H, double* P, double* S0, hipStream_t s) {
+    if (m <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_dense, dim3(grid_for((int64_t)m * m)), dim3(256), 0, s, E, run, m, H, P, S0);
+    return hipGetLastError();
+}
+
 // plain fill kernels (not memset nodes, so the work stays capturable)
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -164,7 +207,13 @@ size_t dense_workspace_doubles(int m, int o, int w, int B, int nanch) {
 
 hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hipStream_t s) {
     const int m = J.m;
-    if (m <= 0) return hipErrorInvalidValue;
+    if (J.o * J.w > 128) return hipErrorInvalidValue;
+    if (m <= 0) {
+        // a run with a zero start vector: its basis columns are zero
+        hipLaunchKernelGGL(k_dassemble, dim3((unsigned)(J.steps + 1)), dim3(128), 0, s, ws, ws, 0, J.o, J.w, J.B,
+                           J.steps, J.basis, J.nruns, J.run0);
+        return hipGetLastError();
+    }
     const int64_t mm = (int64_t)m * m;
     double* X = ws;
     double* X2 = X + mm;

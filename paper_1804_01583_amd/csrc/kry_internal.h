@@ -10,7 +10,8 @@ namespace kry {
 
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kMaxO = 8;         // output rows
-constexpr int kMaxK = 56;        // Krylov dimension (six k x k matrices held in LDS)
+constexpr int kMaxK = 56;        // Krylov dimension of the one-workgroup LDS exponential
+constexpr int kMaxKD = 512;      // Krylov dimension with the dense stage (k > kMaxK)
 constexpr int kExpmThreads = 512;
 constexpr int kMaxP = 8;         // runs advanced per mat-vec launch
 constexpr int kMaxNV = 24;       // values reduced per block: P * (1 + O)
@@ -129,8 +130,8 @@ struct ArnArgs {
     const void* V;           // u_1 .. u_j (j = iteration), each [n][P]
     int64_t vstride;         // elements from u_i to u_{i+1} (n * the plan's largest batch)
     void* w;                 // vector being orthogonalised ([n][P]), u_{j+1} once swept
-    double* hpart;           // [kMaxK][kMaxP][nblocks] partials of u_i . w
-    double* hcoef;           // [kMaxK][kMaxP] coefficients of the current pass (h_i * sigma_i)
+    double* hpart;           // [k][kMaxP][nblocks] partials of u_i . w
+    double* hcoef;           // [k][kMaxP] coefficients of the current pass (h_i * sigma_i)
     int32_t f32;             // 1: E = float, else double
     int32_t lanczos;         // 1: w is a Lanczos three-term result; H_{j-1,j} and H_{j,j} add beta_{j-1}, alpha_j
 };
@@ -195,6 +196,9 @@ struct DenseJob {
 size_t dense_workspace_doubles(int m, int o, int w, int B, int nanch);
 // Enqueues the whole stage; waits once for |H|_1 (the number of squarings).
 hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hipStream_t s);
+// H (m x m), P (o x m) and S0 = scale e_1 (m) of one single-vector run for
+// the dense stage, laid out as the LDS exponential assembles them.
+hipError_t launch_build_dense(const ExpmArgs& E, int run, int m, double* H, double* P, double* S0, hipStream_t s);
 hipError_t launch_fill(double* p, int64_t count, double v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 

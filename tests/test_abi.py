@@ -68,7 +68,8 @@ def test_footprint_is_host_only_and_scales_with_n():
     assert big - small <= 4 * 2 * 8 * (1_000_000 - 10_000) + (1 << 20)
 
 
-@pytest.mark.parametrize("bad", ["n", "k", "o", "steps", "dt", "seg_order", "seg_range", "nonsym", "precision"])
+@pytest.mark.parametrize("bad", ["n", "k", "k_big", "o", "steps", "dt", "seg_order", "seg_range", "nonsym",
+                                 "precision"])
 def test_plan_rejects_bad_arguments(bad):
     from paper_1804_01583_amd import kry
     import workloads as W
@@ -81,6 +82,8 @@ def test_plan_rejects_bad_arguments(bad):
         s.n = 0
     elif bad == "k":
         k = 0
+    elif bad == "k_big":
+        k = 513
     elif bad == "o":
         C = [W.segments_from_ranges([(5, 9)])] * 9
     elif bad == "steps":
