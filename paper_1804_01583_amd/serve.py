@@ -1,0 +1,210 @@
+"""Serving loop: a stream of verification queries on one GPU.
+
+Queries arrive over time (each a set of box generators, output rows, an
+unsafe threshold, a time grid and a precision against one of the resident
+systems).  The server
+
+* admits a waiting query, oldest first, as soon as a slot is free and the
+  HBM budget covers its plan's workspace (kry_footprint),
+* runs admitted queries concurrently, each on its own HIP stream, so their
+  kernels overlap on the device (a query's generators are already advanced
+  together by every mat-vec launch of its plan),
+* keeps every plan's basis and state on the device until its verdict is
+  read, and records arrival -> verdict latency.
+
+A query's result does not depend on what runs beside it: every kernel's
+arithmetic and reduction order depend only on the query's own sizes.
+
+Systems are resident: a catalog holds one device copy per (family, grid)
+and queries borrow them.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import deque
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import kry
+
+
+class Catalog:
+    """Device-resident systems keyed by (family, m), built on first use."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self._systems: Dict[Tuple[str, int], "kry.DeviceSystem"] = {}
+        self._lock = threading.Lock()
+
+    def get(self, family: str, m: int):
+        import workloads as W
+        key = (family, m)
+        with self._lock:
+            if key not in self._systems:
+                self._systems[key] = kry.DeviceSystem(W.serving_system(family, m), device=self.device)
+            return self._systems[key]
+
+    def preload(self, queries):
+        import torch
+        for q in queries:
+            self.get(q.family, q.m)
+        torch.cuda.synchronize(self.device)
+
+    def resident_bytes(self) -> int:
+        total = 0
+        for ds in self._systems.values():
+            for name in ("rowptr", "colidx", "vals", "b", "center"):
+                t = getattr(ds, name, None)
+                if t is not None:
+                    total += t.numel() * t.element_size()
+        return total
+
+
+@dataclass
+class Result:
+    qid: int
+    arrival: float
+    admitted: float
+    done: float
+    verdict: dict
+    footprint: int
+    verified_steps: int
+    basis: Optional[np.ndarray] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class _Pending:
+    query: object
+    footprint: int
+    released: float
+
+
+class Server:
+    """slots: queries in flight at once; budget_bytes: HBM for their plans.
+    ``runner(query, slot, keep_basis) -> (verdict, basis, runs)`` and
+    ``footprint(query) -> bytes`` default to the GPU plan and kry_footprint;
+    other ones serve for testing the scheduling on the host."""
+
+    def __init__(self, catalog: Optional[Catalog], slots: int = 8, budget_bytes: int = 200 << 30,
+                 runner=None, footprint=None):
+        self.catalog = catalog
+        self.slots = slots
+        self.budget = budget_bytes
+        self._runner = runner
+        self._footprint = footprint
+
+    def footprint(self, q) -> int:
+        if self._footprint is not None:
+            return self._footprint(q)
+        dsys = self.catalog.get(q.family, q.m)
+        prec = kry.KRY_FP32_BASIS if q.precision == "fp32" else kry.KRY_FP64
+        nseg = sum(g.seg.nseg for g in q.gens) + sum(c.nseg for c in q.C)
+        return kry.kry_footprint(dsys.sys, len(q.gens), len(q.C), q.k, q.steps, nseg, prec, kry.KRY_AUTO, 0)
+
+    def _run_one(self, q, stream, keep_basis: bool):
+        import torch
+        dsys = self.catalog.get(q.family, q.m)
+        prec = kry.KRY_FP32_BASIS if q.precision == "fp32" else kry.KRY_FP64
+        with torch.cuda.stream(stream):
+            plan = kry.Plan(dsys, k=q.k, dt=q.dt, steps=q.steps, precision=prec, stream=stream, gens=q.gens, C=q.C)
+            out = None
+            if keep_basis:
+                out = torch.empty((q.steps + 1, len(q.C), plan.nruns), dtype=torch.float64, device=dsys.device)
+            plan.project_expm(out)
+            verdict = plan.check(q.unsafe)          # waits for this stream only
+            basis = out.cpu().numpy() if keep_basis else None
+            runs = plan.nruns
+            plan.close()
+        return verdict, basis, runs
+
+    def serve(self, queries, keep_basis: bool = False, time_scale: float = 1.0) -> List[Result]:
+        """Plays the queries at their arrival times (times time_scale) and
+        returns one Result per query, in query order."""
+        order = sorted(queries, key=lambda q: q.arrival)
+        pending: deque = deque()
+        results: Dict[int, Result] = {}
+        errors: List[BaseException] = []
+        cond = threading.Condition()
+        state = {"in_use": 0, "dispatched": False}
+        if self._runner is None:
+            import torch
+            streams = [torch.cuda.Stream(device=self.catalog.device) for _ in range(self.slots)]
+            run = lambda q, slot, keep: self._run_one(q, streams[slot], keep)   # noqa: E731
+        else:
+            run = self._runner
+        t0 = time.perf_counter()
+
+        def dispatcher():
+            try:
+                for q in order:
+                    if errors:
+                        break
+                    fp = self.footprint(q)
+                    wait = t0 + q.arrival * time_scale - time.perf_counter()
+                    if wait > 0:
+                        time.sleep(wait)
+                    with cond:
+                        pending.append(_Pending(q, fp, time.perf_counter() - t0))
+                        cond.notify_all()
+            finally:
+                with cond:
+                    state["dispatched"] = True
+                    cond.notify_all()
+
+        def worker(slot):
+            while True:
+                with cond:
+                    while True:
+                        if errors:
+                            return
+                        if pending and (state["in_use"] + pending[0].footprint <= self.budget
+                                        or state["in_use"] == 0):
+                            item = pending.popleft()
+                            state["in_use"] += item.footprint
+                            break
+                        if state["dispatched"] and not pending:
+                            return
+                        cond.wait()
+                admitted = time.perf_counter() - t0
+                try:
+                    verdict, basis, runs = run(item.query, slot, keep_basis)
+                except BaseException as e:  # noqa: BLE001 - surfaced after the threads stop
+                    with cond:
+                        errors.append(e)
+                        state["in_use"] -= item.footprint
+                        cond.notify_all()
+                    return
+                done = time.perf_counter() - t0
+                q = item.query
+                with cond:
+                    state["in_use"] -= item.footprint
+                    results[q.qid] = Result(q.qid, q.arrival * time_scale, admitted, done, verdict, item.footprint,
+                                            (q.steps + 1) * runs, basis)
+                    cond.notify_all()
+
+        threads = [threading.Thread(target=worker, args=(s,), daemon=True) for s in range(self.slots)]
+        for t in threads:
+            t.start()
+        dispatcher()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+        return [results[q.qid] for q in queries]
+
+
+def summarize(results: List[Result]) -> dict:
+    lat = np.array([r.latency for r in results])
+    span = max(r.done for r in results) - min(r.arrival for r in results)
+    steps = sum(r.verified_steps for r in results)
+    return {"queries": len(results), "p50_ms": 1000.0 * float(np.percentile(lat, 50)),
+            "p99_ms": 1000.0 * float(np.percentile(lat, 99)), "max_ms": 1000.0 * float(lat.max()),
+            "verified_steps_per_s": steps / span if span > 0 else float("nan"), "span_s": span,
+            "unsafe": int(sum(r.verdict["first_step"] >= 0 for r in results))}

@@ -1,0 +1,91 @@
+"""Scheduling of the serving loop on the host (no GPU): arrival order,
+admission by the HBM budget and by free slots, latency accounting, error
+propagation.  The runner is a stand-in that sleeps; the GPU runner is
+exercised by tests/test_gpu_serve.py."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1804_01583_amd.serve import Server, summarize
+
+
+def _fake(service_s, log, lock):
+    def run(q, slot, keep):
+        with lock:
+            log.append(("start", q.qid, time.perf_counter()))
+        time.sleep(service_s)
+        with lock:
+            log.append(("end", q.qid, time.perf_counter()))
+        return {"first_step": -1, "row": -1}, None, len(q.gens)
+    return run
+
+
+def test_fifo_admission_and_budget():
+    qs = W.serving_queries(24, rate=200.0, seed=300)
+    fp = {q.qid: 10 + (q.qid % 3) * 10 for q in qs}       # 10, 20 or 30 units
+    log, lock = [], threading.Lock()
+    srv = Server(None, slots=4, budget_bytes=45, runner=_fake(0.02, log, lock), footprint=lambda q: fp[q.qid])
+    res = srv.serve(qs)
+    # admission is in arrival order
+    starts = [e[1] for e in log if e[0] == "start"]
+    assert starts == sorted(starts, key=lambda i: qs[i].arrival)
+    # at no time do the running queries exceed the budget or the slots
+    events = sorted(log, key=lambda e: (e[2], e[0] == "start"))
+    running = set()
+    for kind, qid, _ in events:
+        if kind == "start":
+            running.add(qid)
+            assert len(running) <= 4
+            assert sum(fp[i] for i in running) <= 45
+        else:
+            running.discard(qid)
+    # latency = done - arrival >= the service time, admission after arrival
+    for r in res:
+        assert r.admitted >= r.arrival - 1e-3
+        assert r.latency >= 0.02 - 1e-3
+    s = summarize(res)
+    assert s["queries"] == 24 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_oversized_query_runs_alone():
+    qs = W.serving_queries(5, rate=1000.0, seed=301)
+    log, lock = [], threading.Lock()
+    big = qs[2].qid
+    srv = Server(None, slots=3, budget_bytes=100, runner=_fake(0.01, log, lock),
+                 footprint=lambda q: 500 if q.qid == big else 10)
+    srv.serve(qs)
+    t_start = {e[1]: e[2] for e in log if e[0] == "start"}
+    t_end = {e[1]: e[2] for e in log if e[0] == "end"}
+    for q in qs:
+        if q.qid != big:
+            overlap = t_start[q.qid] < t_end[big] and t_start[big] < t_end[q.qid]
+            assert not overlap
+
+
+def test_runner_error_is_raised():
+    qs = W.serving_queries(6, rate=1000.0, seed=302)
+
+    def run(q, slot, keep):
+        if q.qid == 3:
+            raise RuntimeError("query 3 failed")
+        return {"first_step": -1, "row": -1}, None, 1
+    srv = Server(None, slots=2, budget_bytes=1 << 40, runner=run, footprint=lambda q: 1)
+    with pytest.raises(RuntimeError, match="query 3 failed"):
+        srv.serve(qs)
+
+
+def test_query_stream_is_seeded_and_in_range():
+    a = W.serving_queries(50, rate=20.0, seed=100)
+    b = W.serving_queries(50, rate=20.0, seed=100)
+    assert [(q.arrival, q.m, q.steps, q.precision) for q in a] == [(q.arrival, q.m, q.steps, q.precision) for q in b]
+    for q in a:
+        assert q.family in ("heat", "conv") and q.m in W.SERVING_EDGES
+        assert 1 <= len(q.gens) <= 8 and 1 <= len(q.C) <= 4 and 100 <= q.steps <= 2000
+        assert 0.05 <= q.unsafe[0, 0] <= 1.5
+        for s in [g.seg for g in q.gens] + q.C:
+            assert s.lo.min() >= 0 and s.hi.max() <= q.n
+    gaps = np.diff([q.arrival for q in a])
+    assert np.all(gaps >= 0)

@@ -401,3 +401,97 @@ def conv_diff3d(nx=200, ny=200, nz=250, peclet=5.0, extra_per_row=2, extra_sigma
                    rowptr=rowptr, colidx=cols_m.astype(np.int32), vals=vals_m, seed=seed,
                    meta={"grid": (nx, ny, nz), "D": D, "h": h},
                    note="nonsymmetric upwind convection-diffusion with random off-stencil entries")
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: seeded verification queries with Poisson arrivals
+# ---------------------------------------------------------------------------
+
+# Grid edges of the resident systems: n = m^3 log-spaced from 10^3 to ~10^7.
+SERVING_EDGES = (10, 13, 17, 22, 28, 36, 46, 60, 77, 100, 129, 167, 215)
+SERVING_DT = {"heat": 0.02, "conv": 1e-4}
+
+
+def serving_system(family: str, m: int, D=0.01) -> Problem:
+    """The system of one resident catalog entry (the generators and outputs
+    of a query are attached per query): 3D heat on an m^3 grid as a matrix-
+    free stencil (D = 0.01, h = 1/(m+1), Dirichlet), or the convection-
+    diffusion matrix of ``conv_diff3d`` on an m^3 grid (seed m)."""
+    if family == "heat":
+        h = 1.0 / (m + 1)
+        c = D / h**2
+        coef = (-6.0 * c, c, c, c)
+        one = segments_from_ranges([(0, 1)])
+        return Problem(f"serve_heat_{m}", m**3, "stencil7", True, [Generator(one, 1.0, 0.1)], [one],
+                       np.array([[math.inf, math.inf]]), k=30, dt=SERVING_DT["heat"], steps=100,
+                       grid=(m, m, m), coef=coef, seed=m, meta={"m": m})
+    p = conv_diff3d(m, m, m, ngen=1, gen_len=1, o=1, k=30, dt=SERVING_DT["conv"], steps=100, seed=m)
+    p.name = f"serve_conv_{m}"
+    p.meta["m"] = m
+    return p
+
+
+@dataclass
+class Query:
+    qid: int
+    arrival: float           # seconds after the stream starts
+    family: str              # "heat" | "conv"
+    m: int                   # grid edge of its system (n = m^3)
+    gens: list
+    C: list
+    unsafe: np.ndarray       # (o, 2)
+    steps: int
+    dt: float
+    k: int
+    precision: str           # "fp64" | "fp32"
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return self.m ** 3
+
+
+def serving_query(q: int, arrival: float, seed: int) -> Query:
+    """Query q of the stream: heat or convection-diffusion (even odds), size
+    n = 10^U[3,7] taken to the nearest resident grid in log scale, 1-8 box
+    generators (disjoint seeded index ranges at 1.0 +- 0.1), 1-4 outputs
+    (means over seeded ranges, the first one overlapping generator 0),
+    100-2000 steps, unsafe when an output reaches theta ~ U[0.05, 1.5],
+    FP64 or FP32-basis (even odds), k = 30."""
+    rng = np.random.default_rng(seed)
+    family = "heat" if rng.uniform() < 0.5 else "conv"
+    n_target = 10.0 ** rng.uniform(3.0, 7.0)
+    edges = np.array(SERVING_EDGES, dtype=np.float64)
+    m = int(SERVING_EDGES[int(np.argmin(np.abs(np.log(edges**3) - math.log(n_target))))])
+    n = m**3
+    ngen = int(rng.integers(1, 9))
+    o = int(rng.integers(1, 5))
+    steps = int(rng.integers(100, 2001))
+    theta = float(rng.uniform(0.05, 1.5))
+    precision = "fp32" if rng.uniform() < 0.5 else "fp64"
+    L = max(1, min(1000, n // (4 * (ngen + o))))
+    slots = rng.choice(n // L, size=ngen + o, replace=False) * L
+    gens = [Generator(segments_from_ranges([(int(s), int(s) + L)], 1.0), zc=1.0, radius=0.1)
+            for s in slots[:ngen]]
+    out = [int(s) for s in slots[ngen:]]
+    out[0] = min(int(slots[0]) + L // 2, n - L)
+    C = [segments_from_ranges([(s, s + L)], 1.0 / L) for s in out]
+    unsafe = np.array([[theta, math.inf]] * o)
+    return Query(q, arrival, family, m, gens, C, unsafe, steps, SERVING_DT[family], 30, precision, seed)
+
+
+def serving_queries(count: int, rate: float, seed: int = 100):
+    """`count` queries with Poisson arrivals at `rate` per second (seeded
+    exponential gaps); query q draws its own parameters from seed + q."""
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=count)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    return [serving_query(q, float(arrivals[q]), seed + q) for q in range(count)]
+
+
+def query_problem(system: Problem, query: Query) -> Problem:
+    """The whole Problem of one query (its system with its generators,
+    outputs, unsafe set and time grid), e.g. for the oracle."""
+    p = Problem(f"{system.name}_q{query.qid}", system.n, system.kind, system.symmetric, query.gens, query.C,
+                query.unsafe, k=query.k, dt=query.dt, steps=query.steps, rowptr=system.rowptr,
+                colidx=system.colidx, vals=system.vals, grid=system.grid, coef=system.coef, seed=query.seed)
+    return p
