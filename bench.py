@@ -37,6 +37,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+# sources of the 100^3 CSR mat-vec whose counters profiles/ records
+KERNEL_SOURCES = ("kry_sell.hip", "kry_device.h", "kry_internal.h")
 
 
 def log(msg):
@@ -325,8 +327,10 @@ def counter_traffic(path):
             key, _, val = line.strip()[2:].partition(":")
             vals[key.strip()] = val.strip().strip("`")
     try:
-        src = os.path.join(ROOT, "paper_1804_01583_amd", "csrc", "kry_lanczos.hip")
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != vals["kernel_source_sha256"]:
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(os.path.join(ROOT, "paper_1804_01583_amd", "csrc", f), "rb").read())
+        if h.hexdigest() != vals["kernel_source_sha256"]:
             return None
         rd = float(vals["fetch_kib_per_launch"]) * 1024 * float(vals["calib_read_factor"])
         wr = float(vals["write_kib_per_launch"]) * 1024 * float(vals["calib_write_factor"])

@@ -70,7 +70,7 @@ Profiler& prof() {
 
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
-    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm";
+    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -134,6 +134,14 @@ int32_t march_blocks_for(const kry_system& sys) {
 
 constexpr int kProjGroups = 32;   // workgroups per output row in the block projection
 
+// CSR systems of the single-vector methods read a sliced-ELL copy (see
+// kry_sell.hip) unless KRY_SELL=0.
+int64_t sell_nnz_for(const kry_system& sys, int32_t method) {
+    if (sys.kind != KRY_CSR || method == KRY_BLOCK_ARNOLDI || sys.nnz <= 0) return 0;
+    if (env_int("KRY_SELL", 1) == 0) return 0;
+    return sys.nnz;
+}
+
 int max_batch_for(int o, int block_p) {
     int p = 8;
     while (p > 1 && p * (1 + o) > kMaxNV) p >>= 1;
@@ -163,13 +171,16 @@ struct Layout {
            bdense = 0;
     int32_t esize;        // bytes per stored vector element: 8 (FP64) or 4 (FP32 basis)
     bool dense_runs = false;   // k > 56: each run's exponential in the dense stage
+    int64_t scap = 0;          // sliced-ELL entry capacity (0: no sliced-ELL copy)
+    size_t swidth = 0, soff = 0, stiles = 0, scol = 0, sval = 0;
     size_t dH = 0, dP = 0, dS0 = 0, dws = 0;
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     size_t hpart, hcoef, vals32;
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
-                   size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32) {
+                   size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32,
+                   int64_t sell_nnz) {
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
     Y.nblocks = nblocks_for(n, Y.rpb);
@@ -206,6 +217,17 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.hpart = Y.stored ? take((size_t)k * kMaxP * Y.nblocks * sizeof(double)) : 0;
     Y.hcoef = Y.stored ? take((size_t)k * kMaxP * sizeof(double)) : 0;
     Y.vals32 = nnz32 > 0 ? take((size_t)nnz32 * sizeof(float)) : 0;
+    // sliced-ELL copy of a CSR matrix: room for the entries plus a quarter
+    // for padding (and one slice's worth); a matrix that needs more keeps CSR
+    if (sell_nnz > 0) {
+        const int64_t ns = sell_slices(n);
+        Y.scap = sell_nnz + sell_nnz / 4 + (int64_t)kSlice * 8;
+        Y.swidth = take((size_t)ns * sizeof(int32_t));
+        Y.soff = take((size_t)(ns + 1) * sizeof(int64_t));
+        Y.stiles = take((size_t)sell_scan_tiles(n) * sizeof(int64_t));
+        Y.scol = take((size_t)Y.scap * sizeof(int32_t));
+        Y.sval = take((size_t)Y.scap * (precision == KRY_FP32_BASIS ? sizeof(float) : sizeof(double)));
+    }
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
     Y.ap_part = take((size_t)std::max(Y.nblocks, Y.march) * kMaxP * sizeof(double));
@@ -357,6 +379,7 @@ struct kry_plan {
 
     bool f32 = false;
     bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
+    bool use_sell = false;    // the mat-vec reads the sliced-ELL copy
 
     void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
     float* vals32() { return reinterpret_cast<float*>(ws + Y.vals32); }
@@ -444,7 +467,7 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
-                                 march_blocks_for(*sys), precision, nnz32);
+                                 march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method));
     *bytes = Y.total;
     return KRY_OK;
 }
@@ -529,7 +552,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys), precision,
-                          nnz32);
+                          nnz32, sell_nnz_for(*sys, method));
     plan->method = method;
     plan->f32 = precision == KRY_FP32_BASIS;
     plan->hess_mode = plan->Y.stored;
@@ -625,7 +648,28 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
         if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e)));
     }
     // FP32-basis mode reads an FP32 copy of the CSR values
-    if (Y.vals32) {
+    if (Y.scap > 0) {
+        CsrArgs A{sys->rowptr, sys->colidx, sys->vals, nullptr};
+        hipError_t e = timed("sell_build", plan->stream, [&] {
+            return launch_sell_layout(A, n, plan->at<int32_t>(Y.swidth), plan->at<int64_t>(Y.soff),
+                                      plan->at<int64_t>(Y.stiles), plan->stream);
+        });
+        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell layout: ") + hipGetErrorString(e)));
+        int64_t total = 0;
+        if (hipMemcpyAsync(&total, plan->at<int64_t>(Y.soff) + sell_slices(n), sizeof(total), hipMemcpyDeviceToHost,
+                           plan->stream) != hipSuccess ||
+            hipStreamSynchronize(plan->stream) != hipSuccess)
+            return cleanup(fail(KRY_EDEVICE, "sell layout readback failed"));
+        if (total <= Y.scap) {
+            e = timed("sell_build", plan->stream, [&] {
+                return launch_sell_fill(plan->f32, A, n, plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
+                                        plan->at<int32_t>(Y.scol), plan->ws + Y.sval, plan->stream);
+            });
+            if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell fill: ") + hipGetErrorString(e)));
+            plan->use_sell = true;
+        }
+    }
+    if (Y.vals32 && !plan->use_sell) {
         hipError_t e = launch_to_f32(sys->vals, plan->vals32(), sys->nnz, plan->stream);
         if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("to_f32: ") + hipGetErrorString(e)));
     }
@@ -844,10 +888,16 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                                                          : plan->vec((j + 1) % 3));   // (j - 2) mod 3
             void* w = Y.stored ? plan->vec(j) : plan->vec(j % 3);
             if (plan->sys.kind == KRY_CSR) {
-                CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
-                e = timed("spmv_csr", s, [&] {
-                    return launch_spmv_csr(P, plan->lpr, f32, A, ucur, uprev, w, B, j, s);
-                });
+                if (plan->use_sell) {
+                    SellArgs A{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth), plan->at<int32_t>(Y.scol),
+                               f32 ? nullptr : plan->at<double>(Y.sval), f32 ? plan->at<float>(Y.sval) : nullptr};
+                    e = timed("spmv_csr", s, [&] { return launch_spmv_sell(P, f32, A, ucur, uprev, w, B, j, s); });
+                } else {
+                    CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
+                    e = timed("spmv_csr", s, [&] {
+                        return launch_spmv_csr(P, plan->lpr, f32, A, ucur, uprev, w, B, j, s);
+                    });
+                }
             } else {
                 StencilArgs A{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx,
                               plan->sys.cy, plan->sys.cz};

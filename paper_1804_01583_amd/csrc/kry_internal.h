@@ -74,6 +74,24 @@ struct CsrArgs {
     const float* vals32;     // FP32 copy of vals, read by the FP32-basis kernels
 };
 
+// Sliced-ELL copy of a CSR matrix (kry_sell.hip): slices of kSlice rows,
+// entries column-major within a slice, padded to the slice's longest row.
+constexpr int kSlice = 64;
+struct SellArgs {
+    const int64_t* off;      // [slices + 1] first entry of each slice
+    const int32_t* width;    // [slices] entries per row in the slice
+    const int32_t* col;
+    const double* val;       // FP64 values, or
+    const float* val32;      // FP32 values (FP32-basis mode)
+};
+int64_t sell_slices(int64_t n);
+int64_t sell_scan_tiles(int64_t n);
+struct CsrArgs;
+hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64_t* off, int64_t* tiles,
+                              hipStream_t s);
+hipError_t launch_sell_fill(bool f32, const CsrArgs& A, int64_t n, const int64_t* off, const int32_t* width,
+                            int32_t* col, void* val, hipStream_t s);
+
 struct StencilArgs {
     int64_t nx, ny, nz;
     double c0, cx, cy, cz;
@@ -210,6 +228,8 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 // f32 selects E = float storage of the Krylov vectors (and vals32 for CSR).
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
                         void* u, const BatchArgs& B, hipStream_t s);
+hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,
+                            const BatchArgs& B, int j, hipStream_t s);
 hipError_t launch_spmv_csr(int P, int lpr, bool f32, const CsrArgs& A, const void* ucur,
                            const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s);
 // march: the column-marching kernel (grid ap_nblocks), else the row kernel.

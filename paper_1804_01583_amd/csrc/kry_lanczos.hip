@@ -125,41 +125,6 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
     store_partials<NV>(acc, stage_part(B, 0), B.nblocks, s_lds, B.xcd_map);
 }
 
-// Loads for the reduction of stage j-1's norms, issued before any row work
-// so their latency overlaps it; thread t sums blocks t, t + kBlock, ...
-template <int P>
-__device__ __forceinline__ void load_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
-                                                 double (&sig_prev)[P], double& anorm) {
-    const double* part = stage_part(B, j - 1);
-#pragma unroll
-    for (int p = 0; p < P; ++p) pacc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) pacc[p] += part[(int64_t)p * B.nblocks + b];
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) sig_prev[p] = (j > 1) ? run_scal(B, p)[B.L.sigma + j - 1] : 0.0;
-    anorm = *B.anorm;
-}
-
-// Finishes the stage j-1 reduction: sigma_j and cprev = beta_{j-1} sigma_{j-1}
-// for every run; block 0 records the stage.  Every thread must call it.
-template <int P>
-__device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
-                                                   const double (&sig_prev)[P], double anorm, double* s_lds,
-                                                   double* s_nrm, double (&sig)[P], double (&cprev)[P]) {
-    const double t = block_sum<P>(pacc, s_lds);
-    if (threadIdx.x < P) s_nrm[threadIdx.x] = t;
-    __syncthreads();
-    if (blockIdx.x == 0) record_stage(B, P, j, s_nrm);
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        const Stage st = stage_update_v(B.L.k, sig_prev[p], B.tau_scale * anorm, j, s_nrm[p]);
-        sig[p] = st.sigma;
-        cprev[p] = st.cprev;
-    }
-}
-
 // a3 + first half of a4: w = sigma_j A u_j - beta_{j-1} sigma_{j-1} u_{j-1}
 // (Lanczos), or w = sigma_j A u_j when uprev is null (Arnoldi); partials of
 // (sigma_j u_j) . w.  LPR lanes cooperate on one row.  Rows are

@@ -1,0 +1,251 @@
+// Sliced-ELL copy of a CSR matrix and the mat-vec that reads it (gfx950).
+//
+// Rows are grouped in slices of 64 (one wavefront).  Slice s stores its
+// entries column-major: entry k of row 64 s + l sits at off[s] + 64 k + l,
+// k < width[s] = the slice's longest row; shorter rows are padded with
+// value 0 at their own row index.  A wavefront then reads entry k of its 64
+// rows with one contiguous load (the CSR layout spreads the same load over
+// 64 rows' worth of entries), needs no row-pointer loads, and issues the
+// loads of 8 entries per row at once.  Each row's sum runs over its entries
+// in CSR order, as in k_spmv_csr; padding adds exact zeros for finite
+// vectors.
+//
+// The conversion runs once per plan: slice widths, an exclusive scan of the
+// slice sizes (tiles of kScanTile slices, then the tile totals), and a fill.
+#include "kry_device.h"
+
+#include <cmath>
+
+namespace kry {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kScanTile = 4096;   // slices per scan workgroup (256 threads x 16)
+
+__global__ __launch_bounds__(256) void k_sell_width(const int64_t* __restrict__ rowptr, int64_t n, int64_t ns,
+                                                    int32_t* __restrict__ width) {
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < ns; s += (int64_t)gridDim.x * 256) {
+        int64_t w = 0;
+        const int64_t r0 = s * kSlice, r1 = min(n, r0 + kSlice);
+        for (int64_t r = r0; r < r1; ++r) w = max(w, rowptr[r + 1] - rowptr[r]);
+        width[s] = (int32_t)w;
+    }
+}
+
+// exclusive scan of 64 * width within tiles; tile totals to `tiles`
+__global__ __launch_bounds__(256) void k_sell_scan_tiles(const int32_t* __restrict__ width, int64_t ns,
+                                                         int64_t* __restrict__ off, int64_t* __restrict__ tiles) {
+    __shared__ int64_t s_sum[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * (kScanTile / 256);
+    int64_t local = 0;
+    for (int i = 0; i < kScanTile / 256; ++i) {
+        const int64_t s = base + i;
+        if (s < ns) local += (int64_t)kSlice * width[s];
+    }
+    s_sum[threadIdx.x] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int64_t v = s_sum[t];
+            s_sum[t] = run;
+            run += v;
+        }
+        tiles[blockIdx.x] = run;
+    }
+    __syncthreads();
+    int64_t run = s_sum[threadIdx.x];
+    for (int i = 0; i < kScanTile / 256; ++i) {
+        const int64_t s = base + i;
+        if (s < ns) {
+            off[s] = run;
+            run += (int64_t)kSlice * width[s];
+        }
+    }
+}
+
+// adds the exclusive prefix of the tile totals (one thread walks them) and
+// writes off[ns] = total
+__global__ __launch_bounds__(256) void k_sell_scan_add(int64_t* __restrict__ off, int64_t ns,
+                                                       const int64_t* __restrict__ tiles, int64_t ntiles) {
+    __shared__ int64_t s_pre;
+    const int64_t tile = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int64_t t = 0; t < tile; ++t) run += tiles[t];
+        s_pre = run;
+        if (tile == ntiles - 1) off[ns] = run + tiles[tile];
+    }
+    __syncthreads();
+    const int64_t pre = s_pre;
+    for (int64_t i = threadIdx.x; i < kScanTile; i += 256) {
+        const int64_t s = tile * kScanTile + i;
+        if (s < ns) off[s] += pre;
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_sell_fill(CsrArgs A, int64_t n, int64_t ns, const int64_t* __restrict__ off,
+                                                   const int32_t* __restrict__ width, int32_t* __restrict__ col,
+                                                   V* __restrict__ val) {
+    const int64_t rows = ns * kSlice;
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
+        const int64_t s = r / kSlice, l = r % kSlice;
+        const int32_t w = width[s];
+        const int64_t base = off[s] + l;
+        int64_t e0 = 0, len = 0;
+        if (r < n) {
+            e0 = A.rowptr[r];
+            len = A.rowptr[r + 1] - e0;
+        }
+        for (int32_t k = 0; k < w; ++k) {
+            const bool real = k < len;
+            col[base + (int64_t)k * kSlice] = real ? A.colidx[e0 + k] : (int32_t)(r < n ? r : 0);
+            val[base + (int64_t)k * kSlice] = real ? (V)A.vals[e0 + k] : (V)0;
+        }
+    }
+}
+
+// a3 + first half of a4 on the sliced-ELL copy: w = sigma_j A u_j -
+// beta_{j-1} sigma_{j-1} u_{j-1} (or without the second term), partials of
+// (sigma_j u_j) . w.  Rows in chunks of RC per thread; entries of a row in
+// groups of KU whose loads are issued together (slots past the slice width
+// re-read the last entry and add nothing).
+template <typename E, int P>
+__global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __restrict__ ucur,
+                                                      const E* __restrict__ uprev, E* __restrict__ w, BatchArgs B,
+                                                      int j) {
+    constexpr int RC = 2;
+    constexpr int KU = 8;
+    __shared__ double s_lds[(kBlock / 64) * P];
+    __shared__ double s_nrm[P];
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
+    const int lane = threadIdx.x & 63;
+    double pacc[P], sig_prev[P], anorm;
+    load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
+    double sig[P], cprev[P], dot[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) { sig[p] = 0.0; cprev[p] = 0.0; dot[p] = 0.0; }
+    const int64_t span = (int64_t)kBlock * RC;
+    const int nch = (int)((B.rows_per_block + span - 1) / span);
+    const bool prev = j > 1 && uprev != nullptr;
+    for (int ch = 0; ch < nch; ++ch) {
+        int64_t rr[RC], off[RC];
+        int32_t wd[RC];
+        double acc[RC][P];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            // a wavefront's 64 rows are one slice; rows past the block (or n)
+            // read slice 0 and are not stored
+            const int64_t rs = rr[i] < r1 ? rr[i] : (r0 < B.n ? r0 : 0);
+            const int64_t s = rs / kSlice;
+            off[i] = A.off[s] + lane;
+            wd[i] = A.width[s];
+#pragma unroll
+            for (int p = 0; p < P; ++p) acc[i][p] = 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            for (int kb = 0; kb < wd[i]; kb += KU) {
+                int32_t c[KU];
+                double a[KU];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    const int k = kb + u < wd[i] ? kb + u : wd[i] - 1;
+                    const int64_t idx = off[i] + (int64_t)k * kSlice;
+                    c[u] = A.col[idx];
+                    const double v = sizeof(E) == 4 ? (double)A.val32[idx] : A.val[idx];
+                    a[u] = kb + u < wd[i] ? v : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const double x = (double)ucur[(int64_t)c[u] * P + p];
+                        acc[i][p] = kb + u < wd[i] ? fma(a[u], x, acc[i][p]) : acc[i][p];
+                    }
+                }
+            }
+        }
+        if (ch == 0) finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            if (rr[i] < r1) {
+                const int64_t r = rr[i];
+                double own[P], pv[P], y[P];
+                load_row<E, P>(ucur, r, own);
+                if (prev) load_row<E, P>(uprev, r, pv);
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    y[p] = sig[p] * acc[i][p];
+                    if (prev) y[p] = fma(-cprev[p], pv[p], y[p]);
+                    y[p] = (double)(E)y[p];
+                    dot[p] = fma(sig[p] * own[p], y[p], dot[p]);
+                }
+                store_row<E, P>(w, r, y);
+            }
+        }
+    }
+    if (nch == 0) finish_stage_norms<P>(B, j, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
+    store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
+}
+
+int grid_for(int64_t count) { return (int)std::min<int64_t>((count + 255) / 256, 4096); }
+
+}  // namespace
+
+int64_t sell_slices(int64_t n) { return (n + kSlice - 1) / kSlice; }
+int64_t sell_scan_tiles(int64_t n) { return (sell_slices(n) + kScanTile - 1) / kScanTile; }
+
+hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64_t* off, int64_t* tiles,
+                              hipStream_t s) {
+    const int64_t ns = sell_slices(n), nt = sell_scan_tiles(n);
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(ns)), dim3(256), 0, s, A.rowptr, n, ns, width);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sell_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, width, ns, off, tiles);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sell_scan_add, dim3((unsigned)nt), dim3(256), 0, s, off, ns, tiles, nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell_fill(bool f32, const CsrArgs& A, int64_t n, const int64_t* off, const int32_t* width,
+                            int32_t* col, void* val, hipStream_t s) {
+    const int64_t ns = sell_slices(n);
+    if (f32)
+        hipLaunchKernelGGL(k_sell_fill<float>, dim3(grid_for(ns * kSlice)), dim3(256), 0, s, A, n, ns, off, width, col,
+                           static_cast<float*>(val));
+    else
+        hipLaunchKernelGGL(k_sell_fill<double>, dim3(grid_for(ns * kSlice)), dim3(256), 0, s, A, n, ns, off, width,
+                           col, static_cast<double*>(val));
+    return hipGetLastError();
+}
+
+template <typename E>
+hipError_t launch_spmv_sell_e(int P, const SellArgs& A, const void* ucur, const void* uprev, void* w,
+                              const BatchArgs& B, int j, hipStream_t s) {
+    const E* uc = static_cast<const E*>(ucur);
+    const E* up = static_cast<const E*>(uprev);
+    E* ww = static_cast<E*>(w);
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
+        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
+        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
+        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,
+                            const BatchArgs& B, int j, hipStream_t s) {
+    return f32 ? launch_spmv_sell_e<float>(P, A, ucur, uprev, w, B, j, s)
+               : launch_spmv_sell_e<double>(P, A, ucur, uprev, w, B, j, s);
+}
+
+}  // namespace kry

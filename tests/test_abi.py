@@ -63,9 +63,19 @@ def test_footprint_is_host_only_and_scales_with_n():
     from paper_1804_01583_amd import kry
     small = kry.kry_footprint(_csr_system(10_000), 2, 3, 40, 2000, 300)
     big = kry.kry_footprint(_csr_system(1_000_000), 2, 3, 40, 2000, 300)
-    # three interleaved vectors of the batch dominate (Lanczos keeps 3 vectors, paper Sec. 3.5)
-    assert big - small >= 3 * 2 * 8 * (1_000_000 - 10_000)
-    assert big - small <= 4 * 2 * 8 * (1_000_000 - 10_000) + (1 << 20)
+    # three interleaved vectors of the batch dominate (Lanczos keeps 3 vectors, paper Sec. 3.5),
+    # plus the sliced-ELL copy of the matrix (nnz = n here: 1.25 entries of 12 bytes per row at most)
+    d = 1_000_000 - 10_000
+    assert big - small >= 3 * 2 * 8 * d
+    assert big - small <= 4 * 2 * 8 * d + 16 * d + (1 << 20)
+
+
+def test_footprint_without_sliced_ell_copy(monkeypatch):
+    from paper_1804_01583_amd import kry
+    with_copy = kry.kry_footprint(_csr_system(1_000_000), 2, 3, 40, 2000, 300)
+    monkeypatch.setenv("KRY_SELL", "0")
+    without = kry.kry_footprint(_csr_system(1_000_000), 2, 3, 40, 2000, 300)
+    assert 12 * 1_000_000 <= with_copy - without <= 16 * 1_000_000 + (1 << 20)
 
 
 @pytest.mark.parametrize("bad", ["n", "k", "k_big", "o", "steps", "dt", "seg_order", "seg_range", "nonsym",
