@@ -20,7 +20,8 @@ Billion Dimensions", arXiv 1804.01583):
 * the per-step check, specialised from the LP of Section 2.1 to a box
   initial set and per-row interval unsafe sets, with a counter-example,
 * block Arnoldi over p generator columns at once (``block``), the same
-  Galerkin approximant for a block start.
+  Galerkin approximant for a block start,
+* the a-posteriori choice of k by the error bound of Lemma 1 (``adaptive``).
 
 All pins of these functions live in ``tests/test_oracle_*.py``.
 """
@@ -30,3 +31,4 @@ from .krylov import (  # noqa: F401
     RunResult, krylov_run,
 )
 from .block import BlockResult, block_arnoldi, block_project_steps, block_verify, qr_posdiag  # noqa: F401
+from . import adaptive  # noqa: F401
