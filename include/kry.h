@@ -199,6 +199,31 @@ kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks,
 kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
                            double* h_next, double* P);
 
+/* kry_plan_set_error_target -- choose each run's Krylov dimension a
+ * posteriori (paper Section 4.2, Lemma 1; the checks of Algorithms 2 and 4).
+ * With eps > 0, kry_project_expm evaluates after iteration j = 4, then
+ * j <- ceil(1.1 j), the bound
+ *     beta0 h_{j+1,j} e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
+ * (tau = steps * dt; lambda a Gershgorin upper bound of the largest
+ * eigenvalue of A, computed here, on the device for a CSR system; w = 1, or
+ * tau - t for the augmented run, whose bordered matrix integrates the
+ * approximation of e^{As} b) and ends a run at the first checkpoint where the
+ * bound is below eps; a batch stops iterating once all its runs have ended.
+ * k stays the cap (the augmented run: k - 1 Lanczos steps).  The integral
+ * uses a fixed composite 8-point Gauss-Legendre rule on [0, tau 2^-40] and on
+ * [tau 2^-(i+1), tau 2^-i], i < 40, each cut into 8 equal parts.  eps = 0
+ * turns the control off (the default: every run uses k).  Lanczos plans
+ * only (symmetric A; KRY_ENOTSUP otherwise).  Waits for the plan's stream
+ * for a CSR system. */
+kry_status kry_plan_set_error_target(kry_plan* plan, double eps);
+/* kry_plan_error -- after kry_project_expm, run `run`'s Krylov dimension
+ * (k_used: Lanczos steps used, the least of the breakdown dimension, the
+ * error-control stop and k, or k - 1 for the augmented run) and
+ * its last evaluated bound (-1 when none was evaluated, 0 after a breakdown,
+ * which makes the projection exact).  Either pointer may be NULL; waits for
+ * the plan's stream.  KRY_ENOTSUP for block plans. */
+kry_status kry_plan_error(kry_plan* plan, int32_t run, int32_t* k_used, double* bound);
+
 void kry_plan_destroy(kry_plan* plan);
 
 /* Thread-local text of the last error on this thread. */

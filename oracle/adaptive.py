@@ -98,7 +98,7 @@ def k_schedule(k0: int, kmax: int):
 def adaptive_lanczos(A, v, C, eps, tau, kmax, lam_upper, opnorm, affine=False):
     """Algorithm 4 with error control: Lanczos from v (|v| = beta0); at each
     checkpoint k the bound uses T_k and h = beta_k.  Returns dict(k_stop,
-    bound, H, P, beta0, k_eff).  k_stop = kmax (bound above eps) when no
+    bound, H, P, beta0, k_eff, h = h_{k+1,k} at the stop).  k_stop = kmax (bound above eps) when no
     checkpoint reaches the target; a breakdown ends the run exactly
     (bound 0) at k_eff."""
     v = np.asarray(v, np.float64)
@@ -106,7 +106,7 @@ def adaptive_lanczos(A, v, C, eps, tau, kmax, lam_upper, opnorm, affine=False):
     o = C.shape[0]
     if beta0 == 0.0:
         return {"k_stop": 0, "bound": 0.0, "H": np.zeros((0, 0)), "P": np.zeros((o, 0)), "beta0": 0.0,
-                "k_eff": 0}
+                "k_eff": 0, "h": 0.0}
     checks = set(k_schedule(4, kmax))
     H = np.zeros((kmax + 1, kmax))
     P = np.zeros((o, kmax + 1))
@@ -124,16 +124,16 @@ def adaptive_lanczos(A, v, C, eps, tau, kmax, lam_upper, opnorm, affine=False):
         H[i, i - 1] = eta
         if eta <= BREAKDOWN_FACTOR * EPS * opnorm:
             return {"k_stop": i, "bound": 0.0, "H": H[:i, :i].copy(), "P": P[:, :i].copy(), "beta0": beta0,
-                    "k_eff": i}
+                    "k_eff": i, "h": eta}
         if i in checks:
             bound = lemma1_bound(H[:i, :i], eta, beta0, tau, lam_upper, affine)
             if bound < eps:
                 return {"k_stop": i, "bound": bound, "H": H[:i, :i].copy(), "P": P[:, :i].copy(), "beta0": beta0,
-                        "k_eff": i}
+                        "k_eff": i, "h": eta}
         v_prev, v_cur = v_cur, w / eta
         P[:, i] = C @ v_cur
     return {"k_stop": kmax, "bound": bound, "H": H[:kmax, :kmax].copy(), "P": P[:, :kmax].copy(), "beta0": beta0,
-            "k_eff": kmax}
+            "k_eff": kmax, "h": float(H[kmax, kmax - 1])}
 
 
 def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
@@ -141,7 +141,9 @@ def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
     the error control above (generator and center runs: Lanczos on A; the
     augmented run: Lanczos on A from b, bordered by the augmented variable).
     Returns dict(basis (S+1, o, nruns), roles, runs: dicts with k_stop,
-    bound, dim (Krylov dimension used), verdict)."""
+    bound, dim (Krylov dimension used), k_eff, H (the Lanczos matrix up to
+    k_stop), h, beta0, affine, kmax (the run's cap), verdict) and lam (the
+    Gershgorin bound used)."""
     from .krylov import box_check, build_runs, inf_norm, output_matrix, system_matrix
     if not problem.symmetric:
         raise ValueError("the error-controlled path here is Lanczos (symmetric A)")
@@ -176,10 +178,12 @@ def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
             for s in range(steps + 1):
                 out[s] = scale * (Pb @ (expm_pade13(Hb * (s * dt)) @ e1))
         cols.append(out)
-        info.append({"k_stop": r["k_stop"], "bound": r["bound"], "dim": dim, "k_eff": r["k_eff"]})
+        info.append({"k_stop": r["k_stop"], "bound": r["bound"], "dim": dim, "k_eff": r["k_eff"], "H": r["H"],
+                     "h": r["h"], "beta0": r["beta0"], "affine": run.role == "affine", "kmax": kmax - 1 if run.role == "affine"
+                     else kmax})
     basis = np.stack(cols, axis=2)
     roles = [r.role for r in runs]
     zc = np.array([g.zc for g in problem.gens])
     rad = np.array([g.radius for g in problem.gens])
-    return {"basis": basis, "roles": roles, "runs": info,
+    return {"basis": basis, "roles": roles, "runs": info, "lam": lam,
             "verdict": box_check(basis, roles, zc, rad, problem.unsafe)}

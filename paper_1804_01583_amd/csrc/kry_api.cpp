@@ -70,7 +70,7 @@ Profiler& prof() {
 
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
-    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build";
+    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -173,6 +173,7 @@ struct Layout {
     bool dense_runs = false;   // k > 56: each run's exponential in the dense stage
     int64_t scap = 0;          // sliced-ELL entry capacity (0: no sliced-ELL copy)
     size_t swidth = 0, soff = 0, stiles = 0, scol = 0, sval = 0;
+    size_t eflags = 0;          // error control: per-run stop flags, then the Gershgorin bound
     size_t dH = 0, dP = 0, dS0 = 0, dws = 0;
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     size_t hpart, hcoef, vals32;
@@ -252,6 +253,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.cpart = take((size_t)2 * check_blocks(steps, o) * sizeof(double));
     Y.verdict = take((size_t)(6 + nruns) * sizeof(double));
     Y.anorm = take(sizeof(double));
+    Y.eflags = take(kMaxP * sizeof(double) + sizeof(double));
     if (method == KRY_BLOCK_ARNOLDI) {
         Y.bw = block_p;
         Y.brb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 63) / 64));
@@ -335,6 +337,31 @@ void pade13(double* b) {
     }
 }
 
+// Nodes and weights of the 8-point Gauss-Legendre rule on [-1, 1]: roots of
+// the Legendre polynomial P_8 by Newton's method from the Chebyshev-like
+// guesses cos(pi (i - 1/4) / (8 + 1/2)); w_i = 2 / ((1 - x_i^2) P_8'(x_i)^2).
+void gauss_legendre8(double* x, double* w) {
+    const int n = 8;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;           // P_0, P_1
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);   // P_8'(z)
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
 kry_status prepare_device() {
     static std::once_flag once;
     static hipError_t err = hipSuccess;
@@ -380,6 +407,8 @@ struct kry_plan {
     bool f32 = false;
     bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
     bool use_sell = false;    // the mat-vec reads the sliced-ELL copy
+    double err_eps = 0.0;     // error target of the a-posteriori k (0: fixed k)
+    double lam_plus = 0.0;    // max(0, Gershgorin bound of lambda_max of the symmetric part of A)
 
     void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
     float* vals32() { return reinterpret_cast<float*>(ws + Y.vals32); }
@@ -881,6 +910,17 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
         const bool lanczos = plan->method == KRY_LANCZOS;
+        int kdone = plan->k, next_check = 4;
+        ErrArgs X{};
+        if (plan->err_eps > 0.0) {
+            X.role = plan->role_dev;
+            X.tau = (double)plan->steps * plan->dt;
+            X.lam_plus = plan->lam_plus;
+            X.eps = plan->err_eps;
+            gauss_legendre8(X.gl_x, X.gl_w);
+            X.flags = plan->at<double>(Y.eflags);
+            X.hess = plan->hess_mode ? 1 : 0;
+        }
         for (int j = 1; j <= plan->k; ++j) {
             // FP64 Lanczos rotates three vectors (Algorithm 4); otherwise u_1..u_{k+1} are kept
             void* ucur = Y.stored ? plan->vec(j - 1) : plan->vec((j - 1) % 3);
@@ -911,25 +951,44 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                     return launch_sweep(P, plan->o, f32, plan->T, plan->oset0, ucur, w, B, j, s);
                 });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
-                if (!Y.stored) continue;
             }
-            // Arnoldi: CGS2 against u_1..u_j (Algorithm 1's projection loop, classical
-            // form, twice).  Lanczos with a stored basis: one classical pass over the
-            // three-term result removes what rounding left along u_1..u_j.
-            ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef(), f32 ? 1 : 0, lanczos ? 1 : 0};
-            const int passes = lanczos ? 1 : 2;
-            for (int pass = 1; pass <= passes; ++pass) {
-                e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ar, B, j, s); });
-                if (e == hipSuccess) e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ar, B, j, pass, s); });
-                if (e == hipSuccess)
-                    e = timed("arn_update", s, [&] {
-                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j, pass == passes ? 1 : 0,
-                                                 s);
-                    });
-                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
+            if (Y.stored || !lanczos) {
+                // Arnoldi: CGS2 against u_1..u_j (Algorithm 1's projection loop, classical
+                // form, twice).  Lanczos with a stored basis: one classical pass over the
+                // three-term result removes what rounding left along u_1..u_j.
+                ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef(), f32 ? 1 : 0, lanczos ? 1 : 0};
+                const int passes = lanczos ? 1 : 2;
+                for (int pass = 1; pass <= passes; ++pass) {
+                    e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ar, B, j, s); });
+                    if (e == hipSuccess)
+                        e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ar, B, j, pass, s); });
+                    if (e == hipSuccess)
+                        e = timed("arn_update", s, [&] {
+                            return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j,
+                                                     pass == passes ? 1 : 0, s);
+                        });
+                    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
+                }
+            }
+            // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k);
+            // the batch ends once every run met the target
+            if (plan->err_eps > 0.0 && j == next_check) {
+                next_check = (11 * next_check + 9) / 10;
+                e = timed("errctl", s, [&] { return launch_record_stage(P, B, j, s); });
+                if (e == hipSuccess) e = timed("errctl", s, [&] { return launch_lemma1(P, B, X, j, s); });
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("error control: ") + hipGetErrorString(e));
+                double flags[kMaxP];
+                KRY_HIP(hipMemcpyAsync(flags, X.flags, P * sizeof(double), hipMemcpyDeviceToHost, s));
+                KRY_HIP(hipStreamSynchronize(s));
+                bool all = true;
+                for (int p = 0; p < P; ++p) all = all && flags[p] != 0.0;
+                if (all) {
+                    kdone = j;
+                    break;
+                }
             }
         }
-        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, s); });
+        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, kdone, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
         r0 += P;
     }
@@ -947,7 +1006,8 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal(), sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         KRY_HIP(hipStreamSynchronize(s));
         for (int32_t run = 0; run < plan->nruns; ++run) {
-            const int keff = (int)sc[(size_t)run * Y.L.stride + Y.L.misc + MISC_KEFF];
+            const double* msc = sc.data() + (size_t)run * Y.L.stride + Y.L.misc;
+            const int keff = std::min((int)msc[MISC_KEFF], (int)msc[MISC_KSTOP]);
             const bool bordered = plan->role[run] == 2;
             int m = bordered ? std::min(keff, plan->k - 1) + 1 : keff;
             if (keff <= 0) m = 0;
@@ -1051,7 +1111,7 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
                            hipMemcpyDeviceToHost, plan->stream));
     KRY_HIP(hipStreamSynchronize(plan->stream));
     const int k = plan->k;
-    int m = (int)sc[L.misc + MISC_KEFF];
+    int m = std::min((int)sc[L.misc + MISC_KEFF], (int)sc[L.misc + MISC_KSTOP]);
     const bool bordered = plan->role[run] == 2;
     // dimension of the (augmented) Krylov space
     int dim = m;
@@ -1085,6 +1145,50 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
             for (int c = 0; c < tri; ++c) row[c0 + c] = sc[L.proj + q * (k + 1) + c];
         }
     }
+    return KRY_OK;
+}
+
+kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
+    if (eps > 0.0 && plan->method != KRY_LANCZOS)
+        return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
+    plan->err_eps = eps;
+    if (eps == 0.0) return KRY_OK;
+    // lambda_max of the symmetric part of A, bounded by Gershgorin
+    double lam;
+    if (plan->sys.kind == KRY_STENCIL7) {
+        lam = plan->sys.c0 + 2.0 * (std::fabs(plan->sys.cx) + std::fabs(plan->sys.cy) + std::fabs(plan->sys.cz));
+    } else {
+        const Layout& Y = plan->Y;
+        CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
+        double* out = plan->at<double>(Y.eflags) + kMaxP;
+        hipError_t e = launch_row_gersh(A, plan->sys.n, plan->np_part(), Y.nblocks, Y.rpb, out, plan->stream);
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("row_gersh: ") + hipGetErrorString(e));
+        KRY_HIP(hipMemcpyAsync(&lam, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+        KRY_HIP(hipStreamSynchronize(plan->stream));
+    }
+    plan->lam_plus = lam > 0.0 ? lam : 0.0;
+    plan->projected = false;
+    return KRY_OK;
+}
+
+kry_status kry_plan_error(kry_plan* plan, int32_t run, int32_t* k_used, double* bound) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
+    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs carry no error bound");
+    const ScalLayout& L = plan->Y.L;
+    double misc[MISC_COUNT];
+    KRY_HIP(hipMemcpyAsync(misc, plan->scal() + (size_t)run * L.stride + L.misc, sizeof(misc), hipMemcpyDeviceToHost,
+                           plan->stream));
+    KRY_HIP(hipStreamSynchronize(plan->stream));
+    const int keff = (int)misc[MISC_KEFF], kstop = (int)misc[MISC_KSTOP];
+    // the augmented run's bordered matrix holds k - 1 Lanczos steps at most
+    const int cap = plan->role[run] == 2 ? plan->k - 1 : plan->k;
+    if (k_used) *k_used = std::min(std::min(keff, kstop), cap);
+    // a breakdown makes the projection exact
+    if (bound) *bound = keff < kstop ? 0.0 : misc[MISC_BOUND];
     return KRY_OK;
 }
 

@@ -190,7 +190,12 @@ __device__ __forceinline__ void record_stage(const BatchArgs& B, int P, int j, c
         sc[B.L.beta + j - 1] = st.beta;
         sc[B.L.sigma + j] = st.sigma;
         if (st.keff >= 0) sc[B.L.misc + MISC_KEFF] = (double)st.keff;
-        if (j == 1) sc[B.L.misc + MISC_NONFINITE] = st.nonfinite ? 1.0 : 0.0;
+        if (j == 1) {
+            sc[B.L.misc + MISC_NONFINITE] = st.nonfinite ? 1.0 : 0.0;
+            sc[B.L.misc + MISC_KSTOP] = (double)B.L.k;
+            sc[B.L.misc + MISC_STOPPED] = 0.0;
+            sc[B.L.misc + MISC_BOUND] = -1.0;
+        }
         else if (st.nonfinite) sc[B.L.misc + MISC_NONFINITE] = 1.0;
     }
 }

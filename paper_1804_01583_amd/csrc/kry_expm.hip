@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     const int run = blockIdx.x;
     const double* sc = run_scal(E, run);
     const int k = E.L.k, o = E.L.o;
-    const int keff = (int)sc[E.L.misc + MISC_KEFF];
+    const int keff = min((int)sc[E.L.misc + MISC_KEFF], (int)sc[E.L.misc + MISC_KSTOP]);
     const bool bordered = E.role[run] == 2;
     int m = keff;                            // size of H
     if (bordered) m = (keff > k - 1 ? k - 1 : keff) + 1;

@@ -42,7 +42,10 @@ struct ScalLayout {
     int32_t misc;
     int32_t hess;    // Arnoldi: H[i][c] at hess + i * k + c, i <= k, c < k
 };
-enum { MISC_KEFF = 0, MISC_DONE = 1, MISC_NONFINITE = 2, MISC_COUNT = 4 };
+// misc: k_eff (breakdown), done, non-finite, k_stop (error control; k when
+// off), the last error bound, stopped (error target met)
+enum { MISC_KEFF = 0, MISC_DONE = 1, MISC_NONFINITE = 2, MISC_KSTOP = 3, MISC_BOUND = 4, MISC_STOPPED = 5,
+       MISC_COUNT = 6 };
 
 // One batch of runs that a mat-vec launch advances together.
 //
@@ -155,6 +158,21 @@ struct ArnArgs {
 };
 constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
 
+// ---- error control (kry_errctl.hip) ----------------------------------------
+struct ErrArgs {
+    const int32_t* role;     // per run of the plan: 2 = augmented (integrated bound)
+    double tau;              // time horizon steps * dt
+    double lam_plus;         // max(0, upper bound of lambda_max((A + A^T)/2))
+    double eps;              // error target
+    double gl_x[8], gl_w[8]; // 8-point Gauss-Legendre nodes and weights on [-1, 1]
+    double* flags;           // [kMaxP] 1 when the run has stopped
+    int hess;                // T's diagonal from the Hessenberg store (stored-basis Lanczos)
+};
+hipError_t launch_record_stage(int P, const BatchArgs& B, int j, hipStream_t s);
+hipError_t launch_lemma1(int P, const BatchArgs& B, const ErrArgs& X, int j, hipStream_t s);
+hipError_t launch_row_gersh(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks, int64_t rows_per_block,
+                            double* out, hipStream_t s);
+
 // ---- block Arnoldi (kry_block.hip) ------------------------------------------
 constexpr int kBW = 16;          // block width: p <= 16 real columns, the rest zero
 constexpr int kMaxKB = 32;       // block steps (Krylov dimension 16 k <= 512)
@@ -223,7 +241,8 @@ hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 // ---- launchers (kry_lanczos.hip, kry_expm.hip) ----------------------------
 hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks,
                               int64_t rows_per_block, double* out, hipStream_t s);
-hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s);
+// Columns 0..kdone of P = C V and the record of stage kdone.
+hipError_t launch_finish(int P, int O, const BatchArgs& B, int kdone, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // f32 selects E = float storage of the Krylov vectors (and vals32 for CSR).
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,

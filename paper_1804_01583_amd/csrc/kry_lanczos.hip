@@ -509,10 +509,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
 // stage (beta_k, sigma_{k+1}, and k_eff when the run breaks down there).
 // Values are summed by groups of threads, each group in a fixed order.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o) {
+__global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o, int kdone) {
     __shared__ double s_part[kBlock];
     __shared__ double s_tot[P * (1 + kMaxO)];
     const int c = blockIdx.x;
+    if (c > kdone) return;
     const int nv = P * (1 + o);
     const int grp = kBlock / nv;
     const int v = threadIdx.x / grp, g = threadIdx.x % grp;
@@ -529,13 +530,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o) {
         s_tot[v] = t;
     }
     __syncthreads();
-    if (c == B.L.k) record_stage(B, P, c + 1, s_tot);
+    if (c == kdone) record_stage(B, P, c + 1, s_tot);
     __syncthreads();
     if (threadIdx.x < P * o) {
         const int q = threadIdx.x / P, p = threadIdx.x % P;
         double* sc = run_scal(B, p);
         double sig;
-        if (c == B.L.k) sig = stage_update(B, sc, c + 1, s_tot[p]).sigma;
+        if (c == kdone) sig = stage_update(B, sc, c + 1, s_tot[p]).sigma;
         else sig = sc[B.L.sigma + c + 1];
         sc[B.L.proj + q * (B.L.k + 1) + c] = sig * s_tot[P + q * P + p];
     }
@@ -694,13 +695,13 @@ hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0
                : launch_sweep_e<double>(P, O, T, oset0, ucur, w, B, j, s);
 }
 
-hipError_t launch_finish(int P, int O, const BatchArgs& B, hipStream_t s) {
-    const dim3 grid(B.L.k + 1);
+hipError_t launch_finish(int P, int O, const BatchArgs& B, int kdone, hipStream_t s) {
+    const dim3 grid(kdone + 1);
     switch (P) {
-        case 1: hipLaunchKernelGGL((k_finish<1>), grid, dim3(kBlock), 0, s, B, O); break;
-        case 2: hipLaunchKernelGGL((k_finish<2>), grid, dim3(kBlock), 0, s, B, O); break;
-        case 4: hipLaunchKernelGGL((k_finish<4>), grid, dim3(kBlock), 0, s, B, O); break;
-        case 8: hipLaunchKernelGGL((k_finish<8>), grid, dim3(kBlock), 0, s, B, O); break;
+        case 1: hipLaunchKernelGGL((k_finish<1>), grid, dim3(kBlock), 0, s, B, O, kdone); break;
+        case 2: hipLaunchKernelGGL((k_finish<2>), grid, dim3(kBlock), 0, s, B, O, kdone); break;
+        case 4: hipLaunchKernelGGL((k_finish<4>), grid, dim3(kBlock), 0, s, B, O, kdone); break;
+        case 8: hipLaunchKernelGGL((k_finish<8>), grid, dim3(kBlock), 0, s, B, O, kdone); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -3,7 +3,7 @@ every step of the verification path runs in the library's HIP kernels.
 
 The functions keep the C names (kry_plan_create, kry_project_expm,
 kry_check_box_safety, kry_footprint, kry_plan_runs, kry_plan_krylov,
-kry_plan_block, kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
+kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
 tensors a plan borrows alive and destroys the plan when it is dropped.
 """
 from __future__ import annotations
@@ -77,6 +77,8 @@ def _load():
                                     ct.POINTER(ct.c_double), P]
     lib.kry_plan_block.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                                    ct.POINTER(ct.c_int32), P, P, P]
+    lib.kry_plan_set_error_target.argtypes = [P, ct.c_double]
+    lib.kry_plan_error.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
     lib.kry_plan_destroy.argtypes = [P]
     lib.kry_plan_destroy.restype = None
     lib.kry_last_error.restype = ct.c_char_p
@@ -84,8 +86,8 @@ def _load():
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
     for f in ("kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
-              "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_profile_enable", "kry_profile_reset",
-              "kry_profile_read"):
+              "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
+              "kry_plan_error", "kry_profile_enable", "kry_profile_reset", "kry_profile_read"):
         getattr(lib, f).restype = ct.c_int
     return lib
 
@@ -93,7 +95,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ["kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
-            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_destroy", "kry_last_error",
+            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_error",
+            "kry_plan_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
 
 
@@ -168,6 +171,18 @@ def kry_plan_krylov(plan: int, run: int, k: int, o: int):
     m = keff.value
     return {"k_eff": m, "beta0": beta0.value, "H": H[:m * m].reshape(m, m).copy(),
             "h_next": hn.value, "P": P[:o * m].reshape(o, m).copy()}
+
+
+def kry_plan_set_error_target(plan: int, eps: float):
+    _check(lib.kry_plan_set_error_target(plan, eps))
+
+
+def kry_plan_error(plan: int, run: int):
+    """(k_used, bound) of one run."""
+    k = ct.c_int32()
+    b = ct.c_double()
+    _check(lib.kry_plan_error(plan, run, ct.byref(k), ct.byref(b)))
+    return k.value, b.value
 
 
 def kry_plan_block(plan: int, block: int, o: int):
@@ -324,6 +339,14 @@ class Plan:
 
     def krylov(self, run: int):
         return kry_plan_krylov(self.handle, run, self.k, self.o)
+
+    def set_error_target(self, eps: float):
+        """Error-controlled Krylov dimension (see kry_plan_set_error_target)."""
+        kry_plan_set_error_target(self.handle, eps)
+
+    def error(self, run: int):
+        """(k_used, bound) of a run after project_expm."""
+        return kry_plan_error(self.handle, run)
 
     def blocks(self):
         """Block Arnoldi plans: one dict per block run (see kry_plan_block)."""

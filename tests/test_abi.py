@@ -118,3 +118,13 @@ def test_plan_rejects_bad_arguments(bad):
     expected = kry.KRY_EINVAL
     assert ei.value.status == expected
     assert len(kry.lib.kry_last_error()) > 0
+
+
+def test_error_control_entry_points_reject_null_plan():
+    from paper_1804_01583_amd import kry
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_plan_set_error_target(None, 1e-6)
+    assert ei.value.status == kry.KRY_EINVAL
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_plan_error(None, 0)
+    assert ei.value.status == kry.KRY_EINVAL
