@@ -117,7 +117,7 @@ def main():
     achieved = dom.get("GBps", 0.0)
     traffic = None
     if args.workload == "heat3d_csr" and (args.m or 100) == 100 and not f32:
-        traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_csr_heat3d_m100_pmc.md"))
+        traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_sell_heat3d_m100_pmc.md"))
 
     cpu = None
     if not args.no_cpu_baseline and p.n <= 2_000_000:
@@ -242,8 +242,12 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
     else:
         mat = 0                                                   # matrix-free
     lanczos = p.symmetric
+    # the sliced-ELL copy: values and int32 columns of the nnz entries, 12
+    # bytes of slice offset and width per 64 rows (padding is not counted)
+    mat_sell = ((4 if es == 4 else 8) + 4) * nnz + 12 * (-(-n // 64)) if p.kind == "csr" else 0
     per_launch = {
         "spmv_csr": mat + (3 if lanczos else 2) * vec,        # read v_j (and v_{j-1}), write w
+        "spmv_sell": mat_sell + (3 if lanczos else 2) * vec,
         "spmv_stencil": (3 if lanczos else 2) * vec,
         "sweep": 3 * vec,                                     # read v_j, w; write w
         "start": vec,                                         # write u_1
@@ -282,7 +286,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
         return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
                 "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
                 "dom_name": dom_name}
-    mv = "spmv_csr" if p.kind == "csr" else "spmv_stencil"
+    mv = ("spmv_sell" if "spmv_sell" in kern else "spmv_csr") if p.kind == "csr" else "spmv_stencil"
     # the roofline kernel: the mat-vec, or the one with the most time when a
     # stored-basis pass outweighs it
     dom_name = mv

@@ -69,7 +69,7 @@ Profiler& prof() {
 }
 
 const char* kKernelNames =
-    "row_abs_max,start,spmv_csr,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
+    "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
     "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl";
 
 // Runs `launch` bracketed by events when profiling is on.
@@ -931,7 +931,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                 if (plan->use_sell) {
                     SellArgs A{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth), plan->at<int32_t>(Y.scol),
                                f32 ? nullptr : plan->at<double>(Y.sval), f32 ? plan->at<float>(Y.sval) : nullptr};
-                    e = timed("spmv_csr", s, [&] { return launch_spmv_sell(P, f32, A, ucur, uprev, w, B, j, s); });
+                    e = timed("spmv_sell", s, [&] { return launch_spmv_sell(P, f32, A, ucur, uprev, w, B, j, s); });
                 } else {
                     CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
                     e = timed("spmv_csr", s, [&] {

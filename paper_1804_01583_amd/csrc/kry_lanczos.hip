@@ -188,13 +188,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restr
             for (int i = 0; i < RC; ++i) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const bool ok = e0[i] + sub + (int64_t)u * LPR < e1[i];
                     // element-wise gathers keep the live registers (and so the
-                    // occupancy) lower than one wide load per row
+                    // occupancy) lower than one wide load per row; a masked
+                    // slot adds 0 * u[0] unconditionally (a non-finite u is
+                    // flagged through its norm anyway), so no gather waits
+                    // behind a branch of its own
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const double x = (double)ucur[(int64_t)c[i][u] * P + p];
-                        acc[i][p] = ok ? fma(a[i][u], x, acc[i][p]) : acc[i][p];
+                        acc[i][p] = fma(a[i][u], x, acc[i][p]);
                     }
                 }
             }

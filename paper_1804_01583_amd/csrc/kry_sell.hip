@@ -162,12 +162,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
                     const double v = sizeof(E) == 4 ? (double)A.val32[idx] : A.val[idx];
                     a[u] = kb + u < wd[i] ? v : 0.0;
                 }
+                // unconditional: a slot past the width adds 0 * (an entry the
+                // row already reads); a conditional use lets the compiler move
+                // each gather behind a branch of its own and wait for it there
 #pragma unroll
                 for (int u = 0; u < KU; ++u) {
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const double x = (double)ucur[(int64_t)c[u] * P + p];
-                        acc[i][p] = kb + u < wd[i] ? fma(a[u], x, acc[i][p]) : acc[i][p];
+                        acc[i][p] = fma(a[u], x, acc[i][p]);
                     }
                 }
             }
@@ -232,11 +235,12 @@ hipError_t launch_spmv_sell_e(int P, const SellArgs& A, const void* ucur, const 
     const E* uc = static_cast<const E*>(ucur);
     const E* up = static_cast<const E*>(uprev);
     E* ww = static_cast<E*>(w);
+    const dim3 g(B.nblocks), b(kBlock);
     switch (P) {
-        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
-        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
-        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
-        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8>), dim3(B.nblocks), dim3(kBlock), 0, s, A, uc, up, ww, B, j); break;
+        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8>), g, b, 0, s, A, uc, up, ww, B, j); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
