@@ -69,6 +69,8 @@ def main():
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--error-target", type=float, default=0.0,
+                    help="Lanczos workloads: choose each run's Krylov dimension by the Lemma 1 bound (k is the cap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
@@ -102,12 +104,13 @@ def main():
     method = kry.KRY_BLOCK_ARNOLDI if method_name == "block" else kry.KRY_AUTO
     dsys = kry.DeviceSystem(p, device="cuda")
     f32 = args.precision == "fp32"
-    m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method)
+    m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
+                args.error_target)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
         log("plain FP64 on the same workload, for the ratio")
-        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup, method)
+        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup, method, args.error_target)
         fp64_ref = {"value": m64["value"], "ms_per_step": m64["ms_per_step"],
                     "ratio_fp32_over_fp64": m["value"] / m64["value"]}
     kern, nruns, verdict = m["kern"], m["nruns"], m["verdict"]
@@ -140,13 +143,15 @@ def main():
         "config": {"workload": describe(p, nruns, args.precision, method_name), "n": n, "nnz": nnz, "k": p.k,
                    "time_steps": p.steps, "runs": nruns, "precision": args.precision,
                    "method": "block_arnoldi" if method_name == "block" else
-                             ("lanczos" if p.symmetric else "arnoldi")},
+                             ("lanczos" if p.symmetric else "arnoldi"),
+                   "error_target": args.error_target or None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom_name,
                      "bytes_per_launch": dom.get("bytes")},
         "ms_per_step_with_kernel_events": m["ms_per_step_ev"],
         "kernels": kern,
         "fp64_reference": fp64_ref,
+        "error_control": m.get("error_control"),
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
     }
@@ -191,16 +196,22 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
-def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
+def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0):
     """Times `steps` whole verifications (after `warmup`), then the same with
     per-kernel HIP events; returns the throughput and per-kernel figures."""
     stream = torch.cuda.current_stream()
+    used = {}
 
     def step():
         plan = kry.Plan(dsys, stream=stream, precision=precision, method=method)
+        if error_target > 0.0:
+            plan.set_error_target(error_target)
         plan.project_expm(None)
         v = plan.check(p.unsafe)
         nr = plan.nruns
+        if error_target > 0.0 and not used:
+            used["k_used"] = [plan.error(r)[0] for r in range(nr)]
+            used["bound"] = [plan.error(r)[1] for r in range(nr)]
         plan.close()
         return v, nr
 
@@ -285,7 +296,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
                        key=lambda n_: kern[n_]["total_ms_per_step"])
         return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
                 "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
-                "dom_name": dom_name}
+                "dom_name": dom_name, "error_control": used or None}
     mv = ("spmv_sell" if "spmv_sell" in kern else "spmv_csr") if p.kind == "csr" else "spmv_stencil"
     # the roofline kernel: the mat-vec, or the one with the most time when a
     # stored-basis pass outweighs it
@@ -295,7 +306,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0):
             dom_name = name
     return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
             "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
-            "dom_name": dom_name}
+            "dom_name": dom_name, "error_control": used or None}
 
 
 def describe(p, nruns, precision, method_name="auto"):

@@ -324,19 +324,6 @@ double stencil_inf_norm(const kry_system& s) {
     return best;
 }
 
-// Numerator coefficients of the [13/13] Pade approximant of e^x, scaled so
-// the x^13 coefficient is 1: b_j = (26 - j)! / (j! (13 - j)!), exact in 64-bit
-// integers (the largest, 26!/13!, is below 2^56) and rounded once to double.
-void pade13(double* b) {
-    for (int j = 0; j <= 13; ++j) {
-        uint64_t num = 1;
-        for (int t = 14 - j; t <= 26 - j; ++t) num *= (uint64_t)t;   // (26-j)! / (13-j)!
-        uint64_t den = 1;
-        for (int t = 2; t <= j; ++t) den *= (uint64_t)t;            // j!
-        b[j] = (double)(num / den);
-    }
-}
-
 // Nodes and weights of the 8-point Gauss-Legendre rule on [-1, 1]: roots of
 // the Legendre polynomial P_8 by Newton's method from the Chebyshev-like
 // guesses cos(pi (i - 1/4) / (8 + 1/2)); w_i = 2 / ((1 - x_i^2) P_8'(x_i)^2).
@@ -408,6 +395,8 @@ struct kry_plan {
     bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
     bool use_sell = false;    // the mat-vec reads the sliced-ELL copy
     double err_eps = 0.0;     // error target of the a-posteriori k (0: fixed k)
+    double* hflags = nullptr; // pinned host copy of a batch's stop flags
+    hipEvent_t flag_ev = nullptr;
     double lam_plus = 0.0;    // max(0, Gershgorin bound of lambda_max of the symmetric part of A)
 
     void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
@@ -910,7 +899,8 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
         const bool lanczos = plan->method == KRY_LANCZOS;
-        int kdone = plan->k, next_check = 4;
+        int next_check = 4;
+        bool poll_pending = false;
         ErrArgs X{};
         if (plan->err_eps > 0.0) {
             X.role = plan->role_dev;
@@ -920,6 +910,9 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             gauss_legendre8(X.gl_x, X.gl_w);
             X.flags = plan->at<double>(Y.eflags);
             X.hess = plan->hess_mode ? 1 : 0;
+            B.stop = X.flags;
+            e = launch_fill(X.flags, kMaxP, 0.0, s);
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("error control: ") + hipGetErrorString(e));
         }
         for (int j = 1; j <= plan->k; ++j) {
             // FP64 Lanczos rotates three vectors (Algorithm 4); otherwise u_1..u_{k+1} are kept
@@ -970,25 +963,32 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
                 }
             }
-            // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k);
-            // the batch ends once every run met the target
+            // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k).
+            // Once every run of the batch met the target, the kernels of the
+            // iterations already queued return at once (B.stop); the host
+            // stops queueing when a non-blocking look at the flags of an
+            // earlier checkpoint finds them all set.
             if (plan->err_eps > 0.0 && j == next_check) {
                 next_check = (11 * next_check + 9) / 10;
                 e = timed("errctl", s, [&] { return launch_record_stage(P, B, j, s); });
                 if (e == hipSuccess) e = timed("errctl", s, [&] { return launch_lemma1(P, B, X, j, s); });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("error control: ") + hipGetErrorString(e));
-                double flags[kMaxP];
-                KRY_HIP(hipMemcpyAsync(flags, X.flags, P * sizeof(double), hipMemcpyDeviceToHost, s));
-                KRY_HIP(hipStreamSynchronize(s));
-                bool all = true;
-                for (int p = 0; p < P; ++p) all = all && flags[p] != 0.0;
-                if (all) {
-                    kdone = j;
-                    break;
+                if (poll_pending && hipEventQuery(plan->flag_ev) == hipSuccess) {
+                    poll_pending = false;
+                    bool all = true;
+                    for (int p = 0; p < P; ++p) all = all && plan->hflags[p] != 0.0;
+                    if (all) break;
+                }
+                if (!poll_pending) {
+                    KRY_HIP(hipMemcpyAsync(plan->hflags, X.flags, P * sizeof(double), hipMemcpyDeviceToHost, s));
+                    KRY_HIP(hipEventRecord(plan->flag_ev, s));
+                    poll_pending = true;
                 }
             }
         }
-        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, kdone, s); });
+        // with error control the finishing kernel takes the batch's Krylov
+        // dimension from the device (the largest stop of its runs)
+        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, plan->k, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
         r0 += P;
     }
@@ -1038,7 +1038,6 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         }
         return finish_projection(plan, basis_out);
     }
-    pade13(E.pade);
     E.Z = plan->zmat();
     E.anch = plan->anch();
     E.msize = plan->msize();
@@ -1155,6 +1154,8 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
         return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
     plan->err_eps = eps;
     if (eps == 0.0) return KRY_OK;
+    if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
+    if (!plan->flag_ev) KRY_HIP(hipEventCreateWithFlags(&plan->flag_ev, hipEventDisableTiming));
     // lambda_max of the symmetric part of A, bounded by Gershgorin
     double lam;
     if (plan->sys.kind == KRY_STENCIL7) {
@@ -1211,10 +1212,10 @@ kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks,
 
 void kry_plan_destroy(kry_plan* plan) {
     if (!plan) return;
-    if (plan->owns_ws && plan->ws) {
-        (void)hipStreamSynchronize(plan->stream);
-        (void)hipFree(plan->ws);
-    }
+    if (plan->flag_ev || (plan->owns_ws && plan->ws)) (void)hipStreamSynchronize(plan->stream);
+    if (plan->owns_ws && plan->ws) (void)hipFree(plan->ws);
+    if (plan->flag_ev) (void)hipEventDestroy(plan->flag_ev);
+    if (plan->hflags) (void)hipHostFree(plan->hflags);
     delete plan;
 }
 

@@ -31,6 +31,7 @@ using namespace dev;
 
 template <typename E, int P>
 __global__ __launch_bounds__(kBlock) void k_arn_dots(ArnArgs A, BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int NV = kArnChunk * P;
     __shared__ double s_lds[(kBlock / 64) * NV];
     const int lb = logical_block(B.nblocks, B.xcd_map);
@@ -67,15 +68,13 @@ __global__ __launch_bounds__(kBlock) void k_arn_dots(ArnArgs A, BatchArgs B, int
 // One block per basis vector i: h = sigma_i * (u_i . w) over all row blocks.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_arn_reduce(ArnArgs A, BatchArgs B, int j, int pass) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     __shared__ double s_lds[(kBlock / 64) * P];
     const int i = blockIdx.x;
     double acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) acc[p] += A.hpart[((int64_t)i * kMaxP + p) * B.nblocks + b];
-    }
+    add_strided_partials<P>(A.hpart + (int64_t)i * kMaxP * B.nblocks, B.nblocks, 0, acc);
     const double t = block_sum<P>(acc, s_lds);
     if (threadIdx.x < P) {
         const int p = threadIdx.x;
@@ -98,6 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_arn_reduce(ArnArgs A, BatchArgs B, i
 template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_arn_update(SegTable T, int32_t oset0, ArnArgs A, BatchArgs B, int j,
                                                        int last) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int NV = P * (1 + O);
     __shared__ double s_lds[(kBlock / 64) * NV];
     __shared__ double s_c[kMaxKD * P];

@@ -51,6 +51,18 @@ __device__ __forceinline__ int logical_block(int nblocks, int xcd_map = 1) {
     return (int)(blockIdx.x & 7) * (nblocks >> 3) + (int)(blockIdx.x >> 3);
 }
 
+// Error control: once every run of the batch has met its error target, the
+// iterations the host has already queued do nothing (the host does not wait
+// for the flags at each checkpoint).  False when the Krylov dimension is fixed.
+template <int P>
+__device__ __forceinline__ bool batch_stopped(const BatchArgs& B) {
+    if (B.stop == nullptr) return false;
+    bool all = true;
+#pragma unroll
+    for (int p = 0; p < P; ++p) all = all && B.stop[p] != 0.0;
+    return all;
+}
+
 // Writes the block totals of v as partials part[i * nblocks + block].
 template <int NV>
 __device__ __forceinline__ void store_partials(double (&v)[NV], double* part, int nblocks, double* lds,
@@ -59,6 +71,79 @@ __device__ __forceinline__ void store_partials(double (&v)[NV], double* part, in
     if (threadIdx.x < NV) part[(int64_t)threadIdx.x * nblocks + logical_block(nblocks, xcd_map)] = t;
 }
 
+// acc[i] += part[(vbeg + i) * nb + b] for b = first, first + kBlock, ..., in
+// that order.  The loads of U consecutive b are issued before any is
+// waited for: a plain loop waits for each load pair in turn (a wait covers
+// every earlier load), serialising the round trips.
+template <int NV>
+struct PartialLoads {
+    static constexpr int U = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
+};
+template <int NV>
+__device__ __forceinline__ void add_strided_partials(const double* part, int nb, int vbeg, double (&acc)[NV],
+                                                     int first) {
+    constexpr int U = PartialLoads<NV>::U;
+    for (int b0 = first; b0 < nb; b0 += U * kBlock) {
+        double v[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // clamped, unconditional loads (a load under a condition becomes
+            // a branch that waits for it); entries past nb are not added
+            const int b = min(b0 + u * kBlock, nb - 1);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[u][i] = part[(int64_t)(vbeg + i) * nb + b];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (b0 + u * kBlock < nb) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[i] += v[u][i];
+            }
+        }
+    }
+}
+template <int NV>
+__device__ __forceinline__ void add_strided_partials(const double* part, int nb, int vbeg, double (&acc)[NV]) {
+    add_strided_partials<NV>(part, nb, vbeg, acc, (int)threadIdx.x);
+}
+
+// The same sum split in two, so that other loads can be issued between
+// them: issue() requests the first U strided partials into registers, sum()
+// adds them and the rest, in the same order as add_strided_partials.
+// Requires nb >= 1.
+template <int NV>
+struct PartialBatch {
+    static constexpr int U = PartialLoads<NV>::U;
+    double v[U][NV];
+    __device__ __forceinline__ void issue(const double* part, int nb, int vbeg) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = min((int)threadIdx.x + u * kBlock, nb - 1);   // nb >= 1; see above
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[u][i] = part[(int64_t)(vbeg + i) * nb + b];
+        }
+    }
+    __device__ __forceinline__ void sum(const double* part, int nb, int vbeg, double (&acc)[NV]) const {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if ((int)threadIdx.x + u * kBlock < nb) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) {
+                    // opaque to the optimiser: the sum stays where sum() is
+                    // called instead of being hoisted (with its wait for the
+                    // loads) ahead of the caller's own loads
+                    double x = v[u][i];
+                    asm volatile("" : "+v"(x));
+                    acc[i] += x;
+                }
+            }
+        }
+        add_strided_partials<NV>(part, nb, vbeg, acc, (int)threadIdx.x + U * kBlock);
+    }
+};
+
 // Totals of values vbeg..vbeg+NV-1 of a partial array over nb blocks, in a
 // fixed order; result in s_out[0..NV) for every thread.
 template <int NV>
@@ -66,10 +151,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nb, int vbe
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += part[(int64_t)(vbeg + i) * nb + b];
-    }
+    add_strided_partials<NV>(part, nb, vbeg, acc);
     const double t = block_sum<NV>(acc, lds);
     if (threadIdx.x < NV) s_out[threadIdx.x] = t;
     __syncthreads();
@@ -204,8 +286,9 @@ __device__ __forceinline__ double* stage_part(const BatchArgs& B, int stage) {
     return B.np_part + (int64_t)stage * B.nvp * B.nblocks;
 }
 
-// Loads for the reduction of stage j-1's norms, issued before any row work
-// so their latency overlaps it; thread t sums blocks t, t + kBlock, ...
+// The reduction of stage j-1's norms, done first: thread t sums blocks t,
+// t + kBlock, ... (every block reads the same few KB of partials; issuing
+// them alongside the row work, instead of before it, measured slower)
 template <int P>
 __device__ __forceinline__ void load_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
                                                  double (&sig_prev)[P], double& anorm) {
@@ -255,19 +338,30 @@ struct SegStage {
     int32_t beg[NS], end[NS];
 };
 
-// Every thread must call it.  sets[i] < 0 stages an empty set.
+// Two halves, so a kernel can issue other loads between them: thread i < NS
+// loads set i's segment range for the block (seg_range), then every thread
+// calls stage_segments with it.  sets[i] < 0 stages an empty set.
+struct SegRange {
+    int32_t b, e;
+};
 template <int NS>
-__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, const int (&sets)[NS],
-                                               int lb, int nblocks) {
+__device__ __forceinline__ SegRange seg_range(const SegTable& T, const int (&sets)[NS], int lb, int nblocks) {
+    SegRange r{0, 0};
     if (threadIdx.x < NS) {
         const int s = sets[threadIdx.x];
-        int32_t b = 0, e = 0;
         if (s >= 0) {
-            b = T.blk[((int64_t)s * nblocks + lb) * 2];
-            e = T.blk[((int64_t)s * nblocks + lb) * 2 + 1];
+            r.b = T.blk[((int64_t)s * nblocks + lb) * 2];
+            r.e = T.blk[((int64_t)s * nblocks + lb) * 2 + 1];
         }
-        st.beg[threadIdx.x] = b;
-        st.end[threadIdx.x] = e;
+    }
+    return r;
+}
+
+template <int NS>
+__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, SegRange r) {
+    if (threadIdx.x < NS) {
+        st.beg[threadIdx.x] = r.b;
+        st.end[threadIdx.x] = r.e;
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < NS * kSegCap; idx += kBlock) {
@@ -280,6 +374,13 @@ __device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable&
         }
     }
     __syncthreads();
+}
+
+// Both halves at once.  Every thread must call it.
+template <int NS>
+__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, const int (&sets)[NS],
+                                               int lb, int nblocks) {
+    stage_segments<NS>(st, T, seg_range<NS>(T, sets, lb, nblocks));
 }
 
 // Weight of increasing rows in one staged set, amortised O(1) per row.

@@ -29,16 +29,14 @@ constexpr int kQuadNodes = (kQuadLevels + 1) * kQuadSplit * 8;
 // next mat-vec would record them; one block.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_record_stage(BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     __shared__ double s_lds[(kBlock / 64) * P];
     __shared__ double s_nrm[P];
     const double* part = stage_part(B, j);
     double acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) acc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) acc[p] += part[(int64_t)p * B.nblocks + b];
-    }
+    add_strided_partials<P>(part, B.nblocks, 0, acc);
     const double t = block_sum<P>(acc, s_lds);
     if (threadIdx.x < P) s_nrm[threadIdx.x] = t;
     __syncthreads();
@@ -46,6 +44,13 @@ __global__ __launch_bounds__(kBlock) void k_record_stage(BatchArgs B, int j) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_lemma1(BatchArgs B, ErrArgs X, int j) {
+    {
+        // the whole batch stopped at an earlier checkpoint (a block that sees
+        // its own run's flag already set may skip: it would change nothing)
+        bool all = true;
+        for (int q = 0; q < (int)gridDim.x; ++q) all = all && X.flags[q] != 0.0;
+        if (all) return;
+    }
     __shared__ double s_d[kMaxKD], s_e[kMaxKD], s_q1[kMaxKD], s_qm[kMaxKD];
     __shared__ double s_red[kBlock / 64];
     __shared__ int s_state;   // 0 evaluate, 1 already stopped, 2 exact (breakdown), 3 no eigenvalues, 4 past k - 1

@@ -3,8 +3,9 @@
 // per-step box check that stands in for the LP of Section 2.1.
 //
 // Per run, one workgroup keeps H in LDS and computes
-//   Phi = e^{H dt}   by Pade [13/13] with scaling and squaring
-//                    (N. J. Higham, SIAM J. Matrix Anal. Appl. 26(4), 2005),
+//   Phi = e^{H dt}   by the degree-18 Taylor polynomial of H dt / 2^s with
+//                    |H dt / 2^s|_1 <= 1 (Paterson-Stockmeyer), then s squarings
+//                    (the same approximant as the dense stage for larger k),
 //   Psi = Phi^B      by squaring (B a power of two near sqrt(steps + 1)),
 // then two short chains, Z_r = P Phi^r (r < B) and a_b = Psi^b e_1, so that
 //   y_s = beta0 * Z_{s mod B} a_{s div B},   s = 0..steps,
@@ -22,87 +23,60 @@ namespace {
 
 constexpr int kLd = kMaxK + 1;          // padded LDS row length
 constexpr int kSlot = kMaxK * kLd;      // one matrix in LDS
-constexpr double kTheta13 = 5.371920351148152;   // Higham 2005: degree-13 limit of |X|_1
 
 __device__ __forceinline__ const double* run_scal(const ExpmArgs& E, int r) {
     return E.scal + (int64_t)r * E.L.stride;
 }
 
-// C = A * B(l, j) for mm x mm matrices in LDS (mm even); `extra(i, j)` is
-// added to each entry.  Each thread owns 2x2 output blocks.  C must not
-// alias A or the storage B reads.
-template <class FB, class FE>
-__device__ __forceinline__ void mm_lds(const double* A, FB Bf, double* C, int mm, FE extra) {
-    const int nb = mm >> 1;
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
-        const int i = 2 * (t / nb), j = 2 * (t % nb);
-        double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
-        for (int l = 0; l < mm; ++l) {
-            const double a0 = A[i * kLd + l], a1 = A[(i + 1) * kLd + l];
-            const double b0 = Bf(l, j), b1 = Bf(l, j + 1);
-            c00 = fma(a0, b0, c00);
-            c01 = fma(a0, b1, c01);
-            c10 = fma(a1, b0, c10);
-            c11 = fma(a1, b1, c11);
+// Barrier that orders LDS traffic only: a __syncthreads() would also wait for
+// every global store of the wave (the chain publishes one step per pass).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// C = A B + extra(i, j) for mm x mm matrices in LDS slots sa, sb, sc (mm
+// even, <= kMaxK; sc differs from sa and sb) on the f64 16x16x4 matrix cores:
+// the 16 x 16 output tiles are spread over the waves, entries past mm read as
+// zero.  Lane layout: A[m][k] in lane m + 16k, B[k][n] in lane n + 16k,
+// D[m][n] in lane n + 16 (m % 4), accumulator register m / 4.
+template <class FE>
+__device__ __forceinline__ void mm_mfma(double* lds, int sa, int sb, int sc, int mm, FE extra) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
+    const int mt = (mm + 15) >> 4;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int tile = wave; tile < mt * mt; tile += nw) {
+        const int ti = tile / mt, tj = tile % mt;
+        const int arow = ti * 16 + lr, bcol = tj * 16 + lr;
+        // every fragment of the tile is loaded before the first product (the
+        // loads pipeline); clamped addresses stay inside the slot, values past
+        // mm are masked to zero
+        const int ar = min(arow, mm - 1), bc = min(bcol, mm - 1);
+        constexpr int KS = kMaxK / 4;
+        double a[KS], b[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int kq = 4 * s + lk, kc = min(kq, mm - 1);
+            a[s] = lds[sa * kSlot + ar * kLd + kc];
+            b[s] = lds[sb * kSlot + kc * kLd + bc];
+            a[s] = (arow < mm && kq < mm) ? a[s] : 0.0;
+            b[s] = (bcol < mm && kq < mm) ? b[s] : 0.0;
         }
-        C[i * kLd + j] = c00 + extra(i, j);
-        C[i * kLd + j + 1] = c01 + extra(i, j + 1);
-        C[(i + 1) * kLd + j] = c10 + extra(i + 1, j);
-        C[(i + 1) * kLd + j + 1] = c11 + extra(i + 1, j + 1);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (4 * s < mm) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+        const int n = tj * 16 + lr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mrow = ti * 16 + 4 * r + lk;
+            if (mrow < mm && n < mm) lds[sc * kSlot + mrow * kLd + n] = acc[r] + extra(mrow, n);
+        }
     }
     __syncthreads();
-}
-
-__device__ __forceinline__ void square_lds(const double* A, double* C, int mm) {
-    mm_lds(A, [A](int l, int j) { return A[l * kLd + j]; }, C, mm, [](int, int) { return 0.0; });
-}
-
-// Solve M F = R in place (F overwrites R) by Gauss-Jordan elimination with
-// partial pivoting; M is destroyed.  mm <= 64 so one wave finds the pivot.
-__device__ void solve_lds(double* M, double* R, int mm, int* s_piv, double* s_f) {
-    for (int c = 0; c < mm; ++c) {
-        if (threadIdx.x < 64) {
-            const int r = c + threadIdx.x;
-            double v = (r < mm) ? fabs(M[r * kLd + c]) : -1.0;
-            int at = r;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(v, off, 64);
-                const int oa = __shfl_xor(at, off, 64);
-                if (ov > v || (ov == v && oa < at)) { v = ov; at = oa; }
-            }
-            if (threadIdx.x == 0) *s_piv = at;
-        }
-        __syncthreads();
-        const int piv = *s_piv;
-        if (piv != c) {
-            for (int j = threadIdx.x; j < 2 * mm; j += blockDim.x) {
-                double* X = (j < mm) ? M : R;
-                const int jj = (j < mm) ? j : j - mm;
-                const double t = X[c * kLd + jj];
-                X[c * kLd + jj] = X[piv * kLd + jj];
-                X[piv * kLd + jj] = t;
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x < mm) s_f[threadIdx.x] = M[threadIdx.x * kLd + c];
-        __syncthreads();
-        const double inv = 1.0 / s_f[c];
-        for (int j = threadIdx.x; j < 2 * mm; j += blockDim.x) {
-            double* X = (j < mm) ? M : R;
-            const int jj = (j < mm) ? j : j - mm;
-            X[c * kLd + jj] *= inv;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < mm * 2 * mm; e += blockDim.x) {
-            const int r = e / (2 * mm), j = e % (2 * mm);
-            if (r == c) continue;
-            double* X = (j < mm) ? M : R;
-            const int jj = (j < mm) ? j : j - mm;
-            X[r * kLd + jj] = fma(-s_f[r], X[c * kLd + jj], X[r * kLd + jj]);
-        }
-        __syncthreads();
-    }
 }
 
 // One workgroup per run: Phi, Psi and the two chains.
@@ -114,9 +88,7 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     double* S3 = lds + 3 * kSlot;
     double* S4 = lds + 4 * kSlot;
     double* S5 = lds + 5 * kSlot;
-    __shared__ double s_f[kMaxK];
     __shared__ double s_red[kExpmThreads / 64];
-    __shared__ int s_piv;
 
     const int run = blockIdx.x;
     const double* sc = run_scal(E, run);
@@ -159,7 +131,7 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     }
     __syncthreads();
 
-    // scaling: |X|_1 <= theta_13 after dividing by 2^sq
+    // scaling: |X / 2^sq|_1 <= 1
     double colsum = 0.0;
     if (tid < mm) {
         for (int i = 0; i < mm; ++i) colsum += fabs(S0[i * kLd + tid]);
@@ -171,7 +143,8 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     double nrm = 0.0;
     for (int w = 0; w < (int)blockDim.x / 64; ++w) nrm = fmax(nrm, s_red[w]);
     int sq = 0;
-    if (nrm > kTheta13) sq = (int)ceil(log2(nrm / kTheta13));
+    // a non-finite H (flagged by the iteration) gets no squarings
+    while (isfinite(nrm) && nrm > ldexp(1.0, sq) && sq < 1100) ++sq;
     const double shrink = ldexp(1.0, -sq);
     __syncthreads();
     for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
@@ -180,105 +153,121 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     }
     __syncthreads();
 
-    // Pade [13/13]: U = X (X6 (b13 X6 + b11 X4 + b9 X2) + b7 X6 + b5 X4 + b3 X2 + b1 I)
-    //               V =    X6 (b12 X6 + b10 X4 + b8 X2) + b6 X6 + b4 X4 + b2 X2 + b0 I
-    const double* b = E.pade;
-    square_lds(S0, S1, mm);                                                    // X2
-    square_lds(S1, S2, mm);                                                    // X4
-    mm_lds(S2, [S1](int l, int j) { return S1[l * kLd + j]; }, S3, mm,
-           [](int, int) { return 0.0; });                                      // X6
-    mm_lds(S3, [=](int l, int j) {
-               const int e = l * kLd + j;
-               return b[13] * S3[e] + b[11] * S2[e] + b[9] * S1[e];
-           }, S4, mm, [=](int i, int j) {
-               const int e = i * kLd + j;
-               return b[7] * S3[e] + b[5] * S2[e] + b[3] * S1[e] + (i == j ? b[1] : 0.0);
-           });                                                                 // U' in S4
-    mm_lds(S3, [=](int l, int j) {
-               const int e = l * kLd + j;
-               return b[12] * S3[e] + b[10] * S2[e] + b[8] * S1[e];
-           }, S5, mm, [=](int i, int j) {
-               const int e = i * kLd + j;
-               return b[6] * S3[e] + b[4] * S2[e] + b[2] * S1[e] + (i == j ? b[0] : 0.0);
-           });                                                                 // V in S5
-    mm_lds(S0, [S4](int l, int j) { return S4[l * kLd + j]; }, S1, mm,
-           [](int, int) { return 0.0; });                                      // U in S1
+    // Taylor polynomial of degree 18 by Paterson-Stockmeyer in chunks of 4:
+    //   T(X) = L0 + X4 (L1 + X4 (L2 + X4 (L3 + X4 L4))),
+    //   L_q = f_{4q} I + f_{4q+1} X + f_{4q+2} X2 + f_{4q+3} X3,  f_i = 1/i! (0 past 18);
+    // with |X|_1 <= 1 the remainder is below e/19! < 2e-17 relative.
+    double f[20];
+    f[0] = 1.0;
+    for (int i = 1; i < 20; ++i) f[i] = i <= 18 ? f[i - 1] / i : 0.0;
+    auto none = [](int, int) { return 0.0; };
+    mm_mfma(lds, 0, 0, 1, mm, none);                                           // X2
+    mm_mfma(lds, 1, 0, 2, mm, none);                                           // X3
+    mm_mfma(lds, 1, 1, 3, mm, none);                                           // X4
+    auto chunk = [=](int q, int i, int j) {
+        const int e = i * kLd + j;
+        return (i == j ? f[4 * q] : 0.0) + f[4 * q + 1] * S0[e] + f[4 * q + 2] * S1[e] + f[4 * q + 3] * S2[e];
+    };
     for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
-        const int e = (idx / mm) * kLd + idx % mm;
-        const double u = S1[e], v = S5[e];
-        S5[e] = v - u;
-        S1[e] = v + u;
+        const int i = idx / mm, c = idx % mm;
+        S4[i * kLd + c] = chunk(4, i, c);
     }
     __syncthreads();
-    solve_lds(S5, S1, mm, &s_piv, s_f);                                        // r13(X) in S1
+    mm_mfma(lds, 4, 3, 5, mm, [=](int i, int j) { return chunk(3, i, j); });
+    mm_mfma(lds, 5, 3, 4, mm, [=](int i, int j) { return chunk(2, i, j); });
+    mm_mfma(lds, 4, 3, 5, mm, [=](int i, int j) { return chunk(1, i, j); });
+    mm_mfma(lds, 5, 3, 4, mm, [=](int i, int j) { return chunk(0, i, j); });   // T(X) in S4
 
     // LDS matrices below are addressed as lds + slot * kSlot with an integer
     // slot, never through stored pointers, so the accesses stay ds_* (LDS)
     // instructions instead of generic flat ones.
-    // undo the scaling: Phi = r13(X)^(2^sq), ping-pong between slots 1 and 2
-    int phi = 1;
+    // undo the scaling: Phi = T(X)^(2^sq), ping-pong between slots 4 and 5
+    int phi = 4;
     for (int i = 0; i < sq; ++i) {
-        square_lds(lds + phi * kSlot, lds + (3 - phi) * kSlot, mm);
-        phi = 3 - phi;
+        mm_mfma(lds, phi, phi, 9 - phi, mm, none);
+        phi = 9 - phi;
     }
-    // Psi = Phi^B, ping-pong between slots 3 and 4
+    // Psi = Phi^B, ping-pong between slots 1 and 2
     int psi = phi;
-    for (int e = 1, nxt = 3; e < E.B; e <<= 1) {
-        square_lds(lds + psi * kSlot, lds + nxt * kSlot, mm);
+    for (int e = 1, nxt = 1; e < E.B; e <<= 1) {
+        mm_mfma(lds, psi, psi, nxt, mm, none);
         psi = nxt;
-        nxt = 7 - nxt;
+        nxt = 3 - nxt;
     }
     const double* Phi = lds + phi * kSlot;
     const double* Psi = lds + psi * kSlot;
 
-    // chains: Z_{r+1} = Z_r Phi (r + 1 < B), a_{b+1} = Psi a_b (b + 1 < nanch);
-    // slot 0 holds the ping-pong buffers: Z at [cur * kMaxO * kLd], a at [2 * kMaxO * kLd + cur * kLd]
+    // chains: Z_{r+1} = Z_r Phi (r + 1 < B), a_{b+1} = Psi a_b (b + 1 < nanch).
+    // Thread t < o mm owns Z entry (q, c) = (t / mm, t % mm) and keeps column c
+    // of Phi in registers; thread o mm + i (i < mm) owns anchor entry i and
+    // keeps row i of Psi.  Slot 0 holds the ping-pong vectors: Z at
+    // [cur * kMaxO * kLd], a at [2 * kMaxO * kLd + cur * kLd].
     constexpr int kZ = kMaxO * kLd;
-    for (int idx = tid; idx < o * mm; idx += blockDim.x) {
-        const int q = idx / mm, c = idx % mm;
-        double pv = 0.0;
-        if (c < m) {
-            const int col = bordered ? c - 1 : c;
-            pv = (col >= 0) ? sc[E.L.proj + q * (k + 1) + col] : 0.0;
-        }
-        lds[q * kLd + c] = pv;
-    }
-    if (tid < mm) lds[2 * kZ + tid] = (tid == 0) ? 1.0 : 0.0;
-    __syncthreads();
     double* Zg = E.Z + (int64_t)run * E.B * kMaxO * kMaxK;
     double* Ag = E.anch + (int64_t)run * E.nanch * kMaxK;
-    const int iters = max(E.B, E.nanch);
+    const int nz = o * mm;
+    const bool zthr = tid < nz, athr = tid >= nz && tid < nz + mm;
+    const int zq = zthr ? tid / mm : 0, zc_ = zthr ? tid % mm : 0, ai = athr ? tid - nz : 0;
+    double reg[kMaxK];
+#pragma unroll
+    for (int l = 0; l < kMaxK; ++l) {
+        double v = 0.0;
+        if (l < mm) {
+            if (zthr) v = Phi[l * kLd + zc_];
+            else if (athr) v = Psi[ai * kLd + l];
+        }
+        reg[l] = v;
+    }
+    // entries mm..kMaxK-1 of both ping-pong buffers stay zero, so the dot
+    // products below run over kMaxK entries without a branch
+    for (int idx = tid; idx < 2 * (kMaxO + 1) * kLd; idx += blockDim.x) {
+        const int row = idx / kLd, col = idx % kLd;
+        const int off = row < 2 * kMaxO ? row * kLd + col : 2 * kZ + (row - 2 * kMaxO) * kLd + col;
+        if (col >= mm) lds[off] = 0.0;
+    }
+    // step 0: Z_0 = P (bordered: column 0 is the augmented variable), a_0 = e_1
+    if (zthr) {
+        double pv = 0.0;
+        if (zc_ < m) {
+            const int col = bordered ? zc_ - 1 : zc_;
+            pv = (col >= 0) ? sc[E.L.proj + zq * (k + 1) + col] : 0.0;
+        }
+        lds[zq * kLd + zc_] = pv;
+        Zg[(int64_t)zq * kMaxK + zc_] = pv;
+    } else if (athr) {
+        const double v = ai == 0 ? 1.0 : 0.0;
+        lds[2 * kZ + ai] = v;
+        Ag[ai] = v;
+    }
+    __syncthreads();
+    const int iters = max(E.B, E.nanch) - 1;
     for (int r = 0; r < iters; ++r) {
         const int cur = r & 1, nxt = cur ^ 1;
-        const double* zc = lds + cur * kZ;
-        const double* ac = lds + 2 * kZ + cur * kLd;
-        // publish step r
-        if (r < E.B) {
-            for (int idx = tid; idx < o * mm; idx += blockDim.x) {
-                const int q = idx / mm, c = idx % mm;
-                Zg[((int64_t)r * kMaxO + q) * kMaxK + c] = zc[q * kLd + c];
+        // step r + 1 from step r; two accumulators halve the dependent chain
+        if (zthr && r + 1 < E.B) {
+            const double* zr = lds + cur * kZ + zq * kLd;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int l = 0; l < kMaxK; l += 2) {
+                a0 = fma(zr[l], reg[l], a0);
+                a1 = fma(zr[l + 1], reg[l + 1], a1);
             }
-        }
-        if (r < E.nanch) {
-            for (int c = tid; c < mm; c += blockDim.x) Ag[(int64_t)r * kMaxK + c] = ac[c];
-        }
-        // advance
-        if (tid < o * mm) {
-            if (r + 1 < E.B) {
-                const int q = tid / mm, c = tid % mm;
-                double acc = 0.0;
-                for (int l = 0; l < mm; ++l) acc = fma(zc[q * kLd + l], Phi[l * kLd + c], acc);
-                lds[nxt * kZ + q * kLd + c] = acc;
+            const double v = a0 + a1;
+            lds[nxt * kZ + zq * kLd + zc_] = v;
+            Zg[((int64_t)(r + 1) * kMaxO + zq) * kMaxK + zc_] = v;
+        } else if (athr && r + 1 < E.nanch) {
+            const double* ar = lds + 2 * kZ + cur * kLd;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int l = 0; l < kMaxK; l += 2) {
+                a0 = fma(reg[l], ar[l], a0);
+                a1 = fma(reg[l + 1], ar[l + 1], a1);
             }
-        } else if (tid < o * mm + mm) {
-            if (r + 1 < E.nanch) {
-                const int i = tid - o * mm;
-                double acc = 0.0;
-                for (int l = 0; l < mm; ++l) acc = fma(Psi[i * kLd + l], ac[l], acc);
-                lds[2 * kZ + nxt * kLd + i] = acc;
-            }
+            const double v = a0 + a1;
+            lds[2 * kZ + nxt * kLd + ai] = v;
+            Ag[(int64_t)(r + 1) * kMaxK + ai] = v;
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 

@@ -68,6 +68,7 @@ struct BatchArgs {
     int32_t ap_nblocks;      // blocks of the mat-vec launch (its own partition for the marching stencil)
     const double* anorm;     // ||A||_inf on the device
     double tau_scale;        // breakdown when beta_j <= tau_scale * ||A||_inf
+    const double* stop;      // error control: [P] nonzero once run p met its target; null: fixed k
 };
 
 struct CsrArgs {
@@ -115,7 +116,6 @@ struct ExpmArgs {
     int32_t hess_mode;       // 0: tridiagonal from alpha/beta (Lanczos); 1: Hessenberg (Arnoldi)
     int32_t B;               // anchor spacing (power of two)
     int32_t nanch;           // anchors per run: ceil((steps + 1) / B)
-    double pade[14];         // [13/13] Pade numerator coefficients, b_13 = 1
     double* Z;               // [nruns][B][kMaxO][kMaxK]  P Phi^r
     double* anch;            // [nruns][nanch][kMaxK]     Psi^b e_1
     int32_t* msize;          // [nruns] size of H used (0: the run contributes 0)

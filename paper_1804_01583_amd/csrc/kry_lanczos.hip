@@ -140,6 +140,7 @@ template <typename E, int P, int LPR>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restrict__ ucur,
                                                      const E* __restrict__ uprev,
                                                      E* __restrict__ w, BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int G = kBlock / LPR;
     constexpr int RC = 2;
     constexpr int U = P >= 8 ? 2 : (P >= 4 ? 4 : 8);
@@ -256,6 +257,7 @@ template <typename E, int P>
 __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const E* __restrict__ ucur,
                                                          const E* __restrict__ uprev,
                                                          E* __restrict__ w, BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     __shared__ double s_lds[(kBlock / 64) * P];
     __shared__ double s_nrm[P];
     const int lb = logical_block(B.nblocks, B.xcd_map);
@@ -370,6 +372,7 @@ template <typename E, int P>
 __global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, const E* __restrict__ ucur,
                                                                const E* __restrict__ uprev,
                                                                E* __restrict__ w, BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     __shared__ double s_lds[(kBlock / 64) * P];
     __shared__ double s_nrm[P];
     const int cb = logical_block(B.ap_nblocks, B.xcd_map);
@@ -426,6 +429,7 @@ template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                                                   const E* __restrict__ ucur,
                                                   E* __restrict__ w, BatchArgs B, int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int NV = P * (1 + O);
     constexpr int RC = 4;
     __shared__ double s_lds[(kBlock / 64) * NV];
@@ -434,53 +438,57 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
     const int lb = logical_block(B.nblocks, B.xcd_map);
     const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
-    // alpha partials and sigma_j: loads issued first
-    double pacc[P], sigj[P];
+    const int64_t span = (int64_t)kBlock * RC;
+    const int nch = max((int)((B.rows_per_block + span - 1) / span), 1);
+    // rows of chunk ch; dead rows read row 0 and drop it
+    double uv[RC][P], wv[RC][P];
+    int64_t rr[RC];
+    auto load_chunk = [&](int ch) {
 #pragma unroll
-    for (int p = 0; p < P; ++p) pacc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.ap_nblocks; b += kBlock) {
-#pragma unroll
-        for (int p = 0; p < P; ++p) pacc[p] += B.ap_part[(int64_t)p * B.ap_nblocks + b];
-    }
+        for (int i = 0; i < RC; ++i) {
+            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            const int64_t rl = rr[i] < r1 ? rr[i] : 0;
+            load_row<E, P>(ucur, rl, uv[i]);
+            load_row<E, P>(w, rl, wv[i]);
+        }
+    };
+    // Loads are issued in the order they are waited for (a wait covers every
+    // load issued before it): the alpha partials, sigma_j and the output
+    // sets' segment ranges, then the first chunk's rows, which stay in
+    // flight through the alpha reduction and the segment staging.
+    PartialBatch<P> pb;
+    pb.issue(B.ap_part, B.ap_nblocks, 0);
+    double sigj[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) sigj[p] = run_scal(B, p)[B.L.sigma + j];
     int sets[O];
 #pragma unroll
     for (int q = 0; q < O; ++q) sets[q] = oset0 + q;
-    stage_segments<O>(st, T, sets, lb, B.nblocks);
+    const SegRange srange = seg_range<O>(T, sets, lb, B.nblocks);
+    load_chunk(0);
+    stage_segments<O>(st, T, srange);
     SegCursor cur[O];
 #pragma unroll
     for (int q = 0; q < O; ++q) cur[q].init(st, q);
     double acc[NV], coef[P];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    {
+        double pacc[P];
+        pb.sum(B.ap_part, B.ap_nblocks, 0, pacc);
+        const double t = block_sum<P>(pacc, s_lds);
+        if (threadIdx.x < P) s_alpha[threadIdx.x] = t;
+        __syncthreads();
 #pragma unroll
-    for (int p = 0; p < P; ++p) coef[p] = 0.0;
-    const int64_t span = (int64_t)kBlock * RC;
-    const int nch = (int)((B.rows_per_block + span - 1) / span);
-    for (int ch = 0; ch < max(nch, 1); ++ch) {
-        double uv[RC][P], wv[RC][P];
-        int64_t rr[RC];
-#pragma unroll
-        for (int i = 0; i < RC; ++i) {
-            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
-            const bool live = rr[i] < r1;
-            const int64_t rl = live ? rr[i] : 0;    // dead rows read row 0 and drop it
-            load_row<E, P>(ucur, rl, uv[i]);
-            load_row<E, P>(w, rl, wv[i]);
+        for (int p = 0; p < P; ++p) coef[p] = s_alpha[p] * sigj[p];
+        if (blockIdx.x == 0 && threadIdx.x < P) {
+            double* sc = run_scal(B, threadIdx.x);
+            sc[B.L.alpha + j] = s_alpha[threadIdx.x];
+            if (!isfinite(s_alpha[threadIdx.x])) sc[B.L.misc + MISC_NONFINITE] = 1.0;
         }
-        if (ch == 0) {
-            const double t = block_sum<P>(pacc, s_lds);
-            if (threadIdx.x < P) s_alpha[threadIdx.x] = t;
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < P; ++p) coef[p] = s_alpha[p] * sigj[p];
-            if (blockIdx.x == 0 && threadIdx.x < P) {
-                double* sc = run_scal(B, threadIdx.x);
-                sc[B.L.alpha + j] = s_alpha[threadIdx.x];
-                if (!isfinite(s_alpha[threadIdx.x])) sc[B.L.misc + MISC_NONFINITE] = 1.0;
-            }
-        }
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch > 0) load_chunk(ch);
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
             if (rr[i] < r1) {
@@ -506,15 +514,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
     store_partials<NV>(acc, stage_part(B, j), B.nblocks, s_lds, B.xcd_map);
 }
 
-// After the last sweep, one block per stage c = 0..k: P[:, c] = sigma_{c+1} C u_{c+1}
-// from the stored partials of that stage; block k also records the final
-// stage (beta_k, sigma_{k+1}, and k_eff when the run breaks down there).
+// After the last sweep, one block per stage c = 0..kdone: P[:, c] = sigma_{c+1} C u_{c+1}
+// from the stored partials of that stage; block kdone also records the final
+// stage (beta_kdone, sigma_{kdone+1}, and k_eff when the run breaks down there).
 // Values are summed by groups of threads, each group in a fixed order.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o, int kdone) {
     __shared__ double s_part[kBlock];
     __shared__ double s_tot[P * (1 + kMaxO)];
     const int c = blockIdx.x;
+    if (B.stop != nullptr) {
+        // error control: the batch iterated up to the largest Krylov dimension
+        // its runs settled on (k when one of them never met its target)
+        int kd = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) kd = max(kd, (int)run_scal(B, p)[B.L.misc + MISC_KSTOP]);
+        kdone = min(kd, kdone);
+    }
     if (c > kdone) return;
     const int nv = P * (1 + o);
     const int grp = kBlock / nv;
@@ -522,7 +538,16 @@ __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o, int kdone
     const double* part = stage_part(B, c);
     double acc = 0.0;
     if (v < nv) {
-        for (int b = g; b < B.nblocks; b += grp) acc += part[(int64_t)v * B.nblocks + b];
+        // four loads in flight per step, summed in b order
+        const double* pv = part + (int64_t)v * B.nblocks;
+        for (int b0 = g; b0 < B.nblocks; b0 += 4 * grp) {
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = b0 + u * grp < B.nblocks ? pv[b0 + u * grp] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (b0 + u * grp < B.nblocks) acc += x[u];
+        }
     }
     s_part[threadIdx.x] = acc;
     __syncthreads();

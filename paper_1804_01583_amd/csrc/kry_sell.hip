@@ -117,6 +117,7 @@ template <typename E, int P>
 __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __restrict__ ucur,
                                                       const E* __restrict__ uprev, E* __restrict__ w, BatchArgs B,
                                                       int j) {
+    if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int RC = 2;
     constexpr int KU = 8;
     __shared__ double s_lds[(kBlock / 64) * P];
