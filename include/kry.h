@@ -72,7 +72,12 @@ typedef struct kry_segs {
  * symmetric: the caller promises A == A^T (needed by Lanczos, Section 4.3).
  * anorm: max absolute row sum of A, or 0 to let kry_plan compute it; it only
  *   scales the breakdown test (a Krylov step whose new norm is at most
- *   1024 * eps * anorm ends the run: the space is invariant, Section 4.2). */
+ *   1024 * eps * anorm ends the run: the space is invariant, Section 4.2).
+ * prepared: NULL, or a kry_matrix made by kry_matrix_create from this same
+ *   CSR system (same three arrays) for the plan's precision.  Plans then read
+ *   its sliced-ELL copy and its anorm instead of building their own, and
+ *   kry_footprint leaves the copy out. */
+typedef struct kry_matrix kry_matrix;
 typedef struct kry_system {
     int64_t n;
     int32_t kind;
@@ -86,6 +91,7 @@ typedef struct kry_system {
     const double* b;
     double anorm;
     const kry_segs* b_segs;
+    const kry_matrix* prepared;
 } kry_system;
 
 /* One column g_j of E with its box coefficient z_j in [zc - radius, zc + radius]
@@ -225,6 +231,22 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps);
 kry_status kry_plan_error(kry_plan* plan, int32_t run, int32_t* k_used, double* bound);
 
 void kry_plan_destroy(kry_plan* plan);
+
+/* kry_matrix_create -- device-side preparation of a KRY_CSR system that any
+ * number of plans can share (every simulation of Section 4.1, one per
+ * column of E, and every later query uses the same A): a sliced-ELL copy of
+ * A (slices of 64 rows,
+ * entries column-major within a slice and padded to the slice's longest row;
+ * FP64 values, or FP32 values for precision KRY_FP32_BASIS) and
+ * anorm = max absolute row sum, both computed on the device.  sys->vals,
+ * colidx and rowptr must not change while the matrix is in use.  The library
+ * allocates the matrix's device memory (kry_matrix_bytes reports it); the
+ * call waits for `hip_stream` (NULL: the default stream).  KRY_EINVAL for a
+ * stencil system, nnz = 0 or bad arguments; KRY_ENOMEM when allocation fails. */
+kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip_stream, kry_matrix** out);
+kry_status kry_matrix_bytes(const kry_matrix* mat, size_t* bytes);
+/* Frees the matrix; destroy the plans that use it first. */
+void kry_matrix_destroy(kry_matrix* mat);
 
 /* Thread-local text of the last error on this thread. */
 const char* kry_last_error(void);

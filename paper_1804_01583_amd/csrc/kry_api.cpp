@@ -137,7 +137,7 @@ constexpr int kProjGroups = 32;   // workgroups per output row in the block proj
 // CSR systems of the single-vector methods read a sliced-ELL copy (see
 // kry_sell.hip) unless KRY_SELL=0.
 int64_t sell_nnz_for(const kry_system& sys, int32_t method) {
-    if (sys.kind != KRY_CSR || method == KRY_BLOCK_ARNOLDI || sys.nnz <= 0) return 0;
+    if (sys.kind != KRY_CSR || method == KRY_BLOCK_ARNOLDI || sys.nnz <= 0 || sys.prepared) return 0;
     if (env_int("KRY_SELL", 1) == 0) return 0;
     return sys.nnz;
 }
@@ -359,6 +359,19 @@ kry_status prepare_device() {
 
 }  // namespace
 
+// A CSR system prepared once for many plans: sliced-ELL copy and ||A||_inf.
+struct kry_matrix {
+    int64_t n = 0, nnz = 0;
+    const int64_t* rowptr = nullptr;
+    const int32_t* colidx = nullptr;
+    const double* vals = nullptr;
+    int32_t precision = KRY_FP64;
+    char* mem = nullptr;
+    size_t bytes = 0;
+    kry::SellArgs sell{};
+    double* anorm_dev = nullptr;
+};
+
 struct kry_plan {
     kry_system sys{};
     int32_t ngen = 0, nruns = 0, o = 0, k = 0;
@@ -394,6 +407,8 @@ struct kry_plan {
     bool f32 = false;
     bool hess_mode = false;   // H assembled from the Hessenberg store (else alpha/beta tridiagonal)
     bool use_sell = false;    // the mat-vec reads the sliced-ELL copy
+    SellArgs sell{};          // that copy: the plan's own or a prepared matrix's
+    const double* anorm_dev = nullptr;   // ||A||_inf on the device (the plan's or a prepared matrix's)
     double err_eps = 0.0;     // error target of the a-posteriori k (0: fixed k)
     double* hflags = nullptr; // pinned host copy of a batch's stop flags
     hipEvent_t flag_ev = nullptr;
@@ -451,6 +466,12 @@ kry_status validate_system(const kry_system* sys) {
         return fail(KRY_EINVAL, "unknown system kind");
     }
     if (!(sys->anorm >= 0.0) || !std::isfinite(sys->anorm)) return fail(KRY_EINVAL, "anorm must be finite and >= 0");
+    if (sys->prepared) {
+        const kry_matrix* M = sys->prepared;
+        if (sys->kind != KRY_CSR || M->n != sys->n || M->nnz != sys->nnz || M->rowptr != sys->rowptr ||
+            M->colidx != sys->colidx || M->vals != sys->vals)
+            return fail(KRY_EINVAL, "the prepared matrix was made from another system");
+    }
     if (sys->b && sys->b_segs) return fail(KRY_EINVAL, "give the forcing as b or as b_segs, not both");
     if (sys->b_segs) {
         const kry_status st = check_segs(*sys->b_segs, sys->n, "forcing");
@@ -509,6 +530,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (steps < 0) return fail(KRY_EINVAL, "steps must be >= 0");
     if (!std::isfinite(dt)) return fail(KRY_EINVAL, "dt must be finite");
     if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+    if (sys->prepared && sys->prepared->precision != precision)
+        return fail(KRY_EINVAL, "the prepared matrix holds values of another precision");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
     if (method != KRY_LANCZOS && method != KRY_ARNOLDI && method != KRY_BLOCK_ARNOLDI)
         return fail(KRY_EINVAL, "unknown method");
@@ -650,7 +673,10 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
         return cleanup(fail(KRY_EDEVICE, "metadata upload failed"));
 
     // ||A||_inf scales the breakdown test
-    if (sys->anorm > 0.0 || sys->kind == KRY_STENCIL7) {
+    plan->anorm_dev = plan->anorm();
+    if (sys->prepared) {
+        plan->anorm_dev = sys->prepared->anorm_dev;
+    } else if (sys->anorm > 0.0 || sys->kind == KRY_STENCIL7) {
         const double a = sys->anorm > 0.0 ? sys->anorm : stencil_inf_norm(*sys);
         plan->verdict_host.assign(1, a);
         if (hipMemcpyAsync(plan->anorm(), plan->verdict_host.data(), sizeof(double), hipMemcpyHostToDevice,
@@ -685,7 +711,14 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
             });
             if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell fill: ") + hipGetErrorString(e)));
             plan->use_sell = true;
+            plan->sell = SellArgs{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth), plan->at<int32_t>(Y.scol),
+                                  plan->f32 ? nullptr : plan->at<double>(Y.sval),
+                                  plan->f32 ? plan->at<float>(Y.sval) : nullptr};
         }
+    }
+    if (sys->prepared && method != KRY_BLOCK_ARNOLDI) {
+        plan->use_sell = true;
+        plan->sell = sys->prepared->sell;
     }
     if (Y.vals32 && !plan->use_sell) {
         hipError_t e = launch_to_f32(sys->vals, plan->vals32(), sys->nnz, plan->stream);
@@ -744,7 +777,7 @@ kry_status project_block(kry_plan* plan) {
     B.R0 = plan->at<double>(Y.bR0);
     B.rfirst = plan->at<double>(Y.brfirst);
     B.state = plan->at<int32_t>(Y.bstate);
-    B.anorm = plan->anorm();
+    B.anorm = plan->anorm_dev;
     B.tau_scale = 1024.0 * (f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
     CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
     plan->blocks.clear();
@@ -882,7 +915,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
         B.nvp = Y.nvp;
         B.ap_part = plan->ap_part();
         B.ap_nblocks = Y.march > 0 ? Y.march : Y.nblocks;
-        B.anorm = plan->anorm();
+        B.anorm = plan->anorm_dev;
         B.tau_scale = tau_scale;
         StartSrc src{};
         for (int p = 0; p < kMaxP; ++p) { src.dense[p] = nullptr; src.set[p] = -1; }
@@ -922,8 +955,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             void* w = Y.stored ? plan->vec(j) : plan->vec(j % 3);
             if (plan->sys.kind == KRY_CSR) {
                 if (plan->use_sell) {
-                    SellArgs A{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth), plan->at<int32_t>(Y.scol),
-                               f32 ? nullptr : plan->at<double>(Y.sval), f32 ? plan->at<float>(Y.sval) : nullptr};
+                    const SellArgs& A = plan->sell;
                     e = timed("spmv_sell", s, [&] { return launch_spmv_sell(P, f32, A, ucur, uprev, w, B, j, s); });
                 } else {
                     CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
@@ -1208,6 +1240,90 @@ kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks,
     if (R0) std::copy(b.R0.begin(), b.R0.end(), R0);
     if (P) std::copy(b.P.begin(), b.P.end(), P);
     return KRY_OK;
+}
+
+kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip_stream, kry_matrix** out) {
+    if (!out) return fail(KRY_EINVAL, "out is NULL");
+    *out = nullptr;
+    kry_status st = validate_system(sys);
+    if (st != KRY_OK) return st;
+    if (sys->kind != KRY_CSR || sys->nnz <= 0) return fail(KRY_EINVAL, "a prepared matrix needs a CSR system with nnz > 0");
+    if (sys->prepared) return fail(KRY_EINVAL, "the system already names a prepared matrix");
+    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = sys->n, ns = sell_slices(n), nt = sell_scan_tiles(n);
+    const int64_t rpb = rows_per_block_for(n);
+    const int32_t nb = nblocks_for(n, rpb);
+    // first allocation: layout arrays, row-sum partials and the norm
+    size_t off = 0;
+    auto take = [&](size_t b) { const size_t o = off; off = align_up(off + b, 256); return o; };
+    const size_t o_width = take((size_t)ns * 4), o_off = take((size_t)(ns + 1) * 8), o_tiles = take((size_t)nt * 8);
+    const size_t o_part = take((size_t)nb * 8), o_norm = take(8);
+    const size_t head = off;
+    char* tmp = nullptr;
+    if (hipMalloc((void**)&tmp, head) != hipSuccess) return fail(KRY_ENOMEM, "prepared matrix: allocation failed");
+    auto bail = [&](kry_status code, const std::string& msg) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+        return fail(code, msg);
+    };
+    CsrArgs A{sys->rowptr, sys->colidx, sys->vals, nullptr};
+    hipError_t e = launch_sell_layout(A, n, reinterpret_cast<int32_t*>(tmp + o_width), reinterpret_cast<int64_t*>(tmp + o_off),
+                                      reinterpret_cast<int64_t*>(tmp + o_tiles), s);
+    if (e == hipSuccess)
+        e = launch_row_abs_max(A, n, reinterpret_cast<double*>(tmp + o_part), nb, rpb,
+                               reinterpret_cast<double*>(tmp + o_norm), s);
+    int64_t total = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&total, reinterpret_cast<int64_t*>(tmp + o_off) + ns, sizeof(total), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
+    // second allocation: the entries, after the layout
+    const size_t esz = precision == KRY_FP32_BASIS ? 4 : 8;
+    const size_t o_col = take((size_t)total * 4), o_val = take((size_t)total * esz);
+    kry_matrix* M = new kry_matrix();
+    M->bytes = off;
+    if (hipMalloc((void**)&M->mem, M->bytes) != hipSuccess) {
+        delete M;
+        return bail(KRY_ENOMEM, "prepared matrix: allocation failed");
+    }
+    e = hipMemcpyAsync(M->mem, tmp, head, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = launch_sell_fill(precision == KRY_FP32_BASIS, A, n, reinterpret_cast<int64_t*>(M->mem + o_off),
+                             reinterpret_cast<int32_t*>(M->mem + o_width), reinterpret_cast<int32_t*>(M->mem + o_col),
+                             M->mem + o_val, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) {
+        (void)hipFree(M->mem);
+        delete M;
+        return fail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
+    }
+    M->n = n;
+    M->nnz = sys->nnz;
+    M->rowptr = sys->rowptr;
+    M->colidx = sys->colidx;
+    M->vals = sys->vals;
+    M->precision = precision;
+    M->sell = SellArgs{reinterpret_cast<int64_t*>(M->mem + o_off), reinterpret_cast<int32_t*>(M->mem + o_width),
+                       reinterpret_cast<int32_t*>(M->mem + o_col),
+                       precision == KRY_FP32_BASIS ? nullptr : reinterpret_cast<double*>(M->mem + o_val),
+                       precision == KRY_FP32_BASIS ? reinterpret_cast<float*>(M->mem + o_val) : nullptr};
+    M->anorm_dev = reinterpret_cast<double*>(M->mem + o_norm);
+    *out = M;
+    return KRY_OK;
+}
+
+kry_status kry_matrix_bytes(const kry_matrix* mat, size_t* bytes) {
+    if (!mat || !bytes) return fail(KRY_EINVAL, "NULL argument");
+    *bytes = mat->bytes;
+    return KRY_OK;
+}
+
+void kry_matrix_destroy(kry_matrix* mat) {
+    if (!mat) return;
+    if (mat->mem) (void)hipFree(mat->mem);
+    delete mat;
 }
 
 void kry_plan_destroy(kry_plan* plan) {

@@ -3,7 +3,8 @@ every step of the verification path runs in the library's HIP kernels.
 
 The functions keep the C names (kry_plan_create, kry_project_expm,
 kry_check_box_safety, kry_footprint, kry_plan_runs, kry_plan_krylov,
-kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy).  ``Plan`` is a small owner object that keeps the device
+kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy, kry_matrix_create,
+kry_matrix_bytes, kry_matrix_destroy).  ``Plan`` is a small owner object that keeps the device
 tensors a plan borrows alive and destroys the plan when it is dropped.
 """
 from __future__ import annotations
@@ -40,7 +41,8 @@ class KrySystem(ct.Structure):
                 ("rowptr", ct.c_void_p), ("colidx", ct.c_void_p), ("vals", ct.c_void_p),
                 ("nnz", ct.c_int64), ("nx", ct.c_int64), ("ny", ct.c_int64), ("nz", ct.c_int64),
                 ("c0", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double), ("cz", ct.c_double),
-                ("b", ct.c_void_p), ("anorm", ct.c_double), ("b_segs", ct.POINTER(KrySegs))]
+                ("b", ct.c_void_p), ("anorm", ct.c_double), ("b_segs", ct.POINTER(KrySegs)),
+                ("prepared", ct.c_void_p)]
 
 
 class KryGen(ct.Structure):
@@ -79,6 +81,10 @@ def _load():
                                    ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_plan_set_error_target.argtypes = [P, ct.c_double]
     lib.kry_plan_error.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
+    lib.kry_matrix_create.argtypes = [ct.POINTER(KrySystem), ct.c_int32, P, ct.POINTER(P)]
+    lib.kry_matrix_bytes.argtypes = [P, ct.POINTER(ct.c_size_t)]
+    lib.kry_matrix_destroy.argtypes = [P]
+    lib.kry_matrix_destroy.restype = None
     lib.kry_plan_destroy.argtypes = [P]
     lib.kry_plan_destroy.restype = None
     lib.kry_last_error.restype = ct.c_char_p
@@ -87,7 +93,8 @@ def _load():
     lib.kry_profile_names.restype = ct.c_char_p
     for f in ("kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
-              "kry_plan_error", "kry_profile_enable", "kry_profile_reset", "kry_profile_read"):
+              "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
+              "kry_profile_reset", "kry_profile_read"):
         getattr(lib, f).restype = ct.c_int
     return lib
 
@@ -96,7 +103,7 @@ lib = _load()
 
 EXPORTED = ["kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_error",
-            "kry_plan_destroy", "kry_last_error",
+            "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
 
 
@@ -171,6 +178,22 @@ def kry_plan_krylov(plan: int, run: int, k: int, o: int):
     m = keff.value
     return {"k_eff": m, "beta0": beta0.value, "H": H[:m * m].reshape(m, m).copy(),
             "h_next": hn.value, "P": P[:o * m].reshape(o, m).copy()}
+
+
+def kry_matrix_create(system: KrySystem, precision=KRY_FP64, stream_ptr=None) -> int:
+    out = ct.c_void_p()
+    _check(lib.kry_matrix_create(ct.byref(system), precision, stream_ptr, ct.byref(out)))
+    return out.value
+
+
+def kry_matrix_bytes(mat: int) -> int:
+    b = ct.c_size_t()
+    _check(lib.kry_matrix_bytes(mat, ct.byref(b)))
+    return b.value
+
+
+def kry_matrix_destroy(mat: int):
+    lib.kry_matrix_destroy(mat)
 
 
 def kry_plan_set_error_target(plan: int, eps: float):
@@ -273,7 +296,34 @@ class DeviceSystem:
         if problem.center is not None:
             self.center = torch.as_tensor(np.asarray(problem.center, np.float64), device=device)
         s.anorm = 0.0
+        s.prepared = None
         self.sys = s
+        self.prepared = {}
+
+    def prepare(self, precision=KRY_FP64, stream=None):
+        """kry_matrix_create for this CSR system and precision, once: plans of
+        that precision then share its sliced-ELL copy and norm."""
+        if precision not in self.prepared:
+            sp = None if stream is None else stream.cuda_stream
+            self.prepared[precision] = kry_matrix_create(self.sys, precision, sp)
+        return self.prepared[precision]
+
+    def system_for(self, precision) -> KrySystem:
+        """The kry_system a plan of `precision` gets (with its prepared matrix)."""
+        s = KrySystem.from_buffer_copy(self.sys)
+        s.prepared = self.prepared.get(precision)
+        return s
+
+    def close(self):
+        for h in self.prepared.values():
+            kry_matrix_destroy(h)
+        self.prepared = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 - interpreter shutdown
+            pass
 
 
 class Plan:
@@ -286,6 +336,7 @@ class Plan:
         import torch
         p = dsys.problem
         self.dsys = dsys
+        self._sys = dsys.system_for(precision)
         self.k = p.k if k is None else k
         self.dt = p.dt if dt is None else dt
         self.steps = p.steps if steps is None else steps
@@ -306,12 +357,12 @@ class Plan:
             nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
             if getattr(p, "b_seg", None) is not None and dsys.b is None:
                 nseg += p.b_seg.nseg
-            ws_bytes = kry_footprint(dsys.sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
+            ws_bytes = kry_footprint(self._sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
                                      method, block_p)
             self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dsys.device)
             ws_ptr = self.workspace.data_ptr()
         self.handle = None
-        self.handle = kry_plan_create(dsys.sys, self._gens, _ptr(dsys.center), self._C, self.k, self.dt,
+        self.handle = kry_plan_create(self._sys, self._gens, _ptr(dsys.center), self._C, self.k, self.dt,
                                       self.steps, precision, method, block_p, ws_ptr, ws_bytes,
                                       self.stream.cuda_stream)
         self.roles = kry_plan_runs(self.handle)

@@ -15,8 +15,9 @@ systems).  The server
 A query's result does not depend on what runs beside it: every kernel's
 arithmetic and reduction order depend only on the query's own sizes.
 
-Systems are resident: a catalog holds one device copy per (family, grid)
-and queries borrow them.
+Systems are resident: a catalog holds one device copy per (family, grid),
+with the prepared matrix (sliced-ELL copy and norm) of each precision a
+CSR system is queried in, and queries borrow them.
 """
 from __future__ import annotations
 
@@ -39,18 +40,23 @@ class Catalog:
         self._systems: Dict[Tuple[str, int], "kry.DeviceSystem"] = {}
         self._lock = threading.Lock()
 
-    def get(self, family: str, m: int):
+    def get(self, family: str, m: int, precision=None):
+        """The resident system; with `precision`, a CSR system also holds its
+        prepared matrix (sliced-ELL copy and norm) for that precision."""
         import workloads as W
         key = (family, m)
         with self._lock:
             if key not in self._systems:
                 self._systems[key] = kry.DeviceSystem(W.serving_system(family, m), device=self.device)
-            return self._systems[key]
+            ds = self._systems[key]
+            if precision is not None and ds.problem.kind == "csr":
+                ds.prepare(precision)
+            return ds
 
     def preload(self, queries):
         import torch
         for q in queries:
-            self.get(q.family, q.m)
+            self.get(q.family, q.m, _precision(q))
         torch.cuda.synchronize(self.device)
 
     def resident_bytes(self) -> int:
@@ -60,7 +66,12 @@ class Catalog:
                 t = getattr(ds, name, None)
                 if t is not None:
                     total += t.numel() * t.element_size()
+            total += sum(kry.kry_matrix_bytes(h) for h in ds.prepared.values())
         return total
+
+
+def _precision(q):
+    return kry.KRY_FP32_BASIS if q.precision == "fp32" else kry.KRY_FP64
 
 
 @dataclass
@@ -103,15 +114,16 @@ class Server:
     def footprint(self, q) -> int:
         if self._footprint is not None:
             return self._footprint(q)
-        dsys = self.catalog.get(q.family, q.m)
-        prec = kry.KRY_FP32_BASIS if q.precision == "fp32" else kry.KRY_FP64
+        prec = _precision(q)
+        dsys = self.catalog.get(q.family, q.m, prec)
         nseg = sum(g.seg.nseg for g in q.gens) + sum(c.nseg for c in q.C)
-        return kry.kry_footprint(dsys.sys, len(q.gens), len(q.C), q.k, q.steps, nseg, prec, kry.KRY_AUTO, 0)
+        return kry.kry_footprint(dsys.system_for(prec), len(q.gens), len(q.C), q.k, q.steps, nseg, prec,
+                                 kry.KRY_AUTO, 0)
 
     def _run_one(self, q, stream, keep_basis: bool):
         import torch
-        dsys = self.catalog.get(q.family, q.m)
-        prec = kry.KRY_FP32_BASIS if q.precision == "fp32" else kry.KRY_FP64
+        prec = _precision(q)
+        dsys = self.catalog.get(q.family, q.m, prec)
         with torch.cuda.stream(stream):
             plan = kry.Plan(dsys, k=q.k, dt=q.dt, steps=q.steps, precision=prec, stream=stream, gens=q.gens, C=q.C)
             out = None

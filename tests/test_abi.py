@@ -36,15 +36,16 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "kry.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(kry_system), sizeof(kry_segs),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(kry_system), sizeof(kry_segs),"
         " sizeof(kry_gen), sizeof(kry_interval), sizeof(kry_verdict), offsetof(kry_system, b),"
-        " offsetof(kry_system, anorm), offsetof(kry_verdict, y)); return 0;}\n")
+        " offsetof(kry_system, anorm), offsetof(kry_verdict, y), offsetof(kry_system, prepared)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     import ctypes as ct
     want = [ct.sizeof(kry.KrySystem), ct.sizeof(kry.KrySegs), ct.sizeof(kry.KryGen), ct.sizeof(kry.KryInterval),
-            ct.sizeof(kry.KryVerdict), kry.KrySystem.b.offset, kry.KrySystem.anorm.offset, kry.KryVerdict.y.offset]
+            ct.sizeof(kry.KryVerdict), kry.KrySystem.b.offset, kry.KrySystem.anorm.offset, kry.KryVerdict.y.offset,
+            kry.KrySystem.prepared.offset]
     assert got == want
 
 
@@ -128,3 +129,19 @@ def test_error_control_entry_points_reject_null_plan():
     with pytest.raises(kry.KryError) as ei:
         kry.kry_plan_error(None, 0)
     assert ei.value.status == kry.KRY_EINVAL
+
+
+def test_prepared_matrix_entry_points_reject_bad_arguments():
+    from paper_1804_01583_amd import kry
+    import ctypes as ct
+    out = ct.c_void_p()
+    assert kry.lib.kry_matrix_create(None, 0, None, ct.byref(out)) == kry.KRY_EINVAL
+    s = kry.KrySystem()
+    s.n, s.kind, s.nx, s.ny, s.nz = 8, kry.KRY_STENCIL7, 2, 2, 2
+    assert kry.lib.kry_matrix_create(ct.byref(s), 0, None, ct.byref(out)) == kry.KRY_EINVAL   # stencil
+    c = _csr_system(50)
+    assert kry.lib.kry_matrix_create(ct.byref(c), 9, None, ct.byref(out)) == kry.KRY_EINVAL   # precision
+    b = ct.c_size_t()
+    assert kry.lib.kry_matrix_bytes(None, ct.byref(b)) == kry.KRY_EINVAL
+    kry.lib.kry_matrix_destroy(None)
+
