@@ -62,10 +62,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=None, help="grid edge (default 100; 1000 for heat3d_stencil)")
     ap.add_argument("--workload", default="heat3d_csr",
-                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "serve"],
+                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper", "serve"],
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--method", default=None, choices=["auto", "block"])
+    ap.add_argument("--method", default=None, choices=["auto", "block", "plain"])
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--slots", type=int, default=8)
@@ -100,10 +100,15 @@ def main():
         p = W.heat3d_stencil(m=args.m or 1000)
     elif args.workload == "heat1d":
         p = W.heat1d()
+    elif args.workload == "heat3d_paper":
+        # the paper's heat benchmark (Section 5.3) with its error-controlled k (target 1e-6)
+        p = W.heat3d_paper(m=args.m or 100)
+        if not args.error_target:
+            args.error_target = 1e-6
     else:
         p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=16, o=5, k=30)
-    method_name = args.method or ("block" if args.workload == "conv_diff3d" else "auto")
-    method = kry.KRY_BLOCK_ARNOLDI if method_name == "block" else kry.KRY_AUTO
+    method_name = args.method or {"conv_diff3d": "block", "heat3d_paper": "plain"}.get(args.workload, "auto")
+    method = {"block": kry.KRY_BLOCK_ARNOLDI, "plain": kry.KRY_LANCZOS_PLAIN}.get(method_name, kry.KRY_AUTO)
     dsys = kry.DeviceSystem(p, device="cuda")
     f32 = args.precision == "fp32"
     prepared = p.kind == "csr" and not args.no_prepared
@@ -150,8 +155,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(p, nruns, args.precision, method_name), "n": n, "nnz": nnz, "k": p.k,
                    "time_steps": p.steps, "runs": nruns, "precision": args.precision,
-                   "method": "block_arnoldi" if method_name == "block" else
-                             ("lanczos" if p.symmetric else "arnoldi"),
+                   "method": {"block": "block_arnoldi", "plain": "lanczos_plain"}.get(
+                       method_name, "lanczos" if p.symmetric else "arnoldi"),
                    "error_target": args.error_target or None,
                    "matrix": ("prepared once (sliced-ELL copy and norm shared by every verification)" if prepared
                               else ("built by every plan" if p.kind == "csr" else "matrix-free stencil"))},
@@ -334,6 +339,11 @@ def describe(p, nruns, precision, method_name="auto"):
         m = p.meta["m"]
         return (f"3D heat {m}^3 matrix-free 7-point (n={p.n}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
                 f"{p.steps} steps, o={p.o}, runs={nruns}, {prec}")
+    if p.name == "heat3d_paper":
+        m = p.meta["m"]
+        return (f"3D heat {m}^3 as in the paper (insulated faces, exchange 0.5 at x=1, CSR n={p.n}, nnz={p.nnz}), "
+                f"centre-point output, three-vector Lanczos with the Lemma 1 error control (k <= {p.k}), "
+                f"dt={p.dt}, {p.steps} steps, {prec}")
     return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} {prec}"
 
 

@@ -46,7 +46,13 @@ typedef enum {
 typedef enum { KRY_FP64 = 0, KRY_FP32_BASIS = 1 } kry_precision;
 
 /* KRY_AUTO picks Lanczos when the system is declared symmetric. */
-typedef enum { KRY_AUTO = 0, KRY_LANCZOS = 1, KRY_ARNOLDI = 2, KRY_BLOCK_ARNOLDI = 3 } kry_method;
+typedef enum {
+    KRY_AUTO = 0,
+    KRY_LANCZOS = 1,
+    KRY_ARNOLDI = 2,
+    KRY_BLOCK_ARNOLDI = 3,
+    KRY_LANCZOS_PLAIN = 4
+} kry_method;
 
 typedef enum { KRY_CSR = 0, KRY_STENCIL7 = 1 } kry_kind;
 
@@ -124,7 +130,8 @@ typedef struct kry_plan kry_plan;
  * [x_c; 0] when center != NULL (device n-vector), one for the augmented
  * variable [0; 1] when sys->b or sys->b_segs is given.
  *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
- *  k: Krylov dimension per run, 1 <= k <= 56.  The augmented run uses k-1
+ *  k: Krylov dimension per run, 1 <= k <= 512 (2048 for KRY_LANCZOS_PLAIN);
+ *     past k = 56 the small exponential runs as a dense stage.  The augmented run uses k-1
  *     Lanczos steps on A from b bordered by one row and column, which spans
  *     the same k-dimensional Krylov space of the augmented matrix.  For
  *     KRY_BLOCK_ARNOLDI, k counts block steps (1 <= k <= 32; dimension p k).
@@ -135,7 +142,11 @@ typedef struct kry_plan kry_plan;
  *     it (Lanczos: one classical pass after the three-term step; Arnoldi and
  *     block Arnoldi: two passes).  Breakdown then uses eps of FP32.
  *  method: KRY_AUTO (Lanczos when symmetric, else Arnoldi), KRY_LANCZOS
- *     (Algorithm 3; needs symmetric), KRY_ARNOLDI (Algorithm 1, classical
+ *     (Algorithm 3; needs symmetric; past k = 56 it keeps its basis and
+ *     reorthogonalises each new vector once), KRY_LANCZOS_PLAIN (the
+ *     three-vector projected Lanczos of Algorithm 4 at any k: three
+ *     n-vectors per run, no reorthogonalisation, FP64 only; the same as
+ *     KRY_LANCZOS for k <= 56), KRY_ARNOLDI (Algorithm 1, classical
  *     Gram-Schmidt twice), or KRY_BLOCK_ARNOLDI: the generators in blocks of
  *     p <= 16 columns, each block one block Krylov space
  *     span{G, AG, ..., A^{k-1} G} with C e^{At} G ~ C V e^{Ht} E_1 R_0

@@ -189,7 +189,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.esize = precision == KRY_FP32_BASIS ? 4 : 8;
     // Lanczos keeps its basis and reorthogonalises when it stores FP32 vectors
     // or runs past k = 56 (plain three-term Lanczos loses orthogonality there)
-    Y.stored = method == KRY_ARNOLDI || precision == KRY_FP32_BASIS || k > kMaxK;
+    Y.stored = method == KRY_ARNOLDI || precision == KRY_FP32_BASIS || (k > kMaxK && method != KRY_LANCZOS_PLAIN);
     Y.pmax = std::min(max_batch_for(o, block_p), std::max(1, nruns));
     if (Y.stored) Y.pmax = std::min(Y.pmax, 2);     // dot partials: 16 vectors x P per block
     {
@@ -493,7 +493,7 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     if (st != KRY_OK) return st;
     if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : kMaxKD;
+    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : (method == KRY_LANCZOS_PLAIN ? kMaxKP : kMaxKD);
     if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kmax || steps < 0 || nseg_total < 0)
         return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 512 (32 block steps), steps >= 0, "
                                 "nseg_total >= 0 required");
@@ -524,6 +524,8 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
     if (method == KRY_BLOCK_ARNOLDI) {
         if (k < 1 || k > kMaxKB) return fail(KRY_EINVAL, "block Arnoldi: k (block steps) must be in [1, 32]");
+    } else if (method == KRY_LANCZOS_PLAIN) {
+        if (k < 1 || k > kMaxKP) return fail(KRY_EINVAL, "plain Lanczos: k must be in [1, 2048]");
     } else if (k < 1 || k > kMaxKD) {
         return fail(KRY_EINVAL, "k must be in [1, 512]");
     }
@@ -533,9 +535,12 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (sys->prepared && sys->prepared->precision != precision)
         return fail(KRY_EINVAL, "the prepared matrix holds values of another precision");
     if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    if (method != KRY_LANCZOS && method != KRY_ARNOLDI && method != KRY_BLOCK_ARNOLDI)
+    if (method != KRY_LANCZOS && method != KRY_ARNOLDI && method != KRY_BLOCK_ARNOLDI && method != KRY_LANCZOS_PLAIN)
         return fail(KRY_EINVAL, "unknown method");
-    if (method == KRY_LANCZOS && !sys->symmetric) return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
+    if ((method == KRY_LANCZOS || method == KRY_LANCZOS_PLAIN) && !sys->symmetric)
+        return fail(KRY_EINVAL, "Lanczos needs a symmetric system");
+    if (method == KRY_LANCZOS_PLAIN && precision != KRY_FP64)
+        return fail(KRY_ENOTSUP, "plain Lanczos runs in FP64 (FP32 storage needs the reorthogonalised basis)");
     if (block_p < 0) return fail(KRY_EINVAL, "block_p must be >= 0");
     if (method == KRY_BLOCK_ARNOLDI) {
         if (sys->kind != KRY_CSR) return fail(KRY_ENOTSUP, "block Arnoldi needs a CSR system");
@@ -594,7 +599,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys), precision,
                           nnz32, sell_nnz_for(*sys, method));
-    plan->method = method;
+    plan->method = method == KRY_LANCZOS_PLAIN ? KRY_LANCZOS : method;   // the layout tells plain from reorthogonalised
     plan->f32 = precision == KRY_FP32_BASIS;
     plan->hess_mode = plan->Y.stored;
     const Layout& Y = plan->Y;

@@ -12,6 +12,7 @@ constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kMaxO = 8;         // output rows
 constexpr int kMaxK = 56;        // Krylov dimension of the one-workgroup LDS exponential
 constexpr int kMaxKD = 512;      // Krylov dimension with the dense stage (k > kMaxK)
+constexpr int kMaxKP = 2048;     // Krylov dimension of three-vector (plain) Lanczos
 constexpr int kExpmThreads = 512;
 constexpr int kMaxP = 8;         // runs advanced per mat-vec launch
 constexpr int kMaxNV = 24;       // values reduced per block: P * (1 + O)

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libkry.so")
 
 KRY_OK, KRY_EINVAL, KRY_ENOMEM, KRY_EDEVICE, KRY_ENUMERIC, KRY_ENOTSUP = range(6)
 KRY_FP64, KRY_FP32_BASIS = 0, 1
-KRY_AUTO, KRY_LANCZOS, KRY_ARNOLDI, KRY_BLOCK_ARNOLDI = range(4)
+KRY_AUTO, KRY_LANCZOS, KRY_ARNOLDI, KRY_BLOCK_ARNOLDI, KRY_LANCZOS_PLAIN = range(5)
 KRY_CSR, KRY_STENCIL7 = 0, 1
 ROLE_NAMES = {0: "gen", 1: "center", 2: "affine"}
 

@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Segments", "Generator", "Problem",
     "segments_from_ranges", "box_segments", "csr_stencil7",
-    "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil",
+    "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil", "heat3d_paper", "csr_heat_insulated",
     "random_symmetric", "small_heat3d", "conv_diff3d",
 ]
 
@@ -261,6 +261,63 @@ def heat3d_csr(m=100, D=0.01, k=40, dt=0.02, steps=2000, seed=2, unsafe_scale=No
                    b=b, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
                    meta={"m": m, "forcing_box": fbox, "gen_box": gbox, "center_box": cbox, "coef": coef},
                    note="3D heat CSR with affine forcing")
+
+
+def csr_heat_insulated(m, c, exchange_diag):
+    """CSR of the cell-centred 7-point heat operator on an m^3 grid with
+    insulated faces (no flux: a face without a neighbour adds neither the
+    neighbour nor its -c to the diagonal) plus `exchange_diag` added to the
+    diagonal of the cells on the x = 1 face (ix = m - 1).  Symmetric."""
+    n = m**3
+    if n >= 2**31:
+        raise ValueError("CSR expansion limited to n < 2^31 (int32 columns)")
+    idx = np.arange(n, dtype=np.int64)
+    iz = idx % m
+    iy = (idx // m) % m
+    ix = idx // (m * m)
+    nbrs = [(-m * m, ix > 0), (-m, iy > 0), (-1, iz > 0), (1, iz < m - 1), (m, iy < m - 1), (m * m, ix < m - 1)]
+    diag = -c * sum(ok.astype(np.float64) for _, ok in nbrs) + np.where(ix == m - 1, exchange_diag, 0.0)
+    cols = np.empty((n, 7), dtype=np.int64)
+    vals = np.empty((n, 7), dtype=np.float64)
+    mask = np.empty((n, 7), dtype=bool)
+    order = nbrs[:3] + [(0, None)] + nbrs[3:]
+    for j, (d, ok) in enumerate(order):
+        cols[:, j] = idx + d
+        vals[:, j] = diag if ok is None else c
+        mask[:, j] = True if ok is None else ok
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(mask.sum(axis=1), out=rowptr[1:])
+    return rowptr, cols[mask].astype(np.int32), vals[mask]
+
+
+def heat3d_paper(m=100, D=0.01, exchange=0.5, k=1024, dt=0.02, steps=1000) -> Problem:
+    """The 3D heat benchmark as the paper states it (Section 5.3): unit cube,
+    all faces insulated except x = 1, which exchanges heat with a 0-degree
+    ambient at constant 0.5; u_t = D (u_xx + u_yy + u_zz), D = 0.01;
+    initially 0.9..1.1 on x in [0, 0.4], y in [0, 0.2], z in [0, 0.1] and 0
+    elsewhere; output = the temperature at the centre point; T = 20 with
+    dt = 0.02.  Discretised here by cell-centred finite volumes (h = 1/m):
+    interior fluxes D (u_j - u_i) / h, no flux through insulated faces, and
+    through the x = 1 face the flux D * exchange * u of the boundary cell, i.e.
+    -c h exchange on those cells' diagonal (c = D / h^2).  The centre point
+    is the mean of the 8 cells around it (m even) or the centre cell (m odd).
+    k is the cap of an error-controlled Krylov dimension."""
+    n = m**3
+    h = 1.0 / m
+    c = D / h**2
+    rowptr, colidx, vals = csr_heat_insulated(m, c, -c * h * exchange)
+    ext = [max(int(round(f * m)), 1) for f in (0.4, 0.2, 0.1)]
+    gbox = ((0, ext[0]), (0, ext[1]), (0, ext[2]))
+    gens = [Generator(box_segments((m, m, m), gbox, 1.0), zc=1.0, radius=0.1)]
+    mid = [m // 2 - 1, m // 2] if m % 2 == 0 else [m // 2]
+    cbox = tuple((mid[0], mid[-1] + 1) for _ in range(3))
+    cells = len(mid) ** 3
+    C = [box_segments((m, m, m), cbox, 1.0 / cells)]
+    unsafe = np.array([[1.0, math.inf]])
+    return Problem("heat3d_paper", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   rowptr=rowptr, colidx=colidx, vals=vals,
+                   meta={"m": m, "gen_box": gbox, "center_box": cbox, "c": c, "h": h, "exchange": exchange},
+                   note="3D heat as stated in the paper: insulated faces, exchange at x = 1, centre-point output")
 
 
 def small_heat3d(m=12, D=0.01, k=20, dt=0.02, steps=200, seed=7) -> Problem:
