@@ -455,21 +455,31 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
     // Loads are issued in the order they are waited for (a wait covers every
     // load issued before it): the alpha partials, sigma_j and the output
     // sets' segment ranges, then the first chunk's rows, which stay in
-    // flight through the alpha reduction and the segment staging.
+    // flight through the alpha reduction and any segment staging.
     PartialBatch<P> pb;
     pb.issue(B.ap_part, B.ap_nblocks, 0);
     double sigj[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) sigj[p] = run_scal(B, p)[B.L.sigma + j];
-    int sets[O];
+    // every thread reads the output sets' segment ranges for this block
+    // (uniform addresses); most blocks meet no output segment and then skip
+    // the staging, its barriers and the per-row weights
+    SegRange own{0, 0};
+    bool any = false;
 #pragma unroll
-    for (int q = 0; q < O; ++q) sets[q] = oset0 + q;
-    const SegRange srange = seg_range<O>(T, sets, lb, B.nblocks);
+    for (int q = 0; q < O; ++q) {
+        const int32_t* rq = T.blk + ((int64_t)(oset0 + q) * B.nblocks + lb) * 2;
+        const SegRange r{rq[0], rq[1]};
+        any = any || r.e > r.b;
+        if ((int)threadIdx.x == q) own = r;
+    }
     load_chunk(0);
-    stage_segments<O>(st, T, srange);
     SegCursor cur[O];
+    if (any) {
+        stage_segments<O>(st, T, own);
 #pragma unroll
-    for (int q = 0; q < O; ++q) cur[q].init(st, q);
+        for (int q = 0; q < O; ++q) cur[q].init(st, q);
+    }
     double acc[NV], coef[P];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
@@ -500,12 +510,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                     acc[p] = fma(val[p], val[p], acc[p]);
                 }
                 store_row<E, P>(w, r, val);
+                if (any) {
 #pragma unroll
-                for (int q = 0; q < O; ++q) {
-                    const double cw = cur[q].weight(st, q, T, r);
-                    if (cw != 0.0) {
+                    for (int q = 0; q < O; ++q) {
+                        const double cw = cur[q].weight(st, q, T, r);
+                        if (cw != 0.0) {
 #pragma unroll
-                        for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+                            for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+                        }
                     }
                 }
             }
