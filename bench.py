@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=None, help="grid edge (default 100; 1000 for heat3d_stencil)")
+    ap.add_argument("--k", type=int, default=None, help="Krylov dimension (matrix-free paper heat only)")
+    ap.add_argument("--no-kernel-events", action="store_true",
+                    help="skip the second timed pass with per-kernel events (long runs)")
     ap.add_argument("--workload", default="heat3d_csr",
                     choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper", "serve"],
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
@@ -101,10 +104,16 @@ def main():
     elif args.workload == "heat1d":
         p = W.heat1d()
     elif args.workload == "heat3d_paper":
-        # the paper's heat benchmark (Section 5.3) with its error-controlled k (target 1e-6)
-        p = W.heat3d_paper(m=args.m or 100)
-        if not args.error_target:
-            args.error_target = 1e-6
+        # the paper's heat benchmark (Section 5.3): up to 160^3 as CSR with its
+        # error-controlled k (target 1e-6); larger grids matrix-free at the
+        # paper's k = 5932 (the error control holds k <= 2048)
+        m = args.m or 100
+        if m <= 160:
+            p = W.heat3d_paper(m=m)
+            if not args.error_target:
+                args.error_target = 1e-6
+        else:
+            p = W.heat3d_paper_stencil(m=m, k=args.k or 5932)
     else:
         p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=16, o=5, k=30)
     method_name = args.method or {"conv_diff3d": "block", "heat3d_paper": "plain"}.get(args.workload, "auto")
@@ -118,7 +127,7 @@ def main():
             dsys.prepare(prec)
         torch.cuda.synchronize()
     m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
-                args.error_target)
+                args.error_target, not args.no_kernel_events)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
@@ -211,7 +220,7 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
-def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0):
+def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0, kernel_events=True):
     """Times `steps` whole verifications (after `warmup`), then the same with
     per-kernel HIP events; returns the throughput and per-kernel figures."""
     stream = torch.cuda.current_stream()
@@ -243,16 +252,18 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
     elapsed = time.perf_counter() - t0
     # timed region 2: the same steps with every kernel launch bracketed by HIP
     # events on the plan's stream -> per-kernel durations for the roofline
-    log(f"timing {steps} steps with per-kernel events")
-    kry.profile_enable(True)
-    kry.profile_reset()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(steps):
-        verdict, nruns = step()
-    torch.cuda.synchronize()
-    elapsed_ev = time.perf_counter() - t1
-    kry.profile_enable(False)
+    elapsed_ev = float("nan")
+    if kernel_events:
+        log(f"timing {steps} steps with per-kernel events")
+        kry.profile_enable(True)
+        kry.profile_reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            verdict, nruns = step()
+        torch.cuda.synchronize()
+        elapsed_ev = time.perf_counter() - t1
+        kry.profile_enable(False)
     kern = {}
     for name in kry.profile_names():
         cnt, ms = kry.profile_read(name)
@@ -339,6 +350,10 @@ def describe(p, nruns, precision, method_name="auto"):
         m = p.meta["m"]
         return (f"3D heat {m}^3 matrix-free 7-point (n={p.n}) + affine forcing, Lanczos k={p.k}, dt={p.dt}, "
                 f"{p.steps} steps, o={p.o}, runs={nruns}, {prec}")
+    if p.name == "heat3d_paper_stencil":
+        m = p.meta["m"]
+        return (f"3D heat {m}^3 as in the paper (insulated faces, exchange 0.5 at x=1, matrix-free n={p.n}), "
+                f"centre-point output, three-vector Lanczos k={p.k}, dt={p.dt}, {p.steps} steps, {prec}")
     if p.name == "heat3d_paper":
         m = p.meta["m"]
         return (f"3D heat {m}^3 as in the paper (insulated faces, exchange 0.5 at x=1, CSR n={p.n}, nnz={p.nnz}), "

@@ -79,6 +79,13 @@ typedef struct kry_segs {
  * anorm: max absolute row sum of A, or 0 to let kry_plan compute it; it only
  *   scales the breakdown test (a Krylov step whose new norm is at most
  *   1024 * eps * anorm ends the run: the space is invariant, Section 4.2).
+ * stencil_bc (KRY_STENCIL7): KRY_BC_DIRICHLET (0; zero outside the grid) or
+ *   KRY_BC_INSULATED (1; no flux through the faces: a face cell's missing
+ *   neighbour is dropped together with its share of the diagonal, i.e. the
+ *   diagonal becomes c0 + cx per missing x neighbour + cy ... + cz ...).
+ * stencil_exchange (KRY_STENCIL7): added to the diagonal of the cells of the
+ *   face ix = nx - 1 (heat exchange through x = 1 with a zero ambient, the
+ *   3D heat benchmark of Section 5.3); 0 for none.
  * prepared: NULL, or a kry_matrix made by kry_matrix_create from this same
  *   CSR system (same three arrays) for the plan's precision.  Plans then read
  *   its sliced-ELL copy and its anorm instead of building their own, and
@@ -98,7 +105,11 @@ typedef struct kry_system {
     double anorm;
     const kry_segs* b_segs;
     const kry_matrix* prepared;
+    int32_t stencil_bc;
+    double stencil_exchange;
 } kry_system;
+
+enum { KRY_BC_DIRICHLET = 0, KRY_BC_INSULATED = 1 };
 
 /* One column g_j of E with its box coefficient z_j in [zc - radius, zc + radius]
  * (Section 3.2, initial space I_z given as a box). */
@@ -130,7 +141,7 @@ typedef struct kry_plan kry_plan;
  * [x_c; 0] when center != NULL (device n-vector), one for the augmented
  * variable [0; 1] when sys->b or sys->b_segs is given.
  *  C, o: o >= 1 output rows (host segment sets, Section 3.1); o <= 8.
- *  k: Krylov dimension per run, 1 <= k <= 512 (2048 for KRY_LANCZOS_PLAIN);
+ *  k: Krylov dimension per run, 1 <= k <= 512 (8192 for KRY_LANCZOS_PLAIN);
  *     past k = 56 the small exponential runs as a dense stage.  The augmented run uses k-1
  *     Lanczos steps on A from b bordered by one row and column, which spans
  *     the same k-dimensional Krylov space of the augmented matrix.  For
@@ -226,7 +237,7 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
  * tau - t for the augmented run, whose bordered matrix integrates the
  * approximation of e^{As} b) and ends a run at the first checkpoint where the
  * bound is below eps; a batch stops iterating once all its runs have ended.
- * k stays the cap (the augmented run: k - 1 Lanczos steps).  The integral
+ * k stays the cap (the augmented run: k - 1 Lanczos steps); k <= 2048.  The integral
  * uses a fixed composite 8-point Gauss-Legendre rule on [0, tau 2^-40] and on
  * [tau 2^-(i+1), tau 2^-i], i < 40, each cut into 8 equal parts.  eps = 0
  * turns the control off (the default: every run uses k).  Lanczos plans

@@ -206,7 +206,8 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     L.proj = L.sigma + (k + 3);
     L.misc = L.proj + o * (k + 1);
     L.hess = L.misc + MISC_COUNT;
-    L.stride = (int64_t)align_up((size_t)(L.hess + (k + 1) * k), 8);
+    // the Hessenberg store only where a basis is kept (Arnoldi, reorthogonalised Lanczos)
+    L.stride = (int64_t)align_up((size_t)(L.hess + (Y.stored ? (int64_t)(k + 1) * k : 0)), 8);
     // offset 0 is reserved: an offset of 0 marks a region the plan does not have
     size_t off = 256;
     auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
@@ -292,9 +293,16 @@ kry_status check_segs(const kry_segs& s, int64_t n, const char* what) {
 // Max absolute row sum of a stencil operator: rows differ only by which
 // neighbours exist, so enumerate the (up to 27) boundary classes.  Terms
 // are added in ascending column order like a CSR row.
-double stencil_inf_norm(const kry_system& s) {
-    double best = 0.0;
+// Over the 27 classes of stencil rows (first, interior or last index in each
+// dimension): the largest absolute row sum (||A||_inf) and the largest
+// diagonal plus off-diagonal absolute row sum (a Gershgorin bound of the
+// largest eigenvalue when A is symmetric).  The diagonal follows the face
+// conditions: insulated faces return a missing neighbour's coefficient to it,
+// and the last x plane adds the exchange term.
+void stencil_row_bounds(const kry_system& s, double* inf_norm, double* gersh) {
+    double best = 0.0, top = -INFINITY;
     const int64_t dims[3] = {s.nx, s.ny, s.nz};
+    const double cf[3] = {s.cx, s.cy, s.cz};
     for (int cx = 0; cx < 3; ++cx)
         for (int cy = 0; cy < 3; ++cy)
             for (int cz = 0; cz < 3; ++cz) {
@@ -311,17 +319,25 @@ double stencil_inf_norm(const kry_system& s) {
                     hi[d] = idx < m - 1;
                 }
                 if (!exists) continue;
-                double t = 0.0;
-                if (lo[0]) t += std::fabs(s.cx);
-                if (lo[1]) t += std::fabs(s.cy);
-                if (lo[2]) t += std::fabs(s.cz);
-                t += std::fabs(s.c0);
-                if (hi[2]) t += std::fabs(s.cz);
-                if (hi[1]) t += std::fabs(s.cy);
-                if (hi[0]) t += std::fabs(s.cx);
-                best = std::max(best, t);
+                double diag = s.c0, off = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    if (lo[d]) off += std::fabs(cf[d]);
+                    else if (s.stencil_bc == KRY_BC_INSULATED) diag += cf[d];
+                    if (hi[d]) off += std::fabs(cf[d]);
+                    else if (s.stencil_bc == KRY_BC_INSULATED) diag += cf[d];
+                }
+                if (!hi[0]) diag += s.stencil_exchange;
+                best = std::max(best, std::fabs(diag) + off);
+                top = std::max(top, diag + off);
             }
-    return best;
+    if (inf_norm) *inf_norm = best;
+    if (gersh) *gersh = top;
+}
+
+double stencil_inf_norm(const kry_system& s) {
+    double a = 0.0;
+    stencil_row_bounds(s, &a, nullptr);
+    return a;
 }
 
 // Nodes and weights of the 8-point Gauss-Legendre rule on [-1, 1]: roots of
@@ -460,8 +476,11 @@ kry_status validate_system(const kry_system* sys) {
     } else if (sys->kind == KRY_STENCIL7) {
         if (sys->nx <= 0 || sys->ny <= 0 || sys->nz <= 0 || sys->nx * sys->ny * sys->nz != sys->n)
             return fail(KRY_EINVAL, "stencil grid must satisfy nx*ny*nz == n");
-        if (!std::isfinite(sys->c0) || !std::isfinite(sys->cx) || !std::isfinite(sys->cy) || !std::isfinite(sys->cz))
+        if (!std::isfinite(sys->c0) || !std::isfinite(sys->cx) || !std::isfinite(sys->cy) || !std::isfinite(sys->cz) ||
+            !std::isfinite(sys->stencil_exchange))
             return fail(KRY_EINVAL, "stencil coefficients must be finite");
+        if (sys->stencil_bc != KRY_BC_DIRICHLET && sys->stencil_bc != KRY_BC_INSULATED)
+            return fail(KRY_EINVAL, "unknown stencil face condition");
     } else {
         return fail(KRY_EINVAL, "unknown system kind");
     }
@@ -525,7 +544,7 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     if (method == KRY_BLOCK_ARNOLDI) {
         if (k < 1 || k > kMaxKB) return fail(KRY_EINVAL, "block Arnoldi: k (block steps) must be in [1, 32]");
     } else if (method == KRY_LANCZOS_PLAIN) {
-        if (k < 1 || k > kMaxKP) return fail(KRY_EINVAL, "plain Lanczos: k must be in [1, 2048]");
+        if (k < 1 || k > kMaxKP) return fail(KRY_EINVAL, "plain Lanczos: k must be in [1, 8192]");
     } else if (k < 1 || k > kMaxKD) {
         return fail(KRY_EINVAL, "k must be in [1, 512]");
     }
@@ -970,7 +989,8 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                 }
             } else {
                 StencilArgs A{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx,
-                              plan->sys.cy, plan->sys.cz};
+                              plan->sys.cy, plan->sys.cz, plan->sys.stencil_bc == KRY_BC_INSULATED ? 1 : 0,
+                              plan->sys.stencil_exchange};
                 e = timed("spmv_stencil", s, [&] {
                     return launch_spmv_stencil(P, Y.march > 0, f32, A, ucur, uprev, w, B, j, s);
                 });
@@ -1189,6 +1209,7 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
     if (eps > 0.0 && plan->method != KRY_LANCZOS)
         return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
+    if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
     plan->err_eps = eps;
     if (eps == 0.0) return KRY_OK;
     if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
@@ -1196,7 +1217,7 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
     // lambda_max of the symmetric part of A, bounded by Gershgorin
     double lam;
     if (plan->sys.kind == KRY_STENCIL7) {
-        lam = plan->sys.c0 + 2.0 * (std::fabs(plan->sys.cx) + std::fabs(plan->sys.cy) + std::fabs(plan->sys.cz));
+        stencil_row_bounds(plan->sys, nullptr, &lam);
     } else {
         const Layout& Y = plan->Y;
         CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};

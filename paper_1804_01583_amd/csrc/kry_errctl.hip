@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_lemma1(BatchArgs B, ErrArgs X, int j
         for (int q = 0; q < (int)gridDim.x; ++q) all = all && X.flags[q] != 0.0;
         if (all) return;
     }
-    __shared__ double s_d[kMaxKP], s_e[kMaxKP], s_q1[kMaxKP], s_qm[kMaxKP];
+    __shared__ double s_d[kMaxKE], s_e[kMaxKE], s_q1[kMaxKE], s_qm[kMaxKE];
     __shared__ double s_red[kBlock / 64];
     __shared__ int s_state;   // 0 evaluate, 1 already stopped, 2 exact (breakdown), 3 no eigenvalues, 4 past k - 1
     const int p = blockIdx.x;
@@ -176,7 +176,7 @@ hipError_t launch_record_stage(int P, const BatchArgs& B, int j, hipStream_t s) 
 }
 
 hipError_t launch_lemma1(int P, const BatchArgs& B, const ErrArgs& X, int j, hipStream_t s) {
-    if (j < 1 || j > kMaxKP) return hipErrorInvalidValue;
+    if (j < 1 || j > kMaxKE) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_lemma1, dim3(P), dim3(kBlock), 0, s, B, X, j);
     return hipGetLastError();
 }

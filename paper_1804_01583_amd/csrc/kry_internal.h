@@ -12,7 +12,8 @@ constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kMaxO = 8;         // output rows
 constexpr int kMaxK = 56;        // Krylov dimension of the one-workgroup LDS exponential
 constexpr int kMaxKD = 512;      // Krylov dimension with the dense stage (k > kMaxK)
-constexpr int kMaxKP = 2048;     // Krylov dimension of three-vector (plain) Lanczos
+constexpr int kMaxKP = 8192;     // Krylov dimension of three-vector (plain) Lanczos
+constexpr int kMaxKE = 2048;     // Krylov dimension the error control's eigen-solve holds in LDS
 constexpr int kExpmThreads = 512;
 constexpr int kMaxP = 8;         // runs advanced per mat-vec launch
 constexpr int kMaxNV = 24;       // values reduced per block: P * (1 + O)
@@ -100,6 +101,8 @@ hipError_t launch_sell_fill(bool f32, const CsrArgs& A, int64_t n, const int64_t
 struct StencilArgs {
     int64_t nx, ny, nz;
     double c0, cx, cy, cz;
+    int32_t insulated;       // 1: faces without flux (missing neighbours leave the diagonal)
+    double ex;               // added to the diagonal on the face ix = nx - 1
 };
 
 // Start-vector sources of the runs in a batch.

@@ -249,6 +249,24 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restr
     store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
 }
 
+// Diagonal of a stencil row from which neighbours exist: c0, plus for
+// insulated faces each missing neighbour's coefficient, plus the exchange
+// term on the last x plane.
+__device__ __forceinline__ double stencil_diag(const StencilArgs& S, bool xl, bool xh, bool yl, bool yh, bool zl,
+                                               bool zh) {
+    double d = S.c0;
+    if (S.insulated) {
+        if (!xl) d += S.cx;
+        if (!xh) d += S.cx;
+        if (!yl) d += S.cy;
+        if (!yh) d += S.cy;
+        if (!zl) d += S.cz;
+        if (!zh) d += S.cz;
+    }
+    if (!xh) d += S.ex;
+    return d;
+}
+
 // Matrix-free 7-point stencil version of k_spmv_csr (zero outside the grid),
 // neighbours summed in ascending index order like a CSR row.  Each thread
 // decodes its first row's grid coordinates once and advances them as it
@@ -289,13 +307,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const E*
         load_row<E, P>(ucur, yh ? r + sy : r, vyh);
         load_row<E, P>(ucur, xh ? r + sx : r, vxh);
         load_row<E, P>(prev ? uprev : ucur, r, pv);
+        const double diag = stencil_diag(S, xl, xh, yl, yh, zl, zh);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             double acc = 0.0;
             if (xl) acc = fma(S.cx, vxl[p], acc);
             if (yl) acc = fma(S.cy, vyl[p], acc);
             if (zl) acc = fma(S.cz, vzl[p], acc);
-            acc = fma(S.c0, own[p], acc);
+            acc = fma(diag, own[p], acc);
             if (zh) acc = fma(S.cz, vzh[p], acc);
             if (yh) acc = fma(S.cy, vyh[p], acc);
             if (xh) acc = fma(S.cx, vxh[p], acc);
@@ -340,13 +359,14 @@ __device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol&
     load_row<E, P>(up, r, vpr);
     load_row<E, P>(ucur, ix + 2 < S.nx ? r + 2 * M.sx : r, nx2);
     double y[P];
+    const double diag = stencil_diag(S, ix > 0, ix < S.nx - 1, M.yl, M.yh, M.zl, M.zh);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         double acc = 0.0;
         if (ix > 0) acc = fma(S.cx, xm[p], acc);
         if (M.yl) acc = fma(S.cy, vyl[p], acc);
         if (M.zl) acc = fma(S.cz, vzl[p], acc);
-        acc = fma(S.c0, x0[p], acc);
+        acc = fma(diag, x0[p], acc);
         if (M.zh) acc = fma(S.cz, vzh[p], acc);
         if (M.yh) acc = fma(S.cy, vyh[p], acc);
         if (ix < S.nx - 1) acc = fma(S.cx, xp[p], acc);

@@ -23,6 +23,7 @@ KRY_OK, KRY_EINVAL, KRY_ENOMEM, KRY_EDEVICE, KRY_ENUMERIC, KRY_ENOTSUP = range(6
 KRY_FP64, KRY_FP32_BASIS = 0, 1
 KRY_AUTO, KRY_LANCZOS, KRY_ARNOLDI, KRY_BLOCK_ARNOLDI, KRY_LANCZOS_PLAIN = range(5)
 KRY_CSR, KRY_STENCIL7 = 0, 1
+KRY_BC_DIRICHLET, KRY_BC_INSULATED = 0, 1
 ROLE_NAMES = {0: "gen", 1: "center", 2: "affine"}
 
 
@@ -42,7 +43,7 @@ class KrySystem(ct.Structure):
                 ("nnz", ct.c_int64), ("nx", ct.c_int64), ("ny", ct.c_int64), ("nz", ct.c_int64),
                 ("c0", ct.c_double), ("cx", ct.c_double), ("cy", ct.c_double), ("cz", ct.c_double),
                 ("b", ct.c_void_p), ("anorm", ct.c_double), ("b_segs", ct.POINTER(KrySegs)),
-                ("prepared", ct.c_void_p)]
+                ("prepared", ct.c_void_p), ("stencil_bc", ct.c_int32), ("stencil_exchange", ct.c_double)]
 
 
 class KryGen(ct.Structure):
@@ -284,6 +285,8 @@ class DeviceSystem:
             s.kind = KRY_STENCIL7
             s.nx, s.ny, s.nz = problem.grid
             s.c0, s.cx, s.cy, s.cz = problem.coef
+            s.stencil_bc = KRY_BC_INSULATED if getattr(problem, "bc", "dirichlet") == "insulated" else KRY_BC_DIRICHLET
+            s.stencil_exchange = float(getattr(problem, "exchange", 0.0))
         self.b = None
         self._keep = []
         if problem.b is not None:

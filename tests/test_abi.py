@@ -36,16 +36,17 @@ def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "kry.h"\n'
-        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(kry_system), sizeof(kry_segs),"
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(kry_system), sizeof(kry_segs),"
         " sizeof(kry_gen), sizeof(kry_interval), sizeof(kry_verdict), offsetof(kry_system, b),"
-        " offsetof(kry_system, anorm), offsetof(kry_verdict, y), offsetof(kry_system, prepared)); return 0;}\n")
+        " offsetof(kry_system, anorm), offsetof(kry_verdict, y), offsetof(kry_system, prepared),"
+        " offsetof(kry_system, stencil_exchange)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     import ctypes as ct
     want = [ct.sizeof(kry.KrySystem), ct.sizeof(kry.KrySegs), ct.sizeof(kry.KryGen), ct.sizeof(kry.KryInterval),
             ct.sizeof(kry.KryVerdict), kry.KrySystem.b.offset, kry.KrySystem.anorm.offset, kry.KryVerdict.y.offset,
-            kry.KrySystem.prepared.offset]
+            kry.KrySystem.prepared.offset, kry.KrySystem.stencil_exchange.offset]
     assert got == want
 
 

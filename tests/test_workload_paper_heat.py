@@ -46,3 +46,14 @@ def test_exchange_face_and_problem_shape():
     assert q.gens[0].seg.count == 8 * 4 * 2 and q.C[0].count == 8
     assert abs(q.C[0].w.sum() * 1 - q.C[0].nseg * q.C[0].w[0]) == 0.0
     assert (q.steps, q.dt) == (1000, 0.02)
+
+
+def test_stencil_form_expands_to_the_same_operator():
+    m = 7
+    p = W.heat3d_paper(m=m)
+    s = W.heat3d_paper_stencil(m=m, k=20)
+    A = _dense(p.rowptr, p.colidx, p.vals, p.n)
+    B = _dense(*s.csr(), s.n)
+    assert np.abs(A - B).max() <= 1e-13 * p.meta["c"]
+    assert [g.seg.count for g in s.gens] == [g.seg.count for g in p.gens]
+    assert np.array_equal(s.C[0].lo, p.C[0].lo) and s.C[0].w[0] == p.C[0].w[0]

@@ -28,6 +28,7 @@ __all__ = [
     "Segments", "Generator", "Problem",
     "segments_from_ranges", "box_segments", "csr_stencil7",
     "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil", "heat3d_paper", "csr_heat_insulated",
+    "heat3d_paper_stencil", "csr_stencil7_faces",
     "random_symmetric", "small_heat3d", "conv_diff3d",
 ]
 
@@ -99,6 +100,11 @@ class Problem:
     note: str = ""
     meta: dict = field(default_factory=dict)
     b_seg: Optional[Segments] = None    # forcing as index ranges (instead of a dense b)
+    # stencil face conditions: "dirichlet" (zero outside the grid) or "insulated"
+    # (no flux: a missing neighbour's coefficient returns to the diagonal), and
+    # a term added to the diagonal of the last x plane (exchange through x = 1)
+    bc: str = "dirichlet"
+    exchange: float = 0.0
 
     @property
     def has_forcing(self) -> bool:
@@ -125,7 +131,9 @@ class Problem:
         if self.kind == "csr":
             return self.rowptr, self.colidx, self.vals
         nx, ny, nz = self.grid
-        return csr_stencil7(nx, ny, nz, *self.coef)
+        if self.bc == "dirichlet" and self.exchange == 0.0:
+            return csr_stencil7(nx, ny, nz, *self.coef)
+        return csr_stencil7_faces(nx, ny, nz, *self.coef, insulated=self.bc == "insulated", exchange=self.exchange)
 
 
 def segments_from_ranges(ranges, values=1.0) -> Segments:
@@ -261,6 +269,50 @@ def heat3d_csr(m=100, D=0.01, k=40, dt=0.02, steps=2000, seed=2, unsafe_scale=No
                    b=b, rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
                    meta={"m": m, "forcing_box": fbox, "gen_box": gbox, "center_box": cbox, "coef": coef},
                    note="3D heat CSR with affine forcing")
+
+
+def csr_stencil7_faces(nx, ny, nz, c0, cx, cy, cz, insulated=False, exchange=0.0):
+    """CSR of the 7-point stencil with face conditions: with `insulated`, a
+    row's diagonal is c0 plus the coefficient of each missing neighbour
+    (added in the order x-, x+, y-, y+, z-, z+); `exchange` is then added on
+    the last x plane."""
+    rowptr, colidx, vals = csr_stencil7(nx, ny, nz, c0, cx, cy, cz)
+    n = nx * ny * nz
+    idx = np.arange(n, dtype=np.int64)
+    iz = idx % nz
+    iy = (idx // nz) % ny
+    ix = idx // (ny * nz)
+    d = np.full(n, float(c0))
+    if insulated:
+        for miss, c in ((ix == 0, cx), (ix == nx - 1, cx), (iy == 0, cy), (iy == ny - 1, cy),
+                        (iz == 0, cz), (iz == nz - 1, cz)):
+            d = np.where(miss, d + c, d)
+    d = np.where(ix == nx - 1, d + exchange, d)
+    rows = np.repeat(idx, np.diff(rowptr))
+    on_diag = colidx.astype(np.int64) == rows
+    vals = vals.copy()
+    vals[on_diag] = d[rows[on_diag]]
+    return rowptr, colidx, vals
+
+
+def heat3d_paper_stencil(m=1000, D=0.01, exchange=0.5, k=5932, dt=0.02, steps=1000) -> Problem:
+    """heat3d_paper as a matrix-free stencil (insulated faces, exchange on
+    the x = 1 face), for grids too large to store; the same operator up to
+    the rounding of the diagonal."""
+    p = heat3d_paper(m=min(m, 2), D=D, exchange=exchange)        # shapes only
+    n = m**3
+    h = 1.0 / m
+    c = D / h**2
+    ext = [max(int(round(f * m)), 1) for f in (0.4, 0.2, 0.1)]
+    gbox = ((0, ext[0]), (0, ext[1]), (0, ext[2]))
+    gens = [Generator(box_segments((m, m, m), gbox, 1.0), zc=1.0, radius=0.1)]
+    mid = [m // 2 - 1, m // 2] if m % 2 == 0 else [m // 2]
+    cbox = tuple((mid[0], mid[-1] + 1) for _ in range(3))
+    C = [box_segments((m, m, m), cbox, 1.0 / len(mid) ** 3)]
+    return Problem("heat3d_paper_stencil", n, "stencil7", True, gens, C, p.unsafe, k=k, dt=dt, steps=steps,
+                   grid=(m, m, m), coef=(-6.0 * c, c, c, c), bc="insulated", exchange=-c * h * exchange,
+                   meta={"m": m, "gen_box": gbox, "center_box": cbox, "c": c, "h": h, "exchange": exchange},
+                   note="3D heat as stated in the paper, matrix-free")
 
 
 def csr_heat_insulated(m, c, exchange_diag):
