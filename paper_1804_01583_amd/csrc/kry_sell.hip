@@ -126,13 +126,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
     const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
     const int lane = threadIdx.x & 63;
+    const int64_t span = (int64_t)kBlock * RC;
+    const int nch = (int)((B.rows_per_block + span - 1) / span);
+    // slice offset and width of a chunk's rows; a wavefront's 64 rows are one
+    // slice, rows past the block (or n) read slice 0 and are not stored.
+    // Each chunk's are requested one chunk ahead (the first ones before the
+    // norm partials), so no chunk starts with a round trip of its own.
+    int64_t off_nx[RC];
+    int32_t wd_nx[RC];
+    auto slice_info = [&](int ch) {
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int64_t r = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            const int64_t rs = r < r1 ? r : (r0 < B.n ? r0 : 0);
+            const int64_t s = rs / kSlice;
+            off_nx[i] = A.off[s] + lane;
+            wd_nx[i] = A.width[s];
+        }
+    };
+    slice_info(0);
     double pacc[P], sig_prev[P], anorm;
     load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
     double sig[P], cprev[P], dot[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) { sig[p] = 0.0; cprev[p] = 0.0; dot[p] = 0.0; }
-    const int64_t span = (int64_t)kBlock * RC;
-    const int nch = (int)((B.rows_per_block + span - 1) / span);
     const bool prev = j > 1 && uprev != nullptr;
     for (int ch = 0; ch < nch; ++ch) {
         int64_t rr[RC], off[RC];
@@ -141,15 +158,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
             rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
-            // a wavefront's 64 rows are one slice; rows past the block (or n)
-            // read slice 0 and are not stored
-            const int64_t rs = rr[i] < r1 ? rr[i] : (r0 < B.n ? r0 : 0);
-            const int64_t s = rs / kSlice;
-            off[i] = A.off[s] + lane;
-            wd[i] = A.width[s];
+            off[i] = off_nx[i];
+            wd[i] = wd_nx[i];
 #pragma unroll
             for (int p = 0; p < P; ++p) acc[i][p] = 0.0;
         }
+        if (ch + 1 < nch) slice_info(ch + 1);
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
             for (int kb = 0; kb < wd[i]; kb += KU) {
