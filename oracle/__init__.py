@@ -21,7 +21,9 @@ Billion Dimensions", arXiv 1804.01583):
   initial set and per-row interval unsafe sets, with a counter-example,
 * block Arnoldi over p generator columns at once (``block``), the same
   Galerkin approximant for a block start,
-* the a-posteriori choice of k by the error bound of Lemma 1 (``adaptive``).
+* the a-posteriori choice of k by the error bound of Lemma 1 (``adaptive``),
+* the basis by simulation of the transposed dynamics, one run per output
+  row (Section 4.1, ``transpose``).
 
 All pins of these functions live in ``tests/test_oracle_*.py``.
 """
@@ -32,3 +34,4 @@ from .krylov import (  # noqa: F401
 )
 from .block import BlockResult, block_arnoldi, block_project_steps, block_verify, qr_posdiag  # noqa: F401
 from . import adaptive  # noqa: F401
+from . import transpose  # noqa: F401

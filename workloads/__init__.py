@@ -30,6 +30,7 @@ __all__ = [
     "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil", "heat3d_paper", "csr_heat_insulated",
     "heat3d_paper_stencil", "csr_stencil7_faces",
     "random_symmetric", "small_heat3d", "conv_diff3d",
+    "segments_of_dense", "heat3d_many_inputs",
 ]
 
 
@@ -140,6 +141,24 @@ def segments_from_ranges(ranges, values=1.0) -> Segments:
     ranges = sorted(ranges)
     vals = np.broadcast_to(np.asarray(values, dtype=np.float64), (len(ranges),))
     return Segments(np.array([r[0] for r in ranges]), np.array([r[1] for r in ranges]), np.array(vals))
+
+
+def segments_of_dense(v) -> Segments:
+    """The same vector as index ranges: each maximal run of equal nonzero
+    consecutive entries becomes one range (a change of format only)."""
+    v = np.asarray(v, np.float64)
+    lo, hi, w = [], [], []
+    i, n = 0, v.size
+    while i < n:
+        if v[i] == 0.0:
+            i += 1
+            continue
+        j = i + 1
+        while j < n and v[j] == v[i]:
+            j += 1
+        lo.append(i); hi.append(j); w.append(v[i])
+        i = j
+    return Segments(np.array(lo, np.int64), np.array(hi, np.int64), np.array(w))
 
 
 def box_segments(grid, box, value=1.0) -> Segments:
@@ -377,6 +396,42 @@ def small_heat3d(m=12, D=0.01, k=20, dt=0.02, steps=200, seed=7) -> Problem:
     p = heat3d_csr(m=m, D=D, k=k, dt=dt, steps=steps, seed=seed)
     p.name = "small_heat3d"
     return p
+
+
+def heat3d_many_inputs(m=100, D=0.01, k=40, dt=0.02, steps=1000, seed=5) -> Problem:
+    """An initial space wider than the output space (i = 8 > o = 1), the case
+    the transposed simulation of Section 4.1 is for: 3D heat on an m^3 grid
+    (CSR, Dirichlet), forcing 0.1 on a seeded 10^3 sub-cube given as index
+    ranges, six box generators over disjoint seeded 8^3 cubes (z = 1.0 +- 0.1
+    each), a fixed initial part 0.5 on a 12^3 cube (the center, also as index
+    ranges), and one output: the mean over the central 10^3 cube, unsafe
+    when it reaches 0.3."""
+    n = m**3
+    coef, _, fbox = _heat3d_parts(m, D, seed)
+    bseg = box_segments((m, m, m), fbox, 0.1)
+    rowptr, colidx, vals = csr_stencil7(m, m, m, *coef)
+    rng = np.random.default_rng(seed + 1)
+    g = min(8, m)
+    cells = max(m // g, 1)
+    picks = rng.choice(cells**3, size=min(6, cells**3), replace=False)
+    gens = []
+    for pk in sorted(int(x) for x in picks):
+        cx, cy, cz = pk // (cells * cells), (pk // cells) % cells, pk % cells
+        gb = ((cx * g, cx * g + g), (cy * g, cy * g + g), (cz * g, cz * g + g))
+        gens.append(Generator(box_segments((m, m, m), gb, 1.0), zc=1.0, radius=0.1))
+    wc = min(12, m)
+    woff = int(rng.integers(0, m - wc + 1))
+    wbox = ((woff, woff + wc),) * 3
+    center_seg = box_segments((m, m, m), wbox, 0.5)
+    cc = max(m // 2 - 5, 0)
+    cbox = ((cc, min(cc + 10, m)),) * 3
+    ccount = int(np.prod([hi - lo for lo, hi in cbox]))
+    C = [box_segments((m, m, m), cbox, 1.0 / ccount)]
+    unsafe = np.array([[0.3, math.inf]])
+    return Problem("heat3d_many_inputs", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
+                   b_seg=bseg, center=center_seg.dense(n), rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
+                   meta={"m": m, "forcing_box": fbox, "warm_box": wbox, "out_box": cbox},
+                   note="3D heat, eight initial-space columns, one output")
 
 
 def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
