@@ -176,11 +176,42 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
                            int32_t block_p, void* workspace, size_t workspace_bytes,
                            void* hip_stream, kry_plan** out);
 
+/* kry_plan_create_transposed -- the same basis C e^{At} E by simulations of
+ * the transposed dynamics (Section 4.1): C e^{At} E = (E^T e^{A^T t} C^T)^T,
+ * so one run per output row instead of one per column of E, each projected
+ * on the rows of E^T as it goes (Algorithm 4 with E^T in place of C,
+ * Section 4.3).  Worth it when o is smaller than the number of columns.
+ *  sys_t: the system whose matrix is A^T (for a symmetric A, the system
+ *     itself).  Its forcing, when given, is the original system's b and
+ *     must come as b_segs (it is a projection row); a dense b gives
+ *     KRY_ENOTSUP.
+ *  gens, ngen, center: the initial space (center: host segment set or
+ *     NULL, a fixed coefficient-1 column).  Generators + center + forcing
+ *     make ncols <= 8 basis columns.
+ *  C, o: 1 <= o <= 8 output rows, the runs' start vectors.
+ *  k: 1..56 Krylov steps per run, 1..55 with forcing.  With forcing each
+ *     run is the Galerkin projection of the transposed augmented matrix
+ *     [[A^T, 0], [b^T, 0]] on the run's Krylov basis plus the augmented
+ *     coordinate, a matrix of size k + 1.
+ *  method: KRY_AUTO, KRY_LANCZOS (symmetric sys_t) or KRY_ARNOLDI; others
+ *     give KRY_ENOTSUP.  dt, steps, precision, hip_stream: as for
+ *     kry_plan_create.  The plan allocates its own workspace.
+ * kry_project_expm and kry_check_box_safety then behave as for a forward
+ * plan with columns in the order generators, center, forcing; kry_plan_runs
+ * and kry_plan_krylov describe the o transposed runs (P has one row per
+ * initial-space row).  Error control (kry_plan_set_error_target) is not
+ * offered on this route (KRY_ENOTSUP). */
+kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* gens, int32_t ngen,
+                                      const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
+                                      double dt, int64_t steps, int32_t precision, int32_t method,
+                                      void* hip_stream, kry_plan** out);
+
 /* kry_project_expm -- run the Krylov process of every run (Algorithms 3-4),
  * then form the basis matrix for all steps:
  *   basis[s][r][run] = beta0_run * (P_run e^{H_run s dt} e_1)[r]
  * (Eq. approx-formula projected by C).  basis_out: host or device pointer to
- * (steps+1) * o * nruns doubles, or NULL to keep the basis on the device for
+ * (steps+1) * o * ncols doubles (ncols = generators + center + forcing: the
+ * runs of a forward plan), or NULL to keep the basis on the device for
  * kry_check_box_safety only.  With a host pointer the call waits for the
  * stream; otherwise it returns once the work is enqueued. */
 kry_status kry_project_expm(kry_plan* plan, double* basis_out);

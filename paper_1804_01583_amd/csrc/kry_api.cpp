@@ -181,7 +181,11 @@ struct Layout {
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
                    size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32,
-                   int64_t sell_nnz) {
+                   int64_t sell_nnz, int32_t njobs = -1, int32_t ncols = -1, int32_t o_out = -1) {
+    // the forward route has one job and one basis column per run
+    if (njobs < 0) njobs = nruns;
+    if (ncols < 0) ncols = nruns;
+    if (o_out < 0) o_out = o;
     Layout Y{};
     Y.rpb = rows_per_block_for(n);
     Y.nblocks = nblocks_for(n, Y.rpb);
@@ -240,19 +244,19 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.nanch = (int32_t)((steps + 1 + Y.B - 1) / Y.B);
     // small exponential in LDS (k <= 56) or the dense stage, one run at a time
     Y.dense_runs = method != KRY_BLOCK_ARNOLDI && k > kMaxK;
-    Y.zmat = Y.dense_runs ? 0 : take((size_t)nruns * Y.B * kMaxO * kMaxK * sizeof(double));
-    Y.anch = Y.dense_runs ? 0 : take((size_t)nruns * Y.nanch * kMaxK * sizeof(double));
+    Y.zmat = Y.dense_runs ? 0 : take((size_t)njobs * Y.B * kMaxO * kMaxK * sizeof(double));
+    Y.anch = Y.dense_runs ? 0 : take((size_t)njobs * Y.nanch * kMaxK * sizeof(double));
     if (Y.dense_runs) {
         Y.dH = take((size_t)k * k * sizeof(double));
         Y.dP = take((size_t)o * k * sizeof(double));
         Y.dS0 = take((size_t)k * sizeof(double));
         Y.dws = take(dense_workspace_doubles(k, o, 1, Y.B, Y.nanch) * sizeof(double));
     }
-    Y.msize = take((size_t)nruns * sizeof(int32_t));
-    Y.scale = take((size_t)nruns * sizeof(double));
-    Y.basis = take((size_t)(steps + 1) * o * nruns * sizeof(double));
-    Y.cpart = take((size_t)2 * check_blocks(steps, o) * sizeof(double));
-    Y.verdict = take((size_t)(6 + nruns) * sizeof(double));
+    Y.msize = take((size_t)std::max(njobs, nruns) * sizeof(int32_t));
+    Y.scale = take((size_t)std::max(njobs, nruns) * sizeof(double));
+    Y.basis = take((size_t)(steps + 1) * o_out * ncols * sizeof(double));
+    Y.cpart = take((size_t)2 * check_blocks(steps, o_out) * sizeof(double));
+    Y.verdict = take((size_t)(6 + ncols) * sizeof(double));
     Y.anorm = take(sizeof(double));
     Y.eflags = take(kMaxP * sizeof(double) + sizeof(double));
     if (method == KRY_BLOCK_ARNOLDI) {
@@ -405,9 +409,19 @@ struct kry_plan {
     bool owns_ws = false;
     std::vector<char> meta_host;
     SegTable T{};
-    int32_t* role_dev = nullptr;
-    double* zc_dev = nullptr;
+    int32_t* role_dev = nullptr;   // per job of the small stage (per run on the forward route)
+    double* zc_dev = nullptr;      // per basis column
     double* rad_dev = nullptr;
+    // transposed route (Section 4.1): the Krylov runs start from the output
+    // rows and project on the initial-space rows; the basis keeps the
+    // forward shape (o_out output rows x ncols columns)
+    bool transposed = false;
+    int32_t njobs = 0;             // exponentials of the small stage
+    int32_t o_out = 0, ncols = 0;  // basis shape
+    std::vector<int32_t> col_role; // per basis column: 0 generator, 1 center, 2 forcing
+    std::vector<int32_t> job_role, job_run, out_col;
+    int32_t* job_run_dev = nullptr;
+    int32_t* out_col_dev = nullptr;
     int lpr = 1;
     int32_t method = KRY_LANCZOS;
     bool projected = false;
@@ -453,7 +467,9 @@ namespace {
 
 // Metadata block uploaded once per plan: segment table, per-run roles and
 // box coefficients.
-size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns, int32_t nblocks) {
+size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns, int32_t nblocks, int32_t nmap = 0) {
+    // nruns: entries of the role and box tables (runs, or jobs and columns of
+    // the transposed route); nmap: jobs of a transposed plan's output map
     size_t b = 0;
     b = align_up(b + (size_t)nsets * nblocks * 2 * 4, 16);   // per-block segment ranges
     b = align_up(b + (size_t)total_segs * 8, 16);   // lo
@@ -463,6 +479,8 @@ size_t meta_size(int64_t total_segs, int32_t nsets, int32_t nruns, int32_t nbloc
     b = align_up(b + (size_t)nruns * 4, 16);        // role
     b = align_up(b + (size_t)nruns * 8, 16);        // zc
     b = align_up(b + (size_t)nruns * 8, 16);        // radius
+    b = align_up(b + (size_t)nmap * 4, 16);         // job -> run
+    b = align_up(b + (size_t)nmap * kMaxO * 4, 16); // job row -> basis column
     return b;
 }
 
@@ -530,17 +548,44 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     return KRY_OK;
 }
 
-kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
-                           const double* center, const kry_segs* C, int32_t o, int32_t k,
-                           double dt, int64_t steps, int32_t precision, int32_t method,
-                           int32_t block_p, void* workspace, size_t workspace_bytes,
-                           void* hip_stream, kry_plan** out) {
+}  // extern "C"
+
+namespace {
+
+// Both routes.  Forward: one run per column of E (generators, the dense
+// center, the forcing), projected on the output rows.  Transposed
+// (center_t instead of center): one run of the given system, which is A^T,
+// per output row, projected on the rows of E^T; the basis is scattered back
+// to the forward shape.
+kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
+                       const kry_segs* center_t, bool transposed, const kry_segs* C, int32_t o, int32_t k,
+                       double dt, int64_t steps, int32_t precision, int32_t method, int32_t block_p,
+                       void* workspace, size_t workspace_bytes, void* hip_stream, kry_plan** out) {
     if (!out) return fail(KRY_EINVAL, "out is NULL");
     *out = nullptr;
     kry_status st = validate_system(sys);
     if (st != KRY_OK) return st;
     if (ngen < 0 || (ngen > 0 && !gens)) return fail(KRY_EINVAL, "bad generator list");
     if (o < 1 || o > kMaxO || !C) return fail(KRY_EINVAL, "need 1 <= o <= 8 output rows");
+    // transposed route: the initial-space rows (generators, center, b) are
+    // the projection rows, at most 8; the forcing column's exponential has
+    // size k + 1 and must fit the small stage
+    const bool has_b = sys->b || sys->b_segs;
+    const int32_t nproj = ngen + (center_t ? 1 : 0) + (has_b ? 1 : 0);
+    if (transposed) {
+        if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+        if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
+            return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
+        if (sys->b) return fail(KRY_ENOTSUP, "the transposed route takes the forcing as b_segs (a projection row)");
+        if (nproj < 1 || nproj > kMaxO)
+            return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows (generators, center, forcing)");
+        if (k < 1 || k > (has_b ? kMaxK - 1 : kMaxK))
+            return fail(KRY_EINVAL, "transposed route: k must be in [1, 56] ([1, 55] with forcing)");
+        if (center_t) {
+            st = check_segs(*center_t, sys->n, "center");
+            if (st != KRY_OK) return st;
+        }
+    }
     if (method == KRY_BLOCK_ARNOLDI) {
         if (k < 1 || k > kMaxKB) return fail(KRY_EINVAL, "block Arnoldi: k (block steps) must be in [1, 32]");
     } else if (method == KRY_LANCZOS_PLAIN) {
@@ -586,38 +631,72 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     auto* plan = new kry_plan();
     plan->sys = *sys;
     plan->ngen = ngen;
-    plan->o = o;
     plan->k = k;
     plan->dt = dt;
     plan->steps = steps;
     plan->stream = reinterpret_cast<hipStream_t>(hip_stream);
     plan->center = center;
+    plan->transposed = transposed;
+    // basis columns: generators, the center, the forcing's augmented variable
     for (int32_t g = 0; g < ngen; ++g) {
-        plan->role.push_back(0);
+        plan->col_role.push_back(0);
         plan->zc.push_back(gens[g].zc);
         plan->radius.push_back(gens[g].radius);
     }
-    if (center) { plan->role.push_back(1); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
-    if (sys->b || sys->b_segs) { plan->role.push_back(2); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
-    plan->nruns = (int32_t)plan->role.size();
-    if (plan->nruns == 0) {
+    if (center || center_t) { plan->col_role.push_back(1); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
+    if (has_b) { plan->col_role.push_back(2); plan->zc.push_back(1.0); plan->radius.push_back(0.0); }
+    plan->ncols = (int32_t)plan->col_role.size();
+    plan->o_out = o;
+    if (plan->ncols == 0) {
         delete plan;
         return fail(KRY_EINVAL, "nothing to simulate: no generator, center or forcing");
     }
+    if (transposed) {
+        // one run per output row; projection row r is basis column r.  Job
+        // q exponentiates run q's T for the generator and center columns;
+        // with forcing, job o + q exponentiates the bordered matrix for the
+        // forcing column.
+        plan->o = nproj;
+        plan->role.assign(o, 0);
+        plan->nruns = o;
+        for (int32_t q = 0; q < o; ++q) {
+            plan->job_role.push_back(0);
+            plan->job_run.push_back(q);
+            for (int32_t r = 0; r < kMaxO; ++r)
+                plan->out_col.push_back(r < nproj && plan->col_role[r] != 2 ? r : -1);
+        }
+        if (has_b)
+            for (int32_t q = 0; q < o; ++q) {
+                plan->job_role.push_back(3);
+                plan->job_run.push_back(q);
+                for (int32_t r = 0; r < kMaxO; ++r) plan->out_col.push_back(r == nproj - 1 ? r : -1);
+            }
+    } else {
+        plan->o = o;
+        plan->role = plan->col_role;
+        plan->job_role = plan->role;
+        plan->nruns = plan->ncols;
+    }
+    plan->njobs = (int32_t)plan->job_role.size();
 
-    // segment table: generator sets 0..ngen-1, output sets ngen..ngen+o-1
+    // segment table.  Forward: generator sets 0..ngen-1, output sets
+    // ngen..ngen+o-1, then b.  Transposed: the output rows (start sets) come
+    // first, then the projection sets: generators, center, b.
     int64_t total_segs = 0;
     for (int32_t g = 0; g < ngen; ++g) total_segs += gens[g].seg.nseg;
     for (int32_t q = 0; q < o; ++q) total_segs += C[q].nseg;
     if (sys->b_segs) total_segs += sys->b_segs->nseg;
+    if (center_t) total_segs += center_t->nseg;
     if (total_segs >= ((int64_t)1 << 31)) { delete plan; return fail(KRY_EINVAL, "too many segments"); }
-    const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0);
+    const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0) + (center_t ? 1 : 0);
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
-    const size_t mbytes = meta_size(total_segs, nsets, plan->nruns, nblk);
+    const int32_t ntab = std::max(plan->njobs, plan->ncols);
+    const int32_t nmap = transposed ? plan->njobs : 0;
+    const size_t mbytes = meta_size(total_segs, nsets, ntab, nblk, nmap);
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
-    plan->Y = make_layout(n, plan->nruns, o, k, steps, block_p, mbytes, method, march_blocks_for(*sys), precision,
-                          nnz32, sell_nnz_for(*sys, method));
+    plan->Y = make_layout(n, plan->nruns, plan->o, k, steps, block_p, mbytes, method, march_blocks_for(*sys),
+                          precision, nnz32, sell_nnz_for(*sys, method), plan->njobs, plan->ncols, plan->o_out);
     plan->method = method == KRY_LANCZOS_PLAIN ? KRY_LANCZOS : method;   // the layout tells plain from reorthogonalised
     plan->f32 = precision == KRY_FP32_BASIS;
     plan->hess_mode = plan->Y.stored;
@@ -652,20 +731,30 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     auto* hi = reinterpret_cast<int64_t*>(base + off); off = align_up(off + total_segs * 8, 16);
     auto* w = reinterpret_cast<double*>(base + off); off = align_up(off + total_segs * 8, 16);
     auto* sb = reinterpret_cast<int32_t*>(base + off); off = align_up(off + (nsets + 1) * 4, 16);
-    auto* rl = reinterpret_cast<int32_t*>(base + off); off = align_up(off + plan->nruns * 4, 16);
-    auto* zc = reinterpret_cast<double*>(base + off); off = align_up(off + plan->nruns * 8, 16);
-    auto* rd = reinterpret_cast<double*>(base + off); off = align_up(off + plan->nruns * 8, 16);
+    auto* rl = reinterpret_cast<int32_t*>(base + off); off = align_up(off + ntab * 4, 16);
+    auto* zc = reinterpret_cast<double*>(base + off); off = align_up(off + ntab * 8, 16);
+    auto* rd = reinterpret_cast<double*>(base + off); off = align_up(off + ntab * 8, 16);
+    auto* jr = reinterpret_cast<int32_t*>(base + off); off = align_up(off + nmap * 4, 16);
+    auto* oc = reinterpret_cast<int32_t*>(base + off); off = align_up(off + (size_t)nmap * kMaxO * 4, 16);
     int64_t at = 0;
     int32_t set = 0;
     auto add_set = [&](const kry_segs& s) {
         sb[set++] = (int32_t)at;
         for (int64_t i = 0; i < s.nseg; ++i, ++at) { lo[at] = s.lo[i]; hi[at] = s.hi[i]; w[at] = s.w[i]; }
     };
-    for (int32_t g = 0; g < ngen; ++g) { plan->gen_set.push_back(set); add_set(gens[g].seg); }
-    plan->oset0 = set;
-    for (int32_t q = 0; q < o; ++q) add_set(C[q]);
     plan->bset = -1;
-    if (sys->b_segs) { plan->bset = set; add_set(*sys->b_segs); }
+    if (transposed) {
+        for (int32_t q = 0; q < o; ++q) { plan->gen_set.push_back(set); add_set(C[q]); }
+        plan->oset0 = set;
+        for (int32_t g = 0; g < ngen; ++g) add_set(gens[g].seg);
+        if (center_t) add_set(*center_t);
+        if (sys->b_segs) add_set(*sys->b_segs);
+    } else {
+        for (int32_t g = 0; g < ngen; ++g) { plan->gen_set.push_back(set); add_set(gens[g].seg); }
+        plan->oset0 = set;
+        for (int32_t q = 0; q < o; ++q) add_set(C[q]);
+        if (sys->b_segs) { plan->bset = set; add_set(*sys->b_segs); }
+    }
     sb[set] = (int32_t)at;
     // per logical block b (rows [b*rpb, (b+1)*rpb)), the segments of each set
     // that overlap it: [first with hi > row0, first with lo >= row1)
@@ -681,7 +770,12 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
             blk[((int64_t)s * Y.nblocks + b) * 2 + 1] = r1 > r0 ? last : first;
         }
     }
-    for (int32_t r = 0; r < plan->nruns; ++r) { rl[r] = plan->role[r]; zc[r] = plan->zc[r]; rd[r] = plan->radius[r]; }
+    for (int32_t j = 0; j < plan->njobs; ++j) rl[j] = plan->job_role[j];
+    for (int32_t c = 0; c < plan->ncols; ++c) { zc[c] = plan->zc[c]; rd[c] = plan->radius[c]; }
+    for (int32_t j = 0; j < nmap; ++j) {
+        jr[j] = plan->job_run[j];
+        for (int32_t r = 0; r < kMaxO; ++r) oc[j * kMaxO + r] = plan->out_col[(size_t)j * kMaxO + r];
+    }
     char* dmeta = plan->ws + Y.meta;
     plan->T.lo = reinterpret_cast<const int64_t*>(dmeta + ((char*)lo - base));
     plan->T.hi = reinterpret_cast<const int64_t*>(dmeta + ((char*)hi - base));
@@ -691,6 +785,10 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     plan->role_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)rl - base));
     plan->zc_dev = reinterpret_cast<double*>(dmeta + ((char*)zc - base));
     plan->rad_dev = reinterpret_cast<double*>(dmeta + ((char*)rd - base));
+    if (nmap > 0) {
+        plan->job_run_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)jr - base));
+        plan->out_col_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)oc - base));
+    }
 
     auto cleanup = [&](kry_status s) { kry_plan_destroy(plan); return s; };
     if (hipMemcpyAsync(dmeta, base, mbytes, hipMemcpyHostToDevice, plan->stream) != hipSuccess)
@@ -757,6 +855,29 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
     return KRY_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
+                           const double* center, const kry_segs* C, int32_t o, int32_t k,
+                           double dt, int64_t steps, int32_t precision, int32_t method,
+                           int32_t block_p, void* workspace, size_t workspace_bytes,
+                           void* hip_stream, kry_plan** out) {
+    return plan_create(sys, gens, ngen, center, nullptr, false, C, o, k, dt, steps, precision, method, block_p,
+                       workspace, workspace_bytes, hip_stream, out);
+}
+
+kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* gens, int32_t ngen,
+                                      const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
+                                      double dt, int64_t steps, int32_t precision, int32_t method,
+                                      void* hip_stream, kry_plan** out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(KRY_EINVAL, "out is NULL");
+    return plan_create(sys_t, gens, ngen, nullptr, center, true, C, o, k, dt, steps, precision, method, 0,
+                       nullptr, 0, hip_stream, out);
+}
+
 namespace {
 
 // Marks the basis as formed and copies it out (waits when the target is host memory).
@@ -764,7 +885,7 @@ kry_status finish_projection(kry_plan* plan, double* basis_out) {
     plan->projected = true;
     if (basis_out) {
         hipStream_t s = plan->stream;
-        const size_t bytes = (size_t)(plan->steps + 1) * plan->o * plan->nruns * sizeof(double);
+        const size_t bytes = (size_t)(plan->steps + 1) * plan->o_out * plan->ncols * sizeof(double);
         hipPointerAttribute_t attr{};
         bool device_ptr = false;
         if (hipPointerGetAttributes(&attr, basis_out) == hipSuccess)
@@ -1053,6 +1174,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     E.scal = plan->scal();
     E.L = Y.L;
     E.role = plan->role_dev;
+    E.job_run = plan->job_run_dev;
     E.dt = plan->dt;
     E.hess_mode = plan->hess_mode ? 1 : 0;
     E.B = Y.B;
@@ -1099,10 +1221,11 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
     E.anch = plan->anch();
     E.msize = plan->msize();
     E.scale = plan->scale();
-    hipError_t e = timed("expm_chain", s, [&] { return launch_expm_chain(E, plan->nruns, s); });
+    hipError_t e = timed("expm_chain", s, [&] { return launch_expm_chain(E, plan->njobs, s); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("expm_chain: ") + hipGetErrorString(e));
-    AssembleArgs A{plan->zmat(), plan->anch(), plan->msize(), plan->scale(), plan->nruns, plan->o,
-                   Y.B, Y.nanch, plan->steps, plan->basis()};
+    AssembleArgs A{plan->zmat(), plan->anch(), plan->msize(), plan->scale(), plan->njobs, plan->o,
+                   Y.B, Y.nanch, plan->steps, plan->basis(), plan->job_run_dev, plan->out_col_dev,
+                   plan->o_out, plan->ncols};
     e = timed("assemble", s, [&] { return launch_assemble(A, s); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("assemble: ") + hipGetErrorString(e));
     return finish_projection(plan, basis_out);
@@ -1115,10 +1238,10 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
     C.basis = plan->basis();
     C.zc = plan->zc_dev;
     C.radius = plan->rad_dev;
-    C.nruns = plan->nruns;
-    C.o = plan->o;
+    C.nruns = plan->ncols;
+    C.o = plan->o_out;
     C.steps = plan->steps;
-    for (int q = 0; q < plan->o; ++q) {
+    for (int q = 0; q < plan->o_out; ++q) {
         if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
         C.ulo[q] = unsafe[q].lo;
         C.uhi[q] = unsafe[q].hi;
@@ -1127,7 +1250,7 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
     C.verdict = plan->verdict();
     hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
-    plan->verdict_host.assign(6 + plan->nruns, 0.0);
+    plan->verdict_host.assign(6 + plan->ncols, 0.0);
     KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
                            hipMemcpyDeviceToHost, plan->stream));
     KRY_HIP(hipStreamSynchronize(plan->stream));
@@ -1141,8 +1264,8 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
     if (plan->nonfinite) out->status = KRY_ENUMERIC;
     if (z_out) {
         int32_t g = 0;
-        for (int32_t r = 0; r < plan->nruns; ++r)
-            if (plan->role[r] == 0) z_out[g++] = v[6 + r];
+        for (int32_t c = 0; c < plan->ncols; ++c)
+            if (plan->col_role[c] == 0) z_out[g++] = v[6 + c];
     }
     return KRY_OK;
 }
@@ -1209,6 +1332,8 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
     if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
     if (eps > 0.0 && plan->method != KRY_LANCZOS)
         return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
+    if (eps > 0.0 && plan->transposed)
+        return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
     if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
     plan->err_eps = eps;
     if (eps == 0.0) return KRY_OK;

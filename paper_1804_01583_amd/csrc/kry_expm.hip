@@ -13,6 +13,13 @@
 // at most B and (steps+1)/B long, instead of one recurrence over all steps.
 // The augmented run uses the bordered matrix H~ = [[0, 0], [|b| e_1, T]] and
 // P~ = [0, C Q] with scale 1; generator and center runs use T itself.
+//
+// Transposed route (Section 4.1): a run of A^T from the output row c_q is
+// projected on the rows of E^T.  Its generator and center values come from
+// T itself; the forcing column's value is the b row's projection of
+// beta0 times the integral of e^{T s} e_1, which is the bordered exponential
+// again with the whole of T (size k + 1).  Each such exponential is a job;
+// k_assemble scatters the jobs' rows to their (output row, column) places.
 #include "kry_internal.h"
 
 #include <cmath>
@@ -90,17 +97,21 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     double* S5 = lds + 5 * kSlot;
     __shared__ double s_red[kExpmThreads / 64];
 
-    const int run = blockIdx.x;
+    // one job per workgroup; a job exponentiates the matrix of one Krylov run
+    const int job = blockIdx.x;
+    const int run = E.job_run ? E.job_run[job] : job;
     const double* sc = run_scal(E, run);
     const int k = E.L.k, o = E.L.o;
     const int keff = min((int)sc[E.L.misc + MISC_KEFF], (int)sc[E.L.misc + MISC_KSTOP]);
-    const bool bordered = E.role[run] == 2;
+    const int role = E.role[job];
+    const bool bordered = role >= 2;
     int m = keff;                            // size of H
-    if (bordered) m = (keff > k - 1 ? k - 1 : keff) + 1;
+    if (role == 2) m = (keff > k - 1 ? k - 1 : keff) + 1;
+    if (role == 3) m = keff + 1;
     if (keff <= 0) m = 0;                    // zero start vector: the run contributes nothing
     if (threadIdx.x == 0) {
-        E.msize[run] = m;
-        E.scale[run] = bordered ? 1.0 : sc[E.L.beta + 0];
+        E.msize[job] = m;
+        E.scale[job] = bordered ? 1.0 : sc[E.L.beta + 0];
     }
     if (m == 0) return;
     const int mm = m + (m & 1);
@@ -203,8 +214,8 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     // keeps row i of Psi.  Slot 0 holds the ping-pong vectors: Z at
     // [cur * kMaxO * kLd], a at [2 * kMaxO * kLd + cur * kLd].
     constexpr int kZ = kMaxO * kLd;
-    double* Zg = E.Z + (int64_t)run * E.B * kMaxO * kMaxK;
-    double* Ag = E.anch + (int64_t)run * E.nanch * kMaxK;
+    double* Zg = E.Z + (int64_t)job * E.B * kMaxO * kMaxK;
+    double* Ag = E.anch + (int64_t)job * E.nanch * kMaxK;
     const int nz = o * mm;
     const bool zthr = tid < nz, athr = tid >= nz && tid < nz + mm;
     const int zq = zthr ? tid / mm : 0, zc_ = zthr ? tid % mm : 0, ai = athr ? tid - nz : 0;
@@ -271,7 +282,9 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     }
 }
 
-// basis[s][q][run] = scale * Z_{s mod B}[q] . a_{s div B}; one thread per (s, run)
+// basis[s][q][run] = scale * Z_{s mod B}[q] . a_{s div B}; one thread per (s, job).
+// With an output map, row q of job j goes to basis[s][job_run[j]][out_col[j][q]]
+// of an (o_out x ncols) basis, or nowhere when out_col is negative.
 __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (A.steps + 1) * A.nruns;
@@ -294,6 +307,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
         const double sc = A.scale[run];
 #pragma unroll
         for (int q = 0; q < kMaxO; ++q) y[q] *= sc;
+    }
+    if (A.out_col) {
+        const int64_t row = s * A.o_out + A.job_run[run];
+#pragma unroll
+        for (int q = 0; q < kMaxO; ++q) {
+            const int c = q < A.o ? A.out_col[run * kMaxO + q] : -1;
+            if (c >= 0) A.basis[row * A.ncols + c] = y[q];
+        }
+        return;
     }
 #pragma unroll
     for (int q = 0; q < kMaxO; ++q)

@@ -115,15 +115,17 @@ struct StartSrc {
 struct ExpmArgs {
     const double* scal;
     ScalLayout L;
-    const int32_t* role;     // 0 generator, 1 center, 2 augmented
+    const int32_t* role;     // per job: 0 generator or center, 2 augmented (k - 1 steps of T),
+                             // 3 transposed forcing column (bordered with the whole of T)
+    const int32_t* job_run;  // per job: the Krylov run it exponentiates (null: job j is run j)
     double dt;
     int32_t hess_mode;       // 0: tridiagonal from alpha/beta (Lanczos); 1: Hessenberg (Arnoldi)
     int32_t B;               // anchor spacing (power of two)
     int32_t nanch;           // anchors per run: ceil((steps + 1) / B)
-    double* Z;               // [nruns][B][kMaxO][kMaxK]  P Phi^r
-    double* anch;            // [nruns][nanch][kMaxK]     Psi^b e_1
-    int32_t* msize;          // [nruns] size of H used (0: the run contributes 0)
-    double* scale;           // [nruns] beta0, or 1 for the augmented run
+    double* Z;               // [njobs][B][kMaxO][kMaxK]  P Phi^r
+    double* anch;            // [njobs][nanch][kMaxK]     Psi^b e_1
+    int32_t* msize;          // [njobs] size of H used (0: the job contributes 0)
+    double* scale;           // [njobs] beta0, or 1 for a bordered job
 };
 
 struct AssembleArgs {
@@ -131,9 +133,12 @@ struct AssembleArgs {
     const double* anch;
     const int32_t* msize;
     const double* scale;
-    int32_t nruns, o, B, nanch;
+    int32_t nruns, o, B, nanch;   // nruns: jobs
     int64_t steps;
-    double* basis;           // [(steps+1)][o][nruns]
+    double* basis;           // [(steps+1)][o][nruns], or [(steps+1)][o_out][ncols] with an output map
+    const int32_t* job_run;  // output map (null: none): job -> output row of the basis
+    const int32_t* out_col;  // [njobs][kMaxO]: projection row -> basis column, -1 to drop
+    int32_t o_out, ncols;
 };
 
 struct CheckArgs {

@@ -71,6 +71,9 @@ def _load():
     lib.kry_plan_create.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
                                     ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
                                     ct.c_int32, ct.c_int32, ct.c_int32, P, ct.c_size_t, P, ct.POINTER(P)]
+    lib.kry_plan_create_transposed.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32,
+                                               ct.POINTER(KrySegs), ct.POINTER(KrySegs), ct.c_int32, ct.c_int32,
+                                               ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.POINTER(P)]
     lib.kry_project_expm.argtypes = [P, P]
     lib.kry_check_box_safety.argtypes = [P, ct.POINTER(KryInterval), ct.POINTER(KryVerdict), P]
     lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
@@ -92,7 +95,7 @@ def _load():
     lib.kry_profile_enable.argtypes = [ct.c_int32]
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
-    for f in ("kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
@@ -102,7 +105,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["kry_plan_create", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
@@ -136,6 +139,18 @@ def kry_plan_create(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Se
     _check(lib.kry_plan_create(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps,
                                precision, method, block_p, workspace_ptr, workspace_bytes, stream_ptr,
                                ct.byref(out)))
+    return out.value
+
+
+def kry_plan_create_transposed(system_t: KrySystem, gens: Sequence[KryGen], center: Optional[KrySegs],
+                               C: Sequence[KrySegs], k: int, dt: float, steps: int, precision=KRY_FP64,
+                               method=KRY_AUTO, stream_ptr=None) -> int:
+    garr = (KryGen * max(len(gens), 1))(*gens)
+    carr = (KrySegs * len(C))(*C)
+    out = ct.c_void_p()
+    cptr = ct.byref(center) if center is not None else None
+    _check(lib.kry_plan_create_transposed(ct.byref(system_t), garr, len(gens), cptr, carr, len(C), k, dt, steps,
+                                          precision, method, stream_ptr, ct.byref(out)))
     return out.value
 
 
@@ -259,6 +274,26 @@ def _segs(seg, keep) -> KrySegs:
     w = np.ascontiguousarray(seg.w, dtype=np.float64)
     keep += [lo, hi, w]
     return KrySegs(lo.size, lo.ctypes.data, hi.ctypes.data, w.ctypes.data)
+
+
+class _Runs:
+    """Index ranges [lo, hi) with one value each (the layout of kry_segs)."""
+
+    def __init__(self, lo, hi, w):
+        self.lo, self.hi, self.w = lo, hi, w
+
+
+def _runs_of(v) -> _Runs:
+    """A dense host vector as maximal runs of equal nonzero entries (a change
+    of format for the library's segment sets)."""
+    v = np.asarray(v, np.float64)
+    nz = v != 0.0
+    # a run starts where an entry is nonzero and differs from its left neighbour
+    # (or that neighbour is zero); it ends before the next start or zero
+    start = nz & np.concatenate(([True], (v[1:] != v[:-1]) | ~nz[:-1]))
+    lo = np.flatnonzero(start)
+    stop = np.flatnonzero(nz & np.concatenate(((v[1:] != v[:-1]) | ~nz[1:], [True]))) + 1
+    return _Runs(lo.astype(np.int64), stop.astype(np.int64), v[lo])
 
 
 class DeviceSystem:
@@ -416,3 +451,47 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class TransposedPlan(Plan):
+    """kry_plan_create_transposed: the basis by one run of A^T per output row
+    (Section 4.1).  ``dsys_t`` holds the transposed matrix (for a symmetric
+    system, the system itself); generators, center, forcing and outputs are
+    those of ``dsys_t.problem`` unless given.  A dense forcing or center is
+    handed to the library as index ranges."""
+
+    def __init__(self, dsys_t: DeviceSystem, k=None, dt=None, steps=None, precision=KRY_FP64, method=KRY_AUTO,
+                 stream=None, gens=None, C=None):
+        import torch
+        p = dsys_t.problem
+        self.dsys = dsys_t
+        self._sys = dsys_t.system_for(precision)
+        self.k = p.k if k is None else k
+        self.dt = p.dt if dt is None else dt
+        self.steps = p.steps if steps is None else steps
+        gens = p.gens if gens is None else gens
+        C = p.C if C is None else C
+        self.ngen = len(gens)
+        self.o = len(C)
+        keep = []
+        self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
+        self._C = [_segs(c, keep) for c in C]
+        self._center = _segs(_runs_of(p.center), keep) if p.center is not None else None
+        if p.b is not None:
+            self._bseg = _segs(_runs_of(p.b), keep)
+            self._sys.b = None
+            self._sys.b_segs = ct.pointer(self._bseg)
+        self._keep = keep
+        self.workspace = None
+        self.stream = torch.cuda.current_stream(dsys_t.device) if stream is None else stream
+        self.handle = None
+        self.handle = kry_plan_create_transposed(self._sys, self._gens, self._center, self._C, self.k, self.dt,
+                                                 self.steps, precision, method, self.stream.cuda_stream)
+        self.runs = kry_plan_runs(self.handle)
+        self.ncols = self.ngen + (p.center is not None) + (p.b is not None or getattr(p, "b_seg", None) is not None)
+        self.roles = ["gen"] * self.ngen + (["center"] if p.center is not None else []) + \
+            (["affine"] if self.ncols > self.ngen + (p.center is not None) else [])
+
+    def krylov(self, run: int):
+        """Transposed run ``run`` (output row): P has one row per basis column."""
+        return kry_plan_krylov(self.handle, run, self.k, self.ncols)

@@ -2,6 +2,7 @@
 include/kry.h declares, the ctypes structs have the C layout (checked
 against a C program compiled here with gcc), and argument validation
 rejects bad input before any device work."""
+import ctypes as ct
 import math
 import os
 import re
@@ -146,3 +147,41 @@ def test_prepared_matrix_entry_points_reject_bad_arguments():
     assert kry.lib.kry_matrix_bytes(None, ct.byref(b)) == kry.KRY_EINVAL
     kry.lib.kry_matrix_destroy(None)
 
+
+
+@pytest.mark.parametrize("bad", ["dense_b", "k_forcing", "rows", "block", "plain", "center_range", "empty"])
+def test_transposed_plan_rejects_bad_arguments(bad):
+    from paper_1804_01583_amd import kry
+    import workloads as W
+    s = _csr_system(50)
+    keep = []
+    bseg = kry._segs(W.segments_from_ranges([(10, 20)], 0.5), keep)
+    s.b_segs = ct.pointer(bseg)
+    k, method = 5, kry.KRY_AUTO
+    gens = [W.Generator(W.segments_from_ranges([(0, 3)]), 0.0, 1.0)]
+    center = None
+    expected = kry.KRY_EINVAL
+    if bad == "dense_b":
+        s.b_segs = None
+        s.b = 0x2000                 # never dereferenced: rejected before any device work
+        expected = kry.KRY_ENOTSUP
+    elif bad == "k_forcing":
+        k = 56                       # the forcing column's exponential has size k + 1
+    elif bad == "rows":
+        gens = [W.Generator(W.segments_from_ranges([(j, j + 1)]), 0.0, 1.0) for j in range(8)]
+    elif bad == "block":
+        method = kry.KRY_BLOCK_ARNOLDI
+        expected = kry.KRY_ENOTSUP
+    elif bad == "plain":
+        method = kry.KRY_LANCZOS_PLAIN
+        expected = kry.KRY_ENOTSUP
+    elif bad == "center_range":
+        center = kry._segs(W.segments_from_ranges([(45, 60)]), keep)
+    elif bad == "empty":
+        gens = []
+        s.b_segs = None
+    kg = [kry.KryGen(kry._segs(g.seg, keep), g.zc, g.radius) for g in gens]
+    kc = [kry._segs(W.segments_from_ranges([(5, 9)]), keep)]
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_plan_create_transposed(s, kg, center, kc, k, 0.1, 10, kry.KRY_FP64, method, None)
+    assert ei.value.status == expected, kry.lib.kry_last_error()

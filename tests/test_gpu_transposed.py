@@ -1,0 +1,138 @@
+"""Parity of the transposed route (Section 4.1, kry_plan_create_transposed)
+with the oracle's verify_transposed, element by element: the worked
+example (nonsymmetric, Arnoldi on A^T), random symmetric systems with a
+center and forcing (Lanczos), a CSR heat problem with eight initial-space
+columns and one output, and a matrix-free stencil."""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import oracle.transpose as OT
+import workloads as W
+from gpu_helpers import RTOL, assert_basis_parity, assert_krylov_parity, assert_verdict_parity, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "harmonic.json")))
+
+
+def _transposed_problem(p):
+    """The same problem with A^T stored (a change of input only)."""
+    if p.symmetric or p.kind != "csr":
+        return p
+    At = oracle.system_matrix(p).T.tocsr()
+    At.sort_indices()
+    return dataclasses.replace(p, rowptr=At.indptr.astype(np.int64), colidx=At.indices.astype(np.int32),
+                               vals=At.data.astype(np.float64))
+
+
+def gpu_verify_transposed(p, **kw):
+    from paper_1804_01583_amd import kry
+    print(f"[gpu] transposed {p.name} n={p.n} k={kw.get('k', p.k)} o={p.o} kw={kw}", flush=True)
+    plan = kry.TransposedPlan(kry.DeviceSystem(_transposed_problem(p)), **kw)
+    basis = plan.basis()
+    verdict = plan.check(p.unsafe)
+    runs = [plan.krylov(r) for r in range(len(plan.runs))]
+    roles = list(plan.roles)
+    plan.close()
+    return {"basis": basis, "verdict": verdict, "runs": runs, "roles": roles}
+
+
+def _parity(p, k=None, krylov=None, **kw):
+    """Basis and verdict parity; H and P entrywise too while three-term
+    Lanczos keeps its basis orthogonal (k <= 20 here: past that, rounding
+    changes H while the projected basis still agrees)."""
+    got = gpu_verify_transposed(p, **({"k": k} if k else {}), **kw)
+    ref = OT.verify_transposed(p, k=k)
+    assert got["roles"] == ref["roles"]
+    assert len(got["runs"]) == p.o
+    if krylov is None:
+        krylov = (k or p.k) <= 20 or not p.symmetric
+    for g, r in zip(got["runs"], ref["runs"]):
+        assert g["k_eff"] == r.k_eff
+        if krylov:
+            assert_krylov_parity(g, r)
+    worst = assert_basis_parity(got["basis"], ref["basis"])
+    assert_verdict_parity(got["verdict"], ref["verdict"], ref["basis"])
+    return got, ref, worst
+
+
+def test_worked_example_one_run():
+    require_gpu()
+    p = W.harmonic_oscillator()
+    got, ref, _ = _parity(p)
+    M = got["basis"][3, 0]
+    paper = GOLD["projected_basis_CeAtE_at_3pi_over_4"]["row"]
+    np.testing.assert_allclose([M[0], M[1] + M[2]], paper, atol=5e-3)
+    assert got["verdict"]["first_step"] == GOLD["verdicts"]["unsafe_first_step"]
+
+
+@pytest.mark.parametrize("seed,center,affine,k", [(11, True, True, 12), (12, False, True, 30), (13, True, False, 20),
+                                                  (14, True, True, 55)])
+def test_random_symmetric(seed, center, affine, k):
+    require_gpu()
+    p = W.random_symmetric(n=300, k=k, steps=50, dt=0.05, ngen=3, o=2, seed=seed, affine=affine, center=center)
+    _parity(p)
+
+
+def test_nonsymmetric_arnoldi():
+    require_gpu()
+    p = W.random_symmetric(n=200, k=16, steps=40, dt=0.05, ngen=2, o=3, seed=21, affine=True, center=True)
+    # a nonsymmetric matrix: the lower triangle scaled, so A^T differs from A
+    A = oracle.system_matrix(p).toarray()
+    A = A + 0.3 * np.tril(A, -1)
+    As = sp.csr_matrix(A)
+    As.sort_indices()
+    p = dataclasses.replace(p, symmetric=False, rowptr=As.indptr.astype(np.int64),
+                            colidx=As.indices.astype(np.int32), vals=As.data.astype(np.float64))
+    _parity(p)
+
+
+def test_eight_columns_one_output_csr():
+    require_gpu()
+    p = W.heat3d_many_inputs(m=20, k=30, steps=300, floor=0.4)
+    got, ref, _ = _parity(p, krylov=False)
+    assert ref["verdict"]["first_step"] > 0
+    assert got["basis"].shape == (301, 1, 8)
+
+
+def test_breakdown_and_zero_output_row():
+    require_gpu()
+    # a unit output row on an isolated node breaks down at once; a second
+    # output row over that node only gives a one-dimensional space too
+    p = W.random_symmetric(n=120, k=10, steps=20, dt=0.05, ngen=2, o=1, seed=5, affine=True, center=False)
+    A = oracle.system_matrix(p).tolil()
+    A[7, :] = 0.0
+    A[:, 7] = 0.0
+    A[7, 7] = -0.5
+    As = A.tocsr()
+    As.sort_indices()
+    p = dataclasses.replace(p, rowptr=As.indptr.astype(np.int64), colidx=As.indices.astype(np.int32),
+                            vals=As.data.astype(np.float64),
+                            C=[W.segments_from_ranges([(7, 8)]), W.segments_from_ranges([(7, 8)], 2.0)],
+                            unsafe=np.array([[0.5, np.inf], [0.5, np.inf]]))
+    got, ref, _ = _parity(p)
+    assert all(r["k_eff"] == 1 for r in got["runs"])
+
+
+def test_stencil_matrix_free():
+    require_gpu()
+    p = W.heat3d_stencil(m=16, k=24, dt=0.01, steps=100)
+    _parity(p)
+
+
+def test_forward_and_transposed_agree_on_the_gpu():
+    # both routes converge to the same basis: at k = 55 on n = 8000 heat up
+    # to t = 2 their difference is far below the output scale
+    require_gpu()
+    from gpu_helpers import gpu_verify
+    p = W.heat3d_many_inputs(m=20, k=55, steps=100)
+    fwd = gpu_verify(p)
+    tr = gpu_verify_transposed(p)
+    scale = np.abs(fwd["basis"]).max()
+    assert np.abs(fwd["basis"] - tr["basis"]).max() <= 1e-8 * scale

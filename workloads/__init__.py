@@ -398,14 +398,14 @@ def small_heat3d(m=12, D=0.01, k=20, dt=0.02, steps=200, seed=7) -> Problem:
     return p
 
 
-def heat3d_many_inputs(m=100, D=0.01, k=40, dt=0.02, steps=1000, seed=5) -> Problem:
+def heat3d_many_inputs(m=100, D=0.01, k=40, dt=0.02, steps=1000, seed=5, floor=0.01) -> Problem:
     """An initial space wider than the output space (i = 8 > o = 1), the case
     the transposed simulation of Section 4.1 is for: 3D heat on an m^3 grid
     (CSR, Dirichlet), forcing 0.1 on a seeded 10^3 sub-cube given as index
     ranges, six box generators over disjoint seeded 8^3 cubes (z = 1.0 +- 0.1
-    each), a fixed initial part 0.5 on a 12^3 cube (the center, also as index
-    ranges), and one output: the mean over the central 10^3 cube, unsafe
-    when it reaches 0.3."""
+    each), a fixed initial part 0.5 on a seeded 12^3 warm cube (the center,
+    also as index ranges), and one output: the mean over the warm cube,
+    unsafe when it cools to `floor` or below."""
     n = m**3
     coef, _, fbox = _heat3d_parts(m, D, seed)
     bseg = box_segments((m, m, m), fbox, 0.1)
@@ -423,14 +423,11 @@ def heat3d_many_inputs(m=100, D=0.01, k=40, dt=0.02, steps=1000, seed=5) -> Prob
     woff = int(rng.integers(0, m - wc + 1))
     wbox = ((woff, woff + wc),) * 3
     center_seg = box_segments((m, m, m), wbox, 0.5)
-    cc = max(m // 2 - 5, 0)
-    cbox = ((cc, min(cc + 10, m)),) * 3
-    ccount = int(np.prod([hi - lo for lo, hi in cbox]))
-    C = [box_segments((m, m, m), cbox, 1.0 / ccount)]
-    unsafe = np.array([[0.3, math.inf]])
+    C = [box_segments((m, m, m), wbox, 1.0 / wc**3)]
+    unsafe = np.array([[-math.inf, float(floor)]])
     return Problem("heat3d_many_inputs", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
                    b_seg=bseg, center=center_seg.dense(n), rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
-                   meta={"m": m, "forcing_box": fbox, "warm_box": wbox, "out_box": cbox},
+                   meta={"m": m, "forcing_box": fbox, "warm_box": wbox},
                    note="3D heat, eight initial-space columns, one output")
 
 
