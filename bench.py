@@ -15,7 +15,11 @@ Prints one JSON line.  Options:
   --no-cpu-baseline   skip timing the CPU oracle
   --m M           grid edge (default 100)
   --workload W    heat3d_csr (the benchmark line), heat3d_stencil (1000^3 matrix-free),
-                  heat1d, conv_diff3d
+                  heat1d, conv_diff3d, heat3d_paper, heat3d_many_inputs (eight
+                  initial-space columns, one output)
+  --route R       forward (one run per column of E) or transposed (one run of A^T
+                  per output row, Section 4.1); default transposed for
+                  heat3d_many_inputs, forward otherwise
   --precision P   fp64 (default) or fp32 (FP32-basis mode; the FP64 path is then
                   timed too, for the ratio to plain FP64)
   --method M      auto (Lanczos / Arnoldi by symmetry) or block (block Arnoldi,
@@ -65,9 +69,11 @@ def main():
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="skip the second timed pass with per-kernel events (long runs)")
     ap.add_argument("--workload", default="heat3d_csr",
-                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper", "serve"],
+                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper",
+                             "heat3d_many_inputs", "serve"],
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--route", default=None, choices=["forward", "transposed"])
     ap.add_argument("--method", default=None, choices=["auto", "block", "plain"])
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
@@ -114,8 +120,11 @@ def main():
                 args.error_target = 1e-6
         else:
             p = W.heat3d_paper_stencil(m=m, k=args.k or 5932)
+    elif args.workload == "heat3d_many_inputs":
+        p = W.heat3d_many_inputs(m=args.m or 100)
     else:
         p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=16, o=5, k=30)
+    transposed = (args.route or ("transposed" if args.workload == "heat3d_many_inputs" else "forward")) == "transposed"
     method_name = args.method or {"conv_diff3d": "block", "heat3d_paper": "plain"}.get(args.workload, "auto")
     method = {"block": kry.KRY_BLOCK_ARNOLDI, "plain": kry.KRY_LANCZOS_PLAIN}.get(method_name, kry.KRY_AUTO)
     dsys = kry.DeviceSystem(p, device="cuda")
@@ -127,12 +136,13 @@ def main():
             dsys.prepare(prec)
         torch.cuda.synchronize()
     m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
-                args.error_target, not args.no_kernel_events)
+                args.error_target, not args.no_kernel_events, transposed)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
         log("plain FP64 on the same workload, for the ratio")
-        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup, method, args.error_target)
+        m64 = measure(torch, kry, p, dsys, kry.KRY_FP64, args.steps, args.warmup, method, args.error_target,
+                      True, transposed)
         fp64_ref = {"value": m64["value"], "ms_per_step": m64["ms_per_step"],
                     "ratio_fp32_over_fp64": m["value"] / m64["value"]}
     kern, nruns, verdict = m["kern"], m["nruns"], m["verdict"]
@@ -147,7 +157,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and p.n <= 2_000_000:
         log("timing the CPU oracle on the same workload (one whole verification)")
-        cpu = cpu_baseline(p)
+        cpu = cpu_baseline(p, transposed)
 
     out = {
         "metric": "Krylov step HBM GB/s (% peak); verified time-steps/s vs plain FP64; p99 query latency",
@@ -163,7 +173,8 @@ def main():
         "dtype": "f64" if not f32 else "f32-storage/f64-arith",
         "data": "synthetic",
         "config": {"workload": describe(p, nruns, args.precision, method_name), "n": n, "nnz": nnz, "k": p.k,
-                   "time_steps": p.steps, "runs": nruns, "precision": args.precision,
+                   "time_steps": p.steps, "basis_columns": nruns, "krylov_runs": m["krylov_runs"],
+                   "route": "transposed" if transposed else "forward", "precision": args.precision,
                    "method": {"block": "block_arnoldi", "plain": "lanczos_plain"}.get(
                        method_name, "lanczos" if p.symmetric else "arnoldi"),
                    "error_target": args.error_target or None,
@@ -220,14 +231,21 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
-def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0, kernel_events=True):
+def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0, kernel_events=True,
+            transposed=False):
     """Times `steps` whole verifications (after `warmup`), then the same with
     per-kernel HIP events; returns the throughput and per-kernel figures."""
     stream = torch.cuda.current_stream()
     used = {}
+    krylov_runs = {}
 
     def step():
-        plan = kry.Plan(dsys, stream=stream, precision=precision, method=method)
+        if transposed:
+            plan = kry.TransposedPlan(dsys, stream=stream, precision=precision, method=method)
+            krylov_runs["n"] = len(plan.runs)
+        else:
+            plan = kry.Plan(dsys, stream=stream, precision=precision, method=method)
+            krylov_runs["n"] = plan.nruns
         if error_target > 0.0:
             plan.set_error_target(error_target)
         plan.project_expm(None)
@@ -272,7 +290,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
     # algorithmic bytes per launch, all runs of the plan advanced by one launch
     # (P = runs per batch; every workload here fits one batch)
     es = 4 if precision == kry.KRY_FP32_BASIS else 8
-    n, nnz, P, k = p.n, p.nnz, nruns, p.k
+    n, nnz, P, k = p.n, p.nnz, krylov_runs["n"], p.k
     vec = es * n * P
     if p.kind == "csr":
         mat = (4 if es == 4 else 8) * nnz + 4 * nnz + 8 * (n + 1)   # values, int32 columns, int64 row pointers
@@ -322,7 +340,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
                        key=lambda n_: kern[n_]["total_ms_per_step"])
         return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
                 "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
-                "dom_name": dom_name, "error_control": used or None}
+                "dom_name": dom_name, "error_control": used or None, "krylov_runs": krylov_runs["n"]}
     mv = ("spmv_sell" if "spmv_sell" in kern else "spmv_csr") if p.kind == "csr" else "spmv_stencil"
     # the roofline kernel: the mat-vec, or the one with the most time when a
     # stored-basis pass outweighs it
@@ -332,7 +350,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
             dom_name = name
     return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
             "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
-            "dom_name": dom_name, "error_control": used or None}
+            "dom_name": dom_name, "error_control": used or None, "krylov_runs": krylov_runs["n"]}
 
 
 def describe(p, nruns, precision, method_name="auto"):
@@ -359,6 +377,10 @@ def describe(p, nruns, precision, method_name="auto"):
         return (f"3D heat {m}^3 as in the paper (insulated faces, exchange 0.5 at x=1, CSR n={p.n}, nnz={p.nnz}), "
                 f"centre-point output, three-vector Lanczos with the Lemma 1 error control (k <= {p.k}), "
                 f"dt={p.dt}, {p.steps} steps, {prec}")
+    if p.name == "heat3d_many_inputs":
+        m = p.meta["m"]
+        return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + forcing, 6 generators + center + forcing = "
+                f"{nruns} basis columns, o={p.o} output, Lanczos k={p.k}, dt={p.dt}, {p.steps} steps, {prec}")
     return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} {prec}"
 
 
@@ -389,20 +411,22 @@ def counter_traffic(path):
         return None
 
 
-def cpu_baseline(p):
+def cpu_baseline(p, transposed=False):
     """The oracle as it stands, on this host's CPU, one thread, over one whole
-    verification of the same workload."""
+    verification of the same workload (by the same route)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:   # pragma: no cover
         threadpool_limits = None
     import oracle
+    import oracle.transpose
+    verify = oracle.transpose.verify_transposed if transposed else oracle.verify
     t0 = time.perf_counter()
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):
-            res = oracle.verify(p)
+            res = verify(p)
     else:
-        res = oracle.verify(p)
+        res = verify(p)
     dt = time.perf_counter() - t0
     nruns = res["basis"].shape[2]
     return {"value": (p.steps + 1) * nruns / dt, "unit": "verified time-steps/s", "cores": 1, "kind": "oracle",
