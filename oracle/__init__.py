@@ -23,7 +23,9 @@ Billion Dimensions", arXiv 1804.01583):
   Galerkin approximant for a block start,
 * the a-posteriori choice of k by the error bound of Lemma 1 (``adaptive``),
 * the basis by simulation of the transposed dynamics, one run per output
-  row (Section 4.1, ``transpose``).
+  row (Section 4.1, ``transpose``),
+* the per-step safety LP of Section 2.1 for a polytopic initial set and a
+  conjunction of output halfspaces (``lp``, SciPy's linprog as the solver).
 
 All pins of these functions live in ``tests/test_oracle_*.py``.
 """
@@ -35,3 +37,4 @@ from .krylov import (  # noqa: F401
 from .block import BlockResult, block_arnoldi, block_project_steps, block_verify, qr_posdiag  # noqa: F401
 from . import adaptive  # noqa: F401
 from . import transpose  # noqa: F401
+from . import lp  # noqa: F401

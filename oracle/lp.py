@@ -1,0 +1,95 @@
+"""Per-step safety LP (Section 2.1) in the initial-space coordinates.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+At time step s the reachable outputs are y = M_s z + f_s, with M_s the
+generator columns of the basis C e^{A s dt} E and f_s the sum of its fixed
+columns (center, forcing: coefficient 1).  The initial set is a polytope in
+z: the generators' box |z_j - zc_j| <= r_j intersected with G z <= h (the
+constraints I_x x0 <= iota_x of Section 2.1 written for x0 = E z).  The
+unsafe set is a conjunction of halfspaces in the output space,
+U y <= u (Section 3.1).  Step s is unsafe when
+
+    { z : z in box, G z <= h, U (M_s z + f_s) <= u }
+
+is non-empty (the LP of Section 2.1, whose x = e^{At} x0 equalities are
+substituted through the basis); a feasible z is the counter-example of
+Section 2.2.  The LP solver is SciPy's ``linprog`` (a library primitive).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.optimize import linprog
+
+
+def split_basis(basis_s: np.ndarray, roles):
+    """(M_s, f_s) from one step's basis (o x ncols)."""
+    gen = [i for i, r in enumerate(roles) if r == "gen"]
+    fix = [i for i, r in enumerate(roles) if r != "gen"]
+    return basis_s[:, gen], basis_s[:, fix].sum(axis=1)
+
+
+def lp_feasible(M, f, zlo, zhi, G, h, U, u):
+    """Feasibility of {z in [zlo, zhi], G z <= h, U (M z + f) <= u}.
+    Returns (feasible, z) with z a feasible point (None when infeasible)."""
+    d = M.shape[1]
+    A = np.vstack([G.reshape(-1, d), U @ M])
+    b = np.concatenate([h, u - U @ f])
+    if d == 0:
+        ok = bool(np.all(b >= 0.0))
+        return ok, (np.zeros(0) if ok else None)
+    res = linprog(np.zeros(d), A_ub=A if A.size else None, b_ub=b if b.size else None,
+                  bounds=list(zip(zlo, zhi)), method="highs")
+    if res.status == 0:
+        return True, np.asarray(res.x, np.float64)
+    if res.status == 2:
+        return False, None
+    raise RuntimeError(f"linprog: {res.message}")
+
+
+def lp_margin(M, f, zlo, zhi, G, h, U, u):
+    """The smallest t with {z in box : a_i z - t <= b_i for every G and U
+    row, each row scaled so its largest coefficient in z is 1}: negative
+    when the set has an interior point, positive when it is empty.  Rows
+    without a coefficient in z count with their own sign (-b_i).  Used by
+    tests to keep decisions away from rounding."""
+    d = M.shape[1]
+    A = np.vstack([G.reshape(-1, d), U @ M])
+    b = np.concatenate([h, u - U @ f])
+    zero = np.abs(A).max(axis=1) == 0.0 if A.size else np.zeros(0, bool)
+    t_zero = float(np.max(-b[zero])) if zero.any() else -np.inf
+    A, b = A[~zero], b[~zero]
+    if A.shape[0] == 0:
+        return t_zero if zero.any() else -np.inf
+    s = np.abs(A).max(axis=1)
+    A, b = A / s[:, None], b / s
+    # variables (z, t): minimise t
+    c = np.zeros(d + 1); c[d] = 1.0
+    Aub = np.hstack([A, -np.ones((A.shape[0], 1))])
+    res = linprog(c, A_ub=Aub, b_ub=b, bounds=list(zip(zlo, zhi)) + [(None, None)], method="highs")
+    if res.status != 0:
+        raise RuntimeError(f"linprog: {res.message}")
+    return max(float(res.x[d]), t_zero)
+
+
+def lp_check(basis: np.ndarray, roles, zc, radius, G, h, U, u):
+    """The LP at every step s = 0..S.  Returns dict(first_step (-1 when
+    safe), z (counter-example), y (its outputs M z + f), feasible (per-step
+    bool))."""
+    zc = np.asarray(zc, np.float64); radius = np.asarray(radius, np.float64)
+    zlo, zhi = zc - radius, zc + radius
+    G = np.asarray(G, np.float64).reshape(-1, zc.size); h = np.asarray(h, np.float64)
+    U = np.asarray(U, np.float64).reshape(-1, basis.shape[1]); u = np.asarray(u, np.float64)
+    feas = np.zeros(basis.shape[0], bool)
+    first, z_ce = -1, None
+    for s in range(basis.shape[0]):
+        M, f = split_basis(basis[s], roles)
+        ok, z = lp_feasible(M, f, zlo, zhi, G, h, U, u)
+        feas[s] = ok
+        if ok and first < 0:
+            first, z_ce = s, z
+    y = None
+    if first >= 0:
+        M, f = split_basis(basis[first], roles)
+        y = M @ z_ce + f
+    return {"first_step": first, "z": z_ce, "y": y, "feasible": feas}
