@@ -15,11 +15,24 @@ U y <= u (Section 3.1).  Step s is unsafe when
 is non-empty (the LP of Section 2.1, whose x = e^{At} x0 equalities are
 substituted through the basis); a feasible z is the counter-example of
 Section 2.2.  The LP solver is SciPy's ``linprog`` (a library primitive).
+
+Tolerance (the paper's LP solver works to 1e-6, Section 4.2): the decision
+is made on the constraint rows scaled so that each row's largest
+coefficient in z is 1; step s is unsafe when some z in the box violates no
+scaled row by more than LP_TOL = 1e-6.  Scaling a row by a positive number
+leaves the set unchanged, and it makes the tolerance independent of how U
+and G are scaled; a solver's absolute tolerance on unscaled rows is not
+(an output row whose basis entries are 1e-7 would be judged at the
+solver's 1e-7 with a 100 % relative error).  The decision errs towards
+"unsafe" by at most LP_TOL.
 """
 from __future__ import annotations
 
 import numpy as np
 from scipy.optimize import linprog
+
+
+LP_TOL = 1e-6
 
 
 def split_basis(basis_s: np.ndarray, roles):
@@ -30,7 +43,8 @@ def split_basis(basis_s: np.ndarray, roles):
 
 
 def lp_feasible(M, f, zlo, zhi, G, h, U, u):
-    """Feasibility of {z in [zlo, zhi], G z <= h, U (M z + f) <= u}.
+    """Exact-arithmetic feasibility of {z in [zlo, zhi], G z <= h,
+    U (M z + f) <= u} as SciPy decides it (its own absolute tolerance).
     Returns (feasible, z) with z a feasible point (None when infeasible)."""
     d = M.shape[1]
     A = np.vstack([G.reshape(-1, d), U @ M])
@@ -47,20 +61,21 @@ def lp_feasible(M, f, zlo, zhi, G, h, U, u):
     raise RuntimeError(f"linprog: {res.message}")
 
 
-def lp_margin(M, f, zlo, zhi, G, h, U, u):
+def lp_margin(M, f, zlo, zhi, G, h, U, u, with_point=False):
     """The smallest t with {z in box : a_i z - t <= b_i for every G and U
     row, each row scaled so its largest coefficient in z is 1}: negative
     when the set has an interior point, positive when it is empty.  Rows
-    without a coefficient in z count with their own sign (-b_i).  Used by
-    tests to keep decisions away from rounding."""
+    without a coefficient in z count with their own sign (-b_i).  With
+    ``with_point`` also returns the minimising z."""
     d = M.shape[1]
     A = np.vstack([G.reshape(-1, d), U @ M])
     b = np.concatenate([h, u - U @ f])
-    zero = np.abs(A).max(axis=1) == 0.0 if A.size else np.zeros(0, bool)
+    zero = np.abs(A).max(axis=1) == 0.0 if (A.size and d) else np.ones(A.shape[0], bool)
     t_zero = float(np.max(-b[zero])) if zero.any() else -np.inf
     A, b = A[~zero], b[~zero]
     if A.shape[0] == 0:
-        return t_zero if zero.any() else -np.inf
+        # any box point is as good as any other; the centre of the box
+        return (t_zero, 0.5 * (np.asarray(zlo) + np.asarray(zhi))) if with_point else t_zero
     s = np.abs(A).max(axis=1)
     A, b = A / s[:, None], b / s
     # variables (z, t): minimise t
@@ -69,27 +84,31 @@ def lp_margin(M, f, zlo, zhi, G, h, U, u):
     res = linprog(c, A_ub=Aub, b_ub=b, bounds=list(zip(zlo, zhi)) + [(None, None)], method="highs")
     if res.status != 0:
         raise RuntimeError(f"linprog: {res.message}")
-    return max(float(res.x[d]), t_zero)
+    t = max(float(res.x[d]), t_zero)
+    return (t, np.asarray(res.x[:d], np.float64)) if with_point else t
 
 
 def lp_check(basis: np.ndarray, roles, zc, radius, G, h, U, u):
-    """The LP at every step s = 0..S.  Returns dict(first_step (-1 when
-    safe), z (counter-example), y (its outputs M z + f), feasible (per-step
-    bool))."""
+    """The LP at every step s = 0..S, decided with LP_TOL on the scaled rows
+    (see the module docstring).  Returns dict(first_step (-1 when safe), z
+    (counter-example), y (its outputs M z + f), feasible (per-step bool),
+    margin (per-step smallest scaled violation))."""
     zc = np.asarray(zc, np.float64); radius = np.asarray(radius, np.float64)
     zlo, zhi = zc - radius, zc + radius
     G = np.asarray(G, np.float64).reshape(-1, zc.size); h = np.asarray(h, np.float64)
     U = np.asarray(U, np.float64).reshape(-1, basis.shape[1]); u = np.asarray(u, np.float64)
     feas = np.zeros(basis.shape[0], bool)
+    margin = np.zeros(basis.shape[0])
     first, z_ce = -1, None
     for s in range(basis.shape[0]):
         M, f = split_basis(basis[s], roles)
-        ok, z = lp_feasible(M, f, zlo, zhi, G, h, U, u)
-        feas[s] = ok
-        if ok and first < 0:
+        t, z = lp_margin(M, f, zlo, zhi, G, h, U, u, with_point=True)
+        margin[s] = t
+        feas[s] = t <= LP_TOL
+        if feas[s] and first < 0:
             first, z_ce = s, z
     y = None
     if first >= 0:
         M, f = split_basis(basis[first], roles)
         y = M @ z_ce + f
-    return {"first_step": first, "z": z_ce, "y": y, "feasible": feas}
+    return {"first_step": first, "z": z_ce, "y": y, "feasible": feas, "margin": margin}

@@ -44,11 +44,13 @@ def test_box_and_interval_reduce_to_the_box_check(seed):
     box = oracle.box_check(res["basis"], res["roles"], zc, rad, np.array([[lo, hi]]))
     out = OL.lp_check(res["basis"], res["roles"], zc, rad, np.zeros((0, 3)), np.zeros(0),
                       np.array([[1.0], [-1.0]]), np.array([hi, -lo]))
-    # compare where the range is not within rounding of the interval ends
-    clear = (np.abs(box["lo"][:, 0] - hi) > 1e-9) & (np.abs(box["hi"][:, 0] - lo) > 1e-9)
+    # compare where the range is not within the LP tolerance of the interval
+    # ends (the LP errs towards unsafe by at most LP_TOL on scaled rows)
+    clear = (np.abs(out["margin"] - OL.LP_TOL) > 1e-7)
     assert clear.sum() > 30
     np.testing.assert_array_equal(out["feasible"][clear], box["unsafe_mask"][clear, 0])
     assert out["first_step"] == box["first_step"]
+    np.testing.assert_array_equal(out["feasible"][out["margin"] < -1e-7], True)
 
 
 def _brute_force_feasible(A, b):
