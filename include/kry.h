@@ -228,6 +228,33 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out);
 kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out,
                                 double* z_out);
 
+/* kry_check_lp_safety -- the per-step LP of Section 2.1 for a polytopic
+ * initial set and a conjunction of output halfspaces, on the basis of
+ * kry_project_expm.  With M_s the generator columns of the basis at step s
+ * and f_s the sum of its fixed columns (center, forcing), step s is unsafe
+ * when some z with
+ *     zc_j - r_j <= z_j <= zc_j + r_j (the generators' box),  G z <= h,
+ *     U (M_s z + f_s) <= u
+ * exists.  Each step is decided by phase one of the simplex method (one
+ * artificial variable, Bland's rule) on rows scaled to a largest
+ * coefficient of 1: unsafe when the smallest uniform violation is <= 1e-6
+ * (the LP tolerance of Section 4.2; the decision errs towards unsafe by at
+ * most that much).
+ *  G: host, mI x ngen row-major; h: mI.  U: host, mU x o row-major; u: mU.
+ *     ngen <= 16 and ngen + mI + mU <= 64; all entries finite.
+ *  first_step: the first unsafe step, -1 when every step is safe.
+ *  status: 0, or KRY_ENUMERIC when a step up to first_step (every step when
+ *     safe) was left undecided (iteration cap, non-finite basis).
+ *  z_out (ngen), y_out (o): the counter-example of Section 2.2 at
+ *     first_step and its outputs (may be NULL).
+ *  step_flags: host array of steps + 1 ints (1 unsafe, 0 safe, -1
+ *     undecided) or NULL.
+ * The plan keeps a device buffer for the LP from the first call on.
+ * Needs kry_project_expm first.  Waits for the stream. */
+kry_status kry_check_lp_safety(kry_plan* plan, const double* G, const double* h, int32_t mI, const double* U,
+                               const double* u, int32_t mU, int64_t* first_step, int32_t* status, double* z_out,
+                               double* y_out, int32_t* step_flags);
+
 /* kry_footprint -- device workspace bytes a plan with these sizes needs
  * (the Krylov vectors, per-block partial sums, H, P and the basis; Section 3.5
  * gives the method's own memory model, this adds the GPU's staging).

@@ -70,7 +70,7 @@ Profiler& prof() {
 
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
-    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl";
+    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp";
 
 // Runs `launch` bracketed by events when profiling is on.
 template <class F>
@@ -422,6 +422,9 @@ struct kry_plan {
     std::vector<int32_t> job_role, job_run, out_col;
     int32_t* job_run_dev = nullptr;
     int32_t* out_col_dev = nullptr;
+    // per-step LP: inputs, per-step records and verdict (allocated on first use)
+    char* lp_mem = nullptr;
+    std::vector<double> lp_host;
     int lpr = 1;
     int32_t method = KRY_LANCZOS;
     bool projected = false;
@@ -1270,6 +1273,86 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
     return KRY_OK;
 }
 
+kry_status kry_check_lp_safety(kry_plan* plan, const double* G, const double* h, int32_t mI, const double* U,
+                               const double* u, int32_t mU, int64_t* first_step, int32_t* status, double* z_out,
+                               double* y_out, int32_t* step_flags) {
+    if (!plan || !first_step || !status) return fail(KRY_EINVAL, "plan, first_step and status must be non-NULL");
+    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+    const int32_t d = plan->ngen, o = plan->o_out;
+    if (d > kLpMaxD) return fail(KRY_ENOTSUP, "the per-step LP holds at most 16 generators");
+    if (mI < 0 || mU < 0 || d + mI + mU > kLpMaxRows)
+        return fail(KRY_EINVAL, "need mI, mU >= 0 and generators + mI + mU <= 64 rows");
+    if ((mI > 0 && (!G || !h)) || (mU > 0 && (!U || !u))) return fail(KRY_EINVAL, "G, h, U, u must be non-NULL");
+    auto finite = [](const double* a, int64_t cnt) {
+        for (int64_t i = 0; i < cnt; ++i)
+            if (!std::isfinite(a[i])) return false;
+        return true;
+    };
+    if (!finite(G, (int64_t)mI * d) || !finite(h, mI) || !finite(U, (int64_t)mU * o) || !finite(u, mU))
+        return fail(KRY_EINVAL, "LP constraints must be finite");
+    hipStream_t s = plan->stream;
+    const int64_t nin = 2 * kLpMaxD + (int64_t)kLpMaxRows * kLpMaxD + kLpMaxRows + (int64_t)kLpMaxRows * kMaxO +
+                        kLpMaxRows;
+    const int64_t nrec = (plan->steps + 1) * kLpRec;
+    const int64_t nver = 2 + kLpMaxD + kMaxO;
+    if (!plan->lp_mem) {
+        void* p = nullptr;
+        if (hipMalloc(&p, (size_t)(nin + nrec + nver) * sizeof(double)) != hipSuccess)
+            return fail(KRY_ENOMEM, "LP buffers: hipMalloc failed");
+        plan->lp_mem = static_cast<char*>(p);
+    }
+    double* dev = reinterpret_cast<double*>(plan->lp_mem);
+    // inputs: zlo, zhi, G, h, U, u
+    std::vector<double>& H = plan->lp_host;
+    H.assign((size_t)nin, 0.0);
+    for (int32_t j = 0; j < d; ++j) {
+        H[j] = plan->zc[j] - plan->radius[j];
+        H[kLpMaxD + j] = plan->zc[j] + plan->radius[j];
+    }
+    double* hG = H.data() + 2 * kLpMaxD;
+    double* hh = hG + (int64_t)kLpMaxRows * kLpMaxD;
+    double* hU = hh + kLpMaxRows;
+    double* hu = hU + (int64_t)kLpMaxRows * kMaxO;
+    if (mI > 0) { std::copy(G, G + (int64_t)mI * d, hG); std::copy(h, h + mI, hh); }
+    if (mU > 0) { std::copy(U, U + (int64_t)mU * o, hU); std::copy(u, u + mU, hu); }
+    KRY_HIP(hipMemcpyAsync(dev, H.data(), (size_t)nin * sizeof(double), hipMemcpyHostToDevice, s));
+    LpArgs L{};
+    L.basis = plan->basis();
+    L.o = o;
+    L.ncols = plan->ncols;
+    L.d = d;
+    L.mI = mI;
+    L.mU = mU;
+    L.steps = plan->steps;
+    L.zlo = dev;
+    L.zhi = dev + kLpMaxD;
+    L.G = dev + (hG - H.data());
+    L.h = dev + (hh - H.data());
+    L.U = dev + (hU - H.data());
+    L.u = dev + (hu - H.data());
+    L.tol = 1e-6;      // the LP tolerance of Section 4.2, on rows scaled to a largest coefficient of 1
+    L.max_pivots = 20 * (d + mI + mU + 2) + 100;
+    L.rec = dev + nin;
+    L.verdict = dev + nin + nrec;
+    hipError_t e = timed("lp", s, [&] { return launch_lp(L, s); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("lp: ") + hipGetErrorString(e));
+    double v[2 + kLpMaxD + kMaxO];
+    KRY_HIP(hipMemcpyAsync(v, L.verdict, sizeof(v), hipMemcpyDeviceToHost, s));
+    std::vector<double> rec;
+    if (step_flags) {
+        rec.resize((size_t)nrec);
+        KRY_HIP(hipMemcpyAsync(rec.data(), L.rec, (size_t)nrec * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    KRY_HIP(hipStreamSynchronize(s));
+    *first_step = (int64_t)v[0];
+    *status = (int32_t)v[1];
+    if (z_out) std::copy(v + 2, v + 2 + d, z_out);
+    if (y_out) std::copy(v + 2 + kLpMaxD, v + 2 + kLpMaxD + o, y_out);
+    if (step_flags)
+        for (int64_t st = 0; st <= plan->steps; ++st) step_flags[st] = (int32_t)rec[(size_t)st * kLpRec];
+    return KRY_OK;
+}
+
 kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out) {
     if (!plan) return fail(KRY_EINVAL, "plan is NULL");
     if (nruns) *nruns = plan->nruns;
@@ -1481,6 +1564,10 @@ void kry_plan_destroy(kry_plan* plan) {
     if (!plan) return;
     if (plan->flag_ev || (plan->owns_ws && plan->ws)) (void)hipStreamSynchronize(plan->stream);
     if (plan->owns_ws && plan->ws) (void)hipFree(plan->ws);
+    if (plan->lp_mem) {
+        (void)hipStreamSynchronize(plan->stream);
+        (void)hipFree(plan->lp_mem);
+    }
     if (plan->flag_ev) (void)hipEventDestroy(plan->flag_ev);
     if (plan->hflags) (void)hipHostFree(plan->hflags);
     delete plan;

@@ -275,4 +275,26 @@ hipError_t launch_arn_reduce(int P, const ArnArgs& A, const BatchArgs& B, int j,
 hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
                              const BatchArgs& B, int j, int last, hipStream_t s);
 
+// ---- per-step safety LP (kry_lp.hip) -----------------------------------------
+constexpr int kLpMaxD = 16;      // generator coefficients (LP variables)
+constexpr int kLpMaxRows = 64;   // box rows + G rows + U rows
+constexpr int kLpRec = 2 + kLpMaxD;   // per step: flag, t*, z
+struct LpArgs {
+    const double* basis;     // [(steps+1)][o][ncols], generator columns first
+    int32_t o, ncols, d;     // d = generators (the first d columns)
+    int32_t mI, mU;
+    int64_t steps;
+    const double* zlo;       // [d] box lower ends zc - r
+    const double* zhi;       // [d] box upper ends zc + r
+    const double* G;         // [mI][d]
+    const double* h;         // [mI]
+    const double* U;         // [mU][o]
+    const double* u;         // [mU]
+    double tol;              // feasible when the phase-one optimum t* <= tol
+    int32_t max_pivots;
+    double* rec;             // [(steps+1)][kLpRec]: flag (1 feasible, 0 not, -1 undecided), t*, z
+    double* verdict;         // [2 + kLpMaxD + kMaxO]: first step, status, z, y
+};
+hipError_t launch_lp(const LpArgs& L, hipStream_t s);
+
 }  // namespace kry

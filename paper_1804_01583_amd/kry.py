@@ -75,6 +75,8 @@ def _load():
                                                ct.POINTER(KrySegs), ct.POINTER(KrySegs), ct.c_int32, ct.c_int32,
                                                ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.POINTER(P)]
     lib.kry_project_expm.argtypes = [P, P]
+    lib.kry_check_lp_safety.argtypes = [P, P, P, ct.c_int32, P, P, ct.c_int32, ct.POINTER(ct.c_int64),
+                                        ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_check_box_safety.argtypes = [P, ct.POINTER(KryInterval), ct.POINTER(KryVerdict), P]
     lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
                                   ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
@@ -95,7 +97,7 @@ def _load():
     lib.kry_profile_enable.argtypes = [ct.c_int32]
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
-    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
@@ -105,7 +107,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_box_safety", "kry_footprint",
+EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
@@ -165,6 +167,23 @@ def kry_check_box_safety(plan: int, unsafe: np.ndarray, ngen: int):
     z = np.zeros(max(ngen, 1))
     _check(lib.kry_check_box_safety(plan, U, ct.byref(v), z.ctypes.data))
     return v, z[:ngen]
+
+
+def kry_check_lp_safety(plan: int, G, h, U, u, ngen: int, o: int, steps: int, want_flags=False):
+    """Per-step LP; returns (first_step, status, z, y, flags or None)."""
+    G = np.ascontiguousarray(np.asarray(G, np.float64).reshape(-1, ngen) if ngen else np.zeros((len(h), 0)))
+    h = np.ascontiguousarray(h, np.float64)
+    U = np.ascontiguousarray(np.asarray(U, np.float64).reshape(-1, o))
+    u = np.ascontiguousarray(u, np.float64)
+    first = ct.c_int64()
+    status = ct.c_int32()
+    z = np.zeros(max(ngen, 1))
+    y = np.zeros(max(o, 1))
+    flags = np.zeros(steps + 1, np.int32) if want_flags else None
+    _check(lib.kry_check_lp_safety(plan, G.ctypes.data, h.ctypes.data, h.size, U.ctypes.data, u.ctypes.data, u.size,
+                                   ct.byref(first), ct.byref(status), z.ctypes.data, y.ctypes.data,
+                                   flags.ctypes.data if want_flags else None))
+    return first.value, status.value, z[:ngen], y[:o], flags
 
 
 def kry_footprint(system: KrySystem, nruns: int, o: int, k: int, steps: int, nseg_total: int,
@@ -425,6 +444,12 @@ class Plan:
         v, z = kry_check_box_safety(self.handle, np.asarray(unsafe, np.float64), self.ngen)
         return {"first_step": int(v.first_step), "row": int(v.row), "status": int(v.status), "y": v.y,
                 "lo": v.lo, "hi": v.hi, "z": z}
+
+    def check_lp(self, G, h, U, u, flags=False):
+        """The per-step LP (kry_check_lp_safety): initial set = the generator
+        box and G z <= h, unsafe set U y <= u.  Needs project_expm first."""
+        first, status, z, y, fl = kry_check_lp_safety(self.handle, G, h, U, u, self.ngen, self.o, self.steps, flags)
+        return {"first_step": first, "status": status, "z": z, "y": y, "flags": fl}
 
     def krylov(self, run: int):
         return kry_plan_krylov(self.handle, run, self.k, self.o)

@@ -185,3 +185,10 @@ def test_transposed_plan_rejects_bad_arguments(bad):
     with pytest.raises(kry.KryError) as ei:
         kry.kry_plan_create_transposed(s, kg, center, kc, k, 0.1, 10, kry.KRY_FP64, method, None)
     assert ei.value.status == expected, kry.lib.kry_last_error()
+
+
+def test_lp_check_rejects_null_plan():
+    from paper_1804_01583_amd import kry
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_check_lp_safety(None, np.zeros((0, 1)), np.zeros(0), np.ones((1, 1)), np.ones(1), 1, 1, 3)
+    assert ei.value.status == kry.KRY_EINVAL
