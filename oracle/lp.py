@@ -17,14 +17,16 @@ substituted through the basis); a feasible z is the counter-example of
 Section 2.2.  The LP solver is SciPy's ``linprog`` (a library primitive).
 
 Tolerance (the paper's LP solver works to 1e-6, Section 4.2): the decision
-is made on the constraint rows scaled so that each row's largest
-coefficient in z is 1; step s is unsafe when some z in the box violates no
+is made on the G and U rows a z <= b each divided by max(|a|_max, |b|), the
+row's own magnitude; step s is unsafe when some z in the box violates no
 scaled row by more than LP_TOL = 1e-6.  Scaling a row by a positive number
 leaves the set unchanged, and it makes the tolerance independent of how U
 and G are scaled; a solver's absolute tolerance on unscaled rows is not
 (an output row whose basis entries are 1e-7 would be judged at the
-solver's 1e-7 with a 100 % relative error).  The decision errs towards
-"unsafe" by at most LP_TOL.
+solver's 1e-7 with a 100 % relative error).  A row whose coefficients
+vanish against its right-hand side then reads 0 <= sign(b); a row of
+magnitude below 1e-280 in both is 0 <= 0 and is dropped.  The decision
+errs towards "unsafe" by at most LP_TOL.
 """
 from __future__ import annotations
 
@@ -63,20 +65,19 @@ def lp_feasible(M, f, zlo, zhi, G, h, U, u):
 
 def lp_margin(M, f, zlo, zhi, G, h, U, u, with_point=False):
     """The smallest t with {z in box : a_i z - t <= b_i for every G and U
-    row, each row scaled so its largest coefficient in z is 1}: negative
-    when the set has an interior point, positive when it is empty.  Rows
-    without a coefficient in z count with their own sign (-b_i).  With
-    ``with_point`` also returns the minimising z."""
+    row, each divided by max(|a_i|_max, |b_i|)}: negative when the set has
+    an interior point, positive when it is empty.  With ``with_point`` also
+    returns the minimising z."""
     d = M.shape[1]
     A = np.vstack([G.reshape(-1, d), U @ M])
     b = np.concatenate([h, u - U @ f])
-    zero = np.abs(A).max(axis=1) == 0.0 if (A.size and d) else np.ones(A.shape[0], bool)
-    t_zero = float(np.max(-b[zero])) if zero.any() else -np.inf
-    A, b = A[~zero], b[~zero]
+    amax = np.abs(A).max(axis=1) if (A.size and d) else np.zeros(A.shape[0])
+    s = np.maximum(amax, np.abs(b))
+    keep = s >= 1e-280
+    A, b, s = A[keep], b[keep], s[keep]
     if A.shape[0] == 0:
-        # any box point is as good as any other; the centre of the box
-        return (t_zero, 0.5 * (np.asarray(zlo) + np.asarray(zhi))) if with_point else t_zero
-    s = np.abs(A).max(axis=1)
+        # no constraint: every box point qualifies; the centre of the box
+        return (-np.inf, 0.5 * (np.asarray(zlo) + np.asarray(zhi))) if with_point else -np.inf
     A, b = A / s[:, None], b / s
     # variables (z, t): minimise t
     c = np.zeros(d + 1); c[d] = 1.0
@@ -84,7 +85,7 @@ def lp_margin(M, f, zlo, zhi, G, h, U, u, with_point=False):
     res = linprog(c, A_ub=Aub, b_ub=b, bounds=list(zip(zlo, zhi)) + [(None, None)], method="highs")
     if res.status != 0:
         raise RuntimeError(f"linprog: {res.message}")
-    t = max(float(res.x[d]), t_zero)
+    t = float(res.x[d])
     return (t, np.asarray(res.x[:d], np.float64)) if with_point else t
 
 
