@@ -20,6 +20,10 @@ Prints one JSON line.  Options:
   --route R       forward (one run per column of E) or transposed (one run of A^T
                   per output row, Section 4.1); default transposed for
                   heat3d_many_inputs, forward otherwise
+  --check C       box (the range check of each output row's interval, default) or
+                  lp (the per-step LP of Section 2.1: the generator box cut by
+                  sum_j (z_j - zc_j) / r_j <= d / 2, unsafe when every output row
+                  is in its interval at once)
   --precision P   fp64 (default) or fp32 (FP32-basis mode; the FP64 path is then
                   timed too, for the ratio to plain FP64)
   --method M      auto (Lanczos / Arnoldi by symmetry) or block (block Arnoldi,
@@ -74,6 +78,7 @@ def main():
                     help="heat3d_csr is the benchmark line; the others are measured the same way")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--route", default=None, choices=["forward", "transposed"])
+    ap.add_argument("--check", default="box", choices=["box", "lp"])
     ap.add_argument("--method", default=None, choices=["auto", "block", "plain"])
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
@@ -136,7 +141,7 @@ def main():
             dsys.prepare(prec)
         torch.cuda.synchronize()
     m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
-                args.error_target, not args.no_kernel_events, transposed)
+                args.error_target, not args.no_kernel_events, transposed, args.check)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
@@ -157,7 +162,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and p.n <= 2_000_000:
         log("timing the CPU oracle on the same workload (one whole verification)")
-        cpu = cpu_baseline(p, transposed)
+        cpu = cpu_baseline(p, transposed, args.check)
 
     out = {
         "metric": "Krylov step HBM GB/s (% peak); verified time-steps/s vs plain FP64; p99 query latency",
@@ -175,6 +180,7 @@ def main():
         "config": {"workload": describe(p, nruns, args.precision, method_name), "n": n, "nnz": nnz, "k": p.k,
                    "time_steps": p.steps, "basis_columns": nruns, "krylov_runs": m["krylov_runs"],
                    "route": "transposed" if transposed else "forward", "precision": args.precision,
+                   "check": args.check,
                    "method": {"block": "block_arnoldi", "plain": "lanczos_plain"}.get(
                        method_name, "lanczos" if p.symmetric else "arnoldi"),
                    "error_target": args.error_target or None,
@@ -231,8 +237,26 @@ def serve_bench(args):
     print(json.dumps(out))
 
 
+def lp_sets(p):
+    """The LP bench's sets: the generator box cut by sum_j (z_j - zc_j) / r_j
+    <= d / 2 (a polytope), and the conjunction of every output row's
+    unsafe interval (its finite ends as halfspaces)."""
+    import numpy as np
+    zc = np.array([g.zc for g in p.gens]); r = np.array([g.radius for g in p.gens])
+    d = len(p.gens)
+    live = r > 0
+    G = np.zeros((1, d)); G[0, live] = 1.0 / r[live]
+    h = np.array([float(G[0] @ zc) + d / 2.0])
+    U, u = [], []
+    for q, (lo, hi) in enumerate(p.unsafe):
+        e = np.zeros(p.o); e[q] = 1.0
+        if np.isfinite(hi): U.append(e); u.append(hi)
+        if np.isfinite(lo): U.append(-e); u.append(-lo)
+    return G, h, np.array(U).reshape(-1, p.o), np.array(u)
+
+
 def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0, kernel_events=True,
-            transposed=False):
+            transposed=False, check="box"):
     """Times `steps` whole verifications (after `warmup`), then the same with
     per-kernel HIP events; returns the throughput and per-kernel figures."""
     stream = torch.cuda.current_stream()
@@ -249,7 +273,11 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         if error_target > 0.0:
             plan.set_error_target(error_target)
         plan.project_expm(None)
-        v = plan.check(p.unsafe)
+        if check == "lp":
+            v = plan.check_lp(*lp_sets(p))
+            v["row"] = -1
+        else:
+            v = plan.check(p.unsafe)
         nr = plan.nruns
         if error_target > 0.0 and not used:
             used["k_used"] = [plan.error(r)[0] for r in range(nr)]
@@ -411,16 +439,24 @@ def counter_traffic(path):
         return None
 
 
-def cpu_baseline(p, transposed=False):
+def cpu_baseline(p, transposed=False, check="box"):
     """The oracle as it stands, on this host's CPU, one thread, over one whole
-    verification of the same workload (by the same route)."""
+    verification of the same workload (by the same route and check)."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:   # pragma: no cover
         threadpool_limits = None
     import oracle
+    import oracle.lp
     import oracle.transpose
-    verify = oracle.transpose.verify_transposed if transposed else oracle.verify
+    route = oracle.transpose.verify_transposed if transposed else oracle.verify
+
+    def verify(p):
+        res = route(p)
+        if check == "lp":
+            zc = [g.zc for g in p.gens]; r = [g.radius for g in p.gens]
+            res["lp"] = oracle.lp.lp_check(res["basis"], res["roles"], zc, r, *lp_sets(p))
+        return res
     t0 = time.perf_counter()
     if threadpool_limits is not None:
         with threadpool_limits(limits=1):

@@ -4,13 +4,16 @@
 // At step s the reachable outputs are y = M_s z + f_s (M_s: the generator
 // columns of the basis, f_s: the sum of its fixed columns).  The step is
 // unsafe when some z with zlo <= z <= zhi, G z <= h also has U y <= u.  In
-// w = z - zlo >= 0 the rows are
-//     w_j <= zhi_j - zlo_j,  G w <= h - G zlo,  (U M_s) w <= u - U (M_s zlo + f_s),
-// each scaled so that its largest coefficient is 1.  Phase one with a single
-// artificial variable t (A w - t 1 <= b, minimise t) decides feasibility:
-// after t enters at the row of the most negative b every right-hand side is
-// non-negative, and the simplex with Bland's rule (smallest entering index,
-// ratio ties to the smallest basic index) cannot cycle.  The step is unsafe
+// w = z - zlo >= 0 the rows are the bounds w_j <= zhi_j - zlo_j and
+//     G w <= h - G zlo,  (U M_s) w <= u - U (M_s zlo + f_s),
+// the G and U rows divided by their magnitude max(|a|_max, |b|) taken in z
+// (b = h, or u - U f_s), so that a row whose coefficients vanish against
+// its right-hand side reads 0 <= sign(b), and a row below 1e-280 in both is
+// dropped.  Phase one with a single artificial variable t in the G and U
+// rows (a w - t <= b, minimise t) decides feasibility: after t enters at the
+// row of the most negative b every right-hand side is non-negative, and the
+// simplex with Bland's rule (smallest entering index, ratio ties to the
+// smallest basic index) cannot cycle.  The step is unsafe
 // when the optimum t* <= tol (the LP tolerance, on the scaled rows); the
 // basic w then gives the counter-example, which violates no scaled row by
 // more than t*.
@@ -59,51 +62,53 @@ __global__ __launch_bounds__(kLpThreads) void k_lp_steps(LpArgs L) {
     }
     __syncthreads();
 
-    // constraint rows (lane i builds row i), scaled to a largest coefficient of 1
+    // constraint rows (lane i builds row i); G and U rows scaled by their magnitude
     bool bad = false;
     if (lane < m) {
         double a[kLpMaxD];
         double b;
         const int i = lane;
+        double bz;                           // right-hand side in z
         if (i < d) {
 #pragma unroll
             for (int j = 0; j < kLpMaxD; ++j) a[j] = j == i ? 1.0 : 0.0;
-            b = L.zhi[i] - L.zlo[i];
+            bz = L.zhi[i];
         } else if (i < d + L.mI) {
             const double* g = L.G + (int64_t)(i - d) * d;
-            b = L.h[i - d];
+            bz = L.h[i - d];
 #pragma unroll
-            for (int j = 0; j < kLpMaxD; ++j) {
-                a[j] = j < d ? g[j] : 0.0;
-                if (j < d) b -= a[j] * L.zlo[j];
-            }
+            for (int j = 0; j < kLpMaxD; ++j) a[j] = j < d ? g[j] : 0.0;
         } else {
             const double* ur = L.U + (int64_t)(i - d - L.mI) * o;
-            b = L.u[i - d - L.mI];
+            bz = L.u[i - d - L.mI];
 #pragma unroll
             for (int j = 0; j < kLpMaxD; ++j) a[j] = 0.0;
             for (int q = 0; q < o; ++q) {
-                double yq = sf[q];
+                bz -= ur[q] * sf[q];
 #pragma unroll
                 for (int j = 0; j < kLpMaxD; ++j)
-                    if (j < d) {
-                        a[j] = fma(ur[q], sM[q * d + j], a[j]);
-                        yq = fma(sM[q * d + j], L.zlo[j], yq);
-                    }
-                b -= ur[q] * yq;
+                    if (j < d) a[j] = fma(ur[q], sM[q * d + j], a[j]);
             }
         }
-        double nrm = 0.0;
+        // in w = z - zlo
+        b = bz;
+#pragma unroll
+        for (int j = 0; j < kLpMaxD; ++j)
+            if (j < d) b -= a[j] * L.zlo[j];
+        double nrm = fabs(bz);
 #pragma unroll
         for (int j = 0; j < kLpMaxD; ++j) nrm = fmax(nrm, fabs(a[j]));
         bad = !std::isfinite(nrm) || !std::isfinite(b);
-        const double sc = nrm > 0.0 ? 1.0 / nrm : 1.0;
+        const bool bound = i < d;
+        const bool drop = !bound && nrm < 1e-280;
+        const double sc = bound || drop ? 1.0 : 1.0 / nrm;
         double* row = T + i * kLpLd;
         for (int c = 0; c < C; ++c) row[c] = 0.0;
-        for (int j = 0; j < d; ++j) row[j] = a[j] * sc;
-        row[tcol] = -1.0;
+        if (!drop)
+            for (int j = 0; j < d; ++j) row[j] = a[j] * sc;
+        row[tcol] = bound ? 0.0 : -1.0;       // the box bounds are not relaxed
         row[d + 1 + i] = 1.0;
-        row[rhs] = b * sc;
+        row[rhs] = drop ? 1.0 : (bound ? L.zhi[i] - L.zlo[i] : b * sc);
         bas[i] = d + 1 + i;
     }
     // reduced costs of min t with the slack basis
