@@ -451,7 +451,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                                                   E* __restrict__ w, BatchArgs B, int j) {
     if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int NV = P * (1 + O);
-    constexpr int RC = 4;
+    // rows per thread and chunk: two chunks in flight at once (measured: one
+    // row per thread for one or four and more runs, two for two runs)
+    constexpr int RC = P == 2 ? 2 : 1;
     __shared__ double s_lds[(kBlock / 64) * NV];
     __shared__ double s_alpha[P];
     __shared__ SegStage<O> st;
@@ -460,18 +462,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
     const int64_t span = (int64_t)kBlock * RC;
     const int nch = max((int)((B.rows_per_block + span - 1) / span), 1);
-    // rows of chunk ch; dead rows read row 0 and drop it
-    double uv[RC][P], wv[RC][P];
-    int64_t rr[RC];
-    auto load_chunk = [&](int ch) {
+    // rows of chunk ch in one of two register buffers (the next chunk's loads
+    // are in flight while a chunk is processed); dead rows read row 0 and drop it
+    double uv[RC][P], wv[RC][P], uv2[RC][P], wv2[RC][P];
+    int64_t rr[RC], rr2[RC];
+    auto load_into = [&](int ch, double (&u_)[RC][P], double (&w_)[RC][P], int64_t (&r_)[RC]) {
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
-            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
-            const int64_t rl = rr[i] < r1 ? rr[i] : 0;
-            load_row<E, P>(ucur, rl, uv[i]);
-            load_row<E, P>(w, rl, wv[i]);
+            r_[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            const int64_t rl = r_[i] < r1 ? r_[i] : 0;
+            load_row<E, P>(ucur, rl, u_[i]);
+            load_row<E, P>(w, rl, w_[i]);
         }
     };
+    auto load_chunk = [&](int ch) { load_into(ch, uv, wv, rr); };
     // Loads are issued in the order they are waited for (a wait covers every
     // load issued before it): the alpha partials, sigma_j and the output
     // sets' segment ranges, then the first chunk's rows, which stay in
@@ -517,16 +521,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
             if (!isfinite(s_alpha[threadIdx.x])) sc[B.L.misc + MISC_NONFINITE] = 1.0;
         }
     }
-    for (int ch = 0; ch < nch; ++ch) {
-        if (ch > 0) load_chunk(ch);
+    auto process = [&](const double (&u_)[RC][P], const double (&w_)[RC][P], const int64_t (&r_)[RC]) {
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
-            if (rr[i] < r1) {
-                const int64_t r = rr[i];
+            if (r_[i] < r1) {
+                const int64_t r = r_[i];
                 double val[P];
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    val[p] = (double)(E)fma(-coef[p], uv[i][p], wv[i][p]);
+                    val[p] = (double)(E)fma(-coef[p], u_[i][p], w_[i][p]);
                     acc[p] = fma(val[p], val[p], acc[p]);
                 }
                 store_row<E, P>(w, r, val);
@@ -541,6 +544,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                     }
                 }
             }
+        }
+    };
+    for (int ch = 0; ch < nch; ch += 2) {
+        if (ch + 1 < nch) load_into(ch + 1, uv2, wv2, rr2);
+        process(uv, wv, rr);
+        if (ch + 1 < nch) {
+            if (ch + 2 < nch) load_into(ch + 2, uv, wv, rr);
+            process(uv2, wv2, rr2);
         }
     }
     store_partials<NV>(acc, stage_part(B, j), B.nblocks, s_lds, B.xcd_map);
