@@ -298,11 +298,29 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
     if (m > 0) {
         const double* z = A.Z + (((int64_t)run * A.B + (s % A.B)) * kMaxO) * kMaxK;
         const double* a = A.anch + ((int64_t)run * A.nanch + (s / A.B)) * kMaxK;
-        for (int i = 0; i < m; ++i) {
-            const double ai = a[i];
+        // eight entries at a time, every load of a chunk issued before the
+        // first product (a loop of single loads waits for each in turn);
+        // entries i < m + 7 <= kMaxK stay inside the row, and those past m,
+        // never written, are replaced by zero
+        constexpr int kC = 8;
+        static_assert(kMaxK % kC == 0, "chunks must tile a row");
+        for (int i0 = 0; i0 < m; i0 += kC) {
+            double av[kC], zv[kMaxO][kC];
+#pragma unroll
+            for (int t = 0; t < kC; ++t) av[t] = a[i0 + t];
 #pragma unroll
             for (int q = 0; q < kMaxO; ++q)
-                if (q < A.o) y[q] = fma(z[q * kMaxK + i], ai, y[q]);
+                if (q < A.o) {
+#pragma unroll
+                    for (int t = 0; t < kC; ++t) zv[q][t] = z[q * kMaxK + i0 + t];
+                }
+#pragma unroll
+            for (int t = 0; t < kC; ++t) {
+                const bool in = i0 + t < m;
+#pragma unroll
+                for (int q = 0; q < kMaxO; ++q)
+                    if (q < A.o && in) y[q] = fma(zv[q][t], av[t], y[q]);
+            }
         }
         const double sc = A.scale[run];
 #pragma unroll

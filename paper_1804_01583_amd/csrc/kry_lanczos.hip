@@ -102,23 +102,40 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += kBlock) {
-        double val[P];
+    // rows r0 + threadIdx.x, + kBlock, ... in chunks of RC per thread; a
+    // chunk's dense start entries are all requested before the first is used
+    constexpr int RC = 4;
+    const int64_t span = (int64_t)kBlock * RC;
+    for (int64_t c0 = r0; c0 < r1; c0 += span) {
+        double dv[RC][P];
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            if (src.dense[p] != nullptr) val[p] = src.dense[p][r];
-            else if (src.set[p] >= 0) val[p] = cur[p].weight(st, p, T, r);
-            else val[p] = 0.0;
-            val[p] = (double)(E)val[p];          // the norm and projection of the stored vector
-            acc[p] = fma(val[p], val[p], acc[p]);
+        for (int i = 0; i < RC; ++i) {
+            const int64_t r = c0 + (int64_t)i * kBlock + threadIdx.x;
+            const int64_t rl = r < r1 ? r : r0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) dv[i][p] = src.dense[p] != nullptr ? src.dense[p][rl] : 0.0;
         }
-        store_row<E, P>(u, r, val);
 #pragma unroll
-        for (int q = 0; q < O; ++q) {
-            const double cw = cur[P + q].weight(st, P + q, T, r);
-            if (cw != 0.0) {
+        for (int i = 0; i < RC; ++i) {
+            const int64_t r = c0 + (int64_t)i * kBlock + threadIdx.x;
+            if (r >= r1) continue;
+            double val[P];
 #pragma unroll
-                for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+            for (int p = 0; p < P; ++p) {
+                if (src.dense[p] != nullptr) val[p] = dv[i][p];
+                else if (src.set[p] >= 0) val[p] = cur[p].weight(st, p, T, r);
+                else val[p] = 0.0;
+                val[p] = (double)(E)val[p];          // the norm and projection of the stored vector
+                acc[p] = fma(val[p], val[p], acc[p]);
+            }
+            store_row<E, P>(u, r, val);
+#pragma unroll
+            for (int q = 0; q < O; ++q) {
+                const double cw = cur[P + q].weight(st, P + q, T, r);
+                if (cw != 0.0) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(cw, val[p], acc[P + q * P + p]);
+                }
             }
         }
     }
