@@ -230,7 +230,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
         Y.scap = sell_nnz + sell_nnz / 4 + (int64_t)kSlice * 8;
         Y.swidth = take((size_t)ns * sizeof(int32_t));
         Y.soff = take((size_t)(ns + 1) * sizeof(int64_t));
-        Y.stiles = take((size_t)sell_scan_tiles(n) * sizeof(int64_t));
+        Y.stiles = take((size_t)(sell_scan_tiles(n) + 1) * sizeof(int64_t));
         Y.scol = take((size_t)Y.scap * sizeof(int32_t));
         Y.sval = take((size_t)Y.scap * (precision == KRY_FP32_BASIS ? sizeof(float) : sizeof(double)));
     }
@@ -824,21 +824,26 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
                                       plan->at<int64_t>(Y.stiles), plan->stream);
         });
         if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell layout: ") + hipGetErrorString(e)));
-        int64_t total = 0;
+        int64_t total = 0, nwide = 0;
         if (hipMemcpyAsync(&total, plan->at<int64_t>(Y.soff) + sell_slices(n), sizeof(total), hipMemcpyDeviceToHost,
                            plan->stream) != hipSuccess ||
+            hipMemcpyAsync(&nwide, plan->at<int64_t>(Y.stiles) + sell_scan_tiles(n), sizeof(nwide),
+                           hipMemcpyDeviceToHost, plan->stream) != hipSuccess ||
             hipStreamSynchronize(plan->stream) != hipSuccess)
             return cleanup(fail(KRY_EDEVICE, "sell layout readback failed"));
         if (total <= Y.scap) {
+            const bool narrow = nwide == 0 && env_int("KRY_SELL_NARROW", 1) != 0;
             e = timed("sell_build", plan->stream, [&] {
-                return launch_sell_fill(plan->f32, A, n, plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
-                                        plan->at<int32_t>(Y.scol), plan->ws + Y.sval, plan->stream);
+                return launch_sell_fill(plan->f32, narrow, A, n, plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
+                                        plan->ws + Y.scol, plan->ws + Y.sval, plan->stream);
             });
             if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell fill: ") + hipGetErrorString(e)));
             plan->use_sell = true;
-            plan->sell = SellArgs{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth), plan->at<int32_t>(Y.scol),
+            plan->sell = SellArgs{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
+                                  narrow ? nullptr : plan->at<int32_t>(Y.scol),
                                   plan->f32 ? nullptr : plan->at<double>(Y.sval),
-                                  plan->f32 ? plan->at<float>(Y.sval) : nullptr};
+                                  plan->f32 ? plan->at<float>(Y.sval) : nullptr,
+                                  narrow ? plan->at<int16_t>(Y.scol) : nullptr, n};
         }
     }
     if (sys->prepared && method != KRY_BLOCK_ARNOLDI) {
@@ -1491,7 +1496,7 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
     // first allocation: layout arrays, row-sum partials and the norm
     size_t off = 0;
     auto take = [&](size_t b) { const size_t o = off; off = align_up(off + b, 256); return o; };
-    const size_t o_width = take((size_t)ns * 4), o_off = take((size_t)(ns + 1) * 8), o_tiles = take((size_t)nt * 8);
+    const size_t o_width = take((size_t)ns * 4), o_off = take((size_t)(ns + 1) * 8), o_tiles = take((size_t)(nt + 1) * 8);
     const size_t o_part = take((size_t)nb * 8), o_norm = take(8);
     const size_t head = off;
     char* tmp = nullptr;
@@ -1507,14 +1512,17 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
     if (e == hipSuccess)
         e = launch_row_abs_max(A, n, reinterpret_cast<double*>(tmp + o_part), nb, rpb,
                                reinterpret_cast<double*>(tmp + o_norm), s);
-    int64_t total = 0;
+    int64_t total = 0, nwide = 0;
     if (e == hipSuccess)
         e = hipMemcpyAsync(&total, reinterpret_cast<int64_t*>(tmp + o_off) + ns, sizeof(total), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&nwide, reinterpret_cast<int64_t*>(tmp + o_tiles) + nt, sizeof(nwide), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const bool narrow = nwide == 0 && env_int("KRY_SELL_NARROW", 1) != 0;
     if (e != hipSuccess) return bail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
     // second allocation: the entries, after the layout
     const size_t esz = precision == KRY_FP32_BASIS ? 4 : 8;
-    const size_t o_col = take((size_t)total * 4), o_val = take((size_t)total * esz);
+    const size_t o_col = take((size_t)total * (narrow ? 2 : 4)), o_val = take((size_t)total * esz);
     kry_matrix* M = new kry_matrix();
     M->bytes = off;
     if (hipMalloc((void**)&M->mem, M->bytes) != hipSuccess) {
@@ -1523,9 +1531,8 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
     }
     e = hipMemcpyAsync(M->mem, tmp, head, hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
-        e = launch_sell_fill(precision == KRY_FP32_BASIS, A, n, reinterpret_cast<int64_t*>(M->mem + o_off),
-                             reinterpret_cast<int32_t*>(M->mem + o_width), reinterpret_cast<int32_t*>(M->mem + o_col),
-                             M->mem + o_val, s);
+        e = launch_sell_fill(precision == KRY_FP32_BASIS, narrow, A, n, reinterpret_cast<int64_t*>(M->mem + o_off),
+                             reinterpret_cast<int32_t*>(M->mem + o_width), M->mem + o_col, M->mem + o_val, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(tmp);
     if (e != hipSuccess) {
@@ -1540,9 +1547,10 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
     M->vals = sys->vals;
     M->precision = precision;
     M->sell = SellArgs{reinterpret_cast<int64_t*>(M->mem + o_off), reinterpret_cast<int32_t*>(M->mem + o_width),
-                       reinterpret_cast<int32_t*>(M->mem + o_col),
+                       narrow ? nullptr : reinterpret_cast<int32_t*>(M->mem + o_col),
                        precision == KRY_FP32_BASIS ? nullptr : reinterpret_cast<double*>(M->mem + o_val),
-                       precision == KRY_FP32_BASIS ? reinterpret_cast<float*>(M->mem + o_val) : nullptr};
+                       precision == KRY_FP32_BASIS ? reinterpret_cast<float*>(M->mem + o_val) : nullptr,
+                       narrow ? reinterpret_cast<int16_t*>(M->mem + o_col) : nullptr, n};
     M->anorm_dev = reinterpret_cast<double*>(M->mem + o_norm);
     *out = M;
     return KRY_OK;

@@ -86,17 +86,22 @@ constexpr int kSlice = 64;
 struct SellArgs {
     const int64_t* off;      // [slices + 1] first entry of each slice
     const int32_t* width;    // [slices] entries per row in the slice
-    const int32_t* col;
+    const int32_t* col;      // column indices, or (col null)
     const double* val;       // FP64 values, or
     const float* val32;      // FP32 values (FP32-basis mode)
+    const int16_t* dcol;     // column - row of every entry, when all of them fit 16 bits
+    int64_t n;               // rows (delta mode clamps reconstructed columns to n - 1)
 };
 int64_t sell_slices(int64_t n);
+// scan tiles of the layout, plus one more int64 after them: the number of
+// slices with a column farther than 32767 from its row
 int64_t sell_scan_tiles(int64_t n);
 struct CsrArgs;
 hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64_t* off, int64_t* tiles,
                               hipStream_t s);
-hipError_t launch_sell_fill(bool f32, const CsrArgs& A, int64_t n, const int64_t* off, const int32_t* width,
-                            int32_t* col, void* val, hipStream_t s);
+// narrow: store column - row as int16 (col then points to int16 storage)
+hipError_t launch_sell_fill(bool f32, bool narrow, const CsrArgs& A, int64_t n, const int64_t* off,
+                            const int32_t* width, void* col, void* val, hipStream_t s);
 
 struct StencilArgs {
     int64_t nx, ny, nz;

@@ -10,8 +10,12 @@
 // in CSR order, as in k_spmv_csr; padding adds exact zeros for finite
 // vectors.
 //
-// The conversion runs once per plan: slice widths, an exclusive scan of the
-// slice sizes (tiles of kScanTile slices, then the tile totals), and a fill.
+// The conversion runs once per plan (or once per system when prepared):
+// slice widths, an exclusive scan of the slice sizes (tiles of kScanTile
+// slices, then the tile totals), and a fill.  When every column lies within
+// 32767 of its row (banded and stencil matrices), the fill stores column -
+// row as 16 bits instead of the 32-bit column, which saves 2 of the 12
+// bytes an FP64 entry streams per mat-vec.
 #include "kry_device.h"
 
 #include <cmath>
@@ -24,13 +28,24 @@ using namespace dev;
 
 constexpr int kScanTile = 4096;   // slices per scan workgroup (256 threads x 16)
 
-__global__ __launch_bounds__(256) void k_sell_width(const int64_t* __restrict__ rowptr, int64_t n, int64_t ns,
-                                                    int32_t* __restrict__ width) {
+__global__ __launch_bounds__(256) void k_sell_width(const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ colidx, int64_t n, int64_t ns,
+                                                    int32_t* __restrict__ width,
+                                                    unsigned long long* __restrict__ nwide) {
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < ns; s += (int64_t)gridDim.x * 256) {
         int64_t w = 0;
+        bool wide = false;
         const int64_t r0 = s * kSlice, r1 = min(n, r0 + kSlice);
-        for (int64_t r = r0; r < r1; ++r) w = max(w, rowptr[r + 1] - rowptr[r]);
+        for (int64_t r = r0; r < r1; ++r) {
+            const int64_t e0 = rowptr[r], e1 = rowptr[r + 1];
+            w = max(w, e1 - e0);
+            for (int64_t e = e0; e < e1; ++e) {
+                const int64_t d = (int64_t)colidx[e] - r;
+                wide = wide || d < -32768 || d > 32767;
+            }
+        }
         width[s] = (int32_t)w;
+        if (wide) atomicAdd(nwide, 1ull);
     }
 }
 
@@ -86,9 +101,9 @@ __global__ __launch_bounds__(256) void k_sell_scan_add(int64_t* __restrict__ off
     }
 }
 
-template <typename V>
+template <typename V, typename IT>
 __global__ __launch_bounds__(256) void k_sell_fill(CsrArgs A, int64_t n, int64_t ns, const int64_t* __restrict__ off,
-                                                   const int32_t* __restrict__ width, int32_t* __restrict__ col,
+                                                   const int32_t* __restrict__ width, IT* __restrict__ col,
                                                    V* __restrict__ val) {
     const int64_t rows = ns * kSlice;
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < rows; r += (int64_t)gridDim.x * 256) {
@@ -102,7 +117,10 @@ __global__ __launch_bounds__(256) void k_sell_fill(CsrArgs A, int64_t n, int64_t
         }
         for (int32_t k = 0; k < w; ++k) {
             const bool real = k < len;
-            col[base + (int64_t)k * kSlice] = real ? A.colidx[e0 + k] : (int32_t)(r < n ? r : 0);
+            if constexpr (sizeof(IT) == 2)   // column - row; padding points at the row itself
+                col[base + (int64_t)k * kSlice] = real ? (IT)((int64_t)A.colidx[e0 + k] - r) : (IT)0;
+            else
+                col[base + (int64_t)k * kSlice] = real ? A.colidx[e0 + k] : (int32_t)(r < n ? r : 0);
             val[base + (int64_t)k * kSlice] = real ? (V)A.vals[e0 + k] : (V)0;
         }
     }
@@ -113,7 +131,7 @@ __global__ __launch_bounds__(256) void k_sell_fill(CsrArgs A, int64_t n, int64_t
 // (sigma_j u_j) . w.  Rows in chunks of RC per thread; entries of a row in
 // groups of KU whose loads are issued together (slots past the slice width
 // re-read the last entry and add nothing).
-template <typename E, int P>
+template <typename E, int P, bool D>
 __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __restrict__ ucur,
                                                       const E* __restrict__ uprev, E* __restrict__ w, BatchArgs B,
                                                       int j) {
@@ -132,7 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
     // slice, rows past the block (or n) read slice 0 and are not stored.
     // Each chunk's are requested one chunk ahead (the first ones before the
     // norm partials), so no chunk starts with a round trip of its own.
-    int64_t off_nx[RC];
+    // (delta mode) the row whose entries a thread reads is 64 s + lane
+    int64_t off_nx[RC], srow_nx[RC];
     int32_t wd_nx[RC];
     auto slice_info = [&](int ch) {
 #pragma unroll
@@ -142,8 +161,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
             const int64_t s = rs / kSlice;
             off_nx[i] = A.off[s] + lane;
             wd_nx[i] = A.width[s];
+            srow_nx[i] = s * kSlice + lane;
         }
     };
+    const int64_t nlast = A.n - 1;
     slice_info(0);
     double pacc[P], sig_prev[P], anorm;
     load_stage_norms<P>(B, j, pacc, sig_prev, anorm);
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
     for (int p = 0; p < P; ++p) { sig[p] = 0.0; cprev[p] = 0.0; dot[p] = 0.0; }
     const bool prev = j > 1 && uprev != nullptr;
     for (int ch = 0; ch < nch; ++ch) {
-        int64_t rr[RC], off[RC];
+        int64_t rr[RC], off[RC], srow[RC];
         int32_t wd[RC];
         double acc[RC][P];
 #pragma unroll
@@ -160,6 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
             rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
             off[i] = off_nx[i];
             wd[i] = wd_nx[i];
+            srow[i] = srow_nx[i];
 #pragma unroll
             for (int p = 0; p < P; ++p) acc[i][p] = 0.0;
         }
@@ -173,7 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(SellArgs A, const E* __res
                 for (int u = 0; u < KU; ++u) {
                     const int k = kb + u < wd[i] ? kb + u : wd[i] - 1;
                     const int64_t idx = off[i] + (int64_t)k * kSlice;
-                    c[u] = A.col[idx];
+                    if constexpr (D) {
+                        // rows past n in the last slice hold delta 0: clamp to a real row
+                        const int64_t cc = srow[i] + (int64_t)A.dcol[idx];
+                        c[u] = (int32_t)min(max(cc, (int64_t)0), nlast);
+                    } else {
+                        c[u] = A.col[idx];
+                    }
                     const double v = sizeof(E) == 4 ? (double)A.val32[idx] : A.val[idx];
                     a[u] = kb + u < wd[i] ? v : 0.0;
                 }
@@ -223,8 +251,12 @@ int64_t sell_scan_tiles(int64_t n) { return (sell_slices(n) + kScanTile - 1) / k
 hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64_t* off, int64_t* tiles,
                               hipStream_t s) {
     const int64_t ns = sell_slices(n), nt = sell_scan_tiles(n);
-    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(ns)), dim3(256), 0, s, A.rowptr, n, ns, width);
-    hipError_t e = hipGetLastError();
+    // the count of wide slices sits after the nt tile totals
+    hipError_t e = launch_fill(reinterpret_cast<double*>(tiles + nt), 1, 0.0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(ns)), dim3(256), 0, s, A.rowptr, A.colidx, n, ns, width,
+                       reinterpret_cast<unsigned long long*>(tiles + nt));
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sell_scan_tiles, dim3((unsigned)nt), dim3(256), 0, s, width, ns, off, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -232,33 +264,43 @@ hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64
     return hipGetLastError();
 }
 
-hipError_t launch_sell_fill(bool f32, const CsrArgs& A, int64_t n, const int64_t* off, const int32_t* width,
-                            int32_t* col, void* val, hipStream_t s) {
+hipError_t launch_sell_fill(bool f32, bool narrow, const CsrArgs& A, int64_t n, const int64_t* off,
+                            const int32_t* width, void* col, void* val, hipStream_t s) {
     const int64_t ns = sell_slices(n);
-    if (f32)
-        hipLaunchKernelGGL(k_sell_fill<float>, dim3(grid_for(ns * kSlice)), dim3(256), 0, s, A, n, ns, off, width, col,
-                           static_cast<float*>(val));
-    else
-        hipLaunchKernelGGL(k_sell_fill<double>, dim3(grid_for(ns * kSlice)), dim3(256), 0, s, A, n, ns, off, width,
-                           col, static_cast<double*>(val));
+    const dim3 g(grid_for(ns * kSlice)), b(256);
+    int16_t* c16 = static_cast<int16_t*>(col);
+    int32_t* c32 = static_cast<int32_t*>(col);
+    float* v32 = static_cast<float*>(val);
+    double* v64 = static_cast<double*>(val);
+    if (f32 && narrow) hipLaunchKernelGGL((k_sell_fill<float, int16_t>), g, b, 0, s, A, n, ns, off, width, c16, v32);
+    else if (f32) hipLaunchKernelGGL((k_sell_fill<float, int32_t>), g, b, 0, s, A, n, ns, off, width, c32, v32);
+    else if (narrow) hipLaunchKernelGGL((k_sell_fill<double, int16_t>), g, b, 0, s, A, n, ns, off, width, c16, v64);
+    else hipLaunchKernelGGL((k_sell_fill<double, int32_t>), g, b, 0, s, A, n, ns, off, width, c32, v64);
+    return hipGetLastError();
+}
+
+template <typename E, bool D>
+hipError_t launch_spmv_sell_ed(int P, const SellArgs& A, const void* ucur, const void* uprev, void* w,
+                               const BatchArgs& B, int j, hipStream_t s) {
+    const E* uc = static_cast<const E*>(ucur);
+    const E* up = static_cast<const E*>(uprev);
+    E* ww = static_cast<E*>(w);
+    const dim3 g(B.nblocks), b(kBlock);
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <typename E>
 hipError_t launch_spmv_sell_e(int P, const SellArgs& A, const void* ucur, const void* uprev, void* w,
                               const BatchArgs& B, int j, hipStream_t s) {
-    const E* uc = static_cast<const E*>(ucur);
-    const E* up = static_cast<const E*>(uprev);
-    E* ww = static_cast<E*>(w);
-    const dim3 g(B.nblocks), b(kBlock);
-    switch (P) {
-        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return A.dcol ? launch_spmv_sell_ed<E, true>(P, A, ucur, uprev, w, B, j, s)
+                  : launch_spmv_sell_ed<E, false>(P, A, ucur, uprev, w, B, j, s);
 }
 
 hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,

@@ -100,6 +100,8 @@ def test_footprint_leaves_the_prepared_copy_out():
     h = ds.prepare(kry.KRY_FP64)
     shared = kry.kry_footprint(ds.system_for(kry.KRY_FP64), 2, len(p.C), p.k, p.steps, nseg)
     mbytes = kry.kry_matrix_bytes(h)
-    assert mbytes >= 12 * p.nnz
+    # FP64 values and 16-bit column offsets (every column is within 1600 of
+    # its row here); a plan that builds its own copy reserves 32-bit columns
+    assert mbytes >= 10 * p.nnz
     assert own - shared >= 12 * p.nnz
     ds.close()
