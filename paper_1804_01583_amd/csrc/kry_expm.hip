@@ -213,18 +213,30 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     // of Phi in registers; thread o mm + i (i < mm) owns anchor entry i and
     // keeps row i of Psi.  Slot 0 holds the ping-pong vectors: Z at
     // [cur * kMaxO * kLd], a at [2 * kMaxO * kLd + cur * kLd].
+    // When the threads suffice, the Z chain runs in two halves at once: the
+    // first B/2 steps by Phi, and Z_{B/2 + r} = Z_r Phi^{B/2} by a second set
+    // of o mm threads that keep a column of Phi^{B/2} (the last square before
+    // Psi), so the chains take max(B/2, nanch - 1) steps instead of B - 1.
     constexpr int kZ = kMaxO * kLd;
     double* Zg = E.Z + (int64_t)job * E.B * kMaxO * kMaxK;
     double* Ag = E.anch + (int64_t)job * E.nanch * kMaxK;
     const int nz = o * mm;
-    const bool zthr = tid < nz, athr = tid >= nz && tid < nz + mm;
-    const int zq = zthr ? tid / mm : 0, zc_ = zthr ? tid % mm : 0, ai = athr ? tid - nz : 0;
+    const int half = (E.B >= 2 && (2 * o + 1) * mm <= (int)blockDim.x) ? E.B / 2 : 0;
+    const int nz2 = half > 0 ? nz : 0;
+    const int zlen = half > 0 ? half : E.B;           // steps of the first chain
+    const double* Phh = lds + (half > 0 && E.B > 2 ? 3 - psi : phi) * kSlot;   // Phi^{B/2} when half > 0
+    const bool zthr = tid < nz;
+    const bool z2thr = tid >= nz && tid < nz + nz2;
+    const bool athr = tid >= nz + nz2 && tid < nz + nz2 + mm;
+    const int zt = zthr ? tid : (z2thr ? tid - nz : 0);
+    const int zq = zt / mm, zc_ = zt % mm, ai = athr ? tid - nz - nz2 : 0;
     double reg[kMaxK];
 #pragma unroll
     for (int l = 0; l < kMaxK; ++l) {
         double v = 0.0;
         if (l < mm) {
             if (zthr) v = Phi[l * kLd + zc_];
+            else if (z2thr) v = Phh[l * kLd + zc_];
             else if (athr) v = Psi[ai * kLd + l];
         }
         reg[l] = v;
@@ -251,11 +263,22 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
         Ag[ai] = v;
     }
     __syncthreads();
-    const int iters = max(E.B, E.nanch) - 1;
+    const int iters = max(max(zlen - 1, half), E.nanch - 1);
     for (int r = 0; r < iters; ++r) {
         const int cur = r & 1, nxt = cur ^ 1;
         // step r + 1 from step r; two accumulators halve the dependent chain
-        if (zthr && r + 1 < E.B) {
+        if (z2thr && r < half) {
+            // Z_{half + r} = Z_r Phi^{half}; Z_r stays in buffer cur (the first
+            // chain has written it and stops before overwriting it)
+            const double* zr = lds + cur * kZ + zq * kLd;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int l = 0; l < kMaxK; l += 2) {
+                a0 = fma(zr[l], reg[l], a0);
+                a1 = fma(zr[l + 1], reg[l + 1], a1);
+            }
+            Zg[((int64_t)(half + r) * kMaxO + zq) * kMaxK + zc_] = a0 + a1;
+        } else if (zthr && r + 1 < zlen) {
             const double* zr = lds + cur * kZ + zq * kLd;
             double a0 = 0.0, a1 = 0.0;
 #pragma unroll
