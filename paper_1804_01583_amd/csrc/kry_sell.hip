@@ -28,24 +28,34 @@ using namespace dev;
 
 constexpr int kScanTile = 4096;   // slices per scan workgroup (256 threads x 16)
 
+// One thread per row, one wavefront per slice: the slice width is the
+// wavefront's largest row, and the slice is wide when any of its rows has a
+// column farther than 32767 from the row.
 __global__ __launch_bounds__(256) void k_sell_width(const int64_t* __restrict__ rowptr,
                                                     const int32_t* __restrict__ colidx, int64_t n, int64_t ns,
                                                     int32_t* __restrict__ width,
                                                     unsigned long long* __restrict__ nwide) {
-    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < ns; s += (int64_t)gridDim.x * 256) {
+    const int64_t rows = ns * kSlice;
+    for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < rows; b0 += (int64_t)gridDim.x * 256) {
+        const int64_t r = b0 + threadIdx.x;    // rows is a multiple of 64, so a wavefront is all in or all out
+        if (r >= rows) continue;
         int64_t w = 0;
         bool wide = false;
-        const int64_t r0 = s * kSlice, r1 = min(n, r0 + kSlice);
-        for (int64_t r = r0; r < r1; ++r) {
+        if (r < n) {
             const int64_t e0 = rowptr[r], e1 = rowptr[r + 1];
-            w = max(w, e1 - e0);
+            w = e1 - e0;
             for (int64_t e = e0; e < e1; ++e) {
                 const int64_t d = (int64_t)colidx[e] - r;
                 wide = wide || d < -32768 || d > 32767;
             }
         }
-        width[s] = (int32_t)w;
-        if (wide) atomicAdd(nwide, 1ull);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) w = max(w, (int64_t)__shfl_xor(w, off, 64));
+        const bool any_wide = __any(wide);
+        if ((threadIdx.x & 63) == 0) {
+            width[r / kSlice] = (int32_t)w;
+            if (any_wide) atomicAdd(nwide, 1ull);
+        }
     }
 }
 
@@ -254,7 +264,7 @@ hipError_t launch_sell_layout(const CsrArgs& A, int64_t n, int32_t* width, int64
     // the count of wide slices sits after the nt tile totals
     hipError_t e = launch_fill(reinterpret_cast<double*>(tiles + nt), 1, 0.0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(ns)), dim3(256), 0, s, A.rowptr, A.colidx, n, ns, width,
+    hipLaunchKernelGGL(k_sell_width, dim3(grid_for(ns * kSlice)), dim3(256), 0, s, A.rowptr, A.colidx, n, ns, width,
                        reinterpret_cast<unsigned long long*>(tiles + nt));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
