@@ -136,3 +136,34 @@ def test_forward_and_transposed_agree_on_the_gpu():
     tr = gpu_verify_transposed(p)
     scale = np.abs(fwd["basis"]).max()
     assert np.abs(fwd["basis"] - tr["basis"]).max() <= 1e-8 * scale
+
+
+def test_fp32_basis():
+    # FP32 storage with full reorthogonalisation: the bound of the forward
+    # FP32 tests, max(1e-5, 2 eps_32 ||A||_inf T) of the output scale
+    require_gpu()
+    from paper_1804_01583_amd import kry
+    p = W.heat3d_many_inputs(m=20, k=30, steps=200, floor=0.45)
+    anorm = oracle.krylov.inf_norm(oracle.krylov.system_matrix(p))
+    tol = max(1e-5, 2.0 * 2.0 ** -23 * anorm * p.steps * p.dt)
+    got = gpu_verify_transposed(p, precision=kry.KRY_FP32_BASIS)
+    ref = OT.verify_transposed(p)
+    assert_basis_parity(got["basis"], ref["basis"], rtol=tol)
+    assert got["verdict"]["first_step"] == ref["verdict"]["first_step"]
+
+
+def test_prepared_matrix_gives_the_same_basis():
+    require_gpu()
+    from paper_1804_01583_amd import kry
+    p = W.heat3d_many_inputs(m=20, k=30, steps=100)
+    print(f"[gpu] transposed prepared {p.name} n={p.n}", flush=True)
+    ds = kry.DeviceSystem(p)
+    own = kry.TransposedPlan(ds)
+    b_own = own.basis()
+    own.close()
+    ds.prepare()
+    shared = kry.TransposedPlan(ds)
+    b_shared = shared.basis()
+    shared.close()
+    ds.close()
+    assert np.array_equal(b_own, b_shared)
