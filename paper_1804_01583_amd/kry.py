@@ -356,6 +356,8 @@ class DeviceSystem:
         s.prepared = None
         self.sys = s
         self.prepared = {}
+        self._marshalled = None      # the problem's generators and outputs as kry_gen / kry_segs
+        self._footprints = {}        # workspace bytes per plan shape
 
     def prepare(self, precision=KRY_FP64, stream=None):
         """kry_matrix_create for this CSR system and precision, once: plans of
@@ -397,14 +399,22 @@ class Plan:
         self.k = p.k if k is None else k
         self.dt = p.dt if dt is None else dt
         self.steps = p.steps if steps is None else steps
+        own = gens is None and C is None
         gens = p.gens if gens is None else gens
         C = p.C if C is None else C
         self.ngen = len(gens)
         self.o = len(C)
-        keep = []
-        self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
-        self._C = [_segs(c, keep) for c in C]
-        self._keep = keep
+        # the problem's own generators and outputs are marshalled once per
+        # device system (plans of one system reuse them)
+        if own and dsys._marshalled is not None:
+            self._gens, self._C, self._keep = dsys._marshalled
+        else:
+            keep = []
+            self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
+            self._C = [_segs(c, keep) for c in C]
+            self._keep = keep
+            if own:
+                dsys._marshalled = (self._gens, self._C, keep)
         has_forcing = dsys.b is not None or getattr(p, "b_seg", None) is not None
         nruns = self.ngen + (dsys.center is not None) + has_forcing
         self.stream = torch.cuda.current_stream(dsys.device) if stream is None else stream
@@ -414,8 +424,13 @@ class Plan:
             nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
             if getattr(p, "b_seg", None) is not None and dsys.b is None:
                 nseg += p.b_seg.nseg
-            ws_bytes = kry_footprint(self._sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
-                                     method, block_p)
+            key = (own, precision, method, block_p, self.k, self.steps, nseg, self.o, nruns, self._sys.prepared)
+            ws_bytes = dsys._footprints.get(key) if own else None
+            if ws_bytes is None:
+                ws_bytes = kry_footprint(self._sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
+                                         method, block_p)
+                if own:
+                    dsys._footprints[key] = ws_bytes
             self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dsys.device)
             ws_ptr = self.workspace.data_ptr()
         self.handle = None
