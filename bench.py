@@ -20,6 +20,9 @@ Prints one JSON line.  Options:
   --route R       forward (one run per column of E) or transposed (one run of A^T
                   per output row, Section 4.1); default transposed for
                   heat3d_many_inputs, forward otherwise
+  --graph         one plan whose projection is recorded as a HIP graph and replayed
+                  each step (plan creation outside the timed region; a separate
+                  measurement, not the default line)
   --check C       box (the range check of each output row's interval, default) or
                   lp (the per-step LP of Section 2.1: the generator box cut by
                   sum_j (z_j - zc_j) / r_j <= d / 2, unsafe when every output row
@@ -79,6 +82,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--route", default=None, choices=["forward", "transposed"])
     ap.add_argument("--check", default="box", choices=["box", "lp"])
+    ap.add_argument("--graph", action="store_true")
     ap.add_argument("--method", default=None, choices=["auto", "block", "plain"])
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
@@ -141,7 +145,7 @@ def main():
             dsys.prepare(prec)
         torch.cuda.synchronize()
     m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
-                args.error_target, not args.no_kernel_events, transposed, args.check)
+                args.error_target, not args.no_kernel_events and not args.graph, transposed, args.check, args.graph)
     fp64_ref = None
     if f32:
         torch.cuda.empty_cache()
@@ -181,6 +185,8 @@ def main():
                    "time_steps": p.steps, "basis_columns": nruns, "krylov_runs": m["krylov_runs"],
                    "route": "transposed" if transposed else "forward", "precision": args.precision,
                    "check": args.check,
+                   "graph": ("one plan made before the timed region, its projection replayed as a HIP graph"
+                             if args.graph else None),
                    "method": {"block": "block_arnoldi", "plain": "lanczos_plain"}.get(
                        method_name, "lanczos" if p.symmetric else "arnoldi"),
                    "error_target": args.error_target or None,
@@ -196,6 +202,8 @@ def main():
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
     }
+    if args.graph:
+        out["roofline"] = None      # per-kernel events and graph replay exclude each other
     print(json.dumps(out))
 
 
@@ -256,14 +264,28 @@ def lp_sets(p):
 
 
 def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_target=0.0, kernel_events=True,
-            transposed=False, check="box"):
+            transposed=False, check="box", graph=False):
     """Times `steps` whole verifications (after `warmup`), then the same with
-    per-kernel HIP events; returns the throughput and per-kernel figures."""
-    stream = torch.cuda.current_stream()
+    per-kernel HIP events; returns the throughput and per-kernel figures.
+    graph: one plan made before the timed region, its projection replayed
+    as a HIP graph each step (on a stream of its own)."""
+    stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+    if graph:
+        torch.cuda.set_stream(stream)
     used = {}
     krylov_runs = {}
+    graph_plan = None
+    if graph:
+        graph_plan = (kry.TransposedPlan(dsys, stream=stream, precision=precision, method=method) if transposed
+                      else kry.Plan(dsys, stream=stream, precision=precision, method=method))
+        graph_plan.set_graph(True)
+        krylov_runs["n"] = len(graph_plan.runs) if transposed else graph_plan.nruns
 
     def step():
+        if graph_plan is not None:
+            graph_plan.project_expm(None)
+            v = graph_plan.check_lp(*lp_sets(p)) if check == "lp" else graph_plan.check(p.unsafe)
+            return v, graph_plan.nruns
         if transposed:
             plan = kry.TransposedPlan(dsys, stream=stream, precision=precision, method=method)
             krylov_runs["n"] = len(plan.runs)
@@ -310,6 +332,9 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         torch.cuda.synchronize()
         elapsed_ev = time.perf_counter() - t1
         kry.profile_enable(False)
+    if graph_plan is not None:
+        graph_plan.close()
+        torch.cuda.set_stream(torch.cuda.default_stream())
     kern = {}
     for name in kry.profile_names():
         cnt, ms = kry.profile_read(name)

@@ -228,6 +228,19 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out);
 kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out,
                                 double* z_out);
 
+/* kry_plan_set_graph -- graph mode (on != 0): the next kry_project_expm
+ * records everything it enqueues (the Krylov batches, the small stage and
+ * the assembly) as one HIP graph and launches it; later calls launch the
+ * recorded graph again, with one host call instead of one per kernel.  The
+ * graph reads the plan's inputs through the same device pointers, so new
+ * values written there (forcing, center, matrix values) are picked up;
+ * the plan's sizes and segment sets are fixed.  For Lanczos and Arnoldi
+ * plans with k <= 56 and no error target, on a stream other than the
+ * default one (KRY_EINVAL), and not while kernel timing is on (the capture
+ * returns KRY_ENOTSUP).  on = 0 returns to per-kernel launches and frees
+ * the graph. */
+kry_status kry_plan_set_graph(kry_plan* plan, int32_t on);
+
 /* kry_check_lp_safety -- the per-step LP of Section 2.1 for a polytopic
  * initial set and a conjunction of output halfspaces, on the basis of
  * kry_project_expm.  With M_s the generator columns of the basis at step s

@@ -424,6 +424,10 @@ struct kry_plan {
     int32_t* out_col_dev = nullptr;
     // per-step LP: inputs, per-step records and verdict (allocated on first use)
     char* lp_mem = nullptr;
+    // graph mode: the projection recorded once and replayed
+    bool graph_on = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     std::vector<double> lp_host;
     int lpr = 1;
     int32_t method = KRY_LANCZOS;
@@ -1039,13 +1043,14 @@ kry_status project_block(kry_plan* plan) {
 
 }  // namespace
 
-kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (plan->method == KRY_BLOCK_ARNOLDI) {
-        kry_status st = project_block(plan);
-        if (st != KRY_OK) return st;
-        return finish_projection(plan, basis_out);
-    }
+}  // extern "C"
+
+namespace {
+
+// Everything kry_project_expm enqueues for the single-vector methods: the
+// Krylov batches, the small stage and the assembly (and, with finish, the
+// copy of the basis).
+kry_status enqueue_projection(kry_plan* plan, double* basis_out, bool finish) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
@@ -1223,7 +1228,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
             e = timed("dense_expm", s, [&] { return dense_expm_steps(J, plan->at<double>(Y.dws), &hn, s); });
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("dense stage: ") + hipGetErrorString(e));
         }
-        return finish_projection(plan, basis_out);
+        return finish ? finish_projection(plan, basis_out) : KRY_OK;
     }
     E.Z = plan->zmat();
     E.anch = plan->anch();
@@ -1236,7 +1241,46 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
                    plan->o_out, plan->ncols};
     e = timed("assemble", s, [&] { return launch_assemble(A, s); });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("assemble: ") + hipGetErrorString(e));
-    return finish_projection(plan, basis_out);
+    return finish ? finish_projection(plan, basis_out) : KRY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (plan->method == KRY_BLOCK_ARNOLDI) {
+        kry_status st = project_block(plan);
+        if (st != KRY_OK) return st;
+        return finish_projection(plan, basis_out);
+    }
+    if (plan->graph_on) {
+        // first call: record the whole projection as one graph; then replay it
+        if (!plan->graph_exec) {
+            if (prof().on) return fail(KRY_ENOTSUP, "kernel timing and graph capture exclude each other");
+            KRY_HIP(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
+            const kry_status st = enqueue_projection(plan, nullptr, false);
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(plan->stream, &g);
+            if (st != KRY_OK || ec != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                if (st != KRY_OK) return st;
+                return fail(KRY_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+            }
+            hipGraphExec_t x = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(KRY_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            }
+            plan->graph = g;
+            plan->graph_exec = x;
+        }
+        KRY_HIP(hipGraphLaunch(plan->graph_exec, plan->stream));
+        return finish_projection(plan, basis_out);
+    }
+    return enqueue_projection(plan, basis_out, true);
 }
 
 kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out, double* z_out) {
@@ -1358,6 +1402,32 @@ kry_status kry_check_lp_safety(kry_plan* plan, const double* G, const double* h,
     return KRY_OK;
 }
 
+kry_status kry_plan_set_graph(kry_plan* plan, int32_t on) {
+    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+    if (on) {
+        if (plan->method == KRY_BLOCK_ARNOLDI)
+            return fail(KRY_ENOTSUP, "graph mode covers the single-vector methods (block runs read sizes back)");
+        if (plan->Y.dense_runs)
+            return fail(KRY_ENOTSUP, "graph mode covers k <= 56 (the dense stage reads sizes back)");
+        if (plan->err_eps > 0.0)
+            return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
+        if (plan->stream == nullptr) return fail(KRY_EINVAL, "graph capture needs a stream other than the default one");
+    }
+    plan->graph_on = on != 0;
+    if (!plan->graph_on) {
+        if (plan->graph_exec) {
+            KRY_HIP(hipStreamSynchronize(plan->stream));
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            plan->graph_exec = nullptr;
+        }
+        if (plan->graph) {
+            (void)hipGraphDestroy(plan->graph);
+            plan->graph = nullptr;
+        }
+    }
+    return KRY_OK;
+}
+
 kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out) {
     if (!plan) return fail(KRY_EINVAL, "plan is NULL");
     if (nruns) *nruns = plan->nruns;
@@ -1422,6 +1492,8 @@ kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
         return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
     if (eps > 0.0 && plan->transposed)
         return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
+    if (eps > 0.0 && plan->graph_on)
+        return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
     if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
     plan->err_eps = eps;
     if (eps == 0.0) return KRY_OK;
@@ -1576,6 +1648,11 @@ void kry_plan_destroy(kry_plan* plan) {
         (void)hipStreamSynchronize(plan->stream);
         (void)hipFree(plan->lp_mem);
     }
+    if (plan->graph_exec) {
+        (void)hipStreamSynchronize(plan->stream);
+        (void)hipGraphExecDestroy(plan->graph_exec);
+    }
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->flag_ev) (void)hipEventDestroy(plan->flag_ev);
     if (plan->hflags) (void)hipHostFree(plan->hflags);
     delete plan;

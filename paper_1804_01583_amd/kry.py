@@ -86,6 +86,7 @@ def _load():
     lib.kry_plan_block.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                                    ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_plan_set_error_target.argtypes = [P, ct.c_double]
+    lib.kry_plan_set_graph.argtypes = [P, ct.c_int32]
     lib.kry_plan_error.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
     lib.kry_matrix_create.argtypes = [ct.POINTER(KrySystem), ct.c_int32, P, ct.POINTER(P)]
     lib.kry_matrix_bytes.argtypes = [P, ct.POINTER(ct.c_size_t)]
@@ -99,7 +100,7 @@ def _load():
     lib.kry_profile_names.restype = ct.c_char_p
     for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
-              "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
+              "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
         getattr(lib, f).restype = ct.c_int
     return lib
@@ -108,7 +109,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
-            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_error",
+            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
+            "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
 
@@ -233,6 +235,10 @@ def kry_matrix_destroy(mat: int):
 
 def kry_plan_set_error_target(plan: int, eps: float):
     _check(lib.kry_plan_set_error_target(plan, eps))
+
+
+def kry_plan_set_graph(plan: int, on: bool):
+    _check(lib.kry_plan_set_graph(plan, 1 if on else 0))
 
 
 def kry_plan_error(plan: int, run: int):
@@ -468,6 +474,11 @@ class Plan:
 
     def krylov(self, run: int):
         return kry_plan_krylov(self.handle, run, self.k, self.o)
+
+    def set_graph(self, on: bool = True):
+        """Graph mode (kry_plan_set_graph): project_expm records its launches
+        once and replays them."""
+        kry_plan_set_graph(self.handle, on)
 
     def set_error_target(self, eps: float):
         """Error-controlled Krylov dimension (see kry_plan_set_error_target)."""

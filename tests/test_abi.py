@@ -192,3 +192,10 @@ def test_lp_check_rejects_null_plan():
     with pytest.raises(kry.KryError) as ei:
         kry.kry_check_lp_safety(None, np.zeros((0, 1)), np.zeros(0), np.ones((1, 1)), np.ones(1), 1, 1, 3)
     assert ei.value.status == kry.KRY_EINVAL
+
+
+def test_graph_mode_rejects_null_plan():
+    from paper_1804_01583_amd import kry
+    with pytest.raises(kry.KryError) as ei:
+        kry.kry_plan_set_graph(None, True)
+    assert ei.value.status == kry.KRY_EINVAL
