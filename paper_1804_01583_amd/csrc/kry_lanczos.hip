@@ -462,15 +462,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil_march(StencilArgs S, co
 // Second half of a4 + the partials of a5 and a6: alpha_j = sum of the dot
 // partials; w -= alpha_j sigma_j u_j; partials of |w|^2 and C w.  The first
 // chunk of rows is loaded before the alpha reduction completes.
-template <typename E, int P, int O>
+constexpr int64_t kSweepLongBlock = 65536;   // rows per block from which the sweep takes long chunks
+
+template <typename E, int P, int O, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
                                                   const E* __restrict__ ucur,
                                                   E* __restrict__ w, BatchArgs B, int j) {
     if (batch_stopped<P>(B)) return;   // the batch met its error target
     constexpr int NV = P * (1 + O);
-    // rows per thread and chunk: two chunks in flight at once (measured: one
-    // row per thread for one or four and more runs, two for two runs)
-    constexpr int RC = P == 2 ? 2 : 1;
+    // rows per thread and chunk, measured on MI355X: blocks of up to a few
+    // thousand rows keep two chunks in flight (one row per thread and chunk,
+    // two for two runs); blocks of very many rows (LONG, chosen at launch)
+    // stream best in chunks of four rows per thread, one chunk at a time
+    constexpr int RC = LONG ? 4 : (P == 2 ? 2 : 1);
     __shared__ double s_lds[(kBlock / 64) * NV];
     __shared__ double s_alpha[P];
     __shared__ SegStage<O> st;
@@ -563,12 +567,19 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SegTable T, int32_t oset0,
             }
         }
     };
-    for (int ch = 0; ch < nch; ch += 2) {
-        if (ch + 1 < nch) load_into(ch + 1, uv2, wv2, rr2);
-        process(uv, wv, rr);
-        if (ch + 1 < nch) {
-            if (ch + 2 < nch) load_into(ch + 2, uv, wv, rr);
-            process(uv2, wv2, rr2);
+    if constexpr (LONG) {
+        for (int ch = 0; ch < nch; ++ch) {
+            if (ch > 0) load_chunk(ch);
+            process(uv, wv, rr);
+        }
+    } else {
+        for (int ch = 0; ch < nch; ch += 2) {
+            if (ch + 1 < nch) load_into(ch + 1, uv2, wv2, rr2);
+            process(uv, wv, rr);
+            if (ch + 1 < nch) {
+                if (ch + 2 < nch) load_into(ch + 2, uv, wv, rr);
+                process(uv2, wv2, rr2);
+            }
         }
     }
     store_partials<NV>(acc, stage_part(B, j), B.nblocks, s_lds, B.xcd_map);
@@ -640,8 +651,12 @@ hipError_t launch_start_t(const StartSrc& src, const SegTable& T, int32_t oset0,
 template <typename E, int P, int O>
 hipError_t launch_sweep_t(const SegTable& T, int32_t oset0, const void* ucur, void* w,
                           const BatchArgs& B, int j, hipStream_t s) {
-    hipLaunchKernelGGL((k_sweep<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0,
-                       static_cast<const E*>(ucur), static_cast<E*>(w), B, j);
+    if (B.rows_per_block >= kSweepLongBlock)
+        hipLaunchKernelGGL((k_sweep<E, P, O, true>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0,
+                           static_cast<const E*>(ucur), static_cast<E*>(w), B, j);
+    else
+        hipLaunchKernelGGL((k_sweep<E, P, O, false>), dim3(B.nblocks), dim3(kBlock), 0, s, T, oset0,
+                           static_cast<const E*>(ucur), static_cast<E*>(w), B, j);
     return hipGetLastError();
 }
 
