@@ -96,7 +96,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(independent runs and queries shard without communication; see DESIGN.md)", file=sys.stderr)
+              "(independent runs and queries shard without communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -40,7 +40,7 @@ typedef enum {
     KRY_ENOMEM = 2,    /* device allocation failed or workspace too small */
     KRY_EDEVICE = 3,   /* a HIP runtime call failed */
     KRY_ENUMERIC = 4,  /* non-finite value met in the Krylov recurrence */
-    KRY_ENOTSUP = 5    /* combination not supported by this build */
+    KRY_ENOTSUP = 5    /* combination of options the library does not offer */
 } kry_status;
 
 typedef enum { KRY_FP64 = 0, KRY_FP32_BASIS = 1 } kry_precision;
