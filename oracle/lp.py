@@ -49,7 +49,7 @@ def lp_feasible(M, f, zlo, zhi, G, h, U, u):
     U (M z + f) <= u} as SciPy decides it (its own absolute tolerance).
     Returns (feasible, z) with z a feasible point (None when infeasible)."""
     d = M.shape[1]
-    A = np.vstack([G.reshape(-1, d), U @ M])
+    A = np.vstack([np.reshape(G, (len(h), d)), U @ M])
     b = np.concatenate([h, u - U @ f])
     if d == 0:
         ok = bool(np.all(b >= 0.0))
@@ -69,7 +69,7 @@ def lp_margin(M, f, zlo, zhi, G, h, U, u, with_point=False):
     an interior point, positive when it is empty.  With ``with_point`` also
     returns the minimising z."""
     d = M.shape[1]
-    A = np.vstack([G.reshape(-1, d), U @ M])
+    A = np.vstack([np.reshape(G, (len(h), d)), U @ M])
     b = np.concatenate([h, u - U @ f])
     amax = np.abs(A).max(axis=1) if (A.size and d) else np.zeros(A.shape[0])
     s = np.maximum(amax, np.abs(b))
@@ -96,8 +96,9 @@ def lp_check(basis: np.ndarray, roles, zc, radius, G, h, U, u):
     margin (per-step smallest scaled violation))."""
     zc = np.asarray(zc, np.float64); radius = np.asarray(radius, np.float64)
     zlo, zhi = zc - radius, zc + radius
-    G = np.asarray(G, np.float64).reshape(-1, zc.size); h = np.asarray(h, np.float64)
-    U = np.asarray(U, np.float64).reshape(-1, basis.shape[1]); u = np.asarray(u, np.float64)
+    h = np.asarray(h, np.float64); u = np.asarray(u, np.float64)
+    G = np.asarray(G, np.float64).reshape(h.size, zc.size)
+    U = np.asarray(U, np.float64).reshape(u.size, basis.shape[1])
     feas = np.zeros(basis.shape[0], bool)
     margin = np.zeros(basis.shape[0])
     first, z_ce = -1, None
