@@ -52,7 +52,7 @@ def _compare(p, basis_ref, roles, G, h, U, u, got, basis_gpu, min_clear=0.9):
         assert np.all(z >= zc - rad - 1e-12) and np.all(z <= zc + rad + 1e-12)
         # no row, scaled to a largest coefficient of 1, is violated by more
         # than the LP tolerance
-        A = np.vstack([G.reshape(-1, len(zc)), U @ M])
+        A = np.vstack([np.reshape(G, (len(h), len(zc))), U @ M])
         b = np.concatenate([h, u - U @ f])
         sc = np.abs(A).max(axis=1) if len(zc) else np.zeros(len(b))
         sc[sc == 0.0] = 1.0
@@ -127,3 +127,22 @@ def test_whole_output_space_unsafe_and_empty_initial_set():
     G = np.array([[1.0, 0.0]]); h = np.array([zc[0] - rad[0] - 0.1])
     _, got = _run(p, G, h, np.zeros((0, 1)), np.zeros(0))
     assert got["first_step"] == -1 and np.all(got["flags"] == 0)
+
+
+def test_point_initial_set_and_no_generators():
+    # every radius 0: the initial set is one point; and a plan without
+    # generators (center and forcing only) decides U f_s <= u alone
+    require_gpu()
+    import dataclasses
+    p = W.random_symmetric(n=300, k=12, steps=120, dt=0.05, ngen=3, o=2, seed=6, affine=True, center=True)
+    p = dataclasses.replace(p, gens=[dataclasses.replace(g, radius=0.0) for g in p.gens])
+    ref = oracle.verify(p)
+    lvl = np.quantile(ref["basis"].sum(axis=2), 0.5, axis=0)
+    U = np.array([[-1.0, 0.0], [0.0, -1.0]]); u = -lvl
+    basis, got = _run(p, np.zeros((0, 3)), np.zeros(0), U, u)
+    r = _compare(p, ref["basis"], ref["roles"], np.zeros((0, 3)), np.zeros(0), U, u, got, basis)
+    np.testing.assert_array_equal(got["z"], [g.zc for g in p.gens] if got["first_step"] >= 0 else got["z"])
+    q = dataclasses.replace(p, gens=[])
+    refq = oracle.verify(q)
+    basis, got = _run(q, np.zeros((0, 0)), np.zeros(0), U, u)
+    _compare(q, refq["basis"], refq["roles"], np.zeros((0, 0)), np.zeros(0), U, u, got, basis)
