@@ -14,7 +14,7 @@ constexpr int kMaxK = 56;        // Krylov dimension of the one-workgroup LDS ex
 constexpr int kMaxKD = 512;      // Krylov dimension with the dense stage (k > kMaxK)
 constexpr int kMaxKP = 8192;     // Krylov dimension of three-vector (plain) Lanczos
 constexpr int kMaxKE = 2048;     // Krylov dimension the error control's eigen-solve holds in LDS
-constexpr int kExpmThreads = 512;
+constexpr int kExpmThreads = 576;
 constexpr int kMaxP = 8;         // runs advanced per mat-vec launch
 constexpr int kMaxNV = 24;       // values reduced per block: P * (1 + O)
 
