@@ -199,3 +199,20 @@ def test_graph_mode_rejects_null_plan():
     with pytest.raises(kry.KryError) as ei:
         kry.kry_plan_set_graph(None, True)
     assert ei.value.status == kry.KRY_EINVAL
+
+
+def test_dense_vectors_become_index_ranges():
+    # the binding hands a dense center or forcing to the transposed route as
+    # index ranges: the same vector, run by run
+    from paper_1804_01583_amd import kry
+    import workloads as W
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        v = rng.choice([0.0, 1.0, 2.5, -1.0], size=int(rng.integers(1, 40)))
+        r = kry._runs_of(v)
+        s = W.segments_of_dense(v)
+        assert np.array_equal(r.lo, s.lo) and np.array_equal(r.hi, s.hi) and np.array_equal(r.w, s.w)
+        back = np.zeros(v.size)
+        for a, b, w in zip(r.lo, r.hi, r.w):
+            back[a:b] = w
+        assert np.array_equal(back, v)
