@@ -16,6 +16,15 @@
  * range with the unsafe set (the per-step LP of Section 2.1, specialised to a
  * box initial set) and returns the first violation with a counter-example.
  *
+ * Beside that path: the same basis one output row at a time by the
+ * transposed dynamics (Section 4.1, kry_plan_create_transposed); the per-step
+ * LP itself for a polytopic initial set and a conjunction of output
+ * halfspaces (kry_check_lp_safety); the Krylov dimension chosen by the
+ * a-posteriori bound of Lemma 1 (kry_plan_set_error_target); block Arnoldi
+ * over up to 16 generators; an FP32-stored basis; a sliced-ELL copy of a CSR
+ * matrix shared by plans (kry_matrix_create); and a projection recorded once
+ * as a HIP graph and replayed (kry_plan_set_graph).
+ *
  * Conventions for every entry point:
  *  - Device pointers are caller-owned and borrowed until kry_plan_destroy.
  *    Host pointers are read during the call only.
