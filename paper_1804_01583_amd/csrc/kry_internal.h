@@ -263,6 +263,13 @@ hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTa
                         void* u, const BatchArgs& B, hipStream_t s);
 hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,
                             const BatchArgs& B, int j, hipStream_t s);
+// Kernel timing: when the pair is set, the next sliced-ELL mat-vec launch
+// passes it to hipExtLaunchKernelGGL, which stamps the kernel's own start
+// and end (instead of events recorded around the launch).
+struct ExtEvents {
+    hipEvent_t start, stop;
+};
+ExtEvents* ext_events();   // this thread's pending pair (null members: none)
 hipError_t launch_spmv_csr(int P, int lpr, bool f32, const CsrArgs& A, const void* ucur,
                            const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s);
 // march: the column-marching kernel (grid ap_nblocks), else the row kernel.

@@ -18,6 +18,8 @@
 // bytes an FP64 entry streams per mat-vec.
 #include "kry_device.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace kry {
@@ -296,11 +298,18 @@ hipError_t launch_spmv_sell_ed(int P, const SellArgs& A, const void* ucur, const
     const E* up = static_cast<const E*>(uprev);
     E* ww = static_cast<E*>(w);
     const dim3 g(B.nblocks), b(kBlock);
+    const ExtEvents ev = *ext_events();
+    auto go = [&](auto kernel) {
+        if (ev.start != nullptr)
+            hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev.start, ev.stop, 0, A, uc, up, ww, B, j);
+        else
+            hipLaunchKernelGGL(kernel, g, b, 0, s, A, uc, up, ww, B, j);
+    };
     switch (P) {
-        case 1: hipLaunchKernelGGL((k_spmv_sell<E, 1, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 2: hipLaunchKernelGGL((k_spmv_sell<E, 2, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 4: hipLaunchKernelGGL((k_spmv_sell<E, 4, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
-        case 8: hipLaunchKernelGGL((k_spmv_sell<E, 8, D>), g, b, 0, s, A, uc, up, ww, B, j); break;
+        case 1: go(k_spmv_sell<E, 1, D>); break;
+        case 2: go(k_spmv_sell<E, 2, D>); break;
+        case 4: go(k_spmv_sell<E, 4, D>); break;
+        case 8: go(k_spmv_sell<E, 8, D>); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
