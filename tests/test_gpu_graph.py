@@ -103,3 +103,22 @@ def test_refusals():
             plan.set_graph(True)
         assert ei.value.status == kry.KRY_ENOTSUP
         plan.close()
+
+
+def test_transposed_plan_replays():
+    torch = require_gpu()
+    from paper_1804_01583_amd import kry
+    p = W.heat3d_many_inputs(m=16, k=24, steps=120)
+    print(f"[gpu] graph transposed n={p.n}", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ds = kry.DeviceSystem(p)
+        ref = kry.TransposedPlan(ds, stream=s)
+        ref_b = ref.basis()
+        ref.close()
+        plan = kry.TransposedPlan(ds, stream=s)
+        plan.set_graph(True)
+        for rep in range(3):
+            assert np.array_equal(plan.basis(), ref_b), f"replay {rep}"
+            torch.cuda.synchronize()
+        plan.close()
