@@ -146,3 +146,19 @@ def test_point_initial_set_and_no_generators():
     refq = oracle.verify(q)
     basis, got = _run(q, np.zeros((0, 0)), np.zeros(0), U, u)
     _compare(q, refq["basis"], refq["roles"], np.zeros((0, 0)), np.zeros(0), U, u, got, basis)
+
+
+def test_block_arnoldi_plan():
+    # sixteen generators advanced as one block Krylov space, then the LP
+    require_gpu()
+    from paper_1804_01583_amd import kry
+    import oracle.block as OB
+    p = W.conv_diff3d(nx=12, ny=12, nz=14, ngen=16, gen_len=20, o=3, k=6, dt=1e-3, steps=60)
+    ref = OB.block_verify(p, p=16)
+    rng = np.random.default_rng(3)
+    zc, rad = _box(p)
+    G = rng.normal(0, 1, (4, 16)); h = G @ zc + rng.uniform(0.05, 0.3, 4)
+    mid = ref["basis"].sum(axis=2)
+    U = rng.normal(0, 1, (3, 3)); u = np.quantile(mid @ U.T, 0.5, axis=0)
+    basis, got = _run(p, G, h, U, u, method=kry.KRY_BLOCK_ARNOLDI, block_p=16)
+    _compare(p, ref["basis"], ref["roles"], G, h, U, u, got, basis)

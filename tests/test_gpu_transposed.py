@@ -167,3 +167,11 @@ def test_prepared_matrix_gives_the_same_basis():
     shared.close()
     ds.close()
     assert np.array_equal(b_own, b_shared)
+
+
+def test_paper_heat_stencil_faces():
+    # insulated faces and the exchange term on x = 1, matrix-free: the
+    # transposed route from the centre output
+    require_gpu()
+    p = W.heat3d_paper_stencil(m=12, k=30, dt=0.02, steps=80)
+    _parity(p)
