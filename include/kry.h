@@ -204,7 +204,9 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
  *     coordinate, a matrix of size k + 1.
  *  method: KRY_AUTO, KRY_LANCZOS (symmetric sys_t) or KRY_ARNOLDI; others
  *     give KRY_ENOTSUP.  dt, steps, precision, hip_stream: as for
- *     kry_plan_create.  The plan allocates its own workspace.
+ *     kry_plan_create.
+ *  workspace: device buffer of workspace_bytes >= kry_footprint_transposed(...)
+ *     (256-byte aligned), or NULL to let the plan allocate its own.
  * kry_project_expm and kry_check_box_safety then behave as for a forward
  * plan with columns in the order generators, center, forcing; kry_plan_runs
  * and kry_plan_krylov describe the o transposed runs (P has one row per
@@ -213,7 +215,16 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
 kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* gens, int32_t ngen,
                                       const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
                                       double dt, int64_t steps, int32_t precision, int32_t method,
-                                      void* hip_stream, kry_plan** out);
+                                      void* workspace, size_t workspace_bytes, void* hip_stream,
+                                      kry_plan** out);
+
+/* kry_footprint_transposed -- device workspace bytes of a transposed plan:
+ * ngen generators, has_center (0/1) a center row, o output rows (the runs),
+ * the forcing when sys_t->b_segs is given; nseg_total = segments of the
+ * generators, the center, the output rows and b_segs together.  Host only. */
+kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32_t has_center, int32_t o,
+                                    int32_t k, int64_t steps, int64_t nseg_total, int32_t precision,
+                                    int32_t method, size_t* bytes);
 
 /* kry_project_expm -- run the Krylov process of every run (Algorithms 3-4),
  * then form the basis matrix for all steps:

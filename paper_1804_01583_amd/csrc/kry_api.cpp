@@ -571,6 +571,37 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
     return KRY_OK;
 }
 
+kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32_t has_center, int32_t o,
+                                    int32_t k, int64_t steps, int64_t nseg_total, int32_t precision,
+                                    int32_t method, size_t* bytes) {
+    kry_status st = validate_system(sys_t);
+    if (st != KRY_OK) return st;
+    if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
+    if (sys_t->b) return fail(KRY_ENOTSUP, "the transposed route takes the forcing as b_segs (a projection row)");
+    if (method == KRY_AUTO) method = sys_t->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+    if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
+        return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
+    const bool has_b = sys_t->b_segs != nullptr;
+    const int32_t nproj = ngen + (has_center ? 1 : 0) + (has_b ? 1 : 0);
+    if (ngen < 0 || nproj < 1 || nproj > kMaxO || o < 1 || o > kMaxO || k < 1 ||
+        k > (has_b ? kMaxK - 1 : kMaxK) || steps < 0 || nseg_total < 0)
+        return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows, 1 <= o <= 8, k in [1, 56] "
+                                "([1, 55] with forcing), steps >= 0, nseg_total >= 0 required");
+    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+    // the shapes kry_plan_create_transposed lays out: o runs projected on
+    // nproj rows, one job per run plus one per run for the forcing column
+    const int32_t njobs = o * (has_b ? 2 : 1);
+    const int32_t nsets = ngen + o + (has_b ? 1 : 0) + (has_center ? 1 : 0);
+    const int32_t nb = nblocks_for(sys_t->n, rows_per_block_for(sys_t->n));
+    const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys_t->kind == KRY_CSR) ? sys_t->nnz : 0;
+    const Layout Y = make_layout(sys_t->n, o, nproj, k, steps, 0,
+                                 meta_size(nseg_total, nsets, std::max(njobs, nproj), nb, njobs), method,
+                                 march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method), njobs,
+                                 nproj, o);
+    *bytes = Y.total;
+    return KRY_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -899,11 +930,12 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
 kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* gens, int32_t ngen,
                                       const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
                                       double dt, int64_t steps, int32_t precision, int32_t method,
-                                      void* hip_stream, kry_plan** out) {
+                                      void* workspace, size_t workspace_bytes, void* hip_stream,
+                                      kry_plan** out) {
     if (out) *out = nullptr;
     if (!out) return fail(KRY_EINVAL, "out is NULL");
     return plan_create(sys_t, gens, ngen, nullptr, center, true, C, o, k, dt, steps, precision, method, 0,
-                       nullptr, 0, hip_stream, out);
+                       workspace, workspace_bytes, hip_stream, out);
 }
 
 namespace {

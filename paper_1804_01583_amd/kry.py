@@ -73,7 +73,10 @@ def _load():
                                     ct.c_int32, ct.c_int32, ct.c_int32, P, ct.c_size_t, P, ct.POINTER(P)]
     lib.kry_plan_create_transposed.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32,
                                                ct.POINTER(KrySegs), ct.POINTER(KrySegs), ct.c_int32, ct.c_int32,
-                                               ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.POINTER(P)]
+                                               ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.c_size_t, P,
+                                               ct.POINTER(P)]
+    lib.kry_footprint_transposed.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
+                                             ct.c_int64, ct.c_int64, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
     lib.kry_project_expm.argtypes = [P, P]
     lib.kry_check_lp_safety.argtypes = [P, P, P, ct.c_int32, P, P, ct.c_int32, ct.POINTER(ct.c_int64),
                                         ct.POINTER(ct.c_int32), P, P, P]
@@ -98,7 +101,8 @@ def _load():
     lib.kry_profile_enable.argtypes = [ct.c_int32]
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
-    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
+    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed", "kry_project_expm",
+              "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
@@ -108,7 +112,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
+EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed", "kry_project_expm",
+            "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
             "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
@@ -148,14 +153,23 @@ def kry_plan_create(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Se
 
 def kry_plan_create_transposed(system_t: KrySystem, gens: Sequence[KryGen], center: Optional[KrySegs],
                                C: Sequence[KrySegs], k: int, dt: float, steps: int, precision=KRY_FP64,
-                               method=KRY_AUTO, stream_ptr=None) -> int:
+                               method=KRY_AUTO, stream_ptr=None, workspace_ptr=None, workspace_bytes=0) -> int:
     garr = (KryGen * max(len(gens), 1))(*gens)
     carr = (KrySegs * len(C))(*C)
     out = ct.c_void_p()
     cptr = ct.byref(center) if center is not None else None
     _check(lib.kry_plan_create_transposed(ct.byref(system_t), garr, len(gens), cptr, carr, len(C), k, dt, steps,
-                                          precision, method, stream_ptr, ct.byref(out)))
+                                          precision, method, workspace_ptr, workspace_bytes, stream_ptr,
+                                          ct.byref(out)))
     return out.value
+
+
+def kry_footprint_transposed(system_t: KrySystem, ngen: int, has_center: bool, o: int, k: int, steps: int,
+                             nseg_total: int, precision=KRY_FP64, method=KRY_AUTO) -> int:
+    b = ct.c_size_t()
+    _check(lib.kry_footprint_transposed(ct.byref(system_t), ngen, 1 if has_center else 0, o, k, steps, nseg_total,
+                                        precision, method, ct.byref(b)))
+    return b.value
 
 
 def kry_project_expm(plan: int, basis_out_ptr=None):
@@ -512,7 +526,7 @@ class TransposedPlan(Plan):
     handed to the library as index ranges."""
 
     def __init__(self, dsys_t: DeviceSystem, k=None, dt=None, steps=None, precision=KRY_FP64, method=KRY_AUTO,
-                 stream=None, gens=None, C=None):
+                 stream=None, gens=None, C=None, workspace="torch"):
         import torch
         p = dsys_t.problem
         self.dsys = dsys_t
@@ -535,9 +549,20 @@ class TransposedPlan(Plan):
         self._keep = keep
         self.workspace = None
         self.stream = torch.cuda.current_stream(dsys_t.device) if stream is None else stream
+        ws_ptr, ws_bytes = None, 0
+        if workspace == "torch":
+            nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
+            nseg += (self._center.nseg if self._center is not None else 0)
+            if self._sys.b_segs:
+                nseg += self._sys.b_segs.contents.nseg
+            ws_bytes = kry_footprint_transposed(self._sys, self.ngen, self._center is not None, self.o, self.k,
+                                                self.steps, nseg, precision, method)
+            self.workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dsys_t.device)
+            ws_ptr = self.workspace.data_ptr()
         self.handle = None
         self.handle = kry_plan_create_transposed(self._sys, self._gens, self._center, self._C, self.k, self.dt,
-                                                 self.steps, precision, method, self.stream.cuda_stream)
+                                                 self.steps, precision, method, self.stream.cuda_stream, ws_ptr,
+                                                 ws_bytes)
         self.runs = kry_plan_runs(self.handle)
         self.ncols = self.ngen + (p.center is not None) + (p.b is not None or getattr(p, "b_seg", None) is not None)
         self.roles = ["gen"] * self.ngen + (["center"] if p.center is not None else []) + \

@@ -184,6 +184,12 @@ def test_transposed_plan_rejects_bad_arguments(bad):
     kc = [kry._segs(W.segments_from_ranges([(5, 9)]), keep)]
     with pytest.raises(kry.KryError) as ei:
         kry.kry_plan_create_transposed(s, kg, center, kc, k, 0.1, 10, kry.KRY_FP64, method, None)
+    if bad in ("dense_b", "k_forcing", "rows", "block", "plain"):
+        # the footprint of the same transposed plan is refused the same way
+        nseg = sum(g.seg.nseg for g in gens) + 1
+        with pytest.raises(kry.KryError) as ef:
+            kry.kry_footprint_transposed(s, len(gens), center is not None, 1, k, 10, nseg, kry.KRY_FP64, method)
+        assert ef.value.status == expected
     assert ei.value.status == expected, kry.lib.kry_last_error()
 
 
@@ -216,3 +222,18 @@ def test_dense_vectors_become_index_ranges():
         for a, b, w in zip(r.lo, r.hi, r.w):
             back[a:b] = w
         assert np.array_equal(back, v)
+
+
+def test_transposed_footprint_is_host_only_and_scales_with_n():
+    from paper_1804_01583_amd import kry
+    import workloads as W
+    keep = []
+    small, big = _csr_system(10_000), _csr_system(1_000_000)
+    bseg = kry._segs(W.segments_from_ranges([(10, 20)], 0.5), keep)
+    for s in (small, big):
+        s.b_segs = ct.pointer(bseg)
+    a = kry.kry_footprint_transposed(small, 6, True, 1, 40, 1000, 120)
+    b = kry.kry_footprint_transposed(big, 6, True, 1, 40, 1000, 120)
+    # three vectors of the one run, plus the sliced-ELL copy (nnz = n here)
+    d = 1_000_000 - 10_000
+    assert 3 * 8 * d <= b - a <= 4 * 8 * d + 16 * d + (1 << 20)

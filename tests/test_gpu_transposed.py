@@ -165,8 +165,14 @@ def test_prepared_matrix_gives_the_same_basis():
     shared = kry.TransposedPlan(ds)
     b_shared = shared.basis()
     shared.close()
+    lib_ws = kry.TransposedPlan(ds, workspace=None)
+    b_lib = lib_ws.basis()
+    lib_ws.close()
     ds.close()
     assert np.array_equal(b_own, b_shared)
+    # the caller's workspace (sized by kry_footprint_transposed) and the
+    # library's give the same basis
+    assert np.array_equal(b_own, b_lib)
 
 
 def test_paper_heat_stencil_faces():
