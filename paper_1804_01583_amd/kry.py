@@ -523,7 +523,9 @@ class TransposedPlan(Plan):
     (Section 4.1).  ``dsys_t`` holds the transposed matrix (for a symmetric
     system, the system itself); generators, center, forcing and outputs are
     those of ``dsys_t.problem`` unless given.  A dense forcing or center is
-    handed to the library as index ranges."""
+    handed to the library as index ranges.  ``workspace``: 'torch' takes the
+    workspace (kry_footprint_transposed bytes) from torch's caching
+    allocator, 'library' lets the plan allocate its own."""
 
     def __init__(self, dsys_t: DeviceSystem, k=None, dt=None, steps=None, precision=KRY_FP64, method=KRY_AUTO,
                  stream=None, gens=None, C=None, workspace="torch"):
@@ -550,6 +552,8 @@ class TransposedPlan(Plan):
         self.workspace = None
         self.stream = torch.cuda.current_stream(dsys_t.device) if stream is None else stream
         ws_ptr, ws_bytes = None, 0
+        if workspace not in ("torch", "library"):
+            raise ValueError(f"workspace must be 'torch' or 'library', not {workspace!r}")
         if workspace == "torch":
             nseg = sum(g.seg.nseg for g in self._gens) + sum(c.nseg for c in self._C)
             nseg += (self._center.nseg if self._center is not None else 0)

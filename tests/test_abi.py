@@ -237,3 +237,4 @@ def test_transposed_footprint_is_host_only_and_scales_with_n():
     # three vectors of the one run, plus the sliced-ELL copy (nnz = n here)
     d = 1_000_000 - 10_000
     assert 3 * 8 * d <= b - a <= 4 * 8 * d + 16 * d + (1 << 20)
+

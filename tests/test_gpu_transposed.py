@@ -165,7 +165,7 @@ def test_prepared_matrix_gives_the_same_basis():
     shared = kry.TransposedPlan(ds)
     b_shared = shared.basis()
     shared.close()
-    lib_ws = kry.TransposedPlan(ds, workspace=None)
+    lib_ws = kry.TransposedPlan(ds, workspace="library")
     b_lib = lib_ws.basis()
     lib_ws.close()
     ds.close()
