@@ -563,7 +563,9 @@ kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_
         block_p = block_p > 0 ? block_p : std::min<int32_t>(nruns, kBW);
     }
     const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
-    const int32_t nsets = nruns + o + (sys->b_segs ? 1 : 0);
+    // one segment set per run (generators, forcing b) and per output row; a
+    // center run is counted too although its dense vector has none (an upper bound)
+    const int32_t nsets = nruns + o;
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
                                  march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method));
