@@ -176,7 +176,9 @@ typedef struct kry_plan kry_plan;
  *     0 = automatic); results do not depend on it.  For KRY_BLOCK_ARNOLDI
  *     the block width p (1..16; 0 = min(ngen, 16)).
  *  workspace: device buffer of workspace_bytes >= kry_footprint(...), or NULL
- *     to let the plan allocate (and free) its own.
+ *     to let the plan allocate (and free) its own.  A smaller one gives
+ *     KRY_ENOMEM (the message names the bytes needed), one not 256-byte
+ *     aligned KRY_EINVAL, both before any device work.
  *  hip_stream: hipStream_t to enqueue on (NULL = default stream).
  * The plan borrows sys->rowptr/colidx/vals/b and center until destroyed. */
 kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
@@ -206,7 +208,9 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
  *     give KRY_ENOTSUP.  dt, steps, precision, hip_stream: as for
  *     kry_plan_create.
  *  workspace: device buffer of workspace_bytes >= kry_footprint_transposed(...)
- *     (256-byte aligned), or NULL to let the plan allocate its own.
+ *     (256-byte aligned), or NULL to let the plan allocate its own.  A
+ *     smaller one gives KRY_ENOMEM (the message names the bytes needed), a
+ *     misaligned one KRY_EINVAL, both before any device work.
  * kry_project_expm and kry_check_box_safety then behave as for a forward
  * plan with columns in the order generators, center, forcing; kry_plan_runs
  * and kry_plan_krylov describe the o transposed runs (P has one row per
