@@ -378,6 +378,7 @@ class DeviceSystem:
         self.prepared = {}
         self._marshalled = None      # the problem's generators and outputs as kry_gen / kry_segs
         self._footprints = {}        # workspace bytes per plan shape
+        self._runs = {}              # index runs of the dense center / forcing (transposed plans)
 
     def prepare(self, precision=KRY_FP64, stream=None):
         """kry_matrix_create for this CSR system and precision, once: plans of
@@ -386,6 +387,15 @@ class DeviceSystem:
             sp = None if stream is None else stream.cuda_stream
             self.prepared[precision] = kry_matrix_create(self.sys, precision, sp)
         return self.prepared[precision]
+
+    def runs_of(self, name) -> "_Runs":
+        """The problem's dense vector ``name`` (center or b) as index runs,
+        converted once: like the uploaded vectors, it is read when the
+        system is made."""
+        r = self._runs.get(name)
+        if r is None:
+            r = self._runs[name] = _runs_of(getattr(self.problem, name))
+        return r
 
     def system_for(self, precision) -> KrySystem:
         """The kry_system a plan of `precision` gets (with its prepared matrix)."""
@@ -543,9 +553,9 @@ class TransposedPlan(Plan):
         keep = []
         self._gens = [KryGen(_segs(g.seg, keep), float(g.zc), float(g.radius)) for g in gens]
         self._C = [_segs(c, keep) for c in C]
-        self._center = _segs(_runs_of(p.center), keep) if p.center is not None else None
+        self._center = _segs(dsys_t.runs_of("center"), keep) if p.center is not None else None
         if p.b is not None:
-            self._bseg = _segs(_runs_of(p.b), keep)
+            self._bseg = _segs(dsys_t.runs_of("b"), keep)
             self._sys.b = None
             self._sys.b_segs = ct.pointer(self._bseg)
         self._keep = keep
