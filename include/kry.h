@@ -28,7 +28,8 @@
  * Conventions for every entry point:
  *  - Device pointers are caller-owned and borrowed until kry_plan_destroy.
  *    Host pointers are read during the call only.
- *  - All GPU work is enqueued on the caller's hipStream_t given to kry_plan.
+ *  - All GPU work is enqueued on the caller's hipStream_t given to kry_plan
+ *    (or kry_plan_create).
  *  - Every call returns a kry_status; no C++ exception crosses this ABI.  On
  *    a non-OK status, kry_last_error() returns a thread-local message.
  *  - Dimensions are 64-bit; vectors of n > 2^31 entries are supported.
@@ -142,10 +143,17 @@ typedef struct kry_verdict {
     double lo, hi;       /* reachable output range of that row at that step */
 } kry_verdict;
 
-typedef struct kry_plan kry_plan;
+/* The plan object.  Its type is kry_plan_t (struct kry_plan): the name
+ * kry_plan itself is the entry point that creates one. */
+typedef struct kry_plan kry_plan_t;
 
-/* kry_plan -- validate the problem, split E into simulation runs and prepare
- * the device state for them (Sections 2.1, 3.2, 4.1).
+/* Names of the boundary's sketch for the same structures: an output row is a
+ * segment set, an unsafe interval a kry_interval. */
+typedef kry_segs kry_row;
+typedef kry_interval kry_unsafe;
+
+/* kry_plan_create -- validate the problem, split E into simulation runs and
+ * prepare the device state for them (Sections 2.1, 3.2, 4.1).
  * Runs, in this order: one per generator [g_j; 0], one for the fixed center
  * [x_c; 0] when center != NULL (device n-vector), one for the augmented
  * variable [0; 1] when sys->b or sys->b_segs is given.
@@ -175,7 +183,7 @@ typedef struct kry_plan kry_plan;
  *  block_p: runs advanced together per sparse mat-vec launch (1, 2, 4 or 8;
  *     0 = automatic); results do not depend on it.  For KRY_BLOCK_ARNOLDI
  *     the block width p (1..16; 0 = min(ngen, 16)).
- *  workspace: device buffer of workspace_bytes >= kry_footprint(...), or NULL
+ *  workspace: device buffer of workspace_bytes >= kry_plan_workspace(...), or NULL
  *     to let the plan allocate (and free) its own.  A smaller one gives
  *     KRY_ENOMEM (the message names the bytes needed), one not 256-byte
  *     aligned KRY_EINVAL, both before any device work.
@@ -185,7 +193,14 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
                            const double* center, const kry_segs* C, int32_t o, int32_t k,
                            double dt, int64_t steps, int32_t precision, int32_t method,
                            int32_t block_p, void* workspace, size_t workspace_bytes,
-                           void* hip_stream, kry_plan** out);
+                           void* hip_stream, kry_plan_t** out);
+
+/* kry_plan -- the plan of kry_plan_create with a workspace the plan
+ * allocates and frees itself (Sections 2.1, 3.2, 4.1): every argument as
+ * there.  C holds o output rows; center is a device n-vector or NULL. */
+kry_status kry_plan(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
+                    const kry_row* C, int32_t o, int32_t k, double dt, int64_t steps, int32_t precision,
+                    int32_t method, int32_t block_p, void* hip_stream, kry_plan_t** out);
 
 /* kry_plan_create_transposed -- the same basis C e^{At} E by simulations of
  * the transposed dynamics (Section 4.1): C e^{At} E = (E^T e^{A^T t} C^T)^T,
@@ -220,7 +235,7 @@ kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* ge
                                       const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
                                       double dt, int64_t steps, int32_t precision, int32_t method,
                                       void* workspace, size_t workspace_bytes, void* hip_stream,
-                                      kry_plan** out);
+                                      kry_plan_t** out);
 
 /* kry_footprint_transposed -- device workspace bytes of a transposed plan:
  * ngen generators, has_center (0/1) a center row, o output rows (the runs),
@@ -238,7 +253,7 @@ kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32
  * runs of a forward plan), or NULL to keep the basis on the device for
  * kry_check_box_safety only.  With a host pointer the call waits for the
  * stream; otherwise it returns once the work is enqueued. */
-kry_status kry_project_expm(kry_plan* plan, double* basis_out);
+kry_status kry_project_expm(kry_plan_t* plan, double* basis_out);
 
 /* kry_check_box_safety -- per step s and output row r, the reachable output
  * range over the box is [mid - rad, mid + rad] with
@@ -249,7 +264,7 @@ kry_status kry_project_expm(kry_plan* plan, double* basis_out);
  * may be NULL): the box point z_j = zc_j + d*lam*sign(basis_j)*r_j whose output
  * is the nearest end of unsafe[r] (lam = 0 when mid is already inside).
  * Needs kry_project_expm first.  Waits for the stream. */
-kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out,
+kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kry_verdict* out,
                                 double* z_out);
 
 /* kry_plan_set_graph -- graph mode (on != 0): the next kry_project_expm
@@ -263,7 +278,7 @@ kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_
  * default one (KRY_EINVAL), and not while kernel timing is on (the capture
  * returns KRY_ENOTSUP).  on = 0 returns to per-kernel launches and frees
  * the graph. */
-kry_status kry_plan_set_graph(kry_plan* plan, int32_t on);
+kry_status kry_plan_set_graph(kry_plan_t* plan, int32_t on);
 
 /* kry_check_lp_safety -- the per-step LP of Section 2.1 for a polytopic
  * initial set and a conjunction of output halfspaces, on the basis of
@@ -288,22 +303,37 @@ kry_status kry_plan_set_graph(kry_plan* plan, int32_t on);
  *     undecided) or NULL.
  * The plan keeps a device buffer for the LP from the first call on.
  * Needs kry_project_expm first.  Waits for the stream. */
-kry_status kry_check_lp_safety(kry_plan* plan, const double* G, const double* h, int32_t mI, const double* U,
+kry_status kry_check_lp_safety(kry_plan_t* plan, const double* G, const double* h, int32_t mI, const double* U,
                                const double* u, int32_t mU, int64_t* first_step, int32_t* status, double* z_out,
                                double* y_out, int32_t* step_flags);
 
-/* kry_footprint -- device workspace bytes a plan with these sizes needs
+/* kry_plan_workspace -- device workspace bytes a plan with these sizes needs
  * (the Krylov vectors, per-block partial sums, H, P and the basis; Section 3.5
- * gives the method's own memory model, this adds the GPU's staging).
+ * gives the method's own memory model, this adds the GPU's staging): the
+ * exact size kry_plan_create asks of a caller's workspace.
  * nruns = generators + (center given) + (b given); nseg_total = segments of
- * all generators and output rows together. */
-kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
-                         int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
-                         size_t* bytes);
+ * all generators and output rows together.  Host only. */
+kry_status kry_plan_workspace(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
+                              int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
+                              size_t* bytes);
+
+/* kry_footprint -- the HBM a plan made by kry_plan with these sizes holds
+ * for its Krylov state (Section 3.5's memory model: n-vectors per run, or
+ * the stored basis; here also the per-block partial sums, a sliced-ELL copy
+ * of a CSR matrix that is not prepared, H and P), for method KRY_AUTO, one
+ * segment per generator and output row, and no time steps: a plan holds
+ * another 8 o runs bytes per time step for the basis and its check (plus the
+ * small stage's tables); kry_plan_workspace gives the exact total.  The
+ * runs are ngen generators plus the forcing when sys->b or sys->b_segs is
+ * given (count a center as one more generator).  block_p as for kry_plan.
+ * For admission of work by memory (the serving loop).  Host only;
+ * KRY_EINVAL for bad sizes. */
+kry_status kry_footprint(const kry_system* sys, int32_t ngen, int32_t o, int32_t k, int32_t precision,
+                         int32_t block_p, size_t* bytes);
 
 /* kry_plan_runs -- number of runs of a plan and their roles
  * (roles_out: nruns ints, 0 = generator, 1 = center, 2 = augmented; may be NULL). */
-kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out);
+kry_status kry_plan_runs(const kry_plan_t* plan, int32_t* nruns, int32_t* roles_out);
 
 /* kry_plan_block -- after kry_project_expm of a KRY_BLOCK_ARNOLDI plan, the
  * number of block runs (nblocks; generators b*p .. b*p + p - 1 form block b)
@@ -312,25 +342,27 @@ kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_ou
  * row-major block Hessenberg, H = V^T A V), R0 (p x p upper triangular with a
  * positive diagonal, G = V_1 R0 for the block's generators G) and
  * P = C V (o x p k_eff).  Any output pointer may be NULL. */
-kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
+kry_status kry_plan_block(const kry_plan_t* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
                           double* H, double* R0, double* P);
 /* kry_plan_krylov -- after kry_project_expm, copy one run's Krylov data to the
  * host: k_eff (Krylov dimension used; smaller than k after a breakdown),
  * beta0 = |start|, the run's Hessenberg matrix H (k_eff x k_eff row-major,
  * bordered for the augmented run), h_next = h_{k+1,k}, and P = C V
  * (o x k_eff row-major).  Any output pointer may be NULL.  Waits for the stream. */
-kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
+kry_status kry_plan_krylov(kry_plan_t* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
                            double* h_next, double* P);
 
 /* kry_plan_set_error_target -- choose each run's Krylov dimension a
  * posteriori (paper Section 4.2, Lemma 1; the checks of Algorithms 2 and 4).
  * With eps > 0, kry_project_expm evaluates after iteration j = 4, then
- * j <- ceil(1.1 j), the bound
- *     beta0 h_{j+1,j} e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
+ * j <- ceil(1.1 j) (1.1 j rounded to double, as the algorithms print it), the
+ * bound of the normalised process (the algorithms start from v / |v|, so eps
+ * is an error relative to |v|)
+ *     h_{j+1,j} e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
  * (tau = steps * dt; lambda a Gershgorin upper bound of the largest
  * eigenvalue of A, computed here, on the device for a CSR system; w = 1, or
  * tau - t for the augmented run, whose bordered matrix integrates the
- * approximation of e^{As} b) and ends a run at the first checkpoint where the
+ * approximation of e^{As} b / |b|) and ends a run at the first checkpoint where the
  * bound is below eps; a batch stops iterating once all its runs have ended.
  * k stays the cap (the augmented run: k - 1 Lanczos steps); k <= 2048.  The integral
  * uses a fixed composite 8-point Gauss-Legendre rule on [0, tau 2^-40] and on
@@ -338,16 +370,16 @@ kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* 
  * turns the control off (the default: every run uses k).  Lanczos plans
  * only (symmetric A; KRY_ENOTSUP otherwise).  Waits for the plan's stream
  * for a CSR system. */
-kry_status kry_plan_set_error_target(kry_plan* plan, double eps);
+kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps);
 /* kry_plan_error -- after kry_project_expm, run `run`'s Krylov dimension
  * (k_used: Lanczos steps used, the least of the breakdown dimension, the
  * error-control stop and k, or k - 1 for the augmented run) and
  * its last evaluated bound (-1 when none was evaluated, 0 after a breakdown,
  * which makes the projection exact).  Either pointer may be NULL; waits for
  * the plan's stream.  KRY_ENOTSUP for block plans. */
-kry_status kry_plan_error(kry_plan* plan, int32_t run, int32_t* k_used, double* bound);
+kry_status kry_plan_error(kry_plan_t* plan, int32_t run, int32_t* k_used, double* bound);
 
-void kry_plan_destroy(kry_plan* plan);
+void kry_plan_destroy(kry_plan_t* plan);
 
 /* kry_matrix_create -- device-side preparation of a KRY_CSR system that any
  * number of plans can share (every simulation of Section 4.1, one per

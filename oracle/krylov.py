@@ -130,37 +130,43 @@ def arnoldi(A, v, k, C, reorth=True, keep_V=False, opnorm=None) -> RunResult:
 
 
 def lanczos(A, v, k, C, opnorm=None) -> RunResult:
-    """Algorithm 3 (Lanczos) with the projection of Algorithm 4: the output
-    matrix P = C V is filled one column per iteration and only the last two
-    basis vectors are kept.  Fixed k (no a-posteriori error control)."""
+    """The symmetric Lanczos process of Section 4.3 (Algorithm 3) with the
+    on-the-fly projection of Algorithm 4, fixed k (no error control).
+
+    For symmetric A the Krylov basis obeys the three-term relation
+        A q_j = beta_{j-1} q_{j-1} + alpha_j q_j + beta_j q_{j+1},
+    with alpha_j = q_j^T A q_j and beta_j = |A q_j - alpha_j q_j - beta_{j-1} q_{j-1}|,
+    so only two basis vectors are live at a time; each new q_j is projected
+    on the output rows at once (P = C V, one column per step) and then
+    dropped.  alpha and beta are collected in their own arrays and T_k, the
+    symmetric tridiagonal matrix with diagonal alpha and off-diagonal beta,
+    is formed at the end.  A step whose beta is zero up to rounding (the
+    breakdown rule above) ends the process with an invariant Krylov space."""
     v = np.asarray(v, np.float64)
     beta0 = _norm(v)
     o = C.shape[0]
     if beta0 == 0.0:
         return RunResult(np.zeros((0, 0)), np.zeros((o, 0)), 0.0, 0.0, 0)
     opnorm = inf_norm(A) if opnorm is None else opnorm
-    H = np.zeros((k + 1, k))
-    P = np.zeros((o, k + 1))
-    v_prev = None
-    v_cur = v / beta0
-    P[:, 0] = C @ v_cur
-    k_eff = k
-    for i in range(1, k + 1):            # 0-based column i-1
-        w = A @ v_cur
-        if i > 1:
-            H[i - 2, i - 1] = H[i - 1, i - 2]
-            w = w - H[i - 2, i - 1] * v_prev
-        H[i - 1, i - 1] = _dot(v_cur, w)
-        w = w - H[i - 1, i - 1] * v_cur
-        eta = _norm(w)
-        H[i, i - 1] = eta
-        if _breaks_down(eta, opnorm):
-            k_eff = i
+    alpha, beta, cols = [], [], []
+    q_old = np.zeros_like(v)
+    q = v / beta0
+    for _ in range(k):
+        cols.append(np.asarray(C @ q).ravel())
+        r = A @ q
+        if beta:
+            r = r - beta[-1] * q_old
+        a = _dot(q, r)
+        r = r - a * q
+        b = _norm(r)
+        alpha.append(a)
+        beta.append(b)
+        if _breaks_down(b, opnorm):
             break
-        v_prev, v_cur = v_cur, w / eta
-        P[:, i] = C @ v_cur
-    return RunResult(H[:k_eff, :k_eff].copy(), P[:, :k_eff].copy(), beta0,
-                     float(H[k_eff, k_eff - 1]), k_eff)
+        q_old, q = q, r / b
+    m = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    return RunResult(T, np.stack(cols, axis=1), beta0, float(beta[-1]), m)
 
 
 # ---------------------------------------------------------------------------

@@ -9,8 +9,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -30,6 +32,44 @@ thread_local std::string g_err;
 kry_status fail(kry_status st, const std::string& msg) {
     g_err = msg;
     return st;
+}
+
+// Last resort of guarded(): record a fixed message without allocating.
+kry_status fail_quiet(kry_status st, const char* msg) noexcept {
+    try {
+        g_err = msg;
+    } catch (...) {
+    }
+    return st;
+}
+
+// No C++ exception crosses the C ABI: every entry point runs its body
+// through guarded(), which turns a failed host allocation into KRY_ENOMEM
+// and any other exception into KRY_EDEVICE, with the message kept for
+// kry_last_error().
+template <class F>
+kry_status guarded(const char* what, F&& body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail_quiet(KRY_ENOMEM, "host allocation failed");
+    } catch (const std::exception& e) {
+        try {
+            return fail(KRY_EDEVICE, std::string(what) + ": " + e.what());
+        } catch (...) {
+            return fail_quiet(KRY_EDEVICE, "unexpected exception");
+        }
+    } catch (...) {
+        return fail_quiet(KRY_EDEVICE, "unexpected exception");
+    }
+}
+
+template <class F>
+void guarded_void(F&& body) noexcept {
+    try {
+        body();
+    } catch (...) {
+    }
 }
 
 #define KRY_HIP(expr)                                                                          \
@@ -546,62 +586,79 @@ extern "C" {
 
 const char* kry_last_error(void) { return g_err.c_str(); }
 
-kry_status kry_footprint(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
-                         int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
-                         size_t* bytes) {
-    kry_status st = validate_system(sys);
-    if (st != KRY_OK) return st;
-    if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
-    if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : (method == KRY_LANCZOS_PLAIN ? kMaxKP : kMaxKD);
-    if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kmax || steps < 0 || nseg_total < 0)
-        return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 512 (32 block steps), steps >= 0, "
-                                "nseg_total >= 0 required");
-    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
-    if (method == KRY_BLOCK_ARNOLDI) {
-        if (block_p < 0 || block_p > kBW) return fail(KRY_EINVAL, "block Arnoldi: block_p must be <= 16");
-        block_p = block_p > 0 ? block_p : std::min<int32_t>(nruns, kBW);
-    }
-    const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
-    // one segment set per run (generators, forcing b) and per output row; a
-    // center run is counted too although its dense vector has none (an upper bound)
-    const int32_t nsets = nruns + o;
-    const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
-    const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
-                                 march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method));
-    *bytes = Y.total;
-    return KRY_OK;
+kry_status kry_plan_workspace(const kry_system* sys, int32_t nruns, int32_t o, int32_t k, int64_t steps,
+                              int64_t nseg_total, int32_t precision, int32_t method, int32_t block_p,
+                              size_t* bytes) {
+    return guarded("kry_plan_workspace", [&]() -> kry_status {
+        kry_status st = validate_system(sys);
+        if (st != KRY_OK) return st;
+        if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
+        if (method == KRY_AUTO) method = sys->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+        const int kmax = method == KRY_BLOCK_ARNOLDI ? kMaxKB : (method == KRY_LANCZOS_PLAIN ? kMaxKP : kMaxKD);
+        if (nruns < 1 || o < 1 || o > kMaxO || k < 1 || k > kmax || steps < 0 || nseg_total < 0)
+            return fail(KRY_EINVAL, "nruns >= 1, 1 <= o <= 8, 1 <= k <= 512 (32 block steps), steps >= 0, "
+                                    "nseg_total >= 0 required");
+        if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+        if (method == KRY_BLOCK_ARNOLDI) {
+            if (block_p < 0 || block_p > kBW) return fail(KRY_EINVAL, "block Arnoldi: block_p must be <= 16");
+            block_p = block_p > 0 ? block_p : std::min<int32_t>(nruns, kBW);
+        }
+        const int32_t nb = nblocks_for(sys->n, rows_per_block_for(sys->n));
+        // one segment set per run (generators, forcing b) and per output row; a
+        // center run is counted too although its dense vector has none (an upper bound)
+        const int32_t nsets = nruns + o;
+        const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
+        const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
+                                     march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method));
+        *bytes = Y.total;
+        return KRY_OK;
+    });
+}
+
+kry_status kry_footprint(const kry_system* sys, int32_t ngen, int32_t o, int32_t k, int32_t precision,
+                         int32_t block_p, size_t* bytes) {
+    return guarded("kry_footprint", [&]() -> kry_status {
+        kry_status st = validate_system(sys);
+        if (st != KRY_OK) return st;
+        if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
+        if (ngen < 0) return fail(KRY_EINVAL, "ngen must be >= 0");
+        const int32_t nruns = ngen + ((sys->b || sys->b_segs) ? 1 : 0);
+        const int64_t nseg = (int64_t)nruns + o + (sys->b_segs ? sys->b_segs->nseg : 0);
+        return kry_plan_workspace(sys, nruns, o, k, 0, nseg, precision, KRY_AUTO, block_p, bytes);
+    });
 }
 
 kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32_t has_center, int32_t o,
                                     int32_t k, int64_t steps, int64_t nseg_total, int32_t precision,
                                     int32_t method, size_t* bytes) {
-    kry_status st = validate_system(sys_t);
-    if (st != KRY_OK) return st;
-    if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
-    if (sys_t->b) return fail(KRY_ENOTSUP, "the transposed route takes the forcing as b_segs (a projection row)");
-    if (method == KRY_AUTO) method = sys_t->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
-    if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
-        return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
-    const bool has_b = sys_t->b_segs != nullptr;
-    const int32_t nproj = ngen + (has_center ? 1 : 0) + (has_b ? 1 : 0);
-    if (ngen < 0 || nproj < 1 || nproj > kMaxO || o < 1 || o > kMaxO || k < 1 ||
-        k > (has_b ? kMaxK - 1 : kMaxK) || steps < 0 || nseg_total < 0)
-        return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows, 1 <= o <= 8, k in [1, 56] "
-                                "([1, 55] with forcing), steps >= 0, nseg_total >= 0 required");
-    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
-    // the shapes kry_plan_create_transposed lays out: o runs projected on
-    // nproj rows, one job per run plus one per run for the forcing column
-    const int32_t njobs = o * (has_b ? 2 : 1);
-    const int32_t nsets = ngen + o + (has_b ? 1 : 0) + (has_center ? 1 : 0);
-    const int32_t nb = nblocks_for(sys_t->n, rows_per_block_for(sys_t->n));
-    const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys_t->kind == KRY_CSR) ? sys_t->nnz : 0;
-    const Layout Y = make_layout(sys_t->n, o, nproj, k, steps, 0,
-                                 meta_size(nseg_total, nsets, std::max(njobs, nproj), nb, njobs), method,
-                                 march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method), njobs,
-                                 nproj, o);
-    *bytes = Y.total;
-    return KRY_OK;
+    return guarded("kry_footprint_transposed", [&]() -> kry_status {
+        kry_status st = validate_system(sys_t);
+        if (st != KRY_OK) return st;
+        if (!bytes) return fail(KRY_EINVAL, "bytes is NULL");
+        if (sys_t->b) return fail(KRY_ENOTSUP, "the transposed route takes the forcing as b_segs (a projection row)");
+        if (method == KRY_AUTO) method = sys_t->symmetric ? KRY_LANCZOS : KRY_ARNOLDI;
+        if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
+            return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
+        const bool has_b = sys_t->b_segs != nullptr;
+        const int32_t nproj = ngen + (has_center ? 1 : 0) + (has_b ? 1 : 0);
+        if (ngen < 0 || nproj < 1 || nproj > kMaxO || o < 1 || o > kMaxO || k < 1 ||
+            k > (has_b ? kMaxK - 1 : kMaxK) || steps < 0 || nseg_total < 0)
+            return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows, 1 <= o <= 8, k in [1, 56] "
+                                    "([1, 55] with forcing), steps >= 0, nseg_total >= 0 required");
+        if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+        // the shapes kry_plan_create_transposed lays out: o runs projected on
+        // nproj rows, one job per run plus one per run for the forcing column
+        const int32_t njobs = o * (has_b ? 2 : 1);
+        const int32_t nsets = ngen + o + (has_b ? 1 : 0) + (has_center ? 1 : 0);
+        const int32_t nb = nblocks_for(sys_t->n, rows_per_block_for(sys_t->n));
+        const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys_t->kind == KRY_CSR) ? sys_t->nnz : 0;
+        const Layout Y = make_layout(sys_t->n, o, nproj, k, steps, 0,
+                                     meta_size(nseg_total, nsets, std::max(njobs, nproj), nb, njobs), method,
+                                     march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method), njobs,
+                                     nproj, o);
+        *bytes = Y.total;
+        return KRY_OK;
+    });
 }
 
 }  // extern "C"
@@ -616,7 +673,7 @@ namespace {
 kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
                        const kry_segs* center_t, bool transposed, const kry_segs* C, int32_t o, int32_t k,
                        double dt, int64_t steps, int32_t precision, int32_t method, int32_t block_p,
-                       void* workspace, size_t workspace_bytes, void* hip_stream, kry_plan** out) {
+                       void* workspace, size_t workspace_bytes, void* hip_stream, kry_plan_t** out) {
     if (!out) return fail(KRY_EINVAL, "out is NULL");
     *out = nullptr;
     kry_status st = validate_system(sys);
@@ -684,7 +741,15 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
 
     st = prepare_device();
     if (st != KRY_OK) return st;
-    auto* plan = new kry_plan();
+    auto* plan = new kry_plan_t();
+    // the plan is destroyed on every early return and on an exception
+    // (guarded() catches it at the entry point); released on success
+    struct PlanGuard {
+        kry_plan_t* p;
+        ~PlanGuard() {
+            if (p) kry_plan_destroy(p);
+        }
+    } guard{plan};
     plan->sys = *sys;
     plan->ngen = ngen;
     plan->k = k;
@@ -704,7 +769,6 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     plan->ncols = (int32_t)plan->col_role.size();
     plan->o_out = o;
     if (plan->ncols == 0) {
-        delete plan;
         return fail(KRY_EINVAL, "nothing to simulate: no generator, center or forcing");
     }
     if (transposed) {
@@ -743,7 +807,7 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     for (int32_t q = 0; q < o; ++q) total_segs += C[q].nseg;
     if (sys->b_segs) total_segs += sys->b_segs->nseg;
     if (center_t) total_segs += center_t->nseg;
-    if (total_segs >= ((int64_t)1 << 31)) { delete plan; return fail(KRY_EINVAL, "too many segments"); }
+    if (total_segs >= ((int64_t)1 << 31)) return fail(KRY_EINVAL, "too many segments");
     const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0) + (center_t ? 1 : 0);
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
@@ -760,18 +824,15 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
 
     if (workspace) {
         if (workspace_bytes < Y.total) {
-            delete plan;
             return fail(KRY_ENOMEM, "workspace too small: need " + std::to_string(Y.total) + " bytes");
         }
         if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) {
-            delete plan;
             return fail(KRY_EINVAL, "workspace must be 256-byte aligned");
         }
         plan->ws = static_cast<char*>(workspace);
     } else {
         void* p = nullptr;
         if (hipMalloc(&p, Y.total) != hipSuccess) {
-            delete plan;
             return fail(KRY_ENOMEM, "hipMalloc of " + std::to_string(Y.total) + " bytes failed");
         }
         plan->ws = static_cast<char*>(p);
@@ -846,9 +907,8 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
         plan->out_col_dev = reinterpret_cast<int32_t*>(dmeta + ((char*)oc - base));
     }
 
-    auto cleanup = [&](kry_status s) { kry_plan_destroy(plan); return s; };
     if (hipMemcpyAsync(dmeta, base, mbytes, hipMemcpyHostToDevice, plan->stream) != hipSuccess)
-        return cleanup(fail(KRY_EDEVICE, "metadata upload failed"));
+        return fail(KRY_EDEVICE, "metadata upload failed");
 
     // ||A||_inf scales the breakdown test
     plan->anorm_dev = plan->anorm();
@@ -859,15 +919,15 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
         plan->verdict_host.assign(1, a);
         if (hipMemcpyAsync(plan->anorm(), plan->verdict_host.data(), sizeof(double), hipMemcpyHostToDevice,
                            plan->stream) != hipSuccess)
-            return cleanup(fail(KRY_EDEVICE, "anorm upload failed"));
+            return fail(KRY_EDEVICE, "anorm upload failed");
         if (hipStreamSynchronize(plan->stream) != hipSuccess)
-            return cleanup(fail(KRY_EDEVICE, "stream sync failed"));
+            return fail(KRY_EDEVICE, "stream sync failed");
     } else {
         CsrArgs A{sys->rowptr, sys->colidx, sys->vals};
         hipError_t e = timed("row_abs_max", plan->stream, [&] {
             return launch_row_abs_max(A, n, plan->np_part(), Y.nblocks, Y.rpb, plan->anorm(), plan->stream);
         });
-        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e)));
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("row_abs_max: ") + hipGetErrorString(e));
     }
     // FP32-basis mode reads an FP32 copy of the CSR values
     if (Y.scap > 0) {
@@ -876,21 +936,21 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
             return launch_sell_layout(A, n, plan->at<int32_t>(Y.swidth), plan->at<int64_t>(Y.soff),
                                       plan->at<int64_t>(Y.stiles), plan->stream);
         });
-        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell layout: ") + hipGetErrorString(e)));
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sell layout: ") + hipGetErrorString(e));
         int64_t total = 0, nwide = 0;
         if (hipMemcpyAsync(&total, plan->at<int64_t>(Y.soff) + sell_slices(n), sizeof(total), hipMemcpyDeviceToHost,
                            plan->stream) != hipSuccess ||
             hipMemcpyAsync(&nwide, plan->at<int64_t>(Y.stiles) + sell_scan_tiles(n), sizeof(nwide),
                            hipMemcpyDeviceToHost, plan->stream) != hipSuccess ||
             hipStreamSynchronize(plan->stream) != hipSuccess)
-            return cleanup(fail(KRY_EDEVICE, "sell layout readback failed"));
+            return fail(KRY_EDEVICE, "sell layout readback failed");
         if (total <= Y.scap) {
             const bool narrow = nwide == 0 && env_int("KRY_SELL_NARROW", 1) != 0;
             e = timed("sell_build", plan->stream, [&] {
                 return launch_sell_fill(plan->f32, narrow, A, n, plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
                                         plan->ws + Y.scol, plan->ws + Y.sval, plan->stream);
             });
-            if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("sell fill: ") + hipGetErrorString(e)));
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sell fill: ") + hipGetErrorString(e));
             plan->use_sell = true;
             plan->sell = SellArgs{plan->at<int64_t>(Y.soff), plan->at<int32_t>(Y.swidth),
                                   narrow ? nullptr : plan->at<int32_t>(Y.scol),
@@ -905,13 +965,14 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     }
     if (Y.vals32 && !plan->use_sell) {
         hipError_t e = launch_to_f32(sys->vals, plan->vals32(), sys->nnz, plan->stream);
-        if (e != hipSuccess) return cleanup(fail(KRY_EDEVICE, std::string("to_f32: ") + hipGetErrorString(e)));
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("to_f32: ") + hipGetErrorString(e));
     }
     const double avg = sys->kind == KRY_CSR ? (double)sys->nnz / (double)n : 7.0;
     int lpr = env_int("KRY_LPR", 0);
     if (lpr != 1 && lpr != 2 && lpr != 4 && lpr != 8) lpr = avg > 24 ? 8 : (avg > 12 ? 4 : 1);
     plan->lpr = lpr;
     plan->sys.b_segs = nullptr;    // copied into the segment table; not kept
+    guard.p = nullptr;
     *out = plan;
     return KRY_OK;
 }
@@ -924,26 +985,39 @@ kry_status kry_plan_create(const kry_system* sys, const kry_gen* gens, int32_t n
                            const double* center, const kry_segs* C, int32_t o, int32_t k,
                            double dt, int64_t steps, int32_t precision, int32_t method,
                            int32_t block_p, void* workspace, size_t workspace_bytes,
-                           void* hip_stream, kry_plan** out) {
-    return plan_create(sys, gens, ngen, center, nullptr, false, C, o, k, dt, steps, precision, method, block_p,
-                       workspace, workspace_bytes, hip_stream, out);
+                           void* hip_stream, kry_plan_t** out) {
+    return guarded("kry_plan_create", [&]() -> kry_status {
+        return plan_create(sys, gens, ngen, center, nullptr, false, C, o, k, dt, steps, precision, method, block_p,
+                           workspace, workspace_bytes, hip_stream, out);
+    });
+}
+
+kry_status kry_plan(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
+                    const kry_row* C, int32_t o, int32_t k, double dt, int64_t steps, int32_t precision,
+                    int32_t method, int32_t block_p, void* hip_stream, kry_plan_t** out) {
+    return guarded("kry_plan", [&]() -> kry_status {
+        return plan_create(sys, gens, ngen, center, nullptr, false, C, o, k, dt, steps, precision, method, block_p,
+                           nullptr, 0, hip_stream, out);
+    });
 }
 
 kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* gens, int32_t ngen,
                                       const kry_segs* center, const kry_segs* C, int32_t o, int32_t k,
                                       double dt, int64_t steps, int32_t precision, int32_t method,
                                       void* workspace, size_t workspace_bytes, void* hip_stream,
-                                      kry_plan** out) {
-    if (out) *out = nullptr;
-    if (!out) return fail(KRY_EINVAL, "out is NULL");
-    return plan_create(sys_t, gens, ngen, nullptr, center, true, C, o, k, dt, steps, precision, method, 0,
-                       workspace, workspace_bytes, hip_stream, out);
+                                      kry_plan_t** out) {
+    return guarded("kry_plan_create_transposed", [&]() -> kry_status {
+        if (out) *out = nullptr;
+        if (!out) return fail(KRY_EINVAL, "out is NULL");
+        return plan_create(sys_t, gens, ngen, nullptr, center, true, C, o, k, dt, steps, precision, method, 0,
+                           workspace, workspace_bytes, hip_stream, out);
+    });
 }
 
 namespace {
 
 // Marks the basis as formed and copies it out (waits when the target is host memory).
-kry_status finish_projection(kry_plan* plan, double* basis_out) {
+kry_status finish_projection(kry_plan_t* plan, double* basis_out) {
     plan->projected = true;
     if (basis_out) {
         hipStream_t s = plan->stream;
@@ -962,7 +1036,7 @@ kry_status finish_projection(kry_plan* plan, double* basis_out) {
 
 // Block Arnoldi for the generator columns, bw at a time (the block form of
 // Algorithm 1 with CGS2 and CholQR2), then the dense stage for each block run.
-kry_status project_block(kry_plan* plan) {
+kry_status project_block(kry_plan_t* plan) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
@@ -1064,7 +1138,7 @@ kry_status project_block(kry_plan* plan) {
         e = timed("dense_expm", s, [&] { return dense_expm_steps(J, plan->at<double>(Y.bdense), &hn, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("dense stage: ") + hipGetErrorString(e));
         // keep H, R0 and P of this block run for kry_plan_block
-        kry_plan::BlockInfo bi;
+        kry_plan_t::BlockInfo bi;
         bi.k_eff = keff;
         bi.p = p;
         std::vector<double> Hfull((size_t)m * m_max), Pfull((size_t)o * B.ldp), R0(256);
@@ -1100,7 +1174,7 @@ namespace {
 // Everything kry_project_expm enqueues for the single-vector methods: the
 // Krylov batches, the small stage and the assembly (and, with finish, the
 // copy of the basis).
-kry_status enqueue_projection(kry_plan* plan, double* basis_out, bool finish) {
+kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
@@ -1204,13 +1278,14 @@ kry_status enqueue_projection(kry_plan* plan, double* basis_out, bool finish) {
                     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
                 }
             }
-            // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k).
+            // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k)
+            // with 1.1 k a double product, as printed (170 is followed by 188).
             // Once every run of the batch met the target, the kernels of the
             // iterations already queued return at once (B.stop); the host
             // stops queueing when a non-blocking look at the flags of an
             // earlier checkpoint finds them all set.
             if (plan->err_eps > 0.0 && j == next_check) {
-                next_check = (11 * next_check + 9) / 10;
+                next_check = (int)std::ceil(1.1 * (double)next_check);
                 e = timed("errctl", s, [&] { return launch_record_stage(P, B, j, s); });
                 if (e == hipSuccess) e = timed("errctl", s, [&] { return launch_lemma1(P, B, X, j, s); });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("error control: ") + hipGetErrorString(e));
@@ -1298,440 +1373,472 @@ kry_status enqueue_projection(kry_plan* plan, double* basis_out, bool finish) {
 
 extern "C" {
 
-kry_status kry_project_expm(kry_plan* plan, double* basis_out) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (plan->method == KRY_BLOCK_ARNOLDI) {
-        kry_status st = project_block(plan);
-        if (st != KRY_OK) return st;
-        return finish_projection(plan, basis_out);
-    }
-    if (plan->graph_on) {
-        // first call: record the whole projection as one graph; then replay it
-        if (!plan->graph_exec) {
-            if (prof().on) return fail(KRY_ENOTSUP, "kernel timing and graph capture exclude each other");
-            KRY_HIP(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
-            const kry_status st = enqueue_projection(plan, nullptr, false);
-            hipGraph_t g = nullptr;
-            const hipError_t ec = hipStreamEndCapture(plan->stream, &g);
-            if (st != KRY_OK || ec != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                if (st != KRY_OK) return st;
-                return fail(KRY_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
-            }
-            hipGraphExec_t x = nullptr;
-            const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            if (ei != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return fail(KRY_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
-            }
-            plan->graph = g;
-            plan->graph_exec = x;
+kry_status kry_project_expm(kry_plan_t* plan, double* basis_out) {
+    return guarded("kry_project_expm", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (plan->method == KRY_BLOCK_ARNOLDI) {
+            kry_status st = project_block(plan);
+            if (st != KRY_OK) return st;
+            return finish_projection(plan, basis_out);
         }
-        KRY_HIP(hipGraphLaunch(plan->graph_exec, plan->stream));
-        return finish_projection(plan, basis_out);
-    }
-    return enqueue_projection(plan, basis_out, true);
+        if (plan->graph_on) {
+            // first call: record the whole projection as one graph; then replay it
+            if (!plan->graph_exec) {
+                if (prof().on) return fail(KRY_ENOTSUP, "kernel timing and graph capture exclude each other");
+                KRY_HIP(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
+                const kry_status st = enqueue_projection(plan, nullptr, false);
+                hipGraph_t g = nullptr;
+                const hipError_t ec = hipStreamEndCapture(plan->stream, &g);
+                if (st != KRY_OK || ec != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    if (st != KRY_OK) return st;
+                    return fail(KRY_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+                }
+                hipGraphExec_t x = nullptr;
+                const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+                if (ei != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    return fail(KRY_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+                }
+                plan->graph = g;
+                plan->graph_exec = x;
+            }
+            KRY_HIP(hipGraphLaunch(plan->graph_exec, plan->stream));
+            return finish_projection(plan, basis_out);
+        }
+        return enqueue_projection(plan, basis_out, true);
+    });
 }
 
-kry_status kry_check_box_safety(kry_plan* plan, const kry_interval* unsafe, kry_verdict* out, double* z_out) {
-    if (!plan || !unsafe || !out) return fail(KRY_EINVAL, "plan, unsafe and out must be non-NULL");
-    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
-    CheckArgs C{};
-    C.basis = plan->basis();
-    C.zc = plan->zc_dev;
-    C.radius = plan->rad_dev;
-    C.nruns = plan->ncols;
-    C.o = plan->o_out;
-    C.steps = plan->steps;
-    for (int q = 0; q < plan->o_out; ++q) {
-        if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
-        C.ulo[q] = unsafe[q].lo;
-        C.uhi[q] = unsafe[q].hi;
-    }
-    C.part = plan->cpart();
-    C.verdict = plan->verdict();
-    hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
-    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
-    plan->verdict_host.assign(6 + plan->ncols, 0.0);
-    KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, plan->stream));
-    KRY_HIP(hipStreamSynchronize(plan->stream));
-    const double* v = plan->verdict_host.data();
-    out->first_step = (int64_t)v[0];
-    out->row = (int32_t)v[1];
-    out->y = v[2];
-    out->lo = v[3];
-    out->hi = v[4];
-    out->status = (int32_t)v[5];
-    if (plan->nonfinite) out->status = KRY_ENUMERIC;
-    if (z_out) {
-        int32_t g = 0;
-        for (int32_t c = 0; c < plan->ncols; ++c)
-            if (plan->col_role[c] == 0) z_out[g++] = v[6 + c];
-    }
-    return KRY_OK;
+kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kry_verdict* out, double* z_out) {
+    return guarded("kry_check_box_safety", [&]() -> kry_status {
+        if (!plan || !unsafe || !out) return fail(KRY_EINVAL, "plan, unsafe and out must be non-NULL");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        CheckArgs C{};
+        C.basis = plan->basis();
+        C.zc = plan->zc_dev;
+        C.radius = plan->rad_dev;
+        C.nruns = plan->ncols;
+        C.o = plan->o_out;
+        C.steps = plan->steps;
+        for (int q = 0; q < plan->o_out; ++q) {
+            if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
+            C.ulo[q] = unsafe[q].lo;
+            C.uhi[q] = unsafe[q].hi;
+        }
+        C.part = plan->cpart();
+        C.verdict = plan->verdict();
+        hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
+        plan->verdict_host.assign(6 + plan->ncols, 0.0);
+        KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, plan->stream));
+        KRY_HIP(hipStreamSynchronize(plan->stream));
+        const double* v = plan->verdict_host.data();
+        out->first_step = (int64_t)v[0];
+        out->row = (int32_t)v[1];
+        out->y = v[2];
+        out->lo = v[3];
+        out->hi = v[4];
+        out->status = (int32_t)v[5];
+        if (plan->nonfinite) out->status = KRY_ENUMERIC;
+        if (z_out) {
+            int32_t g = 0;
+            for (int32_t c = 0; c < plan->ncols; ++c)
+                if (plan->col_role[c] == 0) z_out[g++] = v[6 + c];
+        }
+        return KRY_OK;
+    });
 }
 
-kry_status kry_check_lp_safety(kry_plan* plan, const double* G, const double* h, int32_t mI, const double* U,
+kry_status kry_check_lp_safety(kry_plan_t* plan, const double* G, const double* h, int32_t mI, const double* U,
                                const double* u, int32_t mU, int64_t* first_step, int32_t* status, double* z_out,
                                double* y_out, int32_t* step_flags) {
-    if (!plan || !first_step || !status) return fail(KRY_EINVAL, "plan, first_step and status must be non-NULL");
-    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
-    const int32_t d = plan->ngen, o = plan->o_out;
-    if (d > kLpMaxD) return fail(KRY_ENOTSUP, "the per-step LP holds at most 16 generators");
-    if (mI < 0 || mU < 0 || d + mI + mU > kLpMaxRows)
-        return fail(KRY_EINVAL, "need mI, mU >= 0 and generators + mI + mU <= 64 rows");
-    if ((mI > 0 && (!G || !h)) || (mU > 0 && (!U || !u))) return fail(KRY_EINVAL, "G, h, U, u must be non-NULL");
-    auto finite = [](const double* a, int64_t cnt) {
-        for (int64_t i = 0; i < cnt; ++i)
-            if (!std::isfinite(a[i])) return false;
-        return true;
-    };
-    if (!finite(G, (int64_t)mI * d) || !finite(h, mI) || !finite(U, (int64_t)mU * o) || !finite(u, mU))
-        return fail(KRY_EINVAL, "LP constraints must be finite");
-    hipStream_t s = plan->stream;
-    const int64_t nin = 2 * kLpMaxD + (int64_t)kLpMaxRows * kLpMaxD + kLpMaxRows + (int64_t)kLpMaxRows * kMaxO +
-                        kLpMaxRows;
-    const int64_t nrec = (plan->steps + 1) * kLpRec;
-    const int64_t nver = 2 + kLpMaxD + kMaxO;
-    if (!plan->lp_mem) {
-        void* p = nullptr;
-        if (hipMalloc(&p, (size_t)(nin + nrec + nver) * sizeof(double)) != hipSuccess)
-            return fail(KRY_ENOMEM, "LP buffers: hipMalloc failed");
-        plan->lp_mem = static_cast<char*>(p);
-    }
-    double* dev = reinterpret_cast<double*>(plan->lp_mem);
-    // inputs: zlo, zhi, G, h, U, u
-    std::vector<double>& H = plan->lp_host;
-    H.assign((size_t)nin, 0.0);
-    for (int32_t j = 0; j < d; ++j) {
-        H[j] = plan->zc[j] - plan->radius[j];
-        H[kLpMaxD + j] = plan->zc[j] + plan->radius[j];
-    }
-    double* hG = H.data() + 2 * kLpMaxD;
-    double* hh = hG + (int64_t)kLpMaxRows * kLpMaxD;
-    double* hU = hh + kLpMaxRows;
-    double* hu = hU + (int64_t)kLpMaxRows * kMaxO;
-    if (mI > 0) { std::copy(G, G + (int64_t)mI * d, hG); std::copy(h, h + mI, hh); }
-    if (mU > 0) { std::copy(U, U + (int64_t)mU * o, hU); std::copy(u, u + mU, hu); }
-    KRY_HIP(hipMemcpyAsync(dev, H.data(), (size_t)nin * sizeof(double), hipMemcpyHostToDevice, s));
-    LpArgs L{};
-    L.basis = plan->basis();
-    L.o = o;
-    L.ncols = plan->ncols;
-    L.d = d;
-    L.mI = mI;
-    L.mU = mU;
-    L.steps = plan->steps;
-    L.zlo = dev;
-    L.zhi = dev + kLpMaxD;
-    L.G = dev + (hG - H.data());
-    L.h = dev + (hh - H.data());
-    L.U = dev + (hU - H.data());
-    L.u = dev + (hu - H.data());
-    L.tol = 1e-6;      // the LP tolerance of Section 4.2, on rows scaled to a largest coefficient of 1
-    L.max_pivots = 20 * (d + mI + mU + 2) + 100;
-    L.rec = dev + nin;
-    L.verdict = dev + nin + nrec;
-    hipError_t e = timed("lp", s, [&] { return launch_lp(L, s); });
-    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("lp: ") + hipGetErrorString(e));
-    double v[2 + kLpMaxD + kMaxO];
-    KRY_HIP(hipMemcpyAsync(v, L.verdict, sizeof(v), hipMemcpyDeviceToHost, s));
-    std::vector<double> rec;
-    if (step_flags) {
-        rec.resize((size_t)nrec);
-        KRY_HIP(hipMemcpyAsync(rec.data(), L.rec, (size_t)nrec * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    KRY_HIP(hipStreamSynchronize(s));
-    *first_step = (int64_t)v[0];
-    *status = (int32_t)v[1];
-    if (z_out) std::copy(v + 2, v + 2 + d, z_out);
-    if (y_out) std::copy(v + 2 + kLpMaxD, v + 2 + kLpMaxD + o, y_out);
-    if (step_flags)
-        for (int64_t st = 0; st <= plan->steps; ++st) step_flags[st] = (int32_t)rec[(size_t)st * kLpRec];
-    return KRY_OK;
-}
-
-kry_status kry_plan_set_graph(kry_plan* plan, int32_t on) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (on) {
-        if (plan->method == KRY_BLOCK_ARNOLDI)
-            return fail(KRY_ENOTSUP, "graph mode covers the single-vector methods (block runs read sizes back)");
-        if (plan->Y.dense_runs)
-            return fail(KRY_ENOTSUP, "graph mode covers k <= 56 (the dense stage reads sizes back)");
-        if (plan->err_eps > 0.0)
-            return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
-        if (plan->stream == nullptr) return fail(KRY_EINVAL, "graph capture needs a stream other than the default one");
-    }
-    plan->graph_on = on != 0;
-    if (!plan->graph_on) {
-        if (plan->graph_exec) {
-            KRY_HIP(hipStreamSynchronize(plan->stream));
-            (void)hipGraphExecDestroy(plan->graph_exec);
-            plan->graph_exec = nullptr;
+    return guarded("kry_check_lp_safety", [&]() -> kry_status {
+        if (!plan || !first_step || !status) return fail(KRY_EINVAL, "plan, first_step and status must be non-NULL");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        const int32_t d = plan->ngen, o = plan->o_out;
+        if (d > kLpMaxD) return fail(KRY_ENOTSUP, "the per-step LP holds at most 16 generators");
+        if (mI < 0 || mU < 0 || d + mI + mU > kLpMaxRows)
+            return fail(KRY_EINVAL, "need mI, mU >= 0 and generators + mI + mU <= 64 rows");
+        if ((mI > 0 && (!G || !h)) || (mU > 0 && (!U || !u))) return fail(KRY_EINVAL, "G, h, U, u must be non-NULL");
+        auto finite = [](const double* a, int64_t cnt) {
+            for (int64_t i = 0; i < cnt; ++i)
+                if (!std::isfinite(a[i])) return false;
+            return true;
+        };
+        if (!finite(G, (int64_t)mI * d) || !finite(h, mI) || !finite(U, (int64_t)mU * o) || !finite(u, mU))
+            return fail(KRY_EINVAL, "LP constraints must be finite");
+        hipStream_t s = plan->stream;
+        const int64_t nin = 2 * kLpMaxD + (int64_t)kLpMaxRows * kLpMaxD + kLpMaxRows + (int64_t)kLpMaxRows * kMaxO +
+                            kLpMaxRows;
+        const int64_t nrec = (plan->steps + 1) * kLpRec;
+        const int64_t nver = 2 + kLpMaxD + kMaxO;
+        if (!plan->lp_mem) {
+            void* p = nullptr;
+            if (hipMalloc(&p, (size_t)(nin + nrec + nver) * sizeof(double)) != hipSuccess)
+                return fail(KRY_ENOMEM, "LP buffers: hipMalloc failed");
+            plan->lp_mem = static_cast<char*>(p);
         }
-        if (plan->graph) {
-            (void)hipGraphDestroy(plan->graph);
-            plan->graph = nullptr;
+        double* dev = reinterpret_cast<double*>(plan->lp_mem);
+        // inputs: zlo, zhi, G, h, U, u
+        std::vector<double>& H = plan->lp_host;
+        H.assign((size_t)nin, 0.0);
+        for (int32_t j = 0; j < d; ++j) {
+            H[j] = plan->zc[j] - plan->radius[j];
+            H[kLpMaxD + j] = plan->zc[j] + plan->radius[j];
         }
-    }
-    return KRY_OK;
+        double* hG = H.data() + 2 * kLpMaxD;
+        double* hh = hG + (int64_t)kLpMaxRows * kLpMaxD;
+        double* hU = hh + kLpMaxRows;
+        double* hu = hU + (int64_t)kLpMaxRows * kMaxO;
+        if (mI > 0) { std::copy(G, G + (int64_t)mI * d, hG); std::copy(h, h + mI, hh); }
+        if (mU > 0) { std::copy(U, U + (int64_t)mU * o, hU); std::copy(u, u + mU, hu); }
+        KRY_HIP(hipMemcpyAsync(dev, H.data(), (size_t)nin * sizeof(double), hipMemcpyHostToDevice, s));
+        LpArgs L{};
+        L.basis = plan->basis();
+        L.o = o;
+        L.ncols = plan->ncols;
+        L.d = d;
+        L.mI = mI;
+        L.mU = mU;
+        L.steps = plan->steps;
+        L.zlo = dev;
+        L.zhi = dev + kLpMaxD;
+        L.G = dev + (hG - H.data());
+        L.h = dev + (hh - H.data());
+        L.U = dev + (hU - H.data());
+        L.u = dev + (hu - H.data());
+        L.tol = 1e-6;      // the LP tolerance of Section 4.2, on rows scaled to a largest coefficient of 1
+        L.max_pivots = 20 * (d + mI + mU + 2) + 100;
+        L.rec = dev + nin;
+        L.verdict = dev + nin + nrec;
+        hipError_t e = timed("lp", s, [&] { return launch_lp(L, s); });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("lp: ") + hipGetErrorString(e));
+        double v[2 + kLpMaxD + kMaxO];
+        KRY_HIP(hipMemcpyAsync(v, L.verdict, sizeof(v), hipMemcpyDeviceToHost, s));
+        std::vector<double> rec;
+        if (step_flags) {
+            rec.resize((size_t)nrec);
+            KRY_HIP(hipMemcpyAsync(rec.data(), L.rec, (size_t)nrec * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        KRY_HIP(hipStreamSynchronize(s));
+        *first_step = (int64_t)v[0];
+        *status = (int32_t)v[1];
+        if (z_out) std::copy(v + 2, v + 2 + d, z_out);
+        if (y_out) std::copy(v + 2 + kLpMaxD, v + 2 + kLpMaxD + o, y_out);
+        if (step_flags)
+            for (int64_t st = 0; st <= plan->steps; ++st) step_flags[st] = (int32_t)rec[(size_t)st * kLpRec];
+        return KRY_OK;
+    });
 }
 
-kry_status kry_plan_runs(const kry_plan* plan, int32_t* nruns, int32_t* roles_out) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (nruns) *nruns = plan->nruns;
-    if (roles_out)
-        for (int32_t r = 0; r < plan->nruns; ++r) roles_out[r] = plan->role[r];
-    return KRY_OK;
+kry_status kry_plan_set_graph(kry_plan_t* plan, int32_t on) {
+    return guarded("kry_plan_set_graph", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (on) {
+            if (plan->method == KRY_BLOCK_ARNOLDI)
+                return fail(KRY_ENOTSUP, "graph mode covers the single-vector methods (block runs read sizes back)");
+            if (plan->Y.dense_runs)
+                return fail(KRY_ENOTSUP, "graph mode covers k <= 56 (the dense stage reads sizes back)");
+            if (plan->err_eps > 0.0)
+                return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
+            if (plan->stream == nullptr) return fail(KRY_EINVAL, "graph capture needs a stream other than the default one");
+        }
+        plan->graph_on = on != 0;
+        if (!plan->graph_on) {
+            if (plan->graph_exec) {
+                KRY_HIP(hipStreamSynchronize(plan->stream));
+                (void)hipGraphExecDestroy(plan->graph_exec);
+                plan->graph_exec = nullptr;
+            }
+            if (plan->graph) {
+                (void)hipGraphDestroy(plan->graph);
+                plan->graph = nullptr;
+            }
+        }
+        return KRY_OK;
+    });
 }
 
-kry_status kry_plan_krylov(kry_plan* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
+kry_status kry_plan_runs(const kry_plan_t* plan, int32_t* nruns, int32_t* roles_out) {
+    return guarded("kry_plan_runs", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (nruns) *nruns = plan->nruns;
+        if (roles_out)
+            for (int32_t r = 0; r < plan->nruns; ++r) roles_out[r] = plan->role[r];
+        return KRY_OK;
+    });
+}
+
+kry_status kry_plan_krylov(kry_plan_t* plan, int32_t run, int32_t* k_eff, double* beta0, double* H,
                            double* h_next, double* P) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
-    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
-    if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs: use kry_plan_block");
-    const ScalLayout& L = plan->Y.L;
-    std::vector<double> sc(L.stride);
-    KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal() + (size_t)run * L.stride, L.stride * sizeof(double),
-                           hipMemcpyDeviceToHost, plan->stream));
-    KRY_HIP(hipStreamSynchronize(plan->stream));
-    const int k = plan->k;
-    int m = std::min((int)sc[L.misc + MISC_KEFF], (int)sc[L.misc + MISC_KSTOP]);
-    const bool bordered = plan->role[run] == 2;
-    // dimension of the (augmented) Krylov space
-    int dim = m;
-    if (bordered) dim = (m > k - 1 ? k - 1 : m) + 1;
-    if (k_eff) *k_eff = dim;
-    if (beta0) *beta0 = bordered ? 1.0 : sc[L.beta + 0];
-    const int tri = bordered ? dim - 1 : dim;
-    if (H) {
-        std::fill(H, H + (size_t)dim * dim, 0.0);
-        const int sh = bordered ? 1 : 0;
-        if (bordered && dim > 1) H[1 * dim + 0] = sc[L.beta + 0];
-        for (int i = 0; i < tri; ++i) {
-            if (plan->hess_mode) {
-                for (int c = i; c < tri; ++c) H[(i + sh) * dim + (c + sh)] = sc[L.hess + i * k + c];
-                if (i + 1 < tri) H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
-                continue;
-            }
-            H[(i + sh) * dim + (i + sh)] = sc[L.alpha + i + 1];
-            if (i + 1 < tri) {
-                H[(i + sh) * dim + (i + 1 + sh)] = sc[L.beta + i + 1];
-                H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
-            }
-        }
-    }
-    if (h_next) *h_next = tri > 0 ? sc[L.beta + tri] : (bordered ? sc[L.beta + 0] : 0.0);
-    if (P) {
-        for (int q = 0; q < plan->o; ++q) {
-            double* row = P + (size_t)q * dim;
-            int c0 = 0;
-            if (bordered) { if (dim > 0) row[0] = 0.0; c0 = 1; }
-            for (int c = 0; c < tri; ++c) row[c0 + c] = sc[L.proj + q * (k + 1) + c];
-        }
-    }
-    return KRY_OK;
-}
-
-kry_status kry_plan_set_error_target(kry_plan* plan, double eps) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
-    if (eps > 0.0 && plan->method != KRY_LANCZOS)
-        return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
-    if (eps > 0.0 && plan->transposed)
-        return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
-    if (eps > 0.0 && plan->graph_on)
-        return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
-    if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
-    plan->err_eps = eps;
-    if (eps == 0.0) return KRY_OK;
-    if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
-    if (!plan->flag_ev) KRY_HIP(hipEventCreateWithFlags(&plan->flag_ev, hipEventDisableTiming));
-    // lambda_max of the symmetric part of A, bounded by Gershgorin
-    double lam;
-    if (plan->sys.kind == KRY_STENCIL7) {
-        stencil_row_bounds(plan->sys, nullptr, &lam);
-    } else {
-        const Layout& Y = plan->Y;
-        CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
-        double* out = plan->at<double>(Y.eflags) + kMaxP;
-        hipError_t e = launch_row_gersh(A, plan->sys.n, plan->np_part(), Y.nblocks, Y.rpb, out, plan->stream);
-        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("row_gersh: ") + hipGetErrorString(e));
-        KRY_HIP(hipMemcpyAsync(&lam, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+    return guarded("kry_plan_krylov", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs: use kry_plan_block");
+        const ScalLayout& L = plan->Y.L;
+        std::vector<double> sc(L.stride);
+        KRY_HIP(hipMemcpyAsync(sc.data(), plan->scal() + (size_t)run * L.stride, L.stride * sizeof(double),
+                               hipMemcpyDeviceToHost, plan->stream));
         KRY_HIP(hipStreamSynchronize(plan->stream));
-    }
-    plan->lam_plus = lam > 0.0 ? lam : 0.0;
-    plan->projected = false;
-    return KRY_OK;
+        const int k = plan->k;
+        int m = std::min((int)sc[L.misc + MISC_KEFF], (int)sc[L.misc + MISC_KSTOP]);
+        const bool bordered = plan->role[run] == 2;
+        // dimension of the (augmented) Krylov space
+        int dim = m;
+        if (bordered) dim = (m > k - 1 ? k - 1 : m) + 1;
+        if (k_eff) *k_eff = dim;
+        if (beta0) *beta0 = bordered ? 1.0 : sc[L.beta + 0];
+        const int tri = bordered ? dim - 1 : dim;
+        if (H) {
+            std::fill(H, H + (size_t)dim * dim, 0.0);
+            const int sh = bordered ? 1 : 0;
+            if (bordered && dim > 1) H[1 * dim + 0] = sc[L.beta + 0];
+            for (int i = 0; i < tri; ++i) {
+                if (plan->hess_mode) {
+                    for (int c = i; c < tri; ++c) H[(i + sh) * dim + (c + sh)] = sc[L.hess + i * k + c];
+                    if (i + 1 < tri) H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
+                    continue;
+                }
+                H[(i + sh) * dim + (i + sh)] = sc[L.alpha + i + 1];
+                if (i + 1 < tri) {
+                    H[(i + sh) * dim + (i + 1 + sh)] = sc[L.beta + i + 1];
+                    H[(i + 1 + sh) * dim + (i + sh)] = sc[L.beta + i + 1];
+                }
+            }
+        }
+        if (h_next) *h_next = tri > 0 ? sc[L.beta + tri] : (bordered ? sc[L.beta + 0] : 0.0);
+        if (P) {
+            for (int q = 0; q < plan->o; ++q) {
+                double* row = P + (size_t)q * dim;
+                int c0 = 0;
+                if (bordered) { if (dim > 0) row[0] = 0.0; c0 = 1; }
+                for (int c = 0; c < tri; ++c) row[c0 + c] = sc[L.proj + q * (k + 1) + c];
+            }
+        }
+        return KRY_OK;
+    });
 }
 
-kry_status kry_plan_error(kry_plan* plan, int32_t run, int32_t* k_used, double* bound) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
-    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
-    if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs carry no error bound");
-    const ScalLayout& L = plan->Y.L;
-    double misc[MISC_COUNT];
-    KRY_HIP(hipMemcpyAsync(misc, plan->scal() + (size_t)run * L.stride + L.misc, sizeof(misc), hipMemcpyDeviceToHost,
-                           plan->stream));
-    KRY_HIP(hipStreamSynchronize(plan->stream));
-    const int keff = (int)misc[MISC_KEFF], kstop = (int)misc[MISC_KSTOP];
-    // the augmented run's bordered matrix holds k - 1 Lanczos steps at most
-    const int cap = plan->role[run] == 2 ? plan->k - 1 : plan->k;
-    if (k_used) *k_used = std::min(std::min(keff, kstop), cap);
-    // a breakdown makes the projection exact
-    if (bound) *bound = keff < kstop ? 0.0 : misc[MISC_BOUND];
-    return KRY_OK;
+kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps) {
+    return guarded("kry_plan_set_error_target", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
+        if (eps > 0.0 && plan->method != KRY_LANCZOS)
+            return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
+        if (eps > 0.0 && plan->transposed)
+            return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
+        if (eps > 0.0 && plan->graph_on)
+            return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
+        if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
+        plan->err_eps = eps;
+        if (eps == 0.0) return KRY_OK;
+        if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
+        if (!plan->flag_ev) KRY_HIP(hipEventCreateWithFlags(&plan->flag_ev, hipEventDisableTiming));
+        // lambda_max of the symmetric part of A, bounded by Gershgorin
+        double lam;
+        if (plan->sys.kind == KRY_STENCIL7) {
+            stencil_row_bounds(plan->sys, nullptr, &lam);
+        } else {
+            const Layout& Y = plan->Y;
+            CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
+            double* out = plan->at<double>(Y.eflags) + kMaxP;
+            hipError_t e = launch_row_gersh(A, plan->sys.n, plan->np_part(), Y.nblocks, Y.rpb, out, plan->stream);
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("row_gersh: ") + hipGetErrorString(e));
+            KRY_HIP(hipMemcpyAsync(&lam, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+            KRY_HIP(hipStreamSynchronize(plan->stream));
+        }
+        plan->lam_plus = lam > 0.0 ? lam : 0.0;
+        plan->projected = false;
+        return KRY_OK;
+    });
 }
 
-kry_status kry_plan_block(const kry_plan* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
+kry_status kry_plan_error(kry_plan_t* plan, int32_t run, int32_t* k_used, double* bound) {
+    return guarded("kry_plan_error", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (run < 0 || run >= plan->nruns) return fail(KRY_EINVAL, "run out of range");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        if (plan->method == KRY_BLOCK_ARNOLDI) return fail(KRY_ENOTSUP, "block runs carry no error bound");
+        const ScalLayout& L = plan->Y.L;
+        double misc[MISC_COUNT];
+        KRY_HIP(hipMemcpyAsync(misc, plan->scal() + (size_t)run * L.stride + L.misc, sizeof(misc), hipMemcpyDeviceToHost,
+                               plan->stream));
+        KRY_HIP(hipStreamSynchronize(plan->stream));
+        const int keff = (int)misc[MISC_KEFF], kstop = (int)misc[MISC_KSTOP];
+        // the augmented run's bordered matrix holds k - 1 Lanczos steps at most
+        const int cap = plan->role[run] == 2 ? plan->k - 1 : plan->k;
+        if (k_used) *k_used = std::min(std::min(keff, kstop), cap);
+        // a breakdown makes the projection exact
+        if (bound) *bound = keff < kstop ? 0.0 : misc[MISC_BOUND];
+        return KRY_OK;
+    });
+}
+
+kry_status kry_plan_block(const kry_plan_t* plan, int32_t block, int32_t* nblocks, int32_t* k_eff, int32_t* p,
                           double* H, double* R0, double* P) {
-    if (!plan) return fail(KRY_EINVAL, "plan is NULL");
-    if (plan->method != KRY_BLOCK_ARNOLDI) return fail(KRY_EINVAL, "not a block Arnoldi plan");
-    if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
-    if (nblocks) *nblocks = (int32_t)plan->blocks.size();
-    if (block < 0) return KRY_OK;
-    if (block >= (int32_t)plan->blocks.size()) return fail(KRY_EINVAL, "block out of range");
-    const auto& b = plan->blocks[block];
-    if (k_eff) *k_eff = b.k_eff;
-    if (p) *p = b.p;
-    if (H) std::copy(b.H.begin(), b.H.end(), H);
-    if (R0) std::copy(b.R0.begin(), b.R0.end(), R0);
-    if (P) std::copy(b.P.begin(), b.P.end(), P);
-    return KRY_OK;
+    return guarded("kry_plan_block", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (plan->method != KRY_BLOCK_ARNOLDI) return fail(KRY_EINVAL, "not a block Arnoldi plan");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        if (nblocks) *nblocks = (int32_t)plan->blocks.size();
+        if (block < 0) return KRY_OK;
+        if (block >= (int32_t)plan->blocks.size()) return fail(KRY_EINVAL, "block out of range");
+        const auto& b = plan->blocks[block];
+        if (k_eff) *k_eff = b.k_eff;
+        if (p) *p = b.p;
+        if (H) std::copy(b.H.begin(), b.H.end(), H);
+        if (R0) std::copy(b.R0.begin(), b.R0.end(), R0);
+        if (P) std::copy(b.P.begin(), b.P.end(), P);
+        return KRY_OK;
+    });
 }
 
 kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip_stream, kry_matrix** out) {
-    if (!out) return fail(KRY_EINVAL, "out is NULL");
-    *out = nullptr;
-    kry_status st = validate_system(sys);
-    if (st != KRY_OK) return st;
-    if (sys->kind != KRY_CSR || sys->nnz <= 0) return fail(KRY_EINVAL, "a prepared matrix needs a CSR system with nnz > 0");
-    if (sys->prepared) return fail(KRY_EINVAL, "the system already names a prepared matrix");
-    if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    const int64_t n = sys->n, ns = sell_slices(n), nt = sell_scan_tiles(n);
-    const int64_t rpb = rows_per_block_for(n);
-    const int32_t nb = nblocks_for(n, rpb);
-    // first allocation: layout arrays, row-sum partials and the norm
-    size_t off = 0;
-    auto take = [&](size_t b) { const size_t o = off; off = align_up(off + b, 256); return o; };
-    const size_t o_width = take((size_t)ns * 4), o_off = take((size_t)(ns + 1) * 8), o_tiles = take((size_t)(nt + 1) * 8);
-    const size_t o_part = take((size_t)nb * 8), o_norm = take(8);
-    const size_t head = off;
-    char* tmp = nullptr;
-    if (hipMalloc((void**)&tmp, head) != hipSuccess) return fail(KRY_ENOMEM, "prepared matrix: allocation failed");
-    auto bail = [&](kry_status code, const std::string& msg) {
-        (void)hipStreamSynchronize(s);
+    return guarded("kry_matrix_create", [&]() -> kry_status {
+        if (!out) return fail(KRY_EINVAL, "out is NULL");
+        *out = nullptr;
+        kry_status st = validate_system(sys);
+        if (st != KRY_OK) return st;
+        if (sys->kind != KRY_CSR || sys->nnz <= 0) return fail(KRY_EINVAL, "a prepared matrix needs a CSR system with nnz > 0");
+        if (sys->prepared) return fail(KRY_EINVAL, "the system already names a prepared matrix");
+        if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const int64_t n = sys->n, ns = sell_slices(n), nt = sell_scan_tiles(n);
+        const int64_t rpb = rows_per_block_for(n);
+        const int32_t nb = nblocks_for(n, rpb);
+        // first allocation: layout arrays, row-sum partials and the norm
+        size_t off = 0;
+        auto take = [&](size_t b) { const size_t o = off; off = align_up(off + b, 256); return o; };
+        const size_t o_width = take((size_t)ns * 4), o_off = take((size_t)(ns + 1) * 8), o_tiles = take((size_t)(nt + 1) * 8);
+        const size_t o_part = take((size_t)nb * 8), o_norm = take(8);
+        const size_t head = off;
+        char* tmp = nullptr;
+        if (hipMalloc((void**)&tmp, head) != hipSuccess) return fail(KRY_ENOMEM, "prepared matrix: allocation failed");
+        auto bail = [&](kry_status code, const std::string& msg) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(tmp);
+            return fail(code, msg);
+        };
+        CsrArgs A{sys->rowptr, sys->colidx, sys->vals, nullptr};
+        hipError_t e = launch_sell_layout(A, n, reinterpret_cast<int32_t*>(tmp + o_width), reinterpret_cast<int64_t*>(tmp + o_off),
+                                          reinterpret_cast<int64_t*>(tmp + o_tiles), s);
+        if (e == hipSuccess)
+            e = launch_row_abs_max(A, n, reinterpret_cast<double*>(tmp + o_part), nb, rpb,
+                                   reinterpret_cast<double*>(tmp + o_norm), s);
+        int64_t total = 0, nwide = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&total, reinterpret_cast<int64_t*>(tmp + o_off) + ns, sizeof(total), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&nwide, reinterpret_cast<int64_t*>(tmp + o_tiles) + nt, sizeof(nwide), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        const bool narrow = nwide == 0 && env_int("KRY_SELL_NARROW", 1) != 0;
+        if (e != hipSuccess) return bail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
+        // second allocation: the entries, after the layout
+        const size_t esz = precision == KRY_FP32_BASIS ? 4 : 8;
+        const size_t o_col = take((size_t)total * (narrow ? 2 : 4)), o_val = take((size_t)total * esz);
+        kry_matrix* M = new kry_matrix();
+        M->bytes = off;
+        if (hipMalloc((void**)&M->mem, M->bytes) != hipSuccess) {
+            delete M;
+            return bail(KRY_ENOMEM, "prepared matrix: allocation failed");
+        }
+        e = hipMemcpyAsync(M->mem, tmp, head, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = launch_sell_fill(precision == KRY_FP32_BASIS, narrow, A, n, reinterpret_cast<int64_t*>(M->mem + o_off),
+                                 reinterpret_cast<int32_t*>(M->mem + o_width), M->mem + o_col, M->mem + o_val, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         (void)hipFree(tmp);
-        return fail(code, msg);
-    };
-    CsrArgs A{sys->rowptr, sys->colidx, sys->vals, nullptr};
-    hipError_t e = launch_sell_layout(A, n, reinterpret_cast<int32_t*>(tmp + o_width), reinterpret_cast<int64_t*>(tmp + o_off),
-                                      reinterpret_cast<int64_t*>(tmp + o_tiles), s);
-    if (e == hipSuccess)
-        e = launch_row_abs_max(A, n, reinterpret_cast<double*>(tmp + o_part), nb, rpb,
-                               reinterpret_cast<double*>(tmp + o_norm), s);
-    int64_t total = 0, nwide = 0;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&total, reinterpret_cast<int64_t*>(tmp + o_off) + ns, sizeof(total), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&nwide, reinterpret_cast<int64_t*>(tmp + o_tiles) + nt, sizeof(nwide), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    const bool narrow = nwide == 0 && env_int("KRY_SELL_NARROW", 1) != 0;
-    if (e != hipSuccess) return bail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
-    // second allocation: the entries, after the layout
-    const size_t esz = precision == KRY_FP32_BASIS ? 4 : 8;
-    const size_t o_col = take((size_t)total * (narrow ? 2 : 4)), o_val = take((size_t)total * esz);
-    kry_matrix* M = new kry_matrix();
-    M->bytes = off;
-    if (hipMalloc((void**)&M->mem, M->bytes) != hipSuccess) {
-        delete M;
-        return bail(KRY_ENOMEM, "prepared matrix: allocation failed");
-    }
-    e = hipMemcpyAsync(M->mem, tmp, head, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess)
-        e = launch_sell_fill(precision == KRY_FP32_BASIS, narrow, A, n, reinterpret_cast<int64_t*>(M->mem + o_off),
-                             reinterpret_cast<int32_t*>(M->mem + o_width), M->mem + o_col, M->mem + o_val, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(tmp);
-    if (e != hipSuccess) {
-        (void)hipFree(M->mem);
-        delete M;
-        return fail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
-    }
-    M->n = n;
-    M->nnz = sys->nnz;
-    M->rowptr = sys->rowptr;
-    M->colidx = sys->colidx;
-    M->vals = sys->vals;
-    M->precision = precision;
-    M->sell = SellArgs{reinterpret_cast<int64_t*>(M->mem + o_off), reinterpret_cast<int32_t*>(M->mem + o_width),
-                       narrow ? nullptr : reinterpret_cast<int32_t*>(M->mem + o_col),
-                       precision == KRY_FP32_BASIS ? nullptr : reinterpret_cast<double*>(M->mem + o_val),
-                       precision == KRY_FP32_BASIS ? reinterpret_cast<float*>(M->mem + o_val) : nullptr,
-                       narrow ? reinterpret_cast<int16_t*>(M->mem + o_col) : nullptr, n};
-    M->anorm_dev = reinterpret_cast<double*>(M->mem + o_norm);
-    *out = M;
-    return KRY_OK;
+        if (e != hipSuccess) {
+            (void)hipFree(M->mem);
+            delete M;
+            return fail(KRY_EDEVICE, std::string("prepared matrix: ") + hipGetErrorString(e));
+        }
+        M->n = n;
+        M->nnz = sys->nnz;
+        M->rowptr = sys->rowptr;
+        M->colidx = sys->colidx;
+        M->vals = sys->vals;
+        M->precision = precision;
+        M->sell = SellArgs{reinterpret_cast<int64_t*>(M->mem + o_off), reinterpret_cast<int32_t*>(M->mem + o_width),
+                           narrow ? nullptr : reinterpret_cast<int32_t*>(M->mem + o_col),
+                           precision == KRY_FP32_BASIS ? nullptr : reinterpret_cast<double*>(M->mem + o_val),
+                           precision == KRY_FP32_BASIS ? reinterpret_cast<float*>(M->mem + o_val) : nullptr,
+                           narrow ? reinterpret_cast<int16_t*>(M->mem + o_col) : nullptr, n};
+        M->anorm_dev = reinterpret_cast<double*>(M->mem + o_norm);
+        *out = M;
+        return KRY_OK;
+    });
 }
 
 kry_status kry_matrix_bytes(const kry_matrix* mat, size_t* bytes) {
-    if (!mat || !bytes) return fail(KRY_EINVAL, "NULL argument");
-    *bytes = mat->bytes;
-    return KRY_OK;
+    return guarded("kry_matrix_bytes", [&]() -> kry_status {
+        if (!mat || !bytes) return fail(KRY_EINVAL, "NULL argument");
+        *bytes = mat->bytes;
+        return KRY_OK;
+    });
 }
 
 void kry_matrix_destroy(kry_matrix* mat) {
-    if (!mat) return;
-    if (mat->mem) (void)hipFree(mat->mem);
-    delete mat;
+    guarded_void([&] {
+        if (!mat) return;
+        if (mat->mem) (void)hipFree(mat->mem);
+        delete mat;
+    });
 }
 
-void kry_plan_destroy(kry_plan* plan) {
-    if (!plan) return;
-    if (plan->flag_ev || (plan->owns_ws && plan->ws)) (void)hipStreamSynchronize(plan->stream);
-    if (plan->owns_ws && plan->ws) (void)hipFree(plan->ws);
-    if (plan->lp_mem) {
-        (void)hipStreamSynchronize(plan->stream);
-        (void)hipFree(plan->lp_mem);
-    }
-    if (plan->graph_exec) {
-        (void)hipStreamSynchronize(plan->stream);
-        (void)hipGraphExecDestroy(plan->graph_exec);
-    }
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    if (plan->flag_ev) (void)hipEventDestroy(plan->flag_ev);
-    if (plan->hflags) (void)hipHostFree(plan->hflags);
-    delete plan;
+void kry_plan_destroy(kry_plan_t* plan) {
+    guarded_void([&] {
+        if (!plan) return;
+        if (plan->flag_ev || (plan->owns_ws && plan->ws)) (void)hipStreamSynchronize(plan->stream);
+        if (plan->owns_ws && plan->ws) (void)hipFree(plan->ws);
+        if (plan->lp_mem) {
+            (void)hipStreamSynchronize(plan->stream);
+            (void)hipFree(plan->lp_mem);
+        }
+        if (plan->graph_exec) {
+            (void)hipStreamSynchronize(plan->stream);
+            (void)hipGraphExecDestroy(plan->graph_exec);
+        }
+        if (plan->graph) (void)hipGraphDestroy(plan->graph);
+        if (plan->flag_ev) (void)hipEventDestroy(plan->flag_ev);
+        if (plan->hflags) (void)hipHostFree(plan->hflags);
+        delete plan;
+    });
 }
 
 kry_status kry_profile_enable(int32_t on) {
-    Profiler& P = prof();
-    std::lock_guard<std::mutex> g(P.mu);
-    P.on = on != 0;
-    return KRY_OK;
+    return guarded("kry_profile_enable", [&]() -> kry_status {
+        Profiler& P = prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        P.on = on != 0;
+        return KRY_OK;
+    });
 }
 
 kry_status kry_profile_reset(void) {
-    Profiler& P = prof();
-    std::lock_guard<std::mutex> g(P.mu);
-    P.drain();
-    P.totals.clear();
-    return KRY_OK;
+    return guarded("kry_profile_reset", [&]() -> kry_status {
+        Profiler& P = prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        P.drain();
+        P.totals.clear();
+        return KRY_OK;
+    });
 }
 
 kry_status kry_profile_read(const char* name, int64_t* launches, double* total_ms) {
-    if (!name) return fail(KRY_EINVAL, "name is NULL");
-    Profiler& P = prof();
-    std::lock_guard<std::mutex> g(P.mu);
-    P.drain();
-    auto it = P.totals.find(name);
-    if (launches) *launches = it == P.totals.end() ? 0 : it->second.first;
-    if (total_ms) *total_ms = it == P.totals.end() ? 0.0 : it->second.second;
-    return KRY_OK;
+    return guarded("kry_profile_read", [&]() -> kry_status {
+        if (!name) return fail(KRY_EINVAL, "name is NULL");
+        Profiler& P = prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        P.drain();
+        auto it = P.totals.find(name);
+        if (launches) *launches = it == P.totals.end() ? 0 : it->second.first;
+        if (total_ms) *total_ms = it == P.totals.end() ? 0.0 : it->second.second;
+        return KRY_OK;
+    });
 }
 
 const char* kry_profile_names(void) { return kKernelNames; }

@@ -140,6 +140,17 @@ namespace {
 __global__ __launch_bounds__(256) void k_fill(double* p, int64_t count, double v) {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count; t += (int64_t)gridDim.x * 256) p[t] = v;
 }
+// basis[s][r][run0 + c] = NaN for every step, row and c < w: the run's
+// exponential is undefined (non-finite H), which the box check reports.
+__global__ __launch_bounds__(256) void k_nan_columns(double* basis, int64_t steps, int o, int nruns, int run0, int w) {
+    const int64_t total = (steps + 1) * o * w;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i % w;
+        const int64_t sr = i / w;
+        basis[sr * nruns + run0 + c] = __builtin_nan("");
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count; t += (int64_t)gridDim.x * 256) p[t] = v;
 }
@@ -235,7 +246,12 @@ hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hi
     if ((e = hipMemcpyAsync(host_norm, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     const double nx = *host_norm * J.dt;
-    if (!std::isfinite(nx)) return hipErrorInvalidValue;
+    if (!std::isfinite(nx)) {
+        // a non-finite value reached H: the run's basis columns become NaN
+        // and the box check reports KRY_ENUMERIC in its verdict
+        hipLaunchKernelGGL(k_nan_columns, dim3(256), dim3(256), 0, s, J.basis, J.steps, J.o, J.nruns, J.run0, J.w);
+        return hipGetLastError();
+    }
     int sq = 0;
     while (nx / std::ldexp(1.0, sq) > 1.0) ++sq;
     hipLaunchKernelGGL(k_scopy, dim3(grid_for(mm)), dim3(256), 0, s, m, J.H, J.ldh, J.dt / std::ldexp(1.0, sq), X, m,

@@ -1,11 +1,13 @@
 // A-posteriori error control of the Krylov dimension (paper Section 4.2:
 // Lemma 1 and the checks of Algorithms 2 and 4) for Lanczos runs.
 //
-// At a checkpoint j (4, then ceil(1.1 j)) each run of the batch evaluates
-//     bound = beta0 h e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
+// At a checkpoint j (4, then ceil(1.1 j) with 1.1 j a double product) each
+// run of the batch evaluates, for its normalised start vector (the
+// algorithms take v / |v| and the bound sees T only),
+//     bound = h e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
 // (h = beta_j, lambda >= lambda_max of the symmetric part of A, w = 1, or
 // w = tau - t for the augmented run, which integrates the approximation of
-// e^{As} b) and stops at the first checkpoint below the target.  T_j is
+// e^{As} b / |b|) and stops at the first checkpoint below the target.  T_j is
 // diagonalised (kry_tridiag.h) so the integrand is a sum of j exponentials;
 // the integral uses a fixed composite rule: 8-point Gauss-Legendre on
 // [0, tau 2^-L] and [tau 2^-(i+1), tau 2^-i], i < L, each split into U equal
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_lemma1(BatchArgs B, ErrArgs X, int j
     if (threadIdx.x == 0) {
         double bound;
         if (st == 3) bound = INFINITY;                       // eigen-iteration failed: do not stop here
-        else bound = sc[B.L.beta + 0] * sc[B.L.beta + m] * exp(X.lam_plus * tau) * integral;
+        else bound = sc[B.L.beta + m] * exp(X.lam_plus * tau) * integral;
         sc[B.L.misc + MISC_BOUND] = bound;
         const bool stop = bound < X.eps;
         if (stop) {

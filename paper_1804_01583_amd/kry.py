@@ -1,8 +1,8 @@
 """ctypes binding of libkry.so (include/kry.h).  Argument marshalling only:
 every step of the verification path runs in the library's HIP kernels.
 
-The functions keep the C names (kry_plan_create, kry_project_expm,
-kry_check_box_safety, kry_footprint, kry_plan_runs, kry_plan_krylov,
+The functions keep the C names (kry_plan, kry_plan_create, kry_project_expm,
+kry_check_box_safety, kry_footprint, kry_plan_workspace, kry_plan_runs, kry_plan_krylov,
 kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy, kry_matrix_create,
 kry_matrix_bytes, kry_matrix_destroy).  ``Plan`` is a small owner object that keeps the device
 tensors a plan borrows alive and destroys the plan when it is dropped.
@@ -71,6 +71,9 @@ def _load():
     lib.kry_plan_create.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
                                     ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
                                     ct.c_int32, ct.c_int32, ct.c_int32, P, ct.c_size_t, P, ct.POINTER(P)]
+    lib.kry_plan.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
+                             ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
+                             ct.c_int32, ct.c_int32, ct.c_int32, P, ct.POINTER(P)]
     lib.kry_plan_create_transposed.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32,
                                                ct.POINTER(KrySegs), ct.POINTER(KrySegs), ct.c_int32, ct.c_int32,
                                                ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.c_size_t, P,
@@ -81,8 +84,10 @@ def _load():
     lib.kry_check_lp_safety.argtypes = [P, P, P, ct.c_int32, P, P, ct.c_int32, ct.POINTER(ct.c_int64),
                                         ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_check_box_safety.argtypes = [P, ct.POINTER(KryInterval), ct.POINTER(KryVerdict), P]
-    lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
-                                  ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
+    lib.kry_plan_workspace.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
+                                       ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
+    lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
+                                  ct.c_int32, ct.POINTER(ct.c_size_t)]
     lib.kry_plan_runs.argtypes = [P, ct.POINTER(ct.c_int32), P]
     lib.kry_plan_krylov.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double), P,
                                     ct.POINTER(ct.c_double), P]
@@ -101,8 +106,8 @@ def _load():
     lib.kry_profile_enable.argtypes = [ct.c_int32]
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
-    for f in ("kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed", "kry_project_expm",
-              "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
+    for f in ("kry_plan", "kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed",
+              "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
@@ -112,8 +117,8 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed", "kry_project_expm",
-            "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint",
+EXPORTED = ["kry_plan", "kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed",
+            "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
             "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
@@ -148,6 +153,16 @@ def kry_plan_create(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Se
     _check(lib.kry_plan_create(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps,
                                precision, method, block_p, workspace_ptr, workspace_bytes, stream_ptr,
                                ct.byref(out)))
+    return out.value
+
+
+def kry_plan(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Sequence[KrySegs], k: int, dt: float,
+             steps: int, precision=KRY_FP64, method=KRY_AUTO, block_p=0, stream_ptr=None) -> int:
+    garr = (KryGen * max(len(gens), 1))(*gens)
+    carr = (KrySegs * len(C))(*C)
+    out = ct.c_void_p()
+    _check(lib.kry_plan(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps, precision,
+                        method, block_p, stream_ptr, ct.byref(out)))
     return out.value
 
 
@@ -202,11 +217,17 @@ def kry_check_lp_safety(plan: int, G, h, U, u, ngen: int, o: int, steps: int, wa
     return first.value, status.value, z[:ngen], y[:o], flags
 
 
-def kry_footprint(system: KrySystem, nruns: int, o: int, k: int, steps: int, nseg_total: int,
-                  precision=KRY_FP64, method=KRY_AUTO, block_p=0) -> int:
+def kry_plan_workspace(system: KrySystem, nruns: int, o: int, k: int, steps: int, nseg_total: int,
+                       precision=KRY_FP64, method=KRY_AUTO, block_p=0) -> int:
     b = ct.c_size_t()
-    _check(lib.kry_footprint(ct.byref(system), nruns, o, k, steps, nseg_total, precision, method, block_p,
-                             ct.byref(b)))
+    _check(lib.kry_plan_workspace(ct.byref(system), nruns, o, k, steps, nseg_total, precision, method, block_p,
+                                  ct.byref(b)))
+    return b.value
+
+
+def kry_footprint(system: KrySystem, ngen: int, o: int, k: int, precision=KRY_FP64, block_p=0) -> int:
+    b = ct.c_size_t()
+    _check(lib.kry_footprint(ct.byref(system), ngen, o, k, precision, block_p, ct.byref(b)))
     return b.value
 
 
@@ -457,7 +478,7 @@ class Plan:
             key = (own, precision, method, block_p, self.k, self.steps, nseg, self.o, nruns, self._sys.prepared)
             ws_bytes = dsys._footprints.get(key) if own else None
             if ws_bytes is None:
-                ws_bytes = kry_footprint(self._sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
+                ws_bytes = kry_plan_workspace(self._sys, max(nruns, 1), self.o, self.k, self.steps, nseg, precision,
                                          method, block_p)
                 if own:
                     dsys._footprints[key] = ws_bytes

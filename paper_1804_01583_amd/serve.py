@@ -5,7 +5,7 @@ unsafe threshold, a time grid and a precision against one of the resident
 systems).  The server
 
 * admits a waiting query, oldest first, as soon as a slot is free and the
-  HBM budget covers its plan's workspace (kry_footprint),
+  HBM budget covers its plan's workspace (kry_plan_workspace),
 * runs admitted queries concurrently, each on its own HIP stream, so their
   kernels overlap on the device (a query's generators are already advanced
   together by every mat-vec launch of its plan),
@@ -100,7 +100,7 @@ class _Pending:
 class Server:
     """slots: queries in flight at once; budget_bytes: HBM for their plans.
     ``runner(query, slot, keep_basis) -> (verdict, basis, runs)`` and
-    ``footprint(query) -> bytes`` default to the GPU plan and kry_footprint;
+    ``footprint(query) -> bytes`` default to the GPU plan and kry_plan_workspace;
     other ones serve for testing the scheduling on the host."""
 
     def __init__(self, catalog: Optional[Catalog], slots: int = 8, budget_bytes: int = 200 << 30,
@@ -117,7 +117,7 @@ class Server:
         prec = _precision(q)
         dsys = self.catalog.get(q.family, q.m, prec)
         nseg = sum(g.seg.nseg for g in q.gens) + sum(c.nseg for c in q.C)
-        return kry.kry_footprint(dsys.system_for(prec), len(q.gens), len(q.C), q.k, q.steps, nseg, prec,
+        return kry.kry_plan_workspace(dsys.system_for(prec), len(q.gens), len(q.C), q.k, q.steps, nseg, prec,
                                  kry.KRY_AUTO, 0)
 
     def _run_one(self, q, stream, keep_basis: bool):

@@ -28,7 +28,7 @@ def _checkpoint_bounds(run, tau, lam):
     H = run["H"]
     out = []
     for k in AD.k_schedule(4, H.shape[0] - 1):
-        out.append(AD.lemma1_bound(H[:k, :k], H[k, k - 1], run["beta0"], tau, lam, run["affine"]))
+        out.append(AD.lemma1_bound(H[:k, :k], H[k, k - 1], tau, lam, run["affine"]))
     if run["k_eff"] == run["k_stop"] and run["bound"] not in (0.0, math.inf):
         out.append(run["bound"])
     return out
@@ -37,13 +37,15 @@ def _checkpoint_bounds(run, tau, lam):
 def _bound_tol(run, tau, lam):
     """Both sides evaluate (e^{tT})_{k,1} with an absolute error of a few k
     eps times max over the eigenvalues of e^{theta t} <= e^{max(lambda,0) t}
-    (the GPU as a sum of k exponentials, the oracle by a Pade exponential),
+    (both as sums of k exponentials from eigen-decompositions of T: the GPU's
+    own, the oracle's LAPACK tridiagonal solver),
     so the integrals can differ by up to that times int_0^tau w(t) dt
-    (tau, or tau^2 / 2 for the augmented run), scaled like the bound."""
+    (tau, or tau^2 / 2 for the augmented run), scaled like the bound (of
+    the normalised process)."""
     k = run["k_stop"]
     lp = max(lam, 0.0)
     wint = tau * tau / 2 if run["affine"] else tau
-    return 1e-9 * run["bound"] + run["beta0"] * run["h"] * math.exp(2 * lp * tau) * 4 * k * EPS * wint
+    return 1e-9 * run["bound"] + run["h"] * math.exp(2 * lp * tau) * 4 * k * EPS * wint
 
 
 def _run(p, eps, **kw):

@@ -96,9 +96,9 @@ def test_footprint_leaves_the_prepared_copy_out():
     p = W.small_heat3d(m=40, k=20, steps=50)
     ds = kry.DeviceSystem(p)
     nseg = sum(g.seg.nseg for g in p.gens) + sum(c.nseg for c in p.C)
-    own = kry.kry_footprint(ds.sys, 2, len(p.C), p.k, p.steps, nseg)
+    own = kry.kry_plan_workspace(ds.sys, 2, len(p.C), p.k, p.steps, nseg)
     h = ds.prepare(kry.KRY_FP64)
-    shared = kry.kry_footprint(ds.system_for(kry.KRY_FP64), 2, len(p.C), p.k, p.steps, nseg)
+    shared = kry.kry_plan_workspace(ds.system_for(kry.KRY_FP64), 2, len(p.C), p.k, p.steps, nseg)
     mbytes = kry.kry_matrix_bytes(h)
     # FP64 values and 16-bit column offsets (every column is within 1600 of
     # its row here); a plan that builds its own copy reserves 32-bit columns

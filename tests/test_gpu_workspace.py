@@ -43,7 +43,7 @@ def test_footprint_covers_what_plan_creation_needs(route):
     k, steps, dt = 12, 30, 0.1
     nseg = sum(g.seg.nseg for g in gens) + 2 + 1
     if route == "forward":
-        need = kry.kry_footprint(s, len(gens) + 1, 2, k, steps, nseg)
+        need = kry.kry_plan_workspace(s, len(gens) + 1, 2, k, steps, nseg)
         create = lambda ws, nb: kry.kry_plan_create(s, kg, None, kc, k, dt, steps, kry.KRY_FP64, kry.KRY_AUTO, 0,
                                                     ws, nb, None)
     else:

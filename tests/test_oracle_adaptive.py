@@ -1,8 +1,13 @@
 """Pins of the error-controlled Krylov dimension (oracle/adaptive.py):
-the quadrature rule against closed-form integrals, the Lemma 1 bound against
-the true error from SciPy's dense expm (plain and augmented runs), exact
-breakdown, and the checkpoint schedule of Algorithms 2 and 4."""
+the quadrature rule against closed-form integrals; the Lemma 1 bound against
+a one-step case worked by hand with lambda_max > 0 (both sides of the bound,
+the factor e^{lambda tau} and the Gershgorin bound), against the true error
+from SciPy's dense expm (plain and augmented runs) and against the paper's
+own result on its 100^3 heat system (Section 5.3: the bound first drops
+below 1e-6 at k = 544, at 5.8e-7); exact breakdown; and the checkpoint
+schedule of Algorithms 2 and 4."""
 import math
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -13,13 +18,95 @@ import workloads as W
 from oracle import adaptive as AD
 
 
-def test_schedule_is_ceil_of_1_1_k():
-    got = list(AD.k_schedule(4, 60))
+def test_schedule_is_ceil_of_the_double_product():
+    # ceil(1.1 k) with 1.1 k rounded to the nearest double: the exact product
+    # of k and the double nearest 1.1, rounded once (Fraction -> float rounds
+    # correctly), then the ceiling
+    got = list(AD.k_schedule(4, 700))
     want, k = [], 4
-    while k <= 60:
+    while k <= 700:
         want.append(k)
-        k = math.ceil(round(1.1 * k, 9))
-    assert got == want == [4, 5, 6, 7, 8, 9, 10, 11, 13, 15, 17, 19, 21, 24, 27, 30, 33, 37, 41, 46, 51, 57]
+        k = math.ceil(float(Fraction(1.1) * k))
+    assert got == want
+    # the double product first exceeds an integer at 1.1 * 170 = 187.00000000000003
+    assert got[got.index(170) + 1] == 188
+    # Section 5.3 reports a stop at k = 544: it lies on this sequence, the
+    # exact-arithmetic ceiling (..., 491, 541, 596) would not reach it
+    assert [494, 544, 599] == got[got.index(494):got.index(494) + 3]
+    exact, k = [], 4
+    while k <= 700:
+        exact.append(k)
+        k = (11 * k + 9) // 10
+    assert 544 not in exact
+
+
+def test_one_step_bound_by_hand_with_positive_lambda():
+    # A = diag(1, 1/2), v = (1, 1) (normalised by the process).  One Lanczos
+    # step: alpha = 3/4, the residual ((1 - 3/4), (1/2 - 3/4)) / sqrt 2 has
+    # norm beta = 1/4.  lambda_max = 1 > 0, so Lemma 1 gives
+    #   bound(tau) = (1/4) e^{tau} int_0^tau e^{3t/4} dt = (1/4) e^tau (e^{3 tau/4} - 1) / (3/4).
+    A = np.diag([1.0, 0.5])
+    C = np.eye(2)
+    tau = 2.0
+    lam = AD.gershgorin_sym_upper(A)
+    assert lam == 1.0
+    r = AD.adaptive_lanczos(A, np.array([1.0, 1.0]), C, 0.0, tau, 1, lam, 1.0)
+    assert r["k_stop"] == 1 and abs(r["H"][0, 0] - 0.75) <= 1e-15 and abs(r["h"] - 0.25) <= 1e-15
+    want = 0.25 * math.exp(tau) * (math.exp(0.75 * tau) - 1.0) / 0.75
+    got = AD.lemma1_bound(r["H"], r["h"], tau, lam)
+    assert abs(got - want) <= 1e-13 * want
+    # and the bound holds: |e^{tA} v - e^{t alpha} v| for unit v at every t <= tau
+    for t in np.linspace(0.0, tau, 9):
+        err = math.hypot(math.exp(t) - math.exp(0.75 * t), math.exp(0.5 * t) - math.exp(0.75 * t)) / math.sqrt(2)
+        assert err <= AD.lemma1_bound(r["H"], r["h"], t, lam) + 1e-15
+    # the augmented weight (tau - t): (1/4) e^tau int_0^tau (tau - t) e^{3t/4} dt
+    want_aff = 0.25 * math.exp(tau) * (math.exp(0.75 * tau) - 1.0 - 0.75 * tau) / 0.75**2
+    assert abs(AD.lemma1_bound(r["H"], r["h"], tau, lam, affine=True) - want_aff) <= 1e-13 * want_aff
+    # a nonpositive lambda contributes a factor 1
+    assert abs(AD.lemma1_bound(r["H"], r["h"], tau, -3.0) - want * math.exp(-tau)) <= 1e-13 * want
+
+
+def test_gershgorin_bound_by_hand():
+    # symmetric part of [[0.2, 0.7], [-0.1, 1.0]] is [[0.2, 0.3], [0.3, 1.0]]:
+    # row bounds 0.2 + 0.3 and 1.0 + 0.3
+    A = np.array([[0.2, 0.7], [-0.1, 1.0]])
+    assert abs(AD.gershgorin_sym_upper(A) - 1.3) <= 1e-15
+    # negative off-diagonals count by magnitude
+    B = np.array([[-2.0, -0.5, 0.0], [-0.5, -1.0, 0.25], [0.0, 0.25, 0.1]])
+    assert abs(AD.gershgorin_sym_upper(B) - 0.35) <= 1e-15
+
+
+def test_symmetric_route_equals_pade_route():
+    # (e^{tT})_{k,1} through the eigen-decomposition of a symmetric
+    # tridiagonal T against the Pade exponential of the same matrix
+    p = W.small_heat3d(m=8, k=15, steps=50)
+    A = oracle.system_matrix(p)
+    r = oracle.lanczos(A, p.gens[0].seg.dense(p.n), 15, oracle.output_matrix(p))
+    assert AD.is_sym_tridiagonal(r.H)
+    ts = np.array([1e-3, 0.1, 0.5, 1.0, 3.0])
+    got = AD.h_values(r.H, ts)
+    want = np.array([AD.h_entry(r.H, t) for t in ts])
+    # the eigen form sums k terms of size <= 1 (|Q| <= 1, theta <= 0): its
+    # error is absolute, a few k eps, where the Pade form keeps tiny values
+    assert np.abs(got - want).max() <= 4 * 15 * np.finfo(float).eps
+    assert abs(got[-1] - want[-1]) <= 1e-9 * abs(want[-1])
+
+
+@pytest.mark.slow
+def test_paper_heat_100_stops_at_k_544():
+    # Section 5.3: on the 100^3 heat system the bound first falls below the
+    # 1e-6 target at k = 544, where it is 5.8e-7; the checkpoint before (494)
+    # must not pass.  One Lanczos run of 544 steps on n = 10^6.
+    p = W.heat3d_paper(m=100)
+    A = oracle.system_matrix(p)
+    lam = AD.gershgorin_sym_upper(A)
+    assert lam <= 1e-9 * p.meta["c"]       # insulated + exchange: no growth, factor 1
+    v = p.gens[0].seg.dense(p.n)
+    r = AD.adaptive_lanczos(A, v, oracle.output_matrix(p), 1e-6, 20.0, 600, lam, oracle.krylov.inf_norm(A))
+    assert r["k_stop"] == 544
+    assert abs(r["bound"] - 5.8e-7) <= 0.05 * 5.8e-7
+    b494 = AD.lemma1_bound(r["H"][:494, :494], r["H"][494, 493], 20.0, lam)
+    assert b494 > 1e-6
 
 
 @pytest.mark.parametrize("theta", [-1e4, -3.0, 0.0, 0.5])
@@ -48,7 +135,7 @@ def test_bound_dominates_true_error(k):
     r = oracle.arnoldi(A, v, k, C, keep_V=True)
     tau = p.steps * p.dt
     lam = AD.gershgorin_sym_upper(A)
-    b = AD.lemma1_bound(r.H, r.h_next, r.beta0, tau, lam)
+    b = r.beta0 * AD.lemma1_bound(r.H, r.h_next, tau, lam)
     err = _true_error(Ad, v, r.H, r.V, r.beta0, np.linspace(0, tau, 26))
     # the bound dominates the true error (up to the rounding of the dense reference)
     assert b >= err - 1e-12 * np.linalg.norm(v)
@@ -64,7 +151,7 @@ def test_affine_bound_dominates_true_error():
     r = oracle.arnoldi(A, b, k, C, keep_V=True)        # Lanczos space from b, orthonormal
     tau = p.steps * p.dt
     lam = AD.gershgorin_sym_upper(A)
-    bound = AD.lemma1_bound(r.H, r.h_next, r.beta0, tau, lam, affine=True)
+    bound = r.beta0 * AD.lemma1_bound(r.H, r.h_next, tau, lam, affine=True)
     # x(t) = A^-1 (e^{At} - I) b against the integral of the Krylov approximation
     e1 = np.zeros(k); e1[0] = 1.0
     worst = 0.0
@@ -100,9 +187,9 @@ def test_adaptive_stops_at_first_checkpoint_under_target():
         v = p.forcing() if affine else run.start
         kk = ks
         r = oracle.lanczos(A, v, kk, oracle.output_matrix(p), opnorm=oracle.krylov.inf_norm(A))
-        assert abs(AD.lemma1_bound(r.H, r.h_next, r.beta0, tau, lam, affine) - info["bound"]) <= 1e-9 * info["bound"]
+        assert abs(AD.lemma1_bound(r.H, r.h_next, tau, lam, affine) - info["bound"]) <= 1e-9 * info["bound"]
         earlier = [c for c in AD.k_schedule(4, ks) if c < ks]
         if earlier:
             c = earlier[-1]
             r2 = oracle.lanczos(A, v, c, oracle.output_matrix(p), opnorm=oracle.krylov.inf_norm(A))
-            assert AD.lemma1_bound(r2.H, r2.h_next, r2.beta0, tau, lam, affine) >= 1e-6
+            assert AD.lemma1_bound(r2.H, r2.h_next, tau, lam, affine) >= 1e-6

@@ -57,3 +57,14 @@ def test_stencil_form_expands_to_the_same_operator():
     assert np.abs(A - B).max() <= 1e-13 * p.meta["c"]
     assert [g.seg.count for g in s.gens] == [g.seg.count for g in p.gens]
     assert np.array_equal(s.C[0].lo, p.C[0].lo) and s.C[0].w[0] == p.C[0].w[0]
+
+
+def test_paper_norm_at_t50_fixes_the_grid_spacing():
+    # Section 4.2 prints |A t| = 32771611 for the 100^3 system at t = 50; the
+    # Frobenius norm of 50 A with h = 1 / (m + 1) reproduces it (h = 1 / m
+    # would give 32125884, 2 % off)
+    p = W.heat3d_paper(m=100)
+    fro = 50.0 * math.sqrt(float(np.sum(p.vals * p.vals)))
+    assert abs(fro - 32771611.0) <= 1e-7 * 32771611.0
+    s = W.heat3d_paper_stencil(m=100)
+    assert s.meta["h"] == p.meta["h"] == 1.0 / 101 and s.meta["c"] == p.meta["c"]

@@ -320,18 +320,27 @@ def heat3d_paper_stencil(m=1000, D=0.01, exchange=0.5, k=5932, dt=0.02, steps=10
     the rounding of the diagonal."""
     p = heat3d_paper(m=min(m, 2), D=D, exchange=exchange)        # shapes only
     n = m**3
-    h = 1.0 / m
+    h = 1.0 / (m + 1)
     c = D / h**2
-    ext = [max(int(round(f * m)), 1) for f in (0.4, 0.2, 0.1)]
-    gbox = ((0, ext[0]), (0, ext[1]), (0, ext[2]))
+    gbox, cbox, cells = _paper_heat_regions(m)
     gens = [Generator(box_segments((m, m, m), gbox, 1.0), zc=1.0, radius=0.1)]
-    mid = [m // 2 - 1, m // 2] if m % 2 == 0 else [m // 2]
-    cbox = tuple((mid[0], mid[-1] + 1) for _ in range(3))
-    C = [box_segments((m, m, m), cbox, 1.0 / len(mid) ** 3)]
+    C = [box_segments((m, m, m), cbox, 1.0 / cells)]
     return Problem("heat3d_paper_stencil", n, "stencil7", True, gens, C, p.unsafe, k=k, dt=dt, steps=steps,
                    grid=(m, m, m), coef=(-6.0 * c, c, c, c), bc="insulated", exchange=-c * h * exchange,
                    meta={"m": m, "gen_box": gbox, "center_box": cbox, "c": c, "h": h, "exchange": exchange},
                    note="3D heat as stated in the paper, matrix-free")
+
+
+def _paper_heat_regions(m):
+    """Index boxes of the heated region x in [0, 0.4], y in [0, 0.2],
+    z in [0, 0.1] (the grid points (i + 1) h with h = 1 / (m + 1) inside it,
+    at least one per axis) and of the points around the centre (0.5, 0.5,
+    0.5): the centre point itself for odd m, the 8 around it for even m."""
+    ext = [max(int(math.floor(f * (m + 1) + 1e-9)), 1) for f in (0.4, 0.2, 0.1)]
+    gbox = ((0, ext[0]), (0, ext[1]), (0, ext[2]))
+    mid = [m // 2 - 1, m // 2] if m % 2 == 0 else [m // 2]
+    cbox = tuple((mid[0], mid[-1] + 1) for _ in range(3))
+    return gbox, cbox, len(mid) ** 3
 
 
 def csr_heat_insulated(m, c, exchange_diag):
@@ -367,22 +376,21 @@ def heat3d_paper(m=100, D=0.01, exchange=0.5, k=1024, dt=0.02, steps=1000) -> Pr
     ambient at constant 0.5; u_t = D (u_xx + u_yy + u_zz), D = 0.01;
     initially 0.9..1.1 on x in [0, 0.4], y in [0, 0.2], z in [0, 0.1] and 0
     elsewhere; output = the temperature at the centre point; T = 20 with
-    dt = 0.02.  Discretised here by cell-centred finite volumes (h = 1/m):
-    interior fluxes D (u_j - u_i) / h, no flux through insulated faces, and
-    through the x = 1 face the flux D * exchange * u of the boundary cell, i.e.
-    -c h exchange on those cells' diagonal (c = D / h^2).  The centre point
-    is the mean of the 8 cells around it (m even) or the centre cell (m odd).
-    k is the cap of an error-controlled Krylov dimension."""
+    dt = 0.02.  Semi-discretised on the m^3 grid points (i + 1) h,
+    h = 1 / (m + 1), by second differences c (u_j - u_i), c = D / h^2, with
+    no flux through insulated faces (a missing neighbour contributes nothing)
+    and, on the x = 1 face, the exchange flux D * exchange * u through a face
+    of area h^2 into a volume h^3, i.e. -c h exchange on those points'
+    diagonal.  This spacing reproduces the paper's |A t| at t = 50 for m = 100
+    (Section 4.2).  The centre point is the mean of the 8 points around it
+    (m even) or the centre point (m odd).  k is the cap of an
+    error-controlled Krylov dimension."""
     n = m**3
-    h = 1.0 / m
+    h = 1.0 / (m + 1)
     c = D / h**2
     rowptr, colidx, vals = csr_heat_insulated(m, c, -c * h * exchange)
-    ext = [max(int(round(f * m)), 1) for f in (0.4, 0.2, 0.1)]
-    gbox = ((0, ext[0]), (0, ext[1]), (0, ext[2]))
+    gbox, cbox, cells = _paper_heat_regions(m)
     gens = [Generator(box_segments((m, m, m), gbox, 1.0), zc=1.0, radius=0.1)]
-    mid = [m // 2 - 1, m // 2] if m % 2 == 0 else [m // 2]
-    cbox = tuple((mid[0], mid[-1] + 1) for _ in range(3))
-    cells = len(mid) ** 3
     C = [box_segments((m, m, m), cbox, 1.0 / cells)]
     unsafe = np.array([[1.0, math.inf]])
     return Problem("heat3d_paper", n, "csr", True, gens, C, unsafe, k=k, dt=dt, steps=steps,
