@@ -1,6 +1,7 @@
-"""Throughput of one verification of the 3D heat system (100^3 grid, n = 10^6,
-7-point stencil stored as CSR, affine forcing, Lanczos k = 40, dt = 0.02,
-2000 steps, FP64) on one GPU.
+"""Throughput of one verification of the matrix-free 3D heat system (1000^3
+grid, n = 10^9, 7-point stencil applied on the fly, affine forcing, Lanczos
+k = 20, dt = 0.01, 500 steps, FP64) on one GPU: the largest configuration
+that fits one MI355X.
 
 A step is the whole path on one batch of input already resident in HBM:
 plan (run split, start vectors), the Krylov process of every run, the
@@ -13,10 +14,13 @@ Prints one JSON line.  Options:
   --steps K       timed steps (default 20)
   --warmup W      untimed steps first (default 3)
   --no-cpu-baseline   skip timing the CPU oracle
-  --m M           grid edge (default 100)
-  --workload W    heat3d_csr (the benchmark line), heat3d_stencil (1000^3 matrix-free),
+  --m M           grid edge (default 1000 for heat3d_stencil, 100 otherwise)
+  --workload W    heat3d_stencil (1000^3 matrix-free, the benchmark line),
+                  heat3d_csr (100^3 CSR; its working set fits the 256 MB MALL),
                   heat1d, conv_diff3d, heat3d_paper, heat3d_many_inputs (eight
                   initial-space columns, one output)
+  --no-fp32-side  heat3d_stencil: skip the FP32-basis side measurement (ratio to
+                  FP64 and per-output error against the FP64 basis)
   --route R       forward (one run per column of E) or transposed (one run of A^T
                   per output row, Section 4.1); default transposed for
                   heat3d_many_inputs, forward otherwise
@@ -48,8 +52,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-# sources of the 100^3 CSR mat-vec whose counters profiles/ records
-KERNEL_SOURCES = ("kry_sell.hip", "kry_device.h", "kry_internal.h")
+# the last-level cache (MALL, Infinity Cache) of MI355X: a kernel whose bytes
+# per launch fit in it is not measured against HBM alone
+MALL_BYTES = 256 * 2**20
+# per workload: the committed rocprofv3 counter summary of the dominant
+# kernel and the sources that kernel is built from
+COUNTER_PROFILES = {
+    "heat3d_stencil": ("stencil_march_heat3d_m1000_pmc.md", ("kry_lanczos.hip", "kry_device.h", "kry_internal.h")),
+    "heat3d_csr": ("spmv_sell_heat3d_m100_pmc.md", ("kry_sell.hip", "kry_device.h", "kry_internal.h")),
+}
 
 
 def log(msg):
@@ -75,10 +86,11 @@ def main():
     ap.add_argument("--k", type=int, default=None, help="Krylov dimension (matrix-free paper heat only)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="skip the second timed pass with per-kernel events (long runs)")
-    ap.add_argument("--workload", default="heat3d_csr",
+    ap.add_argument("--workload", default="heat3d_stencil",
                     choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper",
                              "heat3d_many_inputs", "serve"],
-                    help="heat3d_csr is the benchmark line; the others are measured the same way")
+                    help="heat3d_stencil is the benchmark line; the others are measured the same way")
+    ap.add_argument("--no-fp32-side", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--route", default=None, choices=["forward", "transposed"])
     ap.add_argument("--check", default="box", choices=["box", "lp"])
@@ -160,13 +172,24 @@ def main():
     dom = kern.get(dom_name, {})
     achieved = dom.get("GBps", 0.0)
     traffic = None
-    if args.workload == "heat3d_csr" and (args.m or 100) == 100 and not f32:
-        traffic = counter_traffic(os.path.join(ROOT, "profiles", "spmv_sell_heat3d_m100_pmc.md"))
+    default_m = {"heat3d_stencil": 1000}.get(args.workload, 100)
+    if args.workload in COUNTER_PROFILES and (args.m or default_m) == default_m and not f32:
+        fname, sources = COUNTER_PROFILES[args.workload]
+        traffic = counter_traffic(os.path.join(ROOT, "profiles", fname), sources)
+    fp32_side = None
+    if args.workload == "heat3d_stencil" and not f32 and not args.no_fp32_side and not args.graph:
+        torch.cuda.empty_cache()
+        log("FP32-basis side measurement on the same workload")
+        fp32_side = fp32_side_measure(torch, kry, p, dsys, m, method)
 
     cpu = None
-    if not args.no_cpu_baseline and p.n <= 2_000_000:
-        log("timing the CPU oracle on the same workload (one whole verification)")
-        cpu = cpu_baseline(p, transposed, args.check)
+    if not args.no_cpu_baseline:
+        if args.workload == "heat3d_stencil":
+            log("timing the CPU oracle on the locality sub-grids (the same result)")
+            cpu = cpu_baseline_subgrids(p)
+        elif p.n <= 2_000_000:
+            log("timing the CPU oracle on the same workload (one whole verification)")
+            cpu = cpu_baseline(p, transposed, args.check)
 
     out = {
         "metric": "Krylov step HBM GB/s (% peak); verified time-steps/s vs plain FP64; p99 query latency",
@@ -192,12 +215,16 @@ def main():
                    "error_target": args.error_target or None,
                    "matrix": ("prepared once (sliced-ELL copy and norm shared by every verification)" if prepared
                               else ("built by every plan" if p.kind == "csr" else "matrix-free stencil"))},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+        "roofline": {"bound": "hbm" if (dom.get("bytes") or 0) > MALL_BYTES else "mall",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dom_name,
-                     "bytes_per_launch": dom.get("bytes")},
+                     "bytes_per_launch": dom.get("bytes"),
+                     "note": (None if (dom.get("bytes") or 0) > MALL_BYTES else
+                              "bytes per launch fit the 256 MB MALL: an effective rate, not HBM alone")},
         "ms_per_step_with_kernel_events": m["ms_per_step_ev"],
         "kernels": kern,
         "fp64_reference": fp64_ref,
+        "fp32_basis_side": fp32_side,
         "error_control": m.get("error_control"),
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
@@ -437,7 +464,7 @@ def describe(p, nruns, precision, method_name="auto"):
     return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} {prec}"
 
 
-def counter_traffic(path):
+def counter_traffic(path, sources):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 counter summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
     each scaled by what the same counter reads for a plain 1 GiB device copy.
@@ -453,7 +480,7 @@ def counter_traffic(path):
             vals[key.strip()] = val.strip().strip("`")
     try:
         h = hashlib.sha256()
-        for f in KERNEL_SOURCES:
+        for f in sources:
             h.update(open(os.path.join(ROOT, "paper_1804_01583_amd", "csrc", f), "rb").read())
         if h.hexdigest() != vals["kernel_source_sha256"]:
             return None
@@ -462,6 +489,95 @@ def counter_traffic(path):
         return rd + wr
     except (KeyError, ValueError):
         return None
+
+
+def basis_of(kry, dsys, precision, method):
+    """One verification's basis (steps+1, o, columns) on the host."""
+    plan = kry.Plan(dsys, precision=precision, method=method)
+    b = plan.basis()
+    plan.close()
+    return b
+
+
+def per_output_error(b, ref):
+    """Per (output row, basis column): max over steps of |b - ref| divided by
+    max over steps of |ref| (0 where both are exactly zero)."""
+    import numpy as np
+    out = []
+    for q in range(ref.shape[1]):
+        row = []
+        for r in range(ref.shape[2]):
+            scale = float(np.abs(ref[:, q, r]).max())
+            err = float(np.abs(b[:, q, r] - ref[:, q, r]).max())
+            row.append(err / scale if scale > 0 else (0.0 if err == 0.0 else float("inf")))
+        out.append(row)
+    return out
+
+
+def fp32_side_measure(torch, kry, p, dsys, m64, method, steps=3, warmup=1):
+    """The FP32-basis mode on the same workload (a few timed verifications):
+    its throughput against the FP64 line and the error of every output
+    against the FP64 basis."""
+    m32 = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS, steps, warmup, method, kernel_events=False)
+    torch.cuda.empty_cache()
+    b32 = basis_of(kry, dsys, kry.KRY_FP32_BASIS, method)
+    torch.cuda.empty_cache()
+    b64 = basis_of(kry, dsys, kry.KRY_FP64, method)
+    torch.cuda.empty_cache()
+    return {"value": m32["value"], "unit": "verified time-steps/s", "ms_per_step": m32["ms_per_step"],
+            "steps": steps, "warmup": warmup, "ratio_over_fp64": m32["value"] / m64["value"],
+            "max_rel_err_per_output": per_output_error(b32, b64),
+            "error_definition": "per (output row, basis column): max over steps of |FP32-basis - FP64| / "
+                                "max over steps of |FP64| (0 where both are exactly zero)",
+            "verdict": {"first_step": m32["verdict"]["first_step"], "row": m32["verdict"]["row"]}}
+
+
+def host_cores():
+    """Physical cores this process may use, at most 16 (one GPU's share of
+    the host)."""
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False) or 1
+    except Exception:   # pragma: no cover
+        phys = os.cpu_count() or 1
+    return max(1, min(phys, len(os.sched_getaffinity(0)), 16))
+
+
+def cpu_baseline_subgrids(p):
+    """The oracle on the matrix-free heat system through its locality
+    sub-grids: every run of the 1000^3 system equals the same run on the
+    sub-grid of its start box dilated by k + 1 cells (outputs outside it are
+    exactly zero), so the oracle computes the whole verification's basis
+    from those.  Timed at one thread and at the host's physical cores."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:   # pragma: no cover
+        threadpool_limits = None
+    import contextlib
+    import oracle
+    import workloads as W
+    roles = ["gen", "affine"] if p.has_forcing else ["gen"]
+    subs = [(role, W.heat3d_stencil_subgrid(p, role)[0]) for role in roles]
+    live = [sub for _, sub in subs if sub is not None]
+
+    def run(threads):
+        ctx = threadpool_limits(limits=threads) if threadpool_limits else contextlib.nullcontext()
+        with ctx:
+            t0 = time.perf_counter()
+            for sub in live:
+                oracle.verify(sub)
+            return time.perf_counter() - t0
+
+    cores = host_cores()
+    t1 = run(1)
+    tc = run(cores) if cores > 1 else t1
+    cols = len(roles)
+    desc = ", ".join(f"{role}: {'sub-grid ' + 'x'.join(map(str, sub.grid)) + f' ({sub.n} states)' if sub else 'no output within reach, exactly zero'}"
+                     for role, sub in subs)
+    return {"value": (p.steps + 1) * cols / tc, "unit": "verified time-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole verification's basis ({cols} columns x {p.steps + 1} time points) by the oracle "
+                      f"on the locality sub-grids ({desc}); {tc:.1f} s at {cores} threads",
+            "single_thread": {"value": (p.steps + 1) * cols / t1, "cores": 1, "seconds": t1}}
 
 
 def cpu_baseline(p, transposed=False, check="box"):

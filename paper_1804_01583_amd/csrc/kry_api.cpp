@@ -72,6 +72,18 @@ void guarded_void(F&& body) noexcept {
     }
 }
 
+// hipMalloc that leaves no error behind: a failed allocation also sets the
+// thread's last HIP error, which the next launch's hipGetLastError() would
+// report as that launch's own failure.
+hipError_t device_alloc(void** p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+    }
+    return e;
+}
+
 #define KRY_HIP(expr)                                                                          \
     do {                                                                                       \
         hipError_t e_ = (expr);                                                                \
@@ -832,7 +844,7 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
         plan->ws = static_cast<char*>(workspace);
     } else {
         void* p = nullptr;
-        if (hipMalloc(&p, Y.total) != hipSuccess) {
+        if (device_alloc(&p, Y.total) != hipSuccess) {
             return fail(KRY_ENOMEM, "hipMalloc of " + std::to_string(Y.total) + " bytes failed");
         }
         plan->ws = static_cast<char*>(p);
@@ -1349,6 +1361,7 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) 
             J.basis = plan->basis();
             J.nruns = plan->nruns;
             J.run0 = run;
+            J.nonfinite = msc[MISC_NONFINITE] != 0.0 ? 1 : 0;
             double hn = 0.0;
             e = timed("dense_expm", s, [&] { return dense_expm_steps(J, plan->at<double>(Y.dws), &hn, s); });
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("dense stage: ") + hipGetErrorString(e));
@@ -1476,7 +1489,7 @@ kry_status kry_check_lp_safety(kry_plan_t* plan, const double* G, const double* 
         const int64_t nver = 2 + kLpMaxD + kMaxO;
         if (!plan->lp_mem) {
             void* p = nullptr;
-            if (hipMalloc(&p, (size_t)(nin + nrec + nver) * sizeof(double)) != hipSuccess)
+            if (device_alloc(&p, (size_t)(nin + nrec + nver) * sizeof(double)) != hipSuccess)
                 return fail(KRY_ENOMEM, "LP buffers: hipMalloc failed");
             plan->lp_mem = static_cast<char*>(p);
         }
@@ -1716,7 +1729,7 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
         const size_t o_part = take((size_t)nb * 8), o_norm = take(8);
         const size_t head = off;
         char* tmp = nullptr;
-        if (hipMalloc((void**)&tmp, head) != hipSuccess) return fail(KRY_ENOMEM, "prepared matrix: allocation failed");
+        if (device_alloc((void**)&tmp, head) != hipSuccess) return fail(KRY_ENOMEM, "prepared matrix: allocation failed");
         auto bail = [&](kry_status code, const std::string& msg) {
             (void)hipStreamSynchronize(s);
             (void)hipFree(tmp);
@@ -1741,7 +1754,7 @@ kry_status kry_matrix_create(const kry_system* sys, int32_t precision, void* hip
         const size_t o_col = take((size_t)total * (narrow ? 2 : 4)), o_val = take((size_t)total * esz);
         kry_matrix* M = new kry_matrix();
         M->bytes = off;
-        if (hipMalloc((void**)&M->mem, M->bytes) != hipSuccess) {
+        if (device_alloc((void**)&M->mem, M->bytes) != hipSuccess) {
             delete M;
             return bail(KRY_ENOMEM, "prepared matrix: allocation failed");
         }

@@ -140,14 +140,16 @@ namespace {
 __global__ __launch_bounds__(256) void k_fill(double* p, int64_t count, double v) {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count; t += (int64_t)gridDim.x * 256) p[t] = v;
 }
-// basis[s][r][run0 + c] = NaN for every step, row and c < w: the run's
-// exponential is undefined (non-finite H), which the box check reports.
-__global__ __launch_bounds__(256) void k_nan_columns(double* basis, int64_t steps, int o, int nruns, int run0, int w) {
+// basis[s][r][run0 + c] = v for every step, row and c < w: NaN when the
+// run's exponential is undefined (non-finite H), which the box check
+// reports; 0 for a run whose start vector is zero.
+__global__ __launch_bounds__(256) void k_fill_columns(double* basis, int64_t steps, int o, int nruns, int run0, int w,
+                                                      double v) {
     const int64_t total = (steps + 1) * o * w;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = i % w;
         const int64_t sr = i / w;
-        basis[sr * nruns + run0 + c] = __builtin_nan("");
+        basis[sr * nruns + run0 + c] = v;
     }
 }
 
@@ -240,6 +242,11 @@ hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hi
     double* anch = Z + (int64_t)J.B * J.o * m;
     double* nrm = anch + (int64_t)J.nanch * m * J.w;
     hipError_t e;
+    if (J.nonfinite || J.m == 0) {
+        hipLaunchKernelGGL(k_fill_columns, dim3(256), dim3(256), 0, s, J.basis, J.steps, J.o, J.nruns, J.run0, J.w,
+                           J.nonfinite ? __builtin_nan("") : 0.0);
+        return hipGetLastError();
+    }
     // |H dt|_1 -> the number of halvings
     hipLaunchKernelGGL(k_norm1, dim3(1), dim3(256), 0, s, m, J.H, J.ldh, nrm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -249,7 +256,8 @@ hipError_t dense_expm_steps(const DenseJob& J, double* ws, double* host_norm, hi
     if (!std::isfinite(nx)) {
         // a non-finite value reached H: the run's basis columns become NaN
         // and the box check reports KRY_ENUMERIC in its verdict
-        hipLaunchKernelGGL(k_nan_columns, dim3(256), dim3(256), 0, s, J.basis, J.steps, J.o, J.nruns, J.run0, J.w);
+        hipLaunchKernelGGL(k_fill_columns, dim3(256), dim3(256), 0, s, J.basis, J.steps, J.o, J.nruns, J.run0, J.w,
+                           __builtin_nan(""));
         return hipGetLastError();
     }
     int sq = 0;

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     if (keff <= 0) m = 0;                    // zero start vector: the run contributes nothing
     if (threadIdx.x == 0) {
         E.msize[job] = m;
-        E.scale[job] = bordered ? 1.0 : sc[E.L.beta + 0];
+        // a non-finite start norm or coefficient makes the run's columns NaN
+        // (the assembly scales even an empty run), so the box check reports it
+        E.scale[job] = sc[E.L.misc + MISC_NONFINITE] != 0.0 ? __builtin_nan("") :
+                       (bordered ? 1.0 : sc[E.L.beta + 0]);
     }
     if (m == 0) return;
     const int mm = m + (m & 1);
@@ -345,10 +348,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
                     if (q < A.o && in) y[q] = fma(zv[q][t], av[t], y[q]);
             }
         }
-        const double sc = A.scale[run];
-#pragma unroll
-        for (int q = 0; q < kMaxO; ++q) y[q] *= sc;
     }
+    const double sc = A.scale[run];
+#pragma unroll
+    for (int q = 0; q < kMaxO; ++q) y[q] *= sc;
     if (A.out_col) {
         const int64_t row = s * A.o_out + A.job_run[run];
 #pragma unroll

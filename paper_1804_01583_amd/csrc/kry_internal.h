@@ -242,6 +242,7 @@ struct DenseJob {
     int64_t steps;
     double* basis;               // [(steps+1)][o][nruns]
     int32_t nruns, run0;
+    int32_t nonfinite;           // the run met a non-finite value: its columns become NaN
 };
 size_t dense_workspace_doubles(int m, int o, int w, int B, int nanch);
 // Enqueues the whole stage; waits once for |H|_1 (the number of squarings).

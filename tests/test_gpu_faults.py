@@ -99,3 +99,22 @@ def test_kry_plan_short_form_matches_plan_create():
     ref = gpu_verify(p)
     assert np.array_equal(out.numpy(), ref["basis"])
     assert v.first_step == ref["verdict"]["first_step"]
+
+
+def test_zero_generator_in_the_dense_stage():
+    # k > 56 sends every run through the dense stage; a zero generator has
+    # no Krylov space there either and its column is exactly zero
+    require_gpu()
+    p = W.heat1d(steps=50)
+    p.k = 80
+    p.gens = [W.Generator(W.segments_from_ranges([(0, 5)], 0.0), 0.0, 1.0),
+              W.Generator(W.segments_from_ranges([(0, 10)], 1.0), 0.0, 0.1)]
+    p.C = [W.segments_from_ranges([(0, 30)], 1.0 / 30.0)]
+    p.unsafe = np.array([[0.9, math.inf]])
+    print(f"[gpu] zero generator dense stage n={p.n} k={p.k}", flush=True)
+    got = gpu_verify(p)
+    ref = oracle.verify(p)
+    assert [r["k_eff"] for r in got["runs"]][0] == 0
+    assert np.all(got["basis"][:, :, 0] == 0.0)
+    assert_basis_parity(got["basis"], ref["basis"])
+    assert got["verdict"]["status"] == kry.KRY_OK

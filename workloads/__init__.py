@@ -467,6 +467,57 @@ def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
                    note="matrix-free 3D heat with affine forcing")
 
 
+def _clip_box(box, lo, hi):
+    return tuple((max(a, l), min(b, h)) for (a, b), l, h in zip(box, lo, hi))
+
+
+def heat3d_stencil_subgrid(full: Problem, role: str, k: Optional[int] = None):
+    """One run of a heat3d_stencil problem ("gen": the generator over the
+    heated region; "affine": the forcing) restated on a small sub-grid with
+    the same result.  After j Krylov steps from a start vector supported in
+    a box, every basis vector is supported within grid distance j of that
+    box (A is a 7-point stencil), so the run equals the same run on the
+    sub-grid spanned by the box dilated by k + 1 cells (its own zero faces
+    are never reached), with the outputs restricted to that sub-grid.
+    Returns (sub_problem or None, rows): rows[q] is the sub-problem's output
+    index of full output row q, or None when row q lies outside the sub-grid
+    (its basis entries are exactly zero); sub_problem is None when no
+    output row meets the sub-grid."""
+    m = full.meta["m"]
+    k = full.k if k is None else k
+    start_box = full.meta["gen_box"] if role == "gen" else full.meta["forcing_box"]
+    lo = [max(a - (k + 1), 0) for a, _ in start_box]
+    hi = [min(b + (k + 1), m) for _, b in start_box]
+    grid = tuple(h - l for l, h in zip(lo, hi))
+
+    def shift(box):
+        return tuple((a - l, b - l) for (a, b), l in zip(box, lo))
+
+    mid = m // 2
+    gcount = int(np.prod([b - a for a, b in full.meta["gen_box"]]))
+    C, rows = [], []
+    for q, box in enumerate([((mid, mid + 1),) * 3, full.meta["gen_box"]]):
+        cb = _clip_box(box, lo, hi)
+        if all(b > a for a, b in cb):
+            rows.append(len(C))
+            C.append(box_segments(grid, shift(cb), 1.0 if q == 0 else 1.0 / gcount))
+        else:
+            rows.append(None)
+    if not C:
+        return None, rows
+    sb = shift(start_box)
+    gens, bseg = [], None
+    if role == "gen":
+        g = full.gens[0]
+        gens = [Generator(box_segments(grid, sb, 1.0), zc=g.zc, radius=g.radius)]
+    else:
+        bseg = box_segments(grid, sb, 0.1)
+    sub = Problem("heat3d_stencil_subgrid", int(np.prod(grid)), "stencil7", True, gens, C,
+                  np.array([[math.inf, math.inf]] * len(C)), k=k, dt=full.dt, steps=full.steps,
+                  b_seg=bseg, grid=grid, coef=full.coef, meta={"offset": tuple(lo), "role": role})
+    return sub, rows
+
+
 # ---------------------------------------------------------------------------
 # Small random problems for parity edge cases
 # ---------------------------------------------------------------------------
