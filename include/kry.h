@@ -267,6 +267,32 @@ kry_status kry_project_expm(kry_plan_t* plan, double* basis_out);
 kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kry_verdict* out,
                                 double* z_out);
 
+/* kry_verify_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): kry_plan_create + kry_project_expm + kry_check_box_safety in
+ * one call, every argument as there, with the plan's workspace in the
+ * library's fixed per-device scratch array of KRY_NOALLOC_SCRATCH_BYTES
+ * (128 MiB, held by each device the library runs on until the process ends)
+ * instead of a caller buffer or an allocation.  The call makes no device or
+ * pinned-host allocation and frees nothing on the device (its host-side
+ * bookkeeping uses the C++ heap).
+ *  basis_out: host or device pointer to (steps+1) * o * nruns doubles, or
+ *     NULL (the basis then stays in the scratch array until the next call).
+ *  unsafe, verdict, z_out: as for kry_check_box_safety.
+ * Sizes whose workspace (kry_plan_workspace) exceeds the scratch array give
+ * KRY_ENOMEM naming the bytes needed, before any device work; a CSR system
+ * is best passed prepared (kry_matrix_create) so the sliced-ELL copy does
+ * not take scratch space.  No error target, graph mode or LP check.
+ * Waits for hip_stream before returning.  Every call on one device shares
+ * that device's array and leaves its contents behind (each call initialises
+ * what it reads): calls that overlap on one device (other host threads,
+ * other streams) race and must be serialised by the caller. */
+#define KRY_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+kry_status kry_verify_noalloc(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
+                              const kry_segs* C, int32_t o, int32_t k, double dt, int64_t steps, int32_t precision,
+                              int32_t method, int32_t block_p, const kry_interval* unsafe, double* basis_out,
+                              kry_verdict* verdict, double* z_out, void* hip_stream);
+
 /* kry_plan_set_graph -- graph mode (on != 0): the next kry_project_expm
  * records everything it enqueues (the Krylov batches, the small stage and
  * the assembly) as one HIP graph and launches it; later calls launch the

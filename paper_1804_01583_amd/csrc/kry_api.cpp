@@ -1384,6 +1384,37 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) 
 
 }  // namespace
 
+// The one-call entry point that allocates nothing keeps its plan workspace
+// in this fixed array.  Each device holds its own copy for the life of the
+// process; host code only ever uses the address that hipGetSymbolAddress
+// returns for the current device (the array's name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[KRY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+kry_status scratch_address(void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    KRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(KRY_EDEVICE, "device ordinal out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        KRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(KRY_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return KRY_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 kry_status kry_project_expm(kry_plan_t* plan, double* basis_out) {
@@ -1461,6 +1492,30 @@ kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kr
                 if (plan->col_role[c] == 0) z_out[g++] = v[6 + c];
         }
         return KRY_OK;
+    });
+}
+
+kry_status kry_verify_noalloc(const kry_system* sys, const kry_gen* gens, int32_t ngen, const double* center,
+                              const kry_segs* C, int32_t o, int32_t k, double dt, int64_t steps, int32_t precision,
+                              int32_t method, int32_t block_p, const kry_interval* unsafe, double* basis_out,
+                              kry_verdict* verdict, double* z_out, void* hip_stream) {
+    return guarded("kry_verify_noalloc", [&]() -> kry_status {
+        if (!unsafe || !verdict) return fail(KRY_EINVAL, "unsafe and verdict must be non-NULL");
+        void* ws = nullptr;
+        kry_status st = scratch_address(&ws);
+        if (st != KRY_OK) return st;
+        // plan_create checks the sizes against the scratch array before any
+        // device work (KRY_ENOMEM naming the bytes needed when they exceed it)
+        kry_plan_t* plan = nullptr;
+        st = plan_create(sys, gens, ngen, center, nullptr, false, C, o, k, dt, steps, precision, method, block_p, ws,
+                         (size_t)KRY_NOALLOC_SCRATCH_BYTES, hip_stream, &plan);
+        if (st != KRY_OK) return st;
+        st = kry_project_expm(plan, basis_out);
+        if (st == KRY_OK) st = kry_check_box_safety(plan, unsafe, verdict, z_out);
+        // the plan's host state goes; the scratch array keeps its contents
+        (void)hipStreamSynchronize(plan->stream);
+        delete plan;
+        return st;
     });
 }
 

@@ -1,7 +1,7 @@
 """ctypes binding of libkry.so (include/kry.h).  Argument marshalling only:
 every step of the verification path runs in the library's HIP kernels.
 
-The functions keep the C names (kry_plan, kry_plan_create, kry_project_expm,
+The functions keep the C names (kry_plan, kry_plan_create, kry_verify_noalloc, kry_project_expm,
 kry_check_box_safety, kry_footprint, kry_plan_workspace, kry_plan_runs, kry_plan_krylov,
 kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy, kry_matrix_create,
 kry_matrix_bytes, kry_matrix_destroy).  ``Plan`` is a small owner object that keeps the device
@@ -74,6 +74,10 @@ def _load():
     lib.kry_plan.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
                              ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
                              ct.c_int32, ct.c_int32, ct.c_int32, P, ct.POINTER(P)]
+    lib.kry_verify_noalloc.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32, P,
+                                       ct.POINTER(KrySegs), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int64,
+                                       ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(KryInterval), P,
+                                       ct.POINTER(KryVerdict), P, P]
     lib.kry_plan_create_transposed.argtypes = [ct.POINTER(KrySystem), ct.POINTER(KryGen), ct.c_int32,
                                                ct.POINTER(KrySegs), ct.POINTER(KrySegs), ct.c_int32, ct.c_int32,
                                                ct.c_double, ct.c_int64, ct.c_int32, ct.c_int32, P, ct.c_size_t, P,
@@ -106,7 +110,7 @@ def _load():
     lib.kry_profile_enable.argtypes = [ct.c_int32]
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
-    for f in ("kry_plan", "kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed",
+    for f in ("kry_plan", "kry_plan_create", "kry_verify_noalloc", "kry_plan_create_transposed", "kry_footprint_transposed",
               "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
               "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
@@ -117,7 +121,7 @@ def _load():
 
 lib = _load()
 
-EXPORTED = ["kry_plan", "kry_plan_create", "kry_plan_create_transposed", "kry_footprint_transposed",
+EXPORTED = ["kry_plan", "kry_plan_create", "kry_verify_noalloc", "kry_plan_create_transposed", "kry_footprint_transposed",
             "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
             "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
             "kry_plan_error",
@@ -164,6 +168,25 @@ def kry_plan(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Sequence[
     _check(lib.kry_plan(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps, precision,
                         method, block_p, stream_ptr, ct.byref(out)))
     return out.value
+
+
+def kry_verify_noalloc(system: KrySystem, gens: Sequence[KryGen], center_ptr, C: Sequence[KrySegs], k: int,
+                       dt: float, steps: int, unsafe: np.ndarray, basis_out_ptr=None, precision=KRY_FP64,
+                       method=KRY_AUTO, block_p=0, stream_ptr=None):
+    """Plan, projection and box check in one call on the library's scratch
+    array; returns (verdict, z)."""
+    garr = (KryGen * max(len(gens), 1))(*gens)
+    carr = (KrySegs * len(C))(*C)
+    U = (KryInterval * len(unsafe))(*[KryInterval(float(a), float(b)) for a, b in unsafe])
+    v = KryVerdict()
+    z = np.zeros(max(len(gens), 1))
+    _check(lib.kry_verify_noalloc(ct.byref(system), garr, len(gens), center_ptr, carr, len(C), k, dt, steps,
+                                  precision, method, block_p, U, basis_out_ptr, ct.byref(v), z.ctypes.data,
+                                  stream_ptr))
+    return v, z[:len(gens)]
+
+
+KRY_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 def kry_plan_create_transposed(system_t: KrySystem, gens: Sequence[KryGen], center: Optional[KrySegs],

@@ -133,6 +133,17 @@ def test_error_control_entry_points_reject_null_plan():
     assert ei.value.status == kry.KRY_EINVAL
 
 
+def test_noalloc_entry_point_rejects_missing_outputs():
+    # checked on the host before the scratch array is looked up
+    import ctypes as ct
+    from paper_1804_01583_amd import kry
+    s = kry.KrySystem()
+    st = kry.lib.kry_verify_noalloc(ct.byref(s), None, 0, None, None, 1, 10, 0.1, 10, 0, 0, 0, None, None, None,
+                                    None, None)
+    assert st == kry.KRY_EINVAL
+    assert b"non-NULL" in kry.lib.kry_last_error()
+
+
 def test_prepared_matrix_entry_points_reject_bad_arguments():
     from paper_1804_01583_amd import kry
     import ctypes as ct
