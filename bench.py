@@ -58,8 +58,8 @@ MALL_BYTES = 256 * 2**20
 # per workload: the committed rocprofv3 counter summary of the dominant
 # kernel and the sources that kernel is built from
 COUNTER_PROFILES = {
-    "heat3d_stencil": ("stencil_march_heat3d_m1000_pmc.md", ("kry_lanczos.hip", "kry_device.h", "kry_internal.h")),
-    "heat3d_csr": ("spmv_sell_heat3d_m100_pmc.md", ("kry_sell.hip", "kry_device.h", "kry_internal.h")),
+    "heat3d_stencil": ("lz1_march_heat3d_m1000_pmc.md", ("kry_lz1.hip", "kry_device.h", "kry_internal.h")),
+    "heat3d_csr": ("lz1_sell_heat3d_m100_pmc.md", ("kry_lz1.hip", "kry_device.h", "kry_internal.h")),
 }
 
 
@@ -390,6 +390,11 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         # iterations j = 1..k (j stored vectors read per pass)
         "arn_dots": vec * (1 + (k + 1) / 2.0),
         "arn_update": vec * (2 + (k + 1) / 2.0),
+        # one-pass step: read the pair (u_{j-1}, r_j), write (u_j, r_{j+1})
+        "lz1_sell": mat_sell + 4 * vec,
+        "lz1_stencil": 4 * vec,
+        "lz1_march": 4 * vec,
+        "lz1_tail": 2 * vec,                                  # read the last pair
     }
     for name, b in per_launch.items():
         if name in kern:
@@ -421,7 +426,10 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
                 "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
                 "dom_name": dom_name, "error_control": used or None, "krylov_runs": krylov_runs["n"]}
-    mv = ("spmv_sell" if "spmv_sell" in kern else "spmv_csr") if p.kind == "csr" else "spmv_stencil"
+    if p.kind == "csr":
+        mv = next((n_ for n_ in ("lz1_sell", "spmv_sell", "spmv_csr") if n_ in kern), "spmv_csr")
+    else:
+        mv = next((n_ for n_ in ("lz1_march", "lz1_stencil", "spmv_stencil") if n_ in kern), "spmv_stencil")
     # the roofline kernel: the mat-vec, or the one with the most time when a
     # stored-basis pass outweighs it
     dom_name = mv

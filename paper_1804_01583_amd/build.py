@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libkry.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["kry_api.cpp", "kry_lanczos.hip", "kry_arnoldi.hip", "kry_expm.hip", "kry_block.hip", "kry_dense.hip", "kry_sell.hip", "kry_errctl.hip",
+SOURCES = ["kry_api.cpp", "kry_lanczos.hip", "kry_arnoldi.hip", "kry_expm.hip", "kry_block.hip", "kry_dense.hip", "kry_sell.hip", "kry_errctl.hip", "kry_lz1.hip",
            "kry_lp.hip"]
 
 COMMON = [

@@ -129,11 +129,13 @@ Profiler& prof() {
 
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
-    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp";
+    "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp,"
+    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_tail";
 
 // Runs `launch` bracketed by events when profiling is on.  The sliced-ELL
-// mat-vec takes the events into its own launch (hipExtLaunchKernelGGL), so
-// they time the kernel itself rather than the gap around it.
+// mat-vec and the one-pass step's kernels take the events into their own
+// launch (hipExtLaunchKernelGGL), so they time the kernel itself rather than
+// the gap around it.
 template <class F>
 hipError_t timed(const char* name, hipStream_t s, F&& launch) {
     Profiler& P = prof();
@@ -146,7 +148,7 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
     }
     if (!a || !b) return launch();
     hipError_t e;
-    if (std::strcmp(name, "spmv_sell") == 0) {
+    if (std::strcmp(name, "spmv_sell") == 0 || std::strncmp(name, "lz1_", 4) == 0) {
         *ext_events() = ExtEvents{a, b};
         e = launch();
         *ext_events() = ExtEvents{nullptr, nullptr};
@@ -244,7 +246,10 @@ struct Layout {
     size_t eflags = 0;          // error control: per-run stop flags, then the Gershgorin bound
     size_t dH = 0, dP = 0, dS0 = 0, dws = 0;
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
+    bool lz1 = false;     // FP64 three-vector Lanczos: room for the one-pass step (two pair buffers)
     size_t hpart, hcoef, vals32;
+    size_t oflag = 0;     // one-pass step: per-run cancellation flags of a batch
+    size_t ap_stride = 0; // doubles between the two ping-pong partial arrays of the one-pass step
 };
 
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
@@ -286,7 +291,10 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     // Lanczos keeps three vectors per run (Algorithm 4); Arnoldi, and every
     // method in FP32-basis mode (full reorthogonalisation), the whole basis
     if (method == KRY_BLOCK_ARNOLDI) { Y.pmax = 1; Y.stored = false; }
-    Y.nvec = method == KRY_BLOCK_ARNOLDI ? 0 : (Y.stored ? k + 1 : 3);
+    // FP64 three-vector Lanczos may take the one-pass step, whose two pair
+    // buffers (u_{j-1}, r_j) and (u_j, r_{j+1}) need a fourth vector
+    Y.lz1 = (method == KRY_LANCZOS || method == KRY_LANCZOS_PLAIN) && !Y.stored && precision == KRY_FP64;
+    Y.nvec = method == KRY_BLOCK_ARNOLDI ? 0 : (Y.stored ? k + 1 : (Y.lz1 ? 4 : 3));
     Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
     Y.hpart = Y.stored ? take((size_t)k * kMaxP * Y.nblocks * sizeof(double)) : 0;
     Y.hcoef = Y.stored ? take((size_t)k * kMaxP * sizeof(double)) : 0;
@@ -304,7 +312,11 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     }
     Y.nvp = Y.pmax * (1 + o);
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
-    Y.ap_part = take((size_t)std::max(Y.nblocks, Y.march) * kMaxP * sizeof(double));
+    // mat-vec dot partials; the one-pass step keeps two arrays of three
+    // values per run (the previous launch's and its own)
+    Y.ap_stride = (size_t)std::max(Y.nblocks, Y.march) * kMaxP * 3;
+    Y.ap_part = take((Y.lz1 ? 2 * Y.ap_stride : Y.ap_stride / 3) * sizeof(double));
+    Y.oflag = take(kMaxP * sizeof(double));
     Y.scal = take((size_t)nruns * L.stride * sizeof(double));
     // time steps s = b * B + r: B anchors of the Z chain, nanch of the anchor chain
     Y.B = 1;
@@ -516,6 +528,8 @@ struct kry_plan {
     const double* anorm_dev = nullptr;   // ||A||_inf on the device (the plan's or a prepared matrix's)
     double err_eps = 0.0;     // error target of the a-posteriori k (0: fixed k)
     double* hflags = nullptr; // pinned host copy of a batch's stop flags
+    int64_t onepass_batches = 0;   // batches finished by the one-pass step
+    int64_t twopass_redone = 0;    // batches the one-pass step handed back (cancellation)
     hipEvent_t flag_ev = nullptr;
     double lam_plus = 0.0;    // max(0, Gershgorin bound of lambda_max of the symmetric part of A)
 
@@ -1186,7 +1200,76 @@ namespace {
 // Everything kry_project_expm enqueues for the single-vector methods: the
 // Krylov batches, the small stage and the assembly (and, with finish, the
 // copy of the basis).
-kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) {
+// The Krylov process of one batch by the one-pass step (kry_lz1.hip): the
+// start vectors in pair layout, k launches (plus, for the marching stencil,
+// the output projection of each new vector), then the tail that forms
+// u_{k+1}.  Unless `capture`, it waits for the batch and reports in
+// `flagged` whether a run's norm expansion cancelled.
+kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const StartSrc& src, bool capture,
+                         bool* flagged) {
+    const Layout& Y = plan->Y;
+    hipStream_t s = plan->stream;
+    double* X[2] = {static_cast<double*>(plan->vec(0)), static_cast<double*>(plan->vec(2))};
+    double* ap[2] = {plan->ap_part(), plan->ap_part() + Y.ap_stride};
+    const bool csr = plan->sys.kind == KRY_CSR;
+    const bool march = !csr && Y.march > 0;
+    const int32_t nb_step = march ? Y.march : Y.nblocks;
+    double* flag = plan->at<double>(Y.oflag);
+    hipError_t e = launch_fill(flag, kMaxP, 1.0, s);
+    if (e == hipSuccess)
+        e = timed("start", s, [&] {
+            return launch_start(P, plan->o, false, src, plan->T, plan->oset0, X[0], B, s, true);
+        });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
+    StencilArgs S{};
+    if (!csr)
+        S = StencilArgs{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx, plan->sys.cy,
+                        plan->sys.cz, plan->sys.stencil_bc == KRY_BC_INSULATED ? 1 : 0, plan->sys.stencil_exchange};
+    Lz1Args Z{};
+    Z.flag = flag;
+    Z.nb_in = nb_step;
+    const int k = plan->k;
+    for (int j = 1; j <= k; ++j) {
+        const double* xin = X[(j - 1) & 1];
+        double* xout = X[j & 1];
+        Z.ap_in = ap[(j - 1) & 1];
+        Z.ap_out = ap[j & 1];
+        if (csr) {
+            e = timed("lz1_sell", s, [&] {
+                return launch_lz1_sell(P, plan->o, plan->sell, xin, xout, plan->T, plan->oset0, B, Z, j, s);
+            });
+        } else if (march) {
+            e = timed("lz1_march", s, [&] { return launch_lz1_march(P, S, xin, xout, B, Z, j, s); });
+            if (e == hipSuccess && j > 1)
+                e = timed("lz1_proj", s, [&] {
+                    return launch_lz1_proj(P, plan->o, xout, plan->T, plan->oset0, B, j, s);
+                });
+        } else {
+            e = timed("lz1_stencil", s, [&] {
+                return launch_lz1_stencil(P, plan->o, S, xin, xout, plan->T, plan->oset0, B, Z, j, s);
+            });
+        }
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("one-pass step: ") + hipGetErrorString(e));
+    }
+    Z.ap_in = ap[k & 1];
+    Z.ap_out = nullptr;
+    e = timed("lz1_tail", s, [&] {
+        return launch_lz1_tail(P, plan->o, X[k & 1], plan->T, plan->oset0, B, Z, k + 1, s);
+    });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("one-pass tail: ") + hipGetErrorString(e));
+    *flagged = false;
+    if (capture) return KRY_OK;
+    double fl[kMaxP];
+    KRY_HIP(hipMemcpyAsync(fl, flag, P * sizeof(double), hipMemcpyDeviceToHost, s));
+    KRY_HIP(hipStreamSynchronize(s));
+    for (int p = 0; p < P; ++p) *flagged = *flagged || fl[p] == 0.0;
+    return KRY_OK;
+}
+
+// capture: the launches are being recorded into a graph; the one-pass
+// step's fallback is then recorded too and decided on the device (its
+// kernels return at once while every run's flag holds).
+kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, bool capture = false) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
     hipStream_t s = plan->stream;
@@ -1221,11 +1304,30 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) 
             else src.set[p] = plan->bset;
         }
         const bool f32 = plan->f32;
+        const bool lanczos = plan->method == KRY_LANCZOS;
+        // FP64 three-vector Lanczos takes the one-pass step; a batch in which
+        // a run's norm expansion cancelled is computed again two-pass
+        const bool onepass = Y.lz1 && lanczos && plan->err_eps <= 0.0 && env_int("KRY_ONEPASS", 1) != 0 &&
+                             (plan->sys.kind == KRY_STENCIL7 || plan->use_sell);
+        const BatchArgs B_fin = B;           // the finishing kernel never reads stop flags here
+        if (onepass) {
+            bool flagged = false;
+            const kry_status st = onepass_batch(plan, B, P, src, capture, &flagged);
+            if (st != KRY_OK) return st;
+            if (!capture && !flagged) {
+                hipError_t ef = timed("finish", s, [&] { return launch_finish(P, plan->o, B, plan->k, s); });
+                if (ef != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(ef));
+                plan->onepass_batches += 1;
+                r0 += P;
+                continue;
+            }
+            if (capture) B.stop = plan->at<double>(Y.oflag);   // the fallback runs only where a flag was cleared
+            else plan->twopass_redone += 1;
+        }
         hipError_t e = timed("start", s, [&] {
             return launch_start(P, plan->o, f32, src, plan->T, plan->oset0, plan->vec(0), B, s);
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
-        const bool lanczos = plan->method == KRY_LANCZOS;
         int next_check = 4;
         bool poll_pending = false;
         ErrArgs X{};
@@ -1316,7 +1418,7 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish) 
         }
         // with error control the finishing kernel takes the batch's Krylov
         // dimension from the device (the largest stop of its runs)
-        e = timed("finish", s, [&] { return launch_finish(P, plan->o, B, plan->k, s); });
+        e = timed("finish", s, [&] { return launch_finish(P, plan->o, onepass ? B_fin : B, plan->k, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
         r0 += P;
     }
@@ -1430,7 +1532,7 @@ kry_status kry_project_expm(kry_plan_t* plan, double* basis_out) {
             if (!plan->graph_exec) {
                 if (prof().on) return fail(KRY_ENOTSUP, "kernel timing and graph capture exclude each other");
                 KRY_HIP(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal));
-                const kry_status st = enqueue_projection(plan, nullptr, false);
+                const kry_status st = enqueue_projection(plan, nullptr, false, true);
                 hipGraph_t g = nullptr;
                 const hipError_t ec = hipStreamEndCapture(plan->stream, &g);
                 if (st != KRY_OK || ec != hipSuccess) {

@@ -322,6 +322,32 @@ __device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, do
     }
 }
 
+// Diagonal of a stencil row from which neighbours exist: c0, plus for
+// insulated faces each missing neighbour's coefficient, plus the exchange
+// term on the last x plane.
+__device__ __forceinline__ double stencil_diag(const StencilArgs& S, bool xl, bool xh, bool yl, bool yh, bool zl,
+                                               bool zh) {
+    double d = S.c0;
+    if (S.insulated) {
+        if (!xl) d += S.cx;
+        if (!xh) d += S.cx;
+        if (!yl) d += S.cy;
+        if (!yh) d += S.cy;
+        if (!zl) d += S.cz;
+        if (!zh) d += S.cz;
+    }
+    if (!xh) d += S.ex;
+    return d;
+}
+
+// The marching stencil's column: row r = ix * sx + col, its y/z neighbour
+// offsets (0 where the neighbour is missing) and which neighbours exist.
+struct MarchCol {
+    int64_t col, sx;
+    int64_t dyl, dyh, dzl, dzh;
+    bool yl, yh, zl, zh, live, prev;
+};
+
 // ---------------------------------------------------------------------------
 // Segment sets (generators and output rows) a block needs are staged in LDS.
 // The plan precomputes, for every set and logical block, the range of that

@@ -260,8 +260,9 @@ hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int
 hipError_t launch_finish(int P, int O, const BatchArgs& B, int kdone, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // f32 selects E = float storage of the Krylov vectors (and vals32 for CSR).
+// pair: FP64 start in the one-pass step's pair layout [n][2P] (u_0 = 0, r_1 = u_1).
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        void* u, const BatchArgs& B, hipStream_t s);
+                        void* u, const BatchArgs& B, hipStream_t s, bool pair = false);
 hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,
                             const BatchArgs& B, int j, hipStream_t s);
 // Kernel timing: when the pair is set, the next sliced-ELL mat-vec launch
@@ -278,6 +279,31 @@ hipError_t launch_spmv_stencil(int P, bool march, bool f32, const StencilArgs& A
                                const void* uprev, void* w, const BatchArgs& B, int j, hipStream_t s);
 hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,
                         void* w, const BatchArgs& B, int j, hipStream_t s);
+// ---- one-pass Lanczos step (kry_lz1.hip) -----------------------------------
+// Iteration j reads the pair buffer xin = (u_{j-1}, r_j) ([n][2P]) and writes
+// xout = (u_j, r_{j+1}).  Partials ping-pong between two arrays: ap_in holds
+// the previous launch's sigma_{j-1} u_{j-1} . r_j, |r_j|^2 and |u_{j-1}|^2
+// per run ([3P][nb_in]); this launch writes its own to ap_out.
+struct Lz1Args {
+    const double* ap_in;
+    double* ap_out;
+    int32_t nb_in;           // blocks of the launch that wrote ap_in
+    double* flag;            // [P] 1 while a run's |u_j|^2 expansions hold, 0 once one cancelled
+};
+hipError_t launch_lz1_sell(int P, int O, const SellArgs& A, const double* xin, double* xout, const SegTable& T,
+                           int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s);
+hipError_t launch_lz1_stencil(int P, int O, const StencilArgs& S, const double* xin, double* xout,
+                              const SegTable& T, int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j,
+                              hipStream_t s);
+// grid B.ap_nblocks (column blocks); C u_j then comes from launch_lz1_proj
+hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
+                            const Lz1Args& Z, int j, hipStream_t s);
+hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B,
+                           int j, hipStream_t s);
+// after iteration k (j = k + 1): u_{k+1} for stage k, alpha_k
+hipError_t launch_lz1_tail(int P, int O, const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B,
+                           const Lz1Args& Z, int j, hipStream_t s);
+
 hipError_t expm_prepare();
 hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);
 int check_blocks(int64_t steps, int32_t o);

@@ -81,9 +81,10 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ in
 
 // a2: start vectors u_1 of the runs and the partials of |u_1|^2 and C u_1
 // (Algorithm 4, first two statements; the scaling happens in the next kernel).
-template <typename E, int P, int O>
+template <typename E, int P, int O, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int32_t oset0,
                                                   E* __restrict__ u, BatchArgs B) {
+    if (batch_stopped<P>(B)) return;   // a fallback the one-pass step did not need
     constexpr int NV = P * (1 + O);
     __shared__ double s_lds[(kBlock / 64) * NV];
     __shared__ SegStage<P + O> st;
@@ -128,7 +129,18 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
                 val[p] = (double)(E)val[p];          // the norm and projection of the stored vector
                 acc[p] = fma(val[p], val[p], acc[p]);
             }
-            store_row<E, P>(u, r, val);
+            if constexpr (PAIR) {
+                // the one-pass step's pair layout: (u_0 = 0, r_1 = u_1) per row
+                double t[2 * P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    t[p] = 0.0;
+                    t[P + p] = val[p];
+                }
+                store_row<double, 2 * P>(reinterpret_cast<double*>(u), r, t);
+            } else {
+                store_row<E, P>(u, r, val);
+            }
 #pragma unroll
             for (int q = 0; q < O; ++q) {
                 const double cw = cur[P + q].weight(st, P + q, T, r);
@@ -266,24 +278,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(CsrArgs A, const E* __restr
     store_partials<P>(dot, B.ap_part, B.ap_nblocks, s_lds, B.xcd_map);
 }
 
-// Diagonal of a stencil row from which neighbours exist: c0, plus for
-// insulated faces each missing neighbour's coefficient, plus the exchange
-// term on the last x plane.
-__device__ __forceinline__ double stencil_diag(const StencilArgs& S, bool xl, bool xh, bool yl, bool yh, bool zl,
-                                               bool zh) {
-    double d = S.c0;
-    if (S.insulated) {
-        if (!xl) d += S.cx;
-        if (!xh) d += S.cx;
-        if (!yl) d += S.cy;
-        if (!yh) d += S.cy;
-        if (!zl) d += S.cz;
-        if (!zh) d += S.cz;
-    }
-    if (!xh) d += S.ex;
-    return d;
-}
-
 // Matrix-free 7-point stencil version of k_spmv_csr (zero outside the grid),
 // neighbours summed in ascending index order like a CSR row.  Each thread
 // decodes its first row's grid coordinates once and advances them as it
@@ -354,12 +348,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stencil(StencilArgs S, const E*
 // x, x+1 in xm, x0, xp; loads the x+2 plane into nx2 (a clamped in-bounds
 // address past the end: that value is never used, since the x + 1 term is
 // skipped at the last plane).
-struct MarchCol {
-    int64_t col, sx;
-    int64_t dyl, dyh, dzl, dzh;
-    bool yl, yh, zl, zh, live, prev;
-};
-
 template <typename E, int P>
 __device__ __forceinline__ void march_step(const StencilArgs& S, const MarchCol& M, int64_t ix,
                                            const E* __restrict__ ucur, const E* __restrict__ up,
@@ -642,9 +630,13 @@ __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o, int kdone
 
 template <typename E, int P, int O>
 hipError_t launch_start_t(const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
-                          const BatchArgs& B, hipStream_t s) {
-    hipLaunchKernelGGL((k_start<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
-                       static_cast<E*>(u), B);
+                          const BatchArgs& B, bool pair, hipStream_t s) {
+    if (pair)
+        hipLaunchKernelGGL((k_start<double, P, O, true>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
+                           static_cast<double*>(u), B);
+    else
+        hipLaunchKernelGGL((k_start<E, P, O, false>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
+                           static_cast<E*>(u), B);
     return hipGetLastError();
 }
 
@@ -708,8 +700,8 @@ hipError_t launch_spmv_t(const CsrArgs& A, const void* ucur, const void* uprev, 
 
 template <typename E>
 hipError_t launch_start_e(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
-                          const BatchArgs& B, hipStream_t s) {
-    KRY_DISPATCH_PO(launch_start_t, E, P, O, src, T, oset0, u, B, s)
+                          const BatchArgs& B, bool pair, hipStream_t s) {
+    KRY_DISPATCH_PO(launch_start_t, E, P, O, src, T, oset0, u, B, pair, s)
 }
 
 template <typename E>
@@ -784,10 +776,11 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 }
 
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        void* u, const BatchArgs& B, hipStream_t s) {
+                        void* u, const BatchArgs& B, hipStream_t s, bool pair) {
     if (P * (1 + O) > kMaxNV) return hipErrorInvalidValue;
-    return f32 ? launch_start_e<float>(P, O, src, T, oset0, u, B, s)
-               : launch_start_e<double>(P, O, src, T, oset0, u, B, s);
+    if (pair && f32) return hipErrorInvalidValue;
+    return f32 ? launch_start_e<float>(P, O, src, T, oset0, u, B, false, s)
+               : launch_start_e<double>(P, O, src, T, oset0, u, B, pair, s);
 }
 
 hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,

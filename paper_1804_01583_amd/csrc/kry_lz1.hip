@@ -1,0 +1,651 @@
+// The Lanczos iteration in one pass over the vectors (FP64 three-vector
+// Lanczos of Algorithms 3 and 4) on gfx950.
+//
+// The two-launch step of kry_lanczos.hip streams six vector passes per
+// iteration: the mat-vec reads u_j and u_{j-1} and writes w, the sweep reads
+// u_j and w and writes w - alpha_j v_j.  Here an iteration is one launch over
+// a pair buffer that holds, per row, the P entries of u_{j-1} and the P
+// entries of r_j = A v_{j-1} - beta_{j-2} v_{j-2} (the mat-vec result before
+// its alpha term):
+//   u_j     = r_j - alpha_{j-1} sigma_{j-1} u_{j-1}     formed on the fly,
+//                                                     at the row and at every
+//                                                     neighbour it gathers
+//   r_{j+1} = sigma_j A u_j - beta_{j-1} sigma_{j-1} u_{j-1}
+// and it writes the pair (u_j, r_{j+1}): two vectors read and two written,
+// four passes.  alpha_{j-1} is the sum of the previous launch's partials of
+// sigma_{j-1} u_{j-1} . r_j, and |u_j|^2 follows without a pass over u_j:
+//   |u_j|^2 = |r_j|^2 - alpha^2 (2 - sigma_{j-1}^2 |u_{j-1}|^2)
+// (the square of r_j - alpha sigma u_{j-1} expanded with the partials of
+// |r_j|^2 and |u_{j-1}|^2).  The expansion loses accuracy when the new
+// direction is small against r_j (|u_j|^2 well below |r_j|^2: a Krylov space
+// close to invariant, a breakdown); such a step clears the run's flag and
+// the batch is computed again with the two-launch step (whose kernels take
+// the flags as their stop flags, so a fallback recorded into a graph runs
+// only when needed).  The formulas for the
+// vectors are those of the two-launch step, so both produce the same
+// vectors up to the rounding of |u_j|.
+//
+// The partials of |u_j|^2 and C u_j that the finishing kernel turns into P =
+// C V are formed by the launch that forms u_j (stage j - 1).  The marching
+// stencil walks (y, z) columns, which do not follow the row partition of the
+// output segment tables, so there a small kernel sums C u_j over the output
+// segments only.  After the last iteration a tail kernel forms u_{k+1} for
+// its norm and projection, as the last sweep of the two-launch step does.
+#include "kry_device.h"
+
+#include <hip/hip_ext.h>
+
+#include <cmath>
+
+namespace kry {
+
+namespace {
+
+using namespace dev;
+
+// |u_j|^2 expanded below this fraction of |r_j|^2 is not trusted
+constexpr double kLz1Guard = 1e-4;
+
+template <int P>
+__device__ __forceinline__ void load_pair(const double* __restrict__ X, int64_t row, double (&u)[P],
+                                          double (&r)[P]) {
+    double t[2 * P];
+    load_row<double, 2 * P>(X, row, t);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        u[p] = t[p];
+        r[p] = t[P + p];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_pair(double* __restrict__ X, int64_t row, const double (&u)[P],
+                                           const double (&r)[P]) {
+    double t[2 * P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        t[p] = u[p];
+        t[P + p] = r[p];
+    }
+    store_row<double, 2 * P>(X, row, t);
+}
+
+// u_j from the pair (u_{j-1}, r_j): the same expression everywhere it is
+// formed, so the gathered neighbours and the stored vector agree bit for bit
+template <int P>
+__device__ __forceinline__ void form(const double (&coef)[P], const double (&u)[P], const double (&r)[P],
+                                     double (&x)[P]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) x[p] = fma(-coef[p], u[p], r[p]);
+}
+
+// The scalars iteration j starts from, identical in every block (partials
+// summed in a fixed order).  j = 1: |u_1|^2 from the start kernel's stage-0
+// partials, coef = 0.  j >= 2: D = alpha_{j-1}, R = |r_j|^2, N = |u_{j-1}|^2
+// from the previous launch; coef = alpha_{j-1} sigma_{j-1} and |u_j|^2 by the
+// expansion.  With `record`, block 0 records alpha_{j-1}, the stage
+// (beta_{j-1}, sigma_j, k_eff) and the cancellation flag; the tail kernel
+// records alpha_k only (its stage is recorded from the exact norm).
+template <int P>
+__device__ __forceinline__ void lz1_prologue(const BatchArgs& B, const Lz1Args& Z, int j, bool record, double* s_lds,
+                                             double* s_tot, double* s_nrm, double (&coef)[P], double (&sig)[P],
+                                             double (&cprev)[P]) {
+    if (j == 1) {
+        double pacc[P], sig_prev[P], anorm;
+        load_stage_norms<P>(B, 1, pacc, sig_prev, anorm);
+        finish_stage_norms<P>(B, 1, pacc, sig_prev, anorm, s_lds, s_nrm, sig, cprev);
+#pragma unroll
+        for (int p = 0; p < P; ++p) coef[p] = 0.0;
+        return;
+    }
+    double acc[3 * P];
+#pragma unroll
+    for (int i = 0; i < 3 * P; ++i) acc[i] = 0.0;
+    add_strided_partials<3 * P>(Z.ap_in, Z.nb_in, 0, acc);
+    const double t = block_sum<3 * P>(acc, s_lds);
+    if (threadIdx.x < 3 * P) s_tot[threadIdx.x] = t;
+    __syncthreads();
+    const double tau = B.tau_scale * *B.anorm;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const double D = s_tot[p], R = s_tot[P + p], N = s_tot[2 * P + p];
+        const double sp = run_scal(B, p)[B.L.sigma + j - 1];
+        double b2 = R - D * D * (2.0 - sp * sp * N);
+        if (b2 < 0.0) b2 = 0.0;
+        coef[p] = D * sp;
+        const Stage st = stage_update_v(B.L.k, sp, tau, j, b2);
+        sig[p] = st.sigma;
+        cprev[p] = st.cprev;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < P) {
+        const int p = threadIdx.x;
+        const double D = s_tot[p], R = s_tot[P + p], N = s_tot[2 * P + p];
+        double* sc = run_scal(B, p);
+        const double sp = sc[B.L.sigma + j - 1];
+        sc[B.L.alpha + j - 1] = D;
+        if (!isfinite(D)) sc[B.L.misc + MISC_NONFINITE] = 1.0;
+        if (record) {
+            double b2 = R - D * D * (2.0 - sp * sp * N);
+            if (b2 < 0.0) b2 = 0.0;
+            const Stage st = stage_update_v(B.L.k, sp, tau, j, b2);
+            sc[B.L.beta + j - 1] = st.beta;
+            sc[B.L.sigma + j] = st.sigma;
+            if (st.keff >= 0) sc[B.L.misc + MISC_KEFF] = (double)st.keff;
+            if (st.nonfinite) sc[B.L.misc + MISC_NONFINITE] = 1.0;
+            // a live run whose new direction cancelled (a step of at most tau
+            // is a breakdown whatever the rounding: |u_j| <= |r_j| <= tau)
+            if (sp != 0.0 && R > tau * tau && isfinite(b2) && b2 < kLz1Guard * R) Z.flag[p] = 0.0;
+        }
+    }
+}
+
+// Output segments of this block (row partition) staged in LDS, as in the
+// sweep: `any` is false for the (many) blocks that meet no output row.
+template <int O>
+__device__ __forceinline__ bool stage_outputs(SegStage<O>& st, const SegTable& T, int32_t oset0, int lb,
+                                              int nblocks, SegCursor (&cur)[O]) {
+    SegRange own{0, 0};
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < O; ++q) {
+        const int32_t* rq = T.blk + ((int64_t)(oset0 + q) * nblocks + lb) * 2;
+        const SegRange r{rq[0], rq[1]};
+        any = any || r.e > r.b;
+        if ((int)threadIdx.x == q) own = r;
+    }
+    if (any) {
+        stage_segments<O>(st, T, own);
+#pragma unroll
+        for (int q = 0; q < O; ++q) cur[q].init(st, q);
+    }
+    return any;
+}
+
+// One row of a row-partitioned launch: forms u_j, finishes r_{j+1} from the
+// gathered sum, stores the pair and adds the row to the partials
+// (pa: sigma_j u_j . r_{j+1}, |r_{j+1}|^2, |u_j|^2; ps: |u_j|^2, C u_j).
+template <int P, int O, bool MV>
+__device__ __forceinline__ void lz1_row(int64_t r, const double* __restrict__ xin, double* __restrict__ xout,
+                                        const double (&acc)[P], const double (&coef)[P], const double (&sig)[P],
+                                        const double (&cprev)[P], bool any, SegStage<O>& st, SegCursor (&cur)[O],
+                                        const SegTable& T, double (&pa)[3 * P], double (&ps)[P * (1 + O)]) {
+    double up[P], rj[P], uj[P], y[P];
+    load_pair<P>(xin, r, up, rj);
+    form<P>(coef, up, rj, uj);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        ps[p] = fma(uj[p], uj[p], ps[p]);
+        if constexpr (MV) {
+            y[p] = fma(-cprev[p], up[p], sig[p] * acc[p]);
+            pa[p] = fma(sig[p] * uj[p], y[p], pa[p]);
+            pa[P + p] = fma(y[p], y[p], pa[P + p]);
+            pa[2 * P + p] = fma(uj[p], uj[p], pa[2 * P + p]);
+        }
+    }
+    if constexpr (MV) store_pair<P>(xout, r, uj, y);
+    if (any) {
+#pragma unroll
+        for (int q = 0; q < O; ++q) {
+            const double cw = cur[q].weight(st, q, T, r);
+            if (cw != 0.0) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) ps[P + q * P + p] = fma(cw, uj[p], ps[P + q * P + p]);
+            }
+        }
+    }
+}
+
+// Block partials of a row-partitioned launch: the next iteration's
+// (ap_out) and stage j - 1's (|u_j|^2, C u_j); at j = 1 the start kernel has
+// written stage 0 and it is read by this launch, so it is left alone.
+template <int P, int O, bool MV>
+__device__ __forceinline__ void lz1_store(const BatchArgs& B, const Lz1Args& Z, int j, double (&pa)[3 * P],
+                                          double (&ps)[P * (1 + O)], double* s_lds) {
+    if constexpr (MV) store_partials<3 * P>(pa, Z.ap_out, B.nblocks, s_lds, B.xcd_map);
+    if (j > 1) store_partials<P * (1 + O)>(ps, stage_part(B, j - 1), B.nblocks, s_lds, B.xcd_map);
+}
+
+constexpr int lz1_lds(int P, int O) { return (3 * P > P * (1 + O) ? 3 * P : P * (1 + O)) * (kBlock / 64); }
+
+// Sliced-ELL mat-vec step (CSR systems), the layout and gather scheme of
+// k_spmv_sell with the neighbours formed from pairs.  MV = false is the tail:
+// it forms u_{k+1} for stage k and writes nothing else.
+template <int P, int O, bool D, bool MV>
+__global__ __launch_bounds__(kBlock) void k_lz1_sell(SellArgs A, const double* __restrict__ xin,
+                                                     double* __restrict__ xout, SegTable T, int32_t oset0,
+                                                     BatchArgs B, Lz1Args Z, int j) {
+    constexpr int RC = 2;
+    constexpr int KU = 8;
+    __shared__ double s_lds[lz1_lds(P, O)];
+    __shared__ double s_tot[3 * P];
+    __shared__ double s_nrm[P];
+    __shared__ SegStage<O> st;
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
+    const int lane = threadIdx.x & 63;
+    const int64_t span = (int64_t)kBlock * RC;
+    const int nch = (int)((B.rows_per_block + span - 1) / span);
+    int64_t off_nx[RC], srow_nx[RC];
+    int32_t wd_nx[RC];
+    auto slice_info = [&](int ch) {
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int64_t r = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            const int64_t rs = r < r1 ? r : (r0 < B.n ? r0 : 0);
+            const int64_t s = rs / kSlice;
+            off_nx[i] = A.off[s] + lane;
+            wd_nx[i] = A.width[s];
+            srow_nx[i] = s * kSlice + lane;
+        }
+    };
+    const int64_t nlast = A.n - 1;
+    if constexpr (MV) slice_info(0);
+    SegCursor cur[O];
+    const bool any = stage_outputs<O>(st, T, oset0, lb, B.nblocks, cur);
+    double coef[P], sig[P], cprev[P];
+    lz1_prologue<P>(B, Z, j, MV, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    double pa[3 * P], ps[P * (1 + O)];
+#pragma unroll
+    for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < P * (1 + O); ++i) ps[i] = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+        int64_t rr[RC], off[RC], srow[RC];
+        int32_t wd[RC];
+        double acc[RC][P];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            rr[i] = r0 + (int64_t)ch * span + (int64_t)i * kBlock + threadIdx.x;
+            off[i] = off_nx[i];
+            wd[i] = wd_nx[i];
+            srow[i] = srow_nx[i];
+#pragma unroll
+            for (int p = 0; p < P; ++p) acc[i][p] = 0.0;
+        }
+        if constexpr (MV) {
+            if (ch + 1 < nch) slice_info(ch + 1);
+#pragma unroll
+            for (int i = 0; i < RC; ++i) {
+                for (int kb = 0; kb < wd[i]; kb += KU) {
+                    int32_t c[KU];
+                    double a[KU];
+#pragma unroll
+                    for (int u = 0; u < KU; ++u) {
+                        const int k = kb + u < wd[i] ? kb + u : wd[i] - 1;
+                        const int64_t idx = off[i] + (int64_t)k * kSlice;
+                        if constexpr (D) {
+                            const int64_t cc = srow[i] + (int64_t)A.dcol[idx];
+                            c[u] = (int32_t)min(max(cc, (int64_t)0), nlast);
+                        } else {
+                            c[u] = A.col[idx];
+                        }
+                        a[u] = kb + u < wd[i] ? A.val[idx] : 0.0;
+                    }
+                    // unconditional gathers (a slot past the width adds 0 times
+                    // an entry the row already reads)
+#pragma unroll
+                    for (int u = 0; u < KU; ++u) {
+                        double gu[P], gr[P], x[P];
+                        load_pair<P>(xin, c[u], gu, gr);
+                        form<P>(coef, gu, gr, x);
+#pragma unroll
+                        for (int p = 0; p < P; ++p) acc[i][p] = fma(a[u], x[p], acc[i][p]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RC; ++i)
+            if (rr[i] < r1) lz1_row<P, O, MV>(rr[i], xin, xout, acc[i], coef, sig, cprev, any, st, cur, T, pa, ps);
+    }
+    lz1_store<P, O, MV>(B, Z, j, pa, ps, s_lds);
+}
+
+// Row-partitioned 7-point stencil step (grids too small for the marching
+// kernel), neighbours summed in the order of k_spmv_stencil.
+template <int P, int O>
+__global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const double* __restrict__ xin,
+                                                        double* __restrict__ xout, SegTable T, int32_t oset0,
+                                                        BatchArgs B, Lz1Args Z, int j) {
+    __shared__ double s_lds[lz1_lds(P, O)];
+    __shared__ double s_tot[3 * P];
+    __shared__ double s_nrm[P];
+    __shared__ SegStage<O> st;
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
+    SegCursor cur[O];
+    const bool any = stage_outputs<O>(st, T, oset0, lb, B.nblocks, cur);
+    double coef[P], sig[P], cprev[P];
+    lz1_prologue<P>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    double pa[3 * P], ps[P * (1 + O)];
+#pragma unroll
+    for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < P * (1 + O); ++i) ps[i] = 0.0;
+    int64_t r = r0 + threadIdx.x;
+    int64_t iz = r % S.nz;
+    int64_t iy = (r / S.nz) % S.ny;
+    int64_t ix = r / (S.nz * S.ny);
+    const int64_t sx = S.ny * S.nz, sy = S.nz;
+    for (; r < r1; r += kBlock) {
+        const bool xl = ix > 0, xh = ix < S.nx - 1;
+        const bool yl = iy > 0, yh = iy < S.ny - 1;
+        const bool zl = iz > 0, zh = iz < S.nz - 1;
+        double nu[6][P], nr[6][P];
+        load_pair<P>(xin, xl ? r - sx : r, nu[0], nr[0]);
+        load_pair<P>(xin, yl ? r - sy : r, nu[1], nr[1]);
+        load_pair<P>(xin, zl ? r - 1 : r, nu[2], nr[2]);
+        load_pair<P>(xin, zh ? r + 1 : r, nu[3], nr[3]);
+        load_pair<P>(xin, yh ? r + sy : r, nu[4], nr[4]);
+        load_pair<P>(xin, xh ? r + sx : r, nu[5], nr[5]);
+        double own_u[P], own_r[P], own[P];
+        load_pair<P>(xin, r, own_u, own_r);
+        form<P>(coef, own_u, own_r, own);
+        const double diag = stencil_diag(S, xl, xh, yl, yh, zl, zh);
+        double acc[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            double v[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) v[t] = fma(-coef[p], nu[t][p], nr[t][p]);
+            double a = 0.0;
+            if (xl) a = fma(S.cx, v[0], a);
+            if (yl) a = fma(S.cy, v[1], a);
+            if (zl) a = fma(S.cz, v[2], a);
+            a = fma(diag, own[p], a);
+            if (zh) a = fma(S.cz, v[3], a);
+            if (yh) a = fma(S.cy, v[4], a);
+            if (xh) a = fma(S.cx, v[5], a);
+            acc[p] = a;
+        }
+        lz1_row<P, O, true>(r, xin, xout, acc, coef, sig, cprev, any, st, cur, T, pa, ps);
+        iz += kBlock;
+        while (iz >= S.nz) {
+            iz -= S.nz;
+            if (++iy == S.ny) { iy = 0; ++ix; }
+        }
+    }
+    lz1_store<P, O, true>(B, Z, j, pa, ps, s_lds);
+}
+
+// One x step of the marching one-pass stencil.  Pairs at x - 1, x, x + 1 in
+// (um, rm), (u0, r0), (upl, rpl); the x + 2 pair is loaded into (un, rn) (a
+// clamped in-bounds address past the end, never used).
+template <int P>
+__device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const MarchCol& M, int64_t ix,
+                                               const double* __restrict__ xin, double* __restrict__ xout,
+                                               const double (&coef)[P], const double (&sig)[P],
+                                               const double (&cprev)[P], const double (&um)[P],
+                                               const double (&rm)[P], const double (&u0)[P],
+                                               const double (&r0)[P], const double (&upl)[P],
+                                               const double (&rpl)[P], double (&un)[P], double (&rn)[P],
+                                               double (&pa)[3 * P]) {
+    const int64_t r = ix * M.sx + M.col;
+    double nu[4][P], nr[4][P];
+    load_pair<P>(xin, r + M.dyl, nu[0], nr[0]);
+    load_pair<P>(xin, r + M.dzl, nu[1], nr[1]);
+    load_pair<P>(xin, r + M.dzh, nu[2], nr[2]);
+    load_pair<P>(xin, r + M.dyh, nu[3], nr[3]);
+    load_pair<P>(xin, ix + 2 < S.nx ? r + 2 * M.sx : r, un, rn);
+    const double diag = stencil_diag(S, ix > 0, ix < S.nx - 1, M.yl, M.yh, M.zl, M.zh);
+    double x0[P], y[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const double xm = fma(-coef[p], um[p], rm[p]);
+        x0[p] = fma(-coef[p], u0[p], r0[p]);
+        const double xp = fma(-coef[p], upl[p], rpl[p]);
+        const double vyl = fma(-coef[p], nu[0][p], nr[0][p]);
+        const double vzl = fma(-coef[p], nu[1][p], nr[1][p]);
+        const double vzh = fma(-coef[p], nu[2][p], nr[2][p]);
+        const double vyh = fma(-coef[p], nu[3][p], nr[3][p]);
+        double acc = 0.0;
+        if (ix > 0) acc = fma(S.cx, xm, acc);
+        if (M.yl) acc = fma(S.cy, vyl, acc);
+        if (M.zl) acc = fma(S.cz, vzl, acc);
+        acc = fma(diag, x0[p], acc);
+        if (M.zh) acc = fma(S.cz, vzh, acc);
+        if (M.yh) acc = fma(S.cy, vyh, acc);
+        if (ix < S.nx - 1) acc = fma(S.cx, xp, acc);
+        y[p] = fma(-cprev[p], u0[p], sig[p] * acc);
+        pa[p] = fma(sig[p] * x0[p], y[p], pa[p]);
+        pa[P + p] = fma(y[p], y[p], pa[P + p]);
+        pa[2 * P + p] = fma(x0[p], x0[p], pa[2 * P + p]);
+    }
+    if (M.live) store_pair<P>(xout, r, x0, y);
+}
+
+// Marching 7-point stencil step: one thread per (y, z) column walks along x
+// with the pairs of planes x - 1, x, x + 1 in registers (x + 2 loaded one
+// step ahead), as k_spmv_stencil_march; partials over the column blocks.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_lz1_march(StencilArgs S, const double* __restrict__ xin,
+                                                      double* __restrict__ xout, BatchArgs B, Lz1Args Z, int j) {
+    __shared__ double s_lds[(kBlock / 64) * 3 * P];
+    __shared__ double s_tot[3 * P];
+    __shared__ double s_nrm[P];
+    const int cb = logical_block(B.ap_nblocks, B.xcd_map);
+    const int64_t ncol = S.ny * S.nz;
+    const int64_t col0 = (int64_t)cb * kBlock + threadIdx.x;
+    MarchCol M;
+    M.live = col0 < ncol;
+    M.col = M.live ? col0 : ncol - 1;          // dead lanes shadow a live column and store nothing
+    M.sx = ncol;
+    const int64_t iy = M.col / S.nz;
+    const int64_t iz = M.col % S.nz;
+    double ua[P], ra[P], ub[P], rb[P], uc[P], rc[P], ud[P], rd[P];
+    load_pair<P>(xin, M.col, ub, rb);
+    load_pair<P>(xin, S.nx > 1 ? M.col + M.sx : M.col, uc, rc);
+#pragma unroll
+    for (int p = 0; p < P; ++p) { ua[p] = 0.0; ra[p] = 0.0; }
+    double coef[P], sig[P], cprev[P];
+    lz1_prologue<P>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    M.prev = true;
+    M.yl = iy > 0;
+    M.yh = iy < S.ny - 1;
+    M.zl = iz > 0;
+    M.zh = iz < S.nz - 1;
+    M.dyl = M.yl ? -S.nz : 0;
+    M.dyh = M.yh ? S.nz : 0;
+    M.dzl = M.zl ? -1 : 0;
+    M.dzh = M.zh ? 1 : 0;
+    double pa[3 * P];
+#pragma unroll
+    for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
+    for (int64_t ix = 0; ix < S.nx; ix += 4) {
+        lz1_march_step<P>(S, M, ix, xin, xout, coef, sig, cprev, ua, ra, ub, rb, uc, rc, ud, rd, pa);
+        if (ix + 1 >= S.nx) break;
+        lz1_march_step<P>(S, M, ix + 1, xin, xout, coef, sig, cprev, ub, rb, uc, rc, ud, rd, ua, ra, pa);
+        if (ix + 2 >= S.nx) break;
+        lz1_march_step<P>(S, M, ix + 2, xin, xout, coef, sig, cprev, uc, rc, ud, rd, ua, ra, ub, rb, pa);
+        if (ix + 3 >= S.nx) break;
+        lz1_march_step<P>(S, M, ix + 3, xin, xout, coef, sig, cprev, ud, rd, ua, ra, ub, rb, uc, rc, pa);
+    }
+    if (!M.live) {
+#pragma unroll
+        for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
+    }
+    store_partials<3 * P>(pa, Z.ap_out, B.ap_nblocks, s_lds, B.xcd_map);
+}
+
+// C u_j over the output segments only (the marching step's stage j - 1
+// partials; its |u_j|^2 slots are written as 0, the norm travels in the
+// step's own partials).  Row partition of the segment tables: each block
+// takes its segments of every output row up to kBlock at a time, clipped to
+// its rows, lays their lengths out as a prefix sum in LDS and spreads the
+// rows over its threads, several loads in flight per thread.
+template <int P, int O>
+__global__ __launch_bounds__(kBlock) void k_lz1_proj(const double* __restrict__ x, SegTable T, int32_t oset0,
+                                                     BatchArgs B, int j) {
+    constexpr int NV = P * (1 + O);
+    constexpr int U = 8;
+    __shared__ double s_lds[(kBlock / 64) * NV];
+    __shared__ int64_t s_lo[kBlock];
+    __shared__ int64_t s_pre[kBlock + 1];
+    __shared__ double s_w[kBlock];
+    const int lb = logical_block(B.nblocks, B.xcd_map);
+    const int64_t r0 = (int64_t)lb * B.rows_per_block;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_block);
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < O; ++q) {
+        const int32_t* rq = T.blk + ((int64_t)(oset0 + q) * B.nblocks + lb) * 2;
+        const int32_t gb = rq[0], ge = rq[1];
+        for (int32_t g0 = gb; g0 < ge; g0 += kBlock) {
+            const int32_t g = g0 + (int32_t)threadIdx.x;
+            int64_t lo = 0, len = 0;
+            double w = 0.0;
+            if (g < ge) {
+                lo = max(T.lo[g], r0);
+                const int64_t hi = min(T.hi[g], r1);
+                len = hi > lo ? hi - lo : 0;
+                w = T.w[g];
+            }
+            s_lo[threadIdx.x] = lo;
+            s_w[threadIdx.x] = w;
+            s_pre[threadIdx.x + 1] = len;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                s_pre[0] = 0;
+                for (int t = 1; t <= kBlock; ++t) s_pre[t] += s_pre[t - 1];
+            }
+            __syncthreads();
+            const int64_t total = s_pre[kBlock];
+            for (int64_t v0 = 0; v0 < total; v0 += (int64_t)kBlock * U) {
+                int64_t row[U];
+                double wt[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t v = v0 + (int64_t)u * kBlock + threadIdx.x;
+                    // the segment holding virtual row v: the last s with s_pre[s] <= v
+                    int s = 0;
+#pragma unroll
+                    for (int step = kBlock / 2; step >= 1; step >>= 1)
+                        if (s + step < kBlock && s_pre[s + step] <= v) s += step;
+                    const bool ok = v < total;
+                    row[u] = ok ? s_lo[s] + (v - s_pre[s]) : r0;
+                    wt[u] = ok ? s_w[s] : 0.0;
+                }
+                double xv[U][2 * P];
+#pragma unroll
+                for (int u = 0; u < U; ++u) load_row<double, 2 * P>(x, row[u], xv[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int p = 0; p < P; ++p) acc[P + q * P + p] = fma(wt[u], xv[u][p], acc[P + q * P + p]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    store_partials<NV>(acc, stage_part(B, j - 1), B.nblocks, s_lds, B.xcd_map);
+}
+
+// ---- launches ---------------------------------------------------------------
+
+template <typename K, typename... Args>
+void go(K kernel, dim3 g, hipStream_t s, Args... args) {
+    const ExtEvents ev = *ext_events();
+    if (ev.start != nullptr)
+        hipExtLaunchKernelGGL(kernel, g, dim3(kBlock), 0, s, ev.start, ev.stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, g, dim3(kBlock), 0, s, args...);
+}
+
+template <int P, int O, bool MV>
+hipError_t launch_sell_po(const SellArgs& A, const double* xin, double* xout, const SegTable& T, int32_t oset0,
+                          const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
+    if (A.dcol) go(k_lz1_sell<P, O, true, MV>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+    else go(k_lz1_sell<P, O, false, MV>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+    return hipGetLastError();
+}
+
+template <int P, int O>
+hipError_t launch_stencil_po(const StencilArgs& S, const double* xin, double* xout, const SegTable& T,
+                             int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
+    go(k_lz1_stencil<P, O>, dim3(B.nblocks), s, S, xin, xout, T, oset0, B, Z, j);
+    return hipGetLastError();
+}
+
+template <int P, int O>
+hipError_t launch_proj_po(const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B, int j,
+                          hipStream_t s) {
+    go(k_lz1_proj<P, O>, dim3(B.nblocks), s, x, T, oset0, B, j);
+    return hipGetLastError();
+}
+
+// P * (1 + O) <= kMaxNV: P = 4 with O <= 5, P = 8 with O <= 2
+#define KRY_LZ1_O(FN, PP, ...)                                 \
+    switch (O) {                                               \
+        case 1: return FN<PP, 1>(__VA_ARGS__);                 \
+        case 2: return FN<PP, 2>(__VA_ARGS__);                 \
+        case 3: if (PP <= 4) return FN<PP, (PP <= 4 ? 3 : 1)>(__VA_ARGS__); break;   \
+        case 4: if (PP <= 4) return FN<PP, (PP <= 4 ? 4 : 1)>(__VA_ARGS__); break;   \
+        case 5: if (PP <= 4) return FN<PP, (PP <= 4 ? 5 : 1)>(__VA_ARGS__); break;   \
+        case 6: if (PP <= 2) return FN<PP, (PP <= 2 ? 6 : 1)>(__VA_ARGS__); break;   \
+        case 7: if (PP <= 2) return FN<PP, (PP <= 2 ? 7 : 1)>(__VA_ARGS__); break;   \
+        case 8: if (PP <= 2) return FN<PP, (PP <= 2 ? 8 : 1)>(__VA_ARGS__); break;   \
+        default: break;                                        \
+    }                                                          \
+    return hipErrorInvalidValue;
+#define KRY_LZ1_PO(FN, ...)                                    \
+    switch (P) {                                               \
+        case 1: { KRY_LZ1_O(FN, 1, __VA_ARGS__) }              \
+        case 2: { KRY_LZ1_O(FN, 2, __VA_ARGS__) }              \
+        case 4: { KRY_LZ1_O(FN, 4, __VA_ARGS__) }              \
+        case 8: { KRY_LZ1_O(FN, 8, __VA_ARGS__) }              \
+        default: return hipErrorInvalidValue;                  \
+    }
+
+template <int P, int O>
+hipError_t launch_sell_step_po(const SellArgs& A, const double* xin, double* xout, const SegTable& T, int32_t oset0,
+                               const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
+    return launch_sell_po<P, O, true>(A, xin, xout, T, oset0, B, Z, j, s);
+}
+
+template <int P, int O>
+hipError_t launch_tail_po(const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B, const Lz1Args& Z,
+                          int j, hipStream_t s) {
+    SellArgs none{};
+    return launch_sell_po<P, O, false>(none, xin, nullptr, T, oset0, B, Z, j, s);
+}
+
+}  // namespace
+
+hipError_t launch_lz1_sell(int P, int O, const SellArgs& A, const double* xin, double* xout, const SegTable& T,
+                           int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
+    KRY_LZ1_PO(launch_sell_step_po, A, xin, xout, T, oset0, B, Z, j, s)
+}
+
+hipError_t launch_lz1_stencil(int P, int O, const StencilArgs& S, const double* xin, double* xout,
+                              const SegTable& T, int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j,
+                              hipStream_t s) {
+    KRY_LZ1_PO(launch_stencil_po, S, xin, xout, T, oset0, B, Z, j, s)
+}
+
+hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
+                            const Lz1Args& Z, int j, hipStream_t s) {
+    switch (P) {
+        case 1: go(k_lz1_march<1>, dim3(B.ap_nblocks), s, S, xin, xout, B, Z, j); break;
+        case 2: go(k_lz1_march<2>, dim3(B.ap_nblocks), s, S, xin, xout, B, Z, j); break;
+        case 4: go(k_lz1_march<4>, dim3(B.ap_nblocks), s, S, xin, xout, B, Z, j); break;
+        case 8: go(k_lz1_march<8>, dim3(B.ap_nblocks), s, S, xin, xout, B, Z, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B,
+                           int j, hipStream_t s) {
+    KRY_LZ1_PO(launch_proj_po, x, T, oset0, B, j, s)
+}
+
+hipError_t launch_lz1_tail(int P, int O, const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B,
+                           const Lz1Args& Z, int j, hipStream_t s) {
+    KRY_LZ1_PO(launch_tail_po, xin, T, oset0, B, Z, j, s)
+}
+
+}  // namespace kry

@@ -5,6 +5,7 @@ of the same operator."""
 import dataclasses
 import os
 
+import numpy as np
 import pytest
 import torch  # noqa: F401  (imported at collection so the first test does not pay for it)
 
@@ -43,3 +44,36 @@ def test_dirichlet_stencil_with_exchange_face():
     got = gpu_verify(p)
     ref = oracle.verify(p)
     assert_basis_parity(got["basis"], ref["basis"])
+
+
+@pytest.mark.parametrize("form", ["csr", "stencil"])
+def test_paper_heat_100_error_control_stops_at_544(form):
+    # Section 5.3: on the 100^3 heat system the Lemma 1 bound first meets the
+    # 1e-6 target at k = 544, where it is 5.8e-7; the GPU's three-vector
+    # Lanczos with the error control must stop there with the oracle's bound
+    import math
+    from oracle import adaptive as AD
+    from paper_1804_01583_amd import kry
+    from tests.test_gpu_adaptive import _bound_tol
+    require_gpu()
+    p = W.heat3d_paper(m=100) if form == "csr" else W.heat3d_paper_stencil(m=100, k=1024)
+    print(f"[gpu] paper heat 100^3 {form} error control", flush=True)
+    plan = kry.Plan(kry.DeviceSystem(p), method=kry.KRY_LANCZOS_PLAIN)
+    plan.set_error_target(1e-6)
+    basis = plan.basis()
+    k_used, bound = plan.error(0)
+    plan.close()
+    assert k_used == 544, k_used
+    assert abs(bound - 5.8e-7) <= 0.05 * 5.8e-7, bound
+    assert np.isfinite(basis).all()
+    # the oracle's adaptive Lanczos on the CSR form of the same operator
+    q = W.heat3d_paper(m=100)
+    A = oracle.system_matrix(q)
+    lam = AD.gershgorin_sym_upper(A)
+    r = AD.adaptive_lanczos(A, q.gens[0].seg.dense(q.n), oracle.output_matrix(q), 1e-6, 20.0, 600, lam,
+                            oracle.krylov.inf_norm(A))
+    assert r["k_stop"] == 544
+    run = {"k_stop": 544, "affine": False, "bound": r["bound"], "h": r["h"]}
+    assert abs(bound - r["bound"]) <= _bound_tol(run, 20.0, lam), (bound, r["bound"])
+    print(f"  k {k_used} bound {bound:.6e} oracle {r['bound']:.6e}", flush=True)
+    assert math.isfinite(bound)
