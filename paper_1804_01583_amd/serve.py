@@ -4,8 +4,12 @@ Queries arrive over time (each a set of box generators, output rows, an
 unsafe threshold, a time grid and a precision against one of the resident
 systems).  The server
 
-* admits a waiting query, oldest first, as soon as a slot is free and the
-  HBM budget covers its plan's workspace (kry_plan_workspace),
+* admits a waiting query as soon as a slot is free and the HBM budget
+  covers its plan's workspace (kry_plan_workspace): the oldest one, or,
+  when the oldest does not fit, the oldest one behind it that does; a query
+  passed over `max_bypass` times is then waited for (the others stay queued
+  until it fits), so a large query delays later small ones by a bounded
+  amount instead of stalling the queue,
 * runs admitted queries concurrently, each on its own HIP stream, so their
   kernels overlap on the device (a query's generators are already advanced
   together by every mat-vec launch of its plan),
@@ -95,6 +99,27 @@ class _Pending:
     query: object
     footprint: int
     released: float
+    bypassed: int = 0
+
+
+def pick_admission(pending, in_use: int, budget: int, max_bypass: int, scan: int = 64):
+    """Index into `pending` (oldest first) of the query to admit now, or None.
+    The oldest query goes first when it fits (or when nothing runs: a query
+    larger than the budget then runs alone).  Otherwise the oldest of the
+    next `scan` queries that fits passes it, until the oldest has been passed
+    `max_bypass` times; from then on it is waited for."""
+    if not pending:
+        return None
+    head = pending[0]
+    if in_use + head.footprint <= budget or in_use == 0:
+        return 0
+    if head.bypassed >= max_bypass:
+        return None
+    for i in range(1, min(len(pending), scan + 1)):
+        if in_use + pending[i].footprint <= budget:
+            head.bypassed += 1
+            return i
+    return None
 
 
 class Server:
@@ -104,10 +129,11 @@ class Server:
     other ones serve for testing the scheduling on the host."""
 
     def __init__(self, catalog: Optional[Catalog], slots: int = 8, budget_bytes: int = 200 << 30,
-                 runner=None, footprint=None):
+                 runner=None, footprint=None, max_bypass: int = 16):
         self.catalog = catalog
         self.slots = slots
         self.budget = budget_bytes
+        self.max_bypass = max_bypass
         self._runner = runner
         self._footprint = footprint
 
@@ -176,9 +202,10 @@ class Server:
                     while True:
                         if errors:
                             return
-                        if pending and (state["in_use"] + pending[0].footprint <= self.budget
-                                        or state["in_use"] == 0):
-                            item = pending.popleft()
+                        i = pick_admission(pending, state["in_use"], self.budget, self.max_bypass)
+                        if i is not None:
+                            item = pending[i]
+                            del pending[i]
                             state["in_use"] += item.footprint
                             break
                         if state["dispatched"] and not pending:

@@ -27,7 +27,9 @@ def test_fifo_admission_and_budget():
     qs = W.serving_queries(24, rate=200.0, seed=300)
     fp = {q.qid: 10 + (q.qid % 3) * 10 for q in qs}       # 10, 20 or 30 units
     log, lock = [], threading.Lock()
-    srv = Server(None, slots=4, budget_bytes=45, runner=_fake(0.02, log, lock), footprint=lambda q: fp[q.qid])
+    # max_bypass=0: strict arrival order
+    srv = Server(None, slots=4, budget_bytes=45, runner=_fake(0.02, log, lock), footprint=lambda q: fp[q.qid],
+                 max_bypass=0)
     res = srv.serve(qs)
     # admission is in arrival order
     starts = [e[1] for e in log if e[0] == "start"]
@@ -48,6 +50,43 @@ def test_fifo_admission_and_budget():
         assert r.latency >= 0.02 - 1e-3
     s = summarize(res)
     assert s["queries"] == 24 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_small_queries_pass_a_blocked_head_a_bounded_number_of_times():
+    # the third query needs 40 of 50 units: while two 20-unit queries run it
+    # does not fit, and later small queries go first, at most max_bypass of
+    # them; the budget and the slots hold throughout
+    qs = W.serving_queries(30, rate=2000.0, seed=303)
+    big = qs[2].qid
+    fp = {q.qid: (40 if q.qid == big else 20) for q in qs}
+    log, lock = [], threading.Lock()
+    srv = Server(None, slots=4, budget_bytes=50, runner=_fake(0.01, log, lock), footprint=lambda q: fp[q.qid],
+                 max_bypass=3)
+    srv.serve(qs)
+    starts = [e[1] for e in log if e[0] == "start"]
+    pos = starts.index(big)
+    later = [i for i in starts[:pos] if qs[i].arrival > qs[big].arrival]
+    assert 1 <= len(later) <= 3, starts
+    events = sorted(log, key=lambda e: (e[2], e[0] == "start"))
+    running = set()
+    for kind, qid, _ in events:
+        if kind == "start":
+            running.add(qid)
+            assert len(running) <= 4 and sum(fp[i] for i in running) <= 50
+        else:
+            running.discard(qid)
+
+
+def test_pick_admission_rules():
+    from paper_1804_01583_amd.serve import _Pending, pick_admission
+    P = [_Pending(None, f, 0.0) for f in (40, 10, 30, 5)]
+    assert pick_admission(P, 0, 50, 2) == 0            # nothing running: the oldest, whatever its size
+    assert pick_admission(P, 20, 50, 2) == 1           # 40 does not fit beside 20: the 10 goes first
+    assert P[0].bypassed == 1
+    assert pick_admission(P, 20, 50, 2) == 1
+    assert pick_admission(P, 20, 50, 2) is None        # passed twice: now it is waited for
+    assert pick_admission(P, 10, 50, 2) == 0
+    assert pick_admission([], 0, 50, 2) is None
 
 
 def test_oversized_query_runs_alone():
