@@ -36,6 +36,12 @@ then k <- ceil(1.1 k), evaluated in IEEE double as printed (1.1 * 170 rounds
 to 187.00000000000003, so 170 is followed by 188), stop at the first k whose
 bound is below the target.  This is the sequence on which the paper's
 Section 5.3 reports its stop at k = 544.
+
+Algorithm 2 is the same control around Arnoldi (Algorithm 1) for a general
+A: H_k is then upper Hessenberg and the integrand takes the Pade route.
+Arnoldi's first j columns do not depend on the later ones, so the bound at
+checkpoint j is that of the leading j x j block of one run to the cap, with
+h_{j+1,j} its next sub-diagonal entry.
 """
 from __future__ import annotations
 
@@ -45,7 +51,7 @@ import numpy as np
 
 import scipy.linalg as sla
 
-from .krylov import BREAKDOWN_FACTOR, EPS, expm_pade13
+from .krylov import BREAKDOWN_FACTOR, EPS, _breaks_down, arnoldi, expm_pade13
 
 QUAD_LEVELS = 40
 QUAD_SPLIT = 8
@@ -176,17 +182,55 @@ def adaptive_lanczos(A, v, C, eps, tau, kmax, lam_upper, opnorm, affine=False):
     return result(kmax, bound)
 
 
-def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
-    """Every run of a symmetric problem with the Krylov dimension chosen by
-    the error control above (generator and center runs: Lanczos on A; the
-    augmented run: Lanczos on A from b, bordered by the augmented variable).
-    Returns dict(basis (S+1, o, nruns), roles, runs: dicts with k_stop,
-    bound, dim (Krylov dimension used), k_eff, H (the Lanczos matrix up to
-    k_stop), h, beta0, affine, kmax (the run's cap), verdict) and lam (the
-    Gershgorin bound used)."""
+def adaptive_arnoldi(A, v, C, eps, tau, kmax, lam_upper, opnorm, affine=False):
+    """Algorithm 2 with its error control: the Arnoldi process of
+    ``krylov.arnoldi`` on v / |v| to kmax, and at every checkpoint j of
+    ``k_schedule`` (in order) the Lemma 1 bound of the leading block H_j with
+    h_{j+1,j}; the first checkpoint below eps is the stop.  A breakdown at
+    k_eff ends the run exactly (bound 0) unless an earlier checkpoint passed.
+    Returns the dict of ``adaptive_lanczos``."""
+    o = C.shape[0]
+    res = arnoldi(A, v, kmax, C, opnorm=opnorm) if kmax >= 1 else None
+    if res is None or res.k_eff == 0:
+        return {"k_stop": 0, "bound": 0.0, "H": np.zeros((0, 0)), "P": np.zeros((o, 0)), "beta0": 0.0,
+                "k_eff": 0, "h": 0.0}
+    ke = res.k_eff
+    broke = _breaks_down(res.h_next, opnorm)
+
+    def h_after(j):
+        return float(res.H[j, j - 1]) if j < ke else float(res.h_next)
+
+    def result(j, bnd):
+        return {"k_stop": j, "bound": bnd, "H": res.H[:j, :j].copy(), "P": res.P[:, :j].copy(),
+                "beta0": res.beta0, "k_eff": j, "h": h_after(j)}
+
+    bound = math.inf
+    for j in k_schedule(4, kmax):
+        if j > ke or (j == ke and broke):
+            break
+        bound = lemma1_bound(res.H[:j, :j], h_after(j), tau, lam_upper, affine)
+        if bound < eps:
+            return result(j, bound)
+    if broke:
+        return result(ke, 0.0)
+    return result(ke, bound)
+
+
+def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None, method="auto"):
+    """Every run of a problem with the Krylov dimension chosen by the error
+    control above (generator and center runs: Lanczos, or Arnoldi for a
+    nonsymmetric A or method="arnoldi", on A; the augmented run: the same
+    process from b, bordered by the augmented variable).  Returns
+    dict(basis (S+1, o, nruns), roles, runs: dicts with k_stop, bound, dim
+    (Krylov dimension used), k_eff, H (the Krylov matrix up to k_stop), h,
+    beta0, affine, kmax (the run's cap), verdict) and lam (the Gershgorin
+    bound used)."""
     from .krylov import box_check, build_runs, inf_norm, output_matrix, system_matrix
-    if not problem.symmetric:
-        raise ValueError("the error-controlled path here is Lanczos (symmetric A)")
+    if method == "auto":
+        method = "lanczos" if problem.symmetric else "arnoldi"
+    if method == "lanczos" and not problem.symmetric:
+        raise ValueError("Lanczos needs a symmetric A")
+    run_one = adaptive_lanczos if method == "lanczos" else adaptive_arnoldi
     steps = problem.steps if steps is None else steps
     dt = problem.dt if dt is None else dt
     kmax = problem.k if kmax is None else kmax
@@ -199,7 +243,7 @@ def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
     cols, info = [], []
     for run in runs:
         if run.role == "affine":
-            r = adaptive_lanczos(A, problem.forcing(), C, eps, tau, kmax - 1, lam, opnorm, affine=True)
+            r = run_one(A, problem.forcing(), C, eps, tau, kmax - 1, lam, opnorm, affine=True)
             m = r["H"].shape[0]
             Hb = np.zeros((m + 1, m + 1))
             Hb[1:, 1:] = r["H"]
@@ -209,7 +253,7 @@ def adaptive_verify(problem, eps=1e-6, kmax=None, steps=None, dt=None):
             Pb[:, 1:] = r["P"]
             scale, dim = 1.0, m + 1
         else:
-            r = adaptive_lanczos(A, run.start, C, eps, tau, kmax, lam, opnorm)
+            r = run_one(A, run.start, C, eps, tau, kmax, lam, opnorm)
             Hb, Pb, scale, dim = r["H"], r["P"], r["beta0"], r["H"].shape[0]
         out = np.zeros((steps + 1, C.shape[0]))
         if dim > 0 and (run.role == "affine" or scale != 0.0):

@@ -12,6 +12,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 import oracle
 import workloads as W
@@ -193,3 +194,119 @@ def test_adaptive_stops_at_first_checkpoint_under_target():
             c = earlier[-1]
             r2 = oracle.lanczos(A, v, c, oracle.output_matrix(p), opnorm=oracle.krylov.inf_norm(A))
             assert AD.lemma1_bound(r2.H, r2.h_next, tau, lam, affine) >= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2: the same control around Arnoldi for a general A
+# ---------------------------------------------------------------------------
+
+def _shift(n):
+    # e_i -> e_{i+1}: Arnoldi from e_1 keeps V = I and H_j = the j x j shift,
+    # so (e^{t H_j})_{j,1} = t^{j-1} / (j-1)! and h_{j+1,j} = 1
+    return sp.diags([np.ones(n - 1)], [-1], format="csr")
+
+
+def test_arnoldi_bound_on_a_shift_is_the_taylor_tail():
+    n = 40
+    A = _shift(n)
+    lam = AD.gershgorin_sym_upper(A)
+    assert lam == 1.0                    # off-diagonal 1/2 on both sides of interior rows
+    C = sp.csr_matrix(np.ones((1, n)))
+    tau = 1.0
+    v = np.zeros(n); v[0] = 1.0
+    # bound(j) = e^tau tau^j / j!: e / 9! = 7.5e-6 > 1e-6 > e / 10! = 7.5e-7,
+    # and 10 is a checkpoint (4, 5, ..., 11, 13, ...)
+    r = AD.adaptive_arnoldi(A, v, C, 1e-6, tau, 30, lam, 1.0)
+    assert r["k_stop"] == 10
+    assert abs(r["bound"] - math.e / math.factorial(10)) <= 1e-12 * r["bound"]
+    assert r["h"] == 1.0 and np.array_equal(r["H"], np.eye(10, k=-1))
+    # the augmented weight: int_0^tau (tau - t) t^{j-1}/(j-1)! dt = tau^{j+1}/(j+1)!
+    ra = AD.adaptive_arnoldi(A, v, C, 1e-6, 2.0, 30, lam, 1.0, affine=True)
+    j = ra["k_stop"]
+    want = math.exp(2.0) * 2.0 ** (j + 1) / math.factorial(j + 1)
+    assert abs(ra["bound"] - want) <= 1e-12 * want and want < 1e-6
+    prev = [c for c in AD.k_schedule(4, j) if c < j][-1]
+    assert math.exp(2.0) * 2.0 ** (prev + 1) / math.factorial(prev + 1) >= 1e-6
+    # the true error is the tail of the exponential series: below the bound
+    err = math.sqrt(sum((tau**i / math.factorial(i)) ** 2 for i in range(10, 60)))
+    assert err <= r["bound"]
+
+
+def test_arnoldi_breakdown_ends_exactly():
+    n = 12
+    A = _shift(n)
+    v = np.zeros(n); v[0] = 1.0
+    C = sp.csr_matrix(np.ones((1, n)))
+    # A^12 e_1 = 0: the space is invariant at k = 12, before any checkpoint passes
+    r = AD.adaptive_arnoldi(A, v, C, 1e-300, 1.0, 40, 1.0, 1.0)
+    assert r["k_stop"] == 12 and r["bound"] == 0.0
+    # a zero start vector contributes nothing
+    z = AD.adaptive_arnoldi(A, np.zeros(n), C, 1e-6, 1.0, 40, 1.0, 1.0)
+    assert z["k_stop"] == 0 and z["bound"] == 0.0
+
+
+def test_arnoldi_control_equals_lanczos_control_on_a_symmetric_system():
+    # the Hessenberg (Pade) route of the integrand against the tridiagonal
+    # eigen route, and Arnoldi's H against Lanczos' T, through the whole
+    # control: same stops, bounds to rounding, same basis
+    p = W.small_heat3d(m=8, k=40, steps=60)
+    lz = AD.adaptive_verify(p, eps=1e-7, method="lanczos")
+    ar = AD.adaptive_verify(p, eps=1e-7, method="arnoldi")
+    for a, b in zip(lz["runs"], ar["runs"]):
+        assert a["k_stop"] == b["k_stop"]
+        assert abs(a["bound"] - b["bound"]) <= 1e-6 * a["bound"]
+    scale = np.abs(lz["basis"]).max()
+    assert np.abs(lz["basis"] - ar["basis"]).max() <= 1e-10 * scale
+
+
+def test_arnoldi_bound_dominates_true_error_nonsymmetric():
+    # 6^3 convection-diffusion with off-stencil entries: at the stop the
+    # bound exceeds the true error of the normalised process at every
+    # t <= tau (the bound grows with tau); also for the augmented run
+    p = W.conv_diff3d(6, 6, 6, ngen=2, gen_len=20, o=2, k=40, steps=50, dt=2e-3)
+    A = oracle.system_matrix(p)
+    Ad = A.toarray()
+    C = oracle.output_matrix(p)
+    lam = AD.gershgorin_sym_upper(A)
+    tau = p.steps * p.dt
+    opnorm = oracle.krylov.inf_norm(A)
+    for g in p.gens:
+        v = g.seg.dense(p.n)
+        r = AD.adaptive_arnoldi(A, v, C, 1e-8, tau, 40, lam, opnorm)
+        j = r["k_stop"]
+        assert 4 <= j < 40 and r["bound"] < 1e-8
+        full = oracle.arnoldi(A, v, j, C, keep_V=True)
+        assert np.array_equal(full.H, r["H"])
+        err = _true_error(Ad, v / r["beta0"], r["H"], full.V, 1.0, np.linspace(0, tau, 11))
+        assert err <= r["bound"] + 1e-13
+        # one checkpoint earlier the bound was not yet below the target
+        prev = [c for c in AD.k_schedule(4, j) if c < j]
+        if prev:
+            assert AD.lemma1_bound(r["H"][:prev[-1], :prev[-1]], r["H"][prev[-1], prev[-1] - 1], tau, lam) >= 1e-8
+    # augmented run from b: x(t) = int_0^t e^{As} b ds against the bordered approximation
+    b = np.linspace(-1.0, 1.0, p.n)
+    r = AD.adaptive_arnoldi(A, b, C, 1e-9, tau, 39, lam, opnorm, affine=True)
+    j = r["k_stop"]
+    full = oracle.arnoldi(A, b, j, C, keep_V=True)
+    worst = 0.0
+    for t in np.linspace(0, tau, 11):
+        exact = np.linalg.solve(Ad, sla.expm(Ad * t) @ b - b)
+        M = np.zeros((j + 1, j + 1)); M[1:, 1:] = r["H"]; M[1, 0] = 1.0
+        approx = r["beta0"] * full.V @ sla.expm(M * t)[1:, 0]
+        worst = max(worst, np.linalg.norm(exact - approx))
+    assert worst <= r["beta0"] * r["bound"] + 1e-12 * np.linalg.norm(b)
+
+
+def test_adaptive_verify_nonsymmetric_takes_arnoldi():
+    p = W.conv_diff3d(6, 6, 6, ngen=2, gen_len=20, o=2, k=30, steps=40, dt=2e-3)
+    res = AD.adaptive_verify(p, eps=1e-7)
+    ref = oracle.verify(p, method="arnoldi", k=max(r["k_stop"] for r in res["runs"]))
+    for i, info in enumerate(res["runs"]):
+        assert 4 <= info["k_stop"] < 30 and info["bound"] < 1e-7
+        # the columns equal fixed-k Arnoldi at the stop
+        one = oracle.verify(p, method="arnoldi", k=info["k_stop"])
+        np.testing.assert_allclose(res["basis"][:, :, i], one["basis"][:, :, i], rtol=0,
+                                   atol=1e-12 * np.abs(one["basis"][:, :, i]).max())
+    assert res["verdict"]["first_step"] == ref["verdict"]["first_step"]
+    with pytest.raises(ValueError):
+        AD.adaptive_verify(p, eps=1e-7, method="lanczos")
