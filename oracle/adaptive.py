@@ -13,7 +13,7 @@ normalised process (an error relative to |v|):
 
     bound(tau) = h_{k+1,k} e^{max(lambda, 0) tau} int_0^tau |(e^{t H_k})_{k,1}| dt,
 
-lambda any upper bound of lambda_max((A + A^T)/2) (Gershgorin here).
+lambda any upper bound of lambda_max((A + A^T)/2) (a Gershgorin bound here).
 
 The augmented run approximates x(t) = int_0^t e^{As} b ds by integrating the
 Lanczos approximation of e^{As} b (the bordered Krylov matrix does exactly
@@ -116,13 +116,18 @@ def lemma1_bound(H, h_next, tau, lam_upper, affine=False) -> float:
 
 
 def gershgorin_sym_upper(A) -> float:
-    """An upper bound of lambda_max((A + A^T)/2): max_i of the diagonal plus
-    the absolute off-diagonal row sum of the symmetric part."""
+    """An upper bound of lambda_max((A + A^T)/2): Gershgorin's bound of the
+    symmetric part S with each |s_rc| = |a_rc + a_cr| / 2 taken as at most
+    (|a_rc| + |a_cr|) / 2, i.e. max_r of a_rr plus half the absolute
+    off-diagonal sums of row r and of column r.  For a symmetric A this is
+    Gershgorin's bound of A itself."""
     import scipy.sparse as sp
-    S = 0.5 * (sp.csr_matrix(A) + sp.csr_matrix(A).T)
-    d = S.diagonal()
-    off = np.asarray(abs(S).sum(axis=1)).ravel() - np.abs(d)
-    return float(np.max(d + off))
+    A = sp.csr_matrix(A)
+    d = A.diagonal()
+    absA = abs(A)
+    row_off = np.asarray(absA.sum(axis=1)).ravel() - np.abs(d)
+    col_off = np.asarray(absA.sum(axis=0)).ravel() - np.abs(d)
+    return float(np.max(d + 0.5 * (row_off + col_off)))
 
 
 def k_schedule(k0: int, kmax: int):

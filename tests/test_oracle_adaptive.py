@@ -68,10 +68,20 @@ def test_one_step_bound_by_hand_with_positive_lambda():
 
 
 def test_gershgorin_bound_by_hand():
-    # symmetric part of [[0.2, 0.7], [-0.1, 1.0]] is [[0.2, 0.3], [0.3, 1.0]]:
-    # row bounds 0.2 + 0.3 and 1.0 + 0.3
+    # [[0.2, 0.7], [-0.1, 1.0]]: the off-diagonal of the symmetric part,
+    # |0.7 - 0.1| / 2 = 0.3, is taken as at most (0.7 + 0.1) / 2 = 0.4: row
+    # bounds 0.2 + 0.4 and 1.0 + 0.4 (the symmetric part's eigenvalues are
+    # 0.6 +- 0.5, so 1.4 >= 1.1 holds)
     A = np.array([[0.2, 0.7], [-0.1, 1.0]])
-    assert abs(AD.gershgorin_sym_upper(A) - 1.3) <= 1e-15
+    assert abs(AD.gershgorin_sym_upper(A) - 1.4) <= 1e-15
+    assert AD.gershgorin_sym_upper(A) >= np.linalg.eigvalsh(0.5 * (A + A.T)).max()
+    # same-sign mirrored entries lose nothing: [[0, 0.7], [0.1, 0]] -> 0.4,
+    # the largest eigenvalue of its symmetric part
+    A2 = np.array([[0.0, 0.7], [0.1, 0.0]])
+    assert abs(AD.gershgorin_sym_upper(A2) - 0.4) <= 1e-15
+    # one-sided entries count half in their row and half in their column
+    A3 = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, -1.0]])
+    assert AD.gershgorin_sym_upper(A3) == 0.5
     # negative off-diagonals count by magnitude
     B = np.array([[-2.0, -0.5, 0.0], [-0.5, -1.0, 0.25], [0.0, 0.25, 0.1]])
     assert abs(AD.gershgorin_sym_upper(B) - 0.35) <= 1e-15
