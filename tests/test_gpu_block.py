@@ -132,7 +132,7 @@ def test_block_fp32_basis():
     ref = OB.block_verify(prob, p=16)
     got = gpu_block(prob, 16, precision=kry.KRY_FP32_BASIS)
     anorm = oracle.krylov.inf_norm(oracle.system_matrix(prob))
-    tol = max(1e-5, 2.0 * 2.0 ** -23 * anorm * prob.steps * prob.dt)
+    tol = min(1e-4, max(1e-5, 2.0 * 2.0 ** -23 * anorm * prob.steps * prob.dt))
     worst = assert_block_basis_parity(got["basis"], ref["basis"], 16, rtol=tol)
     print(f"  FP32-basis block worst relative error {worst:.2e} (bound {tol:.1e})", flush=True)
 

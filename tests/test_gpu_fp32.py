@@ -7,13 +7,19 @@ Storing a vector in FP32 rounds each entry by a relative 2^-24, and with full
 reorthogonalisation the computed H is V^T A V + E with |E| ~ eps_32 ||A||
 (as for any backward-stable Krylov process): the result is that of a
 perturbed matrix.  For a dissipative A (|e^{At}| <= 1) a perturbation E
-changes e^{At} v by at most t |E| |v| over [0, t], so per (output row, run)
+changes e^{At} v by at most t |E| |v| over [0, t].  That worst case grows
+with ||A|| T and says nothing for stiff systems (0.14 for the 1000^3 heat
+system), where the fast modes a perturbation excites decay at once; so the
+stated bound caps it at 1e-4: per (output row, run)
 
     max_s |y_gpu - y_ref| <= tol * max_s |y_ref|,
-    tol = max(1e-5, 2 eps_32 ||A||_inf T),      T = steps * dt.
+    tol = min(1e-4, max(1e-5, 2 eps_32 ||A||_inf T)),      T = steps * dt.
 
-(Measured errors sit 10x or more below it.)  Rows that are structurally zero
-in the oracle stay exactly zero: the stored zeros are exact."""
+(Measured errors sit 5x or more below it: 2e-7 on the 1000^3 system, whose
+bench line reports them per output.)  Verdicts must equal the FP64 ones
+wherever the FP64 margin to a threshold exceeds tol times the row's scale.
+Rows that are structurally zero in the oracle stay exactly zero: the stored
+zeros are exact."""
 import math
 
 import numpy as np
@@ -32,7 +38,7 @@ EPS32 = 2.0 ** -23
 
 def fp32_tol(problem):
     anorm = oracle.krylov.inf_norm(oracle.krylov.system_matrix(problem))
-    return max(1e-5, 2.0 * EPS32 * anorm * problem.steps * problem.dt)
+    return min(1e-4, max(1e-5, 2.0 * EPS32 * anorm * problem.steps * problem.dt))
 
 
 def _compare32(problem, oracle_method="auto", **kw):
