@@ -58,8 +58,8 @@ MALL_BYTES = 256 * 2**20
 # per workload: the committed rocprofv3 counter summary of the dominant
 # kernel and the sources that kernel is built from
 COUNTER_PROFILES = {
-    "heat3d_stencil": ("lz1_march_heat3d_m1000_pmc.md", ("kry_lz1.hip", "kry_device.h", "kry_internal.h")),
-    "heat3d_csr": ("lz1_sell_heat3d_m100_pmc.md", ("kry_lz1.hip", "kry_device.h", "kry_internal.h")),
+    "heat3d_stencil": ("lz1_march_heat3d_m1000_pmc.md", ("kry_lz1.hip", "kry_device.h")),
+    "heat3d_csr": ("spmv_sell_heat3d_m100_pmc.md", ("kry_sell.hip", "kry_device.h")),
 }
 
 

@@ -267,6 +267,24 @@ kry_status kry_project_expm(kry_plan_t* plan, double* basis_out);
 kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kry_verdict* out,
                                 double* z_out);
 
+/* kry_check_box_subset -- kry_check_box_safety over part of a plan's basis,
+ * for one plan that carries several verification problems on the same
+ * system (Section 4.1: each column of E is its own simulation, so columns
+ * of different problems can share the Krylov launches): the reachable
+ * range of Section 2.1's per-step check over the box of the generator
+ * columns among cols (the other columns enter with coefficient 1), on output
+ * rows rows[i] with unsafe set unsafe[i], at steps 0..steps.
+ *  cols: ncols distinct basis columns of the plan, 1 <= ncols <= 64.
+ *  rows: nrows output rows of the plan (1 <= nrows <= the plan's o).
+ *  steps: 0 <= steps <= the plan's steps.
+ *  out->row is an index into rows; z_out: the counter-example's
+ *     coefficients of the generator columns among cols, in their order.
+ * KRY_EINVAL for bad indices or sizes.  Needs kry_project_expm first.
+ * Waits for the stream. */
+kry_status kry_check_box_subset(kry_plan_t* plan, const int32_t* cols, int32_t ncols, const int32_t* rows,
+                                int32_t nrows, int64_t steps, const kry_interval* unsafe, kry_verdict* out,
+                                double* z_out);
+
 /* kry_verify_noalloc -- for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): kry_plan_create + kry_project_expm + kry_check_box_safety in
@@ -384,18 +402,23 @@ kry_status kry_plan_krylov(kry_plan_t* plan, int32_t run, int32_t* k_eff, double
  * j <- ceil(1.1 j) (1.1 j rounded to double, as the algorithms print it), the
  * bound of the normalised process (the algorithms start from v / |v|, so eps
  * is an error relative to |v|)
- *     h_{j+1,j} e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t T_j})_{j,1}| dt
- * (tau = steps * dt; lambda a Gershgorin upper bound of the largest
- * eigenvalue of A, computed here, on the device for a CSR system; w = 1, or
- * tau - t for the augmented run, whose bordered matrix integrates the
- * approximation of e^{As} b / |b|) and ends a run at the first checkpoint where the
- * bound is below eps; a batch stops iterating once all its runs have ended.
- * k stays the cap (the augmented run: k - 1 Lanczos steps); k <= 2048.  The integral
- * uses a fixed composite 8-point Gauss-Legendre rule on [0, tau 2^-40] and on
- * [tau 2^-(i+1), tau 2^-i], i < 40, each cut into 8 equal parts.  eps = 0
- * turns the control off (the default: every run uses k).  Lanczos plans
- * only (symmetric A; KRY_ENOTSUP otherwise).  Waits for the plan's stream
- * for a CSR system. */
+ *     h_{j+1,j} e^{max(lambda,0) tau} int_0^tau w(t) |(e^{t H_j})_{j,1}| dt
+ * (tau = steps * dt; lambda an upper bound of the largest eigenvalue of
+ * (A + A^T)/2 computed here by Gershgorin, on the device for a CSR system:
+ * max over rows of a_rr plus half the absolute off-diagonal sums of row r
+ * and column r, which is Gershgorin's bound of A for a symmetric A; w = 1,
+ * or tau - t for the augmented run, whose bordered matrix integrates the
+ * approximation of e^{As} b / |b|) and ends a run at the first checkpoint
+ * where the bound is below eps; a batch stops iterating once all its runs
+ * have ended.  k stays the cap (the augmented run: k - 1 Krylov steps).  The
+ * integral uses a fixed composite 8-point Gauss-Legendre rule on
+ * [0, tau 2^-40] and on [tau 2^-(i+1), tau 2^-i], i < 40, each cut into 8
+ * equal parts.  eps = 0 turns the control off (the default: every run uses
+ * k).  Lanczos plans (symmetric A, H_j tridiagonal: Algorithm 4), k <= 2048,
+ * and Arnoldi plans (Algorithm 2, H_j upper Hessenberg), k <= 56; other
+ * methods, the transposed route and graph mode give KRY_ENOTSUP, and so does
+ * a CSR matrix with a column of more than 2^24 entries (Arnoldi).  Waits for
+ * the plan's stream for a CSR system. */
 kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps);
 /* kry_plan_error -- after kry_project_expm, run `run`'s Krylov dimension
  * (k_used: Lanczos steps used, the least of the breakdown dimension, the

@@ -202,6 +202,12 @@ int32_t march_blocks_for(const kry_system& sys) {
     return (int32_t)align_up((size_t)((ncol + kBlock - 1) / kBlock), 8);
 }
 
+// Tiles of the one-pass marching stencil kernel where the marching form is
+// used, else 0.
+int32_t lz1_blocks_for(const kry_system& sys) {
+    return march_blocks_for(sys) > 0 ? lz1_march_blocks(sys.ny, sys.nz, kMaxP) : 0;
+}
+
 constexpr int kProjGroups = 32;   // workgroups per output row in the block projection
 
 // CSR systems of the single-vector methods read a sliced-ELL copy (see
@@ -243,7 +249,7 @@ struct Layout {
     bool dense_runs = false;   // k > 56: each run's exponential in the dense stage
     int64_t scap = 0;          // sliced-ELL entry capacity (0: no sliced-ELL copy)
     size_t swidth = 0, soff = 0, stiles = 0, scol = 0, sval = 0;
-    size_t eflags = 0;          // error control: per-run stop flags, then the Gershgorin bound
+    size_t eflags = 0;          // error control: stop flags, Gershgorin bound, Arnoldi chain sums, overflow
     size_t dH = 0, dP = 0, dS0 = 0, dws = 0;
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     bool lz1 = false;     // FP64 three-vector Lanczos: room for the one-pass step (two pair buffers)
@@ -252,9 +258,10 @@ struct Layout {
     size_t ap_stride = 0; // doubles between the two ping-pong partial arrays of the one-pass step
 };
 
+// lz1_march: tiles of the one-pass marching stencil kernel (0 when it is not used)
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
                    size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32,
-                   int64_t sell_nnz, int32_t njobs = -1, int32_t ncols = -1, int32_t o_out = -1) {
+                   int64_t sell_nnz, int32_t lz1_march, int32_t njobs = -1, int32_t ncols = -1, int32_t o_out = -1) {
     // the forward route has one job and one basis column per run
     if (njobs < 0) njobs = nruns;
     if (ncols < 0) ncols = nruns;
@@ -314,7 +321,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.np_part = take((size_t)(k + 1) * Y.nvp * Y.nblocks * sizeof(double));
     // mat-vec dot partials; the one-pass step keeps two arrays of three
     // values per run (the previous launch's and its own)
-    Y.ap_stride = (size_t)std::max(Y.nblocks, Y.march) * kMaxP * 3;
+    Y.ap_stride = (size_t)std::max(Y.nblocks, lz1_march) * kMaxP * 3;
     Y.ap_part = take((Y.lz1 ? 2 * Y.ap_stride : Y.ap_stride / 3) * sizeof(double));
     Y.oflag = take(kMaxP * sizeof(double));
     Y.scal = take((size_t)nruns * L.stride * sizeof(double));
@@ -338,7 +345,9 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.cpart = take((size_t)2 * check_blocks(steps, o_out) * sizeof(double));
     Y.verdict = take((size_t)(6 + ncols) * sizeof(double));
     Y.anorm = take(sizeof(double));
-    Y.eflags = take(kMaxP * sizeof(double) + sizeof(double));
+    // error control: stop flags, the Gershgorin bound, the Arnoldi chains'
+    // sums, an overflow flag
+    Y.eflags = take((kMaxP + 1 + (size_t)lemma1_hess_partials() + 1) * sizeof(double));
     if (method == KRY_BLOCK_ARNOLDI) {
         Y.bw = block_p;
         Y.brb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 63) / 64));
@@ -452,7 +461,10 @@ void gauss_legendre8(double* x, double* w) {
 kry_status prepare_device() {
     static std::once_flag once;
     static hipError_t err = hipSuccess;
-    std::call_once(once, [] { err = expm_prepare(); });
+    std::call_once(once, [] {
+        err = expm_prepare();
+        if (err == hipSuccess) err = errctl_prepare();
+    });
     if (err != hipSuccess) return fail(KRY_EDEVICE, std::string("expm LDS setup: ") + hipGetErrorString(err));
     return KRY_OK;
 }
@@ -635,7 +647,8 @@ kry_status kry_plan_workspace(const kry_system* sys, int32_t nruns, int32_t o, i
         const int32_t nsets = nruns + o;
         const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
         const Layout Y = make_layout(sys->n, nruns, o, k, steps, block_p, meta_size(nseg_total, nsets, nruns, nb), method,
-                                     march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method));
+                                     march_blocks_for(*sys), precision, nnz32, sell_nnz_for(*sys, method),
+                                     lz1_blocks_for(*sys));
         *bytes = Y.total;
         return KRY_OK;
     });
@@ -680,8 +693,8 @@ kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32
         const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys_t->kind == KRY_CSR) ? sys_t->nnz : 0;
         const Layout Y = make_layout(sys_t->n, o, nproj, k, steps, 0,
                                      meta_size(nseg_total, nsets, std::max(njobs, nproj), nb, njobs), method,
-                                     march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method), njobs,
-                                     nproj, o);
+                                     march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method),
+                                     lz1_blocks_for(*sys_t), njobs, nproj, o);
         *bytes = Y.total;
         return KRY_OK;
     });
@@ -842,7 +855,8 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     const size_t mbytes = meta_size(total_segs, nsets, ntab, nblk, nmap);
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     plan->Y = make_layout(n, plan->nruns, plan->o, k, steps, block_p, mbytes, method, march_blocks_for(*sys),
-                          precision, nnz32, sell_nnz_for(*sys, method), plan->njobs, plan->ncols, plan->o_out);
+                          precision, nnz32, sell_nnz_for(*sys, method), lz1_blocks_for(*sys), plan->njobs, plan->ncols,
+                          plan->o_out);
     plan->method = method == KRY_LANCZOS_PLAIN ? KRY_LANCZOS : method;   // the layout tells plain from reorthogonalised
     plan->f32 = precision == KRY_FP32_BASIS;
     plan->hess_mode = plan->Y.stored;
@@ -1213,7 +1227,8 @@ kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const Star
     double* ap[2] = {plan->ap_part(), plan->ap_part() + Y.ap_stride};
     const bool csr = plan->sys.kind == KRY_CSR;
     const bool march = !csr && Y.march > 0;
-    const int32_t nb_step = march ? Y.march : Y.nblocks;
+    const int32_t nb_step = march ? lz1_march_blocks(plan->sys.ny, plan->sys.nz, P) : Y.nblocks;
+    if ((size_t)nb_step * kMaxP * 3 > Y.ap_stride) return fail(KRY_EDEVICE, "one-pass step: partial array too small");
     double* flag = plan->at<double>(Y.oflag);
     hipError_t e = launch_fill(flag, kMaxP, 1.0, s);
     if (e == hipSuccess)
@@ -1305,10 +1320,15 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         }
         const bool f32 = plan->f32;
         const bool lanczos = plan->method == KRY_LANCZOS;
-        // FP64 three-vector Lanczos takes the one-pass step; a batch in which
-        // a run's norm expansion cancelled is computed again two-pass
-        const bool onepass = Y.lz1 && lanczos && plan->err_eps <= 0.0 && env_int("KRY_ONEPASS", 1) != 0 &&
-                             (plan->sys.kind == KRY_STENCIL7 || plan->use_sell);
+        // FP64 three-vector Lanczos on a stencil takes the one-pass step; a
+        // batch in which a run's norm expansion cancelled is computed again
+        // two-pass.  On a CSR matrix the step gathers two vectors per entry
+        // instead of one, which measured slower than the two launches on the
+        // 100^3 system (whose working set sits in the MALL), so it is used
+        // there only on request (KRY_ONEPASS=1; 0 turns it off everywhere).
+        const int op_mode = env_int("KRY_ONEPASS", -1);
+        const bool onepass = Y.lz1 && lanczos && plan->err_eps <= 0.0 && op_mode != 0 &&
+                             (plan->sys.kind == KRY_STENCIL7 || (plan->use_sell && op_mode == 1));
         const BatchArgs B_fin = B;           // the finishing kernel never reads stop flags here
         if (onepass) {
             bool flagged = false;
@@ -1401,7 +1421,10 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
             if (plan->err_eps > 0.0 && j == next_check) {
                 next_check = (int)std::ceil(1.1 * (double)next_check);
                 e = timed("errctl", s, [&] { return launch_record_stage(P, B, j, s); });
-                if (e == hipSuccess) e = timed("errctl", s, [&] { return launch_lemma1(P, B, X, j, s); });
+                if (e == hipSuccess) e = timed("errctl", s, [&] {
+                    return lanczos ? launch_lemma1(P, B, X, j, s)
+                                   : launch_lemma1_hess(P, B, X, j, X.flags + kMaxP + 1, s);
+                });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("error control: ") + hipGetErrorString(e));
                 if (poll_pending && hipEventQuery(plan->flag_ev) == hipSuccess) {
                     poll_pending = false;
@@ -1498,6 +1521,43 @@ constexpr int kMaxDevices = 64;
 
 // The device address of `scratch` on the current device, looked up once per
 // device with that device current.
+// The box check of the columns and rows C names (sizes and maps set by the
+// caller): launch, verdict to the host, counter-example of the generator
+// columns among `cols` (plan column indices, in order).
+kry_status run_check(kry_plan_t* plan, CheckArgs& C, const int32_t* cols, const kry_interval* unsafe,
+                     kry_verdict* out, double* z_out) {
+    C.basis = plan->basis();
+    C.zc = plan->zc_dev;
+    C.radius = plan->rad_dev;
+    for (int q = 0; q < C.o; ++q) {
+        if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
+        C.ulo[q] = unsafe[q].lo;
+        C.uhi[q] = unsafe[q].hi;
+    }
+    C.part = plan->cpart();
+    C.verdict = plan->verdict();
+    hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
+    plan->verdict_host.assign(6 + C.nruns, 0.0);
+    KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, plan->stream));
+    KRY_HIP(hipStreamSynchronize(plan->stream));
+    const double* v = plan->verdict_host.data();
+    out->first_step = (int64_t)v[0];
+    out->row = (int32_t)v[1];
+    out->y = v[2];
+    out->lo = v[3];
+    out->hi = v[4];
+    out->status = (int32_t)v[5];
+    if (plan->nonfinite) out->status = KRY_ENUMERIC;
+    if (z_out) {
+        int32_t g = 0;
+        for (int32_t r = 0; r < C.nruns; ++r)
+            if (plan->col_role[cols[r]] == 0) z_out[g++] = v[6 + r];
+    }
+    return KRY_OK;
+}
+
 kry_status scratch_address(void** out) {
     static std::mutex mu;
     static void* addr[kMaxDevices] = {};
@@ -1561,39 +1621,44 @@ kry_status kry_check_box_safety(kry_plan_t* plan, const kry_interval* unsafe, kr
         if (!plan || !unsafe || !out) return fail(KRY_EINVAL, "plan, unsafe and out must be non-NULL");
         if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
         CheckArgs C{};
-        C.basis = plan->basis();
-        C.zc = plan->zc_dev;
-        C.radius = plan->rad_dev;
         C.nruns = plan->ncols;
         C.o = plan->o_out;
         C.steps = plan->steps;
-        for (int q = 0; q < plan->o_out; ++q) {
-            if (std::isnan(unsafe[q].lo) || std::isnan(unsafe[q].hi)) return fail(KRY_EINVAL, "unsafe interval is NaN");
-            C.ulo[q] = unsafe[q].lo;
-            C.uhi[q] = unsafe[q].hi;
+        std::vector<int32_t> cols(plan->ncols);
+        for (int32_t c = 0; c < plan->ncols; ++c) cols[c] = c;
+        return run_check(plan, C, cols.data(), unsafe, out, z_out);
+    });
+}
+
+kry_status kry_check_box_subset(kry_plan_t* plan, const int32_t* cols, int32_t ncols, const int32_t* rows,
+                                int32_t nrows, int64_t steps, const kry_interval* unsafe, kry_verdict* out,
+                                double* z_out) {
+    return guarded("kry_check_box_subset", [&]() -> kry_status {
+        if (!plan || !cols || !rows || !unsafe || !out)
+            return fail(KRY_EINVAL, "plan, cols, rows, unsafe and out must be non-NULL");
+        if (!plan->projected) return fail(KRY_EINVAL, "kry_project_expm must run first");
+        if (ncols < 1 || ncols > kMaxCheckCols || ncols > plan->ncols)
+            return fail(KRY_EINVAL, "ncols must be in [1, min(64, the plan's basis columns)]");
+        if (nrows < 1 || nrows > plan->o_out) return fail(KRY_EINVAL, "nrows must be in [1, the plan's output rows]");
+        if (steps < 0 || steps > plan->steps) return fail(KRY_EINVAL, "steps must be in [0, the plan's steps]");
+        std::vector<char> seen(plan->ncols, 0);
+        for (int32_t c = 0; c < ncols; ++c) {
+            if (cols[c] < 0 || cols[c] >= plan->ncols || seen[cols[c]])
+                return fail(KRY_EINVAL, "cols must be distinct basis columns of the plan");
+            seen[cols[c]] = 1;
         }
-        C.part = plan->cpart();
-        C.verdict = plan->verdict();
-        hipError_t e = timed("check", plan->stream, [&] { return launch_check(C, plan->stream); });
-        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("check: ") + hipGetErrorString(e));
-        plan->verdict_host.assign(6 + plan->ncols, 0.0);
-        KRY_HIP(hipMemcpyAsync(plan->verdict_host.data(), plan->verdict(), plan->verdict_host.size() * sizeof(double),
-                               hipMemcpyDeviceToHost, plan->stream));
-        KRY_HIP(hipStreamSynchronize(plan->stream));
-        const double* v = plan->verdict_host.data();
-        out->first_step = (int64_t)v[0];
-        out->row = (int32_t)v[1];
-        out->y = v[2];
-        out->lo = v[3];
-        out->hi = v[4];
-        out->status = (int32_t)v[5];
-        if (plan->nonfinite) out->status = KRY_ENUMERIC;
-        if (z_out) {
-            int32_t g = 0;
-            for (int32_t c = 0; c < plan->ncols; ++c)
-                if (plan->col_role[c] == 0) z_out[g++] = v[6 + c];
-        }
-        return KRY_OK;
+        for (int32_t q = 0; q < nrows; ++q)
+            if (rows[q] < 0 || rows[q] >= plan->o_out) return fail(KRY_EINVAL, "rows must be output rows of the plan");
+        CheckArgs C{};
+        C.nruns = ncols;
+        C.o = nrows;
+        C.steps = steps;
+        C.mapped = 1;
+        C.o_all = plan->o_out;
+        C.n_all = plan->ncols;
+        for (int32_t q = 0; q < nrows; ++q) C.row_of[q] = rows[q];
+        for (int32_t c = 0; c < ncols; ++c) C.col_of[c] = cols[c];
+        return run_check(plan, C, cols, unsafe, out, z_out);
     });
 }
 
@@ -1796,30 +1861,68 @@ kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps) {
     return guarded("kry_plan_set_error_target", [&]() -> kry_status {
         if (!plan) return fail(KRY_EINVAL, "plan is NULL");
         if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(KRY_EINVAL, "error target must be finite and >= 0");
-        if (eps > 0.0 && plan->method != KRY_LANCZOS)
-            return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos plans");
+        const bool arnoldi = plan->method == KRY_ARNOLDI;
+        if (eps > 0.0 && plan->method != KRY_LANCZOS && !arnoldi)
+            return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for Lanczos and Arnoldi plans");
         if (eps > 0.0 && plan->transposed)
             return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
         if (eps > 0.0 && plan->graph_on)
             return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
         if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
-        plan->err_eps = eps;
-        if (eps == 0.0) return KRY_OK;
+        if (eps > 0.0 && arnoldi && plan->k > kMaxK)
+            return fail(KRY_ENOTSUP, "the Arnoldi error control holds k <= 56 (its exponentials sit in LDS)");
+        if (eps == 0.0) {
+            plan->err_eps = 0.0;
+            return KRY_OK;
+        }
         if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
         if (!plan->flag_ev) KRY_HIP(hipEventCreateWithFlags(&plan->flag_ev, hipEventDisableTiming));
         // lambda_max of the symmetric part of A, bounded by Gershgorin
         double lam;
+        const Layout& Y = plan->Y;
+        double* out = plan->at<double>(Y.eflags) + kMaxP;
         if (plan->sys.kind == KRY_STENCIL7) {
             stencil_row_bounds(plan->sys, nullptr, &lam);
-        } else {
-            const Layout& Y = plan->Y;
+        } else if (!arnoldi) {
+            // Lanczos: A is symmetric, its own rows give the bound
             CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
-            double* out = plan->at<double>(Y.eflags) + kMaxP;
             hipError_t e = launch_row_gersh(A, plan->sys.n, plan->np_part(), Y.nblocks, Y.rpb, out, plan->stream);
             if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("row_gersh: ") + hipGetErrorString(e));
             KRY_HIP(hipMemcpyAsync(&lam, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
             KRY_HIP(hipStreamSynchronize(plan->stream));
+        } else {
+            // general A: rows and columns; the column sums in fixed point with
+            // a unit of 2^-40 of the largest |a| (rounded to a power of two)
+            CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
+            const int64_t nnz = plan->sys.nnz;
+            double amax = 0.0;
+            hipError_t e = launch_abs_max(A.vals, nnz, plan->np_part(), Y.nblocks, out, plan->stream);
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("abs_max: ") + hipGetErrorString(e));
+            KRY_HIP(hipMemcpyAsync(&amax, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+            KRY_HIP(hipStreamSynchronize(plan->stream));
+            if (!std::isfinite(amax)) {
+                lam = INFINITY;                  // the runs report the non-finite entries themselves
+            } else if (amax == 0.0) {
+                lam = 0.0;
+            } else {
+                int ex = 0;
+                std::frexp(amax, &ex);           // amax < 2^ex
+                const double u = std::ldexp(1.0, ex - 40);
+                int* overflow = reinterpret_cast<int*>(out + 1 + lemma1_hess_partials());
+                KRY_HIP(hipMemsetAsync(overflow, 0, sizeof(int), plan->stream));
+                // the basis store is free here and holds at least 8 n bytes
+                auto* colfix = plan->at<unsigned long long>(Y.vec);
+                e = launch_gersh_general(A, plan->sys.n, u, colfix, overflow, plan->np_part(), Y.nblocks, Y.rpb, out,
+                                         plan->stream);
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("gersh_general: ") + hipGetErrorString(e));
+                int ovf = 0;
+                KRY_HIP(hipMemcpyAsync(&lam, out, sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+                KRY_HIP(hipMemcpyAsync(&ovf, overflow, sizeof(int), hipMemcpyDeviceToHost, plan->stream));
+                KRY_HIP(hipStreamSynchronize(plan->stream));
+                if (ovf) return fail(KRY_ENOTSUP, "a column of A is too dense for the Gershgorin column sums");
+            }
         }
+        plan->err_eps = eps;
         plan->lam_plus = lam > 0.0 ? lam : 0.0;
         plan->projected = false;
         return KRY_OK;

@@ -62,22 +62,57 @@ __global__ __launch_bounds__(kBlock) void k_bstart(SegTable T, BlockStart S, E* 
 // group reads up to 16 CSR entries of the row at once (one per lane) and
 // passes them round by shuffles, so all 16 gathers of V_j rows (each one
 // contiguous 16-value row) are in flight together; slots past the row's end
-// carry value 0 and column 0.
+// carry value 0 and column 0.  Rows are software-pipelined along the group's
+// walk: while row r's gathers are in flight the group already holds row
+// r + 16's entries and row r + 32's row pointers.  Loads for rows past the
+// range read in-range pointers and are dropped.
+template <typename E>
+__device__ __forceinline__ double bspmm_val(const CsrArgs& A, int64_t e) {
+    if constexpr (sizeof(E) == 4) return (double)A.vals32[e];
+    else return A.vals[e];
+}
+
 template <typename E>
 __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict__ V, E* __restrict__ W, int64_t n,
-                                                  BlockArgs B) {
+                                                  int64_t rows_per_block, BlockArgs B) {
     if (block_done(B)) return;
     const int c = threadIdx.x & 15;
     const int grp = threadIdx.x >> 4;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / 16);
-    for (int64_t r = (int64_t)blockIdx.x * (kBlock / 16) + grp; r < n; r += stride) {
-        const int64_t e0 = A.rowptr[r], e1 = A.rowptr[r + 1];
+    // a contiguous range of rows per workgroup, the ranges of each XCD
+    // contiguous (so the rows a stencil row gathers are near those its XCD
+    // works on); groups take the range's rows in turn
+    const int64_t r0 = (int64_t)logical_block((int)gridDim.x) * rows_per_block;
+    const int64_t r1 = min(n, r0 + rows_per_block);
+    const int64_t stride = kBlock / 16;
+    const int64_t last = n - 1;
+    n = r1;                                        // the walk below ends at the range's end
+    int64_t r = r0 + grp;
+    // row pointers of r and r + stride, entries of r
+    int64_t e0 = A.rowptr[min(r, last)], e1 = A.rowptr[min(r, last) + 1];
+    int64_t f0 = A.rowptr[min(r + stride, last)], f1 = A.rowptr[min(r + stride, last) + 1];
+    int32_t mycol;
+    double myval;
+    {
+        const int64_t e = e0 + c;
+        const bool ok = r < n && e < e1;
+        mycol = ok ? A.colidx[e] : 0;
+        myval = ok ? bspmm_val<E>(A, e) : 0.0;
+    }
+    for (; r < n; r += stride) {
+        // next row's entries (its pointers are here) and the pointers two rows ahead
+        const int64_t rn = r + stride;
+        int32_t ncol;
+        double nval;
+        {
+            const int64_t e = f0 + c;
+            const bool ok = rn < n && e < f1;
+            ncol = ok ? A.colidx[e] : 0;
+            nval = ok ? bspmm_val<E>(A, e) : 0.0;
+        }
+        const int64_t rnn = min(rn + stride, last);
+        const int64_t g0 = A.rowptr[rnn], g1 = A.rowptr[rnn + 1];
         double acc = 0.0;
-        for (int64_t eb = e0; eb < e1; eb += 16) {
-            const int64_t e = eb + c;
-            const bool ok = e < e1;
-            const int32_t mycol = ok ? A.colidx[e] : 0;
-            const double myval = ok ? (sizeof(E) == 4 ? (double)A.vals32[e] : A.vals[e]) : 0.0;
+        {
             double x[16], a[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -88,7 +123,29 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc = fma(a[q], x[q], acc);
         }
+        // rows longer than 16 entries
+        for (int64_t eb = e0 + 16; eb < e1; eb += 16) {
+            const int64_t e = eb + c;
+            const bool ok = e < e1;
+            const int32_t col0 = ok ? A.colidx[e] : 0;
+            const double v0 = ok ? bspmm_val<E>(A, e) : 0.0;
+            double x[16], a[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int32_t col = __shfl(col0, q, 16);
+                a[q] = __shfl(v0, q, 16);
+                x[q] = (double)V[(int64_t)col * kBW + c];
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc = fma(a[q], x[q], acc);
+        }
         W[r * kBW + c] = (E)acc;
+        e0 = f0;
+        e1 = f1;
+        f0 = g0;
+        f1 = g1;
+        mycol = ncol;
+        myval = nval;
     }
 }
 
@@ -361,14 +418,16 @@ hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void*
 }
 
 hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, const BlockArgs& B, hipStream_t s) {
-    const int64_t want = (B.n + kBlock / 16 - 1) / (kBlock / 16);
-    const int grid = (int)std::min<int64_t>(want, 16384);
+    // about 4096 workgroups (a multiple of 8 for the XCD map), at least 16 rows each
+    int64_t rpb = std::max<int64_t>((B.n + 4095) / 4096, kBlock / 16);
+    int64_t grid = (B.n + rpb - 1) / rpb;
+    grid = (grid + 7) / 8 * 8;
     if (f32)
-        hipLaunchKernelGGL(k_bspmm<float>, dim3(grid), dim3(kBlock), 0, s, A, static_cast<const float*>(V),
-                           static_cast<float*>(W), B.n, B);
+        hipLaunchKernelGGL(k_bspmm<float>, dim3((unsigned)grid), dim3(kBlock), 0, s, A,
+                           static_cast<const float*>(V), static_cast<float*>(W), B.n, rpb, B);
     else
-        hipLaunchKernelGGL(k_bspmm<double>, dim3(grid), dim3(kBlock), 0, s, A, static_cast<const double*>(V),
-                           static_cast<double*>(W), B.n, B);
+        hipLaunchKernelGGL(k_bspmm<double>, dim3((unsigned)grid), dim3(kBlock), 0, s, A,
+                           static_cast<const double*>(V), static_cast<double*>(W), B.n, rpb, B);
     return hipGetLastError();
 }
 

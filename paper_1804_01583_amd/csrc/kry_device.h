@@ -22,8 +22,8 @@ __device__ __forceinline__ void wave_sum(double (&v)[NV]) {
 }
 
 // Sum of v over the block; thread i < NV returns total i.  `lds` holds
-// (kBlock / 64) * NV doubles.  Every thread must call it.
-template <int NV>
+// (NTH / 64) * NV doubles (NTH threads in the block).  Every thread must call it.
+template <int NV, int NTH = kBlock>
 __device__ __forceinline__ double block_sum(double (&v)[NV], double* lds) {
     wave_sum<NV>(v);
     const int wave = threadIdx.x >> 6;
@@ -36,7 +36,7 @@ __device__ __forceinline__ double block_sum(double (&v)[NV], double* lds) {
     if (threadIdx.x < NV) {
         t = lds[threadIdx.x];
 #pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) t += lds[w * NV + threadIdx.x];
+        for (int w = 1; w < NTH / 64; ++w) t += lds[w * NV + threadIdx.x];
     }
     __syncthreads();
     return t;
@@ -64,10 +64,10 @@ __device__ __forceinline__ bool batch_stopped(const BatchArgs& B) {
 }
 
 // Writes the block totals of v as partials part[i * nblocks + block].
-template <int NV>
+template <int NV, int NTH = kBlock>
 __device__ __forceinline__ void store_partials(double (&v)[NV], double* part, int nblocks, double* lds,
                                                int xcd_map) {
-    const double t = block_sum<NV>(v, lds);
+    const double t = block_sum<NV, NTH>(v, lds);
     if (threadIdx.x < NV) part[(int64_t)threadIdx.x * nblocks + logical_block(nblocks, xcd_map)] = t;
 }
 
@@ -79,32 +79,32 @@ template <int NV>
 struct PartialLoads {
     static constexpr int U = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
 };
-template <int NV>
+template <int NV, int NTH = kBlock>
 __device__ __forceinline__ void add_strided_partials(const double* part, int nb, int vbeg, double (&acc)[NV],
                                                      int first) {
     constexpr int U = PartialLoads<NV>::U;
-    for (int b0 = first; b0 < nb; b0 += U * kBlock) {
+    for (int b0 = first; b0 < nb; b0 += U * NTH) {
         double v[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             // clamped, unconditional loads (a load under a condition becomes
             // a branch that waits for it); entries past nb are not added
-            const int b = min(b0 + u * kBlock, nb - 1);
+            const int b = min(b0 + u * NTH, nb - 1);
 #pragma unroll
             for (int i = 0; i < NV; ++i) v[u][i] = part[(int64_t)(vbeg + i) * nb + b];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (b0 + u * kBlock < nb) {
+            if (b0 + u * NTH < nb) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] += v[u][i];
             }
         }
     }
 }
-template <int NV>
+template <int NV, int NTH = kBlock>
 __device__ __forceinline__ void add_strided_partials(const double* part, int nb, int vbeg, double (&acc)[NV]) {
-    add_strided_partials<NV>(part, nb, vbeg, acc, (int)threadIdx.x);
+    add_strided_partials<NV, NTH>(part, nb, vbeg, acc, (int)threadIdx.x);
 }
 
 // The same sum split in two, so that other loads can be issued between
@@ -289,13 +289,13 @@ __device__ __forceinline__ double* stage_part(const BatchArgs& B, int stage) {
 // The reduction of stage j-1's norms, done first: thread t sums blocks t,
 // t + kBlock, ... (every block reads the same few KB of partials; issuing
 // them alongside the row work, instead of before it, measured slower)
-template <int P>
+template <int P, int NTH = kBlock>
 __device__ __forceinline__ void load_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
                                                  double (&sig_prev)[P], double& anorm) {
     const double* part = stage_part(B, j - 1);
 #pragma unroll
     for (int p = 0; p < P; ++p) pacc[p] = 0.0;
-    for (int b = threadIdx.x; b < B.nblocks; b += kBlock) {
+    for (int b = threadIdx.x; b < B.nblocks; b += NTH) {
 #pragma unroll
         for (int p = 0; p < P; ++p) pacc[p] += part[(int64_t)p * B.nblocks + b];
     }
@@ -306,11 +306,11 @@ __device__ __forceinline__ void load_stage_norms(const BatchArgs& B, int j, doub
 
 // Finishes the stage j-1 reduction: sigma_j and cprev = beta_{j-1} sigma_{j-1}
 // for every run; block 0 records the stage.  Every thread must call it.
-template <int P>
+template <int P, int NTH = kBlock>
 __device__ __forceinline__ void finish_stage_norms(const BatchArgs& B, int j, double (&pacc)[P],
                                                    const double (&sig_prev)[P], double anorm, double* s_lds,
                                                    double* s_nrm, double (&sig)[P], double (&cprev)[P]) {
-    const double t = block_sum<P>(pacc, s_lds);
+    const double t = block_sum<P, NTH>(pacc, s_lds);
     if (threadIdx.x < P) s_nrm[threadIdx.x] = t;
     __syncthreads();
     if (blockIdx.x == 0) record_stage(B, P, j, s_nrm);

@@ -21,6 +21,7 @@
 // again with the whole of T (size k + 1).  Each such exponential is a job;
 // k_assemble scatters the jobs' rows to their (output row, column) places.
 #include "kry_internal.h"
+#include "kry_ldsmm.h"
 
 #include <cmath>
 
@@ -28,63 +29,11 @@ namespace kry {
 
 namespace {
 
-constexpr int kLd = kMaxK + 1;          // padded LDS row length
-constexpr int kSlot = kMaxK * kLd;      // one matrix in LDS
-
 __device__ __forceinline__ const double* run_scal(const ExpmArgs& E, int r) {
     return E.scal + (int64_t)r * E.L.stride;
 }
 
-// Barrier that orders LDS traffic only: a __syncthreads() would also wait for
-// every global store of the wave (the chain publishes one step per pass).
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// C = A B + extra(i, j) for mm x mm matrices in LDS slots sa, sb, sc (mm
-// even, <= kMaxK; sc differs from sa and sb) on the f64 16x16x4 matrix cores:
-// the 16 x 16 output tiles are spread over the waves, entries past mm read as
-// zero.  Lane layout: A[m][k] in lane m + 16k, B[k][n] in lane n + 16k,
-// D[m][n] in lane n + 16 (m % 4), accumulator register m / 4.
-template <class FE>
-__device__ __forceinline__ void mm_mfma(double* lds, int sa, int sb, int sc, int mm, FE extra) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
-    const int mt = (mm + 15) >> 4;
-    const int lr = lane & 15, lk = lane >> 4;
-    for (int tile = wave; tile < mt * mt; tile += nw) {
-        const int ti = tile / mt, tj = tile % mt;
-        const int arow = ti * 16 + lr, bcol = tj * 16 + lr;
-        // every fragment of the tile is loaded before the first product (the
-        // loads pipeline); clamped addresses stay inside the slot, values past
-        // mm are masked to zero
-        const int ar = min(arow, mm - 1), bc = min(bcol, mm - 1);
-        constexpr int KS = kMaxK / 4;
-        double a[KS], b[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int kq = 4 * s + lk, kc = min(kq, mm - 1);
-            a[s] = lds[sa * kSlot + ar * kLd + kc];
-            b[s] = lds[sb * kSlot + kc * kLd + bc];
-            a[s] = (arow < mm && kq < mm) ? a[s] : 0.0;
-            b[s] = (bcol < mm && kq < mm) ? b[s] : 0.0;
-        }
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-            if (4 * s < mm) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
-        const int n = tj * 16 + lr;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int mrow = ti * 16 + 4 * r + lk;
-            if (mrow < mm && n < mm) lds[sc * kSlot + mrow * kLd + n] = acc[r] + extra(mrow, n);
-        }
-    }
-    __syncthreads();
-}
+using namespace ldsmm;
 
 // One workgroup per run: Phi, Psi and the two chains.
 __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
@@ -146,51 +95,18 @@ __global__ __launch_bounds__(kExpmThreads) void k_expm_chain(ExpmArgs E) {
     __syncthreads();
 
     // scaling: |X / 2^sq|_1 <= 1
-    double colsum = 0.0;
-    if (tid < mm) {
-        for (int i = 0; i < mm; ++i) colsum += fabs(S0[i * kLd + tid]);
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) colsum = fmax(colsum, __shfl_xor(colsum, off, 64));
-    if ((tid & 63) == 0) s_red[tid >> 6] = colsum;
-    __syncthreads();
-    double nrm = 0.0;
-    for (int w = 0; w < (int)blockDim.x / 64; ++w) nrm = fmax(nrm, s_red[w]);
+    const double nrm = norm1_slot0(lds, mm, s_red);
     int sq = 0;
     // a non-finite H (flagged by the iteration) gets no squarings
     while (isfinite(nrm) && nrm > ldexp(1.0, sq) && sq < 1100) ++sq;
     const double shrink = ldexp(1.0, -sq);
-    __syncthreads();
     for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
         const int i = idx / mm, c = idx % mm;
         S0[i * kLd + c] *= shrink;
     }
     __syncthreads();
-
-    // Taylor polynomial of degree 18 by Paterson-Stockmeyer in chunks of 4:
-    //   T(X) = L0 + X4 (L1 + X4 (L2 + X4 (L3 + X4 L4))),
-    //   L_q = f_{4q} I + f_{4q+1} X + f_{4q+2} X2 + f_{4q+3} X3,  f_i = 1/i! (0 past 18);
-    // with |X|_1 <= 1 the remainder is below e/19! < 2e-17 relative.
-    double f[20];
-    f[0] = 1.0;
-    for (int i = 1; i < 20; ++i) f[i] = i <= 18 ? f[i - 1] / i : 0.0;
+    taylor18(lds, mm, 1.0);                                                    // T(X) in slot 4
     auto none = [](int, int) { return 0.0; };
-    mm_mfma(lds, 0, 0, 1, mm, none);                                           // X2
-    mm_mfma(lds, 1, 0, 2, mm, none);                                           // X3
-    mm_mfma(lds, 1, 1, 3, mm, none);                                           // X4
-    auto chunk = [=](int q, int i, int j) {
-        const int e = i * kLd + j;
-        return (i == j ? f[4 * q] : 0.0) + f[4 * q + 1] * S0[e] + f[4 * q + 2] * S1[e] + f[4 * q + 3] * S2[e];
-    };
-    for (int idx = tid; idx < mm * mm; idx += blockDim.x) {
-        const int i = idx / mm, c = idx % mm;
-        S4[i * kLd + c] = chunk(4, i, c);
-    }
-    __syncthreads();
-    mm_mfma(lds, 4, 3, 5, mm, [=](int i, int j) { return chunk(3, i, j); });
-    mm_mfma(lds, 5, 3, 4, mm, [=](int i, int j) { return chunk(2, i, j); });
-    mm_mfma(lds, 4, 3, 5, mm, [=](int i, int j) { return chunk(1, i, j); });
-    mm_mfma(lds, 5, 3, 4, mm, [=](int i, int j) { return chunk(0, i, j); });   // T(X) in S4
 
     // LDS matrices below are addressed as lds + slot * kSlot with an integer
     // slot, never through stored pointers, so the accesses stay ds_* (LDS)
@@ -366,6 +282,23 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs A) {
         if (q < A.o) A.basis[(s * A.o + q) * A.nruns + run] = y[q];
 }
 
+// Basis entry of checked column r at step s and checked row q.
+__device__ __forceinline__ double check_entry(const CheckArgs& C, int64_t s, int q, int r) {
+    if (!C.mapped) return C.basis[(s * C.o + q) * C.nruns + r];
+    return C.basis[(s * C.o_all + C.row_of[q]) * C.n_all + C.col_of[r]];
+}
+__device__ __forceinline__ int check_col(const CheckArgs& C, int r) { return C.mapped ? C.col_of[r] : r; }
+
+// mid = sum_r M_r zc_r and rad = sum_r |M_r| radius_r over the checked columns
+__device__ __forceinline__ void check_range(const CheckArgs& C, int64_t s, int q, double& mid, double& rad) {
+    for (int r = 0; r < C.nruns; ++r) {
+        const double m = check_entry(C, s, q, r);
+        const int c = check_col(C, r);
+        mid = fma(m, C.zc[c], mid);
+        rad = fma(fabs(m), C.radius[c], rad);
+    }
+}
+
 // a9, part 1: each block finds the first violated (step, row) among its
 // entries (step-major order) and whether a non-finite range was met.
 __global__ __launch_bounds__(kBlock) void k_check_blocks(CheckArgs C) {
@@ -378,12 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_check_blocks(CheckArgs C) {
     if (e < total) {
         const int64_t s = e / C.o;
         const int q = (int)(e % C.o);
-        const double* M = C.basis + (s * C.o + q) * C.nruns;
         double mid = 0.0, rad = 0.0;
-        for (int r = 0; r < C.nruns; ++r) {
-            mid = fma(M[r], C.zc[r], mid);
-            rad = fma(fabs(M[r]), C.radius[r], rad);
-        }
+        check_range(C, s, q, mid, rad);
         if (!isfinite(mid) || !isfinite(rad)) bad = 1;
         else if ((mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q])) best = e;
     }
@@ -431,24 +360,22 @@ __global__ __launch_bounds__(kBlock) void k_check_final(CheckArgs C, int nb) {
     out[5] = bad > 0.0 ? 4.0 : 0.0;    // KRY_ENUMERIC
     if (best >= total) {
         out[0] = -1.0; out[1] = -1.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
-        for (int r = 0; r < C.nruns; ++r) out[6 + r] = C.zc[r];
+        for (int r = 0; r < C.nruns; ++r) out[6 + r] = C.zc[check_col(C, r)];
         return;
     }
     const int64_t e = (int64_t)best;
     const int64_t s = e / C.o;
     const int q = (int)(e % C.o);
-    const double* M = C.basis + (s * C.o + q) * C.nruns;
     double mid = 0.0, rad = 0.0;
-    for (int r = 0; r < C.nruns; ++r) {
-        mid = fma(M[r], C.zc[r], mid);
-        rad = fma(fabs(M[r]), C.radius[r], rad);
-    }
+    check_range(C, s, q, mid, rad);
     double lam = 0.0, dir = 0.0;
     if (mid < C.ulo[q]) { lam = (C.ulo[q] - mid) / rad; dir = 1.0; }
     else if (mid > C.uhi[q]) { lam = (mid - C.uhi[q]) / rad; dir = -1.0; }
     for (int r = 0; r < C.nruns; ++r) {
-        const double sg = (M[r] > 0.0) ? 1.0 : ((M[r] < 0.0) ? -1.0 : 0.0);
-        out[6 + r] = C.zc[r] + dir * lam * sg * C.radius[r];
+        const double m = check_entry(C, s, q, r);
+        const int c = check_col(C, r);
+        const double sg = (m > 0.0) ? 1.0 : ((m < 0.0) ? -1.0 : 0.0);
+        out[6 + r] = C.zc[c] + dir * lam * sg * C.radius[c];
     }
     out[0] = (double)s;
     out[1] = (double)q;

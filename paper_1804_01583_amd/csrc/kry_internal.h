@@ -146,15 +146,22 @@ struct AssembleArgs {
     int32_t o_out, ncols;
 };
 
+constexpr int kMaxCheckCols = 64;   // columns of a check over part of the basis
 struct CheckArgs {
     const double* basis;
-    const double* zc;        // per run: box center (1 for fixed runs)
-    const double* radius;    // per run: box radius (0 for fixed runs)
-    int32_t nruns, o;
+    const double* zc;        // per basis column: box center (1 for fixed runs)
+    const double* radius;    // per basis column: box radius (0 for fixed runs)
+    int32_t nruns, o;        // columns and output rows checked
     int64_t steps;
     double ulo[kMaxO], uhi[kMaxO];
     double* part;            // [2 * check_blocks] first hit and non-finite flag per block
     double* verdict;         // [first_step, row, y, lo, hi, status, z[nruns]]
+    // part of the basis: checked row q is basis row row_of[q] and checked
+    // column r basis column col_of[r] of a [steps+1][o_all][n_all] basis
+    int32_t mapped;          // 0: the whole basis (o_all = o, n_all = nruns, identity maps)
+    int32_t o_all, n_all;
+    int32_t row_of[kMaxO];
+    int32_t col_of[kMaxCheckCols];
 };
 
 // Classical Gram-Schmidt against the stored basis: CGS2 for Arnoldi, and the
@@ -186,6 +193,18 @@ hipError_t launch_record_stage(int P, const BatchArgs& B, int j, hipStream_t s);
 hipError_t launch_lemma1(int P, const BatchArgs& B, const ErrArgs& X, int j, hipStream_t s);
 hipError_t launch_row_gersh(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks, int64_t rows_per_block,
                             double* out, hipStream_t s);
+// Arnoldi runs (Hessenberg H): partials holds lemma1_hess_partials() doubles
+hipError_t errctl_prepare();
+int lemma1_hess_partials();
+hipError_t launch_lemma1_hess(int P, const BatchArgs& B, const ErrArgs& X, int j, double* partials, hipStream_t s);
+// largest |a| (block maxima in partials, nblocks of them)
+hipError_t launch_abs_max(const double* vals, int64_t nnz, double* partials, int32_t nblocks, double* out,
+                          hipStream_t s);
+// Gershgorin bound of the symmetric part of a general CSR matrix; colfix
+// holds n integers of scratch, *overflow is set when a column sum overflows
+hipError_t launch_gersh_general(const CsrArgs& A, int64_t n, double u, unsigned long long* colfix, int* overflow,
+                                double* partials, int32_t nblocks, int64_t rows_per_block, double* out,
+                                hipStream_t s);
 
 // ---- block Arnoldi (kry_block.hip) ------------------------------------------
 constexpr int kBW = 16;          // block width: p <= 16 real columns, the rest zero
@@ -295,7 +314,9 @@ hipError_t launch_lz1_sell(int P, int O, const SellArgs& A, const double* xin, d
 hipError_t launch_lz1_stencil(int P, int O, const StencilArgs& S, const double* xin, double* xout,
                               const SegTable& T, int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j,
                               hipStream_t s);
-// grid B.ap_nblocks (column blocks); C u_j then comes from launch_lz1_proj
+// grid lz1_march_blocks(ny, nz, P) ((y, z) tiles, also the count of its
+// partials; the most for P = 8); C u_j then comes from launch_lz1_proj
+int32_t lz1_march_blocks(int64_t ny, int64_t nz, int P);
 hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
                             const Lz1Args& Z, int j, hipStream_t s);
 hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B,

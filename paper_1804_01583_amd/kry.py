@@ -88,6 +88,8 @@ def _load():
     lib.kry_check_lp_safety.argtypes = [P, P, P, ct.c_int32, P, P, ct.c_int32, ct.POINTER(ct.c_int64),
                                         ct.POINTER(ct.c_int32), P, P, P]
     lib.kry_check_box_safety.argtypes = [P, ct.POINTER(KryInterval), ct.POINTER(KryVerdict), P]
+    lib.kry_check_box_subset.argtypes = [P, P, ct.c_int32, P, ct.c_int32, ct.c_int64, ct.POINTER(KryInterval),
+                                         ct.POINTER(KryVerdict), P]
     lib.kry_plan_workspace.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int64,
                                        ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]
     lib.kry_footprint.argtypes = [ct.POINTER(KrySystem), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32,
@@ -111,8 +113,8 @@ def _load():
     lib.kry_profile_read.argtypes = [ct.c_char_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
     lib.kry_profile_names.restype = ct.c_char_p
     for f in ("kry_plan", "kry_plan_create", "kry_verify_noalloc", "kry_plan_create_transposed", "kry_footprint_transposed",
-              "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
-              "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
+              "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_check_box_subset",
+              "kry_footprint", "kry_plan_workspace", "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
               "kry_profile_reset", "kry_profile_read"):
         getattr(lib, f).restype = ct.c_int
@@ -122,8 +124,8 @@ def _load():
 lib = _load()
 
 EXPORTED = ["kry_plan", "kry_plan_create", "kry_verify_noalloc", "kry_plan_create_transposed", "kry_footprint_transposed",
-            "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_footprint", "kry_plan_workspace",
-            "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
+            "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_check_box_subset",
+            "kry_footprint", "kry_plan_workspace", "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
             "kry_plan_error",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
@@ -220,6 +222,19 @@ def kry_check_box_safety(plan: int, unsafe: np.ndarray, ngen: int):
     v = KryVerdict()
     z = np.zeros(max(ngen, 1))
     _check(lib.kry_check_box_safety(plan, U, ct.byref(v), z.ctypes.data))
+    return v, z[:ngen]
+
+
+def kry_check_box_subset(plan: int, cols, rows, steps: int, unsafe: np.ndarray, ngen: int):
+    """The box check over basis columns `cols` and output rows `rows` up to
+    `steps`; ngen = generator columns among cols (length of z)."""
+    c = np.ascontiguousarray(cols, np.int32)
+    r = np.ascontiguousarray(rows, np.int32)
+    U = (KryInterval * len(r))(*[KryInterval(float(a), float(b)) for a, b in unsafe])
+    v = KryVerdict()
+    z = np.zeros(max(ngen, 1))
+    _check(lib.kry_check_box_subset(plan, c.ctypes.data, c.size, r.ctypes.data, r.size, steps, U, ct.byref(v),
+                                    z.ctypes.data))
     return v, z[:ngen]
 
 

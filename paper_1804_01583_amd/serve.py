@@ -10,14 +10,22 @@ systems).  The server
   passed over `max_bypass` times is then waited for (the others stay queued
   until it fits), so a large query delays later small ones by a bounded
   amount instead of stalling the queue,
-* runs admitted queries concurrently, each on its own HIP stream, so their
-  kernels overlap on the device (a query's generators are already advanced
-  together by every mat-vec launch of its plan),
+* batches an admitted query with the waiting queries on the same resident
+  system, precision, time step and Krylov dimension (up to 8 output rows
+  and 64 basis columns together): they become one plan whose runs are all
+  their generators, so every mat-vec launch advances the same Krylov step
+  of all of them, and each query's verdict is the box check over its own
+  columns, rows and steps (kry_check_box_subset),
+* runs admitted batches concurrently, each on its own HIP stream, so their
+  kernels overlap on the device,
 * keeps every plan's basis and state on the device until its verdict is
   read, and records arrival -> verdict latency.
 
-A query's result does not depend on what runs beside it: every kernel's
-arithmetic and reduction order depend only on the query's own sizes.
+A query's result does not depend on what runs beside it on other streams:
+every kernel's arithmetic and reduction order depend only on its plan's
+sizes.  In a batch, a run's Krylov data are those of the run alone (runs do
+not interact); the longer time grid and the extra output rows of the batch's
+plan change its per-step exponentials by rounding only.
 
 Systems are resident: a catalog holds one device copy per (family, grid),
 with the prepared matrix (sliced-ELL copy and norm) of each precision a
@@ -88,6 +96,7 @@ class Result:
     footprint: int
     verified_steps: int
     basis: Optional[np.ndarray] = None
+    group: int = 1            # queries in the plan that ran it
 
     @property
     def latency(self) -> float:
@@ -100,6 +109,40 @@ class _Pending:
     footprint: int
     released: float
     bypassed: int = 0
+
+
+MAX_GROUP_ROWS = 8        # output rows of one plan
+MAX_GROUP_COLS = 64       # basis columns one subset check takes
+
+
+def group_key(q):
+    """Queries that can share one plan: same resident system, precision,
+    time step and Krylov dimension."""
+    return (q.family, q.m, q.precision, q.dt, q.k)
+
+
+def form_group(pending, first: int, max_queries: int = 8, fits=None):
+    """Removes pending[first] and the later waiting queries with its key
+    (oldest first) from `pending` and returns them: together at most
+    MAX_GROUP_ROWS output rows, MAX_GROUP_COLS generators and max_queries
+    queries; `fits(group)` may veto each addition (the HBM budget)."""
+    head = pending[first]
+    del pending[first]
+    group = [head]
+    key = group_key(head.query)
+    rows, cols = len(head.query.C), len(head.query.gens)
+    i = 0
+    while i < len(pending) and len(group) < max_queries:
+        q = pending[i].query
+        if (group_key(q) == key and rows + len(q.C) <= MAX_GROUP_ROWS and cols + len(q.gens) <= MAX_GROUP_COLS
+                and (fits is None or fits(group + [pending[i]]))):
+            group.append(pending[i])
+            rows += len(q.C)
+            cols += len(q.gens)
+            del pending[i]
+        else:
+            i += 1
+    return group
 
 
 def pick_admission(pending, in_use: int, budget: int, max_bypass: int, scan: int = 64):
@@ -129,11 +172,13 @@ class Server:
     other ones serve for testing the scheduling on the host."""
 
     def __init__(self, catalog: Optional[Catalog], slots: int = 8, budget_bytes: int = 200 << 30,
-                 runner=None, footprint=None, max_bypass: int = 16):
+                 runner=None, footprint=None, max_bypass: int = 16, batch: bool = True, max_group: int = 8):
         self.catalog = catalog
         self.slots = slots
         self.budget = budget_bytes
         self.max_bypass = max_bypass
+        # batches need the GPU runner (a stand-in runner takes one query)
+        self.max_group = max_group if (batch and runner is None) else 1
         self._runner = runner
         self._footprint = footprint
 
@@ -145,6 +190,51 @@ class Server:
         nseg = sum(g.seg.nseg for g in q.gens) + sum(c.nseg for c in q.C)
         return kry.kry_plan_workspace(dsys.system_for(prec), len(q.gens), len(q.C), q.k, q.steps, nseg, prec,
                                  kry.KRY_AUTO, 0)
+
+    def group_footprint(self, group) -> int:
+        """Workspace of the plan that runs a group of _Pending queries."""
+        if len(group) == 1:
+            return group[0].footprint
+        qs = [g.query for g in group]
+        prec = _precision(qs[0])
+        dsys = self.catalog.get(qs[0].family, qs[0].m, prec)
+        nseg = sum(g.seg.nseg for q in qs for g in q.gens) + sum(c.nseg for q in qs for c in q.C)
+        return kry.kry_plan_workspace(dsys.system_for(prec), sum(len(q.gens) for q in qs),
+                                      sum(len(q.C) for q in qs), qs[0].k, max(q.steps for q in qs), nseg, prec,
+                                      kry.KRY_AUTO, 0)
+
+    def _run_group(self, qs, stream, keep_basis: bool):
+        """One plan for all queries of a group: their generators are its
+        runs, their output rows its rows, the longest time grid its steps;
+        each query's verdict is the box check over its own columns, rows and
+        steps.  Returns [(verdict, basis, columns)] in group order."""
+        import torch
+        prec = _precision(qs[0])
+        dsys = self.catalog.get(qs[0].family, qs[0].m, prec)
+        gens = [g for q in qs for g in q.gens]
+        rows = [c for q in qs for c in q.C]
+        steps = max(q.steps for q in qs)
+        out_list = []
+        with torch.cuda.stream(stream):
+            plan = kry.Plan(dsys, k=qs[0].k, dt=qs[0].dt, steps=steps, precision=prec, stream=stream, gens=gens,
+                            C=rows)
+            out = None
+            if keep_basis:
+                out = torch.empty((steps + 1, len(rows), plan.nruns), dtype=torch.float64, device=dsys.device)
+            plan.project_expm(out)
+            c0 = r0 = 0
+            for q in qs:
+                g, o = len(q.gens), len(q.C)
+                v, z = kry.kry_check_box_subset(plan.handle, np.arange(c0, c0 + g), np.arange(r0, r0 + o), q.steps,
+                                                np.asarray(q.unsafe, np.float64), g)
+                verdict = {"first_step": int(v.first_step), "row": int(v.row), "status": int(v.status), "y": v.y,
+                           "lo": v.lo, "hi": v.hi, "z": z}
+                basis = out[:q.steps + 1, r0:r0 + o, c0:c0 + g].cpu().numpy() if keep_basis else None
+                out_list.append((verdict, basis, g))
+                c0 += g
+                r0 += o
+            plan.close()
+        return out_list
 
     def _run_one(self, q, stream, keep_basis: bool):
         import torch
@@ -174,9 +264,14 @@ class Server:
         if self._runner is None:
             import torch
             streams = [torch.cuda.Stream(device=self.catalog.device) for _ in range(self.slots)]
-            run = lambda q, slot, keep: self._run_one(q, streams[slot], keep)   # noqa: E731
+
+            def run_group(qs, slot, keep):
+                if len(qs) == 1:
+                    return [self._run_one(qs[0], streams[slot], keep)]
+                return self._run_group(qs, streams[slot], keep)
         else:
-            run = self._runner
+            def run_group(qs, slot, keep):
+                return [self._runner(q, slot, keep) for q in qs]
         t0 = time.perf_counter()
 
         def dispatcher():
@@ -204,28 +299,32 @@ class Server:
                             return
                         i = pick_admission(pending, state["in_use"], self.budget, self.max_bypass)
                         if i is not None:
-                            item = pending[i]
-                            del pending[i]
-                            state["in_use"] += item.footprint
+                            in_use = state["in_use"]
+                            group = form_group(
+                                pending, i, self.max_group,
+                                fits=lambda g: in_use + self.group_footprint(g) <= self.budget)
+                            fp = self.group_footprint(group)
+                            state["in_use"] += fp
                             break
                         if state["dispatched"] and not pending:
                             return
                         cond.wait()
                 admitted = time.perf_counter() - t0
                 try:
-                    verdict, basis, runs = run(item.query, slot, keep_basis)
+                    outs = run_group([g.query for g in group], slot, keep_basis)
                 except BaseException as e:  # noqa: BLE001 - surfaced after the threads stop
                     with cond:
                         errors.append(e)
-                        state["in_use"] -= item.footprint
+                        state["in_use"] -= fp
                         cond.notify_all()
                     return
                 done = time.perf_counter() - t0
-                q = item.query
                 with cond:
-                    state["in_use"] -= item.footprint
-                    results[q.qid] = Result(q.qid, q.arrival * time_scale, admitted, done, verdict, item.footprint,
-                                            (q.steps + 1) * runs, basis)
+                    state["in_use"] -= fp
+                    for item, (verdict, basis, runs) in zip(group, outs):
+                        q = item.query
+                        results[q.qid] = Result(q.qid, q.arrival * time_scale, admitted, done, verdict, fp,
+                                                (q.steps + 1) * runs, basis, len(group))
                     cond.notify_all()
 
         threads = [threading.Thread(target=worker, args=(s,), daemon=True) for s in range(self.slots)]
@@ -246,4 +345,5 @@ def summarize(results: List[Result]) -> dict:
     return {"queries": len(results), "p50_ms": 1000.0 * float(np.percentile(lat, 50)),
             "p99_ms": 1000.0 * float(np.percentile(lat, 99)), "max_ms": 1000.0 * float(lat.max()),
             "verified_steps_per_s": steps / span if span > 0 else float("nan"), "span_s": span,
-            "unsafe": int(sum(r.verdict["first_step"] >= 0 for r in results))}
+            "unsafe": int(sum(r.verdict["first_step"] >= 0 for r in results)),
+            "mean_group": float(np.mean([r.group for r in results]))}

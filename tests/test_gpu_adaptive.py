@@ -1,7 +1,7 @@
 """Error-controlled Krylov dimension on the GPU (paper Section 4.2, Lemma 1;
 the checkpoints of Algorithms 2 and 4) against the oracle's adaptive
-Lanczos: every run stops at the same dimension with the same bound, and the
-basis agrees to the FP64 parity bound.
+Lanczos and Arnoldi: every run stops at the same dimension with the same
+bound, and the basis agrees to the FP64 parity bound.
 
 A stop decision compares a computed bound with the target, so a case is
 only meaningful when no checkpoint's bound lies within rounding of it; each
@@ -48,9 +48,23 @@ def _bound_tol(run, tau, lam):
     return 1e-9 * run["bound"] + run["h"] * math.exp(2 * lp * tau) * 4 * k * EPS * wint
 
 
+def _hess_tol(run, tau, lam):
+    """Arnoldi: the GPU forms (e^{tH})_{k,1} from a Taylor polynomial and up
+    to 40 doublings of e^{tH} - I, the oracle from one Pade exponential per
+    node.  Both are accurate to a few eps relative to |e^{tH}|, which the
+    runs here keep near e^{max(lambda,0) t}; the doublings add at most one
+    rounding each."""
+    k = run["k_stop"]
+    lp = max(lam, 0.0)
+    wint = tau * tau / 2 if run["affine"] else tau
+    return 1e-8 * run["bound"] + run["h"] * math.exp(2 * lp * tau) * 4 * (k + 40) * EPS * wint
+
+
 def _run(p, eps, **kw):
     print(f"[gpu] adaptive {p.name} n={p.n} k={kw.get('k', p.k)} eps={eps:g} kw={kw}", flush=True)
-    ref = AD.adaptive_verify(p, eps=eps, kmax=kw.get("k", p.k))
+    arnoldi = kw.get("method") == kry.KRY_ARNOLDI
+    ref = AD.adaptive_verify(p, eps=eps, kmax=kw.get("k", p.k), method="arnoldi" if arnoldi else "auto")
+    tol = _hess_tol if arnoldi else _bound_tol
     tau = p.steps * p.dt
     for r in ref["runs"]:
         for b in _checkpoint_bounds(r, tau, ref["lam"]):
@@ -70,7 +84,9 @@ def _run(p, eps, **kw):
         elif r["bound"] == 0.0:
             assert bound == 0.0
         else:
-            assert abs(bound - r["bound"]) <= _bound_tol(r, tau, ref["lam"]), (bound, r["bound"])
+            print(f"  bound {bound:.15e} oracle {r['bound']:.15e} diff {abs(bound - r['bound']):.2e} "
+                  f"tol {tol(r, tau, ref['lam']):.2e}", flush=True)
+            assert abs(bound - r["bound"]) <= tol(r, tau, ref["lam"]), (bound, r["bound"])
     worst = assert_basis_parity(basis, ref["basis"])
     print(f"  k_stop {[e[0] for e in errs]} bounds {['%.3e' % e[1] for e in errs]} worst {worst:.2e}",
           flush=True)
@@ -145,11 +161,61 @@ def test_zero_target_is_off():
     assert np.array_equal(base, again)
 
 
-def test_rejected_for_arnoldi_plans():
+def test_arnoldi_rejects_k_past_lds():
     require_gpu()
-    p = W.small_heat3d(m=8, k=10, steps=10)
+    p = W.small_heat3d(m=8, k=60, steps=10)
     plan = kry.Plan(kry.DeviceSystem(p), method=kry.KRY_ARNOLDI)
     with pytest.raises(kry.KryError) as ei:
         plan.set_error_target(1e-6)
     assert ei.value.status == kry.KRY_ENOTSUP
     plan.close()
+    # block Arnoldi has no error control
+    q = W.conv_diff3d(6, 6, 6, ngen=2, gen_len=20, o=2, k=8, steps=10, dt=1e-3)
+    plan = kry.Plan(kry.DeviceSystem(q), method=kry.KRY_BLOCK_ARNOLDI, block_p=2)
+    with pytest.raises(kry.KryError) as ei:
+        plan.set_error_target(1e-6)
+    assert ei.value.status == kry.KRY_ENOTSUP
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2: Arnoldi runs (upper Hessenberg H)
+# ---------------------------------------------------------------------------
+
+def _conv_diff(shift=0.0, forcing=False, center=False):
+    p = W.conv_diff3d(10, 10, 10, ngen=2, gen_len=50, o=3, k=40, steps=100, dt=1e-3, seed=5)
+    if shift:
+        diag = p.colidx == np.repeat(np.arange(p.n), np.diff(p.rowptr))
+        p.vals = p.vals + shift * diag
+    rng = np.random.default_rng(77)
+    if forcing:
+        p.b = rng.uniform(0.0, 1.0, p.n)
+    if center:
+        p.center = rng.uniform(-0.5, 0.5, p.n)
+    return p
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-9])
+def test_arnoldi_nonsymmetric(eps):
+    require_gpu()
+    errs, _ = _run(_conv_diff(), eps, method=kry.KRY_ARNOLDI)
+    assert all(4 <= e[0] < 40 for e in errs)
+
+
+def test_arnoldi_forcing_center_and_positive_lambda():
+    # a diagonal shift past the Gershgorin radius makes lambda > 0; the
+    # augmented run integrates its bound; a dense center adds a run
+    require_gpu()
+    p = _conv_diff(shift=0.5 * 1.0 / (1.0 / 11) / 5.0, forcing=True, center=True)
+    errs, ref = _run(p, 1e-7, method=kry.KRY_ARNOLDI)
+    assert ref["lam"] > 0.0 and len(errs) == 4
+
+
+def test_arnoldi_on_a_symmetric_system_stops_with_lanczos():
+    require_gpu()
+    p = W.small_heat3d(m=10, k=50, steps=100)
+    ea, _ = _run(p, 1e-8, method=kry.KRY_ARNOLDI)
+    el, _ = _run(p, 1e-8)
+    assert [e[0] for e in ea] == [e[0] for e in el]
+    for (_, a), (_, b) in zip(ea, el):
+        assert abs(a - b) <= 1e-6 * b

@@ -1,10 +1,10 @@
 """The one-pass Lanczos step (FP64 three-vector Lanczos, one launch per
 iteration over the pair buffers (u_{j-1}, r_j)) against the FP64 oracle and
-against the two-launch step it replaces (KRY_ONEPASS=0), on the sliced-ELL
-CSR mat-vec, the row stencil and the marching stencil (forced on small
-grids with KRY_STENCIL_MARCH=1), with batches of 1 to 8 runs; and the hand-
-back to the two-launch step when a run's norm expansion cancels (an
-invariant Krylov space)."""
+against the two-launch step it replaces (KRY_ONEPASS=0): on the sliced-ELL
+CSR mat-vec (used there on request, KRY_ONEPASS=1), the row stencil and the
+marching stencil (forced on small grids with KRY_STENCIL_MARCH=1), with
+batches of 1 to 8 runs; and the hand-back to the two-launch step when a
+run's norm expansion cancels (an invariant Krylov space)."""
 import math
 import os
 from contextlib import contextmanager
@@ -47,9 +47,11 @@ def _profiled(problem, **kw):
 
 
 def _check(problem, step_kernel, **kw):
+    # KRY_ONEPASS=1: the step on CSR systems too (by default stencils only)
     require_gpu()
     ref = oracle.verify(problem)
-    got, counts = _profiled(problem, **kw)
+    with env(KRY_ONEPASS=1):
+        got, counts = _profiled(problem, **kw)
     assert counts[step_kernel] > 0, counts
     assert counts["sweep"] == 0, "a batch was handed back to the two-launch step"
     for g, r in zip(got["runs"], ref["runs"]):
@@ -132,7 +134,8 @@ def test_onepass_hands_back_on_an_invariant_space():
     p.center = np.sin(3 * math.pi * np.arange(1, n + 1) * h)
     p.C = [W.segments_from_ranges([(90, 111)], 1.0 / 21.0)]
     ref = oracle.verify(p)
-    got, counts = _profiled(p)
+    with env(KRY_ONEPASS=1):
+        got, counts = _profiled(p)
     assert counts["lz1_sell"] > 0 and counts["sweep"] > 0
     assert [r["k_eff"] for r in got["runs"]] == [r.k_eff for r in ref["runs"]]
     assert got["runs"][1]["k_eff"] == 1
@@ -145,7 +148,8 @@ def test_onepass_plain_lanczos_large_k():
     p = W.heat3d_paper(m=14)
     p.k = 150
     p.steps = 200
-    got, counts = _profiled(p, method=kry.KRY_LANCZOS_PLAIN)
+    with env(KRY_ONEPASS=1):
+        got, counts = _profiled(p, method=kry.KRY_LANCZOS_PLAIN)
     assert counts["lz1_sell"] == 150 and counts["sweep"] == 0
     with env(KRY_ONEPASS=0):
         two = gpu_verify(p, method=kry.KRY_LANCZOS_PLAIN)
