@@ -18,12 +18,13 @@ Prints one JSON line.  Options:
   --workload W    heat3d_stencil (1000^3 matrix-free, the benchmark line),
                   heat3d_csr (100^3 CSR; its working set fits the 256 MB MALL),
                   heat1d, conv_diff3d, heat3d_paper, heat3d_many_inputs (eight
-                  initial-space columns, one output)
+                  initial-space columns, one output), heat3d_many_gens (--ngen
+                  box generators, default 256, plus center and forcing; one output)
   --no-fp32-side  heat3d_stencil: skip the FP32-basis side measurement (ratio to
                   FP64 and per-output error against the FP64 basis)
   --route R       forward (one run per column of E) or transposed (one run of A^T
                   per output row, Section 4.1); default transposed for
-                  heat3d_many_inputs, forward otherwise
+                  heat3d_many_inputs and heat3d_many_gens, forward otherwise
   --graph         one plan whose projection is recorded as a HIP graph and replayed
                   each step (plan creation outside the timed region; a separate
                   measurement, not the default line)
@@ -36,7 +37,8 @@ Prints one JSON line.  Options:
   --method M      auto (Lanczos / Arnoldi by symmetry) or block (block Arnoldi,
                   the default for conv_diff3d: 16 generators as one p = 16 block)
   --workload serve   the serving stream instead: --rates R1,R2,.. (queries/s),
-                  --seconds T of arrivals per rate (at most 2000 queries), --slots S;
+                  --seconds T of arrivals per rate (at most 2000 queries), --slots S,
+                  --serve-batch on|off|both (same-step queries of one system in one plan);
                   reports p50/p99 arrival-to-verdict latency per rate
   --calib-copy    run a plain device copy of known size (for counter calibration) and exit
 """
@@ -86,8 +88,9 @@ def main():
     ap.add_argument("--k", type=int, default=None, help="Krylov dimension (matrix-free paper heat only)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="skip the second timed pass with per-kernel events (long runs)")
+    ap.add_argument("--ngen", type=int, default=0, help="heat3d_many_gens: generators (default 256)")
     ap.add_argument("--workload", default="heat3d_stencil",
-                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper",
+                    choices=["heat3d_csr", "heat3d_stencil", "heat1d", "conv_diff3d", "heat3d_paper", "heat3d_many_gens",
                              "heat3d_many_inputs", "serve"],
                     help="heat3d_stencil is the benchmark line; the others are measured the same way")
     ap.add_argument("--no-fp32-side", action="store_true")
@@ -99,6 +102,7 @@ def main():
     ap.add_argument("--rates", default="5,10,20,50,100,200")
     ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--serve-batch", choices=["on", "off", "both"], default="on")
     ap.add_argument("--error-target", type=float, default=0.0,
                     help="Lanczos workloads: choose each run's Krylov dimension by the Lemma 1 bound (k is the cap)")
     ap.add_argument("--no-prepared", action="store_true",
@@ -143,9 +147,12 @@ def main():
             p = W.heat3d_paper_stencil(m=m, k=args.k or 5932)
     elif args.workload == "heat3d_many_inputs":
         p = W.heat3d_many_inputs(m=args.m or 100)
+    elif args.workload == "heat3d_many_gens":
+        p = W.heat3d_many_gens(m=args.m or 100, ngen=args.ngen or 256)
     else:
         p = W.conv_diff3d(*(((args.m,) * 3) if args.m else (200, 200, 250)), ngen=16, o=5, k=30)
-    transposed = (args.route or ("transposed" if args.workload == "heat3d_many_inputs" else "forward")) == "transposed"
+    transposed = (args.route or ("transposed" if args.workload in ("heat3d_many_inputs", "heat3d_many_gens")
+                                 else "forward")) == "transposed"
     method_name = args.method or {"conv_diff3d": "block", "heat3d_paper": "plain"}.get(args.workload, "auto")
     method = {"block": kry.KRY_BLOCK_ARNOLDI, "plain": kry.KRY_LANCZOS_PLAIN}.get(method_name, kry.KRY_AUTO)
     dsys = kry.DeviceSystem(p, device="cuda")
@@ -229,8 +236,10 @@ def main():
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
     }
-    if args.graph:
-        out["roofline"] = None      # per-kernel events and graph replay exclude each other
+    if args.graph or not dom.get("bytes"):
+        # per-kernel events and graph replay exclude each other; without
+        # events (--no-kernel-events) there is no launch duration either
+        out["roofline"] = None
     print(json.dumps(out))
 
 
@@ -247,16 +256,21 @@ def serve_bench(args):
     warm = W.serving_queries(16, rate=1000.0, seed=99)
     Server(cat, slots=args.slots).serve(warm, time_scale=0.0)
     per_rate = []
+    modes = {"on": [True], "off": [False], "both": [True, False]}[args.serve_batch]
+    unbatched = []
     for rate in rates:
         count = int(min(2000, max(20, round(rate * args.seconds))))
         qs = W.serving_queries(count, rate=rate, seed=100)
-        log(f"rate {rate}/s: {count} queries")
-        res = Server(cat, slots=args.slots).serve(qs)
-        s = summarize(res)
-        s["rate"] = rate
-        s["fp32_share"] = sum(q.precision == "fp32" for q in qs) / count
-        per_rate.append(s)
-        log(f"  p50 {s['p50_ms']:.1f} ms  p99 {s['p99_ms']:.1f} ms  {s['verified_steps_per_s']:.0f} steps/s")
+        for batch in modes:
+            log(f"rate {rate}/s: {count} queries, batching {'on' if batch else 'off'}")
+            res = Server(cat, slots=args.slots, batch=batch).serve(qs)
+            s = summarize(res)
+            s["rate"] = rate
+            s["batch"] = batch
+            s["fp32_share"] = sum(q.precision == "fp32" for q in qs) / count
+            (per_rate if batch == modes[0] else unbatched).append(s)
+            log(f"  p50 {s['p50_ms']:.1f} ms  p99 {s['p99_ms']:.1f} ms  {s['verified_steps_per_s']:.0f} steps/s"
+                f"  mean group {s['mean_group']:.2f}")
     top = per_rate[-1]
     out = {
         "metric": "Krylov step HBM GB/s (% peak); verified time-steps/s vs plain FP64; p99 query latency",
@@ -267,7 +281,8 @@ def serve_bench(args):
         "config": {"workload": "serving stream: heat / conv-diff queries, n in 1e3..1e7 (13 resident grids), "
                                "1-8 generators, 1-4 outputs, 100-2000 steps, FP64 or FP32 basis, Poisson "
                                f"arrivals, {args.slots} slots", "rates": rates, "seconds_per_rate": args.seconds},
-        "latency": per_rate, "resident_system_bytes": cat.resident_bytes(),
+        "latency": per_rate, "latency_unbatched": unbatched or None,
+        "resident_system_bytes": cat.resident_bytes(),
     }
     print(json.dumps(out))
 
@@ -390,11 +405,13 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         # iterations j = 1..k (j stored vectors read per pass)
         "arn_dots": vec * (1 + (k + 1) / 2.0),
         "arn_update": vec * (2 + (k + 1) / 2.0),
-        # one-pass step: read the pair (u_{j-1}, r_j), write (u_j, r_{j+1})
-        "lz1_sell": mat_sell + 4 * vec,
-        "lz1_stencil": 4 * vec,
-        "lz1_march": 4 * vec,
-        "lz1_tail": 2 * vec,                                  # read the last pair
+        # one-pass step: read the pair (u_{j-1}, r_j), write (u_j, r_{j+1});
+        # the first of the k launches reads the plain start vectors (one
+        # vector), so the average over a batch's launches is (4k - 1)/k
+        "lz1_sell": mat_sell + (4 * k - 1) / k * vec,
+        "lz1_stencil": (4 * k - 1) / k * vec,
+        "lz1_march": (4 * k - 1) / k * vec,
+        "lz1_close": 0,                                       # one workgroup: scalars only
     }
     for name, b in per_launch.items():
         if name in kern:
@@ -422,7 +439,7 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
                 kern[name]["bytes"] = b * nblk / max(kern[name]["launches"] / steps, 1)
                 kern[name]["GBps"] = kern[name]["bytes"] / (kern[name]["avg_us"] * 1e-6) / 1e9
         dom_name = max((n_ for n_ in ("bgram", "bupdate", "bspmm") if n_ in kern),
-                       key=lambda n_: kern[n_]["total_ms_per_step"])
+                       key=lambda n_: kern[n_]["total_ms_per_step"], default="bgram")
         return {"value": (p.steps + 1) * nruns / (elapsed / steps), "ms_per_step": 1000.0 * elapsed / steps,
                 "ms_per_step_ev": 1000.0 * elapsed_ev / steps, "kern": kern, "nruns": nruns, "verdict": verdict,
                 "dom_name": dom_name, "error_control": used or None, "krylov_runs": krylov_runs["n"]}
@@ -465,9 +482,9 @@ def describe(p, nruns, precision, method_name="auto"):
         return (f"3D heat {m}^3 as in the paper (insulated faces, exchange 0.5 at x=1, CSR n={p.n}, nnz={p.nnz}), "
                 f"centre-point output, three-vector Lanczos with the Lemma 1 error control (k <= {p.k}), "
                 f"dt={p.dt}, {p.steps} steps, {prec}")
-    if p.name == "heat3d_many_inputs":
+    if p.name in ("heat3d_many_inputs", "heat3d_many_gens"):
         m = p.meta["m"]
-        return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + forcing, 6 generators + center + forcing = "
+        return (f"3D heat {m}^3 CSR (n={p.n}, nnz={p.nnz}) + forcing, {len(p.gens)} generators + center + forcing = "
                 f"{nruns} basis columns, o={p.o} output, Lanczos k={p.k}, dt={p.dt}, {p.steps} steps, {prec}")
     return f"{p.name} n={p.n} nnz={p.nnz} k={p.k} dt={p.dt} steps={p.steps} o={p.o} runs={nruns} {prec}"
 

@@ -213,7 +213,12 @@ kry_status kry_plan(const kry_system* sys, const kry_gen* gens, int32_t ngen, co
  *     KRY_ENOTSUP.
  *  gens, ngen, center: the initial space (center: host segment set or
  *     NULL, a fixed coefficient-1 column).  Generators + center + forcing
- *     make ncols <= 8 basis columns.
+ *     make ncols <= 4096 basis columns.  Up to 8 are projected inside the
+ *     Krylov sweep and exponentiated per run in LDS; past 8 each Krylov
+ *     vector is projected on the rows of E^T by segment sums (one
+ *     wavefront per index range), and the small stage forms
+ *     e^{M s dt} x0 once per step and run (M = H, bordered by b's
+ *     projection row with forcing) and multiplies it by the projections.
  *  C, o: 1 <= o <= 8 output rows, the runs' start vectors.
  *  k: 1..56 Krylov steps per run, 1..55 with forcing.  With forcing each
  *     run is the Galerkin projection of the transposed augmented matrix
@@ -240,7 +245,8 @@ kry_status kry_plan_create_transposed(const kry_system* sys_t, const kry_gen* ge
 /* kry_footprint_transposed -- device workspace bytes of a transposed plan:
  * ngen generators, has_center (0/1) a center row, o output rows (the runs),
  * the forcing when sys_t->b_segs is given; nseg_total = segments of the
- * generators, the center, the output rows and b_segs together.  Host only. */
+ * generators, the center, the output rows and b_segs together (an upper
+ * bound serves: the wide route sizes its segment sums by it).  Host only. */
 kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32_t has_center, int32_t o,
                                     int32_t k, int64_t steps, int64_t nseg_total, int32_t precision,
                                     int32_t method, size_t* bytes);

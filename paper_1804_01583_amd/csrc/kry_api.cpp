@@ -115,6 +115,8 @@ struct Profiler {
                 auto& t = totals[p.name];
                 t.first += 1;
                 t.second += ms;
+            } else {
+                (void)hipGetLastError();   // a timing failure must not surface in a later call
             }
             pool.push_back(p.a);
             pool.push_back(p.b);
@@ -130,7 +132,7 @@ Profiler& prof() {
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
     "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp,"
-    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_tail";
+    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_stage";
 
 // Runs `launch` bracketed by events when profiling is on.  The sliced-ELL
 // mat-vec and the one-pass step's kernels take the events into their own
@@ -149,9 +151,18 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch) {
     if (!a || !b) return launch();
     hipError_t e;
     if (std::strcmp(name, "spmv_sell") == 0 || std::strncmp(name, "lz1_", 4) == 0) {
+        // the launcher stamps the kernel's own start and end into (a, b) and
+        // clears the pending start; a launch that did not leaves them unused
         *ext_events() = ExtEvents{a, b};
         e = launch();
+        const bool used = ext_events()->start == nullptr;
         *ext_events() = ExtEvents{nullptr, nullptr};
+        if (!used) {
+            std::lock_guard<std::mutex> g(P.mu);
+            P.pool.push_back(a);
+            P.pool.push_back(b);
+            return e;
+        }
     } else {
         (void)hipEventRecord(a, s);
         e = launch();
@@ -256,12 +267,16 @@ struct Layout {
     size_t hpart, hcoef, vals32;
     size_t oflag = 0;     // one-pass step: per-run cancellation flags of a batch
     size_t ap_stride = 0; // doubles between the two ping-pong partial arrays of the one-pass step
+    // transposed route with many initial-space rows: E^T u per step, segment
+    // sums, Phi powers and anchors of the wide small stage
+    size_t wpw = 0, wseg = 0, wpow = 0, wanch = 0;
 };
 
 // lz1_march: tiles of the one-pass marching stencil kernel (0 when it is not used)
 Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps, int32_t block_p,
                    size_t meta_bytes, int32_t method, int32_t march, int32_t precision, int64_t nnz32,
-                   int64_t sell_nnz, int32_t lz1_march, int32_t njobs = -1, int32_t ncols = -1, int32_t o_out = -1) {
+                   int64_t sell_nnz, int32_t lz1_march, int32_t njobs = -1, int32_t ncols = -1, int32_t o_out = -1,
+                   int32_t wide_rows = 0, int64_t wide_segs = 0) {
     // the forward route has one job and one basis column per run
     if (njobs < 0) njobs = nruns;
     if (ncols < 0) ncols = nruns;
@@ -338,6 +353,12 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
         Y.dP = take((size_t)o * k * sizeof(double));
         Y.dS0 = take((size_t)k * sizeof(double));
         Y.dws = take(dense_workspace_doubles(k, o, 1, Y.B, Y.nanch) * sizeof(double));
+    }
+    if (wide_rows > 0) {
+        Y.wpw = take((size_t)nruns * wide_rows * k * sizeof(double));
+        Y.wseg = take((size_t)std::max<int64_t>(wide_segs, 1) * kMaxP * sizeof(double));
+        Y.wpow = take((size_t)nruns * Y.B * kMaxK1 * kMaxK1 * sizeof(double));
+        Y.wanch = take((size_t)nruns * Y.nanch * kMaxK1 * sizeof(double));
     }
     Y.msize = take((size_t)std::max(njobs, nruns) * sizeof(int32_t));
     Y.scale = take((size_t)std::max(njobs, nruns) * sizeof(double));
@@ -464,6 +485,7 @@ kry_status prepare_device() {
     std::call_once(once, [] {
         err = expm_prepare();
         if (err == hipSuccess) err = errctl_prepare();
+        if (err == hipSuccess) err = wide_prepare();
     });
     if (err != hipSuccess) return fail(KRY_EDEVICE, std::string("expm LDS setup: ") + hipGetErrorString(err));
     return KRY_OK;
@@ -508,6 +530,11 @@ struct kry_plan {
     // rows and project on the initial-space rows; the basis keeps the
     // forward shape (o_out output rows x ncols columns)
     bool transposed = false;
+    // more initial-space rows than the fused projection holds: the rows of
+    // E^T are sets wset0 .. wset0 + ncols - 1, their segments wseg0 ..
+    // wseg0 + wnseg - 1 (kry_wide.hip)
+    bool wide = false;
+    int32_t wset0 = 0, wseg0 = 0, wnseg = 0;
     int32_t njobs = 0;             // exponentials of the small stage
     int32_t o_out = 0, ncols = 0;  // basis shape
     std::vector<int32_t> col_role; // per basis column: 0 generator, 1 center, 2 forcing
@@ -680,21 +707,24 @@ kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32
             return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
         const bool has_b = sys_t->b_segs != nullptr;
         const int32_t nproj = ngen + (has_center ? 1 : 0) + (has_b ? 1 : 0);
-        if (ngen < 0 || nproj < 1 || nproj > kMaxO || o < 1 || o > kMaxO || k < 1 ||
+        if (ngen < 0 || nproj < 1 || nproj > kMaxWide || o < 1 || o > kMaxO || k < 1 ||
             k > (has_b ? kMaxK - 1 : kMaxK) || steps < 0 || nseg_total < 0)
-            return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows, 1 <= o <= 8, k in [1, 56] "
+            return fail(KRY_EINVAL, "transposed route: 1 to 4096 initial-space rows, 1 <= o <= 8, k in [1, 56] "
                                     "([1, 55] with forcing), steps >= 0, nseg_total >= 0 required");
         if (precision != KRY_FP64 && precision != KRY_FP32_BASIS) return fail(KRY_EINVAL, "unknown precision");
         // the shapes kry_plan_create_transposed lays out: o runs projected on
-        // nproj rows, one job per run plus one per run for the forcing column
-        const int32_t njobs = o * (has_b ? 2 : 1);
-        const int32_t nsets = ngen + o + (has_b ? 1 : 0) + (has_center ? 1 : 0);
+        // nproj rows, one job per run plus one per run for the forcing
+        // column; past 8 rows the wide stage instead (no jobs, one more set)
+        const bool wide = nproj > kMaxO;
+        const int32_t njobs = wide ? 0 : o * (has_b ? 2 : 1);
+        const int32_t nsets = ngen + o + (has_b ? 1 : 0) + (has_center ? 1 : 0) + (wide ? 1 : 0);
         const int32_t nb = nblocks_for(sys_t->n, rows_per_block_for(sys_t->n));
         const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys_t->kind == KRY_CSR) ? sys_t->nnz : 0;
-        const Layout Y = make_layout(sys_t->n, o, nproj, k, steps, 0,
+        const Layout Y = make_layout(sys_t->n, o, wide ? 1 : nproj, k, steps, 0,
                                      meta_size(nseg_total, nsets, std::max(njobs, nproj), nb, njobs), method,
                                      march_blocks_for(*sys_t), precision, nnz32, sell_nnz_for(*sys_t, method),
-                                     lz1_blocks_for(*sys_t), njobs, nproj, o);
+                                     lz1_blocks_for(*sys_t), njobs, nproj, o, wide ? nproj : 0,
+                                     wide ? nseg_total : 0);
         *bytes = Y.total;
         return KRY_OK;
     });
@@ -729,8 +759,8 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
         if (method != KRY_LANCZOS && method != KRY_ARNOLDI)
             return fail(KRY_ENOTSUP, "the transposed route runs Lanczos or Arnoldi");
         if (sys->b) return fail(KRY_ENOTSUP, "the transposed route takes the forcing as b_segs (a projection row)");
-        if (nproj < 1 || nproj > kMaxO)
-            return fail(KRY_EINVAL, "transposed route: 1 to 8 initial-space rows (generators, center, forcing)");
+        if (nproj < 1 || nproj > kMaxWide)
+            return fail(KRY_EINVAL, "transposed route: 1 to 4096 initial-space rows (generators, center, forcing)");
         if (k < 1 || k > (has_b ? kMaxK - 1 : kMaxK))
             return fail(KRY_EINVAL, "transposed route: k must be in [1, 56] ([1, 55] with forcing)");
         if (center_t) {
@@ -810,7 +840,14 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     if (plan->ncols == 0) {
         return fail(KRY_EINVAL, "nothing to simulate: no generator, center or forcing");
     }
-    if (transposed) {
+    if (transposed && nproj > kMaxO) {
+        // wide: the fused projection gets one empty row; the rows of E^T are
+        // projected and exponentiated by the wide kernels
+        plan->wide = true;
+        plan->o = 1;
+        plan->role.assign(o, 0);
+        plan->nruns = o;
+    } else if (transposed) {
         // one run per output row; projection row r is basis column r.  Job
         // q exponentiates run q's T for the generator and center columns;
         // with forcing, job o + q exponentiates the bordered matrix for the
@@ -847,7 +884,13 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     if (sys->b_segs) total_segs += sys->b_segs->nseg;
     if (center_t) total_segs += center_t->nseg;
     if (total_segs >= ((int64_t)1 << 31)) return fail(KRY_EINVAL, "too many segments");
-    const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0) + (center_t ? 1 : 0);
+    const int32_t nsets = ngen + o + (sys->b_segs ? 1 : 0) + (center_t ? 1 : 0) + (plan->wide ? 1 : 0);
+    int64_t wide_segs = 0;
+    if (plan->wide) {
+        for (int32_t g = 0; g < ngen; ++g) wide_segs += gens[g].seg.nseg;
+        if (center_t) wide_segs += center_t->nseg;
+        if (sys->b_segs) wide_segs += sys->b_segs->nseg;
+    }
     const int64_t rpb = rows_per_block_for(n);
     const int32_t nblk = nblocks_for(n, rpb);
     const int32_t ntab = std::max(plan->njobs, plan->ncols);
@@ -856,7 +899,7 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     const int64_t nnz32 = (precision == KRY_FP32_BASIS && sys->kind == KRY_CSR) ? sys->nnz : 0;
     plan->Y = make_layout(n, plan->nruns, plan->o, k, steps, block_p, mbytes, method, march_blocks_for(*sys),
                           precision, nnz32, sell_nnz_for(*sys, method), lz1_blocks_for(*sys), plan->njobs, plan->ncols,
-                          plan->o_out);
+                          plan->o_out, plan->wide ? plan->ncols : 0, wide_segs);
     plan->method = method == KRY_LANCZOS_PLAIN ? KRY_LANCZOS : method;   // the layout tells plain from reorthogonalised
     plan->f32 = precision == KRY_FP32_BASIS;
     plan->hess_mode = plan->Y.stored;
@@ -903,9 +946,16 @@ kry_status plan_create(const kry_system* sys, const kry_gen* gens, int32_t ngen,
     if (transposed) {
         for (int32_t q = 0; q < o; ++q) { plan->gen_set.push_back(set); add_set(C[q]); }
         plan->oset0 = set;
+        plan->wset0 = set;
+        plan->wseg0 = (int32_t)at;
         for (int32_t g = 0; g < ngen; ++g) add_set(gens[g].seg);
         if (center_t) add_set(*center_t);
         if (sys->b_segs) add_set(*sys->b_segs);
+        if (plan->wide) {
+            plan->wnseg = (int32_t)(at - plan->wseg0);
+            plan->oset0 = set;
+            sb[set++] = (int32_t)at;             // the fused projection's empty row
+        }
     } else {
         for (int32_t g = 0; g < ngen; ++g) { plan->gen_set.push_back(set); add_set(gens[g].seg); }
         plan->oset0 = set;
@@ -1233,7 +1283,7 @@ kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const Star
     hipError_t e = launch_fill(flag, kMaxP, 1.0, s);
     if (e == hipSuccess)
         e = timed("start", s, [&] {
-            return launch_start(P, plan->o, false, src, plan->T, plan->oset0, X[0], B, s, true);
+            return launch_start(P, plan->o, false, src, plan->T, plan->oset0, X[0], B, s);
         });
     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
     StencilArgs S{};
@@ -1268,10 +1318,8 @@ kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const Star
     }
     Z.ap_in = ap[k & 1];
     Z.ap_out = nullptr;
-    e = timed("lz1_tail", s, [&] {
-        return launch_lz1_tail(P, plan->o, X[k & 1], plan->T, plan->oset0, B, Z, k + 1, s);
-    });
-    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("one-pass tail: ") + hipGetErrorString(e));
+    e = timed("lz1_close", s, [&] { return launch_lz1_close(P, B, Z, k + 1, s); });
+    if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("one-pass close: ") + hipGetErrorString(e));
     *flagged = false;
     if (capture) return KRY_OK;
     double fl[kMaxP];
@@ -1327,7 +1375,7 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         // 100^3 system (whose working set sits in the MALL), so it is used
         // there only on request (KRY_ONEPASS=1; 0 turns it off everywhere).
         const int op_mode = env_int("KRY_ONEPASS", -1);
-        const bool onepass = Y.lz1 && lanczos && plan->err_eps <= 0.0 && op_mode != 0 &&
+        const bool onepass = Y.lz1 && lanczos && plan->err_eps <= 0.0 && op_mode != 0 && !plan->wide &&
                              (plan->sys.kind == KRY_STENCIL7 || (plan->use_sell && op_mode == 1));
         const BatchArgs B_fin = B;           // the finishing kernel never reads stop flags here
         if (onepass) {
@@ -1348,6 +1396,18 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
             return launch_start(P, plan->o, f32, src, plan->T, plan->oset0, plan->vec(0), B, s);
         });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("start: ") + hipGetErrorString(e));
+        // wide transposed plan: E^T u_{j+1} once u_{j+1} is formed (j = 0: the start)
+        auto wide_proj = [&](const void* x, int j) {
+            return timed("wide_proj", s, [&] {
+                return launch_wide_proj(P, f32, x, plan->T, plan->wset0, plan->ncols, plan->wseg0, plan->wnseg,
+                                        plan->at<double>(Y.wseg), plan->at<double>(Y.wpw), r0, P, plan->ncols,
+                                        plan->k, j, s);
+            });
+        };
+        if (plan->wide) {
+            e = wide_proj(plan->vec(0), 0);
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("wide projection: ") + hipGetErrorString(e));
+        }
         int next_check = 4;
         bool poll_pending = false;
         ErrArgs X{};
@@ -1412,6 +1472,10 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
                     if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
                 }
             }
+            if (plan->wide && j < plan->k) {
+                e = wide_proj(w, j);
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("wide projection: ") + hipGetErrorString(e));
+            }
             // Algorithms 2 and 4: check the error bound at k = 4, then ceil(1.1 k)
             // with 1.1 k a double product, as printed (170 is followed by 188).
             // Once every run of the batch met the target, the kernels of the
@@ -1444,6 +1508,28 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         e = timed("finish", s, [&] { return launch_finish(P, plan->o, onepass ? B_fin : B, plan->k, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
         r0 += P;
+    }
+    if (plan->wide) {
+        WideArgs W{};
+        W.scal = plan->scal();
+        W.L = Y.L;
+        W.Pw = plan->at<double>(Y.wpw);
+        W.ncw = plan->ncols;
+        W.ldk = plan->k;
+        W.forcing = plan->col_role.back() == 2 ? 1 : 0;
+        W.bcol = plan->ncols - 1;
+        W.hess = plan->hess_mode ? 1 : 0;
+        W.dt = plan->dt;
+        W.B = Y.B;
+        W.nanch = Y.nanch;
+        W.pow = plan->at<double>(Y.wpow);
+        W.anch = plan->at<double>(Y.wanch);
+        W.basis = plan->basis();
+        W.o_out = plan->o_out;
+        W.ncols = plan->ncols;
+        hipError_t e = timed("wide_stage", s, [&] { return launch_wide_stage(W, plan->nruns, plan->steps, s); });
+        if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("wide stage: ") + hipGetErrorString(e));
+        return finish ? finish_projection(plan, basis_out) : KRY_OK;
     }
     ExpmArgs E{};
     E.scal = plan->scal();
@@ -1845,7 +1931,15 @@ kry_status kry_plan_krylov(kry_plan_t* plan, int32_t run, int32_t* k_eff, double
             }
         }
         if (h_next) *h_next = tri > 0 ? sc[L.beta + tri] : (bordered ? sc[L.beta + 0] : 0.0);
-        if (P) {
+        if (P && plan->wide) {
+            // one row per initial-space row: sigma_{c+1} E^T u_{c+1}
+            std::vector<double> pw((size_t)plan->ncols * k);
+            KRY_HIP(hipMemcpyAsync(pw.data(), plan->at<double>(plan->Y.wpw) + (size_t)run * plan->ncols * k,
+                                   pw.size() * sizeof(double), hipMemcpyDeviceToHost, plan->stream));
+            KRY_HIP(hipStreamSynchronize(plan->stream));
+            for (int q = 0; q < plan->ncols; ++q)
+                for (int c = 0; c < tri; ++c) P[(size_t)q * dim + c] = sc[L.sigma + c + 1] * pw[(size_t)q * k + c];
+        } else if (P) {
             for (int q = 0; q < plan->o; ++q) {
                 double* row = P + (size_t)q * dim;
                 int c0 = 0;

@@ -146,6 +146,34 @@ struct AssembleArgs {
     int32_t o_out, ncols;
 };
 
+// Transposed route with more initial-space rows than the fused projection
+// holds (kry_wide.hip).
+constexpr int kMaxK1 = kMaxK + 1;   // row stride of the wide stage's stored matrices
+constexpr int kMaxWide = 4096;      // initial-space rows of a wide transposed plan
+struct WideArgs {
+    const double* scal;
+    ScalLayout L;
+    const double* Pw;        // [nruns][ncw][ldk]: E_c^T u_{j+1} (unscaled)
+    int32_t ncw, ldk;        // rows of E^T (= basis columns) and the stride of Pw
+    int32_t bcol;            // the forcing's column (forcing != 0)
+    int32_t forcing;         // the last row is b: bordered matrix of size m + 1
+    int32_t hess;            // H from the Hessenberg store (Arnoldi) or alpha/beta
+    double dt;
+    int32_t B, nanch;        // anchor spacing and count, as for the small stage
+    double* pow;             // [nruns][B][kMaxK1][kMaxK1]: Phi^r
+    double* anch;            // [nruns][nanch][kMaxK1]:     Phi^{B b} x0
+    double* basis;           // [(steps+1)][o_out][ncols]
+    int32_t o_out, ncols;
+};
+hipError_t wide_prepare();
+// Pw[run0 + p][c][j] for the P runs of a batch from their vectors x ([n][P]):
+// segments g0 .. g0 + ng - 1 (those of sets set0 .. set0 + nsets - 1) summed
+// into segsum ([ng][P]), then per set in order
+hipError_t launch_wide_proj(int P, bool f32, const void* x, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0,
+                            int32_t ng, double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw,
+                            int32_t ldk, int32_t j, hipStream_t s);
+hipError_t launch_wide_stage(const WideArgs& W, int32_t nruns, int64_t steps, hipStream_t s);
+
 constexpr int kMaxCheckCols = 64;   // columns of a check over part of the basis
 struct CheckArgs {
     const double* basis;
@@ -279,9 +307,8 @@ hipError_t launch_row_abs_max(const CsrArgs& A, int64_t n, double* partials, int
 hipError_t launch_finish(int P, int O, const BatchArgs& B, int kdone, hipStream_t s);
 hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 // f32 selects E = float storage of the Krylov vectors (and vals32 for CSR).
-// pair: FP64 start in the one-pass step's pair layout [n][2P] (u_0 = 0, r_1 = u_1).
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        void* u, const BatchArgs& B, hipStream_t s, bool pair = false);
+                        void* u, const BatchArgs& B, hipStream_t s);
 hipError_t launch_spmv_sell(int P, bool f32, const SellArgs& A, const void* ucur, const void* uprev, void* w,
                             const BatchArgs& B, int j, hipStream_t s);
 // Kernel timing: when the pair is set, the next sliced-ELL mat-vec launch
@@ -299,7 +326,8 @@ hipError_t launch_spmv_stencil(int P, bool march, bool f32, const StencilArgs& A
 hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,
                         void* w, const BatchArgs& B, int j, hipStream_t s);
 // ---- one-pass Lanczos step (kry_lz1.hip) -----------------------------------
-// Iteration j reads the pair buffer xin = (u_{j-1}, r_j) ([n][2P]) and writes
+// Iteration j reads the pair buffer xin = (u_{j-1}, r_j) ([n][2P]; at j = 1
+// the start kernel's plain [n][P] vectors, u_0 = 0) and writes
 // xout = (u_j, r_{j+1}).  Partials ping-pong between two arrays: ap_in holds
 // the previous launch's sigma_{j-1} u_{j-1} . r_j, |r_j|^2 and |u_{j-1}|^2
 // per run ([3P][nb_in]); this launch writes its own to ap_out.
@@ -321,9 +349,9 @@ hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, doub
                             const Lz1Args& Z, int j, hipStream_t s);
 hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B,
                            int j, hipStream_t s);
-// after iteration k (j = k + 1): u_{k+1} for stage k, alpha_k
-hipError_t launch_lz1_tail(int P, int O, const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B,
-                           const Lz1Args& Z, int j, hipStream_t s);
+// after iteration k (j = k + 1): alpha_k and stage k (beta_k) from the last
+// launch's partials, one workgroup
+hipError_t launch_lz1_close(int P, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s);
 
 hipError_t expm_prepare();
 hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);

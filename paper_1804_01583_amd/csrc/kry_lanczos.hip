@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(const double* __restrict__ in
 
 // a2: start vectors u_1 of the runs and the partials of |u_1|^2 and C u_1
 // (Algorithm 4, first two statements; the scaling happens in the next kernel).
-template <typename E, int P, int O, bool PAIR>
+template <typename E, int P, int O>
 __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int32_t oset0,
                                                   E* __restrict__ u, BatchArgs B) {
     if (batch_stopped<P>(B)) return;   // a fallback the one-pass step did not need
@@ -129,18 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
                 val[p] = (double)(E)val[p];          // the norm and projection of the stored vector
                 acc[p] = fma(val[p], val[p], acc[p]);
             }
-            if constexpr (PAIR) {
-                // the one-pass step's pair layout: (u_0 = 0, r_1 = u_1) per row
-                double t[2 * P];
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    t[p] = 0.0;
-                    t[P + p] = val[p];
-                }
-                store_row<double, 2 * P>(reinterpret_cast<double*>(u), r, t);
-            } else {
-                store_row<E, P>(u, r, val);
-            }
+            store_row<E, P>(u, r, val);
 #pragma unroll
             for (int q = 0; q < O; ++q) {
                 const double cw = cur[P + q].weight(st, P + q, T, r);
@@ -630,13 +619,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(BatchArgs B, int o, int kdone
 
 template <typename E, int P, int O>
 hipError_t launch_start_t(const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
-                          const BatchArgs& B, bool pair, hipStream_t s) {
-    if (pair)
-        hipLaunchKernelGGL((k_start<double, P, O, true>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
-                           static_cast<double*>(u), B);
-    else
-        hipLaunchKernelGGL((k_start<E, P, O, false>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0,
-                           static_cast<E*>(u), B);
+                          const BatchArgs& B, hipStream_t s) {
+    hipLaunchKernelGGL((k_start<E, P, O>), dim3(B.nblocks), dim3(kBlock), 0, s, src, T, oset0, static_cast<E*>(u),
+                       B);
     return hipGetLastError();
 }
 
@@ -700,8 +685,8 @@ hipError_t launch_spmv_t(const CsrArgs& A, const void* ucur, const void* uprev, 
 
 template <typename E>
 hipError_t launch_start_e(int P, int O, const StartSrc& src, const SegTable& T, int32_t oset0, void* u,
-                          const BatchArgs& B, bool pair, hipStream_t s) {
-    KRY_DISPATCH_PO(launch_start_t, E, P, O, src, T, oset0, u, B, pair, s)
+                          const BatchArgs& B, hipStream_t s) {
+    KRY_DISPATCH_PO(launch_start_t, E, P, O, src, T, oset0, u, B, s)
 }
 
 template <typename E>
@@ -776,11 +761,10 @@ hipError_t launch_to_f32(const double* in, float* out, int64_t n, hipStream_t s)
 }
 
 hipError_t launch_start(int P, int O, bool f32, const StartSrc& src, const SegTable& T, int32_t oset0,
-                        void* u, const BatchArgs& B, hipStream_t s, bool pair) {
+                        void* u, const BatchArgs& B, hipStream_t s) {
     if (P * (1 + O) > kMaxNV) return hipErrorInvalidValue;
-    if (pair && f32) return hipErrorInvalidValue;
-    return f32 ? launch_start_e<float>(P, O, src, T, oset0, u, B, false, s)
-               : launch_start_e<double>(P, O, src, T, oset0, u, B, pair, s);
+    return f32 ? launch_start_e<float>(P, O, src, T, oset0, u, B, s)
+               : launch_start_e<double>(P, O, src, T, oset0, u, B, s);
 }
 
 hipError_t launch_sweep(int P, int O, bool f32, const SegTable& T, int32_t oset0, const void* ucur,

@@ -46,9 +46,17 @@ using namespace dev;
 // |u_j|^2 expanded below this fraction of |r_j|^2 is not trusted
 constexpr double kLz1Guard = 1e-4;
 
+// The pair (u_{j-1}, r_j) of a row.  The first step reads the start kernel's
+// plain vectors ([n][P]: r_1 = the start, u_0 = 0) instead.
 template <int P>
-__device__ __forceinline__ void load_pair(const double* __restrict__ X, int64_t row, double (&u)[P],
+__device__ __forceinline__ void load_pair(bool first, const double* __restrict__ X, int64_t row, double (&u)[P],
                                           double (&r)[P]) {
+    if (first) {
+        load_row<double, P>(X, row, r);
+#pragma unroll
+        for (int p = 0; p < P; ++p) u[p] = 0.0;
+        return;
+    }
     double t[2 * P];
     load_row<double, 2 * P>(X, row, t);
 #pragma unroll
@@ -185,25 +193,24 @@ __device__ __forceinline__ bool stage_outputs(SegStage<O>& st, const SegTable& T
 // One row of a row-partitioned launch: forms u_j, finishes r_{j+1} from the
 // gathered sum, stores the pair and adds the row to the partials
 // (pa: sigma_j u_j . r_{j+1}, |r_{j+1}|^2, |u_j|^2; ps: |u_j|^2, C u_j).
-template <int P, int O, bool MV>
-__device__ __forceinline__ void lz1_row(int64_t r, const double* __restrict__ xin, double* __restrict__ xout,
+template <int P, int O>
+__device__ __forceinline__ void lz1_row(bool first, int64_t r, const double* __restrict__ xin,
+                                        double* __restrict__ xout,
                                         const double (&acc)[P], const double (&coef)[P], const double (&sig)[P],
                                         const double (&cprev)[P], bool any, SegStage<O>& st, SegCursor (&cur)[O],
                                         const SegTable& T, double (&pa)[3 * P], double (&ps)[P * (1 + O)]) {
     double up[P], rj[P], uj[P], y[P];
-    load_pair<P>(xin, r, up, rj);
+    load_pair<P>(first, xin, r, up, rj);
     form<P>(coef, up, rj, uj);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         ps[p] = fma(uj[p], uj[p], ps[p]);
-        if constexpr (MV) {
-            y[p] = fma(-cprev[p], up[p], sig[p] * acc[p]);
-            pa[p] = fma(sig[p] * uj[p], y[p], pa[p]);
-            pa[P + p] = fma(y[p], y[p], pa[P + p]);
-            pa[2 * P + p] = fma(uj[p], uj[p], pa[2 * P + p]);
-        }
+        y[p] = fma(-cprev[p], up[p], sig[p] * acc[p]);
+        pa[p] = fma(sig[p] * uj[p], y[p], pa[p]);
+        pa[P + p] = fma(y[p], y[p], pa[P + p]);
+        pa[2 * P + p] = fma(uj[p], uj[p], pa[2 * P + p]);
     }
-    if constexpr (MV) store_pair<P>(xout, r, uj, y);
+    store_pair<P>(xout, r, uj, y);
     if (any) {
 #pragma unroll
         for (int q = 0; q < O; ++q) {
@@ -219,19 +226,18 @@ __device__ __forceinline__ void lz1_row(int64_t r, const double* __restrict__ xi
 // Block partials of a row-partitioned launch: the next iteration's
 // (ap_out) and stage j - 1's (|u_j|^2, C u_j); at j = 1 the start kernel has
 // written stage 0 and it is read by this launch, so it is left alone.
-template <int P, int O, bool MV>
+template <int P, int O>
 __device__ __forceinline__ void lz1_store(const BatchArgs& B, const Lz1Args& Z, int j, double (&pa)[3 * P],
                                           double (&ps)[P * (1 + O)], double* s_lds) {
-    if constexpr (MV) store_partials<3 * P>(pa, Z.ap_out, B.nblocks, s_lds, B.xcd_map);
+    store_partials<3 * P>(pa, Z.ap_out, B.nblocks, s_lds, B.xcd_map);
     if (j > 1) store_partials<P * (1 + O)>(ps, stage_part(B, j - 1), B.nblocks, s_lds, B.xcd_map);
 }
 
 constexpr int lz1_lds(int P, int O) { return (3 * P > P * (1 + O) ? 3 * P : P * (1 + O)) * (kBlock / 64); }
 
 // Sliced-ELL mat-vec step (CSR systems), the layout and gather scheme of
-// k_spmv_sell with the neighbours formed from pairs.  MV = false is the tail:
-// it forms u_{k+1} for stage k and writes nothing else.
-template <int P, int O, bool D, bool MV>
+// k_spmv_sell with the neighbours formed from pairs.
+template <int P, int O, bool D, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_lz1_sell(SellArgs A, const double* __restrict__ xin,
                                                      double* __restrict__ xout, SegTable T, int32_t oset0,
                                                      BatchArgs B, Lz1Args Z, int j) {
@@ -241,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_lz1_sell(SellArgs A, const double* _
     __shared__ double s_tot[3 * P];
     __shared__ double s_nrm[P];
     __shared__ SegStage<O> st;
+    constexpr bool first = FIRST;
     const int lb = logical_block(B.nblocks, B.xcd_map);
     const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_lz1_sell(SellArgs A, const double* _
         }
     };
     const int64_t nlast = A.n - 1;
-    if constexpr (MV) slice_info(0);
+    slice_info(0);
     SegCursor cur[O];
     const bool any = stage_outputs<O>(st, T, oset0, lb, B.nblocks, cur);
     double coef[P], sig[P], cprev[P];
@@ -286,58 +293,85 @@ __global__ __launch_bounds__(kBlock) void k_lz1_sell(SellArgs A, const double* _
 #pragma unroll
             for (int p = 0; p < P; ++p) { acc[i][p] = 0.0; accu[i][p] = 0.0; }
         }
-        if constexpr (MV) {
-            if (ch + 1 < nch) slice_info(ch + 1);
+        if (ch + 1 < nch) slice_info(ch + 1);
 #pragma unroll
-            for (int i = 0; i < RC; ++i) {
-                for (int kb = 0; kb < wd[i]; kb += KU) {
-                    int32_t c[KU];
-                    double a[KU];
+        for (int i = 0; i < RC; ++i) {
+            for (int kb = 0; kb < wd[i]; kb += KU) {
+                int32_t c[KU];
+                double a[KU];
 #pragma unroll
-                    for (int u = 0; u < KU; ++u) {
-                        const int k = kb + u < wd[i] ? kb + u : wd[i] - 1;
-                        const int64_t idx = off[i] + (int64_t)k * kSlice;
-                        if constexpr (D) {
-                            const int64_t cc = srow[i] + (int64_t)A.dcol[idx];
-                            c[u] = (int32_t)min(max(cc, (int64_t)0), nlast);
-                        } else {
-                            c[u] = A.col[idx];
-                        }
-                        a[u] = kb + u < wd[i] ? A.val[idx] : 0.0;
+                for (int u = 0; u < KU; ++u) {
+                    const int k = kb + u < wd[i] ? kb + u : wd[i] - 1;
+                    const int64_t idx = off[i] + (int64_t)k * kSlice;
+                    if constexpr (D) {
+                        const int64_t cc = srow[i] + (int64_t)A.dcol[idx];
+                        c[u] = (int32_t)min(max(cc, (int64_t)0), nlast);
+                    } else {
+                        c[u] = A.col[idx];
                     }
-                    // unconditional gathers (a slot past the width adds 0 times
-                    // an entry the row already reads)
+                    a[u] = kb + u < wd[i] ? A.val[idx] : 0.0;
+                }
+                // unconditional gathers (a slot past the width adds 0 times
+                // an entry the row already reads)
 #pragma unroll
-                    for (int u = 0; u < KU; ++u) {
-                        double gu[P], gr[P];
-                        load_pair<P>(xin, c[u], gu, gr);
+                for (int u = 0; u < KU; ++u) {
+                    double gu[P], gr[P];
+                    load_pair<P>(first, xin, c[u], gu, gr);
 #pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            acc[i][p] = fma(a[u], gr[p], acc[i][p]);
-                            accu[i][p] = fma(a[u], gu[p], accu[i][p]);
-                        }
+                    for (int p = 0; p < P; ++p) {
+                        acc[i][p] = fma(a[u], gr[p], acc[i][p]);
+                        accu[i][p] = fma(a[u], gu[p], accu[i][p]);
                     }
                 }
             }
         }
-        if (ch == 0) lz1_prologue<P>(B, Z, j, MV, s_lds, s_tot, s_nrm, coef, sig, cprev);
+        if (ch == 0) lz1_prologue<P>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
 #pragma unroll
         for (int i = 0; i < RC; ++i) {
 #pragma unroll
             for (int p = 0; p < P; ++p) acc[i][p] = fma(-coef[p], accu[i][p], acc[i][p]);
-            if (rr[i] < r1) lz1_row<P, O, MV>(rr[i], xin, xout, acc[i], coef, sig, cprev, any, st, cur, T, pa, ps);
+            if (rr[i] < r1)
+                lz1_row<P, O>(first, rr[i], xin, xout, acc[i], coef, sig, cprev, any, st, cur, T, pa, ps);
         }
     }
-    if (nch == 0) lz1_prologue<P>(B, Z, j, MV, s_lds, s_tot, s_nrm, coef, sig, cprev);
-    lz1_store<P, O, MV>(B, Z, j, pa, ps, s_lds);
+    if (nch == 0) lz1_prologue<P>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    lz1_store<P, O>(B, Z, j, pa, ps, s_lds);
+}
+
+// After the last step: alpha_k, beta_k, sigma_{k+1} and k_eff from the last
+// launch's partials by the same expansion as every other step (one block,
+// j = k + 1), and stage k's partials written for the finishing kernel:
+// |u_{k+1}|^2 in block 0, zero elsewhere (C u_{k+1} is no column of
+// P = C V_k), so it records the same beta_k.  u_{k+1} itself is never formed.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_lz1_close(BatchArgs B, Lz1Args Z, int j) {
+    __shared__ double s_lds[(kBlock / 64) * 3 * P];
+    __shared__ double s_tot[3 * P];
+    __shared__ double s_nrm[P];
+    double coef[P], sig[P], cprev[P];
+    lz1_prologue<P>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    double* part = stage_part(B, j - 1);
+    const int64_t total = (int64_t)B.nvp * B.nblocks;
+    for (int64_t i = threadIdx.x; i < total; i += kBlock) {
+        const int v = (int)(i / B.nblocks);
+        double val = 0.0;
+        if (i % B.nblocks == 0 && v < P) {
+            const double D = s_tot[v], R = s_tot[P + v], N = s_tot[2 * P + v];
+            const double sp = run_scal(B, v)[B.L.sigma + j - 1];
+            val = R - D * D * (2.0 - sp * sp * N);
+            if (val < 0.0) val = 0.0;
+        }
+        part[i] = val;
+    }
 }
 
 // Row-partitioned 7-point stencil step (grids too small for the marching
 // kernel), neighbours summed in the order of k_spmv_stencil.
-template <int P, int O>
+template <int P, int O, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const double* __restrict__ xin,
                                                         double* __restrict__ xout, SegTable T, int32_t oset0,
                                                         BatchArgs B, Lz1Args Z, int j) {
+    constexpr bool first = FIRST;
     __shared__ double s_lds[lz1_lds(P, O)];
     __shared__ double s_tot[3 * P];
     __shared__ double s_nrm[P];
@@ -364,14 +398,14 @@ __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const dou
         const bool yl = iy > 0, yh = iy < S.ny - 1;
         const bool zl = iz > 0, zh = iz < S.nz - 1;
         double nu[6][P], nr[6][P];
-        load_pair<P>(xin, xl ? r - sx : r, nu[0], nr[0]);
-        load_pair<P>(xin, yl ? r - sy : r, nu[1], nr[1]);
-        load_pair<P>(xin, zl ? r - 1 : r, nu[2], nr[2]);
-        load_pair<P>(xin, zh ? r + 1 : r, nu[3], nr[3]);
-        load_pair<P>(xin, yh ? r + sy : r, nu[4], nr[4]);
-        load_pair<P>(xin, xh ? r + sx : r, nu[5], nr[5]);
+        load_pair<P>(first, xin, xl ? r - sx : r, nu[0], nr[0]);
+        load_pair<P>(first, xin, yl ? r - sy : r, nu[1], nr[1]);
+        load_pair<P>(first, xin, zl ? r - 1 : r, nu[2], nr[2]);
+        load_pair<P>(first, xin, zh ? r + 1 : r, nu[3], nr[3]);
+        load_pair<P>(first, xin, yh ? r + sy : r, nu[4], nr[4]);
+        load_pair<P>(first, xin, xh ? r + sx : r, nu[5], nr[5]);
         double own_u[P], own_r[P], own[P];
-        load_pair<P>(xin, r, own_u, own_r);
+        load_pair<P>(first, xin, r, own_u, own_r);
         form<P>(coef, own_u, own_r, own);
         const double diag = stencil_diag(S, xl, xh, yl, yh, zl, zh);
         double acc[P];
@@ -390,20 +424,23 @@ __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const dou
             if (xh) a = fma(S.cx, v[5], a);
             acc[p] = a;
         }
-        lz1_row<P, O, true>(r, xin, xout, acc, coef, sig, cprev, any, st, cur, T, pa, ps);
+        lz1_row<P, O>(first, r, xin, xout, acc, coef, sig, cprev, any, st, cur, T, pa, ps);
         iz += kBlock;
         while (iz >= S.nz) {
             iz -= S.nz;
             if (++iy == S.ny) { iy = 0; ++ix; }
         }
     }
-    lz1_store<P, O, true>(B, Z, j, pa, ps, s_lds);
+    lz1_store<P, O>(B, Z, j, pa, ps, s_lds);
 }
 
 // Marching one-pass stencil on (y, z) tiles.  A workgroup owns a tile of
-// kTileY grid rows in y by kMarchOwn columns in z and walks it along x: wave w
-// holds row y0 + w, lanes 1..62 its owned columns, lanes 0 and 63 the columns
-// just outside (loaded, never stored).  Per x step every wave forms its
+// TY grid rows in y by kMarchOwn columns in z and walks it along x: wave w
+// holds row y0 + w, lanes 1..60 its owned columns, lanes 0 and 61 the columns
+// just outside (loaded, never stored; lanes 62 and 63 idle).  60 owned
+// columns of pairs are whole 128-byte lines for one to eight runs, so no
+// line is written by two tiles (62 columns wrote 10 % more than the pair
+// buffer on the 1000^3 system, 60 write it once).  Per x step every wave forms its
 // plane-x values, the z neighbours come from the adjacent lanes (wave
 // shuffles), the y neighbours from the adjacent waves through LDS (one
 // barrier per step, double-buffered), and only the tile's first and last wave
@@ -412,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const dou
 // by unrolling); the outer rows of plane x + 1 are loaded during step x.  Each
 // element of the pair buffer is then read from memory about once per
 // iteration (rows beyond a tile twice).
-constexpr int kMarchOwn = 62;                          // z columns a wavefront owns
+constexpr int kMarchOwn = 60;                          // z columns a wavefront owns
 
 
 struct Lz1Col {
@@ -424,8 +461,8 @@ struct Lz1Col {
 // x); (u0, r0), (up, rp): pairs of planes x, x + 1 of this lane's column;
 // (un, rn) receives plane x + 2; (ou, orr): the outer
 // row's pair at plane x (first and last wave), (nou, nor) receives it at
-// plane x + 1.  lds: [2][kTileY][64][P] formed plane values.
-template <int P, bool NT, int TY>
+// plane x + 1.  lds: [2][TY][64][P] formed plane values.
+template <int P, bool NT, int TY, bool FIRST>
 __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Col& M, int64_t ix,
                                                const double* __restrict__ xin, double* __restrict__ xout,
                                                const double (&coef)[P], const double (&sig)[P],
@@ -435,8 +472,8 @@ __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Co
                                                const double (&ou)[P], const double (&orr)[P], double (&nou)[P],
                                                double (&nor)[P], double* lds, double (&pa)[3 * P]) {
     const int64_t r = ix * M.sx + M.col;
-    load_pair<P>(xin, ix + 2 < S.nx ? r + 2 * M.sx : r, un, rn);
-    if (M.outer) load_pair<P>(xin, (ix + 1 < S.nx ? r + M.sx : r) + M.dout, nou, nor);
+    load_pair<P>(FIRST, xin, ix + 2 < S.nx ? r + 2 * M.sx : r, un, rn);
+    if (M.outer) load_pair<P>(FIRST, xin, (ix + 1 < S.nx ? r + M.sx : r) + M.dout, nou, nor);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double x0[P];
 #pragma unroll
@@ -480,7 +517,7 @@ __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Co
     for (int p = 0; p < P; ++p) fm[p] = x0[p];   // plane x - 1 of the next step
 }
 
-template <int P, bool NT, int TY>
+template <int P, bool NT, int TY, bool FIRST>
 __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const double* __restrict__ xin,
                                                        double* __restrict__ xout, BatchArgs B, Lz1Args Z, int nb,
                                                        int tiles_z, int j) {
@@ -512,9 +549,9 @@ __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const doub
     double oa_u[P], oa_r[P], ob_u[P], ob_r[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) { oa_u[p] = 0.0; oa_r[p] = 0.0; ob_u[p] = 0.0; ob_r[p] = 0.0; fm[p] = 0.0; }
-    load_pair<P>(xin, M.col, ua, ra);
-    load_pair<P>(xin, S.nx > 1 ? M.col + M.sx : M.col, ub, rb);
-    if (M.outer) load_pair<P>(xin, M.col + M.dout, oa_u, oa_r);
+    load_pair<P>(FIRST, xin, M.col, ua, ra);
+    load_pair<P>(FIRST, xin, S.nx > 1 ? M.col + M.sx : M.col, ub, rb);
+    if (M.outer) load_pair<P>(FIRST, xin, M.col + M.dout, oa_u, oa_r);
     double coef[P], sig[P], cprev[P];
     lz1_prologue<P, NTH>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
     double pa[3 * P];
@@ -522,14 +559,14 @@ __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const doub
     for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
     // three pair slots rotate by unrolling: planes x, x + 1 and the x + 2 load
     for (int64_t ix = 0; ix < S.nx; ix += 3) {
-        lz1_march_step<P, NT, TY>(S, M, ix, xin, xout, coef, sig, cprev, fm, ua, ra, ub, rb, uc, rc, oa_u, oa_r,
-                                  ob_u, ob_r, s_plane, pa);
+        lz1_march_step<P, NT, TY, FIRST>(S, M, ix, xin, xout, coef, sig, cprev, fm, ua, ra, ub, rb, uc, rc, oa_u,
+                                  oa_r, ob_u, ob_r, s_plane, pa);
         if (ix + 1 >= S.nx) break;
-        lz1_march_step<P, NT, TY>(S, M, ix + 1, xin, xout, coef, sig, cprev, fm, ub, rb, uc, rc, ua, ra, ob_u, ob_r,
-                                  oa_u, oa_r, s_plane, pa);
+        lz1_march_step<P, NT, TY, FIRST>(S, M, ix + 1, xin, xout, coef, sig, cprev, fm, ub, rb, uc, rc, ua, ra,
+                                  ob_u, ob_r, oa_u, oa_r, s_plane, pa);
         if (ix + 2 >= S.nx) break;
-        lz1_march_step<P, NT, TY>(S, M, ix + 2, xin, xout, coef, sig, cprev, fm, uc, rc, ua, ra, ub, rb, oa_u, oa_r,
-                                  ob_u, ob_r, s_plane, pa);
+        lz1_march_step<P, NT, TY, FIRST>(S, M, ix + 2, xin, xout, coef, sig, cprev, fm, uc, rc, ua, ra, ub, rb,
+                                  oa_u, oa_r, ob_u, ob_r, s_plane, pa);
         // (the outer-row slots alternate with odd period: swap them for the next round)
         if (ix + 3 >= S.nx) break;
 #pragma unroll
@@ -622,24 +659,33 @@ __global__ __launch_bounds__(kBlock) void k_lz1_proj(const double* __restrict__ 
 template <typename K, typename... Args>
 void go(K kernel, dim3 g, hipStream_t s, Args... args) {
     const ExtEvents ev = *ext_events();
-    if (ev.start != nullptr)
+    if (ev.start != nullptr) {
         hipExtLaunchKernelGGL(kernel, g, dim3(kBlock), 0, s, ev.start, ev.stop, 0, args...);
-    else
+        ext_events()->start = nullptr;   // consumed
+    } else {
         hipLaunchKernelGGL(kernel, g, dim3(kBlock), 0, s, args...);
+    }
 }
 
-template <int P, int O, bool MV>
+template <int P, int O>
 hipError_t launch_sell_po(const SellArgs& A, const double* xin, double* xout, const SegTable& T, int32_t oset0,
                           const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
-    if (A.dcol) go(k_lz1_sell<P, O, true, MV>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
-    else go(k_lz1_sell<P, O, false, MV>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+    // the first step reads plain start vectors: an instantiation of its own
+    if (j == 1) {
+        if (A.dcol) go(k_lz1_sell<P, O, true, true>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+        else go(k_lz1_sell<P, O, false, true>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+    } else {
+        if (A.dcol) go(k_lz1_sell<P, O, true, false>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+        else go(k_lz1_sell<P, O, false, false>, dim3(B.nblocks), s, A, xin, xout, T, oset0, B, Z, j);
+    }
     return hipGetLastError();
 }
 
 template <int P, int O>
 hipError_t launch_stencil_po(const StencilArgs& S, const double* xin, double* xout, const SegTable& T,
                              int32_t oset0, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
-    go(k_lz1_stencil<P, O>, dim3(B.nblocks), s, S, xin, xout, T, oset0, B, Z, j);
+    if (j == 1) go(k_lz1_stencil<P, O, true>, dim3(B.nblocks), s, S, xin, xout, T, oset0, B, Z, j);
+    else go(k_lz1_stencil<P, O, false>, dim3(B.nblocks), s, S, xin, xout, T, oset0, B, Z, j);
     return hipGetLastError();
 }
 
@@ -676,14 +722,7 @@ hipError_t launch_proj_po(const double* x, const SegTable& T, int32_t oset0, con
 template <int P, int O>
 hipError_t launch_sell_step_po(const SellArgs& A, const double* xin, double* xout, const SegTable& T, int32_t oset0,
                                const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
-    return launch_sell_po<P, O, true>(A, xin, xout, T, oset0, B, Z, j, s);
-}
-
-template <int P, int O>
-hipError_t launch_tail_po(const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B, const Lz1Args& Z,
-                          int j, hipStream_t s) {
-    SellArgs none{};
-    return launch_sell_po<P, O, false>(none, xin, nullptr, T, oset0, B, Z, j, s);
+    return launch_sell_po<P, O>(A, xin, xout, T, oset0, B, Z, j, s);
 }
 
 }  // namespace
@@ -701,11 +740,13 @@ hipError_t launch_lz1_stencil(int P, int O, const StencilArgs& S, const double* 
 
 static int64_t lz1_tiles_z(int64_t nz) { return (nz + kMarchOwn - 1) / kMarchOwn; }
 
-// y rows per tile of the marching kernel (one wavefront each): 8 for up to
-// two runs per launch, 4 for more (their registers leave no room for 8
-// wavefronts).  Measured on the 1000^3 system: 8 rows read 25 % more than the
-// pair buffer instead of 50 % with 4, and run 10 % faster.
-static int lz1_tile_y(int P) { return P <= 2 ? 8 : 4; }
+// y rows per tile of the marching kernel (one wavefront each): 16 for up to
+// two runs per launch, 4 for more (their registers leave no room for more
+// wavefronts).  The rows beyond a tile are read twice, so the reads exceed
+// the pair buffer by 2/TY.  Measured on the 1000^3 system with two runs:
+// 14.8 ms per launch with 8 rows, 14.4 ms with 16 (13.6 ms with 16 rows and
+// 60 owned columns, against 14.2 ms with 8).
+static int lz1_tile_y(int P) { return P <= 2 ? 16 : 4; }
 
 int32_t lz1_march_blocks(int64_t ny, int64_t nz, int P) {
     const int ty = lz1_tile_y(P);
@@ -713,15 +754,27 @@ int32_t lz1_march_blocks(int64_t ny, int64_t nz, int P) {
     return (int32_t)((nb + 7) / 8 * 8);
 }
 
+template <int P, bool NT, int TY, bool FIRST>
+void launch_march_f(const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B, const Lz1Args& Z,
+                    int nb, int tz, int j, hipStream_t s) {
+    const ExtEvents ev = *ext_events();
+    if (ev.start != nullptr) {
+        hipExtLaunchKernelGGL(k_lz1_march<P, NT, TY, FIRST>, dim3(nb), dim3(TY * 64), 0, s, ev.start, ev.stop, 0, S,
+                              xin, xout, B, Z, nb, tz, j);
+        ext_events()->start = nullptr;   // consumed
+    } else {
+        hipLaunchKernelGGL((k_lz1_march<P, NT, TY, FIRST>), dim3(nb), dim3(TY * 64), 0, s, S, xin, xout, B, Z, nb,
+                           tz, j);
+    }
+}
+
+// the first step reads plain start vectors: its own instantiation keeps the
+// pair path's registers as they are
 template <int P, bool NT, int TY>
 void launch_march_t(const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B, const Lz1Args& Z,
                     int nb, int tz, int j, hipStream_t s) {
-    const ExtEvents ev = *ext_events();
-    if (ev.start != nullptr)
-        hipExtLaunchKernelGGL(k_lz1_march<P, NT, TY>, dim3(nb), dim3(TY * 64), 0, s, ev.start, ev.stop, 0, S, xin,
-                              xout, B, Z, nb, tz, j);
-    else
-        hipLaunchKernelGGL((k_lz1_march<P, NT, TY>), dim3(nb), dim3(TY * 64), 0, s, S, xin, xout, B, Z, nb, tz, j);
+    if (j == 1) launch_march_f<P, NT, TY, true>(S, xin, xout, B, Z, nb, tz, j, s);
+    else launch_march_f<P, NT, TY, false>(S, xin, xout, B, Z, nb, tz, j, s);
 }
 
 hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
@@ -729,8 +782,8 @@ hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, doub
     const int nb = lz1_march_blocks(S.ny, S.nz, P);
     const int tz = (int)lz1_tiles_z(S.nz);
     switch (P) {
-        case 1: launch_march_t<1, true, 8>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 2: launch_march_t<2, true, 8>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 1: launch_march_t<1, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 2: launch_march_t<2, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
         case 4: launch_march_t<4, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
         case 8: launch_march_t<8, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
         default: return hipErrorInvalidValue;
@@ -743,9 +796,16 @@ hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int
     KRY_LZ1_PO(launch_proj_po, x, T, oset0, B, j, s)
 }
 
-hipError_t launch_lz1_tail(int P, int O, const double* xin, const SegTable& T, int32_t oset0, const BatchArgs& B,
-                           const Lz1Args& Z, int j, hipStream_t s) {
-    KRY_LZ1_PO(launch_tail_po, xin, T, oset0, B, Z, j, s)
+// (through go(): a timed launch records the events it is handed)
+hipError_t launch_lz1_close(int P, const BatchArgs& B, const Lz1Args& Z, int j, hipStream_t s) {
+    switch (P) {
+        case 1: go(k_lz1_close<1>, dim3(1), s, B, Z, j); break;
+        case 2: go(k_lz1_close<2>, dim3(1), s, B, Z, j); break;
+        case 4: go(k_lz1_close<4>, dim3(1), s, B, Z, j); break;
+        case 8: go(k_lz1_close<8>, dim3(1), s, B, Z, j); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace kry

@@ -300,10 +300,12 @@ hipError_t launch_spmv_sell_ed(int P, const SellArgs& A, const void* ucur, const
     const dim3 g(B.nblocks), b(kBlock);
     const ExtEvents ev = *ext_events();
     auto go = [&](auto kernel) {
-        if (ev.start != nullptr)
+        if (ev.start != nullptr) {
             hipExtLaunchKernelGGL(kernel, g, b, 0, s, ev.start, ev.stop, 0, A, uc, up, ww, B, j);
-        else
+            ext_events()->start = nullptr;   // consumed
+        } else {
             hipLaunchKernelGGL(kernel, g, b, 0, s, A, uc, up, ww, B, j);
+        }
     };
     switch (P) {
         case 1: go(k_spmv_sell<E, 1, D>); break;

@@ -180,7 +180,8 @@ def test_transposed_plan_rejects_bad_arguments(bad):
     elif bad == "k_forcing":
         k = 56                       # the forcing column's exponential has size k + 1
     elif bad == "rows":
-        gens = [W.Generator(W.segments_from_ranges([(j, j + 1)]), 0.0, 1.0) for j in range(8)]
+        # 4096 generators and b: one initial-space row past the wide route's 4096
+        gens = [W.Generator(W.segments_from_ranges([(j % 50, j % 50 + 1)]), 0.0, 1.0) for j in range(4096)]
     elif bad == "block":
         method = kry.KRY_BLOCK_ARNOLDI
         expected = kry.KRY_ENOTSUP

@@ -103,11 +103,13 @@ def test_onepass_row_stencil():
     _check(ps, "lz1_stencil")
 
 
-@pytest.mark.parametrize("grid", [(37, 11, 19), (8, 30, 30)])
+@pytest.mark.parametrize("grid", [(37, 11, 19), (8, 30, 30), (9, 35, 130)])
 def test_onepass_marching_stencil_forced(grid):
     # the marching kernel on a small grid (forced): nx not a multiple of its
-    # four-plane unroll, dead lanes in the last column block, outputs whose
-    # segments start mid-block for the projection kernel
+    # three-plane unroll, dead lanes in the last column block, dead waves in
+    # the last row tile (16 rows), several tiles both ways (35 rows, 130
+    # columns against 60 per tile), outputs whose segments start mid-block
+    # for the projection kernel
     nx, ny, nz = grid
     n = nx * ny * nz
     h = 1.0 / (max(grid) + 1)

@@ -2,7 +2,9 @@
 with the oracle's verify_transposed, element by element: the worked
 example (nonsymmetric, Arnoldi on A^T), random symmetric systems with a
 center and forcing (Lanczos), a CSR heat problem with eight initial-space
-columns and one output, and a matrix-free stencil."""
+columns and one output, a matrix-free stencil, and initial spaces of
+hundreds of columns (the wide projection and small stage), FP64 and FP32
+basis, symmetric and not, against the oracle and against the forward route."""
 import dataclasses
 import json
 import os
@@ -181,3 +183,64 @@ def test_paper_heat_stencil_faces():
     require_gpu()
     p = W.heat3d_paper_stencil(m=12, k=30, dt=0.02, steps=80)
     _parity(p)
+
+
+# ---------------------------------------------------------------------------
+# Hundreds of initial-space rows (i >> o): the wide projection and small stage
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("center,affine,precision", [(True, True, "fp64"), (False, False, "fp64"),
+                                                     (True, True, "fp32")])
+def test_wide_heat3d_256_generators(center, affine, precision):
+    # 256 box generators (+ center + forcing) and one output row: one run of
+    # A^T projected on 256..258 rows of E^T
+    require_gpu()
+    from paper_1804_01583_amd import kry
+    p = W.heat3d_many_gens(m=16, g=2, ngen=256, k=30, steps=100)
+    if not center:
+        p.center = None
+    if not affine:
+        p.b_seg = None
+    prec = kry.KRY_FP64 if precision == "fp64" else kry.KRY_FP32_BASIS
+    if precision == "fp64":
+        got, ref, worst = _parity(p, precision=prec)
+    else:
+        got = gpu_verify_transposed(p, precision=prec)
+        ref = OT.verify_transposed(p)
+        h = 1.0 / 17
+        tol = min(1e-4, max(1e-5, 2 * np.finfo(np.float32).eps * 12 * 0.01 / h**2 * p.steps * p.dt))
+        worst = assert_basis_parity(got["basis"], ref["basis"], rtol=tol)
+        assert got["verdict"]["first_step"] == ref["verdict"]["first_step"]
+    assert got["basis"].shape[2] == 256 + center + affine
+    print(f"  wide {precision} center={center} affine={affine}: worst {worst:.2e}", flush=True)
+
+
+def test_wide_nonsymmetric_two_outputs_arnoldi():
+    # convection-diffusion (Arnoldi on A^T), two output rows, 300 generators
+    # of 5 cells each
+    require_gpu()
+    p = W.conv_diff3d(8, 8, 10, ngen=2, gen_len=5, o=2, k=24, steps=60, dt=2e-3, seed=9)
+    p.gens = [W.Generator(W.segments_from_ranges([(5 * j, 5 * j + 5)], 1.0), 0.3, 0.05 + 0.001 * j)
+              for j in range(128)]
+    p.center = np.linspace(0.0, 1.0, p.n)
+    _parity(p)
+
+
+def test_wide_matches_the_forward_route_on_the_verdict():
+    # the same 258-column basis by 258 forward runs: agreement to the two
+    # routes' Krylov error (k = 40 each) and the same first violation
+    require_gpu()
+    from paper_1804_01583_amd import kry
+    p = W.heat3d_many_gens(m=16, g=2, ngen=256, k=40, steps=100)
+    # unsafe below a level the output's lower end crosses mid-run
+    lo = OT.verify_transposed(p)["verdict"]["lo"][:, 0]
+    assert np.all(np.diff(lo[40:70]) < 0)
+    q = dataclasses.replace(p, unsafe=np.array([[-np.inf, 0.5 * (lo[55] + lo[56])]]))
+    t = gpu_verify_transposed(q)
+    fwd = kry.Plan(kry.DeviceSystem(q))
+    fb = fwd.basis()
+    fv = fwd.check(q.unsafe)
+    fwd.close()
+    scale = np.abs(fb).max()
+    assert np.abs(t["basis"] - fb).max() <= 1e-10 * scale
+    assert t["verdict"]["first_step"] == fv["first_step"] == 56

@@ -29,7 +29,7 @@ __all__ = [
     "segments_from_ranges", "box_segments", "csr_stencil7",
     "harmonic_oscillator", "heat1d", "heat3d_csr", "heat3d_stencil", "heat3d_paper", "csr_heat_insulated",
     "heat3d_paper_stencil", "csr_stencil7_faces",
-    "random_symmetric", "small_heat3d", "conv_diff3d",
+    "random_symmetric", "small_heat3d", "conv_diff3d", "heat3d_many_gens",
     "segments_of_dense", "heat3d_many_inputs",
 ]
 
@@ -437,6 +437,26 @@ def heat3d_many_inputs(m=100, D=0.01, k=40, dt=0.02, steps=1000, seed=5, floor=0
                    b_seg=bseg, center=center_seg.dense(n), rowptr=rowptr, colidx=colidx, vals=vals, seed=seed,
                    meta={"m": m, "forcing_box": fbox, "warm_box": wbox},
                    note="3D heat, eight initial-space columns, one output")
+
+
+def heat3d_many_gens(m=100, g=5, ngen=256, D=0.01, k=40, dt=0.02, steps=1000, seed=6, floor=0.01) -> Problem:
+    """An initial space of hundreds of columns and one output (i >> o, the
+    transposed route's case): the system, forcing and warm cube of
+    heat3d_many_inputs, with `ngen` box generators on distinct seeded g^3
+    cells of the grid (1.0 +- 0.1 each) instead of six."""
+    base = heat3d_many_inputs(m=m, D=D, k=k, dt=dt, steps=steps, seed=seed, floor=floor)
+    cells = m // g
+    rng = np.random.default_rng(seed + 2)
+    picks = rng.choice(cells**3, size=min(ngen, cells**3), replace=False)
+    gens = []
+    for pk in sorted(int(x) for x in picks):
+        cx, cy, cz = pk // (cells * cells), (pk // cells) % cells, pk % cells
+        gb = ((cx * g, cx * g + g), (cy * g, cy * g + g), (cz * g, cz * g + g))
+        gens.append(Generator(box_segments((m, m, m), gb, 1.0), zc=1.0, radius=0.1))
+    base.gens = gens
+    base.name = "heat3d_many_gens"
+    base.note = f"3D heat, {len(gens) + 2} initial-space columns, one output"
+    return base
 
 
 def heat3d_stencil(m=1000, D=0.01, k=20, dt=0.01, steps=500, seed=4) -> Problem:
