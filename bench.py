@@ -40,6 +40,8 @@ Prints one JSON line.  Options:
                   --seconds T of arrivals per rate (at most 2000 queries), --slots S,
                   --serve-batch on|off|both (same-step queries of one system in one plan);
                   reports p50/p99 arrival-to-verdict latency per rate
+  --autotune      before timing, tune the launch choices that change no value
+                  (block mat-vec shape, marching store kind) on one plan
   --calib-copy    run a plain device copy of known size (for counter calibration) and exit
 """
 from __future__ import annotations
@@ -108,6 +110,8 @@ def main():
     ap.add_argument("--no-prepared", action="store_true",
                     help="CSR: every plan builds its own sliced-ELL copy and norm instead of sharing one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the order-neutral launch choices on one plan first (kry_plan_autotune)")
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,6 +167,18 @@ def main():
         for prec in ((kry.KRY_FP32_BASIS, kry.KRY_FP64) if f32 else (kry.KRY_FP64,)):
             dsys.prepare(prec)
         torch.cuda.synchronize()
+    tuned = None
+    if args.autotune and not transposed:
+        # one plan's kernels timed before the timed region; the process keeps
+        # the choices (every choice gives the same basis bit for bit)
+        tp = kry.Plan(dsys, precision=kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, method=method)
+        tuned = {"kernels_tuned": tp.autotune(reps=3)}
+        tp.close()
+        for kname, runs in (("bspmm", 16), ("bspmm32", 16), ("lz1_march", 2)):
+            c = kry.kry_tune_choice(kname, p.n, runs)
+            if c is not None:
+                tuned[kname] = {"a": c[0], "b": c[1], "us": c[2]}
+        log(f"autotune: {tuned}")
     m = measure(torch, kry, p, dsys, kry.KRY_FP32_BASIS if f32 else kry.KRY_FP64, args.steps, args.warmup, method,
                 args.error_target, not args.no_kernel_events and not args.graph, transposed, args.check, args.graph)
     fp64_ref = None
@@ -233,6 +249,7 @@ def main():
         "fp64_reference": fp64_ref,
         "fp32_basis_side": fp32_side,
         "error_control": m.get("error_control"),
+        "autotune": tuned,
         "verdict": {"first_step": verdict["first_step"], "row": verdict["row"]},
         "cpu_baseline": cpu,
     }

@@ -434,6 +434,30 @@ kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps);
  * the plan's stream.  KRY_ENOTSUP for block plans. */
 kry_status kry_plan_error(kry_plan_t* plan, int32_t run, int32_t* k_used, double* bound);
 
+/* kry_plan_autotune -- time the launch choices of this plan's hot kernel
+ * that leave every result bit for bit unchanged, on the plan's own data, and
+ * keep the fastest for this device, kernel, n and runs per launch (a process
+ * table; with the environment variable KRY_TUNE_CACHE naming a file, read from
+ * it on first use and written back after each tuning).  Later plans of the
+ * same shape use the choice.  Tuned: block plans' block mat-vec (rows per
+ * workgroup 32..512, workgroups in row order or XCD-contiguous, timed on the
+ * run's first block) and the one-pass marching stencil step (non-temporal or
+ * plain pair stores, timed over whole projections).  Other plans tune
+ * nothing.  The plan is projected first if it was not; afterwards its basis
+ * and verdicts are valid (the choices change no value).  reps: timed calls
+ * per candidate, 1..1000 (two rounds, the better kept).  *tuned (may be NULL):
+ * kernels tuned.  KRY_ENOTSUP in graph mode.  Waits for the stream. */
+kry_status kry_plan_autotune(kry_plan_t* plan, int32_t reps, int32_t* tuned);
+/* kry_tune_choice -- the stored choice for kernel ("bspmm", "bspmm32" (FP32
+ * basis) with runs = 16; "lz1_march" with runs = runs per launch) and n on the
+ * current device: *found = 1 and (a, b, us) = (rows per workgroup, XCD map,
+ * microseconds) or (non-temporal, 0, microseconds), else *found = 0. */
+kry_status kry_tune_choice(const char* kernel, int64_t n, int32_t runs, int32_t* found, int32_t* a, int32_t* b,
+                           double* us);
+/* kry_tune_clear -- forget every stored choice of this process; the next
+ * lookup reads the KRY_TUNE_CACHE file again (left as it is) when one is set. */
+void kry_tune_clear(void);
+
 void kry_plan_destroy(kry_plan_t* plan);
 
 /* kry_matrix_create -- device-side preparation of a KRY_CSR system that any

@@ -535,6 +535,9 @@ struct kry_plan {
     // wseg0 + wnseg - 1 (kry_wide.hip)
     bool wide = false;
     int32_t wset0 = 0, wseg0 = 0, wnseg = 0;
+    // launch choices forced while the tuner times them (-1: the table's or
+    // the default)
+    int32_t force_spmm_rows = -1, force_spmm_xcd = -1, force_march_nt = -1;
     int32_t njobs = 0;             // exponentials of the small stage
     int32_t o_out = 0, ncols = 0;  // basis shape
     std::vector<int32_t> col_role; // per basis column: 0 generator, 1 center, 2 forcing
@@ -1150,6 +1153,16 @@ kry_status project_block(kry_plan_t* plan) {
     B.state = plan->at<int32_t>(Y.bstate);
     B.anorm = plan->anorm_dev;
     B.tau_scale = 1024.0 * (f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    {
+        TuneChoice c{};
+        if (plan->force_spmm_rows >= 0) {
+            B.spmm_rows = plan->force_spmm_rows;
+            B.spmm_xcd = plan->force_spmm_xcd;
+        } else if (tune_lookup(f32 ? "bspmm32" : "bspmm", n, kBW, &c)) {
+            B.spmm_rows = c.a;
+            B.spmm_xcd = c.b;
+        }
+    }
     CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, f32 ? plan->vals32() : nullptr};
     plan->blocks.clear();
     hipError_t e = hipSuccess;
@@ -1294,6 +1307,12 @@ kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const Star
     Z.flag = flag;
     Z.nb_in = nb_step;
     const int k = plan->k;
+    int nt = 1;   // non-temporal pair stores, unless the tuner found plain ones faster here
+    if (march) {
+        TuneChoice c{};
+        if (plan->force_march_nt >= 0) nt = plan->force_march_nt;
+        else if (tune_lookup("lz1_march", plan->sys.n, P, &c)) nt = c.a;
+    }
     for (int j = 1; j <= k; ++j) {
         const double* xin = X[(j - 1) & 1];
         double* xout = X[j & 1];
@@ -1304,7 +1323,7 @@ kry_status onepass_batch(kry_plan_t* plan, const BatchArgs& B, int P, const Star
                 return launch_lz1_sell(P, plan->o, plan->sell, xin, xout, plan->T, plan->oset0, B, Z, j, s);
             });
         } else if (march) {
-            e = timed("lz1_march", s, [&] { return launch_lz1_march(P, S, xin, xout, B, Z, j, s); });
+            e = timed("lz1_march", s, [&] { return launch_lz1_march(P, S, xin, xout, B, Z, j, s, nt); });
             if (e == hipSuccess && j > 1)
                 e = timed("lz1_proj", s, [&] {
                     return launch_lz1_proj(P, plan->o, xout, plan->T, plan->oset0, B, j, s);
@@ -2154,6 +2173,119 @@ void kry_matrix_destroy(kry_matrix* mat) {
         if (mat->mem) (void)hipFree(mat->mem);
         delete mat;
     });
+}
+
+kry_status kry_plan_autotune(kry_plan_t* plan, int32_t reps, int32_t* tuned) {
+    return guarded("kry_plan_autotune", [&]() -> kry_status {
+        if (!plan) return fail(KRY_EINVAL, "plan is NULL");
+        if (reps < 1 || reps > 1000) return fail(KRY_EINVAL, "reps must be in [1, 1000]");
+        if (plan->graph_on) return fail(KRY_ENOTSUP, "tune before recording the plan as a graph");
+        if (tuned) *tuned = 0;
+        hipStream_t s = plan->stream;
+        const Layout& Y = plan->Y;
+        hipEvent_t a = nullptr, b = nullptr;
+        KRY_HIP(hipEventCreate(&a));
+        KRY_HIP(hipEventCreate(&b));
+        struct Ev {
+            hipEvent_t a, b;
+            ~Ev() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev{a, b};
+        // microseconds per call of `run`, the better of two rounds of reps calls
+        auto time_us = [&](auto&& run, double* us) -> kry_status {
+            double best = INFINITY;
+            for (int round = 0; round < 2; ++round) {
+                KRY_HIP(hipEventRecord(a, s));
+                for (int r = 0; r < reps; ++r) {
+                    const kry_status st = run();
+                    if (st != KRY_OK) return st;
+                }
+                KRY_HIP(hipEventRecord(b, s));
+                KRY_HIP(hipEventSynchronize(b));
+                float ms = 0.f;
+                KRY_HIP(hipEventElapsedTime(&ms, a, b));
+                best = std::min(best, 1000.0 * ms / reps);
+            }
+            *us = best;
+            return KRY_OK;
+        };
+        if (!plan->projected) {
+            const kry_status st = kry_project_expm(plan, nullptr);
+            if (st != KRY_OK) return st;
+        }
+        if (plan->method == KRY_BLOCK_ARNOLDI && plan->k >= 1) {
+            // the block mat-vec on the run's first block, written to the last
+            // stored block (the projection's result is already in the basis)
+            const int64_t n = plan->sys.n;
+            const int64_t vstride = n * kBW;
+            BlockArgs B{};
+            B.n = n;
+            B.state = plan->at<int32_t>(Y.bstate) + 3;   // a flag that stays 0: the kernel runs
+            KRY_HIP(launch_fill_i32(B.state, 1, 0, s));
+            CsrArgs A{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, plan->f32 ? plan->vals32() : nullptr};
+            const void* V0 = plan->ws + Y.bvec;
+            void* W = plan->ws + Y.bvec + (size_t)plan->k * vstride * Y.esize;
+            TuneChoice best{};
+            best.us = INFINITY;
+            for (int32_t rows : {32, 64, 128, 256, 512}) {
+                for (int32_t xcd : {0, 1}) {
+                    B.spmm_rows = rows;
+                    B.spmm_xcd = xcd;
+                    double us = 0.0;
+                    const kry_status st = time_us([&]() -> kry_status {
+                        const hipError_t e = launch_bspmm(plan->f32, A, V0, W, B, s);
+                        return e == hipSuccess ? KRY_OK : fail(KRY_EDEVICE, std::string("bspmm: ") + hipGetErrorString(e));
+                    }, &us);
+                    if (st != KRY_OK) return st;
+                    if (us < best.us) best = TuneChoice{rows, xcd, us};
+                }
+            }
+            tune_store(plan->f32 ? "bspmm32" : "bspmm", n, kBW, best);
+            if (tuned) *tuned += 1;
+            return KRY_OK;
+        }
+        const bool march = plan->sys.kind == KRY_STENCIL7 && Y.march > 0 && Y.lz1 && plan->method == KRY_LANCZOS &&
+                           plan->err_eps <= 0.0 && !plan->wide && env_int("KRY_ONEPASS", -1) != 0;
+        if (march) {
+            // whole projections with plain or non-temporal pair stores (the
+            // marching launches are nearly all of it); the results are equal
+            int P = Y.pmax;
+            while (P > 1 && P > plan->nruns) P >>= 1;
+            TuneChoice best{};
+            best.us = INFINITY;
+            for (int32_t nt : {1, 0}) {
+                plan->force_march_nt = nt;
+                double us = 0.0;
+                kry_status st = enqueue_projection(plan, nullptr, true);
+                if (st == KRY_OK) st = time_us([&] { return enqueue_projection(plan, nullptr, true); }, &us);
+                plan->force_march_nt = -1;
+                if (st != KRY_OK) return st;
+                if (us < best.us) best = TuneChoice{nt, 0, us};
+            }
+            tune_store("lz1_march", plan->sys.n, P, best);
+            if (tuned) *tuned += 1;
+        }
+        return KRY_OK;
+    });
+}
+
+kry_status kry_tune_choice(const char* kernel, int64_t n, int32_t runs, int32_t* found, int32_t* a, int32_t* b,
+                           double* us) {
+    return guarded("kry_tune_choice", [&]() -> kry_status {
+        if (!kernel || !found) return fail(KRY_EINVAL, "kernel and found must not be NULL");
+        TuneChoice c{};
+        *found = tune_lookup(kernel, n, runs, &c) ? 1 : 0;
+        if (a) *a = c.a;
+        if (b) *b = c.b;
+        if (us) *us = c.us;
+        return KRY_OK;
+    });
+}
+
+void kry_tune_clear(void) {
+    guarded_void([&] { tune_clear(); });
 }
 
 void kry_plan_destroy(kry_plan_t* plan) {

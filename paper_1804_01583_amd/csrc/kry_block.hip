@@ -78,11 +78,11 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict
     if (block_done(B)) return;
     const int c = threadIdx.x & 15;
     const int grp = threadIdx.x >> 4;
-    // a short contiguous range of rows per workgroup, workgroups in row
-    // order: the rows in flight on the whole chip stay within a narrow band,
-    // so the rows a stencil row gathers one plane ahead are read again while
-    // they still sit in the MALL; groups take the range's rows in turn
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    // a contiguous range of rows per workgroup, ranges in workgroup order
+    // (the rows in flight on the whole chip stay within a narrow band) or
+    // XCD-contiguous (each XCD walks its own part of the rows); groups take
+    // the range's rows in turn.  Each row's sum is the same either way.
+    const int64_t r0 = (int64_t)(B.spmm_xcd ? logical_block((int)gridDim.x) : (int)blockIdx.x) * rows_per_block;
     const int64_t r1 = min(n, r0 + rows_per_block);
     const int64_t stride = kBlock / 16;
     const int64_t last = n - 1;
@@ -419,12 +419,14 @@ hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void*
 }
 
 hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, const BlockArgs& B, hipStream_t s) {
-    // 64 rows per workgroup (4 per group of 16 lanes).  Measured on the
-    // 10^7-row convection-diffusion system, FP64: 2098 us per launch at 64 or
-    // 256 rows, 2178 us at 1024, 2275 us at 16, and 2341 us with ~4096
-    // workgroups of 2442 rows each mapped XCD-contiguously.
-    const int64_t rpb = 64;
-    const int64_t grid = (B.n + rpb - 1) / rpb;
+    // by default 64 rows per workgroup (4 per group of 16 lanes) in
+    // workgroup order.  Measured on the 10^7-row convection-diffusion
+    // system, FP64: 2098 us per launch at 64 or 256 rows, 2178 us at 1024,
+    // 2275 us at 16, and 2341 us with ~4096 workgroups of 2442 rows each
+    // mapped XCD-contiguously.  The tuner may choose others.
+    const int64_t rpb = B.spmm_rows > 0 ? B.spmm_rows : 64;
+    int64_t grid = (B.n + rpb - 1) / rpb;
+    if (B.spmm_xcd) grid = (grid + 7) / 8 * 8;      // the XCD map takes a multiple of 8
     if (f32)
         hipLaunchKernelGGL(k_bspmm<float>, dim3((unsigned)grid), dim3(kBlock), 0, s, A,
                            static_cast<const float*>(V), static_cast<float*>(W), B.n, rpb, B);

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 #include <cstdint>
 
 namespace kry {
@@ -243,6 +245,16 @@ struct BlockStart {
     int32_t p;
 };
 
+// ---- launch choices that leave results unchanged (kry_tune.cpp) ------------
+struct TuneChoice {
+    int32_t a = 0, b = 0;    // kernel-specific: bspmm (rows per workgroup, XCD map); lz1_march (non-temporal, -)
+    double us = 0.0;         // the measured time per launch
+};
+bool tune_lookup(const std::string& kernel, int64_t n, int32_t runs, TuneChoice* out);
+void tune_store(const std::string& kernel, int64_t n, int32_t runs, const TuneChoice& c);
+void tune_clear();
+std::string tune_device_tag();
+
 struct BlockArgs {
     int64_t n;
     int32_t p;                   // real columns of this block run
@@ -259,6 +271,8 @@ struct BlockArgs {
     int32_t* state;              // [0] done, [1] blocks formed, [2] non-finite
     const double* anorm;         // ||A||_inf on the device
     double tau_scale;            // breakdown when R_cc <= tau_scale * ||A||_inf
+    int32_t spmm_rows;           // rows per workgroup of the block mat-vec (0: the default)
+    int32_t spmm_xcd;            // 1: row ranges XCD-contiguous, 0: in workgroup order
 };
 
 hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void* V, int64_t n, hipStream_t s);
@@ -345,8 +359,9 @@ hipError_t launch_lz1_stencil(int P, int O, const StencilArgs& S, const double* 
 // grid lz1_march_blocks(ny, nz, P) ((y, z) tiles, also the count of its
 // partials; the most for P = 8); C u_j then comes from launch_lz1_proj
 int32_t lz1_march_blocks(int64_t ny, int64_t nz, int P);
+// nt: pair stores non-temporal (1) or plain (0); the values are the same
 hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
-                            const Lz1Args& Z, int j, hipStream_t s);
+                            const Lz1Args& Z, int j, hipStream_t s, int nt = 1);
 hipError_t launch_lz1_proj(int P, int O, const double* x, const SegTable& T, int32_t oset0, const BatchArgs& B,
                            int j, hipStream_t s);
 // after iteration k (j = k + 1): alpha_k and stage k (beta_k) from the last

@@ -778,14 +778,18 @@ void launch_march_t(const StencilArgs& S, const double* xin, double* xout, const
 }
 
 hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
-                            const Lz1Args& Z, int j, hipStream_t s) {
+                            const Lz1Args& Z, int j, hipStream_t s, int nt) {
     const int nb = lz1_march_blocks(S.ny, S.nz, P);
     const int tz = (int)lz1_tiles_z(S.nz);
-    switch (P) {
-        case 1: launch_march_t<1, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 2: launch_march_t<2, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 4: launch_march_t<4, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 8: launch_march_t<8, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
+    switch (P * 2 + (nt ? 1 : 0)) {
+        case 3: launch_march_t<1, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 2: launch_march_t<1, false, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 5: launch_march_t<2, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 4: launch_march_t<2, false, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 9: launch_march_t<4, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 8: launch_march_t<4, false, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 17: launch_march_t<8, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 16: launch_march_t<8, false, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

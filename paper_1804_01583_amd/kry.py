@@ -3,7 +3,8 @@ every step of the verification path runs in the library's HIP kernels.
 
 The functions keep the C names (kry_plan, kry_plan_create, kry_verify_noalloc, kry_project_expm,
 kry_check_box_safety, kry_footprint, kry_plan_workspace, kry_plan_runs, kry_plan_krylov,
-kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_destroy, kry_matrix_create,
+kry_plan_block, kry_plan_set_error_target, kry_plan_error, kry_plan_autotune, kry_tune_choice, kry_tune_clear,
+kry_plan_destroy, kry_matrix_create,
 kry_matrix_bytes, kry_matrix_destroy).  ``Plan`` is a small owner object that keeps the device
 tensors a plan borrows alive and destroys the plan when it is dropped.
 """
@@ -102,6 +103,11 @@ def _load():
     lib.kry_plan_set_error_target.argtypes = [P, ct.c_double]
     lib.kry_plan_set_graph.argtypes = [P, ct.c_int32]
     lib.kry_plan_error.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
+    lib.kry_plan_autotune.argtypes = [P, ct.c_int32, ct.POINTER(ct.c_int32)]
+    lib.kry_tune_choice.argtypes = [ct.c_char_p, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_int32),
+                                    ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_double)]
+    lib.kry_tune_clear.argtypes = []
+    lib.kry_tune_clear.restype = None
     lib.kry_matrix_create.argtypes = [ct.POINTER(KrySystem), ct.c_int32, P, ct.POINTER(P)]
     lib.kry_matrix_bytes.argtypes = [P, ct.POINTER(ct.c_size_t)]
     lib.kry_matrix_destroy.argtypes = [P]
@@ -116,7 +122,7 @@ def _load():
               "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_check_box_subset",
               "kry_footprint", "kry_plan_workspace", "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target",
               "kry_plan_set_graph", "kry_plan_error", "kry_matrix_create", "kry_matrix_bytes", "kry_profile_enable",
-              "kry_profile_reset", "kry_profile_read"):
+              "kry_profile_reset", "kry_profile_read", "kry_plan_autotune", "kry_tune_choice"):
         getattr(lib, f).restype = ct.c_int
     return lib
 
@@ -126,7 +132,7 @@ lib = _load()
 EXPORTED = ["kry_plan", "kry_plan_create", "kry_verify_noalloc", "kry_plan_create_transposed", "kry_footprint_transposed",
             "kry_project_expm", "kry_check_lp_safety", "kry_check_box_safety", "kry_check_box_subset",
             "kry_footprint", "kry_plan_workspace", "kry_plan_runs", "kry_plan_krylov", "kry_plan_block", "kry_plan_set_error_target", "kry_plan_set_graph",
-            "kry_plan_error",
+            "kry_plan_error", "kry_plan_autotune", "kry_tune_choice", "kry_tune_clear",
             "kry_plan_destroy", "kry_matrix_create", "kry_matrix_bytes", "kry_matrix_destroy", "kry_last_error",
             "kry_profile_enable", "kry_profile_reset", "kry_profile_read", "kry_profile_names"]
 
@@ -312,6 +318,24 @@ def kry_plan_set_error_target(plan: int, eps: float):
 
 def kry_plan_set_graph(plan: int, on: bool):
     _check(lib.kry_plan_set_graph(plan, 1 if on else 0))
+
+
+def kry_plan_autotune(plan: int, reps: int = 5) -> int:
+    """kry_plan_autotune: kernels tuned for this plan's shape."""
+    tuned = ct.c_int32()
+    _check(lib.kry_plan_autotune(plan, reps, ct.byref(tuned)))
+    return tuned.value
+
+
+def kry_tune_choice(kernel: str, n: int, runs: int):
+    """The stored choice (a, b, microseconds) or None."""
+    found, a, b, us = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_double()
+    _check(lib.kry_tune_choice(kernel.encode(), n, runs, ct.byref(found), ct.byref(a), ct.byref(b), ct.byref(us)))
+    return (a.value, b.value, us.value) if found.value else None
+
+
+def kry_tune_clear():
+    lib.kry_tune_clear()
 
 
 def kry_plan_error(plan: int, run: int):
@@ -566,6 +590,10 @@ class Plan:
     def set_error_target(self, eps: float):
         """Error-controlled Krylov dimension (see kry_plan_set_error_target)."""
         kry_plan_set_error_target(self.handle, eps)
+
+    def autotune(self, reps: int = 5) -> int:
+        """kry_plan_autotune: kernels tuned (choices that change no value)."""
+        return kry_plan_autotune(self.handle, reps)
 
     def error(self, run: int):
         """(k_used, bound) of a run after project_expm."""

@@ -286,3 +286,20 @@ def test_kry_plan_validates_before_device_work():
         with pytest.raises(kry.KryError) as ei:
             kry.kry_plan(s, [g], None, o_rows, k, 0.1, steps)
         assert ei.value.status == kry.KRY_EINVAL
+
+
+def test_tune_cache_file_round_trip(tmp_path, monkeypatch):
+    # the tuner's table is read from the KRY_TUNE_CACHE file (one entry per
+    # line: device kernel n runs a b microseconds); without a GPU the device
+    # tag is "unknown"
+    from paper_1804_01583_amd import kry
+    path = tmp_path / "tune.txt"
+    path.write_text("unknown bspmm 1000 16 128 1 55.5\nunknown lz1_march 4096 2 0 0 12.25\nnot a line\n")
+    monkeypatch.setenv("KRY_TUNE_CACHE", str(path))
+    kry.kry_tune_clear()
+    assert kry.kry_tune_choice("bspmm", 1000, 16) == (128, 1, 55.5)
+    assert kry.kry_tune_choice("lz1_march", 4096, 2) == (0, 0, 12.25)
+    assert kry.kry_tune_choice("bspmm", 1001, 16) is None
+    monkeypatch.delenv("KRY_TUNE_CACHE")
+    kry.kry_tune_clear()
+    assert kry.kry_tune_choice("bspmm", 1000, 16) is None
