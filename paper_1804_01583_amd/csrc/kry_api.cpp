@@ -132,7 +132,7 @@ Profiler& prof() {
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
     "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp,"
-    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_stage";
+    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_sets,wide_stage";
 
 // Runs `launch` bracketed by events when profiling is on.  The sliced-ELL
 // mat-vec and the one-pass step's kernels take the events into their own
@@ -356,7 +356,7 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     }
     if (wide_rows > 0) {
         Y.wpw = take((size_t)nruns * wide_rows * k * sizeof(double));
-        Y.wseg = take((size_t)std::max<int64_t>(wide_segs, 1) * kMaxP * sizeof(double));
+        Y.wseg = take((size_t)k * std::max<int64_t>(wide_segs, 1) * kMaxP * sizeof(double));   // per step
         Y.wpow = take((size_t)nruns * Y.B * kMaxK1 * kMaxK1 * sizeof(double));
         Y.wanch = take((size_t)nruns * Y.nanch * kMaxK1 * sizeof(double));
     }
@@ -1418,9 +1418,7 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         // wide transposed plan: E^T u_{j+1} once u_{j+1} is formed (j = 0: the start)
         auto wide_proj = [&](const void* x, int j) {
             return timed("wide_proj", s, [&] {
-                return launch_wide_proj(P, f32, x, plan->T, plan->wset0, plan->ncols, plan->wseg0, plan->wnseg,
-                                        plan->at<double>(Y.wseg), plan->at<double>(Y.wpw), r0, P, plan->ncols,
-                                        plan->k, j, s);
+                return launch_wide_proj(P, f32, x, plan->T, plan->wseg0, plan->wnseg, plan->at<double>(Y.wseg), j, s);
             });
         };
         if (plan->wide) {
@@ -1526,6 +1524,14 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         // dimension from the device (the largest stop of its runs)
         e = timed("finish", s, [&] { return launch_finish(P, plan->o, onepass ? B_fin : B, plan->k, s); });
         if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("finish: ") + hipGetErrorString(e));
+        if (plan->wide) {
+            e = timed("wide_sets", s, [&] {
+                return launch_wide_sets(P, plan->T, plan->wset0, plan->ncols, plan->wseg0, plan->wnseg,
+                                        plan->at<double>(Y.wseg), plan->at<double>(Y.wpw), r0, P, plan->ncols, plan->k,
+                                        plan->k, s);
+            });
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("wide projection: ") + hipGetErrorString(e));
+        }
         r0 += P;
     }
     if (plan->wide) {

@@ -299,22 +299,64 @@ __device__ __forceinline__ void check_range(const CheckArgs& C, int64_t s, int q
     }
 }
 
+// The same sums over many columns by a whole wavefront: lane l takes the
+// columns l, l + 64, ... in order, then the lanes are added by a fixed
+// butterfly; every lane ends with the result.
+__device__ __forceinline__ void check_range_wave(const CheckArgs& C, int64_t s, int q, double& mid, double& rad) {
+    const int lane = threadIdx.x & 63;
+    double m0 = 0.0, r0 = 0.0;
+    for (int r = lane; r < C.nruns; r += 64) {
+        const double m = check_entry(C, s, q, r);
+        const int c = check_col(C, r);
+        m0 = fma(m, C.zc[c], m0);
+        r0 = fma(fabs(m), C.radius[c], r0);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        m0 += __shfl_xor(m0, off, 64);
+        r0 += __shfl_xor(r0, off, 64);
+    }
+    mid = m0;
+    rad = r0;
+}
+
+// Plans with more than this many checked columns sum each range with a
+// wavefront (check_range_wave), WIDE below; fewer with one thread.
+constexpr int kWideCheck = 64;
+constexpr int kWideEntries = 16;   // (step, row) entries per wavefront in the wide form
+
 // a9, part 1: each block finds the first violated (step, row) among its
-// entries (step-major order) and whether a non-finite range was met.
+// entries (step-major order) and whether a non-finite range was met.  WIDE:
+// each wavefront takes kWideEntries consecutive entries.
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_check_blocks(CheckArgs C) {
     __shared__ long long s_min[kBlock / 64];
     __shared__ int s_bad[kBlock / 64];
     const int64_t total = (C.steps + 1) * C.o;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     long long best = total;
     int bad = 0;
-    if (e < total) {
-        const int64_t s = e / C.o;
-        const int q = (int)(e % C.o);
-        double mid = 0.0, rad = 0.0;
-        check_range(C, s, q, mid, rad);
-        if (!isfinite(mid) || !isfinite(rad)) bad = 1;
-        else if ((mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q])) best = e;
+    if constexpr (WIDE) {
+        const int64_t e0 = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kWideEntries;
+        for (int i = 0; i < kWideEntries && best == total; ++i) {
+            const int64_t e = e0 + i;
+            if (e >= total) break;
+            const int64_t s = e / C.o;
+            const int q = (int)(e % C.o);
+            double mid, rad;
+            check_range_wave(C, s, q, mid, rad);
+            if (!isfinite(mid) || !isfinite(rad)) bad = 1;
+            else if ((mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q])) best = e;
+        }
+    } else {
+        const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (e < total) {
+            const int64_t s = e / C.o;
+            const int q = (int)(e % C.o);
+            double mid = 0.0, rad = 0.0;
+            check_range(C, s, q, mid, rad);
+            if (!isfinite(mid) || !isfinite(rad)) bad = 1;
+            else if ((mid - rad <= C.uhi[q]) && (mid + rad >= C.ulo[q])) best = e;
+        }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -334,10 +376,14 @@ __global__ __launch_bounds__(kBlock) void k_check_blocks(CheckArgs C) {
     }
 }
 
-// a9, part 2: the first violation over all blocks and its counter-example.
+// a9, part 2: the first violation over all blocks and its counter-example
+// (WIDE: the range by wavefront 0, the counter-example's columns by every
+// thread).
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_check_final(CheckArgs C, int nb) {
     __shared__ double s_min[kBlock / 64];
     __shared__ double s_bad[kBlock / 64];
+    __shared__ double s_sol[4];   // lam, dir, mid, rad
     const double total = (double)((C.steps + 1) * C.o);
     double best = total, bad = 0.0;
     for (int b = threadIdx.x; b < nb; b += kBlock) {
@@ -351,37 +397,53 @@ __global__ __launch_bounds__(kBlock) void k_check_final(CheckArgs C, int nb) {
     }
     if ((threadIdx.x & 63) == 0) { s_min[threadIdx.x >> 6] = best; s_bad[threadIdx.x >> 6] = bad; }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int w = 1; w < kBlock / 64; ++w) {
+    for (int w = 0; w < kBlock / 64; ++w) {
         best = fmin(best, s_min[w]);
         bad = fmax(bad, s_bad[w]);
     }
     double* out = C.verdict;
-    out[5] = bad > 0.0 ? 4.0 : 0.0;    // KRY_ENUMERIC
     if (best >= total) {
-        out[0] = -1.0; out[1] = -1.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
-        for (int r = 0; r < C.nruns; ++r) out[6 + r] = C.zc[check_col(C, r)];
+        if (threadIdx.x == 0) {
+            out[5] = bad > 0.0 ? 4.0 : 0.0;    // KRY_ENUMERIC
+            out[0] = -1.0; out[1] = -1.0; out[2] = 0.0; out[3] = 0.0; out[4] = 0.0;
+        }
+        for (int r = threadIdx.x; r < C.nruns; r += kBlock) out[6 + r] = C.zc[check_col(C, r)];
         return;
     }
     const int64_t e = (int64_t)best;
     const int64_t s = e / C.o;
     const int q = (int)(e % C.o);
-    double mid = 0.0, rad = 0.0;
-    check_range(C, s, q, mid, rad);
+    if constexpr (WIDE) {
+        if (threadIdx.x < 64) {
+            double mid, rad;
+            check_range_wave(C, s, q, mid, rad);
+            if (threadIdx.x == 0) { s_sol[2] = mid; s_sol[3] = rad; }
+        }
+    } else if (threadIdx.x == 0) {
+        double mid = 0.0, rad = 0.0;
+        check_range(C, s, q, mid, rad);
+        s_sol[2] = mid;
+        s_sol[3] = rad;
+    }
+    __syncthreads();
+    const double mid = s_sol[2], rad = s_sol[3];
     double lam = 0.0, dir = 0.0;
     if (mid < C.ulo[q]) { lam = (C.ulo[q] - mid) / rad; dir = 1.0; }
     else if (mid > C.uhi[q]) { lam = (mid - C.uhi[q]) / rad; dir = -1.0; }
-    for (int r = 0; r < C.nruns; ++r) {
+    for (int r = threadIdx.x; r < C.nruns; r += kBlock) {
         const double m = check_entry(C, s, q, r);
         const int c = check_col(C, r);
         const double sg = (m > 0.0) ? 1.0 : ((m < 0.0) ? -1.0 : 0.0);
         out[6 + r] = C.zc[c] + dir * lam * sg * C.radius[c];
     }
-    out[0] = (double)s;
-    out[1] = (double)q;
-    out[2] = mid + dir * lam * rad;
-    out[3] = mid - rad;
-    out[4] = mid + rad;
+    if (threadIdx.x == 0) {
+        out[5] = bad > 0.0 ? 4.0 : 0.0;    // KRY_ENUMERIC
+        out[0] = (double)s;
+        out[1] = (double)q;
+        out[2] = mid + dir * lam * rad;
+        out[3] = mid - rad;
+        out[4] = mid + rad;
+    }
 }
 
 }  // namespace
@@ -406,14 +468,22 @@ hipError_t launch_assemble(const AssembleArgs& A, hipStream_t s) {
     return hipGetLastError();
 }
 
-int check_blocks(int64_t steps, int32_t o) { return (int)(((steps + 1) * o + kBlock - 1) / kBlock); }
+// blocks of the check's first kernel (the wide form's count, the larger)
+int check_blocks(int64_t steps, int32_t o) {
+    const int64_t per = (int64_t)(kBlock / 64) * kWideEntries;
+    return (int)(((steps + 1) * o + per - 1) / per);
+}
 
 hipError_t launch_check(const CheckArgs& C, hipStream_t s) {
-    const int nb = check_blocks(C.steps, C.o);
-    hipLaunchKernelGGL(k_check_blocks, dim3(nb), dim3(kBlock), 0, s, C);
+    const bool wide = C.nruns > kWideCheck;
+    const int64_t total = (C.steps + 1) * C.o;
+    const int nb = wide ? check_blocks(C.steps, C.o) : (int)((total + kBlock - 1) / kBlock);
+    if (wide) hipLaunchKernelGGL(k_check_blocks<true>, dim3(nb), dim3(kBlock), 0, s, C);
+    else hipLaunchKernelGGL(k_check_blocks<false>, dim3(nb), dim3(kBlock), 0, s, C);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_check_final, dim3(1), dim3(kBlock), 0, s, C, nb);
+    if (wide) hipLaunchKernelGGL(k_check_final<true>, dim3(1), dim3(kBlock), 0, s, C, nb);
+    else hipLaunchKernelGGL(k_check_final<false>, dim3(1), dim3(kBlock), 0, s, C, nb);
     return hipGetLastError();
 }
 

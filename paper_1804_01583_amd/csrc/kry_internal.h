@@ -168,12 +168,15 @@ struct WideArgs {
     int32_t o_out, ncols;
 };
 hipError_t wide_prepare();
-// Pw[run0 + p][c][j] for the P runs of a batch from their vectors x ([n][P]):
-// segments g0 .. g0 + ng - 1 (those of sets set0 .. set0 + nsets - 1) summed
-// into segsum ([ng][P]), then per set in order
-hipError_t launch_wide_proj(int P, bool f32, const void* x, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0,
-                            int32_t ng, double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw,
-                            int32_t ldk, int32_t j, hipStream_t s);
+// Step j of a batch of P runs (vectors x, [n][P]): segments g0 .. g0 + ng - 1
+// of the wide rows summed into segsum[j] ([k][ng][P]).  After the batch:
+// Pw[run0 + p][c][j] for every row c < nsets and step j < kdone, the row's
+// segments added in order.
+hipError_t launch_wide_proj(int P, bool f32, const void* x, const SegTable& T, int32_t g0, int32_t ng,
+                            double* segsum, int32_t j, hipStream_t s);
+hipError_t launch_wide_sets(int P, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0, int32_t ng,
+                            const double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw, int32_t ldk,
+                            int32_t kdone, hipStream_t s);
 hipError_t launch_wide_stage(const WideArgs& W, int32_t nruns, int64_t steps, hipStream_t s);
 
 constexpr int kMaxCheckCols = 64;   // columns of a check over part of the basis

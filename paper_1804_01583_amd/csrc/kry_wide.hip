@@ -6,9 +6,10 @@
 // rows) and the per-run LDS chains.
 //
 // Projection: after each Krylov vector u_{j+1} is formed, every segment of
-// the initial-space rows is summed by one wavefront (k_wseg), then the
-// segments of each row are added in their order (k_wset): Pw[run][c][j] =
-// E_c^T u_{j+1}, unscaled (v_{j+1} = sigma_{j+1} u_{j+1}).
+// the initial-space rows is summed by one wavefront (k_wseg, into the
+// step's slice of the segment sums); after the batch's last step one launch
+// adds the segments of each row in their order for every step (k_wset):
+// Pw[run][c][j] = E_c^T u_{j+1}, unscaled (v_{j+1} = sigma_{j+1} u_{j+1}).
 //
 // Small stage, per run (as the oracle states it): the matrix
 //     M = H                          (no forcing), or
@@ -67,19 +68,23 @@ __global__ __launch_bounds__(kBlock) void k_wseg(const E* __restrict__ x, SegTab
     }
 }
 
-// Pw[(run0 + p) ncw + c][j] = the segments of row c added in order; one
-// thread per (row, run) of the batch, nreal runs of it real.
+// Pw[(run0 + p) ncw + c][j] = the segments of row c added in order, for
+// every step j < kdone of the batch at once (segsum: [kdone][ng][P]); one
+// thread per (row, step, run), nreal runs of the batch real.
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_wset(SegTable T, int32_t set0, int32_t nsets, int32_t g0,
+__global__ __launch_bounds__(kBlock) void k_wset(SegTable T, int32_t set0, int32_t nsets, int32_t g0, int32_t ng,
                                                  const double* __restrict__ segsum, double* __restrict__ Pw,
-                                                 int32_t run0, int32_t nreal, int32_t ncw, int32_t ldk, int32_t j) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= nsets * P) return;
-    const int c = t / P, p = t % P;
+                                                 int32_t run0, int32_t nreal, int32_t ncw, int32_t ldk, int32_t kdone) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)nsets * kdone * P) return;
+    const int p = (int)(t % P);
+    const int j = (int)((t / P) % kdone);
+    const int c = (int)(t / ((int64_t)P * kdone));
     if (p >= nreal) return;
     const int32_t s = set0 + c;
+    const double* sj = segsum + (int64_t)j * ng * P;
     double acc = 0.0;
-    for (int32_t g = T.set_begin[s]; g < T.set_begin[s + 1]; ++g) acc += segsum[(int64_t)(g - g0) * P + p];
+    for (int32_t g = T.set_begin[s]; g < T.set_begin[s + 1]; ++g) acc += sj[(int64_t)(g - g0) * P + p];
     Pw[((int64_t)(run0 + p) * ncw + c) * ldk + j] = acc;
 }
 
@@ -236,11 +241,9 @@ hipError_t wide_prepare() {
 }
 
 template <typename E>
-static hipError_t launch_wproj_e(int P, const void* x, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0,
-                                 int32_t ng, double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw,
-                                 int32_t ldk, int32_t j, hipStream_t s) {
+static hipError_t launch_wseg_e(int P, const void* x, const SegTable& T, int32_t g0, int32_t ng, double* segsum,
+                                hipStream_t s) {
     const int wb = (int)std::min<int64_t>(4096, ((int64_t)ng + kBlock / 64 - 1) / (kBlock / 64));
-    const int sb = (nsets * P + kBlock - 1) / kBlock;
     const E* xe = static_cast<const E*>(x);
     switch (P) {
         case 1: hipLaunchKernelGGL((k_wseg<E, 1>), dim3(wb), dim3(kBlock), 0, s, xe, T, g0, ng, segsum); break;
@@ -249,24 +252,30 @@ static hipError_t launch_wproj_e(int P, const void* x, const SegTable& T, int32_
         case 8: hipLaunchKernelGGL((k_wseg<E, 8>), dim3(wb), dim3(kBlock), 0, s, xe, T, g0, ng, segsum); break;
         default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    switch (P) {
-        case 1: hipLaunchKernelGGL((k_wset<1>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, segsum, Pw, run0, nreal, ncw, ldk, j); break;
-        case 2: hipLaunchKernelGGL((k_wset<2>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, segsum, Pw, run0, nreal, ncw, ldk, j); break;
-        case 4: hipLaunchKernelGGL((k_wset<4>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, segsum, Pw, run0, nreal, ncw, ldk, j); break;
-        case 8: hipLaunchKernelGGL((k_wset<8>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, segsum, Pw, run0, nreal, ncw, ldk, j); break;
-        default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
-hipError_t launch_wide_proj(int P, bool f32, const void* x, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0,
-                            int32_t ng, double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw,
-                            int32_t ldk, int32_t j, hipStream_t s) {
-    if (ng <= 0 || nsets <= 0) return hipSuccess;
-    return f32 ? launch_wproj_e<float>(P, x, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, j, s)
-               : launch_wproj_e<double>(P, x, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, j, s);
+hipError_t launch_wide_proj(int P, bool f32, const void* x, const SegTable& T, int32_t g0, int32_t ng,
+                            double* segsum, int32_t j, hipStream_t s) {
+    if (ng <= 0) return hipSuccess;
+    double* sj = segsum + (int64_t)j * ng * P;
+    return f32 ? launch_wseg_e<float>(P, x, T, g0, ng, sj, s) : launch_wseg_e<double>(P, x, T, g0, ng, sj, s);
+}
+
+hipError_t launch_wide_sets(int P, const SegTable& T, int32_t set0, int32_t nsets, int32_t g0, int32_t ng,
+                            const double* segsum, double* Pw, int32_t run0, int32_t nreal, int32_t ncw, int32_t ldk,
+                            int32_t kdone, hipStream_t s) {
+    if (nsets <= 0 || kdone <= 0) return hipSuccess;
+    const int64_t total = (int64_t)nsets * kdone * P;
+    const unsigned sb = (unsigned)((total + kBlock - 1) / kBlock);
+    switch (P) {
+        case 1: hipLaunchKernelGGL((k_wset<1>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, kdone); break;
+        case 2: hipLaunchKernelGGL((k_wset<2>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, kdone); break;
+        case 4: hipLaunchKernelGGL((k_wset<4>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, kdone); break;
+        case 8: hipLaunchKernelGGL((k_wset<8>), dim3(sb), dim3(kBlock), 0, s, T, set0, nsets, g0, ng, segsum, Pw, run0, nreal, ncw, ldk, kdone); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_wide_stage(const WideArgs& W, int32_t nruns, int64_t steps, hipStream_t s) {

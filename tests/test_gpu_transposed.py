@@ -244,3 +244,8 @@ def test_wide_matches_the_forward_route_on_the_verdict():
     scale = np.abs(fb).max()
     assert np.abs(t["basis"] - fb).max() <= 1e-10 * scale
     assert t["verdict"]["first_step"] == fv["first_step"] == 56
+    # the check over 258 columns (one wavefront per range) and its
+    # counter-example against the oracle's
+    ref = OT.verify_transposed(q)
+    assert_verdict_parity(t["verdict"], ref["verdict"], ref["basis"])
+    np.testing.assert_allclose(fv["z"], ref["verdict"]["z"], rtol=1e-8, atol=1e-10)
