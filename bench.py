@@ -140,15 +140,15 @@ def main():
         p = W.heat1d()
     elif args.workload == "heat3d_paper":
         # the paper's heat benchmark (Section 5.3): up to 160^3 as CSR with its
-        # error-controlled k (target 1e-6); larger grids matrix-free at the
-        # paper's k = 5932 (the error control holds k <= 2048)
+        # error-controlled k (target 1e-6); larger grids matrix-free, at the
+        # paper's k = 5932, or with --error-target by the bound up to k = 8192
         m = args.m or 100
         if m <= 160:
             p = W.heat3d_paper(m=m)
             if not args.error_target:
                 args.error_target = 1e-6
         else:
-            p = W.heat3d_paper_stencil(m=m, k=args.k or 5932)
+            p = W.heat3d_paper_stencil(m=m, k=args.k or (8192 if args.error_target else 5932))
     elif args.workload == "heat3d_many_inputs":
         p = W.heat3d_many_inputs(m=args.m or 100)
     elif args.workload == "heat3d_many_gens":

@@ -486,6 +486,7 @@ kry_status prepare_device() {
         err = expm_prepare();
         if (err == hipSuccess) err = errctl_prepare();
         if (err == hipSuccess) err = wide_prepare();
+        if (err == hipSuccess) err = big_prepare();
     });
     if (err != hipSuccess) return fail(KRY_EDEVICE, std::string("expm LDS setup: ") + hipGetErrorString(err));
     return KRY_OK;
@@ -574,6 +575,10 @@ struct kry_plan {
     int64_t twopass_redone = 0;    // batches the one-pass step handed back (cancellation)
     hipEvent_t flag_ev = nullptr;
     double lam_plus = 0.0;    // max(0, Gershgorin bound of lambda_max of the symmetric part of A)
+    // Lanczos error control past kBigFrom: eigenvalues, weights and pivots
+    // of the parallel eigen-solve (allocated with the error target)
+    char* big_mem = nullptr;
+    BigErrArgs big{};
 
     void* vec(int i) { return ws + Y.vec + (size_t)i * sys.n * Y.pmax * Y.esize; }
     float* vals32() { return reinterpret_cast<float*>(ws + Y.vals32); }
@@ -1502,7 +1507,10 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
             if (plan->err_eps > 0.0 && j == next_check) {
                 next_check = (int)std::ceil(1.1 * (double)next_check);
                 e = timed("errctl", s, [&] { return launch_record_stage(P, B, j, s); });
+                const bool big = lanczos && plan->big_mem &&
+                                 (j > kBigFrom || env_int("KRY_ERRCTL_BIG", 0) == 1);
                 if (e == hipSuccess) e = timed("errctl", s, [&] {
+                    if (big) return launch_lemma1_big(P, B, X, j, plan->big, s);
                     return lanczos ? launch_lemma1(P, B, X, j, s)
                                    : launch_lemma1_hess(P, B, X, j, X.flags + kMaxP + 1, s);
                 });
@@ -1987,7 +1995,7 @@ kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps) {
             return fail(KRY_ENOTSUP, "the error-controlled Krylov dimension is built for the forward route");
         if (eps > 0.0 && plan->graph_on)
             return fail(KRY_ENOTSUP, "the error control polls the device between launches: not in graph mode");
-        if (eps > 0.0 && plan->k > kMaxKE) return fail(KRY_ENOTSUP, "the error control holds k <= 2048");
+        if (eps > 0.0 && plan->k > kMaxKP) return fail(KRY_ENOTSUP, "the error control holds k <= 8192");
         if (eps > 0.0 && arnoldi && plan->k > kMaxK)
             return fail(KRY_ENOTSUP, "the Arnoldi error control holds k <= 56 (its exponentials sit in LDS)");
         if (eps == 0.0) {
@@ -1996,6 +2004,23 @@ kry_status kry_plan_set_error_target(kry_plan_t* plan, double eps) {
         }
         if (!plan->hflags) KRY_HIP(hipHostMalloc((void**)&plan->hflags, kMaxP * sizeof(double), hipHostMallocDefault));
         if (!plan->flag_ev) KRY_HIP(hipEventCreateWithFlags(&plan->flag_ev, hipEventDisableTiming));
+        if (!arnoldi && !plan->big_mem && (plan->k > kBigFrom || env_int("KRY_ERRCTL_BIG", 0) == 1)) {
+            // theta and w per run, and the pivots of up to `chunk` eigenvalues at once
+            BigErrArgs G{};
+            G.ld = plan->k;
+            G.chunk = std::min<int32_t>(plan->k, 512);
+            const size_t runs = (size_t)plan->Y.pmax;
+            const size_t bytes = runs * G.ld * (2 + (size_t)G.chunk) * sizeof(double);
+            void* mem = nullptr;
+            if (device_alloc(&mem, bytes) != hipSuccess)
+                return fail(KRY_ENOMEM, "error control: no device memory for the eigen-solve (" +
+                                            std::to_string(bytes) + " bytes)");
+            plan->big_mem = static_cast<char*>(mem);
+            G.theta = reinterpret_cast<double*>(plan->big_mem);
+            G.w = G.theta + runs * G.ld;
+            G.work = G.w + runs * G.ld;
+            plan->big = G;
+        }
         // lambda_max of the symmetric part of A, bounded by Gershgorin
         double lam;
         const Layout& Y = plan->Y;
@@ -2299,6 +2324,10 @@ void kry_plan_destroy(kry_plan_t* plan) {
         if (!plan) return;
         if (plan->flag_ev || (plan->owns_ws && plan->ws)) (void)hipStreamSynchronize(plan->stream);
         if (plan->owns_ws && plan->ws) (void)hipFree(plan->ws);
+        if (plan->big_mem) {
+            (void)hipStreamSynchronize(plan->stream);
+            (void)hipFree(plan->big_mem);
+        }
         if (plan->lp_mem) {
             (void)hipStreamSynchronize(plan->stream);
             (void)hipFree(plan->lp_mem);

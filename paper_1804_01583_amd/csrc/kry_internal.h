@@ -223,6 +223,18 @@ struct ErrArgs {
     int hess;                // T's diagonal from the Hessenberg store (stored-basis Lanczos)
 };
 hipError_t launch_record_stage(int P, const BatchArgs& B, int j, hipStream_t s);
+// Lanczos error control at large k (kry_errbig.hip): per run of the batch,
+// theta [ld] and w [ld] (eigenvalues of T_j and q_{1,i} q_{j,i}), work
+// [ld][chunk] (pivots of the eigenvalues in flight); j <= ld.
+constexpr int kBigFrom = 128;       // checkpoints past this k take the parallel eigen-solve
+struct BigErrArgs {
+    double* theta;
+    double* w;
+    double* work;
+    int32_t ld, chunk;
+};
+hipError_t big_prepare();
+hipError_t launch_lemma1_big(int P, const BatchArgs& B, const ErrArgs& X, int j, const BigErrArgs& G, hipStream_t s);
 hipError_t launch_lemma1(int P, const BatchArgs& B, const ErrArgs& X, int j, hipStream_t s);
 hipError_t launch_row_gersh(const CsrArgs& A, int64_t n, double* partials, int32_t nblocks, int64_t rows_per_block,
                             double* out, hipStream_t s);

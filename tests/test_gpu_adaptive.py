@@ -219,3 +219,40 @@ def test_arnoldi_on_a_symmetric_system_stops_with_lanczos():
     assert [e[0] for e in ea] == [e[0] for e in el]
     for (_, a), (_, b) in zip(ea, el):
         assert abs(a - b) <= 1e-6 * b
+
+
+# ---------------------------------------------------------------------------
+# Large Krylov dimensions: the parallel eigen-solve (bisection, twisted
+# factorisation) that checkpoints past 128 take
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["heat3d", "shifted"])
+def test_parallel_eigensolve_at_every_checkpoint(case):
+    # forced for every checkpoint (KRY_ERRCTL_BIG=1): the same stops and
+    # bounds as the oracle's LAPACK route, as the serial QL gives them
+    require_gpu()
+    from tests.test_gpu_onepass import env
+    if case == "heat3d":
+        p = W.small_heat3d(m=10, k=56, steps=100)
+        eps = 1e-9
+    else:
+        p = W.random_symmetric(n=400, ngen=4, o=2, k=40, steps=50, dt=0.05, seed=21, affine=True, center=True)
+        diag = p.colidx == np.repeat(np.arange(p.n), np.diff(p.rowptr))
+        p.vals = p.vals + 1.2 * diag
+        eps = 1e-7
+    with env(KRY_ERRCTL_BIG=1):
+        _run(p, eps)
+
+
+def test_stop_past_2048():
+    # 1D heat, n = 10^5, a 50-cell start, horizon 8e-6: the bound first
+    # drops below 1e-6 at k = 2283 (the oracle's stop)
+    require_gpu()
+    import math
+    n = 100_000
+    p = W.heat1d(n=n, k=2600, steps=2, dt=4e-6)      # few steps: the oracle exponentiates each at k = 2283
+    p.gens = [W.Generator(W.segments_from_ranges([(n // 3, n // 3 + 50)], 1.0), 1.0, 0.1)]
+    p.C = [W.segments_from_ranges([(n // 2 - 10, n // 2 + 10)], 0.05)]
+    p.unsafe = np.array([[math.inf, math.inf]])
+    errs, ref = _run(p, 1e-6, method=kry.KRY_LANCZOS_PLAIN)
+    assert errs[0][0] == ref["runs"][0]["k_stop"] > 2048
