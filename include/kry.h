@@ -420,8 +420,10 @@ kry_status kry_plan_krylov(kry_plan_t* plan, int32_t run, int32_t* k_eff, double
  * integral uses a fixed composite 8-point Gauss-Legendre rule on
  * [0, tau 2^-40] and on [tau 2^-(i+1), tau 2^-i], i < 40, each cut into 8
  * equal parts.  eps = 0 turns the control off (the default: every run uses
- * k).  Lanczos plans (symmetric A, H_j tridiagonal: Algorithm 4), k <= 2048,
- * and Arnoldi plans (Algorithm 2, H_j upper Hessenberg), k <= 56; other
+ * k).  Lanczos plans (symmetric A, H_j tridiagonal: Algorithm 4), k <= 8192
+ * (past k = 128 the eigen-solve of T_j runs in parallel on device memory
+ * this call allocates: runs per batch x k x 514 doubles), and Arnoldi plans
+ * (Algorithm 2, H_j upper Hessenberg), k <= 56; other
  * methods, the transposed route and graph mode give KRY_ENOTSUP, and so does
  * a CSR matrix with a column of more than 2^24 entries (Arnoldi).  Waits for
  * the plan's stream for a CSR system. */
