@@ -43,6 +43,14 @@ namespace {
 
 using namespace dev;
 
+// A double that every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // |u_j|^2 expanded below this fraction of |r_j|^2 is not trusted
 constexpr double kLz1Guard = 1e-4;
 
@@ -76,27 +84,6 @@ __device__ __forceinline__ void store_pair(double* __restrict__ X, int64_t row, 
         t[P + p] = r[p];
     }
     store_row<double, 2 * P>(X, row, t);
-}
-
-// store_pair with non-temporal stores: the marching kernel's output stream
-// bypasses the L2 it needs for the rows other tiles read again (on the 1000^3
-// system the launch took 13.8 ms this way against 15.2 ms with plain stores)
-template <int P>
-__device__ __forceinline__ void store_pair_nt(double* __restrict__ X, int64_t row, const double (&u)[P],
-                                              const double (&r)[P]) {
-    typedef double v2d __attribute__((ext_vector_type(2)));
-    v2d* q = reinterpret_cast<v2d*>(X + row * 2 * P);
-    double t[2 * P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        t[p] = u[p];
-        t[P + p] = r[p];
-    }
-#pragma unroll
-    for (int h = 0; h < P; ++h) {
-        v2d v = {t[2 * h], t[2 * h + 1]};
-        __builtin_nontemporal_store(v, q + h);
-    }
 }
 
 // u_j from the pair (u_{j-1}, r_j): the same expression everywhere it is
@@ -439,8 +426,13 @@ __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const dou
 // holds row y0 + w, lanes 1..60 its owned columns, lanes 0 and 61 the columns
 // just outside (loaded, never stored; lanes 62 and 63 idle).  60 owned
 // columns of pairs are whole 128-byte lines for one to eight runs, so no
-// line is written by two tiles (62 columns wrote 10 % more than the pair
-// buffer on the 1000^3 system, 60 write it once).  Per x step every wave forms its
+// line is written by two tiles.  Each lane's pair is 2P doubles, which one
+// store instruction cannot cover: written straight from the lanes, every
+// instruction would fill only part of each line (on the 1000^3 system 6.6 %
+// more than the pair buffer reached HBM that way).  The owned pairs are
+// therefore staged in LDS and stored as consecutive 16-byte pieces, so each
+// instruction writes whole contiguous lines (the buffer is then written
+// once).  Per x step every wave forms its
 // plane-x values, the z neighbours come from the adjacent lanes (wave
 // shuffles), the y neighbours from the adjacent waves through LDS (one
 // barrier per step, double-buffered), and only the tile's first and last wave
@@ -448,12 +440,16 @@ __global__ __launch_bounds__(kBlock) void k_lz1_stencil(StencilArgs S, const dou
 // x + 1 stay in registers (x + 2 loaded one step ahead, four planes rotated
 // by unrolling); the outer rows of plane x + 1 are loaded during step x.  Each
 // element of the pair buffer is then read from memory about once per
-// iteration (rows beyond a tile twice).
+// iteration (rows beyond a tile twice).  Tiles are numbered y first, so the
+// workgroups an XCD runs at once hold neighbouring rows of the same columns
+// (2.3 % faster on the 1000^3 system than z first).
 constexpr int kMarchOwn = 60;                          // z columns a wavefront owns
 
 
 struct Lz1Col {
     int64_t col, sx, dout;     // dout: offset of this wave's outer row (y - 1 for wave 0, y + 1 for the last)
+    int64_t base;              // the wave's first owned column at plane 0
+    int nchunk;                // 16-byte pieces of the wave's owned columns (0 past the grid)
     bool own, yl, yh, zl, zh, outer;
 };
 
@@ -470,7 +466,8 @@ __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Co
                                                const double (&r0)[P], const double (&up)[P],
                                                const double (&rp)[P], double (&un)[P], double (&rn)[P],
                                                const double (&ou)[P], const double (&orr)[P], double (&nou)[P],
-                                               double (&nor)[P], double* lds, double (&pa)[3 * P]) {
+                                               double (&nor)[P], double* lds, double (&pa)[3 * P],
+                                               double* stage) {
     const int64_t r = ix * M.sx + M.col;
     load_pair<P>(FIRST, xin, ix + 2 < S.nx ? r + 2 * M.sx : r, un, rn);
     if (M.outer) load_pair<P>(FIRST, xin, (ix + 1 < S.nx ? r + M.sx : r) + M.dout, nou, nor);
@@ -509,9 +506,38 @@ __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Co
             pa[2 * P + p] = fma(x0[p], x0[p], pa[2 * P + p]);
         }
     }
-    if (M.own) {
-        if constexpr (NT) store_pair_nt<P>(xout, r, x0, y);
-        else store_pair<P>(xout, r, x0, y);
+    {
+        // the wave's owned pairs go through LDS so that every store
+        // instruction writes whole contiguous lines
+        double* st = stage + wave * 64 * 2 * P;
+        if (M.own) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                st[(lane - 1) * 2 * P + p] = x0[p];
+                st[(lane - 1) * 2 * P + P + p] = y[p];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        typedef double v2d __attribute__((ext_vector_type(2)));
+        v2d* q = reinterpret_cast<v2d*>(xout + (ix * M.sx + M.base) * 2 * P);
+        constexpr int NQ = (kMarchOwn * P + 63) / 64;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int c = i * 64 + lane;
+            if (c < M.nchunk) {
+                const v2d v = *reinterpret_cast<const v2d*>(st + 2 * c);
+                // non-temporal: the output stream bypasses the L2 that the
+                // rows other tiles read again need (13.8 ms against 15.2 ms
+                // with plain stores on the 1000^3 system, before staging)
+                if constexpr (NT) __builtin_nontemporal_store(v, q + c);
+                else q[c] = v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) fm[p] = x0[p];   // plane x - 1 of the next step
@@ -520,15 +546,17 @@ __device__ __forceinline__ void lz1_march_step(const StencilArgs& S, const Lz1Co
 template <int P, bool NT, int TY, bool FIRST>
 __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const double* __restrict__ xin,
                                                        double* __restrict__ xout, BatchArgs B, Lz1Args Z, int nb,
-                                                       int tiles_z, int j) {
+                                                       int j) {
     constexpr int NTH = TY * 64;
     __shared__ double s_lds[TY * 3 * P];
     __shared__ double s_tot[3 * P];
     __shared__ double s_nrm[P];
     __shared__ double s_plane[2 * TY * 64 * P];
+    __shared__ double s_stage[TY * 64 * 2 * P];
     const int cb = logical_block(nb, B.xcd_map);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t ty = cb / tiles_z, tz = cb % tiles_z;
+    const int tiles_y = (int)((S.ny + TY - 1) / TY);
+    const int64_t ty = cb % tiles_y, tz = cb / tiles_y;
     const int64_t iy = ty * TY + wave;
     const int64_t iz = tz * kMarchOwn + lane - 1;
     const int64_t ncol = S.ny * S.nz;
@@ -545,6 +573,8 @@ __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const doub
     M.zh = iz < S.nz - 1;
     M.outer = (wave == 0 && M.yl) || (wave == TY - 1 && M.yh);
     M.dout = wave == 0 ? -S.nz : S.nz;
+    M.base = cy * S.nz + tz * kMarchOwn;
+    M.nchunk = iy < S.ny ? (int)min((int64_t)kMarchOwn, S.nz - tz * kMarchOwn) * P : 0;
     double fm[P], ua[P], ra[P], ub[P], rb[P], uc[P], rc[P];
     double oa_u[P], oa_r[P], ob_u[P], ob_r[P];
 #pragma unroll
@@ -554,19 +584,26 @@ __global__ __launch_bounds__(TY * 64) void k_lz1_march(StencilArgs S, const doub
     if (M.outer) load_pair<P>(FIRST, xin, M.col + M.dout, oa_u, oa_r);
     double coef[P], sig[P], cprev[P];
     lz1_prologue<P, NTH>(B, Z, j, true, s_lds, s_tot, s_nrm, coef, sig, cprev);
+    // the same for every thread: keep them in scalar registers
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        coef[p] = wave_uniform(coef[p]);
+        sig[p] = wave_uniform(sig[p]);
+        cprev[p] = wave_uniform(cprev[p]);
+    }
     double pa[3 * P];
 #pragma unroll
     for (int i = 0; i < 3 * P; ++i) pa[i] = 0.0;
     // three pair slots rotate by unrolling: planes x, x + 1 and the x + 2 load
     for (int64_t ix = 0; ix < S.nx; ix += 3) {
         lz1_march_step<P, NT, TY, FIRST>(S, M, ix, xin, xout, coef, sig, cprev, fm, ua, ra, ub, rb, uc, rc, oa_u,
-                                  oa_r, ob_u, ob_r, s_plane, pa);
+                                  oa_r, ob_u, ob_r, s_plane, pa, s_stage);
         if (ix + 1 >= S.nx) break;
         lz1_march_step<P, NT, TY, FIRST>(S, M, ix + 1, xin, xout, coef, sig, cprev, fm, ub, rb, uc, rc, ua, ra,
-                                  ob_u, ob_r, oa_u, oa_r, s_plane, pa);
+                                  ob_u, ob_r, oa_u, oa_r, s_plane, pa, s_stage);
         if (ix + 2 >= S.nx) break;
         lz1_march_step<P, NT, TY, FIRST>(S, M, ix + 2, xin, xout, coef, sig, cprev, fm, uc, rc, ua, ra, ub, rb,
-                                  oa_u, oa_r, ob_u, ob_r, s_plane, pa);
+                                  oa_u, oa_r, ob_u, ob_r, s_plane, pa, s_stage);
         // (the outer-row slots alternate with odd period: swap them for the next round)
         if (ix + 3 >= S.nx) break;
 #pragma unroll
@@ -756,15 +793,15 @@ int32_t lz1_march_blocks(int64_t ny, int64_t nz, int P) {
 
 template <int P, bool NT, int TY, bool FIRST>
 void launch_march_f(const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B, const Lz1Args& Z,
-                    int nb, int tz, int j, hipStream_t s) {
+                    int nb, int j, hipStream_t s) {
     const ExtEvents ev = *ext_events();
     if (ev.start != nullptr) {
         hipExtLaunchKernelGGL(k_lz1_march<P, NT, TY, FIRST>, dim3(nb), dim3(TY * 64), 0, s, ev.start, ev.stop, 0, S,
-                              xin, xout, B, Z, nb, tz, j);
+                              xin, xout, B, Z, nb, j);
         ext_events()->start = nullptr;   // consumed
     } else {
         hipLaunchKernelGGL((k_lz1_march<P, NT, TY, FIRST>), dim3(nb), dim3(TY * 64), 0, s, S, xin, xout, B, Z, nb,
-                           tz, j);
+                           j);
     }
 }
 
@@ -772,24 +809,23 @@ void launch_march_f(const StencilArgs& S, const double* xin, double* xout, const
 // pair path's registers as they are
 template <int P, bool NT, int TY>
 void launch_march_t(const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B, const Lz1Args& Z,
-                    int nb, int tz, int j, hipStream_t s) {
-    if (j == 1) launch_march_f<P, NT, TY, true>(S, xin, xout, B, Z, nb, tz, j, s);
-    else launch_march_f<P, NT, TY, false>(S, xin, xout, B, Z, nb, tz, j, s);
+                    int nb, int j, hipStream_t s) {
+    if (j == 1) launch_march_f<P, NT, TY, true>(S, xin, xout, B, Z, nb, j, s);
+    else launch_march_f<P, NT, TY, false>(S, xin, xout, B, Z, nb, j, s);
 }
 
 hipError_t launch_lz1_march(int P, const StencilArgs& S, const double* xin, double* xout, const BatchArgs& B,
                             const Lz1Args& Z, int j, hipStream_t s, int nt) {
     const int nb = lz1_march_blocks(S.ny, S.nz, P);
-    const int tz = (int)lz1_tiles_z(S.nz);
     switch (P * 2 + (nt ? 1 : 0)) {
-        case 3: launch_march_t<1, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 2: launch_march_t<1, false, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 5: launch_march_t<2, true, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 4: launch_march_t<2, false, 16>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 9: launch_march_t<4, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 8: launch_march_t<4, false, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 17: launch_march_t<8, true, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
-        case 16: launch_march_t<8, false, 4>(S, xin, xout, B, Z, nb, tz, j, s); break;
+        case 3: launch_march_t<1, true, 16>(S, xin, xout, B, Z, nb, j, s); break;
+        case 2: launch_march_t<1, false, 16>(S, xin, xout, B, Z, nb, j, s); break;
+        case 5: launch_march_t<2, true, 16>(S, xin, xout, B, Z, nb, j, s); break;
+        case 4: launch_march_t<2, false, 16>(S, xin, xout, B, Z, nb, j, s); break;
+        case 9: launch_march_t<4, true, 4>(S, xin, xout, B, Z, nb, j, s); break;
+        case 8: launch_march_t<4, false, 4>(S, xin, xout, B, Z, nb, j, s); break;
+        case 17: launch_march_t<8, true, 4>(S, xin, xout, B, Z, nb, j, s); break;
+        case 16: launch_march_t<8, false, 4>(S, xin, xout, B, Z, nb, j, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
