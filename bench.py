@@ -441,11 +441,17 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         tot = {"bspmm": 0.0, "bgram": 0.0, "bupdate": 0.0, "bstart": blk}
         tot["bgram"] += 2 * blk                      # start block CholQR2: Gram of V_1
         tot["bupdate"] += 2 * 2 * blk                # and V_1 R^{-1} in place
+        # the default step takes the second Gram-Schmidt pass from the Gram
+        # matrix (one pass over V_1..V_j and W for the coefficients, one for
+        # the update); KRY_BLOCK_GS=0 makes both passes over the basis.  The
+        # conditional second pass (only after a projection that cancels) is
+        # not counted: its launches return at once otherwise.
+        passes = (1,) if os.environ.get("KRY_BLOCK_GS", "1") != "0" else (1, 2)
         for j in range(1, k + 1):
             tot["bspmm"] += mat + 2 * blk            # A, V_j streamed once, W written
-            for ps in (1, 2):
+            for ps in passes:
                 tot["bgram"] += (j + 1) * blk        # V_1..V_j and W
-                if j < k or ps == 1:
+                if j < k or (ps == 1 and len(passes) == 2):
                     tot["bupdate"] += (j + 2) * blk  # V_1..V_j, W read, W written
             if j < k:
                 tot["bgram"] += 2 * blk

@@ -179,6 +179,12 @@ int env_int(const char* name, int dflt) {
     return std::atoi(v);
 }
 
+double env_double(const char* name, double dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::strtod(v, nullptr);
+}
+
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Row partition: depends on n only (never on the batch), so results of a run
@@ -254,7 +260,8 @@ struct Layout {
     int32_t bw = 0;       // block width (generators per block run)
     int32_t brb = 0;      // row blocks of the Gram kernel
     int64_t brows = 0;    // rows per Gram row block
-    size_t bvec = 0, bgpart = 0, bcoef = 0, bH = 0, bP = 0, bR0 = 0, brfirst = 0, bstate = 0, bppart = 0, bS0 = 0,
+    size_t bvec = 0, bgpart = 0, bgpart2 = 0, bsbuf = 0, bG = 0, bcoef = 0, bH = 0, bP = 0, bR0 = 0, brfirst = 0,
+           bstate = 0, bppart = 0, bS0 = 0,
            bdense = 0;
     int32_t esize;        // bytes per stored vector element: 8 (FP64) or 4 (FP32 basis)
     bool dense_runs = false;   // k > 56: each run's exponential in the dense stage
@@ -376,12 +383,15 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
         const int64_t m = (int64_t)kBW * k;
         Y.bvec = take((size_t)(k + 1) * n * kBW * Y.esize);
         Y.bgpart = take((size_t)(k + 1) * Y.brb * 256 * sizeof(double));
+        Y.bgpart2 = take((size_t)(k + 1) * Y.brb * 256 * sizeof(double));
+        Y.bsbuf = take((size_t)(k + 1) * 256 * sizeof(double));
+        Y.bG = take((size_t)m * m * sizeof(double));
         Y.bcoef = take((size_t)(k + 1) * 256 * sizeof(double));
         Y.bH = take((size_t)(m + kBW) * m * sizeof(double));
         Y.bP = take((size_t)o * (m + kBW) * sizeof(double));
         Y.bR0 = take(256 * sizeof(double));
         Y.brfirst = take(256 * sizeof(double));
-        Y.bstate = take(4 * sizeof(int32_t));
+        Y.bstate = take(8 * sizeof(int32_t));
         Y.bppart = take((size_t)o * kProjGroups * kBW * sizeof(double));
         Y.bS0 = take((size_t)m * kBW * sizeof(double));
         Y.bdense = take(dense_workspace_doubles((int)m, o, kBW, Y.B, Y.nanch) * sizeof(double));
@@ -1134,6 +1144,9 @@ kry_status finish_projection(kry_plan_t* plan, double* basis_out) {
 
 // Block Arnoldi for the generator columns, bw at a time (the block form of
 // Algorithm 1 with CGS2 and CholQR2), then the dense stage for each block run.
+// By default the second Gram-Schmidt pass is taken from the Gram matrix of
+// the stored blocks (one pass over the basis for the coefficients, one for
+// the update); KRY_BLOCK_GS=0 runs both passes over the basis.
 kry_status project_block(kry_plan_t* plan) {
     const Layout& Y = plan->Y;
     const int64_t n = plan->sys.n;
@@ -1147,7 +1160,14 @@ kry_status project_block(kry_plan_t* plan) {
     B.n = n;
     B.rb = Y.brb;
     B.rows_per_rb = Y.brows;
+    const bool gs1 = env_int("KRY_BLOCK_GS", 1) != 0;
     B.gpart = plan->at<double>(Y.bgpart);
+    B.gpart2 = plan->at<double>(Y.bgpart2);
+    B.sbuf = plan->at<double>(Y.bsbuf);
+    B.G = plan->at<double>(Y.bG);
+    // a column that keeps less than 1e-3 of its norm through the projection
+    // gets the plain second pass (KRY_BLOCK_REORTH2 sets the squared ratio)
+    B.reorth2 = gs1 ? env_double("KRY_BLOCK_REORTH2", 1e-6) : 0.0;
     B.coef = plan->at<double>(Y.bcoef);
     B.H = plan->at<double>(Y.bH);
     B.ldh = (int32_t)m_max;
@@ -1182,7 +1202,7 @@ kry_status project_block(kry_plan_t* plan) {
         BlockStart S{};
         for (int c = 0; c < kBW; ++c) S.set[c] = c < p ? plan->gen_set[b0 + c] : -1;
         S.p = p;
-        KRY_STEP("bfill", launch_fill_i32(B.state, 4, 0, s));
+        KRY_STEP("bfill", launch_fill_i32(B.state, 8, 0, s));
         KRY_STEP("bfill", launch_fill(B.H, (m_max + kBW) * m_max, 0.0, s));
         KRY_STEP("bfill", launch_fill(B.P, (int64_t)o * (m_max + kBW), 0.0, s));
         KRY_STEP("bfill", launch_fill(plan->at<double>(Y.bS0), m_max * kBW, 0.0, s));
@@ -1196,21 +1216,44 @@ kry_status project_block(kry_plan_t* plan) {
         }
         KRY_STEP("bproj", launch_bproj(f32, plan->T, plan->oset0, o, V(0), plan->at<double>(Y.bppart), kProjGroups, 0,
                                        B, s));
+        BlockArgs Bc = B;                   // launches that run only when a second pass is wanted
+        Bc.cond = B.state + 4;
         for (int j = 1; j <= k; ++j) {
             void* W = V(j);
             KRY_STEP("bspmm", launch_bspmm(f32, A, V(j - 1), W, B, s));
-            // CGS2 against V_1..V_j; the last step only needs the coefficients
-            for (int pass = 1; pass <= 2; ++pass) {
-                KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, j, W, B, s));
-                KRY_STEP("bgram_red", launch_bgram_red(B, j, j, pass - 1, s));
-                if (j < k || pass == 1) KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, j, W, 1, B, s));
+            if (gs1) {
+                // V_i^T W, V_i^T V_j (i <= j) and W^T W in one pass (W is
+                // stored right after V_j); H_{:,j} from them; the last step
+                // only needs the coefficients
+                KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, j + 1, W, B, s, V(j - 1)));
+                KRY_STEP("bgram_red", launch_bgram_red(B, j + 1, j, 3, s));
+                KRY_STEP("bcorr", launch_bcorr(B, j, s));
+                if (j == k) break;
+                KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, j, W, 1, B, s));
+            } else {
+                // CGS2 against V_1..V_j; the last step only needs the coefficients
+                for (int pass = 1; pass <= 2; ++pass) {
+                    KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, j, W, B, s));
+                    KRY_STEP("bgram_red", launch_bgram_red(B, j, j, pass - 1, s));
+                    if (j < k || pass == 1) KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, j, W, 1, B, s));
+                }
+                if (j == k) break;
             }
-            if (j == k) break;
             // CholQR2: W = V_{j+1} H_{j+1,j}
             for (int pass = 1; pass <= 2; ++pass) {
                 KRY_STEP("bgram", launch_bgram(f32, W, vstride, 1, W, B, s));
                 KRY_STEP("bgram_red", launch_bgram_red(B, 1, j, 2, s));
                 KRY_STEP("bchol", launch_bchol(B, j, pass, s));
+                if (pass == 1 && gs1) {
+                    // W kept too little of its norm: a plain second pass over
+                    // the basis, then the first factorisation again
+                    KRY_STEP("bgram", launch_bgram(f32, V(0), vstride, j, W, Bc, s));
+                    KRY_STEP("bgram_red", launch_bgram_red(Bc, j, j, 1, s));
+                    KRY_STEP("bupdate", launch_bupdate(f32, V(0), vstride, j, W, 1, Bc, s));
+                    KRY_STEP("bgram", launch_bgram(f32, W, vstride, 1, W, Bc, s));
+                    KRY_STEP("bgram_red", launch_bgram_red(Bc, 1, j, 2, s));
+                    KRY_STEP("bchol", launch_bchol(Bc, j, 1, s));
+                }
                 KRY_STEP("bupdate", launch_bupdate(f32, W, vstride, 1, W, 0, B, s));
             }
             KRY_STEP("bproj", launch_bproj(f32, plan->T, plan->oset0, o, W, plan->at<double>(Y.bppart), kProjGroups,

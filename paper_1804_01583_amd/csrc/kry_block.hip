@@ -7,13 +7,22 @@
 // row of FP64, or 64 bytes of FP32, per grid row), blocks kept for the whole
 // run.  One block step j:
 //   k_bspmm      W = A V_j                               (16 lanes per CSR row)
-//   k_bgram      partials of V_i^T W, i = 1..j           (MFMA f64 16x16x4)
-//   k_bgram_red  H_{i,j} += sum of partials; -H_{i,j} kept for the update
+//   k_bgram      partials of V_i^T W and V_i^T V_j, i = 1..j, and W^T W
+//                (MFMA f64 16x16x4, one pass over the basis)
+//   k_bgram_red  S_i = V_i^T W; block column j of G = V^T V
+//   k_bcorr      H_{:,j} = S + (I - G) S, the classical Gram-Schmidt
+//                coefficients with the second (re-orthogonalising) pass
+//                taken from the Gram matrix instead of a second pass over the
+//                basis; -H_{:,j} kept for the update
 //   k_bupdate    W += sum_i V_i (-H_{i,j})               (MFMA f64 16x16x4)
-//   (the Gram-Schmidt pair runs twice: CGS2)
 //   k_bgram / k_bchol / k_bupdate: CholQR2 of W = V_{j+1} H_{j+1,j} (Gram
-//   matrix, Cholesky in one thread, W R^{-1} in place), twice
+//   matrix, Cholesky in one thread, W R^{-1} in place), twice.  When W lost
+//   most of its norm to the projection (|W_c| below 1e-3 of what it was for
+//   a column c), the first Cholesky step raises a flag and a plain second
+//   Gram-Schmidt pass over the basis runs before the factorisation is redone
+//   (kernels launched with a condition return at once while it is down).
 //   k_bproj      partials of C V_{j+1}                   (only rows inside C's segments)
+// The plain two-pass form (both passes over the basis) stays available.
 // All sums are FP64 and in a fixed order; no atomics.
 //
 // MFMA f64 16x16x4 lane layout (measured on gfx950): A[m][k] is held by lane
@@ -35,7 +44,10 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ bool block_done(const BlockArgs& B) { return B.state[0] != 0; }
+// the run has ended, or the launch carries a condition that is down
+__device__ __forceinline__ bool block_done(const BlockArgs& B) {
+    return B.state[0] != 0 || (B.cond != nullptr && *B.cond == 0);
+}
 
 // ---------------------------------------------------------------------------
 // Start block: column c < p of V_1 (unnormalised) is generator c of the block.
@@ -156,9 +168,10 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(CsrArgs A, const E* __restrict
 // an iteration issues the loads of RS MFMA steps before using them.  Slots
 // past nx re-read X_{nx-1} and are never stored; rows past the block's end
 // read row r0 and are multiplied by zero.
-template <typename E, int NI>
+// TWO: the same partials against a second block Y2 as well (into gpart2).
+template <typename E, int NI, bool TWO>
 __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int64_t xstride, int nx,
-                                                  const E* __restrict__ Y, BlockArgs B) {
+                                                  const E* __restrict__ Y, const E* __restrict__ Y2, BlockArgs B) {
     constexpr int RS = NI <= 4 ? 4 : 2;
     if (block_done(B)) return;
     const int l = threadIdx.x & 63;
@@ -166,22 +179,25 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
     const int64_t r0 = (int64_t)blockIdx.x * B.rows_per_rb;
     const int64_t r1 = min(B.n, r0 + B.rows_per_rb);
     const int col = l & 15, sub = l >> 4;
-    v4d acc[NI];
+    v4d acc[NI], acc2[TWO ? NI : 1];
 #pragma unroll
     for (int u = 0; u < NI; ++u) acc[u] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < (TWO ? NI : 1); ++u) acc2[u] = v4d{0.0, 0.0, 0.0, 0.0};
     const E* Xu[NI];
 #pragma unroll
     for (int u = 0; u < NI; ++u) Xu[u] = X0 + (int64_t)min(wave + 4 * u, nx - 1) * xstride;
     for (int64_t r = r0; r < r1; r += 4 * RS) {
         int64_t rr[RS];
         bool ok[RS];
-        double yb[RS], xa[NI][RS];
+        double yb[RS], yc[RS], xa[NI][RS];
 #pragma unroll
         for (int q = 0; q < RS; ++q) {
             const int64_t row = r + 4 * q + sub;
             ok[q] = row < r1;
             rr[q] = ok[q] ? row : r0;
             yb[q] = (double)Y[rr[q] * kBW + col];
+            if constexpr (TWO) yc[q] = (double)Y2[rr[q] * kBW + col];
         }
 #pragma unroll
         for (int u = 0; u < NI; ++u) {
@@ -193,6 +209,11 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
             const double b = ok[q] ? yb[q] : 0.0;
 #pragma unroll
             for (int u = 0; u < NI; ++u) acc[u] = mfma16(xa[u][q], b, acc[u]);
+            if constexpr (TWO) {
+                const double c = ok[q] ? yc[q] : 0.0;
+#pragma unroll
+                for (int u = 0; u < NI; ++u) acc2[u] = mfma16(xa[u][q], c, acc2[u]);
+            }
         }
     }
 #pragma unroll
@@ -202,6 +223,11 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
         double* out = B.gpart + ((int64_t)i * B.rb + blockIdx.x) * 256;
 #pragma unroll
         for (int q = 0; q < 4; ++q) out[(4 * q + sub) * 16 + col] = acc[u][q];   // D[m][col], m = 4q + sub
+        if constexpr (TWO) {
+            double* out2 = B.gpart2 + ((int64_t)i * B.rb + blockIdx.x) * 256;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out2[(4 * q + sub) * 16 + col] = acc2[u][q];
+        }
     }
 }
 
@@ -209,14 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
 // 16 blockIdx.y .. 16 blockIdx.y + 15: 16 threads per entry take every 16th
 // row block, then their sums are added in order.  mode 0/1: Gram-Schmidt
 // pass 1/2, H_{i,j} = / += result and coef_i = -result; mode 2: Gram matrix
-// into coef_0.
+// into coef_0; mode 3 (the one-pass step, blockIdx.z = 0 / 1): S_i into
+// sbuf, and V_i^T V_j (i < j) into block column j of G and its transpose
+// into block row j.
 __global__ __launch_bounds__(256) void k_bgram_red(BlockArgs B, int j, int mode) {
     if (block_done(B)) return;
     __shared__ double s_sum[256];
     const int i = blockIdx.x;
     const int t = blockIdx.y * 16 + (threadIdx.x & 15);
     const int chunk = threadIdx.x >> 4;
-    const double* part = B.gpart + (int64_t)i * B.rb * 256;
+    const bool second = mode == 3 && blockIdx.z == 1;
+    const double* part = (second ? B.gpart2 : B.gpart) + (int64_t)i * B.rb * 256;
     double s = 0.0;
     for (int b = chunk; b < B.rb; b += 16) s += part[(int64_t)b * 256 + t];
     s_sum[threadIdx.x] = s;
@@ -229,10 +258,51 @@ __global__ __launch_bounds__(256) void k_bgram_red(BlockArgs B, int j, int mode)
         return;
     }
     const int m = t >> 4, c = t & 15;
+    if (mode == 3) {
+        if (!second) {
+            B.sbuf[(int64_t)i * 256 + t] = s;
+        } else if (i < j) {
+            // G[i][j-1] (0-based blocks) = V_i^T V_j; the diagonal block is
+            // written once, as computed
+            const int64_t col = 16 * (j - 1);
+            B.G[(int64_t)(16 * i + m) * B.ldh + col + c] = s;
+            if (i < j - 1) B.G[(col + c) * B.ldh + 16 * i + m] = s;
+        }
+        return;
+    }
     double* h = B.H + (int64_t)(16 * i + m) * B.ldh + 16 * (j - 1) + c;
     if (mode == 0) *h = s;
     else *h += s;
     B.coef[(int64_t)i * 256 + t] = -s;
+}
+
+// Block column j of H for the one-pass step, block i = blockIdx.x < j (entry
+// (a, c) per thread): with S_l = V_l^T W and E = V^T V - I over blocks
+// 1..j,  H_{i,j} = S_i - (E S)_i.  This is the second classical Gram-Schmidt
+// pass, V^T (W - V S) = S - V^T V S, evaluated on the Gram matrix; E S is
+// formed directly (E's diagonal as G_aa - 1) so the small correction keeps
+// its relative accuracy.  coef_i = -H_{i,j} for the update.  Block 0 also
+// lowers the re-orthogonalisation flag of the step.
+__global__ __launch_bounds__(256) void k_bcorr(BlockArgs B, int j) {
+    if (block_done(B)) return;
+    const int i = blockIdx.x, t = threadIdx.x;
+    const int a = t >> 4, c = t & 15;
+    const int64_t row = 16 * i + a;
+    const double* g = B.G + row * B.ldh;
+    double es = 0.0;
+    for (int l = 0; l < j; ++l) {
+        const double* sl = B.sbuf + (int64_t)l * 256;
+#pragma unroll 4
+        for (int b = 0; b < 16; ++b) {
+            const int64_t gc = 16 * l + b;
+            const double e = g[gc] - (gc == row ? 1.0 : 0.0);
+            es = fma(e, sl[b * 16 + c], es);
+        }
+    }
+    const double h = B.sbuf[(int64_t)i * 256 + t] - es;
+    B.H[row * B.ldh + 16 * (j - 1) + c] = h;
+    B.coef[(int64_t)i * 256 + t] = -h;
+    if (i == 0 && t == 0) B.state[4] = 0;
 }
 
 // CholQR step on the Gram matrix G = W^T W in coef_0 (one wave, 16 x 16 in
@@ -258,6 +328,16 @@ __global__ __launch_bounds__(64) void k_bchol(BlockArgs B, int j, int pass) {
     double gmax = 0.0;
     for (int c = 0; c < B.p; ++c) gmax = fmax(gmax, sqrt(fmax(G[c][c], 0.0)));
     const double tau = j == 0 ? B.tau_scale * gmax : B.tau_scale * *B.anorm;
+    // one-pass step: a column that kept less than sqrt(reorth2) of its norm
+    // through the projection asks for a plain second pass (|W_c|^2 before
+    // the projection is W^T W's diagonal in sbuf); the breakdown decision is
+    // then left to the factorisation that follows that pass
+    bool raise = false;
+    if (pass == 1 && j >= 1 && B.cond == nullptr && B.reorth2 > 0.0) {
+        for (int c = 0; c < B.p; ++c)
+            raise = raise || G[c][c] < B.reorth2 * B.sbuf[(int64_t)j * 256 + c * 17];
+    }
+    if (raise && tid == 0) B.state[4] = 1;
     for (int c = 0; c < 16; ++c) {
         // every thread forms the pivot (same operations, same value)
         double d = G[c][c];
@@ -266,7 +346,7 @@ __global__ __launch_bounds__(64) void k_bchol(BlockArgs B, int j, int pass) {
         const double rc = real ? (d > 0.0 ? sqrt(d) : 0.0) : 1.0;
         if (tid == 0 && real) {
             if (!isfinite(d)) s_bad = 2;
-            else if (!(rc > 0.0) || (pass == 1 && !(rc > tau))) s_bad = s_bad ? s_bad : 1;
+            else if (!raise && (!(rc > 0.0) || (pass == 1 && !(rc > tau)))) s_bad = s_bad ? s_bad : 1;
         }
         const double piv = rc > 0.0 ? rc : 1.0;
         if (tid == c) R[c][c] = piv;
@@ -436,39 +516,52 @@ hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, cons
     return hipGetLastError();
 }
 
-template <typename E, int NI>
-hipError_t launch_bgram_t(const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
-                          hipStream_t s) {
-    hipLaunchKernelGGL((k_bgram<E, NI>), dim3(B.rb), dim3(kBlock), 0, s, static_cast<const E*>(X0), xstride, nx,
-                       static_cast<const E*>(Y), B);
+template <typename E, int NI, bool TWO>
+hipError_t launch_bgram_t(const void* X0, int64_t xstride, int nx, const void* Y, const void* Y2,
+                          const BlockArgs& B, hipStream_t s) {
+    hipLaunchKernelGGL((k_bgram<E, NI, TWO>), dim3(B.rb), dim3(kBlock), 0, s, static_cast<const E*>(X0), xstride,
+                       nx, static_cast<const E*>(Y), static_cast<const E*>(Y2), B);
     return hipGetLastError();
 }
 
-template <typename E>
-hipError_t launch_bgram_e(const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
-                          hipStream_t s) {
+template <typename E, bool TWO>
+hipError_t launch_bgram_e(const void* X0, int64_t xstride, int nx, const void* Y, const void* Y2,
+                          const BlockArgs& B, hipStream_t s) {
     switch ((nx + 3) / 4) {
-        case 1: return launch_bgram_t<E, 1>(X0, xstride, nx, Y, B, s);
-        case 2: return launch_bgram_t<E, 2>(X0, xstride, nx, Y, B, s);
-        case 3: return launch_bgram_t<E, 3>(X0, xstride, nx, Y, B, s);
-        case 4: return launch_bgram_t<E, 4>(X0, xstride, nx, Y, B, s);
-        case 5: return launch_bgram_t<E, 5>(X0, xstride, nx, Y, B, s);
-        case 6: return launch_bgram_t<E, 6>(X0, xstride, nx, Y, B, s);
-        case 7: return launch_bgram_t<E, 7>(X0, xstride, nx, Y, B, s);
-        case 8: return launch_bgram_t<E, 8>(X0, xstride, nx, Y, B, s);
-        case 9: return launch_bgram_t<E, 9>(X0, xstride, nx, Y, B, s);
+        case 1: return launch_bgram_t<E, 1, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 2: return launch_bgram_t<E, 2, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 3: return launch_bgram_t<E, 3, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 4: return launch_bgram_t<E, 4, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 5: return launch_bgram_t<E, 5, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 6: return launch_bgram_t<E, 6, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 7: return launch_bgram_t<E, 7, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 8: return launch_bgram_t<E, 8, TWO>(X0, xstride, nx, Y, Y2, B, s);
+        case 9: return launch_bgram_t<E, 9, TWO>(X0, xstride, nx, Y, Y2, B, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
-                        hipStream_t s) {
+                        hipStream_t s, const void* Y2) {
     if (nx < 1 || nx > kMaxKB + 1) return hipErrorInvalidValue;
-    return f32 ? launch_bgram_e<float>(X0, xstride, nx, Y, B, s) : launch_bgram_e<double>(X0, xstride, nx, Y, B, s);
+    if (Y2 != nullptr) {
+        if (B.gpart2 == nullptr) return hipErrorInvalidValue;
+        return f32 ? launch_bgram_e<float, true>(X0, xstride, nx, Y, Y2, B, s)
+                   : launch_bgram_e<double, true>(X0, xstride, nx, Y, Y2, B, s);
+    }
+    return f32 ? launch_bgram_e<float, false>(X0, xstride, nx, Y, Y, B, s)
+               : launch_bgram_e<double, false>(X0, xstride, nx, Y, Y, B, s);
 }
 
 hipError_t launch_bgram_red(const BlockArgs& B, int nx, int j, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_bgram_red, dim3(nx, 16), dim3(256), 0, s, B, j, mode);
+    if (mode == 3 && (B.sbuf == nullptr || B.G == nullptr)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bgram_red, dim3(nx, 16, mode == 3 ? 2 : 1), dim3(256), 0, s, B, j, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_bcorr(const BlockArgs& B, int j, hipStream_t s) {
+    if (B.sbuf == nullptr || B.G == nullptr || j < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bcorr, dim3(j), dim3(256), 0, s, B, j);
     return hipGetLastError();
 }
 

@@ -276,14 +276,19 @@ struct BlockArgs {
     int32_t rb;                  // row blocks of the Gram kernel
     int64_t rows_per_rb;         // rows per row block
     double* gpart;               // [kMaxKB + 1][rb][256] partials of 16 x 16 products
+    double* gpart2;              // the same for the second right-hand side of the one-pass Gram
     double* coef;                // [kMaxKB + 1][256] reduced blocks / update coefficients
+    double* sbuf;                // [kMaxKB + 1][256] S_i = V_i^T W of the one-pass step (last: W^T W)
+    double* G;                   // V^T V of the stored blocks, row-major, ldh columns
+    const int32_t* cond;         // launches with a condition return while *cond == 0 (null: none)
+    double reorth2;              // one-pass step: a plain second pass when |W''_c|^2 < reorth2 |W_c|^2
     double* H;                   // block Hessenberg, row-major, ldh columns
     int32_t ldh;
     double* P;                   // C V, o rows of ldp
     int32_t ldp;
     double* R0;                  // 16 x 16: G = V_1 R0
     double* rfirst;              // 16 x 16: R of the first CholQR pass
-    int32_t* state;              // [0] done, [1] blocks formed, [2] non-finite
+    int32_t* state;              // [0] done, [1] blocks formed, [2] non-finite, [4] second pass wanted
     const double* anorm;         // ||A||_inf on the device
     double tau_scale;            // breakdown when R_cc <= tau_scale * ||A||_inf
     int32_t spmm_rows;           // rows per workgroup of the block mat-vec (0: the default)
@@ -292,10 +297,13 @@ struct BlockArgs {
 
 hipError_t launch_bstart(bool f32, const SegTable& T, const BlockStart& S, void* V, int64_t n, hipStream_t s);
 hipError_t launch_bspmm(bool f32, const CsrArgs& A, const void* V, void* W, const BlockArgs& B, hipStream_t s);
+// Y2 non-null: the partials against Y2 as well (gpart2)
 hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const void* Y, const BlockArgs& B,
-                        hipStream_t s);
-// mode 0 / 1: Gram-Schmidt pass 1 / 2 of block column j; mode 2: Gram matrix
+                        hipStream_t s, const void* Y2 = nullptr);
+// mode 0 / 1: Gram-Schmidt pass 1 / 2 of block column j; mode 2: Gram matrix;
+// mode 3: S and block column j of V^T V for the one-pass step
 hipError_t launch_bgram_red(const BlockArgs& B, int nx, int j, int mode, hipStream_t s);
+hipError_t launch_bcorr(const BlockArgs& B, int j, hipStream_t s);
 hipError_t launch_bchol(const BlockArgs& B, int j, int pass, hipStream_t s);
 hipError_t launch_bupdate(bool f32, const void* X0, int64_t xstride, int nx, void* Y, int accumulate,
                           const BlockArgs& B, hipStream_t s);

@@ -8,7 +8,9 @@ own scale: the columns of a block share one basis, so a column whose output
 on a row is far smaller than another column's is formed by cancellation at
 the larger scale, and both sides can only resolve it to eps times that
 scale."""
+import contextlib
 import math
+import os
 
 import numpy as np
 import pytest
@@ -143,3 +145,75 @@ def test_block_rejects_center_and_forcing():
     with pytest.raises(kry.KryError) as ei:
         gpu_block(prob, 1)
     assert ei.value.args[0].startswith(f"kry status {kry.KRY_ENOTSUP}")
+
+
+@contextlib.contextmanager
+def _env(**kv):
+    old = {k: os.environ.get(k) for k in kv}
+    os.environ.update(kv)
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("precision", [kry.KRY_FP64, kry.KRY_FP32_BASIS])
+def test_block_gram_corrected_pass_against_two_passes(precision):
+    # the second Gram-Schmidt pass from the Gram matrix of the stored blocks
+    # against the plain second pass over the basis, and both against the oracle
+    prob = W.conv_diff3d(12, 12, 14, ngen=16, gen_len=6, o=3, k=10, steps=60, dt=2e-3, seed=11)
+    ref = OB.block_verify(prob, p=16)
+    with _env(KRY_BLOCK_GS="0"):
+        two = gpu_block(prob, 16, precision=precision)
+    one = gpu_block(prob, 16, precision=precision)
+    if precision == kry.KRY_FP64:
+        _compare_blocks(one, ref)
+        assert_block_basis_parity(one["basis"], ref["basis"], 16)
+        d = assert_block_basis_parity(one["basis"], two["basis"], 16, rtol=1e-12)
+    else:
+        anorm = oracle.krylov.inf_norm(oracle.system_matrix(prob))
+        tol = min(1e-4, max(1e-5, 2.0 * 2.0 ** -23 * anorm * prob.steps * prob.dt))
+        assert_block_basis_parity(one["basis"], ref["basis"], 16, rtol=tol)
+        d = assert_block_basis_parity(one["basis"], two["basis"], 16, rtol=tol)
+    print(f"  one-pass against two-pass: {d:.2e}", flush=True)
+
+
+def _near_invariant_problem():
+    # two Dirichlet sine modes plus 5e-6 of a local bump each: the first block
+    # step keeps 8e-5 and 5e-4 of |A V_1| after the projection (far above
+    # breakdown, and far enough that the later directions, which come from
+    # the bumps, are fixed to ~1e-12 by the data)
+    prob = W.heat1d(n=120, k=6, steps=30)
+    n = prob.n
+    x = np.arange(1, n + 1) / (n + 1)
+    gens = []
+    for mode, (a, b) in ((2, (40, 51)), (5, (70, 76))):
+        v = np.sin(mode * math.pi * x)
+        v[a:b] += 5e-6
+        gens.append(W.Generator(W.Segments(np.arange(n), np.arange(n) + 1, v), zc=1.0, radius=0.1))
+    prob.gens = gens
+    prob.C = [W.segments_from_ranges([(30, 50)], 0.05), W.segments_from_ranges([(70, 71)], 1.0)]
+    prob.unsafe = np.array([[math.inf, math.inf]] * 2)
+    return prob
+
+
+def test_block_second_pass_when_the_projection_cancels():
+    prob = _near_invariant_problem()
+    ref = OB.block_verify(prob, p=2)
+    got = gpu_block(prob, 2)
+    _compare_blocks(got, ref)
+    assert_block_basis_parity(got["basis"], ref["basis"], 2)
+    # the plain second pass ran: it adds its (tiny) coefficients to H, so
+    # without it H differs (the outputs, dominated by the sine modes, may not)
+    with _env(KRY_BLOCK_REORTH2="0"):
+        nopass = gpu_block(prob, 2)
+    assert not np.array_equal(got["blocks"][0]["H"], nopass["blocks"][0]["H"])
+    # the conditional launches give the oracle's result when forced every step
+    with _env(KRY_BLOCK_REORTH2="1e300"):
+        always = gpu_block(prob, 2)
+    _compare_blocks(always, ref)
+    assert_block_basis_parity(always["basis"], ref["basis"], 2)
