@@ -231,6 +231,47 @@ __global__ __launch_bounds__(kBlock) void k_bgram(const E* __restrict__ X0, int6
     }
 }
 
+// k_bgram for one block X (the CholQR Gram matrix W^T W, and any nx = 1):
+// the four waves take every fourth group of row steps of the row block
+// instead of one wave holding the only block while the others idle, and
+// their sums are added in wave order through LDS.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_bgram1(const E* __restrict__ X, const E* __restrict__ Y, BlockArgs B) {
+    constexpr int RS = 4;
+    constexpr int NW = kBlock / 64;
+    __shared__ v4d s_acc[NW - 1][64];
+    if (block_done(B)) return;
+    const int l = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * B.rows_per_rb;
+    const int64_t r1 = min(B.n, r0 + B.rows_per_rb);
+    const int col = l & 15, sub = l >> 4;
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0 + (int64_t)wave * 4 * RS; r < r1; r += (int64_t)4 * RS * NW) {
+        int64_t rr[RS];
+        bool ok[RS];
+        double yb[RS], xa[RS];
+#pragma unroll
+        for (int q = 0; q < RS; ++q) {
+            const int64_t row = r + 4 * q + sub;
+            ok[q] = row < r1;
+            rr[q] = ok[q] ? row : r0;
+            yb[q] = (double)Y[rr[q] * kBW + col];
+            xa[q] = (double)X[rr[q] * kBW + col];
+        }
+#pragma unroll
+        for (int q = 0; q < RS; ++q) acc = mfma16(xa[q], ok[q] ? yb[q] : 0.0, acc);
+    }
+    if (wave > 0) s_acc[wave - 1][l] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < NW - 1; ++w) acc += s_acc[w][l];
+    double* out = B.gpart + (int64_t)blockIdx.x * 256;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(4 * q + sub) * 16 + col] = acc[q];   // D[m][col], m = 4q + sub
+}
+
 // Sums the row-block partials of block i = blockIdx.x, entries
 // 16 blockIdx.y .. 16 blockIdx.y + 15: 16 threads per entry take every 16th
 // row block, then their sums are added in order.  mode 0/1: Gram-Schmidt
@@ -548,6 +589,15 @@ hipError_t launch_bgram(bool f32, const void* X0, int64_t xstride, int nx, const
         if (B.gpart2 == nullptr) return hipErrorInvalidValue;
         return f32 ? launch_bgram_e<float, true>(X0, xstride, nx, Y, Y2, B, s)
                    : launch_bgram_e<double, true>(X0, xstride, nx, Y, Y2, B, s);
+    }
+    if (nx == 1) {
+        if (f32)
+            hipLaunchKernelGGL(k_bgram1<float>, dim3(B.rb), dim3(kBlock), 0, s, static_cast<const float*>(X0),
+                               static_cast<const float*>(Y), B);
+        else
+            hipLaunchKernelGGL(k_bgram1<double>, dim3(B.rb), dim3(kBlock), 0, s, static_cast<const double*>(X0),
+                               static_cast<const double*>(Y), B);
+        return hipGetLastError();
     }
     return f32 ? launch_bgram_e<float, false>(X0, xstride, nx, Y, Y, B, s)
                : launch_bgram_e<double, false>(X0, xstride, nx, Y, Y, B, s);
