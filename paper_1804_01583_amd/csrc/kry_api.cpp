@@ -272,6 +272,7 @@ struct Layout {
     bool stored;          // whole basis kept (Arnoldi, or any method in FP32-basis mode)
     bool lz1 = false;     // FP64 three-vector Lanczos: room for the one-pass step (two pair buffers)
     size_t hpart, hcoef, vals32;
+    size_t hpart2 = 0, sraw = 0, gram = 0, guard = 0;   // Arnoldi: the second pass from the Gram matrix
     size_t oflag = 0;     // one-pass step: per-run cancellation flags of a batch
     size_t ap_stride = 0; // doubles between the two ping-pong partial arrays of the one-pass step
     // transposed route with many initial-space rows: E^T u per step, segment
@@ -325,8 +326,14 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.lz1 = (method == KRY_LANCZOS || method == KRY_LANCZOS_PLAIN) && !Y.stored && precision == KRY_FP64;
     Y.nvec = method == KRY_BLOCK_ARNOLDI ? 0 : (Y.stored ? k + 1 : (Y.lz1 ? 4 : 3));
     Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
-    Y.hpart = Y.stored ? take((size_t)k * kMaxP * Y.nblocks * sizeof(double)) : 0;
+    Y.hpart = Y.stored ? take((size_t)(k + 1) * kMaxP * Y.nblocks * sizeof(double)) : 0;
     Y.hcoef = Y.stored ? take((size_t)k * kMaxP * sizeof(double)) : 0;
+    if (method == KRY_ARNOLDI) {
+        Y.hpart2 = take((size_t)(k + 1) * kMaxP * Y.nblocks * sizeof(double));
+        Y.sraw = take((size_t)(k + 1) * kMaxP * sizeof(double));
+        Y.gram = take((size_t)kMaxP * k * k * sizeof(double));
+        Y.guard = take(sizeof(int32_t));
+    }
     Y.vals32 = nnz32 > 0 ? take((size_t)nnz32 * sizeof(float)) : 0;
     // sliced-ELL copy of a CSR matrix: room for the entries plus a quarter
     // for padding (and one slice's worth); a matrix that needs more keeps CSR
@@ -1435,6 +1442,16 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         }
         const bool f32 = plan->f32;
         const bool lanczos = plan->method == KRY_LANCZOS;
+        // Arnoldi takes its second Gram-Schmidt pass from the Gram matrix on
+        // systems of 2^16 rows or more (below, a step is bound by launches,
+        // which this form has more of); KRY_ARN_GS=1 / 0 forces it on / off.
+        // A run whose w keeps less than 1e-3 of its norm through the
+        // projection gets the plain second pass (KRY_ARN_REORTH2: the squared
+        // ratio).
+        const int arn_gs = env_int("KRY_ARN_GS", -1);
+        const bool arn_gram = plan->method == KRY_ARNOLDI && Y.gram != 0 &&
+                              (arn_gs == 1 || (arn_gs != 0 && plan->sys.n >= 65536));
+        const double arn_reorth2 = env_double("KRY_ARN_REORTH2", 1e-6);
         // FP64 three-vector Lanczos on a stencil takes the one-pass step; a
         // batch in which a run's norm expansion cancelled is computed again
         // two-pass.  On a CSR matrix the step gathers two vectors per entry
@@ -1519,7 +1536,36 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
                 });
                 if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("sweep: ") + hipGetErrorString(e));
             }
-            if (Y.stored || !lanczos) {
+            if (!lanczos && arn_gram) {
+                // Arnoldi with the second pass from the Gram matrix: u_i . w,
+                // u_i . u_j (i <= j) and w . w in one pass (w is stored right
+                // after u_j), H_{:,j} = S - (V^T V - I) S, one update; a plain
+                // second pass follows only for a run whose w kept too little
+                // of its norm (the guard)
+                ArnArgs Ar{plan->vec(0), n * Y.pmax, w, plan->hpart(), plan->hcoef(), f32 ? 1 : 0, 0};
+                Ar.hpart2 = plan->at<double>(Y.hpart2);
+                Ar.sraw = plan->at<double>(Y.sraw);
+                Ar.gram = plan->at<double>(Y.gram);
+                Ar.guard = plan->at<int32_t>(Y.guard);
+                Ar.reorth2 = arn_reorth2;
+                e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ar, B, j, s, j + 1, true); });
+                if (e == hipSuccess) e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ar, B, j, 3, s); });
+                if (e == hipSuccess) e = timed("arn_corr", s, [&] { return launch_arn_corr(P, Ar, B, j, s); });
+                if (e == hipSuccess)
+                    e = timed("arn_update", s, [&] {
+                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ar, B, j, 1, s);
+                    });
+                if (e == hipSuccess) e = timed("arn_guard", s, [&] { return launch_arn_guard(P, Ar, B, j, s); });
+                ArnArgs Ac = Ar;
+                Ac.conditional = 1;
+                if (e == hipSuccess) e = timed("arn_dots", s, [&] { return launch_arn_dots(P, Ac, B, j, s); });
+                if (e == hipSuccess) e = timed("arn_reduce", s, [&] { return launch_arn_reduce(P, Ac, B, j, 2, s); });
+                if (e == hipSuccess)
+                    e = timed("arn_update", s, [&] {
+                        return launch_arn_update(P, plan->o, plan->T, plan->oset0, Ac, B, j, 1, s);
+                    });
+                if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("arnoldi: ") + hipGetErrorString(e));
+            } else if (Y.stored || !lanczos) {
                 // Arnoldi: CGS2 against u_1..u_j (Algorithm 1's projection loop, classical
                 // form, twice).  Lanczos with a stored basis: one classical pass over the
                 // three-term result removes what rounding left along u_1..u_j.

@@ -209,6 +209,13 @@ struct ArnArgs {
     double* hcoef;           // [k][kMaxP] coefficients of the current pass (h_i * sigma_i)
     int32_t f32;             // 1: E = float, else double
     int32_t lanczos;         // 1: w is a Lanczos three-term result; H_{j-1,j} and H_{j,j} add beta_{j-1}, alpha_j
+    // the step with the second pass from the Gram matrix (Arnoldi):
+    double* hpart2;          // [k + 1][kMaxP][nblocks] partials of u_i . u_j
+    double* sraw;            // [k + 1][kMaxP] u_i . w (last: w . w)
+    double* gram;            // [kMaxP][k][k] V^T V of the batch's runs (v_i = sigma_i u_i)
+    int32_t* guard;          // 1: a run's w kept too little of its norm; a plain second pass follows
+    int32_t conditional;     // 1: the launch returns at once unless *guard
+    double reorth2;          // the guard: |w''|^2 < reorth2 |w|^2
 };
 constexpr int kArnChunk = 16;    // basis vectors per block of the dot kernel
 
@@ -396,8 +403,16 @@ hipError_t launch_expm_chain(const ExpmArgs& E, int32_t nruns, hipStream_t s);
 int check_blocks(int64_t steps, int32_t o);
 hipError_t launch_assemble(const AssembleArgs& A, hipStream_t s);
 hipError_t launch_check(const CheckArgs& C, hipStream_t s);
-hipError_t launch_arn_dots(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s);
+// nx vectors u_1..u_nx against w; two: against u_j as well (hpart2)
+hipError_t launch_arn_dots(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s, int nx = 0,
+                           bool two = false);
+// pass 1 / 2: H_{:,j} = / += the pass's coefficients; pass 3: u_i . w into
+// sraw and column j of V^T V into gram (i <= j, the one-pass step)
 hipError_t launch_arn_reduce(int P, const ArnArgs& A, const BatchArgs& B, int j, int pass, hipStream_t s);
+// H_{:,j} = S - (V^T V - I) S from sraw and gram; coefficients for the update
+hipError_t launch_arn_corr(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s);
+// raises *guard when a run's |w''|^2 (stage j partials) < reorth2 (w . w)
+hipError_t launch_arn_guard(int P, const ArnArgs& A, const BatchArgs& B, int j, hipStream_t s);
 hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
                              const BatchArgs& B, int j, int last, hipStream_t s);
 

@@ -1,5 +1,8 @@
 """Shared helpers of the GPU tests: run a problem through the C ABI and
 compare with the oracle."""
+import contextlib
+import os
+
 import numpy as np
 import pytest
 
@@ -72,3 +75,19 @@ def assert_verdict_parity(gv, ov, basis, tol=1e-9):
     assert (gv["first_step"], gv["row"]) == (ov["first_step"], ov["row"])
     np.testing.assert_allclose(gv["z"], ov["z"], rtol=1e-8, atol=1e-10)
     assert abs(gv["y"] - ov["y"]) <= tol * max(1.0, abs(ov["y"]))
+
+
+@contextlib.contextmanager
+def env(**kv):
+    """Environment variables set for the duration of a with-block (the
+    library reads its switches when a plan projects)."""
+    old = {k: os.environ.get(k) for k in kv}
+    os.environ.update(kv)
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

@@ -10,7 +10,7 @@ import torch  # noqa: F401  (imported at collection so the first test does not p
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import (assert_basis_parity, assert_krylov_parity, assert_verdict_parity, gpu_verify,
+from tests.gpu_helpers import (assert_basis_parity, assert_krylov_parity, assert_verdict_parity, env, gpu_verify,
                                require_gpu)
 
 pytestmark = pytest.mark.gpu
@@ -81,3 +81,65 @@ def test_nilpotent_terminates_exactly():
     t = 5 * 0.3
     exact = np.array([t**j / math.factorial(j) for j in range(n)])
     np.testing.assert_allclose(got["basis"][5, :, 0], exact, rtol=1e-12)
+
+
+@pytest.mark.parametrize("precision", [0, 1])   # KRY_FP64, KRY_FP32_BASIS
+def test_gram_corrected_second_pass_against_two_passes(precision):
+    # the second Gram-Schmidt pass from the Gram matrix (forced on at this
+    # size) against the plain second pass over the basis, and the oracle
+    p = W.conv_diff3d(12, 12, 14, ngen=3, gen_len=40, o=3, k=20, steps=120, dt=1e-3, seed=3)
+    with env(KRY_ARN_GS="0"):
+        two = gpu_verify(p, precision=precision)
+    with env(KRY_ARN_GS="1"):
+        if precision == 0:
+            one, _ = _compare(p)
+        else:
+            one = gpu_verify(p, precision=precision)
+    if precision == 0:
+        d = assert_basis_parity(one["basis"], two["basis"], rtol=1e-12)
+    else:
+        ref = oracle.verify(p)
+        anorm = oracle.krylov.inf_norm(oracle.system_matrix(p))
+        tol = min(1e-4, max(1e-5, 2.0 * 2.0 ** -23 * anorm * p.steps * p.dt))
+        assert_basis_parity(one["basis"], ref["basis"], rtol=tol)
+        d = assert_basis_parity(one["basis"], two["basis"], rtol=tol)
+    print(f"  one Gram pass against two passes: {d:.2e}", flush=True)
+
+
+def test_gram_corrected_pass_is_the_default_on_large_systems():
+    # 41^3 = 68921 rows (>= 2^16): the Gram form without being asked for
+    p = W.conv_diff3d(41, 41, 41, ngen=2, gen_len=300, o=2, k=16, steps=60, dt=1e-3, seed=6)
+    one, _ = _compare(p)
+    with env(KRY_ARN_GS="0"):
+        two = gpu_verify(p)
+    d = assert_basis_parity(one["basis"], two["basis"], rtol=1e-12)
+    assert not all(np.array_equal(a["H"], b["H"]) for a, b in zip(one["runs"], two["runs"]))
+    print(f"  one Gram pass against two passes: {d:.2e}", flush=True)
+
+
+def _near_invariant_heat():
+    # sine mode 5 of the 1D heat operator plus 5e-6 of a local bump: the first
+    # step keeps 8e-5 of |A v_1| after the projection.  (The later directions
+    # come from the bump; two plain CGS2 codes agree on this run to ~1e-11,
+    # while the same bump on mode 2 leaves them 2e-10 apart.)
+    p = W.heat1d(n=120, k=6, steps=30)
+    n = p.n
+    x = np.arange(1, n + 1) / (n + 1)
+    v = np.sin(5 * math.pi * x)
+    v[70:76] += 5e-6
+    p.gens = [W.Generator(W.Segments(np.arange(n), np.arange(n) + 1, v), zc=1.0, radius=0.1)]
+    p.C = [W.segments_from_ranges([(30, 50)], 0.05), W.segments_from_ranges([(70, 71)], 1.0)]
+    p.unsafe = np.array([[math.inf, math.inf]] * 2)
+    return p
+
+
+def test_gram_corrected_pass_guard_runs_the_plain_pass():
+    p = _near_invariant_heat()
+    with env(KRY_ARN_GS="1"):
+        got, _ = _compare(p, oracle_method="arnoldi", method=2)   # KRY_ARNOLDI
+        with env(KRY_ARN_REORTH2="0"):
+            off = gpu_verify(p, method=2)
+        with env(KRY_ARN_REORTH2="1e300"):
+            always, _ = _compare(p, oracle_method="arnoldi", method=2)
+    # the guard's plain pass adds its (tiny) coefficients to H
+    assert not all(np.array_equal(a["H"], b["H"]) for a, b in zip(got["runs"], off["runs"]))

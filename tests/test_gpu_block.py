@@ -8,9 +8,7 @@ own scale: the columns of a block share one basis, so a column whose output
 on a row is far smaller than another column's is formed by cancellation at
 the larger scale, and both sides can only resolve it to eps times that
 scale."""
-import contextlib
 import math
-import os
 
 import numpy as np
 import pytest
@@ -20,7 +18,7 @@ import oracle
 import workloads as W
 from oracle import block as OB
 from paper_1804_01583_amd import kry
-from tests.gpu_helpers import RTOL, assert_basis_parity, gpu_verify, require_gpu
+from tests.gpu_helpers import RTOL, assert_basis_parity, env, gpu_verify, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -147,27 +145,13 @@ def test_block_rejects_center_and_forcing():
     assert ei.value.args[0].startswith(f"kry status {kry.KRY_ENOTSUP}")
 
 
-@contextlib.contextmanager
-def _env(**kv):
-    old = {k: os.environ.get(k) for k in kv}
-    os.environ.update(kv)
-    try:
-        yield
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-
-
 @pytest.mark.parametrize("precision", [kry.KRY_FP64, kry.KRY_FP32_BASIS])
 def test_block_gram_corrected_pass_against_two_passes(precision):
     # the second Gram-Schmidt pass from the Gram matrix of the stored blocks
     # against the plain second pass over the basis, and both against the oracle
     prob = W.conv_diff3d(12, 12, 14, ngen=16, gen_len=6, o=3, k=10, steps=60, dt=2e-3, seed=11)
     ref = OB.block_verify(prob, p=16)
-    with _env(KRY_BLOCK_GS="0"):
+    with env(KRY_BLOCK_GS="0"):
         two = gpu_block(prob, 16, precision=precision)
     one = gpu_block(prob, 16, precision=precision)
     if precision == kry.KRY_FP64:
@@ -209,11 +193,11 @@ def test_block_second_pass_when_the_projection_cancels():
     assert_block_basis_parity(got["basis"], ref["basis"], 2)
     # the plain second pass ran: it adds its (tiny) coefficients to H, so
     # without it H differs (the outputs, dominated by the sine modes, may not)
-    with _env(KRY_BLOCK_REORTH2="0"):
+    with env(KRY_BLOCK_REORTH2="0"):
         nopass = gpu_block(prob, 2)
     assert not np.array_equal(got["blocks"][0]["H"], nopass["blocks"][0]["H"])
     # the conditional launches give the oracle's result when forced every step
-    with _env(KRY_BLOCK_REORTH2="1e300"):
+    with env(KRY_BLOCK_REORTH2="1e300"):
         always = gpu_block(prob, 2)
     _compare_blocks(always, ref)
     assert_block_basis_parity(always["basis"], ref["basis"], 2)
