@@ -409,6 +409,8 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
     else:
         mat = 0                                                   # matrix-free
     lanczos = p.symmetric
+    gs = os.environ.get("KRY_ARN_GS", "-1")
+    arn_twins = 2 if (not lanczos and (gs == "1" or (gs != "0" and n >= 65536))) else 1
     # the sliced-ELL copy: values and int32 columns of the nnz entries, 12
     # bytes of slice offset and width per 64 rows (padding is not counted)
     mat_sell = ((4 if es == 4 else 8) + 4) * nnz + 12 * (-(-n // 64)) if p.kind == "csr" else 0
@@ -419,9 +421,11 @@ def measure(torch, kry, p, dsys, precision, steps, warmup, method=0, error_targe
         "sweep": 3 * vec,                                     # read v_j, w; write w
         "start": vec,                                         # write u_1
         # classical Gram-Schmidt passes over the stored basis, averaged over
-        # iterations j = 1..k (j stored vectors read per pass)
-        "arn_dots": vec * (1 + (k + 1) / 2.0),
-        "arn_update": vec * (2 + (k + 1) / 2.0),
+        # iterations j = 1..k (j stored vectors read per pass); with the second
+        # pass from the Gram matrix every real launch has a conditional twin
+        # that returns at once, so the bytes per launch halve
+        "arn_dots": vec * (1 + (k + 1) / 2.0) / arn_twins,
+        "arn_update": vec * (2 + (k + 1) / 2.0) / arn_twins,
         # one-pass step: read the pair (u_{j-1}, r_j), write (u_j, r_{j+1});
         # the first of the k launches reads the plain start vectors (one
         # vector), so the average over a batch's launches is (4k - 1)/k
