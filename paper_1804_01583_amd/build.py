@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "libkry.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["kry_api.cpp", "kry_lanczos.hip", "kry_arnoldi.hip", "kry_expm.hip", "kry_block.hip", "kry_dense.hip", "kry_sell.hip", "kry_errctl.hip", "kry_lz1.hip",
-           "kry_lp.hip", "kry_wide.hip", "kry_tune.cpp", "kry_errbig.hip"]
+           "kry_lp.hip", "kry_wide.hip", "kry_tune.cpp", "kry_errbig.hip", "kry_small.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

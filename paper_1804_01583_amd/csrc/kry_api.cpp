@@ -132,7 +132,8 @@ Profiler& prof() {
 const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
     "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp,"
-    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_sets,wide_stage";
+    "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_sets,wide_stage,bcorr,arn_corr,arn_guard,"
+    "small_lanczos";
 
 // Runs `launch` bracketed by events when profiling is on.  The sliced-ELL
 // mat-vec and the one-pass step's kernels take the events into their own
@@ -1414,6 +1415,45 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
     // vectors are stored in (FP32 rounding noise must not pass for a new direction)
     const double tau_scale = 1024.0 * (plan->f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
     int32_t r0 = 0;
+    // FP64 three-vector Lanczos of a small system: every run in one launch
+    // of the persistent kernel (KRY_SMALL=0 keeps the general path)
+    const bool small = (plan->method == KRY_LANCZOS || plan->method == KRY_LANCZOS_PLAIN) && !plan->f32 &&
+                       !Y.stored && plan->err_eps <= 0.0 && !plan->wide && n <= kSmallN && plan->o <= kMaxO &&
+                       (plan->sys.kind == KRY_CSR || plan->sys.kind == KRY_STENCIL7) &&
+                       env_int("KRY_SMALL", 1) != 0;
+    if (small) {
+        SmallArgs a{};
+        a.kind = plan->sys.kind == KRY_CSR ? 0 : 1;
+        a.A = CsrArgs{plan->sys.rowptr, plan->sys.colidx, plan->sys.vals, nullptr};
+        if (a.kind == 1)
+            a.S = StencilArgs{plan->sys.nx, plan->sys.ny, plan->sys.nz, plan->sys.c0, plan->sys.cx, plan->sys.cy,
+                              plan->sys.cz, plan->sys.stencil_bc == KRY_BC_INSULATED ? 1 : 0,
+                              plan->sys.stencil_exchange};
+        a.n = n;
+        a.o = plan->o;
+        a.T = plan->T;
+        a.oset0 = plan->oset0;
+        a.scal = plan->scal();
+        a.L = Y.L;
+        a.anorm = plan->anorm_dev;
+        a.tau_scale = tau_scale;
+        a.center = plan->center;
+        a.b = plan->sys.b;
+        for (r0 = 0; r0 < plan->nruns; r0 += kSmallRuns) {
+            const int32_t nr = std::min<int32_t>(kSmallRuns, plan->nruns - r0);
+            a.run0 = r0;
+            for (int32_t i = 0; i < nr; ++i) {
+                const int r = r0 + i;
+                // generator segments, the center, the forcing (dense, or as segments)
+                a.src[i] = plan->role[r] == 0   ? plan->gen_set[r]
+                           : plan->role[r] == 1 ? -1
+                           : plan->sys.b        ? -2
+                                                : plan->bset;
+            }
+            const hipError_t e = timed("small_lanczos", s, [&] { return launch_small_lanczos(a, nr, s); });
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("small Lanczos: ") + hipGetErrorString(e));
+        }
+    }
     while (r0 < plan->nruns) {
         int P = Y.pmax;
         while (P > 1 && r0 + P > plan->nruns) P >>= 1;

@@ -416,6 +416,28 @@ hipError_t launch_arn_guard(int P, const ArnArgs& A, const BatchArgs& B, int j, 
 hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, const ArnArgs& A,
                              const BatchArgs& B, int j, int last, hipStream_t s);
 
+// ---- persistent Lanczos for small systems (kry_small.hip) --------------------
+constexpr int kSmallN = 2048;     // rows: three vectors in LDS
+constexpr int kSmallRuns = 64;    // runs (workgroups) per launch
+struct SmallArgs {
+    int32_t kind;                // 0: CSR, 1: 7-point stencil
+    CsrArgs A;
+    StencilArgs S;
+    int64_t n;
+    int32_t o;                   // output sets oset0 .. oset0 + o - 1
+    SegTable T;
+    int32_t oset0;
+    double* scal;                // per-run scalars; run r at r * L.stride
+    ScalLayout L;
+    const double* anorm;         // ||A||_inf on the device
+    double tau_scale;            // breakdown when beta_j <= tau_scale * ||A||_inf
+    const double* center;
+    const double* b;
+    int32_t run0;                // run of workgroup 0
+    int32_t src[kSmallRuns];     // start of each run: segment set (>= 0), -1 center, -2 forcing
+};
+hipError_t launch_small_lanczos(const SmallArgs& a, int32_t nruns, hipStream_t s);
+
 // ---- per-step safety LP (kry_lp.hip) -----------------------------------------
 constexpr int kLpMaxD = 16;      // generator coefficients (LP variables)
 constexpr int kLpMaxRows = 64;   // box rows + G rows + U rows

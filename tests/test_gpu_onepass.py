@@ -21,6 +21,13 @@ from tests.gpu_helpers import assert_basis_parity, assert_krylov_parity, gpu_ver
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _general_path(monkeypatch):
+    # these kernels belong to the general path: small systems would take the
+    # persistent small-system kernel instead
+    monkeypatch.setenv("KRY_SMALL", "0")
+
+
 @contextmanager
 def env(**kv):
     old = {k: os.environ.get(k) for k in kv}

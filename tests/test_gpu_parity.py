@@ -15,6 +15,16 @@ from tests.gpu_helpers import (RTOL, assert_basis_parity, assert_krylov_parity, 
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True, params=["small", "general"])
+def _path(request, monkeypatch):
+    # every test on both FP64 Lanczos paths: the persistent small-system
+    # kernel (the default up to 2048 rows) and the general launches
+    if request.param == "general":
+        monkeypatch.setenv("KRY_SMALL", "0")
+    else:
+        monkeypatch.delenv("KRY_SMALL", raising=False)
+
+
 def _compare(problem, method="auto", **kw):
     require_gpu()
     ref = oracle.verify(problem, method=method, k=kw.get("k"), steps=kw.get("steps"), dt=kw.get("dt"))

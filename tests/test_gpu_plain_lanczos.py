@@ -19,6 +19,16 @@ from tests.test_gpu_adaptive import _bound_tol
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True, params=["small", "general"])
+def _path(request, monkeypatch):
+    # every test on both FP64 Lanczos paths: the persistent small-system
+    # kernel (the default up to 2048 rows) and the general launches
+    if request.param == "general":
+        monkeypatch.setenv("KRY_SMALL", "0")
+    else:
+        monkeypatch.delenv("KRY_SMALL", raising=False)
+
+
 def test_plain_lanczos_large_k_matches_the_oracle():
     require_gpu()
     p = W.heat3d_paper(m=14, k=150, steps=1000)

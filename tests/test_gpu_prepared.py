@@ -13,6 +13,13 @@ from tests.gpu_helpers import require_gpu
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _general_path(monkeypatch):
+    # these kernels belong to the general path: small systems would take the
+    # persistent small-system kernel instead
+    monkeypatch.setenv("KRY_SMALL", "0")
+
+
 def _same_verdict(a, b):
     return a.keys() == b.keys() and all(np.array_equal(np.asarray(a[k]), np.asarray(b[k])) for k in a)
 

@@ -15,6 +15,13 @@ from gpu_helpers import assert_basis_parity, assert_verdict_parity, require_gpu
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True)
+def _general_path(monkeypatch):
+    # these kernels belong to the general path: small systems would take the
+    # persistent small-system kernel instead
+    monkeypatch.setenv("KRY_SMALL", "0")
+
+
 def _basis(p, prepared, narrow):
     from paper_1804_01583_amd import kry
     print(f"[gpu] sell columns {p.name} n={p.n} prepared={prepared} narrow={narrow}", flush=True)
