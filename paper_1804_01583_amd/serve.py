@@ -97,6 +97,7 @@ class Result:
     verified_steps: int
     basis: Optional[np.ndarray] = None
     group: int = 1            # queries in the plan that ran it
+    cancelled: bool = False   # withdrawn by Server.cancel: verdict is {"cancelled": True}
 
     @property
     def latency(self) -> float:
@@ -181,6 +182,26 @@ class Server:
         self.max_group = max_group if (batch and runner is None) else 1
         self._runner = runner
         self._footprint = footprint
+        self._cancel_lock = threading.Lock()
+        self._cancelled = set()
+        self._cond = None
+
+    def cancel(self, qid: int) -> None:
+        """Withdraws query qid (callable from any thread while serve runs).
+        A query still waiting, or not yet arrived, never runs; one already
+        running finishes on the device (its launches are not interrupted) and
+        its verdict is dropped.  Either way its Result has cancelled=True and
+        its slot and HBM are released as usual."""
+        with self._cancel_lock:
+            self._cancelled.add(qid)
+            cond = self._cond
+        if cond is not None:
+            with cond:
+                cond.notify_all()
+
+    def _is_cancelled(self, qid: int) -> bool:
+        with self._cancel_lock:
+            return qid in self._cancelled
 
     def footprint(self, q) -> int:
         if self._footprint is not None:
@@ -260,6 +281,8 @@ class Server:
         results: Dict[int, Result] = {}
         errors: List[BaseException] = []
         cond = threading.Condition()
+        with self._cancel_lock:
+            self._cond = cond
         state = {"in_use": 0, "dispatched": False}
         if self._runner is None:
             import torch
@@ -274,6 +297,12 @@ class Server:
                 return [self._runner(q, slot, keep) for q in qs]
         t0 = time.perf_counter()
 
+        def drop(q, fp, admitted):
+            # caller holds cond
+            now = time.perf_counter() - t0
+            results[q.qid] = Result(q.qid, q.arrival * time_scale, admitted if admitted is not None else now, now,
+                                    {"cancelled": True}, fp, 0, None, 1, cancelled=True)
+
         def dispatcher():
             try:
                 for q in order:
@@ -284,7 +313,10 @@ class Server:
                     if wait > 0:
                         time.sleep(wait)
                     with cond:
-                        pending.append(_Pending(q, fp, time.perf_counter() - t0))
+                        if self._is_cancelled(q.qid):
+                            drop(q, fp, None)
+                        else:
+                            pending.append(_Pending(q, fp, time.perf_counter() - t0))
                         cond.notify_all()
             finally:
                 with cond:
@@ -297,6 +329,9 @@ class Server:
                     while True:
                         if errors:
                             return
+                        for item in [p for p in pending if self._is_cancelled(p.query.qid)]:
+                            pending.remove(item)
+                            drop(item.query, item.footprint, None)
                         i = pick_admission(pending, state["in_use"], self.budget, self.max_bypass)
                         if i is not None:
                             in_use = state["in_use"]
@@ -323,6 +358,9 @@ class Server:
                     state["in_use"] -= fp
                     for item, (verdict, basis, runs) in zip(group, outs):
                         q = item.query
+                        if self._is_cancelled(q.qid):
+                            drop(q, fp, admitted)
+                            continue
                         results[q.qid] = Result(q.qid, q.arrival * time_scale, admitted, done, verdict, fp,
                                                 (q.steps + 1) * runs, basis, len(group))
                     cond.notify_all()
@@ -333,16 +371,21 @@ class Server:
         dispatcher()
         for t in threads:
             t.join()
+        with self._cancel_lock:
+            self._cond = None
         if errors:
             raise errors[0]
         return [results[q.qid] for q in queries]
 
 
 def summarize(results: List[Result]) -> dict:
+    """Latency and throughput over the queries that were not cancelled."""
+    cancelled = sum(r.cancelled for r in results)
+    results = [r for r in results if not r.cancelled]
     lat = np.array([r.latency for r in results])
     span = max(r.done for r in results) - min(r.arrival for r in results)
     steps = sum(r.verified_steps for r in results)
-    return {"queries": len(results), "p50_ms": 1000.0 * float(np.percentile(lat, 50)),
+    return {"queries": len(results), "cancelled": cancelled, "p50_ms": 1000.0 * float(np.percentile(lat, 50)),
             "p99_ms": 1000.0 * float(np.percentile(lat, 99)), "max_ms": 1000.0 * float(lat.max()),
             "verified_steps_per_s": steps / span if span > 0 else float("nan"), "span_s": span,
             "unsafe": int(sum(r.verdict["first_step"] >= 0 for r in results)),

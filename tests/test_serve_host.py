@@ -128,3 +128,46 @@ def test_query_stream_is_seeded_and_in_range():
             assert s.lo.min() >= 0 and s.hi.max() <= q.n
     gaps = np.diff([q.arrival for q in a])
     assert np.all(gaps >= 0)
+
+
+def test_cancel_waiting_and_running_queries():
+    # one slot: query 0 runs (held by a gate), 1 and 2 wait.  Cancelling 1
+    # while it waits keeps it from running; cancelling 0 while it runs drops
+    # its verdict once it finishes; 2 runs normally; 3, cancelled before it
+    # arrives, never enters the queue.
+    qs = W.serving_queries(4, rate=1000.0, seed=304)
+    for i, q in enumerate(qs):
+        q.arrival = 0.0 if i < 3 else 0.5
+    started, gate = [], threading.Event()
+    lock = threading.Lock()
+
+    def run(q, slot, keep):
+        with lock:
+            started.append(q.qid)
+        if q.qid == qs[0].qid:
+            gate.wait(5.0)
+        return {"first_step": -1, "row": -1}, None, len(q.gens)
+    srv = Server(None, slots=1, budget_bytes=1 << 40, runner=run, footprint=lambda q: 1)
+
+    def client():
+        while True:
+            with lock:
+                if started:
+                    break
+            time.sleep(0.001)
+        srv.cancel(qs[1].qid)
+        srv.cancel(qs[0].qid)
+        srv.cancel(qs[3].qid)
+        gate.set()
+    t = threading.Thread(target=client)
+    t.start()
+    res = srv.serve(qs)
+    t.join()
+    assert started == [qs[0].qid, qs[2].qid]
+    by = {r.qid: r for r in res}
+    assert by[qs[0].qid].cancelled and by[qs[0].qid].verdict == {"cancelled": True}
+    assert by[qs[1].qid].cancelled and by[qs[1].qid].verified_steps == 0
+    assert by[qs[3].qid].cancelled
+    assert not by[qs[2].qid].cancelled and by[qs[2].qid].verdict["first_step"] == -1
+    s = summarize(res)
+    assert s["cancelled"] == 3 and s["queries"] == 1
