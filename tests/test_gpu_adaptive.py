@@ -15,7 +15,7 @@ import torch  # noqa: F401  (imported at collection so the first test does not p
 import workloads as W
 from oracle import adaptive as AD
 from paper_1804_01583_amd import kry
-from tests.gpu_helpers import assert_basis_parity, require_gpu
+from tests.gpu_helpers import assert_basis_parity, env, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -195,19 +195,25 @@ def _conv_diff(shift=0.0, forcing=False, center=False):
     return p
 
 
+# gs: the plain two-pass Gram-Schmidt these sizes take by default, and the
+# second pass from the Gram matrix (forced on here; the default from 2^16 rows)
+@pytest.mark.parametrize("gs", ["0", "1"])
 @pytest.mark.parametrize("eps", [1e-6, 1e-9])
-def test_arnoldi_nonsymmetric(eps):
+def test_arnoldi_nonsymmetric(eps, gs):
     require_gpu()
-    errs, _ = _run(_conv_diff(), eps, method=kry.KRY_ARNOLDI)
+    with env(KRY_ARN_GS=gs):
+        errs, _ = _run(_conv_diff(), eps, method=kry.KRY_ARNOLDI)
     assert all(4 <= e[0] < 40 for e in errs)
 
 
-def test_arnoldi_forcing_center_and_positive_lambda():
+@pytest.mark.parametrize("gs", ["0", "1"])
+def test_arnoldi_forcing_center_and_positive_lambda(gs):
     # a diagonal shift past the Gershgorin radius makes lambda > 0; the
     # augmented run integrates its bound; a dense center adds a run
     require_gpu()
     p = _conv_diff(shift=0.5 * 1.0 / (1.0 / 11) / 5.0, forcing=True, center=True)
-    errs, ref = _run(p, 1e-7, method=kry.KRY_ARNOLDI)
+    with env(KRY_ARN_GS=gs):
+        errs, ref = _run(p, 1e-7, method=kry.KRY_ARNOLDI)
     assert ref["lam"] > 0.0 and len(errs) == 4
 
 

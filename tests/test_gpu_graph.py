@@ -22,10 +22,14 @@ def _eager(kry, p, ds, stream):
     return b, v
 
 
-@pytest.mark.parametrize("name", ["heat1d", "small_heat3d", "random_arnoldi"])
-def test_replays_match_eager_bitwise(name):
+@pytest.mark.parametrize("name", ["heat1d", "small_heat3d", "random_arnoldi", "random_arnoldi_gram"])
+def test_replays_match_eager_bitwise(name, monkeypatch):
     torch = require_gpu()
     from paper_1804_01583_amd import kry
+    if name == "random_arnoldi_gram":
+        # the second Gram-Schmidt pass from the Gram matrix, its guard and
+        # the conditional launches recorded in the graph
+        monkeypatch.setenv("KRY_ARN_GS", "1")
     if name == "heat1d":
         p = W.heat1d(steps=300)
         method = kry.KRY_AUTO
