@@ -259,9 +259,10 @@ kry_status kry_footprint_transposed(const kry_system* sys_t, int32_t ngen, int32
  * runs of a forward plan), or NULL to keep the basis on the device for
  * kry_check_box_safety only.  With a host pointer the call waits for the
  * stream; otherwise it returns once the work is enqueued.  FP64 Lanczos
- * plans of at most 2048 rows without an error target run every run's whole
- * Krylov process in one launch (results equal the general path's to
- * rounding); set KRY_SMALL=0 in the environment to keep the general path. */
+ * plans, and FP64 Arnoldi plans with k <= 64, of at most 2048 rows and
+ * without an error target run every run's whole Krylov process in one
+ * launch (results equal the general path's to rounding); set KRY_SMALL=0 in
+ * the environment to keep the general path. */
 kry_status kry_project_expm(kry_plan_t* plan, double* basis_out);
 
 /* kry_check_box_safety -- per step s and output row r, the reachable output

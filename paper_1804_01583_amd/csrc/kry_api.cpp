@@ -133,7 +133,7 @@ const char* kKernelNames =
     "row_abs_max,start,spmv_csr,spmv_sell,spmv_stencil,sweep,arn_dots,arn_reduce,arn_update,finish,expm_chain,"
     "assemble,check,bfill,bstart,bspmm,bgram,bgram_red,bchol,bupdate,bproj,dense_expm,sell_build,errctl,lp,"
     "lz1_sell,lz1_stencil,lz1_march,lz1_proj,lz1_close,wide_proj,wide_sets,wide_stage,bcorr,arn_corr,arn_guard,"
-    "small_lanczos";
+    "small_lanczos,small_arnoldi";
 
 // Runs `launch` bracketed by events when profiling is on.  The sliced-ELL
 // mat-vec and the one-pass step's kernels take the events into their own
@@ -274,6 +274,7 @@ struct Layout {
     bool lz1 = false;     // FP64 three-vector Lanczos: room for the one-pass step (two pair buffers)
     size_t hpart, hcoef, vals32;
     size_t hpart2 = 0, sraw = 0, gram = 0, guard = 0;   // Arnoldi: the second pass from the Gram matrix
+    size_t sbasis = 0;    // small FP64 Arnoldi: the persistent kernel's per-run basis
     size_t oflag = 0;     // one-pass step: per-run cancellation flags of a batch
     size_t ap_stride = 0; // doubles between the two ping-pong partial arrays of the one-pass step
     // transposed route with many initial-space rows: E^T u per step, segment
@@ -329,6 +330,8 @@ Layout make_layout(int64_t n, int32_t nruns, int32_t o, int32_t k, int64_t steps
     Y.vec = take((size_t)Y.nvec * n * Y.pmax * Y.esize);
     Y.hpart = Y.stored ? take((size_t)(k + 1) * kMaxP * Y.nblocks * sizeof(double)) : 0;
     Y.hcoef = Y.stored ? take((size_t)k * kMaxP * sizeof(double)) : 0;
+    if (method == KRY_ARNOLDI && precision == KRY_FP64 && n <= kSmallN && k <= kSmallArnK)
+        Y.sbasis = take((size_t)std::min(std::max(nruns, 1), kSmallRuns) * (k + 1) * n * sizeof(double));
     if (method == KRY_ARNOLDI) {
         Y.hpart2 = take((size_t)(k + 1) * kMaxP * Y.nblocks * sizeof(double));
         Y.sraw = take((size_t)(k + 1) * kMaxP * sizeof(double));
@@ -1415,10 +1418,13 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
     // vectors are stored in (FP32 rounding noise must not pass for a new direction)
     const double tau_scale = 1024.0 * (plan->f32 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
     int32_t r0 = 0;
-    // FP64 three-vector Lanczos of a small system: every run in one launch
-    // of the persistent kernel (KRY_SMALL=0 keeps the general path)
-    const bool small = (plan->method == KRY_LANCZOS || plan->method == KRY_LANCZOS_PLAIN) && !plan->f32 &&
-                       !Y.stored && plan->err_eps <= 0.0 && !plan->wide && n <= kSmallN && plan->o <= kMaxO &&
+    // FP64 three-vector Lanczos or Arnoldi (k <= 64) of a small system: every
+    // run in one launch of a persistent kernel (KRY_SMALL=0 keeps the general
+    // path)
+    const bool small_lz = (plan->method == KRY_LANCZOS || plan->method == KRY_LANCZOS_PLAIN) && !Y.stored;
+    const bool small_arn = plan->method == KRY_ARNOLDI && Y.sbasis != 0;
+    const bool small = (small_lz || small_arn) && !plan->f32 && plan->err_eps <= 0.0 && !plan->wide &&
+                       n <= kSmallN && plan->o <= kMaxO &&
                        (plan->sys.kind == KRY_CSR || plan->sys.kind == KRY_STENCIL7) &&
                        env_int("KRY_SMALL", 1) != 0;
     if (small) {
@@ -1439,6 +1445,7 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
         a.tau_scale = tau_scale;
         a.center = plan->center;
         a.b = plan->sys.b;
+        a.basis = small_arn ? plan->at<double>(Y.sbasis) : nullptr;
         for (r0 = 0; r0 < plan->nruns; r0 += kSmallRuns) {
             const int32_t nr = std::min<int32_t>(kSmallRuns, plan->nruns - r0);
             a.run0 = r0;
@@ -1450,8 +1457,10 @@ kry_status enqueue_projection(kry_plan_t* plan, double* basis_out, bool finish, 
                            : plan->sys.b        ? -2
                                                 : plan->bset;
             }
-            const hipError_t e = timed("small_lanczos", s, [&] { return launch_small_lanczos(a, nr, s); });
-            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("small Lanczos: ") + hipGetErrorString(e));
+            const hipError_t e = small_arn
+                                     ? timed("small_arnoldi", s, [&] { return launch_small_arnoldi(a, nr, s); })
+                                     : timed("small_lanczos", s, [&] { return launch_small_lanczos(a, nr, s); });
+            if (e != hipSuccess) return fail(KRY_EDEVICE, std::string("small Krylov: ") + hipGetErrorString(e));
         }
     }
     while (r0 < plan->nruns) {

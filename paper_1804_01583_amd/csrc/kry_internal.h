@@ -419,6 +419,7 @@ hipError_t launch_arn_update(int P, int O, const SegTable& T, int32_t oset0, con
 // ---- persistent Lanczos for small systems (kry_small.hip) --------------------
 constexpr int kSmallN = 2048;     // rows: three vectors in LDS
 constexpr int kSmallRuns = 64;    // runs (workgroups) per launch
+constexpr int kSmallArnK = 64;    // Krylov dimension of the small Arnoldi kernel
 struct SmallArgs {
     int32_t kind;                // 0: CSR, 1: 7-point stencil
     CsrArgs A;
@@ -435,8 +436,10 @@ struct SmallArgs {
     const double* b;
     int32_t run0;                // run of workgroup 0
     int32_t src[kSmallRuns];     // start of each run: segment set (>= 0), -1 center, -2 forcing
+    double* basis;               // Arnoldi: [kSmallRuns][k + 1][n] basis of the launch's runs
 };
 hipError_t launch_small_lanczos(const SmallArgs& a, int32_t nruns, hipStream_t s);
+hipError_t launch_small_arnoldi(const SmallArgs& a, int32_t nruns, hipStream_t s);
 
 // ---- per-step safety LP (kry_lp.hip) -----------------------------------------
 constexpr int kLpMaxD = 16;      // generator coefficients (LP variables)

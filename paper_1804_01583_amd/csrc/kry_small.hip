@@ -191,7 +191,127 @@ __global__ __launch_bounds__(kBlock) void k_small_lanczos(SmallArgs a) {
     }
 }
 
+// sum over rows r in [c0, c1) of x[r] y[r] for the stored vector x
+__device__ __forceinline__ double row_dot(const double* __restrict__ x, const double* y, int64_t c0, int64_t c1) {
+    double acc = 0.0;
+    for (int64_t r = c0; r < c1; ++r) acc = fma(x[r], y[r], acc);
+    return acc;
+}
+
+// Arnoldi (Algorithm 1 with classical Gram-Schmidt applied twice, as the
+// general path) for one run per workgroup: w and v_j in LDS, the basis
+// v_1..v_{k+1} in this workgroup's slice of a.basis (at these sizes it
+// stays in L2).  A pass forms the j dot products from per-thread partials:
+// each wave sums a dot by butterfly, the waves' sums land in LDS and every
+// thread adds them in wave order, one barrier per pass.
+__global__ __launch_bounds__(kBlock) void k_small_arnoldi(SmallArgs a) {
+    constexpr int NW = kBlock / 64;
+    __shared__ double s_vc[kSmallN];
+    __shared__ double s_w[kSmallN];
+    __shared__ double s_dot[kSmallArnK][NW];
+    __shared__ double s_h[kSmallArnK];
+    __shared__ double s_red[NW];
+    const int64_t n = a.n;
+    const int k = a.L.k;
+    const int64_t rpt = (n + kBlock - 1) / kBlock;
+    const int64_t c0 = min(n, (int64_t)threadIdx.x * rpt), c1 = min(n, c0 + rpt);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* sc = a.scal + (int64_t)(a.run0 + blockIdx.x) * a.L.stride;
+    double* V = a.basis + (int64_t)blockIdx.x * (k + 1) * n;    // v_{i+1} at V + i n
+    const double tau = a.tau_scale * *a.anorm;
+    const int src = a.src[blockIdx.x];
+    const double* dense = src == -1 ? a.center : (src == -2 ? a.b : nullptr);
+    for (int64_t r = c0; r < c1; ++r) s_vc[r] = dense != nullptr ? dense[r] : 0.0;
+    if (src >= 0) seg_fill(a.T, src, c0, c1, s_vc);
+    double nrm = 0.0;
+    for (int64_t r = c0; r < c1; ++r) nrm = fma(s_vc[r], s_vc[r], nrm);
+    nrm = wg_sum(nrm, s_red);
+    Stage st = stage_update_v(k, 0.0, tau, 1, nrm);
+    if (threadIdx.x == 0) {
+        sc[a.L.beta + 0] = st.beta;
+        sc[a.L.sigma + 1] = st.sigma;
+        sc[a.L.misc + MISC_KEFF] = (double)st.keff;
+        sc[a.L.misc + MISC_NONFINITE] = st.nonfinite ? 1.0 : 0.0;
+        sc[a.L.misc + MISC_KSTOP] = (double)k;
+        sc[a.L.misc + MISC_STOPPED] = 0.0;
+        sc[a.L.misc + MISC_BOUND] = -1.0;
+    }
+    double sig = st.sigma;
+    for (int64_t r = c0; r < c1; ++r) {
+        s_vc[r] *= sig;
+        V[r] = s_vc[r];
+    }
+    small_project(a, sc, 0, c0, c1, s_vc, s_red);
+    __syncthreads();
+    int j = 1;
+    for (; j <= k && sig != 0.0; ++j) {
+        small_matvec(a, c0, c1, s_vc, s_w);
+        // two classical Gram-Schmidt passes against v_1..v_j; this thread's
+        // own rows of w only, so no barrier is needed between the passes'
+        // subtractions and the next dots
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int i = 0; i < j; ++i) {
+                double d = row_dot(V + (int64_t)i * n, s_w, c0, c1);
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) d += __shfl_xor(d, off, 64);
+                if (lane == 0) s_dot[i][wave] = d;
+            }
+            __syncthreads();
+            for (int i = 0; i < j; ++i) {
+                double h = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) h += s_dot[i][w];
+                for (int64_t r = c0; r < c1; ++r) s_w[r] = fma(-h, V[(int64_t)i * n + r], s_w[r]);
+                if (threadIdx.x == 0) s_h[i] = pass == 0 ? h : s_h[i] + h;
+            }
+            __syncthreads();     // s_dot is rewritten by the next pass
+        }
+        if (threadIdx.x == 0) {
+            bool bad = false;
+            for (int i = 0; i < j; ++i) {
+                sc[a.L.hess + i * k + (j - 1)] = s_h[i];
+                bad = bad || !isfinite(s_h[i]);
+            }
+            if (bad) sc[a.L.misc + MISC_NONFINITE] = 1.0;
+        }
+        nrm = 0.0;
+        for (int64_t r = c0; r < c1; ++r) nrm = fma(s_w[r], s_w[r], nrm);
+        nrm = wg_sum(nrm, s_red);
+        st = stage_update_v(k, sig, tau, j + 1, nrm);
+        if (threadIdx.x == 0) {
+            sc[a.L.beta + j] = st.beta;
+            sc[a.L.sigma + j + 1] = st.sigma;
+            if (st.keff >= 0) sc[a.L.misc + MISC_KEFF] = (double)st.keff;
+            if (st.nonfinite) sc[a.L.misc + MISC_NONFINITE] = 1.0;
+        }
+        sig = st.sigma;
+        for (int64_t r = c0; r < c1; ++r) {
+            const double v = s_w[r] * sig;
+            s_vc[r] = v;
+            V[(int64_t)j * n + r] = v;
+        }
+        small_project(a, sc, j, c0, c1, s_vc, s_red);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (; j <= k; ++j) {
+            for (int i = 0; i < j; ++i) sc[a.L.hess + i * k + (j - 1)] = 0.0;
+            sc[a.L.beta + j] = 0.0;
+            sc[a.L.sigma + j + 1] = 0.0;
+            for (int q = 0; q < a.o; ++q) sc[a.L.proj + q * (k + 1) + j] = 0.0;
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_small_arnoldi(const SmallArgs& a, int32_t nruns, hipStream_t s) {
+    if (a.n < 1 || a.n > kSmallN || nruns < 1 || nruns > kSmallRuns || a.o > kMaxO || a.L.k > kSmallArnK ||
+        a.basis == nullptr)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_small_arnoldi, dim3(nruns), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_small_lanczos(const SmallArgs& a, int32_t nruns, hipStream_t s) {
     if (a.n < 1 || a.n > kSmallN || nruns < 1 || nruns > kSmallRuns || a.o > kMaxO) return hipErrorInvalidValue;

@@ -15,6 +15,17 @@ from tests.gpu_helpers import (assert_basis_parity, assert_krylov_parity, assert
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True, params=["small", "general"])
+def _path(request, monkeypatch):
+    # every test on both FP64 Arnoldi paths: the persistent small-system
+    # kernel (the default up to 2048 rows and k = 64) and the general launches;
+    # the tests of the general path's Gram-matrix second pass pin it themselves
+    if request.param == "general":
+        monkeypatch.setenv("KRY_SMALL", "0")
+    else:
+        monkeypatch.delenv("KRY_SMALL", raising=False)
+
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "harmonic.json")))
 
 
@@ -84,9 +95,10 @@ def test_nilpotent_terminates_exactly():
 
 
 @pytest.mark.parametrize("precision", [0, 1])   # KRY_FP64, KRY_FP32_BASIS
-def test_gram_corrected_second_pass_against_two_passes(precision):
+def test_gram_corrected_second_pass_against_two_passes(precision, monkeypatch):
     # the second Gram-Schmidt pass from the Gram matrix (forced on at this
     # size) against the plain second pass over the basis, and the oracle
+    monkeypatch.setenv("KRY_SMALL", "0")
     p = W.conv_diff3d(12, 12, 14, ngen=3, gen_len=40, o=3, k=20, steps=120, dt=1e-3, seed=3)
     with env(KRY_ARN_GS="0"):
         two = gpu_verify(p, precision=precision)
@@ -133,7 +145,8 @@ def _near_invariant_heat():
     return p
 
 
-def test_gram_corrected_pass_guard_runs_the_plain_pass():
+def test_gram_corrected_pass_guard_runs_the_plain_pass(monkeypatch):
+    monkeypatch.setenv("KRY_SMALL", "0")
     p = _near_invariant_heat()
     with env(KRY_ARN_GS="1"):
         got, _ = _compare(p, oracle_method="arnoldi", method=2)   # KRY_ARNOLDI

@@ -28,8 +28,10 @@ def test_replays_match_eager_bitwise(name, monkeypatch):
     from paper_1804_01583_amd import kry
     if name == "random_arnoldi_gram":
         # the second Gram-Schmidt pass from the Gram matrix, its guard and
-        # the conditional launches recorded in the graph
+        # the conditional launches recorded in the graph (the general path:
+        # this size would take the persistent small-system kernel)
         monkeypatch.setenv("KRY_ARN_GS", "1")
+        monkeypatch.setenv("KRY_SMALL", "0")
     if name == "heat1d":
         p = W.heat1d(steps=300)
         method = kry.KRY_AUTO

@@ -1,6 +1,8 @@
-"""GPU parity of the persistent small-system Lanczos (FP64, three vectors, at
-most 2048 rows: every run of a plan in one launch, vectors in LDS) against
-the oracle and against the general multi-launch path (KRY_SMALL=0)."""
+"""GPU parity of the persistent small-system kernels (FP64, at most 2048
+rows: every run of a plan in one launch; Lanczos with its three vectors in
+LDS, Arnoldi up to k = 64 with its basis in a per-run slice of the
+workspace) against the oracle and against the general multi-launch path
+(KRY_SMALL=0)."""
 import math
 
 import numpy as np
@@ -83,3 +85,39 @@ def test_breakdown_on_an_eigenvector():
     t = np.arange(p.steps + 1) * p.dt
     want = oracle.output_matrix(p).toarray() @ v
     np.testing.assert_allclose(small["basis"][:, 0, 0], want[0] * np.exp(lam * t), rtol=1e-12)
+
+
+def test_arnoldi_convection_diffusion():
+    p = W.conv_diff3d(12, 12, 14, ngen=3, gen_len=40, o=3, k=20, steps=120, dt=1e-3, seed=3)
+    small, _, _ = _both(p)
+    assert small["roles"] == ["gen"] * 3
+
+
+def test_arnoldi_with_center_and_forcing():
+    p = W.conv_diff3d(10, 10, 11, ngen=2, gen_len=30, o=2, k=16, steps=60, dt=2e-3, seed=8)
+    rng = np.random.default_rng(8)
+    p.b = rng.normal(0, 1, p.n) * (rng.uniform(size=p.n) < 0.05)
+    p.center = rng.normal(0, 1, p.n) * (rng.uniform(size=p.n) < 0.05)
+    small, _, _ = _both(p)
+    assert small["roles"] == ["gen", "gen", "center", "affine"]
+
+
+def test_arnoldi_nilpotent_terminates_exactly():
+    # down-shift: the Krylov space from e_1 is the whole space (k_eff = n)
+    n = 6
+    p = W.Problem("shift", n, "csr", False, [W.Generator(W.segments_from_ranges([(0, 1)]), 0.0, 1.0)],
+                  [W.segments_from_ranges([(q, q + 1)]) for q in range(n)],
+                  np.array([[math.inf, math.inf]] * n), k=10, dt=0.3, steps=5,
+                  rowptr=np.array([0, 0, 1, 2, 3, 4, 5], dtype=np.int64),
+                  colidx=np.arange(0, 5, dtype=np.int32), vals=np.ones(5))
+    small, _, _ = _both(p)
+    assert small["runs"][0]["k_eff"] == n
+    t = 5 * 0.3
+    exact = np.array([t**j / math.factorial(j) for j in range(n)])
+    np.testing.assert_allclose(small["basis"][5, :, 0], exact, rtol=1e-12)
+
+
+def test_arnoldi_past_the_small_kernels_k():
+    # k = 65 > 64: the general path, and its result
+    p = W.conv_diff3d(9, 10, 11, ngen=1, gen_len=40, o=2, k=65, steps=40, dt=1e-3, seed=2)
+    _both(p)
