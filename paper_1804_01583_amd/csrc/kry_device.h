@@ -352,15 +352,15 @@ struct MarchCol {
 // Segment sets (generators and output rows) a block needs are staged in LDS.
 // The plan precomputes, for every set and logical block, the range of that
 // set's segments overlapping the block's rows (SegTable::blk), so a block
-// finds them with one load; up to kSegCap of them are copied to LDS, a set
-// with more keeps reading global memory.
+// finds them with one load; up to CAP of them (kSegCap unless a kernel asks
+// for more) are copied to LDS, a set with more keeps reading global memory.
 constexpr int kSegCap = 64;
 
-template <int NS>
+template <int NS, int CAP = kSegCap>
 struct SegStage {
-    int64_t lo[NS][kSegCap];
-    int64_t hi[NS][kSegCap];
-    double w[NS][kSegCap];
+    int64_t lo[NS][CAP];
+    int64_t hi[NS][CAP];
+    double w[NS][CAP];
     int32_t beg[NS], end[NS];
 };
 
@@ -383,15 +383,15 @@ __device__ __forceinline__ SegRange seg_range(const SegTable& T, const int (&set
     return r;
 }
 
-template <int NS>
-__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, SegRange r) {
+template <int NS, int CAP = kSegCap>
+__device__ __forceinline__ void stage_segments(SegStage<NS, CAP>& st, const SegTable& T, SegRange r) {
     if (threadIdx.x < NS) {
         st.beg[threadIdx.x] = r.b;
         st.end[threadIdx.x] = r.e;
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < NS * kSegCap; idx += kBlock) {
-        const int i = idx / kSegCap, c = idx % kSegCap;
+    for (int idx = threadIdx.x; idx < NS * CAP; idx += kBlock) {
+        const int i = idx / CAP, c = idx % CAP;
         const int g = st.beg[i] + c;
         if (g < st.end[i]) {
             st.lo[i][c] = T.lo[g];
@@ -403,25 +403,25 @@ __device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable&
 }
 
 // Both halves at once.  Every thread must call it.
-template <int NS>
-__device__ __forceinline__ void stage_segments(SegStage<NS>& st, const SegTable& T, const int (&sets)[NS],
+template <int NS, int CAP = kSegCap>
+__device__ __forceinline__ void stage_segments(SegStage<NS, CAP>& st, const SegTable& T, const int (&sets)[NS],
                                                int lb, int nblocks) {
-    stage_segments<NS>(st, T, seg_range<NS>(T, sets, lb, nblocks));
+    stage_segments<NS, CAP>(st, T, seg_range<NS>(T, sets, lb, nblocks));
 }
 
 // Weight of increasing rows in one staged set, amortised O(1) per row.
 struct SegCursor {
     int32_t cur, cnt, gcur, gend;
-    template <int NS>
-    __device__ __forceinline__ void init(const SegStage<NS>& st, int i) {
+    template <int NS, int CAP>
+    __device__ __forceinline__ void init(const SegStage<NS, CAP>& st, int i) {
         const int n = st.end[i] - st.beg[i];
         cur = 0;
-        cnt = n <= kSegCap ? n : 0;
-        gcur = n <= kSegCap ? 0 : st.beg[i];
-        gend = n <= kSegCap ? 0 : st.end[i];
+        cnt = n <= CAP ? n : 0;
+        gcur = n <= CAP ? 0 : st.beg[i];
+        gend = n <= CAP ? 0 : st.end[i];
     }
-    template <int NS>
-    __device__ __forceinline__ double weight(const SegStage<NS>& st, int i, const SegTable& T, int64_t r) {
+    template <int NS, int CAP>
+    __device__ __forceinline__ double weight(const SegStage<NS, CAP>& st, int i, const SegTable& T, int64_t r) {
         while (cur < cnt && st.hi[i][cur] <= r) ++cur;
         if (cur < cnt) return st.lo[i][cur] <= r ? st.w[i][cur] : 0.0;
         while (gcur < gend && T.hi[gcur] <= r) ++gcur;

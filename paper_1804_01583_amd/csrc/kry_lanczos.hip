@@ -86,8 +86,13 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
                                                   E* __restrict__ u, BatchArgs B) {
     if (batch_stopped<P>(B)) return;   // a fallback the one-pass step did not need
     constexpr int NV = P * (1 + O);
+    // up to 256 segments per set and block in LDS when there are few sets:
+    // a generator over a region of a large grid has a few hundred per block
+    // (the 1000^3 heated region about 200), and a set past the capacity is
+    // read from global memory row by row
+    constexpr int CAP = P + O <= 4 ? 256 : kSegCap;
     __shared__ double s_lds[(kBlock / 64) * NV];
-    __shared__ SegStage<P + O> st;
+    __shared__ SegStage<P + O, CAP> st;
     const int lb = logical_block(B.nblocks, B.xcd_map);
     const int64_t r0 = (int64_t)lb * B.rows_per_block;
     const int64_t r1 = min(B.n, r0 + B.rows_per_block);
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_start(StartSrc src, SegTable T, int3
     for (int i = 0; i < P; ++i) sets[i] = src.set[i];
 #pragma unroll
     for (int q = 0; q < O; ++q) sets[P + q] = oset0 + q;
-    stage_segments<P + O>(st, T, sets, lb, B.nblocks);
+    stage_segments<P + O, CAP>(st, T, sets, lb, B.nblocks);
     SegCursor cur[P + O];
 #pragma unroll
     for (int i = 0; i < P + O; ++i) cur[i].init(st, i);
