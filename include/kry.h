@@ -33,6 +33,16 @@
  *  - Every call returns a kry_status; no C++ exception crosses this ABI.  On
  *    a non-OK status, kry_last_error() returns a thread-local message.
  *  - Dimensions are 64-bit; vectors of n > 2^31 entries are supported.
+ *  - Environment switches, read when a plan projects, choose between forms
+ *    that compute the same quantities (results agree to rounding):
+ *    KRY_SMALL=0 keeps systems of at most 2048 rows off the one-launch
+ *    persistent kernels; KRY_BLOCK_GS=0 / KRY_ARN_GS=0 make both classical
+ *    Gram-Schmidt passes of block / single-vector Arnoldi over the basis
+ *    instead of taking the second from the Gram matrix (KRY_ARN_GS=1 forces
+ *    that form below its default of 2^16 rows); KRY_BLOCK_REORTH2 /
+ *    KRY_ARN_REORTH2 set the squared norm ratio under which the Gram-matrix
+ *    form adds a plain second pass (default 1e-6); KRY_ONEPASS=0/1 turns the
+ *    one-pass Lanczos step off / on for CSR matrices.
  */
 #ifndef KRY_H
 #define KRY_H
